@@ -1,0 +1,171 @@
+"""Benchmark of the checkerboard Metropolis sweep on one MI355X.
+
+Workload (the paper's Table 2 size (32x2048)^2): L = 65536, 2^32 spins at
+1 bit/spin (512 MiB per lattice), J = 1, beta in {0.40, 0.4406868, 0.50}, one
+lattice per beta from the seed-7 start.  One step = one full sweep (black then
+white half-sweep) of each of the three lattices; the default 200 steps are the
+workload's 200 sweeps per beta.  The timed region starts from freshly
+initialised lattices already resident in HBM.
+
+Prints one JSON line: spin flips/ns (attempted single-spin updates per ns),
+the half-sweep kernel against the HBM roofline (algorithmic bytes: target
+read + write and source read, 3 bits per spin update), and the CPU oracle
+timed on a bounded sample on the host.
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import math
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+if ROOT not in sys.path:
+    sys.path.insert(0, ROOT)
+
+import workloads  # noqa: E402
+
+HBM_PEAK_GBS = 8000.0  # MI355X HBM3E, GB/s
+
+
+def onsager_energy(beta: float) -> float:
+    """Infinite-lattice energy per site (Onsager 1944), J = 1, for reporting."""
+    from scipy.special import ellipk
+
+    K = beta
+    kappa = 2 * math.sinh(2 * K) / math.cosh(2 * K) ** 2
+    m = min(kappa * kappa, 1.0)
+    term = 0.0 if m >= 1.0 else (2 * math.tanh(2 * K) ** 2 - 1) * float(ellipk(m))
+    return -1.0 / math.tanh(2 * K) * (1 + (2 / math.pi) * term)
+
+
+def cpu_baseline(target_s: float = 15.0) -> dict:
+    """The CPU oracle, as it stands, on a bounded sample of the workload."""
+    import oracle
+
+    oracle.lib()
+    cores = oracle.max_threads()
+    L, beta, seed = 8192, workloads.BETA_CRIT_CONFIG, workloads.HEADLINE["seed"]
+    s = oracle.init(L, seed, 0)
+    t0 = time.perf_counter()
+    oracle.sweeps(s, beta, 1.0, seed, 0, 1, 0)
+    one = time.perf_counter() - t0
+    extra = max(0, min(40, int(target_s / max(one, 1e-3)) - 1))
+    t0 = time.perf_counter()
+    if extra:
+        oracle.sweeps(s, beta, 1.0, seed, 0, extra, 1)
+    dt = time.perf_counter() - t0
+    nsw, secs = (extra, dt) if extra else (1, one)
+    return {
+        "value": nsw * L * L / (secs * 1e9),
+        "unit": "flips/ns",
+        "cores": cores,
+        "kind": "oracle",
+        "sample": (f"C/OpenMP int8 oracle (all 32 bit-planes per spin), {nsw} sweeps of an "
+                   f"L={L} lattice at beta={beta} from the seed-{seed} start, {secs:.1f} s"),
+    }
+
+
+def main() -> int:
+    ap = argparse.ArgumentParser(description=__doc__)
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=workloads.HEADLINE["nsweeps"])
+    ap.add_argument("--warmup", type=int, default=2)
+    ap.add_argument("--no-cpu-baseline", action="store_true",
+                    help="skip the CPU oracle timing (for profiler runs)")
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print(f"bench.py measures one GPU; --gpus {args.gpus} is not supported (the sweep is "
+              "built and measured on a single MI355X)", file=sys.stderr)
+        return 2
+
+    import torch
+
+    import paper_1906_06297_amd as ising
+
+    assert torch.cuda.is_available(), "bench.py needs a HIP device"
+    torch.cuda.set_device(0)
+    cfg = workloads.HEADLINE
+    L, betas, seed, J = cfg["L"], cfg["betas"], cfg["seed"], cfg["J"]
+    K, Wm = args.steps, args.warmup
+    W = ising.words_per_colour(L)
+    bufs = [torch.empty(2 * W, dtype=torch.int64, device="cuda") for _ in betas]
+
+    # warmup on the same buffers, then a fresh start for the timed region
+    lats = [ising.Lattice(L, seed, words=b) for b in bufs]
+    for lat, beta in zip(lats, betas):
+        lat.sweep(beta, J, Wm, 0)
+    lats = [ising.Lattice(L, seed, words=b) for b in bufs]
+    torch.cuda.synchronize()
+
+    ev = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)) for _ in betas]
+    t0 = time.perf_counter()
+    for (e0, e1), lat, beta in zip(ev, lats, betas):
+        e0.record()
+        lat.sweep(beta, J, K, 0)
+        e1.record()
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    per_beta_ms = [e0.elapsed_time(e1) for e0, e1 in ev]
+    gpu_ms = sum(per_beta_ms)
+
+    updates = len(betas) * K * L * L
+    value = updates / (wall * 1e9)
+    half_sweep_ms = gpu_ms / (len(betas) * 2 * K)
+    alg_bytes = 3 * (L * L // 2) // 8  # target read + write, source read: 3 bits per update
+    achieved = alg_bytes / (half_sweep_ms * 1e-3) / 1e9
+
+    physics = {}
+    for lat, beta, ms in zip(lats, betas, per_beta_ms):
+        bond, mag = lat.observables()
+        physics[f"{beta}"] = {
+            "flips_per_ns": K * L * L / (ms * 1e6),
+            "E_per_site": -J * bond / (L * L),
+            "onsager_E_per_site": onsager_energy(beta),
+            "abs_m": abs(mag) / (L * L),
+        }
+
+    out = {
+        "metric": "spin flips/ns + % HBM roofline (1 GPU)",
+        "value": value,
+        "unit": "flips/ns",
+        "n_gpus": 1,
+        "steps": K,
+        "warmup": Wm,
+        "ms_per_step": wall * 1e3 / K,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "u64 (1 bit/spin), u32 Philox",
+        "data": "synthetic",
+        "config": {
+            "workload": "checkerboard Metropolis, L=65536 (2^32 spins, 512 MiB at 1 bit/spin), "
+                        "J=1, beta in {0.40, 0.4406868, 0.50}, seed 7, one full sweep per beta "
+                        "per step from a fresh start",
+            "L": L,
+            "betas": list(betas),
+            "sweeps_per_beta": K,
+            "per_beta": physics,
+        },
+        "roofline": {
+            "bound": "hbm",
+            "kernel": "half-sweep",
+            "achieved": achieved,
+            "peak": HBM_PEAK_GBS,
+            "unit": "GB/s",
+            "frac": achieved / HBM_PEAK_GBS,
+            "traffic": None,
+            "avg_launch_us": half_sweep_ms * 1e3,
+            "alg_bytes_per_launch": alg_bytes,
+        },
+    }
+    if not args.no_cpu_baseline:
+        out["cpu_baseline"] = cpu_baseline()
+    print(json.dumps(out), flush=True)
+    return 0
+
+
+if __name__ == "__main__":
+    sys.exit(main())

@@ -1,0 +1,114 @@
+/*
+ * ising.h -- C ABI of libising.so, a gfx950 (MI355X) implementation of the
+ * checkerboard Metropolis simulation of the 2D ferromagnetic Ising model
+ * (Romero, Bisson, Fatica, Bernaschi, "A Performance study of the 2D Ising
+ * model on GPUs", arXiv:1906.06297).
+ *
+ * Model (Sec. 2, Eq. (1)): spins sigma = +/-1 on a periodic L x L square
+ * lattice, H = -J * sum over nearest-neighbour bonds (each bond once) of
+ * sigma_i sigma_j.  A sweep updates all sites of one checkerboard colour in
+ * parallel from the other colour, then the other colour (Sec. 2), each site
+ * by the Metropolis rule (Sec. 2): a flip with energy change dE <= 0 is
+ * accepted, otherwise with probability exp(-beta * dE).
+ *
+ * Conventions shared by every entry point
+ *  - Colour of site (i, j) is (i + j) & 1; colour 0 ("black") is updated
+ *    first in each sweep.
+ *  - Layout (Sec. 3.1 / Sec. 3.3 compact the two colours into separate
+ *    arrays along the rows; here at one bit per spin): colour c is the bit
+ *    string of its L*L/2 spins in colour-linear order n = i*(L/2) + j/2, bit
+ *    n&63 of 64-bit word n>>6, least significant bit first, bit 1 <=> +1.
+ *    A lattice occupies 2 * ising_words_per_colour(L) words, colour 0 first.
+ *    Bits past the last spin of a colour are zero and stay zero.
+ *  - Acceptance is exact in integers: the flip of a site with a aligned
+ *    neighbours is taken iff r < T[a], r a 32-bit uniform and
+ *    T[a] = 2^32 if dE <= 0, floor(exp(-beta*dE) * 2^32) otherwise, with
+ *    dE = 4*J*(a - 2), evaluated on the host in IEEE double precision.
+ *  - Random numbers: Philox4x32-10 (Salmon et al., SC'11), the generator the
+ *    paper uses (Sec. 3.2, 3.3), addressed statelessly as the paper does with
+ *    seed/sequence/offset: key = seed, counter = (stream_id<<8 | domain<<4 | q,
+ *    t mod 2^32, t >> 32, n>>6), t = 2*(rng_counter + sweep) + colour.
+ *    Block q gives bit-planes 2q (words x1:x0) and 2q+1 (x3:x2); plane p is
+ *    bit 31-p of the spin's r.  The initial state uses domain 1, t = colour,
+ *    q = 0: sigma = +1 iff the spin's bit of plane 0 is set.
+ *  - Device pointers are HIP device memory owned by the caller.  Host
+ *    pointers are ordinary host memory owned by the caller.
+ *  - hip_stream is a hipStream_t (0 = the null stream).  Work is enqueued
+ *    asynchronously on it unless stated otherwise.
+ *  - Every function returns ISING_OK or a negative code and, on error,
+ *    enqueues no work; ising_last_error() then describes the failure.
+ */
+#ifndef ISING_H
+#define ISING_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+enum {
+    ISING_OK = 0,
+    ISING_E_BADARG = -1, /* invalid value or null pointer */
+    ISING_E_SIZE = -2,   /* buffer too small, or size outside the supported range */
+    ISING_E_HIP = -3     /* a HIP runtime call or kernel launch failed */
+};
+
+/* A lattice: plain data, owned by the caller, as is the memory it points to. */
+typedef struct ising_lattice {
+    uint64_t *words;    /* device: 2 * ising_words_per_colour(L) words */
+    int64_t L;          /* linear size: even, 4 <= L, with L*L/128 < 2^32 */
+    uint64_t seed;      /* Philox key */
+    uint32_t stream_id; /* counter field that separates lattices sharing a seed; < 2^24 */
+    uint32_t reserved;  /* zero */
+} ising_lattice;
+
+/* Words per colour, ceil(L*L/128); -1 if L is not a supported size. */
+int64_t ising_words_per_colour(int64_t L);
+
+/* The threshold table T[0..4] for (beta, J) (Sec. 2 Metropolis rule with
+ * dE from Eq. (1)); host only, no GPU work.  beta >= 0 and J finite. */
+int ising_thresholds(double beta, double J, uint64_t *T_out);
+
+/* Fills *lat and writes the initial state into d_words (bytes >= 16 *
+ * ising_words_per_colour(L)).  Asynchronous. */
+int ising_init(ising_lattice *lat, uint64_t *d_words, size_t bytes, int64_t L, uint64_t seed,
+               uint32_t stream_id, void *hip_stream);
+
+/* nsweeps checkerboard sweeps at (beta, J), black then white half-sweep,
+ * sweep s using t = 2*(rng_counter + s) + colour (Sec. 2; the counter plays the
+ * role of the paper's Philox offset, Sec. 3.2).  Splitting a run into calls
+ * with consecutive rng_counter gives the same lattice.  Asynchronous. */
+int ising_sweep(const ising_lattice *lat, double beta, double J, int64_t nsweeps,
+                uint64_t rng_counter, void *hip_stream);
+
+/* As ising_sweep, and after sweep s writes the bond sum and magnetisation of
+ * the lattice to d_bond_trace[s] and d_mag_trace[s] (device, nsweeps int64
+ * each).  Asynchronous. */
+int ising_sweep_traced(const ising_lattice *lat, double beta, double J, int64_t nsweeps,
+                       uint64_t rng_counter, int64_t *d_bond_trace, int64_t *d_mag_trace,
+                       void *hip_stream);
+
+/* Writes the bond sum B = sum over bonds of sigma_i sigma_j (energy
+ * E = -J * B, Eq. (1)) and the magnetisation M = sum of sigma (Sec. 5.3) to
+ * the device int64 pointers d_bond and d_mag.  Asynchronous. */
+int ising_observables(const ising_lattice *lat, int64_t *d_bond, int64_t *d_mag,
+                      void *hip_stream);
+
+/* Copies the lattice to host_spins as an L x L row-major int8 array of
+ * +1/-1.  Synchronises hip_stream. */
+int ising_get_spins(const ising_lattice *lat, int8_t *host_spins, void *hip_stream);
+
+/* Overwrites the lattice from an L x L row-major int8 array of +1/-1 (any
+ * other value is rejected).  Synchronises hip_stream. */
+int ising_set_spins(const ising_lattice *lat, const int8_t *host_spins, void *hip_stream);
+
+/* Description of the last error on the calling thread ("" if none). */
+const char *ising_last_error(void);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* ISING_H */

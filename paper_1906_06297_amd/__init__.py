@@ -1,0 +1,7 @@
+"""MI355X (gfx950) checkerboard Metropolis simulation of the 2D Ising model.
+
+The hot path lives in hand-written HIP kernels behind the C ABI of
+``libising.so`` (include/ising.h); this package is the thin Python binding.
+"""
+from ._lib import IsingError, load  # noqa: F401
+from .lattice import Lattice, thresholds, words_per_colour  # noqa: F401

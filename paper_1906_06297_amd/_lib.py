@@ -1,0 +1,80 @@
+"""ctypes binding of libising.so (the C ABI declared in include/ising.h).
+
+Argument marshalling only: every step of the simulation runs in the HIP
+kernels behind the C ABI.  If the built library is missing this raises; there
+is no fallback implementation.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "libising.so")
+
+ISING_OK = 0
+ISING_E_BADARG = -1
+ISING_E_SIZE = -2
+ISING_E_HIP = -3
+
+
+class IsingError(RuntimeError):
+    def __init__(self, code: int, message: str):
+        super().__init__(f"ising error {code}: {message}")
+        self.code = code
+
+
+class LatticeStruct(ctypes.Structure):
+    _fields_ = [
+        ("words", ctypes.c_void_p),
+        ("L", ctypes.c_int64),
+        ("seed", ctypes.c_uint64),
+        ("stream_id", ctypes.c_uint32),
+        ("reserved", ctypes.c_uint32),
+    ]
+
+
+_vp = ctypes.c_void_p
+_i64 = ctypes.c_int64
+_u64 = ctypes.c_uint64
+_u32 = ctypes.c_uint32
+_dbl = ctypes.c_double
+_lat_p = ctypes.POINTER(LatticeStruct)
+
+# name -> (restype, argtypes); mirrors include/ising.h
+SIGNATURES = {
+    "ising_words_per_colour": (_i64, [_i64]),
+    "ising_thresholds": (ctypes.c_int, [_dbl, _dbl, ctypes.POINTER(_u64)]),
+    "ising_init": (ctypes.c_int, [_lat_p, _vp, ctypes.c_size_t, _i64, _u64, _u32, _vp]),
+    "ising_sweep": (ctypes.c_int, [_lat_p, _dbl, _dbl, _i64, _u64, _vp]),
+    "ising_sweep_traced": (ctypes.c_int, [_lat_p, _dbl, _dbl, _i64, _u64, _vp, _vp, _vp]),
+    "ising_observables": (ctypes.c_int, [_lat_p, _vp, _vp, _vp]),
+    "ising_get_spins": (ctypes.c_int, [_lat_p, _vp, _vp]),
+    "ising_set_spins": (ctypes.c_int, [_lat_p, _vp, _vp]),
+    "ising_last_error": (ctypes.c_char_p, []),
+}
+
+_lib = None
+
+
+def load() -> ctypes.CDLL:
+    """Load libising.so; raises if it has not been built."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(LIB_PATH):
+        raise ImportError(f"{LIB_PATH} is not built; run __graft_entry__.build() or "
+                          "python paper_1906_06297_amd/build.py")
+    lib = ctypes.CDLL(LIB_PATH)
+    for name, (res, args) in SIGNATURES.items():
+        fn = getattr(lib, name)
+        fn.restype = res
+        fn.argtypes = args
+    _lib = lib
+    return lib
+
+
+def check(code: int) -> None:
+    if code != ISING_OK:
+        msg = load().ising_last_error().decode(errors="replace")
+        raise IsingError(code, msg)

@@ -1,0 +1,273 @@
+// The C ABI of libising (declared in include/ising.h): argument checks,
+// the host-side threshold table, and the sweep driver.
+#include <hip/hip_runtime.h>
+
+#include <cmath>
+#include <cstdarg>
+#include <cstdio>
+#include <cstring>
+#include <string>
+#include <vector>
+
+#include "../../include/ising.h"
+#include "launch.hpp"
+
+namespace {
+
+thread_local std::string g_error;
+
+int fail(int code, const char *fmt, ...)
+{
+    char buf[512];
+    va_list ap;
+    va_start(ap, fmt);
+    std::vsnprintf(buf, sizeof buf, fmt, ap);
+    va_end(ap);
+    g_error = buf;
+    return code;
+}
+
+int ok()
+{
+    g_error.clear();
+    return ISING_OK;
+}
+
+int hip_fail(hipError_t e, const char *what)
+{
+    return fail(ISING_E_HIP, "%s: %s", what, hipGetErrorString(e));
+}
+
+// Largest supported size: chunk indices must fit the 32-bit counter word.
+constexpr int64_t kMaxL = 741454; // floor(sqrt(128 * (2^32 - 1)))
+
+int check_L(int64_t L)
+{
+    if (L < 4 || (L & 1))
+        return fail(ISING_E_BADARG, "L must be even and >= 4 (got %lld)", (long long)L);
+    if (L > kMaxL)
+        return fail(ISING_E_SIZE, "L = %lld exceeds the supported maximum %lld", (long long)L,
+                    (long long)kMaxL);
+    return ISING_OK;
+}
+
+int check_lattice(const ising_lattice *lat)
+{
+    if (!lat)
+        return fail(ISING_E_BADARG, "null lattice");
+    if (int e = check_L(lat->L))
+        return e;
+    if (!lat->words)
+        return fail(ISING_E_BADARG, "null lattice words");
+    if (lat->stream_id >= (1u << 24))
+        return fail(ISING_E_BADARG, "stream_id must be < 2^24");
+    return ISING_OK;
+}
+
+int check_temperature(double beta, double J)
+{
+    if (!std::isfinite(beta) || beta < 0.0)
+        return fail(ISING_E_BADARG, "beta must be finite and >= 0");
+    if (!std::isfinite(J))
+        return fail(ISING_E_BADARG, "J must be finite");
+    return ISING_OK;
+}
+
+// T[a] = 2^32 for dE <= 0, floor(exp(-beta dE) 2^32) otherwise; dE = 4J(a-2).
+void threshold_table(double beta, double J, uint64_t T[5])
+{
+    for (int a = 0; a < 5; ++a) {
+        const double dE = 4.0 * J * (double)(a - 2);
+        if (dE <= 0.0)
+            T[a] = 1ull << 32;
+        else
+            T[a] = (uint64_t)std::floor(std::exp(-(beta * dE)) * 4294967296.0);
+    }
+}
+
+ising::Accept accept_params(double beta, double J)
+{
+    uint64_t T[5];
+    threshold_table(beta, J, T);
+    ising::Accept ap{};
+    for (int a = 0; a < 5; ++a) {
+        if (T[a] >= (1ull << 32)) {
+            ap.always_mask |= 1u << a;
+        } else if (T[a] > 0) {
+            ap.random_mask |= 1u << a;
+            ap.thr[a] = (uint32_t)T[a];
+        }
+    }
+    return ap;
+}
+
+int64_t words_per_colour(int64_t L) { return (L * L / 2 + 63) / 64; }
+
+int run_sweeps(const ising_lattice *lat, double beta, double J, int64_t nsweeps,
+               uint64_t rng_counter, int64_t *d_bond, int64_t *d_mag, hipStream_t s)
+{
+    const ising::Accept ap = accept_params(beta, J);
+    for (int64_t sw = 0; sw < nsweeps; ++sw) {
+        for (int c = 0; c < 2; ++c) {
+            const uint64_t t = 2 * (rng_counter + (uint64_t)sw) + (uint64_t)c;
+            hipError_t e = ising::launch_half_sweep(lat->words, lat->L, c, ap, t, lat->seed,
+                                                    lat->stream_id, s);
+            if (e != hipSuccess)
+                return hip_fail(e, "half-sweep launch");
+        }
+        if (d_bond) {
+            hipError_t e = ising::launch_observables(lat->words, lat->L, d_bond + sw,
+                                                     d_mag + sw, s);
+            if (e != hipSuccess)
+                return hip_fail(e, "observables launch");
+        }
+    }
+    return ok();
+}
+
+} // namespace
+
+extern "C" {
+
+int64_t ising_words_per_colour(int64_t L)
+{
+    if (check_L(L) != ISING_OK)
+        return -1;
+    return words_per_colour(L);
+}
+
+int ising_thresholds(double beta, double J, uint64_t *T_out)
+{
+    if (!T_out)
+        return fail(ISING_E_BADARG, "null output");
+    if (int e = check_temperature(beta, J))
+        return e;
+    threshold_table(beta, J, T_out);
+    return ok();
+}
+
+int ising_init(ising_lattice *lat, uint64_t *d_words, size_t bytes, int64_t L, uint64_t seed,
+               uint32_t stream_id, void *hip_stream)
+{
+    if (!lat || !d_words)
+        return fail(ISING_E_BADARG, "null lattice or words");
+    if (int e = check_L(L))
+        return e;
+    if (stream_id >= (1u << 24))
+        return fail(ISING_E_BADARG, "stream_id must be < 2^24");
+    const int64_t W = words_per_colour(L);
+    if (bytes < (size_t)(2 * W) * sizeof(uint64_t))
+        return fail(ISING_E_SIZE, "buffer of %zu bytes is smaller than the %lld needed", bytes,
+                    (long long)(16 * W));
+    lat->words = d_words;
+    lat->L = L;
+    lat->seed = seed;
+    lat->stream_id = stream_id;
+    lat->reserved = 0;
+    hipError_t e = ising::launch_init(d_words, L, seed, stream_id, (hipStream_t)hip_stream);
+    if (e != hipSuccess)
+        return hip_fail(e, "init launch");
+    return ok();
+}
+
+int ising_sweep(const ising_lattice *lat, double beta, double J, int64_t nsweeps,
+                uint64_t rng_counter, void *hip_stream)
+{
+    if (int e = check_lattice(lat))
+        return e;
+    if (int e = check_temperature(beta, J))
+        return e;
+    if (nsweeps < 0)
+        return fail(ISING_E_BADARG, "nsweeps must be >= 0");
+    return run_sweeps(lat, beta, J, nsweeps, rng_counter, nullptr, nullptr,
+                      (hipStream_t)hip_stream);
+}
+
+int ising_sweep_traced(const ising_lattice *lat, double beta, double J, int64_t nsweeps,
+                       uint64_t rng_counter, int64_t *d_bond_trace, int64_t *d_mag_trace,
+                       void *hip_stream)
+{
+    if (int e = check_lattice(lat))
+        return e;
+    if (int e = check_temperature(beta, J))
+        return e;
+    if (nsweeps < 0)
+        return fail(ISING_E_BADARG, "nsweeps must be >= 0");
+    if (nsweeps > 0 && (!d_bond_trace || !d_mag_trace))
+        return fail(ISING_E_BADARG, "null trace pointer");
+    return run_sweeps(lat, beta, J, nsweeps, rng_counter, d_bond_trace, d_mag_trace,
+                      (hipStream_t)hip_stream);
+}
+
+int ising_observables(const ising_lattice *lat, int64_t *d_bond, int64_t *d_mag,
+                      void *hip_stream)
+{
+    if (int e = check_lattice(lat))
+        return e;
+    if (!d_bond || !d_mag)
+        return fail(ISING_E_BADARG, "null output pointer");
+    hipError_t e =
+        ising::launch_observables(lat->words, lat->L, d_bond, d_mag, (hipStream_t)hip_stream);
+    if (e != hipSuccess)
+        return hip_fail(e, "observables launch");
+    return ok();
+}
+
+int ising_get_spins(const ising_lattice *lat, int8_t *host_spins, void *hip_stream)
+{
+    if (int e = check_lattice(lat))
+        return e;
+    if (!host_spins)
+        return fail(ISING_E_BADARG, "null host buffer");
+    const int64_t L = lat->L, H = L / 2, W = words_per_colour(L);
+    std::vector<uint64_t> w((size_t)(2 * W));
+    hipStream_t s = (hipStream_t)hip_stream;
+    hipError_t e = hipMemcpyAsync(w.data(), lat->words, w.size() * sizeof(uint64_t),
+                                  hipMemcpyDeviceToHost, s);
+    if (e == hipSuccess)
+        e = hipStreamSynchronize(s);
+    if (e != hipSuccess)
+        return hip_fail(e, "copy to host");
+    for (int64_t i = 0; i < L; ++i)
+        for (int64_t j = 0; j < L; ++j) {
+            const int c = (int)((i + j) & 1);
+            const int64_t n = i * H + (j >> 1);
+            const uint64_t bit = (w[(size_t)(c * W + (n >> 6))] >> (n & 63)) & 1u;
+            host_spins[i * L + j] = bit ? 1 : -1;
+        }
+    return ok();
+}
+
+int ising_set_spins(const ising_lattice *lat, const int8_t *host_spins, void *hip_stream)
+{
+    if (int e = check_lattice(lat))
+        return e;
+    if (!host_spins)
+        return fail(ISING_E_BADARG, "null host buffer");
+    const int64_t L = lat->L, H = L / 2, W = words_per_colour(L);
+    std::vector<uint64_t> w((size_t)(2 * W), 0);
+    for (int64_t i = 0; i < L; ++i)
+        for (int64_t j = 0; j < L; ++j) {
+            const int8_t v = host_spins[i * L + j];
+            if (v != 1 && v != -1)
+                return fail(ISING_E_BADARG, "spin (%lld, %lld) is %d, not +1/-1", (long long)i,
+                            (long long)j, (int)v);
+            if (v == 1) {
+                const int c = (int)((i + j) & 1);
+                const int64_t n = i * H + (j >> 1);
+                w[(size_t)(c * W + (n >> 6))] |= 1ull << (n & 63);
+            }
+        }
+    hipStream_t s = (hipStream_t)hip_stream;
+    hipError_t e = hipMemcpyAsync(lat->words, w.data(), w.size() * sizeof(uint64_t),
+                                  hipMemcpyHostToDevice, s);
+    if (e == hipSuccess)
+        e = hipStreamSynchronize(s);
+    if (e != hipSuccess)
+        return hip_fail(e, "copy to device");
+    return ok();
+}
+
+const char *ising_last_error(void) { return g_error.c_str(); }
+
+} // extern "C"

@@ -1,0 +1,264 @@
+// Device building blocks of the checkerboard Metropolis sweep on gfx950.
+//
+// One 64-bit word holds 64 spins of one colour (bit = 1 <=> +1).  For a word
+// of target spins the kernels build four 64-bit neighbour vectors (up, down,
+// centre, side) from the other colour, count per spin the neighbours that are
+// aligned with it with a bit-sliced adder (the multi-spin coding idea of
+// Sec. 3.3, here at one bit per spin), and take the Metropolis decision
+// (Sec. 2) exactly in integers against the threshold table, comparing the
+// spin's 32-bit uniform most significant bit first, one Philox block (two
+// bit-planes) at a time, and stopping as soon as every spin of the word is
+// decided.
+#pragma once
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace ising {
+
+// ---------------------------------------------------------------- Philox
+// Philox4x32-10 (Salmon, Moraes, Dror, Shaw, SC'11): ten rounds, each two
+// 32x32->64 products; the key advances by the two Weyl constants between
+// rounds.
+struct Block {
+    uint32_t x0, x1, x2, x3;
+};
+
+__host__ __device__ __forceinline__ Block philox4x32_10(uint32_t c0, uint32_t c1, uint32_t c2, uint32_t c3,
+                                               uint32_t k0, uint32_t k1)
+{
+#pragma unroll
+    for (int round = 0; round < 10; ++round) {
+        if (round > 0) {
+            k0 += 0x9E3779B9u;
+            k1 += 0xBB67AE85u;
+        }
+        const uint64_t pa = (uint64_t)0xD2511F53u * c0;
+        const uint64_t pb = (uint64_t)0xCD9E8D57u * c2;
+        const uint32_t n0 = (uint32_t)(pb >> 32) ^ c1 ^ k0;
+        const uint32_t n1 = (uint32_t)pb;
+        const uint32_t n2 = (uint32_t)(pa >> 32) ^ c3 ^ k1;
+        const uint32_t n3 = (uint32_t)pa;
+        c0 = n0;
+        c1 = n1;
+        c2 = n2;
+        c3 = n3;
+    }
+    return Block{c0, c1, c2, c3};
+}
+
+enum : uint32_t { kDomainSweep = 0, kDomainInit = 1 };
+
+// Sweep acceptance parameters of one lattice at one temperature: thresholds
+// of the classes that need a random number, and which classes always flip.
+struct Accept {
+    uint32_t thr[5];      // T[a] for the classes in random_mask (0 < T < 2^32)
+    uint32_t always_mask; // bit a set: T[a] = 2^32
+    uint32_t random_mask; // bit a set: 0 < T[a] < 2^32
+};
+
+// Counter word 0 of a Philox block.
+__host__ __device__ __forceinline__ uint32_t ctr_word0(uint32_t stream_id, uint32_t domain, uint32_t q)
+{
+    return (stream_id << 8) | (domain << 4) | q;
+}
+
+// ----------------------------------------------------- aligned-count classes
+// One-hot masks e[a], a = 0..4: bit set where exactly a of the four
+// neighbours equal the target spin.
+struct Classes {
+    uint64_t e[5];
+};
+
+__host__ __device__ __forceinline__ Classes classify(uint64_t t, uint64_t up, uint64_t dn, uint64_t ce,
+                                            uint64_t sd)
+{
+    const uint64_t x1 = ~(t ^ up), x2 = ~(t ^ dn), x3 = ~(t ^ ce), x4 = ~(t ^ sd);
+    const uint64_t s1 = x1 ^ x2, c1 = x1 & x2;
+    const uint64_t s2 = x3 ^ x4, c2 = x3 & x4;
+    const uint64_t a0 = s1 ^ s2, c3 = s1 & s2;
+    // c3 = 1 forces x1 != x2 and x3 != x4, so at most c1 and c2 are both set
+    const uint64_t a1 = c1 ^ c2 ^ c3, a2 = c1 & c2;
+    Classes k;
+    k.e[4] = a2;
+    k.e[3] = a1 & a0;
+    k.e[2] = a1 & ~a0;
+    k.e[1] = a0 & ~a1;
+    k.e[0] = ~(a0 | a1 | a2);
+    return k;
+}
+
+// Flip mask of one word: exact r < T[a] per spin.  `valid` masks the spins
+// that exist.  The planes of block q come from counter
+// (stream<<8 | q, t_lo, t_hi, chunk).
+__host__ __device__ __forceinline__ uint64_t decide(const Classes &k, uint64_t valid, const Accept &acc_par,
+                                           uint32_t chunk, uint32_t t_lo, uint32_t t_hi,
+                                           uint32_t stream_id, uint32_t key0, uint32_t key1)
+{
+    uint64_t always = 0, pending = 0;
+#pragma unroll
+    for (int a = 0; a < 5; ++a) {
+        if ((acc_par.always_mask >> a) & 1u)
+            always |= k.e[a];
+        if ((acc_par.random_mask >> a) & 1u)
+            pending |= k.e[a];
+    }
+    always &= valid;
+    pending &= valid;
+    uint64_t accepted = 0;
+    for (uint32_t q = 0; q < 16 && pending != 0; ++q) {
+        const Block x = philox4x32_10(ctr_word0(stream_id, kDomainSweep, q), t_lo, t_hi, chunk,
+                                      key0, key1);
+        const uint64_t planes[2] = {(uint64_t)x.x0 | ((uint64_t)x.x1 << 32),
+                                    (uint64_t)x.x2 | ((uint64_t)x.x3 << 32)};
+#pragma unroll
+        for (int h = 0; h < 2; ++h) {
+            const int bit = 31 - (int)(2 * q + h);
+            uint64_t tb = 0;
+#pragma unroll
+            for (int a = 0; a < 5; ++a)
+                if (((acc_par.random_mask >> a) & 1u) && ((acc_par.thr[a] >> bit) & 1u))
+                    tb |= k.e[a];
+            const uint64_t differ = pending & (planes[h] ^ tb);
+            accepted |= differ & tb; // r bit 0 where T bit 1: r < T
+            pending ^= differ;       // decided either way
+        }
+    }
+    return always | accepted; // r == T after 32 planes: not < T, rejected
+}
+
+// ------------------------------------------- general colour-linear geometry
+// 64 consecutive spins of a colour-linear bit string of M spins starting at
+// spin x, cyclically (x taken mod M).  Bits past M in the last word are zero.
+template <typename Ptr>
+__host__ __device__ __forceinline__ uint64_t cyclic_bits(Ptr src, int64_t M, int64_t W, int64_t x)
+{
+    x %= M;
+    if (x < 0)
+        x += M;
+    if (M >= 64) {
+        const int64_t w = x >> 6;
+        const int sh = (int)(x & 63);
+        uint64_t lo = src[w] >> sh;
+        if (sh != 0 && w + 1 < W)
+            lo |= src[w + 1] << (64 - sh);
+        const int64_t avail = M - x;
+        if (avail >= 64)
+            return lo;
+        return (lo & ((1ull << avail) - 1)) | (src[0] << avail);
+    }
+    // fewer than 64 spins: the whole colour sits in word 0; repeat it
+    const uint64_t full = (1ull << M) - 1;
+    const uint64_t p = src[0] & full;
+    const uint64_t rot = x ? (((p >> x) | (p << (M - x))) & full) : p;
+    uint64_t r = 0;
+    for (int64_t f = 0; f < 64; f += M)
+        r |= rot << f;
+    return r;
+}
+
+// Row structure of word `chunk` of colour c: which bits start or end a
+// colour row, and which bits sit on rows whose side neighbour is on the left
+// ((i + c) even: column j/2 - 1 of the other colour, Fig. 2 and Fig. 3).
+struct RowMasks {
+    uint64_t left_rows, row_start, row_end;
+};
+
+__host__ __device__ __forceinline__ RowMasks row_masks(int64_t chunk, int64_t H, int64_t M, int c)
+{
+    const int64_t n0 = chunk << 6;
+    const int64_t end = (n0 + 64 < M) ? n0 + 64 : M;
+    int64_t i = n0 / H;
+    RowMasks r{0, 0, 0};
+    for (int64_t rs = i * H; rs < end; ++i, rs += H) {
+        const int64_t a = (rs > n0 ? rs : n0) - n0;
+        const int64_t b = ((rs + H < end) ? rs + H : end) - n0;
+        const uint64_t seg = (b - a >= 64) ? ~0ull : (((1ull << (b - a)) - 1) << a);
+        if (((i + c) & 1) == 0)
+            r.left_rows |= seg;
+        if (rs >= n0)
+            r.row_start |= 1ull << (rs - n0);
+        if (rs + H - 1 < end)
+            r.row_end |= 1ull << (rs + H - 1 - n0);
+    }
+    return r;
+}
+
+struct Neighbours {
+    uint64_t up, dn, ce, sd;
+};
+
+// The four neighbour vectors of target word `chunk` of colour c, read from
+// the other colour's bit string `src` (any lattice size).
+template <typename Ptr>
+__host__ __device__ __forceinline__ Neighbours neighbours_general(Ptr src, int64_t H, int64_t M, int64_t W,
+                                                         int64_t chunk, int c)
+{
+    const int64_t n0 = chunk << 6;
+    const RowMasks rm = row_masks(chunk, H, M, c);
+    Neighbours nb;
+    nb.ce = cyclic_bits(src, M, W, n0);
+    nb.up = cyclic_bits(src, M, W, n0 - H);
+    nb.dn = cyclic_bits(src, M, W, n0 + H);
+    const uint64_t left = (cyclic_bits(src, M, W, n0 - 1) & ~rm.row_start) |
+                          (cyclic_bits(src, M, W, n0 + H - 1) & rm.row_start);
+    const uint64_t right = (cyclic_bits(src, M, W, n0 + 1) & ~rm.row_end) |
+                           (cyclic_bits(src, M, W, n0 - H + 1) & rm.row_end);
+    nb.sd = (left & rm.left_rows) | (right & ~rm.left_rows);
+    return nb;
+}
+
+__host__ __device__ __forceinline__ uint64_t valid_mask(int64_t chunk, int64_t M)
+{
+    const int64_t n0 = chunk << 6;
+    return (n0 + 64 <= M) ? ~0ull : ((1ull << (M - n0)) - 1);
+}
+
+// Sweep parameters shared by every word of one half-sweep launch.
+struct SweepArgs {
+    Accept ap;
+    uint32_t t_lo, t_hi, stream_id, key0, key1;
+};
+
+// New value of target word `chunk` of colour c, any geometry.
+template <typename Ptr>
+__host__ __device__ __forceinline__ uint64_t update_word_general(uint64_t t, Ptr src, int64_t H,
+                                                                 int64_t M, int64_t W,
+                                                                 int64_t chunk, int c,
+                                                                 const SweepArgs &a)
+{
+    const Neighbours nb = neighbours_general(src, H, M, W, chunk, c);
+    const Classes k = classify(t, nb.up, nb.dn, nb.ce, nb.sd);
+    return t ^ decide(k, valid_mask(chunk, M), a.ap, (uint32_t)chunk, a.t_lo, a.t_hi,
+                      a.stream_id, a.key0, a.key1);
+}
+
+// Row-aligned geometry (each colour row is a whole number of words): the side
+// vector of a target word from the centre source word and the adjacent source
+// word of the same row, left (j/2 - 1) or right (j/2 + 1) neighbours.
+__host__ __device__ __forceinline__ uint64_t side_vector(uint64_t centre, uint64_t adjacent,
+                                                         bool left)
+{
+    return left ? (centre << 1) | (adjacent >> 63) : (centre >> 1) | (adjacent << 63);
+}
+
+// New value of row-aligned target word `chunk` from its four source words.
+__host__ __device__ __forceinline__ uint64_t update_word_rows(uint64_t t, uint64_t up, uint64_t dn,
+                                                              uint64_t centre, uint64_t adjacent,
+                                                              bool left, uint32_t chunk,
+                                                              const SweepArgs &a)
+{
+    const Classes k = classify(t, up, dn, centre, side_vector(centre, adjacent, left));
+    return t ^ decide(k, ~0ull, a.ap, chunk, a.t_lo, a.t_hi, a.stream_id, a.key0, a.key1);
+}
+
+// Initial value of word `chunk` of colour c.
+__host__ __device__ __forceinline__ uint64_t init_word(int64_t chunk, uint32_t c, int64_t M,
+                                                       uint32_t stream_id, uint32_t key0,
+                                                       uint32_t key1)
+{
+    const Block x = philox4x32_10(ctr_word0(stream_id, kDomainInit, 0), c, 0u, (uint32_t)chunk,
+                                  key0, key1);
+    return ((uint64_t)x.x0 | ((uint64_t)x.x1 << 32)) & valid_mask(chunk, M);
+}
+
+} // namespace ising

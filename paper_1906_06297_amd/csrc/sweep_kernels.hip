@@ -1,0 +1,185 @@
+// gfx950 kernels of the checkerboard Metropolis sweep: initial state,
+// half-sweep (general geometry and row-aligned streaming), observables.
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include "ising_device.hpp"
+#include "launch.hpp"
+
+namespace ising {
+
+// ------------------------------------------------------------ initial state
+__global__ __launch_bounds__(256) void k_init(uint64_t *__restrict__ words, int64_t M, int64_t W,
+                                              uint32_t key0, uint32_t key1, uint32_t stream_id)
+{
+    const int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (idx >= 2 * W)
+        return;
+    const uint32_t c = (uint32_t)(idx / W);
+    const int64_t chunk = idx - (int64_t)c * W;
+    words[idx] = init_word(chunk, c, M, stream_id, key0, key1);
+}
+
+// ------------------------------------------------- half-sweep, any geometry
+// One thread per target word; neighbour vectors by cyclic extraction from the
+// other colour (row-straddling words, partial last word, tiny lattices).
+__global__ __launch_bounds__(256) void k_sweep_general(uint64_t *__restrict__ tgt,
+                                                       const uint64_t *__restrict__ src, int64_t H,
+                                                       int64_t M, int64_t W, int c, SweepArgs a)
+{
+    const int64_t chunk = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (chunk >= W)
+        return;
+    tgt[chunk] = update_word_general(tgt[chunk], src, H, M, W, chunk, c, a);
+}
+
+// ------------------------------------------- half-sweep, row-aligned lattices
+// L % 128 == 0: each colour row is Wr = L/128 whole words, so the up, down and
+// centre neighbours of word (i, w) are words (i-1, w), (i+1, w), (i, w) of the
+// other colour and the side neighbour is the centre word shifted by one spin
+// with the adjacent word's edge bit shifted in (Sec. 3.3, Fig. 3).  A thread
+// owns one word column of a band of kRows rows and marches down it keeping
+// three source rows in registers, so each source word is read from memory
+// (kRows + 2) / kRows times.
+constexpr int kRows = 16;
+
+__global__ __launch_bounds__(256) void k_sweep_rows(uint64_t *__restrict__ tgt,
+                                                    const uint64_t *__restrict__ src, int64_t L,
+                                                    int64_t Wr, int64_t blocks_per_band, int c,
+                                                    SweepArgs a)
+{
+    const int64_t band = blockIdx.x / blocks_per_band;
+    const int64_t w = (blockIdx.x - band * blocks_per_band) * (int64_t)blockDim.x + threadIdx.x;
+    if (w >= Wr)
+        return;
+    const int64_t i0 = band * kRows;
+    const int64_t wl = (w == 0) ? Wr - 1 : w - 1;
+    const int64_t wr = (w == Wr - 1) ? 0 : w + 1;
+    uint64_t prev = src[((i0 == 0) ? L - 1 : i0 - 1) * Wr + w];
+    uint64_t cur = src[i0 * Wr + w];
+    for (int r = 0; r < kRows; ++r) {
+        const int64_t i = i0 + r;
+        if (i >= L)
+            break;
+        const int64_t inext = (i + 1 == L) ? 0 : i + 1;
+        const uint64_t next = src[inext * Wr + w];
+        const int64_t idx = i * Wr + w;
+        const bool left = ((i + c) & 1) == 0;
+        const uint64_t adj = src[i * Wr + (left ? wl : wr)];
+        tgt[idx] = update_word_rows(tgt[idx], prev, next, cur, adj, left, (uint32_t)idx, a);
+        prev = cur;
+        cur = next;
+    }
+}
+
+// --------------------------------------------------------------- observables
+__global__ __launch_bounds__(256) void k_fill_i64(int64_t *__restrict__ p, int64_t n, int64_t v)
+{
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < n)
+        p[i] = v;
+}
+
+__device__ __forceinline__ int64_t wave_sum(int64_t v)
+{
+#pragma unroll
+    for (int off = 32; off > 0; off >>= 1)
+        v += __shfl_xor(v, off, 64);
+    return v;
+}
+
+// Bond sum and magnetisation.  Each bond joins a black and a white site, so
+// summing (2a - 4) over black sites (a = aligned neighbours) counts every
+// bond once.  M = sum over both colours of (2*popcount - spins).
+__global__ __launch_bounds__(256) void k_observables(const uint64_t *__restrict__ black,
+                                                     const uint64_t *__restrict__ white, int64_t H,
+                                                     int64_t M, int64_t W, int64_t *bond_out,
+                                                     int64_t *mag_out)
+{
+    int64_t bond = 0, mag = 0;
+    const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+    for (int64_t chunk = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; chunk < W;
+         chunk += stride) {
+        const uint64_t valid = valid_mask(chunk, M);
+        const uint64_t t = black[chunk];
+        const Neighbours nb = neighbours_general(white, H, M, W, chunk, 0);
+        // popcounts are unsigned: widen to signed 64-bit before subtracting
+        const int64_t aligned =
+            (int64_t)__popcll(~(t ^ nb.up) & valid) + (int64_t)__popcll(~(t ^ nb.dn) & valid) +
+            (int64_t)__popcll(~(t ^ nb.ce) & valid) + (int64_t)__popcll(~(t ^ nb.sd) & valid);
+        const int64_t nvalid = (int64_t)__popcll(valid);
+        const int64_t up_spins =
+            (int64_t)__popcll(t & valid) + (int64_t)__popcll(white[chunk] & valid);
+        bond += 2 * aligned - 4 * nvalid;
+        mag += 2 * up_spins - 2 * nvalid;
+    }
+    bond = wave_sum(bond);
+    mag = wave_sum(mag);
+    __shared__ int64_t part[2][4];
+    const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+    if (lane == 0) {
+        part[0][wv] = bond;
+        part[1][wv] = mag;
+    }
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        int64_t b = 0, m = 0;
+        for (int q = 0; q < (int)(blockDim.x >> 6); ++q) {
+            b += part[0][q];
+            m += part[1][q];
+        }
+        atomicAdd((unsigned long long *)bond_out, (unsigned long long)b);
+        atomicAdd((unsigned long long *)mag_out, (unsigned long long)m);
+    }
+}
+
+// ------------------------------------------------------------------ launches
+static inline uint32_t blocks_for(int64_t n, int threads)
+{
+    return (uint32_t)((n + threads - 1) / threads);
+}
+
+hipError_t launch_init(uint64_t *words, int64_t L, uint64_t seed, uint32_t stream_id,
+                       hipStream_t s)
+{
+    const int64_t M = L * L / 2, W = (M + 63) / 64;
+    hipLaunchKernelGGL(k_init, dim3(blocks_for(2 * W, 256)), dim3(256), 0, s, words, M, W,
+                       (uint32_t)seed, (uint32_t)(seed >> 32), stream_id);
+    return hipGetLastError();
+}
+
+hipError_t launch_half_sweep(uint64_t *words, int64_t L, int c, const Accept &ap, uint64_t t,
+                             uint64_t seed, uint32_t stream_id, hipStream_t s)
+{
+    const int64_t H = L / 2, M = L * L / 2, W = (M + 63) / 64;
+    uint64_t *tgt = words + (int64_t)c * W;
+    const uint64_t *src = words + (int64_t)(1 - c) * W;
+    const SweepArgs a{ap, (uint32_t)t, (uint32_t)(t >> 32), stream_id, (uint32_t)seed,
+                      (uint32_t)(seed >> 32)};
+    if (L % 128 == 0) {
+        const int64_t Wr = L / 128;
+        const int threads = Wr >= 256 ? 256 : (Wr >= 64 ? 64 * (int)((Wr + 63) / 64) : 64);
+        const int64_t bpb = (Wr + threads - 1) / threads;
+        const int64_t bands = (L + kRows - 1) / kRows;
+        hipLaunchKernelGGL(k_sweep_rows, dim3((uint32_t)(bands * bpb)), dim3(threads), 0, s, tgt,
+                           src, L, Wr, bpb, c, a);
+    } else {
+        hipLaunchKernelGGL(k_sweep_general, dim3(blocks_for(W, 256)), dim3(256), 0, s, tgt, src,
+                           H, M, W, c, a);
+    }
+    return hipGetLastError();
+}
+
+hipError_t launch_observables(const uint64_t *words, int64_t L, int64_t *bond, int64_t *mag,
+                              hipStream_t s)
+{
+    const int64_t H = L / 2, M = L * L / 2, W = (M + 63) / 64;
+    hipLaunchKernelGGL(k_fill_i64, dim3(1), dim3(64), 0, s, bond, (int64_t)1, (int64_t)0);
+    hipLaunchKernelGGL(k_fill_i64, dim3(1), dim3(64), 0, s, mag, (int64_t)1, (int64_t)0);
+    const uint32_t nb = (uint32_t)((W + 255) / 256 < 4096 ? (W + 255) / 256 : 4096);
+    hipLaunchKernelGGL(k_observables, dim3(nb), dim3(256), 0, s, words, words + W, H, M, W, bond,
+                       mag);
+    return hipGetLastError();
+}
+
+} // namespace ising

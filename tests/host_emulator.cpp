@@ -1,0 +1,61 @@
+// Host emulation of the sweep kernels: runs the same per-word device helpers
+// (ising_device.hpp) over every word on the CPU, with the kernels' indexing,
+// so the kernel logic can be checked against the oracle without a GPU.
+#include <cstdint>
+#include <vector>
+
+#include "../paper_1906_06297_amd/csrc/ising_device.hpp"
+
+using namespace ising;
+
+static Accept accept_from_table(const uint64_t *T)
+{
+    Accept ap{};
+    for (int a = 0; a < 5; ++a) {
+        if (T[a] >= (1ull << 32))
+            ap.always_mask |= 1u << a;
+        else if (T[a] > 0) {
+            ap.random_mask |= 1u << a;
+            ap.thr[a] = (uint32_t)T[a];
+        }
+    }
+    return ap;
+}
+
+extern "C" {
+
+void emu_init(uint64_t *words, int64_t L, uint64_t seed, uint32_t stream)
+{
+    const int64_t M = L * L / 2, W = (M + 63) / 64;
+    for (int64_t idx = 0; idx < 2 * W; ++idx)
+        words[idx] = init_word(idx % W, (uint32_t)(idx / W), M, stream, (uint32_t)seed,
+                               (uint32_t)(seed >> 32));
+}
+
+// rows = 1: the row-aligned kernel's formulas (needs L % 128 == 0).
+void emu_half_sweep(uint64_t *words, int64_t L, int c, const uint64_t *T, uint64_t t,
+                    uint64_t seed, uint32_t stream, int rows)
+{
+    const int64_t H = L / 2, M = L * L / 2, W = (M + 63) / 64;
+    uint64_t *tgt = words + c * W;
+    const uint64_t *src = words + (1 - c) * W;
+    const SweepArgs a{accept_from_table(T), (uint32_t)t, (uint32_t)(t >> 32), stream,
+                      (uint32_t)seed, (uint32_t)(seed >> 32)};
+    if (!rows) {
+        for (int64_t k = 0; k < W; ++k)
+            tgt[k] = update_word_general(tgt[k], src, H, M, W, k, c, a);
+        return;
+    }
+    const int64_t Wr = L / 128;
+    for (int64_t i = 0; i < L; ++i)
+        for (int64_t w = 0; w < Wr; ++w) {
+            const bool left = ((i + c) & 1) == 0;
+            const int64_t adjw = left ? (w == 0 ? Wr - 1 : w - 1) : (w == Wr - 1 ? 0 : w + 1);
+            const int64_t idx = i * Wr + w;
+            tgt[idx] = update_word_rows(tgt[idx], src[((i + L - 1) % L) * Wr + w],
+                                        src[((i + 1) % L) * Wr + w], src[idx], src[i * Wr + adjw],
+                                        left, (uint32_t)idx, a);
+        }
+}
+
+} // extern "C"

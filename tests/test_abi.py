@@ -1,0 +1,103 @@
+"""The C ABI library: loads without a GPU, exports every symbol that
+include/ising.h declares, validates arguments before touching the device,
+and builds the same threshold table as the oracle."""
+import ctypes
+import os
+import re
+
+import numpy as np
+import pytest
+
+import workloads
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+def header_functions():
+    text = open(os.path.join(ROOT, "include", "ising.h")).read()
+    text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+    return sorted(set(re.findall(r"\b(ising_[a-z0-9_]+)\s*\(", text)))
+
+
+@pytest.fixture(scope="module")
+def lib():
+    from paper_1906_06297_amd import _lib
+
+    return _lib.load()
+
+
+def test_exports_every_declared_symbol(lib):
+    names = header_functions()
+    assert "ising_sweep" in names and "ising_init" in names and "ising_observables" in names
+    for n in names:
+        assert hasattr(lib, n), n
+
+
+def test_binding_covers_header(lib):
+    from paper_1906_06297_amd import _lib
+
+    assert set(header_functions()) <= set(_lib.SIGNATURES)
+
+
+def test_words_per_colour(lib):
+    assert lib.ising_words_per_colour(4) == 1
+    assert lib.ising_words_per_colour(24) == 5  # 288 spins per colour
+    assert lib.ising_words_per_colour(64) == 32
+    assert lib.ising_words_per_colour(65536) == 1 << 25
+    for bad in (0, 2, 3, 63, -8, 741456):
+        assert lib.ising_words_per_colour(bad) == -1
+
+
+def test_thresholds_match_oracle(lib, orc):
+    from paper_1906_06297_amd import thresholds
+
+    for J in (1.0, -1.0, 0.5, 0.0):
+        for beta in [0.0, 0.3, workloads.BETA_CRIT_CONFIG, 0.5, 7.0] + list(np.linspace(0.3, 0.6, 32)):
+            assert np.array_equal(thresholds(beta, J), orc.thresholds(beta, J)), (beta, J)
+
+
+def test_argument_errors_without_device(lib):
+    from paper_1906_06297_amd import _lib
+
+    lat = _lib.LatticeStruct()
+    fake = ctypes.c_void_p(0x1000)  # never dereferenced: validation fails first
+    assert lib.ising_init(ctypes.byref(lat), fake, 1 << 20, 63, 1, 0, None) == _lib.ISING_E_BADARG
+    assert b"even" in lib.ising_last_error()
+    assert lib.ising_init(ctypes.byref(lat), fake, 8, 64, 1, 0, None) == _lib.ISING_E_SIZE
+    assert lib.ising_init(None, fake, 1 << 20, 64, 1, 0, None) == _lib.ISING_E_BADARG
+    assert lib.ising_init(ctypes.byref(lat), fake, 1 << 20, 64, 1, 1 << 24, None) == _lib.ISING_E_BADARG
+    good = _lib.LatticeStruct(words=0x1000, L=64, seed=1, stream_id=0)
+    for beta, J, n in ((float("nan"), 1.0, 1), (0.4, float("inf"), 1), (-0.1, 1.0, 1), (0.4, 1.0, -1)):
+        assert lib.ising_sweep(ctypes.byref(good), beta, J, n, 0, None) == _lib.ISING_E_BADARG
+    nowords = _lib.LatticeStruct(words=None, L=64)
+    assert lib.ising_sweep(ctypes.byref(nowords), 0.4, 1.0, 1, 0, None) == _lib.ISING_E_BADARG
+    odd = _lib.LatticeStruct(words=0x1000, L=65)
+    assert lib.ising_sweep(ctypes.byref(odd), 0.4, 1.0, 1, 0, None) == _lib.ISING_E_BADARG
+    assert lib.ising_sweep_traced(ctypes.byref(good), 0.4, 1.0, 3, 0, None, None, None) == _lib.ISING_E_BADARG
+    assert lib.ising_observables(ctypes.byref(good), None, None, None) == _lib.ISING_E_BADARG
+    T = (ctypes.c_uint64 * 5)()
+    assert lib.ising_thresholds(float("nan"), 1.0, T) == _lib.ISING_E_BADARG
+    assert lib.ising_thresholds(0.4, 1.0, T) == _lib.ISING_OK
+    assert lib.ising_last_error() == b""
+
+
+def test_set_spins_rejects_non_spin_values(lib):
+    from paper_1906_06297_amd import _lib
+
+    good = _lib.LatticeStruct(words=0x1000, L=4, seed=1, stream_id=0)
+    s = np.ones((4, 4), np.int8)
+    s[1, 2] = 0
+    assert lib.ising_set_spins(ctypes.byref(good), s.ctypes.data_as(ctypes.c_void_p), None) == _lib.ISING_E_BADARG
+
+
+def test_layout_helper_roundtrip():
+    from layout import pack, unpack
+
+    for L in (4, 6, 10, 24, 64):
+        s = workloads.random_spins(L, L)
+        w = pack(s)
+        assert np.array_equal(unpack(w, L), s)
+        # padding bits beyond the last spin stay zero
+        M = L * L // 2
+        if M % 64:
+            assert int(w[0, -1]) >> (M % 64) == 0 and int(w[1, -1]) >> (M % 64) == 0

@@ -1,0 +1,68 @@
+"""The kernels' per-word logic (the device helpers, compiled for the host)
+against the oracle, bit for bit, on the CPU: general and row-aligned
+geometries, several temperatures and couplings."""
+import ctypes
+import os
+import shutil
+import subprocess
+
+import numpy as np
+import pytest
+
+import workloads
+from layout import pack
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+
+
+@pytest.fixture(scope="module")
+def emu(tmp_path_factory):
+    hipcc = shutil.which("hipcc") or "/opt/rocm/bin/hipcc"
+    if not os.path.exists(hipcc):
+        pytest.skip("hipcc not available")
+    so = str(tmp_path_factory.mktemp("emu") / "libemu.so")
+    subprocess.run([hipcc, "-O2", "-std=c++17", "-fPIC", "-shared", "--offload-arch=gfx950",
+                    "-x", "hip", os.path.join(HERE, "host_emulator.cpp"), "-o", so], check=True,
+                   capture_output=True)
+    lib = ctypes.CDLL(so)
+    u64p = ctypes.POINTER(ctypes.c_uint64)
+    lib.emu_init.argtypes = [u64p, ctypes.c_int64, ctypes.c_uint64, ctypes.c_uint32]
+    lib.emu_half_sweep.argtypes = [u64p, ctypes.c_int64, ctypes.c_int, u64p, ctypes.c_uint64,
+                                   ctypes.c_uint64, ctypes.c_uint32, ctypes.c_int]
+    return lib
+
+
+def _p(a):
+    return a.ctypes.data_as(ctypes.POINTER(ctypes.c_uint64))
+
+
+def run_emu(emu, orc, L, seed, stream, beta, J, n, ctr, rows):
+    W = (L * L // 2 + 63) // 64
+    words = np.zeros(2 * W, dtype=np.uint64)
+    emu.emu_init(_p(words), L, seed, stream)
+    T = np.ascontiguousarray(orc.thresholds(beta, J), dtype=np.uint64)
+    for s in range(n):
+        for c in (0, 1):
+            emu.emu_half_sweep(_p(words), L, c, _p(T), 2 * (ctr + s) + c, seed, stream, rows)
+    return words.reshape(2, W)
+
+
+@pytest.mark.parametrize("L", [4, 6, 8, 10, 12, 16, 24, 30, 48, 64, 96, 100, 128, 256])
+@pytest.mark.parametrize("beta,J", [(0.0, 1.0), (workloads.BETA_CRIT_CONFIG, 1.0), (0.5, 1.0),
+                                    (9.0, 1.0), (0.3, -1.0), (0.4, 0.0)])
+def test_general_kernel_logic(emu, orc, L, beta, J):
+    seed, stream, n, ctr = 77 + L, 5, 4, 3
+    ref = orc.init(L, seed, stream)
+    w0 = run_emu(emu, orc, L, seed, stream, beta, J, 0, ctr, 0)
+    assert np.array_equal(w0, pack(ref))
+    orc.sweeps(ref, beta, J, seed, stream, n, ctr)
+    assert np.array_equal(run_emu(emu, orc, L, seed, stream, beta, J, n, ctr, 0), pack(ref))
+
+
+@pytest.mark.parametrize("L", [128, 256, 512])
+@pytest.mark.parametrize("beta", [0.0, 0.40, workloads.BETA_CRIT_CONFIG, 0.5])
+def test_row_kernel_logic(emu, orc, L, beta):
+    seed, stream, n, ctr = 7, 0, 3, 0
+    ref = orc.init(L, seed, stream)
+    orc.sweeps(ref, beta, 1.0, seed, stream, n, ctr)
+    assert np.array_equal(run_emu(emu, orc, L, seed, stream, beta, 1.0, n, ctr, 1), pack(ref))
