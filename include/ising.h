@@ -104,6 +104,15 @@ int ising_get_spins(const ising_lattice *lat, int8_t *host_spins, void *hip_stre
  * other value is rejected).  Synchronises hip_stream. */
 int ising_set_spins(const ising_lattice *lat, const int8_t *host_spins, void *hip_stream);
 
+/* Selects the half-sweep kernel for later calls in this process, for tests and
+ * measurements: 0 = default (row-aligned sizes, L % 128 == 0, use the
+ * streaming row kernel with its per-wavefront work queue; other sizes the
+ * general kernel), 1 = the general-geometry kernel for every size, 2 = the
+ * row kernel without the work queue.  All choices give identical lattices.
+ * Process-wide setting; not synchronised with calls running on other
+ * threads. */
+int ising_set_sweep_kernel(int variant);
+
 /* Description of the last error on the calling thread ("" if none). */
 const char *ising_last_error(void);
 

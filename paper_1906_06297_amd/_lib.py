@@ -51,6 +51,7 @@ SIGNATURES = {
     "ising_observables": (ctypes.c_int, [_lat_p, _vp, _vp, _vp]),
     "ising_get_spins": (ctypes.c_int, [_lat_p, _vp, _vp]),
     "ising_set_spins": (ctypes.c_int, [_lat_p, _vp, _vp]),
+    "ising_set_sweep_kernel": (ctypes.c_int, [ctypes.c_int]),
     "ising_last_error": (ctypes.c_char_p, []),
 }
 

@@ -16,6 +16,9 @@ namespace {
 
 thread_local std::string g_error;
 
+// Half-sweep kernel selection (for tests and measurements; 0 = default).
+int g_variant = 0;
+
 int fail(int code, const char *fmt, ...)
 {
     char buf[512];
@@ -85,20 +88,22 @@ void threshold_table(double beta, double J, uint64_t T[5])
     }
 }
 
-ising::Accept accept_params(double beta, double J)
+// The two classes with dE > 0 under the Metropolis rule (A: |dE| = 4|J|,
+// B: |dE| = 8|J|) and how each is decided.
+ising::Metro2 metro2_params(double beta, double J)
 {
     uint64_t T[5];
     threshold_table(beta, J, T);
-    ising::Accept ap{};
-    for (int a = 0; a < 5; ++a) {
-        if (T[a] >= (1ull << 32)) {
-            ap.always_mask |= 1u << a;
-        } else if (T[a] > 0) {
-            ap.random_mask |= 1u << a;
-            ap.thr[a] = (uint32_t)T[a];
-        }
-    }
-    return ap;
+    ising::Metro2 m{};
+    m.anti = J < 0.0 ? 1u : 0u;
+    const uint64_t tA = m.anti ? T[1] : T[3], tB = m.anti ? T[0] : T[4];
+    m.alwaysA = tA >= (1ull << 32);
+    m.alwaysB = tB >= (1ull << 32);
+    m.randA = !m.alwaysA && tA > 0;
+    m.randB = !m.alwaysB && tB > 0;
+    m.thrA = m.randA ? (uint32_t)tA : 0u;
+    m.thrB = m.randB ? (uint32_t)tB : 0u;
+    return m;
 }
 
 int64_t words_per_colour(int64_t L) { return (L * L / 2 + 63) / 64; }
@@ -106,12 +111,12 @@ int64_t words_per_colour(int64_t L) { return (L * L / 2 + 63) / 64; }
 int run_sweeps(const ising_lattice *lat, double beta, double J, int64_t nsweeps,
                uint64_t rng_counter, int64_t *d_bond, int64_t *d_mag, hipStream_t s)
 {
-    const ising::Accept ap = accept_params(beta, J);
+    const ising::Metro2 m = metro2_params(beta, J);
     for (int64_t sw = 0; sw < nsweeps; ++sw) {
         for (int c = 0; c < 2; ++c) {
             const uint64_t t = 2 * (rng_counter + (uint64_t)sw) + (uint64_t)c;
-            hipError_t e = ising::launch_half_sweep(lat->words, lat->L, c, ap, t, lat->seed,
-                                                    lat->stream_id, s);
+            hipError_t e = ising::launch_half_sweep(lat->words, lat->L, c, m, t, lat->seed,
+                                                    lat->stream_id, s, g_variant);
             if (e != hipSuccess)
                 return hip_fail(e, "half-sweep launch");
         }
@@ -265,6 +270,14 @@ int ising_set_spins(const ising_lattice *lat, const int8_t *host_spins, void *hi
         e = hipStreamSynchronize(s);
     if (e != hipSuccess)
         return hip_fail(e, "copy to device");
+    return ok();
+}
+
+int ising_set_sweep_kernel(int variant)
+{
+    if (variant < 0 || variant > 2)
+        return fail(ISING_E_BADARG, "sweep kernel variant must be 0, 1 or 2");
+    g_variant = variant;
     return ok();
 }
 

@@ -126,6 +126,88 @@ __host__ __device__ __forceinline__ uint64_t decide(const Classes &k, uint64_t v
     return always | accepted; // r == T after 32 planes: not < T, rejected
 }
 
+// --------------------------------------------- Metropolis, two random classes
+// Under the Metropolis rule (Sec. 2) at most two classes have dE > 0: for
+// J > 0 the spins with a = 3 and a = 4 aligned neighbours (dE = 4J, 8J), for
+// J < 0 those with a = 1 and a = 0.  Call them A (|dE| = 4|J|) and B
+// (|dE| = 8|J|); every other class has dE <= 0 and always flips.
+struct Metro2 {
+    uint32_t thrA, thrB;       // thresholds of A and B when they need a random number
+    uint32_t randA, randB;     // 1: 0 < T < 2^32, compare against thr
+    uint32_t alwaysA, alwaysB; // 1: T = 2^32 (dE rounds to a certain flip)
+    uint32_t anti;             // 1: J < 0 (A = 1 aligned, B = 0 aligned)
+};
+
+// Decision state of one word: flips decided so far, spins still undecided,
+// and which undecided spins belong to class A (the rest are class B).
+struct WordState {
+    uint64_t flips, pending, classA;
+};
+
+__host__ __device__ __forceinline__ WordState start_word(const Classes &k, uint64_t valid,
+                                                         const Metro2 &m)
+{
+    const uint64_t eA = m.anti ? k.e[1] : k.e[3];
+    const uint64_t eB = m.anti ? k.e[0] : k.e[4];
+    const uint64_t base = m.anti ? (k.e[2] | k.e[3] | k.e[4]) : (k.e[0] | k.e[1] | k.e[2]);
+    WordState s;
+    s.flips = (base | (m.alwaysA ? eA : 0) | (m.alwaysB ? eB : 0)) & valid;
+    s.classA = m.randA ? (eA & valid) : 0;
+    s.pending = s.classA | (m.randB ? (eB & valid) : 0);
+    return s;
+}
+
+// All ones where bit `bit` of thr is set, else zero.
+__host__ __device__ __forceinline__ uint64_t bit_mask(uint32_t thr, int bit)
+{
+    return (uint64_t)0 - (uint64_t)((thr >> bit) & 1u);
+}
+
+// One bit-plane of the exact compare r < T: spins whose r bit differs from
+// their threshold bit are decided (accepted where the threshold bit is 1).
+__host__ __device__ __forceinline__ void compare_plane(WordState &s, uint64_t plane, uint64_t mA,
+                                                       uint64_t mB)
+{
+    const uint64_t tb = (s.classA & mA) | (~s.classA & mB);
+    const uint64_t differ = s.pending & (plane ^ tb);
+    s.flips |= differ & tb;
+    s.pending ^= differ;
+}
+
+// Philox block q of word `chunk`: bit-planes 2q and 2q+1.  After the last
+// block a spin still undecided has r == T, which is not < T: rejected.
+__host__ __device__ __forceinline__ void advance_block(WordState &s, uint32_t q, uint32_t chunk,
+                                                       const Metro2 &m, uint32_t t_lo,
+                                                       uint32_t t_hi, uint32_t stream_id,
+                                                       uint32_t key0, uint32_t key1)
+{
+    const Block x =
+        philox4x32_10(ctr_word0(stream_id, kDomainSweep, q), t_lo, t_hi, chunk, key0, key1);
+    const int bit = 31 - 2 * (int)q;
+    compare_plane(s, (uint64_t)x.x0 | ((uint64_t)x.x1 << 32), bit_mask(m.thrA, bit),
+                  bit_mask(m.thrB, bit));
+    compare_plane(s, (uint64_t)x.x2 | ((uint64_t)x.x3 << 32), bit_mask(m.thrA, bit - 1),
+                  bit_mask(m.thrB, bit - 1));
+    if (q == 15)
+        s.pending = 0;
+}
+
+// Sweep parameters shared by every word of one half-sweep launch.
+struct SweepArgs2 {
+    Metro2 m;
+    uint32_t t_lo, t_hi, stream_id, key0, key1;
+};
+
+// Complete decision for one word (all its blocks in order).
+__host__ __device__ __forceinline__ uint64_t decide_word(const Classes &k, uint64_t valid,
+                                                         uint32_t chunk, const SweepArgs2 &a)
+{
+    WordState s = start_word(k, valid, a.m);
+    for (uint32_t q = 0; q < 16 && s.pending != 0; ++q)
+        advance_block(s, q, chunk, a.m, a.t_lo, a.t_hi, a.stream_id, a.key0, a.key1);
+    return s.flips;
+}
+
 // ------------------------------------------- general colour-linear geometry
 // 64 consecutive spins of a colour-linear bit string of M spins starting at
 // spin x, cyclically (x taken mod M).  Bits past M in the last word are zero.
@@ -213,23 +295,16 @@ __host__ __device__ __forceinline__ uint64_t valid_mask(int64_t chunk, int64_t M
     return (n0 + 64 <= M) ? ~0ull : ((1ull << (M - n0)) - 1);
 }
 
-// Sweep parameters shared by every word of one half-sweep launch.
-struct SweepArgs {
-    Accept ap;
-    uint32_t t_lo, t_hi, stream_id, key0, key1;
-};
-
 // New value of target word `chunk` of colour c, any geometry.
 template <typename Ptr>
 __host__ __device__ __forceinline__ uint64_t update_word_general(uint64_t t, Ptr src, int64_t H,
                                                                  int64_t M, int64_t W,
                                                                  int64_t chunk, int c,
-                                                                 const SweepArgs &a)
+                                                                 const SweepArgs2 &a)
 {
     const Neighbours nb = neighbours_general(src, H, M, W, chunk, c);
     const Classes k = classify(t, nb.up, nb.dn, nb.ce, nb.sd);
-    return t ^ decide(k, valid_mask(chunk, M), a.ap, (uint32_t)chunk, a.t_lo, a.t_hi,
-                      a.stream_id, a.key0, a.key1);
+    return t ^ decide_word(k, valid_mask(chunk, M), (uint32_t)chunk, a);
 }
 
 // Row-aligned geometry (each colour row is a whole number of words): the side
@@ -245,10 +320,10 @@ __host__ __device__ __forceinline__ uint64_t side_vector(uint64_t centre, uint64
 __host__ __device__ __forceinline__ uint64_t update_word_rows(uint64_t t, uint64_t up, uint64_t dn,
                                                               uint64_t centre, uint64_t adjacent,
                                                               bool left, uint32_t chunk,
-                                                              const SweepArgs &a)
+                                                              const SweepArgs2 &a)
 {
     const Classes k = classify(t, up, dn, centre, side_vector(centre, adjacent, left));
-    return t ^ decide(k, ~0ull, a.ap, chunk, a.t_lo, a.t_hi, a.stream_id, a.key0, a.key1);
+    return t ^ decide_word(k, ~0ull, chunk, a);
 }
 
 // Initial value of word `chunk` of colour c.

@@ -9,8 +9,13 @@ namespace ising {
 
 hipError_t launch_init(uint64_t *words, int64_t L, uint64_t seed, uint32_t stream_id,
                        hipStream_t s);
-hipError_t launch_half_sweep(uint64_t *words, int64_t L, int c, const Accept &ap, uint64_t t,
-                             uint64_t seed, uint32_t stream_id, hipStream_t s);
+// Half-sweep kernel choice: the default picks the queued row kernel for
+// row-aligned sizes (L % 128 == 0) and the general kernel otherwise.
+enum { kVariantDefault = 0, kVariantGeneral = 1, kVariantRowsPlain = 2 };
+
+hipError_t launch_half_sweep(uint64_t *words, int64_t L, int c, const Metro2 &m, uint64_t t,
+                             uint64_t seed, uint32_t stream_id, hipStream_t s,
+                             int variant = kVariantDefault);
 hipError_t launch_observables(const uint64_t *words, int64_t L, int64_t *bond, int64_t *mag,
                               hipStream_t s);
 

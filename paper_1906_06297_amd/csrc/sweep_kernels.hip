@@ -25,7 +25,7 @@ __global__ __launch_bounds__(256) void k_init(uint64_t *__restrict__ words, int6
 // other colour (row-straddling words, partial last word, tiny lattices).
 __global__ __launch_bounds__(256) void k_sweep_general(uint64_t *__restrict__ tgt,
                                                        const uint64_t *__restrict__ src, int64_t H,
-                                                       int64_t M, int64_t W, int c, SweepArgs a)
+                                                       int64_t M, int64_t W, int c, SweepArgs2 a)
 {
     const int64_t chunk = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (chunk >= W)
@@ -46,7 +46,7 @@ constexpr int kRows = 16;
 __global__ __launch_bounds__(256) void k_sweep_rows(uint64_t *__restrict__ tgt,
                                                     const uint64_t *__restrict__ src, int64_t L,
                                                     int64_t Wr, int64_t blocks_per_band, int c,
-                                                    SweepArgs a)
+                                                    SweepArgs2 a)
 {
     const int64_t band = blockIdx.x / blocks_per_band;
     const int64_t w = (blockIdx.x - band * blocks_per_band) * (int64_t)blockDim.x + threadIdx.x;
@@ -70,6 +70,149 @@ __global__ __launch_bounds__(256) void k_sweep_rows(uint64_t *__restrict__ tgt,
         prev = cur;
         cur = next;
     }
+}
+
+// ------------------------------- half-sweep, row-aligned, with a work queue
+// The lazy compare needs a different number of Philox blocks per word (about
+// 3.8 on average near T_c, up to 16); a wavefront that waits for its slowest
+// word spends about 6.8.  Here every word first gets kStreamBlocks blocks in
+// lock step; words still undecided then go to a per-wavefront queue in LDS,
+// which is drained 64 entries at a time so that every lane works on some
+// undecided word.  Each word still receives its blocks q = 0, 1, 2, ... in
+// order, so the result is the same as deciding each word on its own.
+constexpr int kBandRows = 16;
+constexpr uint32_t kStreamBlocks = 3;
+constexpr int kQueueCap = 128; // < 64 entries left after a drain + 64 pushed per row
+constexpr int kWaves = 4;
+
+struct WaveQueue {
+    uint64_t t[kQueueCap];       // target word before the half-sweep
+    uint64_t flips[kQueueCap];   // flips decided so far
+    uint64_t pending[kQueueCap]; // spins still undecided
+    uint64_t classA[kQueueCap];  // undecided spins of class A
+    uint32_t chunk[kQueueCap];   // word index in its colour
+    uint32_t q[kQueueCap];       // next Philox block
+};
+
+__device__ __forceinline__ uint32_t lanes_below(uint64_t ballot)
+{
+    return __builtin_amdgcn_mbcnt_hi((uint32_t)(ballot >> 32),
+                                     __builtin_amdgcn_mbcnt_lo((uint32_t)ballot, 0u));
+}
+
+// One pass over the last n (<= 64) queue entries: one Philox block each;
+// finished words are stored, the rest written back compacted.  Returns the
+// new queue length.
+__device__ __forceinline__ uint32_t drain_once(WaveQueue &wq, uint32_t qlen, uint32_t n,
+                                               uint64_t *__restrict__ tgt, const SweepArgs2 &a,
+                                               int lane)
+{
+    const uint32_t base = qlen - n;
+    const bool mine = (uint32_t)lane < n;
+    WordState s{0, 0, 0};
+    uint64_t t = 0;
+    uint32_t chunk = 0, q = 0;
+    if (mine) {
+        const uint32_t e = base + (uint32_t)lane;
+        t = wq.t[e];
+        s.flips = wq.flips[e];
+        s.pending = wq.pending[e];
+        s.classA = wq.classA[e];
+        chunk = wq.chunk[e];
+        q = wq.q[e];
+        advance_block(s, q, chunk, a.m, a.t_lo, a.t_hi, a.stream_id, a.key0, a.key1);
+        ++q;
+    }
+    __builtin_amdgcn_wave_barrier();
+    const bool keep = mine && s.pending != 0;
+    if (mine && !keep)
+        tgt[chunk] = t ^ s.flips;
+    const uint64_t bal = __ballot(keep);
+    if (keep) {
+        const uint32_t e = base + lanes_below(bal);
+        wq.t[e] = t;
+        wq.flips[e] = s.flips;
+        wq.pending[e] = s.pending;
+        wq.classA[e] = s.classA;
+        wq.chunk[e] = chunk;
+        wq.q[e] = q;
+    }
+    __builtin_amdgcn_wave_barrier();
+    return base + (uint32_t)__popcll(bal);
+}
+
+// L % 128 == 0.  A wavefront owns 64 consecutive word columns of a band of
+// kBandRows colour rows and marches down it, holding the three source rows it
+// needs in registers; the side neighbour comes from the adjacent word of the
+// same source row (Sec. 3.3, Fig. 3).
+__global__ __launch_bounds__(256) void k_sweep_rows_q(uint64_t *__restrict__ tgt,
+                                                      const uint64_t *__restrict__ src,
+                                                      int64_t L, int64_t Wr, int64_t waves_per_band,
+                                                      int64_t nbands, int c, SweepArgs2 a)
+{
+    __shared__ WaveQueue queues[kWaves];
+    const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+    WaveQueue &wq = queues[wv];
+    const int64_t gwave = (int64_t)blockIdx.x * kWaves + wv;
+    const int64_t band = gwave / waves_per_band;
+    if (band >= nbands)
+        return; // whole wavefront
+    const int64_t w = (gwave - band * waves_per_band) * 64 + lane;
+    const bool active = w < Wr;
+    const int64_t wl = (w == 0) ? Wr - 1 : w - 1;
+    const int64_t wr = (w + 1 >= Wr) ? 0 : w + 1;
+    const int64_t i0 = band * kBandRows;
+    uint64_t prev = 0, cur = 0;
+    if (active) {
+        prev = src[((i0 == 0) ? L - 1 : i0 - 1) * Wr + w];
+        cur = src[i0 * Wr + w];
+    }
+    uint32_t qlen = 0;
+    for (int r = 0; r < kBandRows; ++r) {
+        const int64_t i = i0 + r;
+        if (i >= L)
+            break;
+        const int64_t inext = (i + 1 == L) ? 0 : i + 1;
+        const int64_t idx = i * Wr + w;
+        const bool left = ((i + c) & 1) == 0;
+        uint64_t next = 0, t = 0;
+        WordState s{0, 0, 0};
+        if (active) {
+            next = src[inext * Wr + w];
+            t = tgt[idx];
+            const uint64_t adj = src[i * Wr + (left ? wl : wr)];
+            const Classes k = classify(t, prev, next, cur, side_vector(cur, adj, left));
+            s = start_word(k, ~0ull, a.m);
+        }
+        for (uint32_t q = 0; q < kStreamBlocks; ++q) {
+            if (__ballot(s.pending != 0) == 0)
+                break;
+            if (s.pending != 0)
+                advance_block(s, q, (uint32_t)idx, a.m, a.t_lo, a.t_hi, a.stream_id, a.key0,
+                              a.key1);
+        }
+        const bool push = active && s.pending != 0;
+        if (active && !push)
+            tgt[idx] = t ^ s.flips;
+        const uint64_t bal = __ballot(push);
+        if (push) {
+            const uint32_t e = qlen + lanes_below(bal);
+            wq.t[e] = t;
+            wq.flips[e] = s.flips;
+            wq.pending[e] = s.pending;
+            wq.classA[e] = s.classA;
+            wq.chunk[e] = (uint32_t)idx;
+            wq.q[e] = kStreamBlocks;
+        }
+        __builtin_amdgcn_wave_barrier();
+        qlen += (uint32_t)__popcll(bal);
+        while (qlen >= 64)
+            qlen = drain_once(wq, qlen, 64, tgt, a, lane);
+        prev = cur;
+        cur = next;
+    }
+    while (qlen > 0)
+        qlen = drain_once(wq, qlen, qlen < 64 ? qlen : 64, tgt, a, lane);
 }
 
 // --------------------------------------------------------------- observables
@@ -148,21 +291,29 @@ hipError_t launch_init(uint64_t *words, int64_t L, uint64_t seed, uint32_t strea
     return hipGetLastError();
 }
 
-hipError_t launch_half_sweep(uint64_t *words, int64_t L, int c, const Accept &ap, uint64_t t,
-                             uint64_t seed, uint32_t stream_id, hipStream_t s)
+hipError_t launch_half_sweep(uint64_t *words, int64_t L, int c, const Metro2 &m, uint64_t t,
+                             uint64_t seed, uint32_t stream_id, hipStream_t s, int variant)
 {
     const int64_t H = L / 2, M = L * L / 2, W = (M + 63) / 64;
     uint64_t *tgt = words + (int64_t)c * W;
     const uint64_t *src = words + (int64_t)(1 - c) * W;
-    const SweepArgs a{ap, (uint32_t)t, (uint32_t)(t >> 32), stream_id, (uint32_t)seed,
-                      (uint32_t)(seed >> 32)};
-    if (L % 128 == 0) {
+    const SweepArgs2 a{m, (uint32_t)t, (uint32_t)(t >> 32), stream_id, (uint32_t)seed,
+                       (uint32_t)(seed >> 32)};
+    if (L % 128 == 0 && variant != kVariantGeneral) {
         const int64_t Wr = L / 128;
-        const int threads = Wr >= 256 ? 256 : (Wr >= 64 ? 64 * (int)((Wr + 63) / 64) : 64);
-        const int64_t bpb = (Wr + threads - 1) / threads;
-        const int64_t bands = (L + kRows - 1) / kRows;
-        hipLaunchKernelGGL(k_sweep_rows, dim3((uint32_t)(bands * bpb)), dim3(threads), 0, s, tgt,
-                           src, L, Wr, bpb, c, a);
+        if (variant == kVariantRowsPlain) {
+            const int threads = Wr >= 256 ? 256 : (Wr >= 64 ? 64 * (int)((Wr + 63) / 64) : 64);
+            const int64_t bpb = (Wr + threads - 1) / threads;
+            const int64_t bands = (L + kRows - 1) / kRows;
+            hipLaunchKernelGGL(k_sweep_rows, dim3((uint32_t)(bands * bpb)), dim3(threads), 0, s,
+                               tgt, src, L, Wr, bpb, c, a);
+        } else {
+            const int64_t wpb = (Wr + 63) / 64;
+            const int64_t nbands = (L + kBandRows - 1) / kBandRows;
+            const int64_t waves = wpb * nbands;
+            hipLaunchKernelGGL(k_sweep_rows_q, dim3((uint32_t)((waves + kWaves - 1) / kWaves)),
+                               dim3(64 * kWaves), 0, s, tgt, src, L, Wr, wpb, nbands, c, a);
+        }
     } else {
         hipLaunchKernelGGL(k_sweep_general, dim3(blocks_for(W, 256)), dim3(256), 0, s, tgt, src,
                            H, M, W, c, a);

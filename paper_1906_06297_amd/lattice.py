@@ -27,6 +27,11 @@ def thresholds(beta: float, J: float) -> np.ndarray:
     return np.array(list(T), dtype=np.uint64)
 
 
+def set_sweep_kernel(variant: int) -> None:
+    """0 = default, 1 = general-geometry kernel, 2 = row kernel without work queue."""
+    _lib.check(_lib.load().ising_set_sweep_kernel(int(variant)))
+
+
 def _stream_handle(stream=None):
     s = stream if stream is not None else torch.cuda.current_stream()
     return ctypes.c_void_p(s.cuda_stream)

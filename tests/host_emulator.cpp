@@ -8,18 +8,19 @@
 
 using namespace ising;
 
-static Accept accept_from_table(const uint64_t *T)
+// The two dE > 0 classes of the table, as the library's host code maps them.
+static Metro2 metro2_from_table(const uint64_t *T, int anti)
 {
-    Accept ap{};
-    for (int a = 0; a < 5; ++a) {
-        if (T[a] >= (1ull << 32))
-            ap.always_mask |= 1u << a;
-        else if (T[a] > 0) {
-            ap.random_mask |= 1u << a;
-            ap.thr[a] = (uint32_t)T[a];
-        }
-    }
-    return ap;
+    Metro2 m{};
+    m.anti = (uint32_t)anti;
+    const uint64_t tA = anti ? T[1] : T[3], tB = anti ? T[0] : T[4];
+    m.alwaysA = tA >= (1ull << 32);
+    m.alwaysB = tB >= (1ull << 32);
+    m.randA = !m.alwaysA && tA > 0;
+    m.randB = !m.alwaysB && tB > 0;
+    m.thrA = m.randA ? (uint32_t)tA : 0u;
+    m.thrB = m.randB ? (uint32_t)tB : 0u;
+    return m;
 }
 
 extern "C" {
@@ -33,14 +34,14 @@ void emu_init(uint64_t *words, int64_t L, uint64_t seed, uint32_t stream)
 }
 
 // rows = 1: the row-aligned kernel's formulas (needs L % 128 == 0).
-void emu_half_sweep(uint64_t *words, int64_t L, int c, const uint64_t *T, uint64_t t,
+void emu_half_sweep(uint64_t *words, int64_t L, int c, const uint64_t *T, int anti, uint64_t t,
                     uint64_t seed, uint32_t stream, int rows)
 {
     const int64_t H = L / 2, M = L * L / 2, W = (M + 63) / 64;
     uint64_t *tgt = words + c * W;
     const uint64_t *src = words + (1 - c) * W;
-    const SweepArgs a{accept_from_table(T), (uint32_t)t, (uint32_t)(t >> 32), stream,
-                      (uint32_t)seed, (uint32_t)(seed >> 32)};
+    const SweepArgs2 a{metro2_from_table(T, anti), (uint32_t)t, (uint32_t)(t >> 32), stream,
+                       (uint32_t)seed, (uint32_t)(seed >> 32)};
     if (!rows) {
         for (int64_t k = 0; k < W; ++k)
             tgt[k] = update_word_general(tgt[k], src, H, M, W, k, c, a);

@@ -155,3 +155,32 @@ def test_headline_size_sampled_windows(gpu, orc, beta):
         bits = (word >> (jc & 63).astype(np.uint64)) & np.uint64(1)
         got = np.where(bits == 1, 1, -1).astype(np.int8)
         assert np.array_equal(got, inner), f"window at {(ci, cj)} differs"
+
+
+@pytest.mark.parametrize("variant", [0, 1, 2])
+@pytest.mark.parametrize("L,nsw", [(128, 6), (384, 6), (1024, 4), (8192, 2), (8320, 2)])
+@pytest.mark.parametrize("beta,J", [(workloads.BETA_CRIT_CONFIG, 1.0), (0.40, 1.0), (0.5, 1.0),
+                                    (0.33, -1.0), (0.0, 1.0), (6.0, 1.0)])
+def test_every_kernel_variant_bit_exact(gpu, orc, variant, L, nsw, beta, J):
+    """Default (queued row kernel), general-geometry kernel and the row kernel
+    without the queue give the oracle's lattice; sizes include wavefronts with
+    idle lanes (384: 3 words per colour row; 8320: 65)."""
+    say(f"variant {variant} L={L} beta={beta} J={J}")
+    seed, stream = 300 + L, 1
+    gpu.set_sweep_kernel(variant)
+    try:
+        lat = gpu.Lattice(L, seed=seed, stream_id=stream)
+        lat.sweep(beta, J, nsw, 2)
+        got = lat.packed()
+    finally:
+        gpu.set_sweep_kernel(0)
+    key = (L, nsw, beta, J, seed, stream)
+    ref = _ref_cache.get(key)
+    if ref is None:
+        s = orc.init(L, seed, stream)
+        orc.sweeps(s, beta, J, seed, stream, nsw, 2)
+        ref = _ref_cache[key] = pack(s)
+    assert np.array_equal(got, ref)
+
+
+_ref_cache = {}

@@ -27,8 +27,8 @@ def emu(tmp_path_factory):
     lib = ctypes.CDLL(so)
     u64p = ctypes.POINTER(ctypes.c_uint64)
     lib.emu_init.argtypes = [u64p, ctypes.c_int64, ctypes.c_uint64, ctypes.c_uint32]
-    lib.emu_half_sweep.argtypes = [u64p, ctypes.c_int64, ctypes.c_int, u64p, ctypes.c_uint64,
-                                   ctypes.c_uint64, ctypes.c_uint32, ctypes.c_int]
+    lib.emu_half_sweep.argtypes = [u64p, ctypes.c_int64, ctypes.c_int, u64p, ctypes.c_int,
+                                   ctypes.c_uint64, ctypes.c_uint64, ctypes.c_uint32, ctypes.c_int]
     return lib
 
 
@@ -43,7 +43,7 @@ def run_emu(emu, orc, L, seed, stream, beta, J, n, ctr, rows):
     T = np.ascontiguousarray(orc.thresholds(beta, J), dtype=np.uint64)
     for s in range(n):
         for c in (0, 1):
-            emu.emu_half_sweep(_p(words), L, c, _p(T), 2 * (ctr + s) + c, seed, stream, rows)
+            emu.emu_half_sweep(_p(words), L, c, _p(T), int(J < 0), 2 * (ctr + s) + c, seed, stream, rows)
     return words.reshape(2, W)
 
 
