@@ -75,6 +75,9 @@ def main() -> int:
     ap.add_argument("--warmup", type=int, default=2)
     ap.add_argument("--no-cpu-baseline", action="store_true",
                     help="skip the CPU oracle timing (for profiler runs)")
+    ap.add_argument("--copy-calibration", action="store_true",
+                    help="also run three plain 1 GiB device-to-device copies, whose HBM counter "
+                         "readings scale the profiler's byte counts")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py measures one GPU; --gpus {args.gpus} is not supported (the sweep is "
@@ -161,6 +164,14 @@ def main() -> int:
             "alg_bytes_per_launch": alg_bytes,
         },
     }
+    if args.copy_calibration:
+        del bufs, lats
+        a = torch.empty(1 << 27, dtype=torch.int64, device="cuda").fill_(1)
+        b = torch.empty_like(a)
+        for _ in range(3):
+            b.copy_(a)
+        torch.cuda.synchronize()
+        out["copy_calibration_bytes"] = a.numel() * 8
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline()
     print(json.dumps(out), flush=True)

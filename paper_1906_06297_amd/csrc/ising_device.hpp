@@ -192,6 +192,42 @@ __host__ __device__ __forceinline__ void advance_block(WordState &s, uint32_t q,
         s.pending = 0;
 }
 
+// As compare_plane, for threshold bits known to be the same for every lane:
+// the four (bit of T_A, bit of T_B) cases reduce to fewer operations.
+__host__ __device__ __forceinline__ void compare_plane_uniform(WordState &s, uint64_t plane,
+                                                               bool bitA, bool bitB)
+{
+    if (!bitA && !bitB) { // threshold bit 0: a set r bit rejects, a clear one stays equal
+        s.pending &= ~plane;
+    } else if (bitA && bitB) { // threshold bit 1: a clear r bit accepts
+        s.flips |= s.pending & ~plane;
+        s.pending &= plane;
+    } else {
+        const uint64_t tb = bitA ? s.classA : ~s.classA;
+        const uint64_t differ = s.pending & (plane ^ tb);
+        s.flips |= differ & tb;
+        s.pending ^= differ;
+    }
+}
+
+// advance_block for a block index q that is the same for every lane.
+__host__ __device__ __forceinline__ void advance_block_uniform(WordState &s, uint32_t q,
+                                                               uint32_t chunk, const Metro2 &m,
+                                                               uint32_t t_lo, uint32_t t_hi,
+                                                               uint32_t stream_id, uint32_t key0,
+                                                               uint32_t key1)
+{
+    const Block x =
+        philox4x32_10(ctr_word0(stream_id, kDomainSweep, q), t_lo, t_hi, chunk, key0, key1);
+    const int bit = 31 - 2 * (int)q;
+    compare_plane_uniform(s, (uint64_t)x.x0 | ((uint64_t)x.x1 << 32), (m.thrA >> bit) & 1u,
+                          (m.thrB >> bit) & 1u);
+    compare_plane_uniform(s, (uint64_t)x.x2 | ((uint64_t)x.x3 << 32), (m.thrA >> (bit - 1)) & 1u,
+                          (m.thrB >> (bit - 1)) & 1u);
+    if (q == 15)
+        s.pending = 0;
+}
+
 // Sweep parameters shared by every word of one half-sweep launch.
 struct SweepArgs2 {
     Metro2 m;

@@ -76,13 +76,15 @@ __global__ __launch_bounds__(256) void k_sweep_rows(uint64_t *__restrict__ tgt,
 // The lazy compare needs a different number of Philox blocks per word (about
 // 3.8 on average near T_c, up to 16); a wavefront that waits for its slowest
 // word spends about 6.8.  Here every word first gets kStreamBlocks blocks in
-// lock step; words still undecided then go to a per-wavefront queue in LDS,
-// which is drained 64 entries at a time so that every lane works on some
+// lock step; words still undecided then go to a per-wavefront FIFO queue in
+// LDS, which is drained 64 entries at a time so that every lane works on some
 // undecided word.  Each word still receives its blocks q = 0, 1, 2, ... in
-// order, so the result is the same as deciding each word on its own.
-constexpr int kBandRows = 16;
+// order, so the result is the same as deciding each word on its own.  The
+// FIFO order finishes words soon after their row, so partly written cache
+// lines are completed before they leave L2.
+constexpr int kBandRows = 32;
 constexpr uint32_t kStreamBlocks = 3;
-constexpr int kQueueCap = 128; // < 64 entries left after a drain + 64 pushed per row
+constexpr uint32_t kQueueCap = 128; // < 64 entries left after a drain + 64 pushed per row
 constexpr int kWaves = 4;
 
 struct WaveQueue {
@@ -100,20 +102,29 @@ __device__ __forceinline__ uint32_t lanes_below(uint64_t ballot)
                                      __builtin_amdgcn_mbcnt_lo((uint32_t)ballot, 0u));
 }
 
-// One pass over the last n (<= 64) queue entries: one Philox block each;
-// finished words are stored, the rest written back compacted.  Returns the
-// new queue length.
-__device__ __forceinline__ uint32_t drain_once(WaveQueue &wq, uint32_t qlen, uint32_t n,
-                                               uint64_t *__restrict__ tgt, const SweepArgs2 &a,
-                                               int lane)
+__device__ __forceinline__ void queue_put(WaveQueue &wq, uint32_t e, uint64_t t,
+                                          const WordState &s, uint32_t chunk, uint32_t q)
 {
-    const uint32_t base = qlen - n;
+    wq.t[e] = t;
+    wq.flips[e] = s.flips;
+    wq.pending[e] = s.pending;
+    wq.classA[e] = s.classA;
+    wq.chunk[e] = chunk;
+    wq.q[e] = q;
+}
+
+// One pass over the oldest n (<= 64) queue entries: one Philox block each;
+// finished words are stored, the rest appended again at the tail.
+__device__ __forceinline__ void drain_once(WaveQueue &wq, uint32_t &head, uint32_t &len,
+                                           uint32_t n, uint64_t *__restrict__ tgt,
+                                           const SweepArgs2 &a, int lane)
+{
     const bool mine = (uint32_t)lane < n;
     WordState s{0, 0, 0};
     uint64_t t = 0;
     uint32_t chunk = 0, q = 0;
     if (mine) {
-        const uint32_t e = base + (uint32_t)lane;
+        const uint32_t e = (head + (uint32_t)lane) & (kQueueCap - 1);
         t = wq.t[e];
         s.flips = wq.flips[e];
         s.pending = wq.pending[e];
@@ -124,56 +135,52 @@ __device__ __forceinline__ uint32_t drain_once(WaveQueue &wq, uint32_t qlen, uin
         ++q;
     }
     __builtin_amdgcn_wave_barrier();
+    head = (head + n) & (kQueueCap - 1);
+    len -= n;
     const bool keep = mine && s.pending != 0;
     if (mine && !keep)
         tgt[chunk] = t ^ s.flips;
     const uint64_t bal = __ballot(keep);
-    if (keep) {
-        const uint32_t e = base + lanes_below(bal);
-        wq.t[e] = t;
-        wq.flips[e] = s.flips;
-        wq.pending[e] = s.pending;
-        wq.classA[e] = s.classA;
-        wq.chunk[e] = chunk;
-        wq.q[e] = q;
-    }
+    if (keep)
+        queue_put(wq, (head + len + lanes_below(bal)) & (kQueueCap - 1), t, s, chunk, q);
     __builtin_amdgcn_wave_barrier();
-    return base + (uint32_t)__popcll(bal);
+    len += (uint32_t)__popcll(bal);
 }
 
 // L % 128 == 0.  A wavefront owns 64 consecutive word columns of a band of
 // kBandRows colour rows and marches down it, holding the three source rows it
 // needs in registers; the side neighbour comes from the adjacent word of the
-// same source row (Sec. 3.3, Fig. 3).
+// same source row (Sec. 3.3, Fig. 3).  Word indices fit in 32 bits.
 __global__ __launch_bounds__(256) void k_sweep_rows_q(uint64_t *__restrict__ tgt,
                                                       const uint64_t *__restrict__ src,
-                                                      int64_t L, int64_t Wr, int64_t waves_per_band,
-                                                      int64_t nbands, int c, SweepArgs2 a)
+                                                      uint32_t L, uint32_t Wr,
+                                                      uint32_t waves_per_band, uint32_t nbands,
+                                                      int c, SweepArgs2 a)
 {
     __shared__ WaveQueue queues[kWaves];
     const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
     WaveQueue &wq = queues[wv];
-    const int64_t gwave = (int64_t)blockIdx.x * kWaves + wv;
-    const int64_t band = gwave / waves_per_band;
+    const uint32_t gwave = blockIdx.x * kWaves + wv;
+    const uint32_t band = gwave / waves_per_band;
     if (band >= nbands)
         return; // whole wavefront
-    const int64_t w = (gwave - band * waves_per_band) * 64 + lane;
+    const uint32_t w = (gwave - band * waves_per_band) * 64 + lane;
     const bool active = w < Wr;
-    const int64_t wl = (w == 0) ? Wr - 1 : w - 1;
-    const int64_t wr = (w + 1 >= Wr) ? 0 : w + 1;
-    const int64_t i0 = band * kBandRows;
+    const uint32_t wl = (w == 0) ? Wr - 1 : w - 1;
+    const uint32_t wr = (w + 1 >= Wr) ? 0 : w + 1;
+    const uint32_t i0 = band * kBandRows;
     uint64_t prev = 0, cur = 0;
     if (active) {
         prev = src[((i0 == 0) ? L - 1 : i0 - 1) * Wr + w];
         cur = src[i0 * Wr + w];
     }
-    uint32_t qlen = 0;
+    uint32_t head = 0, len = 0;
     for (int r = 0; r < kBandRows; ++r) {
-        const int64_t i = i0 + r;
+        const uint32_t i = i0 + r;
         if (i >= L)
             break;
-        const int64_t inext = (i + 1 == L) ? 0 : i + 1;
-        const int64_t idx = i * Wr + w;
+        const uint32_t inext = (i + 1 == L) ? 0 : i + 1;
+        const uint32_t idx = i * Wr + w;
         const bool left = ((i + c) & 1) == 0;
         uint64_t next = 0, t = 0;
         WordState s{0, 0, 0};
@@ -184,35 +191,30 @@ __global__ __launch_bounds__(256) void k_sweep_rows_q(uint64_t *__restrict__ tgt
             const Classes k = classify(t, prev, next, cur, side_vector(cur, adj, left));
             s = start_word(k, ~0ull, a.m);
         }
+#pragma unroll
         for (uint32_t q = 0; q < kStreamBlocks; ++q) {
             if (__ballot(s.pending != 0) == 0)
                 break;
             if (s.pending != 0)
-                advance_block(s, q, (uint32_t)idx, a.m, a.t_lo, a.t_hi, a.stream_id, a.key0,
-                              a.key1);
+                advance_block_uniform(s, q, idx, a.m, a.t_lo, a.t_hi, a.stream_id, a.key0,
+                                      a.key1);
         }
         const bool push = active && s.pending != 0;
         if (active && !push)
             tgt[idx] = t ^ s.flips;
         const uint64_t bal = __ballot(push);
-        if (push) {
-            const uint32_t e = qlen + lanes_below(bal);
-            wq.t[e] = t;
-            wq.flips[e] = s.flips;
-            wq.pending[e] = s.pending;
-            wq.classA[e] = s.classA;
-            wq.chunk[e] = (uint32_t)idx;
-            wq.q[e] = kStreamBlocks;
-        }
+        if (push)
+            queue_put(wq, (head + len + lanes_below(bal)) & (kQueueCap - 1), t, s, idx,
+                      kStreamBlocks);
         __builtin_amdgcn_wave_barrier();
-        qlen += (uint32_t)__popcll(bal);
-        while (qlen >= 64)
-            qlen = drain_once(wq, qlen, 64, tgt, a, lane);
+        len += (uint32_t)__popcll(bal);
+        while (len >= 64)
+            drain_once(wq, head, len, 64, tgt, a, lane);
         prev = cur;
         cur = next;
     }
-    while (qlen > 0)
-        qlen = drain_once(wq, qlen, qlen < 64 ? qlen : 64, tgt, a, lane);
+    while (len > 0)
+        drain_once(wq, head, len, len < 64 ? len : 64, tgt, a, lane);
 }
 
 // --------------------------------------------------------------- observables
@@ -312,7 +314,8 @@ hipError_t launch_half_sweep(uint64_t *words, int64_t L, int c, const Metro2 &m,
             const int64_t nbands = (L + kBandRows - 1) / kBandRows;
             const int64_t waves = wpb * nbands;
             hipLaunchKernelGGL(k_sweep_rows_q, dim3((uint32_t)((waves + kWaves - 1) / kWaves)),
-                               dim3(64 * kWaves), 0, s, tgt, src, L, Wr, wpb, nbands, c, a);
+                               dim3(64 * kWaves), 0, s, tgt, src, (uint32_t)L, (uint32_t)Wr,
+                               (uint32_t)wpb, (uint32_t)nbands, c, a);
         }
     } else {
         hipLaunchKernelGGL(k_sweep_general, dim3(blocks_for(W, 256)), dim3(256), 0, s, tgt, src,

@@ -33,7 +33,21 @@ void emu_init(uint64_t *words, int64_t L, uint64_t seed, uint32_t stream)
                                (uint32_t)(seed >> 32));
 }
 
-// rows = 1: the row-aligned kernel's formulas (needs L % 128 == 0).
+// The queued row kernel's sequence for one word: the first three blocks with
+// the uniform-threshold compare, the rest with the per-lane compare.
+static uint64_t decide_queued(const Classes &k, uint32_t chunk, const SweepArgs2 &a)
+{
+    WordState s = start_word(k, ~0ull, a.m);
+    uint32_t q = 0;
+    for (; q < 3 && s.pending != 0; ++q)
+        advance_block_uniform(s, q, chunk, a.m, a.t_lo, a.t_hi, a.stream_id, a.key0, a.key1);
+    for (; q < 16 && s.pending != 0; ++q)
+        advance_block(s, q, chunk, a.m, a.t_lo, a.t_hi, a.stream_id, a.key0, a.key1);
+    return s.flips;
+}
+
+// rows = 1: the row-aligned kernel's formulas (needs L % 128 == 0);
+// rows = 2: the same with the queued kernel's compare sequence.
 void emu_half_sweep(uint64_t *words, int64_t L, int c, const uint64_t *T, int anti, uint64_t t,
                     uint64_t seed, uint32_t stream, int rows)
 {
@@ -53,9 +67,16 @@ void emu_half_sweep(uint64_t *words, int64_t L, int c, const uint64_t *T, int an
             const bool left = ((i + c) & 1) == 0;
             const int64_t adjw = left ? (w == 0 ? Wr - 1 : w - 1) : (w == Wr - 1 ? 0 : w + 1);
             const int64_t idx = i * Wr + w;
-            tgt[idx] = update_word_rows(tgt[idx], src[((i + L - 1) % L) * Wr + w],
-                                        src[((i + 1) % L) * Wr + w], src[idx], src[i * Wr + adjw],
-                                        left, (uint32_t)idx, a);
+            if (rows == 2) {
+                const Classes k = classify(tgt[idx], src[((i + L - 1) % L) * Wr + w],
+                                           src[((i + 1) % L) * Wr + w], src[idx],
+                                           side_vector(src[idx], src[i * Wr + adjw], left));
+                tgt[idx] ^= decide_queued(k, (uint32_t)idx, a);
+            } else {
+                tgt[idx] = update_word_rows(tgt[idx], src[((i + L - 1) % L) * Wr + w],
+                                            src[((i + 1) % L) * Wr + w], src[idx],
+                                            src[i * Wr + adjw], left, (uint32_t)idx, a);
+            }
         }
 }
 

@@ -59,10 +59,12 @@ def test_general_kernel_logic(emu, orc, L, beta, J):
     assert np.array_equal(run_emu(emu, orc, L, seed, stream, beta, J, n, ctr, 0), pack(ref))
 
 
+@pytest.mark.parametrize("rows", [1, 2])
 @pytest.mark.parametrize("L", [128, 256, 512])
-@pytest.mark.parametrize("beta", [0.0, 0.40, workloads.BETA_CRIT_CONFIG, 0.5])
-def test_row_kernel_logic(emu, orc, L, beta):
+@pytest.mark.parametrize("beta,J", [(0.0, 1.0), (0.40, 1.0), (workloads.BETA_CRIT_CONFIG, 1.0),
+                                    (0.5, 1.0), (0.3, -1.0), (7.0, 1.0)])
+def test_row_kernel_logic(emu, orc, rows, L, beta, J):
     seed, stream, n, ctr = 7, 0, 3, 0
     ref = orc.init(L, seed, stream)
-    orc.sweeps(ref, beta, 1.0, seed, stream, n, ctr)
-    assert np.array_equal(run_emu(emu, orc, L, seed, stream, beta, 1.0, n, ctr, 1), pack(ref))
+    orc.sweeps(ref, beta, J, seed, stream, n, ctr)
+    assert np.array_equal(run_emu(emu, orc, L, seed, stream, beta, J, n, ctr, rows), pack(ref))
