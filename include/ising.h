@@ -104,6 +104,71 @@ int ising_get_spins(const ising_lattice *lat, int8_t *host_spins, void *hip_stre
  * other value is rejected).  Synchronises hip_stream. */
 int ising_set_spins(const ising_lattice *lat, const int8_t *host_spins, void *hip_stream);
 
+/* ------------------------------------------------------------------------
+ * Batches of independent lattices (each L <= 722, so that a lattice fits in
+ * LDS), all advanced by one persistent kernel launch.  Each lattice follows
+ * exactly the single-lattice rules above with its own seed, stream id and
+ * beta; J is shared.  Lattice q occupies 2 * ising_words_per_colour(L_q)
+ * words of one caller-owned device buffer, lattices in order, so any lattice
+ * can also be used with the single-lattice calls (ising_batch_lattice).
+ * The batch object is owned by the library (ising_batch_destroy); it keeps
+ * the batch's sweep counter on the device.  Calls on one batch must not
+ * overlap from several host threads.
+ * ------------------------------------------------------------------------ */
+typedef struct ising_batch ising_batch;
+
+/* Total words of a batch buffer; -1 if some L is unsupported. */
+int64_t ising_batch_words(int32_t n, const int64_t *Ls);
+
+/* Creates a batch over d_words (bytes >= 8 * ising_batch_words(n, Ls)).
+ * Ls, betas, seeds, stream_ids: host arrays of n entries.  Synchronous;
+ * allocates the batch's device descriptors and sets its counter to 0. */
+int ising_batch_create(ising_batch **out, int32_t n, const int64_t *Ls, const double *betas,
+                       double J, const uint64_t *seeds, const uint32_t *stream_ids,
+                       uint64_t *d_words, size_t bytes);
+
+/* Frees what ising_batch_create allocated (not the caller's buffer). */
+int ising_batch_destroy(ising_batch *b);
+
+/* A single-lattice view of lattice q (words inside the batch buffer). */
+int ising_batch_lattice(const ising_batch *b, int32_t q, ising_lattice *out);
+
+/* Initial state of every lattice (same rule as ising_init).  Asynchronous. */
+int ising_batch_init(ising_batch *b, void *hip_stream);
+
+/* nsweeps sweeps of every lattice, sweep s of lattice q with
+ * t = 2*(counter + s) + colour, then counter += nsweeps; the counter is the
+ * batch's own, on the device, so consecutive calls continue every chain
+ * exactly as one longer call.  The three kernels of one call (queue reset,
+ * persistent sweep, counter advance) are captured once per nsweeps value as a
+ * HIP graph and replayed.  Asynchronous. */
+int ising_batch_sweep(ising_batch *b, int64_t nsweeps, void *hip_stream);
+
+/* Sets / reads the batch's sweep counter.  Synchronise hip_stream. */
+int ising_batch_set_counter(ising_batch *b, uint64_t rng_counter, void *hip_stream);
+int ising_batch_get_counter(const ising_batch *b, uint64_t *rng_counter, void *hip_stream);
+
+/* Bond sum and magnetisation of every lattice into device arrays of n int64
+ * (E_q = -J * bond[q]).  Asynchronous. */
+int ising_batch_observables(const ising_batch *b, int64_t *d_bond, int64_t *d_mag,
+                            void *hip_stream);
+
+/* Words per thread used for lattices of size L (the persistent kernel's tile:
+ * a lattice of W words per colour is served by ceil(W / wpt) threads, and
+ * floor(256 / that) lattices share a workgroup).  set replans the batch;
+ * results never depend on it. */
+int ising_batch_get_tiles(const ising_batch *b, int64_t L, uint32_t *wpt);
+int ising_batch_set_tiles(ising_batch *b, int64_t L, uint32_t wpt);
+
+/* Times every tile candidate of every lattice size in the batch over
+ * tune_sweeps sweeps of a scratch copy (the batch itself is unchanged),
+ * requires all candidates to produce identical lattices, and keeps the
+ * fastest.  cache_path (may be NULL) is a JSON file keyed by target and
+ * kernel version: read if it covers every size, written after tuning.
+ * Synchronises hip_stream; allocates scratch device memory while it runs. */
+int ising_batch_autotune(ising_batch *b, int64_t tune_sweeps, const char *cache_path,
+                         void *hip_stream);
+
 /* Selects the half-sweep kernel for later calls in this process, for tests and
  * measurements: 0 = default (row-aligned sizes, L % 128 == 0, use the
  * streaming row kernel with its per-wavefront work queue; other sizes the

@@ -4,4 +4,5 @@ The hot path lives in hand-written HIP kernels behind the C ABI of
 ``libising.so`` (include/ising.h); this package is the thin Python binding.
 """
 from ._lib import IsingError, load  # noqa: F401
-from .lattice import Lattice, set_sweep_kernel, thresholds, words_per_colour  # noqa: F401
+from .lattice import (Batch, Lattice, batch_words, set_sweep_kernel, thresholds,  # noqa: F401
+                      words_per_colour)

@@ -51,6 +51,20 @@ SIGNATURES = {
     "ising_observables": (ctypes.c_int, [_lat_p, _vp, _vp, _vp]),
     "ising_get_spins": (ctypes.c_int, [_lat_p, _vp, _vp]),
     "ising_set_spins": (ctypes.c_int, [_lat_p, _vp, _vp]),
+    "ising_batch_words": (_i64, [ctypes.c_int32, ctypes.POINTER(_i64)]),
+    "ising_batch_create": (ctypes.c_int, [ctypes.POINTER(_vp), ctypes.c_int32, ctypes.POINTER(_i64),
+                                          ctypes.POINTER(_dbl), _dbl, ctypes.POINTER(_u64),
+                                          ctypes.POINTER(_u32), _vp, ctypes.c_size_t]),
+    "ising_batch_destroy": (ctypes.c_int, [_vp]),
+    "ising_batch_lattice": (ctypes.c_int, [_vp, ctypes.c_int32, _lat_p]),
+    "ising_batch_init": (ctypes.c_int, [_vp, _vp]),
+    "ising_batch_sweep": (ctypes.c_int, [_vp, _i64, _vp]),
+    "ising_batch_set_counter": (ctypes.c_int, [_vp, _u64, _vp]),
+    "ising_batch_get_counter": (ctypes.c_int, [_vp, ctypes.POINTER(_u64), _vp]),
+    "ising_batch_observables": (ctypes.c_int, [_vp, _vp, _vp, _vp]),
+    "ising_batch_get_tiles": (ctypes.c_int, [_vp, _i64, ctypes.POINTER(_u32)]),
+    "ising_batch_set_tiles": (ctypes.c_int, [_vp, _i64, _u32]),
+    "ising_batch_autotune": (ctypes.c_int, [_vp, _i64, ctypes.c_char_p, _vp]),
     "ising_set_sweep_kernel": (ctypes.c_int, [ctypes.c_int]),
     "ising_last_error": (ctypes.c_char_p, []),
 }

@@ -1,0 +1,579 @@
+// C ABI of batched lattices (include/ising.h): planning bundles for the
+// persistent kernel, the captured HIP graph of one batch sweep, the
+// autotuner of words per thread, and per-lattice observables.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstdio>
+#include <cstring>
+#include <fstream>
+#include <map>
+#include <sstream>
+#include <string>
+#include <vector>
+
+#include "../../include/ising.h"
+#include "batch.hpp"
+#include "host_common.hpp"
+
+using namespace ising;
+
+struct ising_batch {
+    int32_t n = 0;
+    std::vector<int64_t> Ls;
+    std::vector<BatchLattice> lats; // host copy
+    uint64_t *words = nullptr;      // caller's buffer
+    size_t bytes = 0;
+    std::map<int64_t, uint32_t> wpt; // words per thread, per lattice size
+    // device state owned by the batch
+    BatchLattice *d_lats = nullptr;
+    uint32_t *d_members = nullptr;
+    BatchBundle *d_bundles = nullptr;
+    uint32_t *d_next = nullptr;
+    uint64_t *d_counter = nullptr;
+    uint32_t nbundles = 0, grid = 0;
+    size_t lds_bytes = 0;
+    // captured sweep
+    hipStream_t capture_stream = nullptr;
+    hipGraphExec_t exec = nullptr;
+    int64_t exec_nsweeps = -1;
+};
+
+namespace {
+
+constexpr uint32_t kMaxBatchL = 722; // two extended colour arrays within 64 KiB of LDS
+
+uint32_t words_of(int64_t L) { return (uint32_t)((L * L / 2 + 63) / 64); }
+
+uint32_t default_wpt(uint32_t W) { return (W + kBatchThreads - 1) / kBatchThreads; }
+
+struct Plan {
+    std::vector<uint32_t> members;
+    std::vector<BatchBundle> bundles;
+    size_t lds_bytes = 0;
+};
+
+// Bundles of same-size lattices, largest work first.  `only_L` restricts the
+// plan to one size (autotuning), 0 = all.
+Plan make_plan(const ising_batch *b, int64_t only_L, uint32_t only_wpt)
+{
+    std::map<int64_t, std::vector<uint32_t>> by_size;
+    for (int32_t q = 0; q < b->n; ++q)
+        if (!only_L || b->Ls[q] == only_L)
+            by_size[b->Ls[q]].push_back((uint32_t)q);
+    struct Item {
+        double work;
+        BatchBundle bd;
+        std::vector<uint32_t> ids;
+    };
+    std::vector<Item> items;
+    for (auto &kv : by_size) {
+        const int64_t L = kv.first;
+        const uint32_t W = words_of(L);
+        uint32_t wpt = only_L ? only_wpt : b->wpt.at(L);
+        wpt = std::max(1u, std::min(wpt, W));
+        const uint32_t tpl = (W + wpt - 1) / wpt;
+        const uint32_t per = std::max(1u, (uint32_t)kBatchThreads / tpl);
+        for (size_t i = 0; i < kv.second.size(); i += per) {
+            Item it;
+            const uint32_t cnt = (uint32_t)std::min<size_t>(per, kv.second.size() - i);
+            it.ids.assign(kv.second.begin() + i, kv.second.begin() + i + cnt);
+            it.bd = BatchBundle{0, cnt, wpt, tpl};
+            it.work = (double)cnt * (double)(L * L);
+            items.push_back(std::move(it));
+        }
+    }
+    std::stable_sort(items.begin(), items.end(),
+                     [](const Item &a, const Item &c) { return a.work > c.work; });
+    Plan p;
+    for (auto &it : items) {
+        it.bd.first = (uint32_t)p.members.size();
+        p.members.insert(p.members.end(), it.ids.begin(), it.ids.end());
+        p.bundles.push_back(it.bd);
+        const uint32_t W = b->lats[it.ids[0]].W;
+        p.lds_bytes = std::max(p.lds_bytes, (size_t)it.bd.count * batch_lds_words(W) * 8);
+    }
+    return p;
+}
+
+void free_plan_buffers(ising_batch *b)
+{
+    if (b->d_members)
+        (void)hipFree(b->d_members);
+    if (b->d_bundles)
+        (void)hipFree(b->d_bundles);
+    b->d_members = nullptr;
+    b->d_bundles = nullptr;
+    if (b->exec)
+        (void)hipGraphExecDestroy(b->exec);
+    b->exec = nullptr;
+    b->exec_nsweeps = -1;
+}
+
+// Workgroups of the persistent kernel: enough for every compute unit to hold
+// as many as its LDS allows (at most 8 of 256 threads), never more than bundles.
+int persistent_grid(size_t lds_bytes, uint32_t nbundles, uint32_t *grid)
+{
+    int dev = 0, cus = 0;
+    hipError_t e = hipGetDevice(&dev);
+    if (e == hipSuccess)
+        e = hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev);
+    if (e != hipSuccess || cus <= 0)
+        return host::fail(ISING_E_HIP, "cannot query the number of compute units");
+    const int by_lds = lds_bytes ? (int)((160 * 1024) / lds_bytes) : 8;
+    const int occ = std::max(1, std::min(8, by_lds));
+    *grid = std::max(1u, std::min(nbundles, (uint32_t)(cus * occ)));
+    return ISING_OK;
+}
+
+int install_plan(ising_batch *b, const Plan &p)
+{
+    free_plan_buffers(b);
+    hipError_t e = hipMalloc(&b->d_members, std::max<size_t>(1, p.members.size()) * 4);
+    if (e == hipSuccess)
+        e = hipMalloc(&b->d_bundles, std::max<size_t>(1, p.bundles.size()) * sizeof(BatchBundle));
+    if (e == hipSuccess && !p.members.empty())
+        e = hipMemcpy(b->d_members, p.members.data(), p.members.size() * 4, hipMemcpyHostToDevice);
+    if (e == hipSuccess && !p.bundles.empty())
+        e = hipMemcpy(b->d_bundles, p.bundles.data(), p.bundles.size() * sizeof(BatchBundle),
+                      hipMemcpyHostToDevice);
+    if (e != hipSuccess)
+        return host::hip_fail(e, "batch plan upload");
+    b->nbundles = (uint32_t)p.bundles.size();
+    b->lds_bytes = p.lds_bytes;
+    return persistent_grid(p.lds_bytes, b->nbundles, &b->grid);
+}
+
+int check_batch(const ising_batch *b)
+{
+    if (!b)
+        return host::fail(ISING_E_BADARG, "null batch");
+    return ISING_OK;
+}
+
+// ---------------------------------------------------------------- cache file
+std::string cache_key() { return "gfx950/batch-sweep-v1"; }
+
+bool read_cache(const char *path, std::map<int64_t, uint32_t> &out)
+{
+    std::ifstream f(path);
+    if (!f)
+        return false;
+    std::stringstream ss;
+    ss << f.rdbuf();
+    const std::string s = ss.str();
+    const std::string tag = "\"key\": \"" + cache_key() + "\"";
+    if (s.find(tag) == std::string::npos)
+        return false;
+    size_t pos = s.find("\"wpt\"");
+    if (pos == std::string::npos)
+        return false;
+    pos = s.find('{', pos);
+    const size_t end = s.find('}', pos);
+    if (pos == std::string::npos || end == std::string::npos)
+        return false;
+    std::string body = s.substr(pos + 1, end - pos - 1);
+    for (char &ch : body)
+        if (ch == '"' || ch == ',' || ch == ':')
+            ch = ' ';
+    std::istringstream in(body);
+    long long L;
+    unsigned w;
+    while (in >> L >> w)
+        out[(int64_t)L] = w;
+    return true;
+}
+
+bool write_cache(const char *path, const std::map<int64_t, uint32_t> &wpt)
+{
+    std::ofstream f(path);
+    if (!f)
+        return false;
+    f << "{\"key\": \"" << cache_key() << "\", \"wpt\": {";
+    bool first = true;
+    for (auto &kv : wpt) {
+        f << (first ? "" : ", ") << "\"" << kv.first << "\": " << kv.second;
+        first = false;
+    }
+    f << "}}\n";
+    return (bool)f;
+}
+
+} // namespace
+
+extern "C" {
+
+int64_t ising_batch_words(int32_t n, const int64_t *Ls)
+{
+    if (n < 0 || (n > 0 && !Ls))
+        return -1;
+    int64_t total = 0;
+    for (int32_t q = 0; q < n; ++q) {
+        if (Ls[q] < 4 || (Ls[q] & 1) || Ls[q] > (int64_t)kMaxBatchL)
+            return -1;
+        total += 2 * (int64_t)words_of(Ls[q]);
+    }
+    return total;
+}
+
+int ising_batch_create(ising_batch **out, int32_t n, const int64_t *Ls, const double *betas,
+                       double J, const uint64_t *seeds, const uint32_t *stream_ids,
+                       uint64_t *d_words, size_t bytes)
+{
+    if (!out)
+        return host::fail(ISING_E_BADARG, "null output");
+    *out = nullptr;
+    if (n <= 0 || !Ls || !betas || !seeds || !stream_ids || !d_words)
+        return host::fail(ISING_E_BADARG, "empty batch or null pointer");
+    if (!std::isfinite(J))
+        return host::fail(ISING_E_BADARG, "J must be finite");
+    const int64_t need = ising_batch_words(n, Ls);
+    if (need < 0)
+        return host::fail(ISING_E_SIZE, "every L must be even, >= 4 and <= %u", kMaxBatchL);
+    if (bytes < (size_t)need * 8)
+        return host::fail(ISING_E_SIZE, "buffer of %zu bytes is smaller than the %lld needed",
+                          bytes, (long long)(need * 8));
+    ising_batch *b = new ising_batch();
+    b->n = n;
+    b->words = d_words;
+    b->bytes = bytes;
+    uint64_t off = 0;
+    for (int32_t q = 0; q < n; ++q) {
+        if (!std::isfinite(betas[q]) || betas[q] < 0.0 || stream_ids[q] >= (1u << 24)) {
+            delete b;
+            return host::fail(ISING_E_BADARG, "lattice %d: beta must be finite and >= 0, "
+                              "stream id < 2^24", (int)q);
+        }
+        BatchLattice lt{};
+        lt.word_off = off;
+        lt.L = (uint32_t)Ls[q];
+        lt.H = lt.L / 2;
+        lt.M = lt.L * lt.L / 2;
+        lt.W = words_of(Ls[q]);
+        lt.m = host::metro2_params(betas[q], J);
+        lt.key0 = (uint32_t)seeds[q];
+        lt.key1 = (uint32_t)(seeds[q] >> 32);
+        lt.stream_id = stream_ids[q];
+        b->lats.push_back(lt);
+        b->Ls.push_back(Ls[q]);
+        if (!b->wpt.count(Ls[q]))
+            b->wpt[Ls[q]] = default_wpt(lt.W);
+        off += 2 * (uint64_t)lt.W;
+    }
+    hipError_t e = hipMalloc(&b->d_lats, b->lats.size() * sizeof(BatchLattice));
+    if (e == hipSuccess)
+        e = hipMalloc(&b->d_next, 4);
+    if (e == hipSuccess)
+        e = hipMalloc(&b->d_counter, 8);
+    if (e == hipSuccess)
+        e = hipMemcpy(b->d_lats, b->lats.data(), b->lats.size() * sizeof(BatchLattice),
+                      hipMemcpyHostToDevice);
+    const uint64_t zero = 0;
+    if (e == hipSuccess)
+        e = hipMemcpy(b->d_counter, &zero, 8, hipMemcpyHostToDevice);
+    if (e == hipSuccess)
+        e = hipStreamCreateWithFlags(&b->capture_stream, hipStreamNonBlocking);
+    if (e != hipSuccess) {
+        ising_batch_destroy(b);
+        return host::hip_fail(e, "batch allocation");
+    }
+    if (int r = install_plan(b, make_plan(b, 0, 0))) {
+        ising_batch_destroy(b);
+        return r;
+    }
+    *out = b;
+    return host::ok();
+}
+
+int ising_batch_destroy(ising_batch *b)
+{
+    if (!b)
+        return host::ok();
+    free_plan_buffers(b);
+    if (b->d_lats)
+        (void)hipFree(b->d_lats);
+    if (b->d_next)
+        (void)hipFree(b->d_next);
+    if (b->d_counter)
+        (void)hipFree(b->d_counter);
+    if (b->capture_stream)
+        (void)hipStreamDestroy(b->capture_stream);
+    delete b;
+    return host::ok();
+}
+
+int ising_batch_lattice(const ising_batch *b, int32_t q, ising_lattice *out)
+{
+    if (int e = check_batch(b))
+        return e;
+    if (!out || q < 0 || q >= b->n)
+        return host::fail(ISING_E_BADARG, "lattice index out of range");
+    const BatchLattice &lt = b->lats[(size_t)q];
+    out->words = b->words + lt.word_off;
+    out->L = lt.L;
+    out->seed = ((uint64_t)lt.key1 << 32) | lt.key0;
+    out->stream_id = lt.stream_id;
+    out->reserved = 0;
+    return host::ok();
+}
+
+int ising_batch_init(ising_batch *b, void *hip_stream)
+{
+    if (int e = check_batch(b))
+        return e;
+    hipError_t e = launch_batch_init(b->d_lats, (uint32_t)b->n, b->words, (hipStream_t)hip_stream);
+    if (e != hipSuccess)
+        return host::hip_fail(e, "batch init launch");
+    return host::ok();
+}
+
+int ising_batch_set_counter(ising_batch *b, uint64_t rng_counter, void *hip_stream)
+{
+    if (int e = check_batch(b))
+        return e;
+    hipStream_t s = (hipStream_t)hip_stream;
+    hipError_t e = hipMemcpyAsync(b->d_counter, &rng_counter, 8, hipMemcpyHostToDevice, s);
+    if (e == hipSuccess)
+        e = hipStreamSynchronize(s);
+    if (e != hipSuccess)
+        return host::hip_fail(e, "set batch counter");
+    return host::ok();
+}
+
+int ising_batch_get_counter(const ising_batch *b, uint64_t *rng_counter, void *hip_stream)
+{
+    if (int e = check_batch(b))
+        return e;
+    if (!rng_counter)
+        return host::fail(ISING_E_BADARG, "null output");
+    hipStream_t s = (hipStream_t)hip_stream;
+    hipError_t e = hipMemcpyAsync(rng_counter, b->d_counter, 8, hipMemcpyDeviceToHost, s);
+    if (e == hipSuccess)
+        e = hipStreamSynchronize(s);
+    if (e != hipSuccess)
+        return host::hip_fail(e, "get batch counter");
+    return host::ok();
+}
+
+int ising_batch_sweep(ising_batch *b, int64_t nsweeps, void *hip_stream)
+{
+    if (int e = check_batch(b))
+        return e;
+    if (nsweeps < 0)
+        return host::fail(ISING_E_BADARG, "nsweeps must be >= 0");
+    if (nsweeps == 0)
+        return host::ok();
+    hipStream_t s = (hipStream_t)hip_stream;
+    if (!b->exec || b->exec_nsweeps != nsweeps) {
+        if (b->exec)
+            (void)hipGraphExecDestroy(b->exec);
+        b->exec = nullptr;
+        hipGraph_t graph = nullptr;
+        hipError_t e = hipStreamBeginCapture(b->capture_stream, hipStreamCaptureModeThreadLocal);
+        if (e == hipSuccess) {
+            hipError_t le = launch_batch_sweep(b->d_lats, b->d_members, b->d_bundles, b->nbundles,
+                                               b->grid, b->lds_bytes, b->d_next, b->words,
+                                               b->d_counter, nsweeps, b->capture_stream);
+            e = hipStreamEndCapture(b->capture_stream, &graph);
+            if (le != hipSuccess)
+                e = le;
+        }
+        if (e == hipSuccess)
+            e = hipGraphInstantiate(&b->exec, graph, nullptr, nullptr, 0);
+        if (graph)
+            (void)hipGraphDestroy(graph);
+        if (e != hipSuccess) {
+            b->exec = nullptr;
+            return host::hip_fail(e, "batch sweep graph capture");
+        }
+        b->exec_nsweeps = nsweeps;
+    }
+    hipError_t e = hipGraphLaunch(b->exec, s);
+    if (e != hipSuccess)
+        return host::hip_fail(e, "batch sweep graph launch");
+    return host::ok();
+}
+
+int ising_batch_observables(const ising_batch *b, int64_t *d_bond, int64_t *d_mag,
+                            void *hip_stream)
+{
+    if (int e = check_batch(b))
+        return e;
+    if (!d_bond || !d_mag)
+        return host::fail(ISING_E_BADARG, "null output pointer");
+    hipError_t e = launch_batch_observables(b->d_lats, (uint32_t)b->n, b->words, d_bond, d_mag,
+                                            (hipStream_t)hip_stream);
+    if (e != hipSuccess)
+        return host::hip_fail(e, "batch observables launch");
+    return host::ok();
+}
+
+int ising_batch_get_tiles(const ising_batch *b, int64_t L, uint32_t *wpt)
+{
+    if (int e = check_batch(b))
+        return e;
+    auto it = b->wpt.find(L);
+    if (!wpt || it == b->wpt.end())
+        return host::fail(ISING_E_BADARG, "no lattice of that size in the batch");
+    *wpt = it->second;
+    return host::ok();
+}
+
+int ising_batch_set_tiles(ising_batch *b, int64_t L, uint32_t wpt)
+{
+    if (int e = check_batch(b))
+        return e;
+    auto it = b->wpt.find(L);
+    if (it == b->wpt.end())
+        return host::fail(ISING_E_BADARG, "no lattice of that size in the batch");
+    const uint32_t W = words_of(L);
+    if (wpt < 1 || (W + wpt - 1) / wpt > (uint32_t)kBatchThreads)
+        return host::fail(ISING_E_BADARG, "words per thread must be >= 1 and leave at most %d "
+                          "threads per lattice", kBatchThreads);
+    it->second = wpt;
+    return install_plan(b, make_plan(b, 0, 0));
+}
+
+int ising_batch_autotune(ising_batch *b, int64_t tune_sweeps, const char *cache_path,
+                         void *hip_stream)
+{
+    if (int e = check_batch(b))
+        return e;
+    if (tune_sweeps <= 0)
+        return host::fail(ISING_E_BADARG, "tune_sweeps must be > 0");
+    hipStream_t s = (hipStream_t)hip_stream;
+    std::map<int64_t, uint32_t> cached;
+    if (cache_path && read_cache(cache_path, cached)) {
+        bool complete = true;
+        for (auto &kv : b->wpt)
+            complete = complete && cached.count(kv.first);
+        if (complete) {
+            for (auto &kv : b->wpt)
+                kv.second = cached[kv.first];
+            return install_plan(b, make_plan(b, 0, 0));
+        }
+    }
+    // Scratch copy of the lattices and counter: tuning never changes the batch.
+    const size_t nbytes = (size_t)ising_batch_words(b->n, b->Ls.data()) * 8;
+    uint64_t *scratch = nullptr, *ctr = nullptr;
+    uint32_t *members = nullptr, *next = nullptr;
+    BatchBundle *bundles = nullptr;
+    hipEvent_t e0 = nullptr, e1 = nullptr;
+    hipError_t e = hipMalloc(&scratch, nbytes);
+    if (e == hipSuccess)
+        e = hipMalloc(&ctr, 8);
+    if (e == hipSuccess)
+        e = hipMalloc(&next, 4);
+    if (e == hipSuccess)
+        e = hipEventCreate(&e0);
+    if (e == hipSuccess)
+        e = hipEventCreate(&e1);
+    std::vector<uint64_t> out_ref, out_try;
+    int rc = ISING_OK;
+    for (auto &kv : b->wpt) {
+        if (e != hipSuccess)
+            break;
+        const int64_t L = kv.first;
+        const uint32_t W = words_of(L);
+        std::vector<uint32_t> cands;
+        for (uint32_t w : {1u, 2u, 3u, 4u, 6u, 8u, 12u, 16u}) {
+            if (w > W || (W + w - 1) / w > (uint32_t)kBatchThreads)
+                continue;
+            const uint32_t tpl = (W + w - 1) / w;
+            bool dup = false;
+            for (uint32_t c : cands)
+                dup = dup || (W + c - 1) / c == tpl;
+            if (!dup)
+                cands.push_back(w);
+        }
+        float best_ms = 1e30f;
+        uint32_t best = kv.second;
+        bool have_ref = false;
+        for (uint32_t w : cands) {
+            const Plan p = make_plan(b, L, w);
+            uint32_t grid = 0;
+            if ((rc = persistent_grid(p.lds_bytes, (uint32_t)p.bundles.size(), &grid)))
+                break;
+            if (members)
+                (void)hipFree(members);
+            if (bundles)
+                (void)hipFree(bundles);
+            members = nullptr;
+            bundles = nullptr;
+            e = hipMalloc(&members, p.members.size() * 4);
+            if (e == hipSuccess)
+                e = hipMalloc(&bundles, p.bundles.size() * sizeof(BatchBundle));
+            if (e == hipSuccess)
+                e = hipMemcpy(members, p.members.data(), p.members.size() * 4,
+                              hipMemcpyHostToDevice);
+            if (e == hipSuccess)
+                e = hipMemcpy(bundles, p.bundles.data(), p.bundles.size() * sizeof(BatchBundle),
+                              hipMemcpyHostToDevice);
+            float ms = 0.f;
+            for (int rep = 0; rep < 2 && e == hipSuccess; ++rep) {
+                // same start for every candidate: the batch's lattices, counter 0
+                const uint64_t zero = 0;
+                e = hipMemcpyAsync(scratch, b->words, nbytes, hipMemcpyDeviceToDevice, s);
+                if (e == hipSuccess)
+                    e = hipMemcpyAsync(ctr, &zero, 8, hipMemcpyHostToDevice, s);
+                if (e == hipSuccess)
+                    e = hipEventRecord(e0, s);
+                if (e == hipSuccess)
+                    e = launch_batch_sweep(b->d_lats, members, bundles,
+                                           (uint32_t)p.bundles.size(), grid, p.lds_bytes, next,
+                                           scratch, ctr, tune_sweeps, s);
+                if (e == hipSuccess)
+                    e = hipEventRecord(e1, s);
+                if (e == hipSuccess)
+                    e = hipEventSynchronize(e1);
+                if (e == hipSuccess)
+                    e = hipEventElapsedTime(&ms, e0, e1);
+            }
+            if (e != hipSuccess)
+                break;
+            // every candidate must reproduce the same lattices bit for bit
+            std::vector<uint64_t> &dst = have_ref ? out_try : out_ref;
+            dst.resize(nbytes / 8);
+            e = hipMemcpy(dst.data(), scratch, nbytes, hipMemcpyDeviceToHost);
+            if (e != hipSuccess)
+                break;
+            if (have_ref && out_try != out_ref) {
+                rc = host::fail(ISING_E_HIP, "autotune: tile %u of L=%lld changed the lattice",
+                                w, (long long)L);
+                break;
+            }
+            have_ref = true;
+            if (ms < best_ms) {
+                best_ms = ms;
+                best = w;
+            }
+        }
+        if (rc != ISING_OK)
+            break;
+        kv.second = best;
+    }
+    if (members)
+        (void)hipFree(members);
+    if (bundles)
+        (void)hipFree(bundles);
+    if (scratch)
+        (void)hipFree(scratch);
+    if (ctr)
+        (void)hipFree(ctr);
+    if (next)
+        (void)hipFree(next);
+    if (e0)
+        (void)hipEventDestroy(e0);
+    if (e1)
+        (void)hipEventDestroy(e1);
+    if (rc != ISING_OK)
+        return rc;
+    if (e != hipSuccess)
+        return host::hip_fail(e, "autotune");
+    if (cache_path && !write_cache(cache_path, b->wpt))
+        return host::fail(ISING_E_BADARG, "cannot write the autotune cache %s", cache_path);
+    return install_plan(b, make_plan(b, 0, 0));
+}
+
+} // extern "C"

@@ -1,0 +1,181 @@
+// gfx950 kernels for batches of independent lattices that fit in LDS: the
+// persistent sweep kernel, initial states and per-lattice observables.
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include "batch.hpp"
+
+namespace ising {
+
+// Initial state of every lattice; one workgroup per lattice.
+__global__ __launch_bounds__(256) void k_batch_init(const BatchLattice *__restrict__ lats,
+                                                    uint64_t *__restrict__ words)
+{
+    const BatchLattice lt = lats[blockIdx.x];
+    for (uint32_t k = threadIdx.x; k < 2 * lt.W; k += blockDim.x) {
+        const uint32_t c = k >= lt.W;
+        words[lt.word_off + k] =
+            init_word(k - c * lt.W, c, lt.M, lt.stream_id, lt.key0, lt.key1);
+    }
+}
+
+// Writes the cyclic continuation of one extended colour array.
+__device__ __forceinline__ void ext_refresh(uint64_t *E, uint32_t M, uint32_t W)
+{
+    uint64_t tail[3];
+    ext_tail(E, M, W, tail);
+    E[W - 1] = tail[0];
+    E[W] = tail[1];
+    E[W + 1] = tail[2];
+}
+
+// Persistent sweep kernel.  Workgroups take bundles from an atomic counter
+// (the host orders them by decreasing work), copy the bundle's lattices into
+// LDS, run every sweep there -- all spins of one colour from the other
+// colour, a barrier, then the other colour (Sec. 2) -- and copy them back.
+// Sweep s of the call uses half-sweep index t = 2*(rng_counter + s) + colour.
+__global__ __launch_bounds__(kBatchThreads) void k_batch_sweep(
+    const BatchLattice *__restrict__ lats, const uint32_t *__restrict__ members,
+    const BatchBundle *__restrict__ bundles, uint32_t nbundles, uint32_t *__restrict__ next_bundle,
+    uint64_t *__restrict__ words, const uint64_t *__restrict__ rng_counter, int64_t nsweeps)
+{
+    extern __shared__ uint64_t lds[];
+    __shared__ uint32_t item;
+    const uint64_t ctr = *rng_counter;
+    for (;;) {
+        __syncthreads(); // the previous bundle is written back and `item` consumed
+        if (threadIdx.x == 0)
+            item = atomicAdd(next_bundle, 1u);
+        __syncthreads();
+        const uint32_t b = item;
+        if (b >= nbundles)
+            return;
+        const BatchBundle bd = bundles[b];
+        const uint32_t slot = threadIdx.x / bd.tpl, li = threadIdx.x % bd.tpl;
+        const bool on = slot < bd.count;
+        BatchLattice lt{};
+        if (on)
+            lt = lats[members[bd.first + slot]];
+        uint64_t *E0 = lds + (size_t)slot * batch_lds_words(lt.W);
+        uint64_t *E1 = E0 + lt.W + 2;
+        if (on)
+            for (uint32_t k = li; k < 2 * lt.W; k += bd.tpl) {
+                const uint32_t c = k >= lt.W;
+                (c ? E1 : E0)[k - c * lt.W] = words[lt.word_off + k];
+            }
+        __syncthreads();
+        if (on && li < 2 && (li < bd.tpl))
+            ext_refresh(li ? E1 : E0, lt.M, lt.W);
+        if (on && bd.tpl == 1)
+            ext_refresh(E1, lt.M, lt.W);
+        __syncthreads();
+        for (int64_t sw = 0; sw < nsweeps; ++sw) {
+            for (int c = 0; c < 2; ++c) {
+                const uint64_t t = 2 * (ctr + (uint64_t)sw) + (uint64_t)c;
+                uint64_t *tgt = c ? E1 : E0;
+                const uint64_t *src = c ? E0 : E1;
+                if (on) {
+                    const SweepArgs2 a{lt.m,      (uint32_t)t, (uint32_t)(t >> 32), lt.stream_id,
+                                       lt.key0, lt.key1};
+                    for (uint32_t j = 0; j < bd.wpt; ++j) {
+                        const uint32_t k = li + j * bd.tpl;
+                        if (k >= lt.W)
+                            break;
+                        const Neighbours nb = neighbours_ext(src, lt.H, lt.M, k, c);
+                        const uint64_t tw = tgt[k];
+                        const Classes cl = classify(tw, nb.up, nb.dn, nb.ce, nb.sd);
+                        tgt[k] = tw ^ decide_word(cl, valid_mask(k, lt.M), k, a);
+                    }
+                }
+                __syncthreads();
+                if (on && li == 0)
+                    ext_refresh(tgt, lt.M, lt.W);
+                __syncthreads();
+            }
+        }
+        if (on)
+            for (uint32_t k = li; k < 2 * lt.W; k += bd.tpl) {
+                const uint32_t c = k >= lt.W;
+                const uint32_t kk = k - c * lt.W;
+                words[lt.word_off + k] = (c ? E1 : E0)[kk] & valid_mask(kk, lt.M);
+            }
+    }
+}
+
+__global__ void k_batch_prepare(uint32_t *next_bundle)
+{
+    if (threadIdx.x == 0)
+        *next_bundle = 0;
+}
+
+__global__ void k_batch_advance(uint64_t *rng_counter, int64_t nsweeps)
+{
+    if (threadIdx.x == 0)
+        *rng_counter += (uint64_t)nsweeps;
+}
+
+// Per-lattice bond sum and magnetisation; one workgroup per lattice.
+__global__ __launch_bounds__(256) void k_batch_observables(const BatchLattice *__restrict__ lats,
+                                                           const uint64_t *__restrict__ words,
+                                                           int64_t *bond_out, int64_t *mag_out)
+{
+    const BatchLattice lt = lats[blockIdx.x];
+    const uint64_t *black = words + lt.word_off, *white = black + lt.W;
+    int64_t bond = 0, mag = 0;
+    for (uint32_t k = threadIdx.x; k < lt.W; k += blockDim.x) {
+        const uint64_t valid = valid_mask(k, lt.M);
+        const uint64_t t = black[k];
+        const Neighbours nb = neighbours_general(white, lt.H, lt.M, lt.W, k, 0);
+        const int64_t aligned =
+            (int64_t)__popcll(~(t ^ nb.up) & valid) + (int64_t)__popcll(~(t ^ nb.dn) & valid) +
+            (int64_t)__popcll(~(t ^ nb.ce) & valid) + (int64_t)__popcll(~(t ^ nb.sd) & valid);
+        const int64_t nvalid = (int64_t)__popcll(valid);
+        bond += 2 * aligned - 4 * nvalid;
+        mag += 2 * ((int64_t)__popcll(t & valid) + (int64_t)__popcll(white[k] & valid)) -
+               2 * nvalid;
+    }
+    __shared__ int64_t sb[256], sm[256];
+    sb[threadIdx.x] = bond;
+    sm[threadIdx.x] = mag;
+    __syncthreads();
+    for (uint32_t h = blockDim.x / 2; h > 0; h >>= 1) {
+        if (threadIdx.x < h) {
+            sb[threadIdx.x] += sb[threadIdx.x + h];
+            sm[threadIdx.x] += sm[threadIdx.x + h];
+        }
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) {
+        bond_out[blockIdx.x] = sb[0];
+        mag_out[blockIdx.x] = sm[0];
+    }
+}
+
+hipError_t launch_batch_init(const BatchLattice *lats, uint32_t n, uint64_t *words,
+                             hipStream_t s)
+{
+    hipLaunchKernelGGL(k_batch_init, dim3(n), dim3(256), 0, s, lats, words);
+    return hipGetLastError();
+}
+
+hipError_t launch_batch_sweep(const BatchLattice *lats, const uint32_t *members,
+                              const BatchBundle *bundles, uint32_t nbundles, uint32_t grid,
+                              size_t lds_bytes, uint32_t *next_bundle, uint64_t *words,
+                              uint64_t *rng_counter, int64_t nsweeps, hipStream_t s)
+{
+    hipLaunchKernelGGL(k_batch_prepare, dim3(1), dim3(64), 0, s, next_bundle);
+    hipLaunchKernelGGL(k_batch_sweep, dim3(grid), dim3(kBatchThreads), lds_bytes, s, lats,
+                       members, bundles, nbundles, next_bundle, words,
+                       (const uint64_t *)rng_counter, nsweeps);
+    hipLaunchKernelGGL(k_batch_advance, dim3(1), dim3(64), 0, s, rng_counter, nsweeps);
+    return hipGetLastError();
+}
+
+hipError_t launch_batch_observables(const BatchLattice *lats, uint32_t n, const uint64_t *words,
+                                    int64_t *bond, int64_t *mag, hipStream_t s)
+{
+    hipLaunchKernelGGL(k_batch_observables, dim3(n), dim3(256), 0, s, lats, words, bond, mag);
+    return hipGetLastError();
+}
+
+} // namespace ising

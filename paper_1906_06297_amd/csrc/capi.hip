@@ -10,14 +10,15 @@
 #include <vector>
 
 #include "../../include/ising.h"
+#include "host_common.hpp"
 #include "launch.hpp"
 
+namespace ising {
+namespace host {
+
 namespace {
-
 thread_local std::string g_error;
-
-// Half-sweep kernel selection (for tests and measurements; 0 = default).
-int g_variant = 0;
+} // namespace
 
 int fail(int code, const char *fmt, ...)
 {
@@ -40,6 +41,47 @@ int hip_fail(hipError_t e, const char *what)
 {
     return fail(ISING_E_HIP, "%s: %s", what, hipGetErrorString(e));
 }
+
+const char *last_error() { return g_error.c_str(); }
+
+void threshold_table(double beta, double J, uint64_t T[5])
+{
+    for (int a = 0; a < 5; ++a) {
+        const double dE = 4.0 * J * (double)(a - 2);
+        if (dE <= 0.0)
+            T[a] = 1ull << 32;
+        else
+            T[a] = (uint64_t)std::floor(std::exp(-(beta * dE)) * 4294967296.0);
+    }
+}
+
+Metro2 metro2_params(double beta, double J)
+{
+    uint64_t T[5];
+    threshold_table(beta, J, T);
+    Metro2 m{};
+    m.anti = J < 0.0 ? 1u : 0u;
+    const uint64_t tA = m.anti ? T[1] : T[3], tB = m.anti ? T[0] : T[4];
+    m.alwaysA = tA >= (1ull << 32);
+    m.alwaysB = tB >= (1ull << 32);
+    m.randA = !m.alwaysA && tA > 0;
+    m.randB = !m.alwaysB && tB > 0;
+    m.thrA = m.randA ? (uint32_t)tA : 0u;
+    m.thrB = m.randB ? (uint32_t)tB : 0u;
+    return m;
+}
+
+} // namespace host
+} // namespace ising
+
+namespace {
+
+using ising::host::fail;
+using ising::host::hip_fail;
+using ising::host::ok;
+
+// Half-sweep kernel selection (for tests and measurements; 0 = default).
+int g_variant = 0;
 
 // Largest supported size: chunk indices must fit the 32-bit counter word.
 constexpr int64_t kMaxL = 741454; // floor(sqrt(128 * (2^32 - 1)))
@@ -76,42 +118,12 @@ int check_temperature(double beta, double J)
     return ISING_OK;
 }
 
-// T[a] = 2^32 for dE <= 0, floor(exp(-beta dE) 2^32) otherwise; dE = 4J(a-2).
-void threshold_table(double beta, double J, uint64_t T[5])
-{
-    for (int a = 0; a < 5; ++a) {
-        const double dE = 4.0 * J * (double)(a - 2);
-        if (dE <= 0.0)
-            T[a] = 1ull << 32;
-        else
-            T[a] = (uint64_t)std::floor(std::exp(-(beta * dE)) * 4294967296.0);
-    }
-}
-
-// The two classes with dE > 0 under the Metropolis rule (A: |dE| = 4|J|,
-// B: |dE| = 8|J|) and how each is decided.
-ising::Metro2 metro2_params(double beta, double J)
-{
-    uint64_t T[5];
-    threshold_table(beta, J, T);
-    ising::Metro2 m{};
-    m.anti = J < 0.0 ? 1u : 0u;
-    const uint64_t tA = m.anti ? T[1] : T[3], tB = m.anti ? T[0] : T[4];
-    m.alwaysA = tA >= (1ull << 32);
-    m.alwaysB = tB >= (1ull << 32);
-    m.randA = !m.alwaysA && tA > 0;
-    m.randB = !m.alwaysB && tB > 0;
-    m.thrA = m.randA ? (uint32_t)tA : 0u;
-    m.thrB = m.randB ? (uint32_t)tB : 0u;
-    return m;
-}
-
 int64_t words_per_colour(int64_t L) { return (L * L / 2 + 63) / 64; }
 
 int run_sweeps(const ising_lattice *lat, double beta, double J, int64_t nsweeps,
                uint64_t rng_counter, int64_t *d_bond, int64_t *d_mag, hipStream_t s)
 {
-    const ising::Metro2 m = metro2_params(beta, J);
+    const ising::Metro2 m = ising::host::metro2_params(beta, J);
     for (int64_t sw = 0; sw < nsweeps; ++sw) {
         for (int c = 0; c < 2; ++c) {
             const uint64_t t = 2 * (rng_counter + (uint64_t)sw) + (uint64_t)c;
@@ -147,7 +159,7 @@ int ising_thresholds(double beta, double J, uint64_t *T_out)
         return fail(ISING_E_BADARG, "null output");
     if (int e = check_temperature(beta, J))
         return e;
-    threshold_table(beta, J, T_out);
+    ising::host::threshold_table(beta, J, T_out);
     return ok();
 }
 
@@ -281,6 +293,6 @@ int ising_set_sweep_kernel(int variant)
     return ok();
 }
 
-const char *ising_last_error(void) { return g_error.c_str(); }
+const char *ising_last_error(void) { return ising::host::last_error(); }
 
 } // extern "C"

@@ -331,6 +331,54 @@ __host__ __device__ __forceinline__ uint64_t valid_mask(int64_t chunk, int64_t M
     return (n0 + 64 <= M) ? ~0ull : ((1ull << (M - n0)) - 1);
 }
 
+// -------------------------------- extended colour arrays (lattices in LDS)
+// An extended colour array E holds the W words of one colour, then two more
+// words; the padding bits of word W-1 and the two extra words continue the
+// bit string cyclically (spin M follows spin M-1 with spin 0).  64 spins
+// starting at any x in [0, M) are then one funnel shift of E[x/64], E[x/64+1].
+template <typename Ptr>
+__host__ __device__ __forceinline__ uint64_t ext_bits(Ptr E, uint32_t x)
+{
+    const uint32_t w = x >> 6, sh = x & 63;
+    const uint64_t lo = E[w], hi = E[w + 1];
+    return sh ? (lo >> sh) | (hi << (64 - sh)) : lo;
+}
+
+// New contents of E[W-1], E[W], E[W+1] after the W words of the colour changed.
+template <typename Ptr>
+__host__ __device__ __forceinline__ void ext_tail(Ptr E, uint32_t M, uint32_t W, uint64_t out[3])
+{
+    const uint32_t r = M & 63;
+    const uint64_t head = cyclic_bits(E, M, W, 0);
+    out[0] = r ? ((E[W - 1] & ((1ull << r) - 1)) | (head << r)) : E[W - 1];
+    out[1] = cyclic_bits(E, M, W, (int64_t)64 * W - M);
+    out[2] = cyclic_bits(E, M, W, (int64_t)64 * W + 64 - M);
+}
+
+__host__ __device__ __forceinline__ uint32_t wrap_spin(int64_t x, uint32_t M)
+{
+    return (uint32_t)(x < 0 ? x + M : (x >= (int64_t)M ? x - M : x));
+}
+
+// Neighbour vectors of target word k of colour c from an extended source array.
+template <typename Ptr>
+__host__ __device__ __forceinline__ Neighbours neighbours_ext(Ptr E, uint32_t H, uint32_t M,
+                                                              uint32_t k, int c)
+{
+    const int64_t n0 = (int64_t)k << 6;
+    const RowMasks rm = row_masks(k, H, M, c);
+    Neighbours nb;
+    nb.ce = ext_bits(E, (uint32_t)n0);
+    nb.up = ext_bits(E, wrap_spin(n0 - H, M));
+    nb.dn = ext_bits(E, wrap_spin(n0 + H, M));
+    const uint64_t left = (ext_bits(E, wrap_spin(n0 - 1, M)) & ~rm.row_start) |
+                          (ext_bits(E, wrap_spin(n0 + H - 1, M)) & rm.row_start);
+    const uint64_t right = (ext_bits(E, wrap_spin(n0 + 1, M)) & ~rm.row_end) |
+                           (ext_bits(E, wrap_spin(n0 - H + 1, M)) & rm.row_end);
+    nb.sd = (left & rm.left_rows) | (right & ~rm.left_rows);
+    return nb;
+}
+
 // New value of target word `chunk` of colour c, any geometry.
 template <typename Ptr>
 __host__ __device__ __forceinline__ uint64_t update_word_general(uint64_t t, Ptr src, int64_t H,

@@ -47,6 +47,8 @@ class Lattice:
 
     def __init__(self, L: int, seed: int, stream_id: int = 0, device="cuda", words=None,
                  stream=None):
+        if words is _VIEW:  # internal: wraps an existing descriptor, see view()
+            return
         self.L = int(L)
         W = words_per_colour(self.L)
         if words is None:
@@ -58,6 +60,17 @@ class Lattice:
         _lib.check(_lib.load().ising_init(ctypes.byref(self.desc), ctypes.c_void_p(words.data_ptr()),
                                           words.numel() * 8, self.L, int(seed), int(stream_id),
                                           _stream_handle(stream)))
+
+    @classmethod
+    def view(cls, desc, words):
+        """A lattice over an existing descriptor (no initialisation); `words`
+        is the tensor that owns the memory."""
+        obj = cls(0, 0, words=_VIEW)
+        obj.desc = desc
+        obj.L = int(desc.L)
+        obj.words = words
+        obj._base = int(desc.words)
+        return obj
 
     @property
     def seed(self) -> int:
@@ -118,4 +131,97 @@ class Lattice:
     def packed(self) -> np.ndarray:
         """Host copy of the packed words as uint64 (2, words_per_colour)."""
         W = words_per_colour(self.L)
-        return self.words[: 2 * W].cpu().numpy().view(np.uint64).reshape(2, W)
+        off = (getattr(self, "_base", self.words.data_ptr()) - self.words.data_ptr()) // 8
+        return self.words[off: off + 2 * W].cpu().numpy().view(np.uint64).reshape(2, W)
+
+
+_VIEW = object()
+
+
+def batch_words(Ls) -> int:
+    arr = (ctypes.c_int64 * len(Ls))(*[int(x) for x in Ls])
+    n = _lib.load().ising_batch_words(len(Ls), arr)
+    if n < 0:
+        raise ValueError("unsupported lattice size in batch")
+    return int(n)
+
+
+class Batch:
+    """Independent lattices advanced together by the persistent batch kernel.
+
+    ``words`` is one torch int64 tensor holding every lattice back to back.
+    The batch keeps its own sweep counter on the device; consecutive sweep()
+    calls continue every chain.
+    """
+
+    def __init__(self, Ls, betas, J: float, seeds, stream_ids, device="cuda"):
+        n = len(Ls)
+        self.n = n
+        self.Ls = [int(x) for x in Ls]
+        self.J = float(J)
+        self.words = torch.zeros(batch_words(self.Ls), dtype=torch.int64, device=device)
+        self._h = ctypes.c_void_p()
+        L_arr = (ctypes.c_int64 * n)(*self.Ls)
+        b_arr = (ctypes.c_double * n)(*[float(x) for x in betas])
+        s_arr = (ctypes.c_uint64 * n)(*[int(x) for x in seeds])
+        i_arr = (ctypes.c_uint32 * n)(*[int(x) for x in stream_ids])
+        _lib.check(_lib.load().ising_batch_create(
+            ctypes.byref(self._h), n, L_arr, b_arr, float(J), s_arr, i_arr,
+            ctypes.c_void_p(self.words.data_ptr()), self.words.numel() * 8))
+
+    def close(self) -> None:
+        if self._h:
+            _lib.load().ising_batch_destroy(self._h)
+            self._h = ctypes.c_void_p()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def init(self, stream=None) -> None:
+        _lib.check(_lib.load().ising_batch_init(self._h, _stream_handle(stream)))
+
+    def sweep(self, nsweeps: int, stream=None) -> None:
+        _lib.check(_lib.load().ising_batch_sweep(self._h, int(nsweeps), _stream_handle(stream)))
+
+    def set_counter(self, value: int, stream=None) -> None:
+        _lib.check(_lib.load().ising_batch_set_counter(self._h, int(value), _stream_handle(stream)))
+
+    def counter(self, stream=None) -> int:
+        v = ctypes.c_uint64()
+        _lib.check(_lib.load().ising_batch_get_counter(self._h, ctypes.byref(v),
+                                                       _stream_handle(stream)))
+        return int(v.value)
+
+    def observables_async(self, stream=None):
+        """Device tensors (bond[n], M[n]); E_q = -J * bond[q]."""
+        out = torch.empty((2, self.n), dtype=torch.int64, device=self.words.device)
+        _lib.check(_lib.load().ising_batch_observables(
+            self._h, ctypes.c_void_p(out[0].data_ptr()), ctypes.c_void_p(out[1].data_ptr()),
+            _stream_handle(stream)))
+        return out
+
+    def observables(self, stream=None):
+        out = self.observables_async(stream).cpu().numpy()
+        return out[0], out[1]
+
+    def lattice(self, q: int) -> "Lattice":
+        desc = _lib.LatticeStruct()
+        _lib.check(_lib.load().ising_batch_lattice(self._h, int(q), ctypes.byref(desc)))
+        return Lattice.view(desc, self.words)
+
+    def tiles(self, L: int) -> int:
+        v = ctypes.c_uint32()
+        _lib.check(_lib.load().ising_batch_get_tiles(self._h, int(L), ctypes.byref(v)))
+        return int(v.value)
+
+    def set_tiles(self, L: int, wpt: int) -> None:
+        _lib.check(_lib.load().ising_batch_set_tiles(self._h, int(L), int(wpt)))
+
+    def autotune(self, tune_sweeps: int = 20, cache_path=None, stream=None) -> dict:
+        path = cache_path.encode() if cache_path else None
+        _lib.check(_lib.load().ising_batch_autotune(self._h, int(tune_sweeps), path,
+                                                    _stream_handle(stream)))
+        return {L: self.tiles(L) for L in sorted(set(self.Ls))}

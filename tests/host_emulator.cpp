@@ -80,4 +80,46 @@ void emu_half_sweep(uint64_t *words, int64_t L, int c, const uint64_t *T, int an
         }
 }
 
+// The persistent batch kernel's per-lattice sequence: extended colour arrays
+// refreshed after every half-sweep, neighbours by funnel shifts.
+void emu_batch_lattice(uint64_t *words, int64_t L, double beta, double J, uint64_t seed,
+                       uint32_t stream, int64_t nsweeps, uint64_t ctr, const uint64_t *T)
+{
+    (void)beta;
+    const uint32_t H = (uint32_t)L / 2, M = (uint32_t)(L * L / 2), W = (M + 63) / 64;
+    std::vector<uint64_t> E0(W + 2), E1(W + 2);
+    for (uint32_t k = 0; k < W; ++k) {
+        E0[k] = words[k];
+        E1[k] = words[W + k];
+    }
+    auto refresh = [&](std::vector<uint64_t> &E) {
+        uint64_t tail[3];
+        ext_tail(E.data(), M, W, tail);
+        E[W - 1] = tail[0];
+        E[W] = tail[1];
+        E[W + 1] = tail[2];
+    };
+    refresh(E0);
+    refresh(E1);
+    const Metro2 m = metro2_from_table(T, J < 0);
+    for (int64_t sw = 0; sw < nsweeps; ++sw)
+        for (int c = 0; c < 2; ++c) {
+            const uint64_t t = 2 * (ctr + (uint64_t)sw) + (uint64_t)c;
+            std::vector<uint64_t> &tgt = c ? E1 : E0;
+            const std::vector<uint64_t> &src = c ? E0 : E1;
+            const SweepArgs2 a{m, (uint32_t)t, (uint32_t)(t >> 32), stream, (uint32_t)seed,
+                               (uint32_t)(seed >> 32)};
+            for (uint32_t k = 0; k < W; ++k) {
+                const Neighbours nb = neighbours_ext(src.data(), H, M, k, c);
+                const Classes cl = classify(tgt[k], nb.up, nb.dn, nb.ce, nb.sd);
+                tgt[k] ^= decide_word(cl, valid_mask(k, M), k, a);
+            }
+            refresh(tgt);
+        }
+    for (uint32_t k = 0; k < W; ++k) {
+        words[k] = E0[k] & valid_mask(k, M);
+        words[W + k] = E1[k] & valid_mask(k, M);
+    }
+}
+
 } // extern "C"

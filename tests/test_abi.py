@@ -104,3 +104,25 @@ def test_layout_helper_roundtrip():
         M = L * L // 2
         if M % 64:
             assert int(w[0, -1]) >> (M % 64) == 0 and int(w[1, -1]) >> (M % 64) == 0
+
+
+def test_batch_argument_errors_without_device(lib):
+    from paper_1906_06297_amd import _lib
+
+    L = (ctypes.c_int64 * 3)(16, 24, 722)
+    assert lib.ising_batch_words(3, L) == 2 * (2 + 5 + 4073)  # 128, 288, 260642 spins per colour
+    bad = (ctypes.c_int64 * 2)(16, 724)
+    assert lib.ising_batch_words(2, bad) == -1
+    odd = (ctypes.c_int64 * 1)(15)
+    assert lib.ising_batch_words(1, odd) == -1
+    h = ctypes.c_void_p()
+    b = (ctypes.c_double * 3)(0.4, 0.4, 0.4)
+    s = (ctypes.c_uint64 * 3)(1, 1, 1)
+    i = (ctypes.c_uint32 * 3)(0, 1, 2)
+    fake = ctypes.c_void_p(0x1000)
+    assert lib.ising_batch_create(None, 3, L, b, 1.0, s, i, fake, 1 << 20) == _lib.ISING_E_BADARG
+    assert lib.ising_batch_create(ctypes.byref(h), 0, L, b, 1.0, s, i, fake, 1 << 20) == _lib.ISING_E_BADARG
+    assert lib.ising_batch_create(ctypes.byref(h), 3, L, b, 1.0, s, i, fake, 64) == _lib.ISING_E_SIZE
+    assert lib.ising_batch_create(ctypes.byref(h), 2, bad, b, 1.0, s, i, fake, 1 << 20) == _lib.ISING_E_SIZE
+    assert lib.ising_batch_sweep(None, 1, None) == _lib.ISING_E_BADARG
+    assert lib.ising_batch_destroy(None) == _lib.ISING_OK

@@ -29,6 +29,9 @@ def emu(tmp_path_factory):
     lib.emu_init.argtypes = [u64p, ctypes.c_int64, ctypes.c_uint64, ctypes.c_uint32]
     lib.emu_half_sweep.argtypes = [u64p, ctypes.c_int64, ctypes.c_int, u64p, ctypes.c_int,
                                    ctypes.c_uint64, ctypes.c_uint64, ctypes.c_uint32, ctypes.c_int]
+    lib.emu_batch_lattice.argtypes = [u64p, ctypes.c_int64, ctypes.c_double, ctypes.c_double,
+                                      ctypes.c_uint64, ctypes.c_uint32, ctypes.c_int64,
+                                      ctypes.c_uint64, u64p]
     return lib
 
 
@@ -68,3 +71,17 @@ def test_row_kernel_logic(emu, orc, rows, L, beta, J):
     ref = orc.init(L, seed, stream)
     orc.sweeps(ref, beta, J, seed, stream, n, ctr)
     assert np.array_equal(run_emu(emu, orc, L, seed, stream, beta, J, n, ctr, rows), pack(ref))
+
+
+@pytest.mark.parametrize("L", [4, 6, 8, 10, 12, 16, 24, 32, 48, 64, 96, 100, 128, 192, 256])
+@pytest.mark.parametrize("beta,J", [(0.0, 1.0), (workloads.BETA_CRIT_CONFIG, 1.0), (0.31, 1.0),
+                                    (0.3, -1.0), (5.0, 1.0)])
+def test_batch_kernel_logic(emu, orc, L, beta, J):
+    """The persistent batch kernel's LDS sequence (extended cyclic colour arrays)."""
+    seed, stream, n, ctr = 3, 17, 5, 9
+    ref = orc.init(L, seed, stream)
+    words = np.ascontiguousarray(pack(ref).reshape(-1))
+    T = np.ascontiguousarray(orc.thresholds(beta, J), dtype=np.uint64)
+    emu.emu_batch_lattice(_p(words), L, beta, J, seed, stream, n, ctr, _p(T))
+    orc.sweeps(ref, beta, J, seed, stream, n, ctr)
+    assert np.array_equal(words.reshape(2, -1), pack(ref))
