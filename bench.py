@@ -68,6 +68,56 @@ def cpu_baseline(target_s: float = 15.0) -> dict:
     }
 
 
+def bench_batched(ising, torch, nsweeps: int) -> dict:
+    """The batched workload: 1024 lattices of uneven L and beta in one persistent launch."""
+    cfg = workloads.BATCHED
+    Ls, betas, seeds, streams = workloads.batched_lattices()
+    b = ising.Batch(Ls, betas, cfg["J"], seeds, streams)
+    t0 = time.perf_counter()
+    tiles = b.autotune(20, None)
+    tune_s = time.perf_counter() - t0
+    b.init()
+    b.sweep(nsweeps)  # captures the graph (untimed), then a timed replay from a fresh start
+    b.init()
+    b.set_counter(0)
+    torch.cuda.synchronize()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record()
+    b.sweep(nsweeps)
+    e1.record()
+    torch.cuda.synchronize()
+    ms = e0.elapsed_time(e1)
+    updates = float(sum(int(L) * int(L) for L in Ls)) * nsweeps
+    # the largest lattices alone bound the makespan of one launch
+    big = [q for q in range(len(Ls)) if Ls[q] == max(Ls)]
+    bb = ising.Batch([Ls[q] for q in big], [betas[q] for q in big], cfg["J"],
+                     [seeds[q] for q in big], [streams[q] for q in big])
+    bb.set_tiles(int(max(Ls)), *tiles[int(max(Ls))])
+    bb.init()
+    bb.sweep(nsweeps)
+    bb.init()
+    bb.set_counter(0)
+    torch.cuda.synchronize()
+    e0.record()
+    bb.sweep(nsweeps)
+    e1.record()
+    torch.cuda.synchronize()
+    big_ms = e0.elapsed_time(e1)
+    b.close()
+    bb.close()
+    return {
+        "workload": "1024 lattices, L uniform over {16,...,256}, beta over linspace(0.30,0.60,32), "
+                    f"{nsweeps} sweeps each, one graph-replayed persistent launch",
+        "flips_per_ns": updates / (ms * 1e6),
+        "ms": ms,
+        "updates": updates,
+        "largest_size_alone_ms": big_ms,
+        "largest_size_count": len(big),
+        "tiles_words_lanes": {str(k): list(v) for k, v in tiles.items()},
+        "autotune_s": tune_s,
+    }
+
+
 def main() -> int:
     ap = argparse.ArgumentParser(description=__doc__)
     ap.add_argument("--gpus", type=int, default=1)
@@ -75,6 +125,8 @@ def main() -> int:
     ap.add_argument("--warmup", type=int, default=2)
     ap.add_argument("--no-cpu-baseline", action="store_true",
                     help="skip the CPU oracle timing (for profiler runs)")
+    ap.add_argument("--batched-sweeps", type=int, default=workloads.BATCHED["nsweeps"],
+                    help="sweeps of the batched workload reported beside the headline (0 = skip)")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="also run three plain 1 GiB device-to-device copies, whose HBM counter "
                          "readings scale the profiler's byte counts")
@@ -164,6 +216,8 @@ def main() -> int:
             "alg_bytes_per_launch": alg_bytes,
         },
     }
+    if args.batched_sweeps > 0:
+        out["batched"] = bench_batched(ising, torch, args.batched_sweeps)
     if args.copy_calibration:
         del bufs, lats
         a = torch.empty(1 << 27, dtype=torch.int64, device="cuda").fill_(1)

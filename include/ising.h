@@ -153,12 +153,14 @@ int ising_batch_get_counter(const ising_batch *b, uint64_t *rng_counter, void *h
 int ising_batch_observables(const ising_batch *b, int64_t *d_bond, int64_t *d_mag,
                             void *hip_stream);
 
-/* Words per thread used for lattices of size L (the persistent kernel's tile:
- * a lattice of W words per colour is served by ceil(W / wpt) threads, and
- * floor(256 / that) lattices share a workgroup).  set replans the batch;
- * results never depend on it. */
-int ising_batch_get_tiles(const ising_batch *b, int64_t L, uint32_t *wpt);
-int ising_batch_set_tiles(ising_batch *b, int64_t L, uint32_t wpt);
+/* Tile of lattices of size L in the persistent kernel: lpw (1 or 2) lanes per
+ * word -- a pair of lanes computes alternate Philox blocks of one word and
+ * both apply them in order -- and wpt words per lane group, so a lattice of W
+ * words per colour takes ceil(W / wpt) * lpw threads and floor(1024 / that)
+ * lattices share a workgroup.  set replans the batch; results never depend
+ * on the tile. */
+int ising_batch_get_tiles(const ising_batch *b, int64_t L, uint32_t *wpt, uint32_t *lpw);
+int ising_batch_set_tiles(ising_batch *b, int64_t L, uint32_t wpt, uint32_t lpw);
 
 /* Times every tile candidate of every lattice size in the batch over
  * tune_sweeps sweeps of a scratch copy (the batch itself is unchanged),

@@ -62,8 +62,9 @@ SIGNATURES = {
     "ising_batch_set_counter": (ctypes.c_int, [_vp, _u64, _vp]),
     "ising_batch_get_counter": (ctypes.c_int, [_vp, ctypes.POINTER(_u64), _vp]),
     "ising_batch_observables": (ctypes.c_int, [_vp, _vp, _vp, _vp]),
-    "ising_batch_get_tiles": (ctypes.c_int, [_vp, _i64, ctypes.POINTER(_u32)]),
-    "ising_batch_set_tiles": (ctypes.c_int, [_vp, _i64, _u32]),
+    "ising_batch_get_tiles": (ctypes.c_int, [_vp, _i64, ctypes.POINTER(_u32),
+                                             ctypes.POINTER(_u32)]),
+    "ising_batch_set_tiles": (ctypes.c_int, [_vp, _i64, _u32, _u32]),
     "ising_batch_autotune": (ctypes.c_int, [_vp, _i64, ctypes.c_char_p, _vp]),
     "ising_set_sweep_kernel": (ctypes.c_int, [ctypes.c_int]),
     "ising_last_error": (ctypes.c_char_p, []),

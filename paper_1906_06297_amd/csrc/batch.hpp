@@ -18,16 +18,19 @@ struct BatchLattice {
 };
 
 // A work item of the persistent kernel: `count` lattices of one size, swept
-// together by one workgroup.  Thread t serves lattice slot t / tpl and its
-// words t % tpl + j * tpl, j < wpt.
+// together by one workgroup.  Thread t serves lattice slot t / tpl; within
+// the slot, lanes form groups of lpw adjacent lanes, and group g serves
+// words g + j * (tpl / lpw), j < wpt.
 struct BatchBundle {
     uint32_t first; // index of the first slot in the member list
     uint32_t count; // lattices in the bundle
-    uint32_t wpt;   // words per thread (per colour)
-    uint32_t tpl;   // threads per lattice
+    uint32_t wpt;   // words per lane group (per colour)
+    uint32_t tpl;   // threads per lattice: ceil(W / wpt) * lpw
+    uint32_t lpw;   // lanes per word: 1, or 2 (the pair computes alternate Philox blocks)
+    uint32_t pad;
 };
 
-constexpr int kBatchThreads = 256;
+constexpr int kBatchThreads = 1024;
 
 // LDS words a lattice occupies in the persistent kernel: two extended colour arrays.
 __host__ __device__ inline uint32_t batch_lds_words(uint32_t W) { return 2 * (W + 2); }

@@ -19,13 +19,20 @@
 
 using namespace ising;
 
+namespace {
+struct Tile {
+    uint32_t wpt; // words per lane group
+    uint32_t lpw; // lanes per word (1 or 2)
+};
+} // namespace
+
 struct ising_batch {
     int32_t n = 0;
     std::vector<int64_t> Ls;
     std::vector<BatchLattice> lats; // host copy
     uint64_t *words = nullptr;      // caller's buffer
     size_t bytes = 0;
-    std::map<int64_t, uint32_t> wpt; // words per thread, per lattice size
+    std::map<int64_t, Tile> tiles;   // per lattice size
     // device state owned by the batch
     BatchLattice *d_lats = nullptr;
     uint32_t *d_members = nullptr;
@@ -42,11 +49,29 @@ struct ising_batch {
 
 namespace {
 
-constexpr uint32_t kMaxBatchL = 722; // two extended colour arrays within 64 KiB of LDS
+constexpr size_t kMaxBundleLds = 64 * 1024; // LDS of one workgroup
+constexpr uint32_t kMaxBatchL = 722;        // two extended colour arrays within 64 KiB of LDS
 
 uint32_t words_of(int64_t L) { return (uint32_t)((L * L / 2 + 63) / 64); }
 
-uint32_t default_wpt(uint32_t W) { return (W + kBatchThreads - 1) / kBatchThreads; }
+uint32_t threads_per_lattice(uint32_t W, Tile t) { return ((W + t.wpt - 1) / t.wpt) * t.lpw; }
+
+bool tile_ok(uint32_t W, Tile t)
+{
+    return t.wpt >= 1 && t.wpt <= W && (t.lpw == 1 || t.lpw == 2) &&
+           threads_per_lattice(W, t) <= (uint32_t)kBatchThreads;
+}
+
+// Without tuning: a lane pair per word when the lattice leaves room for it,
+// and as few words per lane group as the workgroup allows.
+Tile default_tile(uint32_t W)
+{
+    for (uint32_t lpw : {2u, 1u})
+        for (uint32_t wpt = 1; wpt <= W; ++wpt)
+            if (tile_ok(W, Tile{wpt, lpw}))
+                return Tile{wpt, lpw};
+    return Tile{W, 1};
+}
 
 struct Plan {
     std::vector<uint32_t> members;
@@ -55,8 +80,8 @@ struct Plan {
 };
 
 // Bundles of same-size lattices, largest work first.  `only_L` restricts the
-// plan to one size (autotuning), 0 = all.
-Plan make_plan(const ising_batch *b, int64_t only_L, uint32_t only_wpt)
+// plan to one size (autotuning) with tile `only`, 0 = all sizes, own tiles.
+Plan make_plan(const ising_batch *b, int64_t only_L, Tile only)
 {
     std::map<int64_t, std::vector<uint32_t>> by_size;
     for (int32_t q = 0; q < b->n; ++q)
@@ -71,15 +96,17 @@ Plan make_plan(const ising_batch *b, int64_t only_L, uint32_t only_wpt)
     for (auto &kv : by_size) {
         const int64_t L = kv.first;
         const uint32_t W = words_of(L);
-        uint32_t wpt = only_L ? only_wpt : b->wpt.at(L);
-        wpt = std::max(1u, std::min(wpt, W));
-        const uint32_t tpl = (W + wpt - 1) / wpt;
-        const uint32_t per = std::max(1u, (uint32_t)kBatchThreads / tpl);
+        const Tile tile = only_L ? only : b->tiles.at(L);
+        const uint32_t tpl = threads_per_lattice(W, tile);
+        // lattices per workgroup: limited by its threads and by 64 KiB of LDS
+        const uint32_t lds_per = (uint32_t)(kMaxBundleLds / ((size_t)batch_lds_words(W) * 8));
+        const uint32_t per =
+            std::max(1u, std::min((uint32_t)kBatchThreads / tpl, lds_per));
         for (size_t i = 0; i < kv.second.size(); i += per) {
             Item it;
             const uint32_t cnt = (uint32_t)std::min<size_t>(per, kv.second.size() - i);
             it.ids.assign(kv.second.begin() + i, kv.second.begin() + i + cnt);
-            it.bd = BatchBundle{0, cnt, wpt, tpl};
+            it.bd = BatchBundle{0, cnt, tile.wpt, tpl, tile.lpw, 0};
             it.work = (double)cnt * (double)(L * L);
             items.push_back(std::move(it));
         }
@@ -112,7 +139,8 @@ void free_plan_buffers(ising_batch *b)
 }
 
 // Workgroups of the persistent kernel: enough for every compute unit to hold
-// as many as its LDS allows (at most 8 of 256 threads), never more than bundles.
+// as many as its LDS and wavefront slots allow (two of 1024 threads), never
+// more than bundles.
 int persistent_grid(size_t lds_bytes, uint32_t nbundles, uint32_t *grid)
 {
     int dev = 0, cus = 0;
@@ -121,8 +149,8 @@ int persistent_grid(size_t lds_bytes, uint32_t nbundles, uint32_t *grid)
         e = hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev);
     if (e != hipSuccess || cus <= 0)
         return host::fail(ISING_E_HIP, "cannot query the number of compute units");
-    const int by_lds = lds_bytes ? (int)((160 * 1024) / lds_bytes) : 8;
-    const int occ = std::max(1, std::min(8, by_lds));
+    const int by_lds = lds_bytes ? (int)((160 * 1024) / lds_bytes) : 2;
+    const int occ = std::max(1, std::min(2, by_lds));
     *grid = std::max(1u, std::min(nbundles, (uint32_t)(cus * occ)));
     return ISING_OK;
 }
@@ -153,9 +181,9 @@ int check_batch(const ising_batch *b)
 }
 
 // ---------------------------------------------------------------- cache file
-std::string cache_key() { return "gfx950/batch-sweep-v1"; }
+std::string cache_key() { return "gfx950/batch-sweep-v2"; }
 
-bool read_cache(const char *path, std::map<int64_t, uint32_t> &out)
+bool read_cache(const char *path, std::map<int64_t, Tile> &out)
 {
     std::ifstream f(path);
     if (!f)
@@ -166,7 +194,7 @@ bool read_cache(const char *path, std::map<int64_t, uint32_t> &out)
     const std::string tag = "\"key\": \"" + cache_key() + "\"";
     if (s.find(tag) == std::string::npos)
         return false;
-    size_t pos = s.find("\"wpt\"");
+    size_t pos = s.find("\"tiles\"");
     if (pos == std::string::npos)
         return false;
     pos = s.find('{', pos);
@@ -175,25 +203,26 @@ bool read_cache(const char *path, std::map<int64_t, uint32_t> &out)
         return false;
     std::string body = s.substr(pos + 1, end - pos - 1);
     for (char &ch : body)
-        if (ch == '"' || ch == ',' || ch == ':')
+        if (ch == '"' || ch == ',' || ch == ':' || ch == '[' || ch == ']')
             ch = ' ';
     std::istringstream in(body);
     long long L;
-    unsigned w;
-    while (in >> L >> w)
-        out[(int64_t)L] = w;
+    unsigned w, l;
+    while (in >> L >> w >> l)
+        out[(int64_t)L] = Tile{w, l};
     return true;
 }
 
-bool write_cache(const char *path, const std::map<int64_t, uint32_t> &wpt)
+bool write_cache(const char *path, const std::map<int64_t, Tile> &tiles)
 {
     std::ofstream f(path);
     if (!f)
         return false;
-    f << "{\"key\": \"" << cache_key() << "\", \"wpt\": {";
+    f << "{\"key\": \"" << cache_key() << "\", \"tiles\": {";
     bool first = true;
-    for (auto &kv : wpt) {
-        f << (first ? "" : ", ") << "\"" << kv.first << "\": " << kv.second;
+    for (auto &kv : tiles) {
+        f << (first ? "" : ", ") << "\"" << kv.first << "\": [" << kv.second.wpt << ", "
+          << kv.second.lpw << "]";
         first = false;
     }
     f << "}}\n";
@@ -257,8 +286,8 @@ int ising_batch_create(ising_batch **out, int32_t n, const int64_t *Ls, const do
         lt.stream_id = stream_ids[q];
         b->lats.push_back(lt);
         b->Ls.push_back(Ls[q]);
-        if (!b->wpt.count(Ls[q]))
-            b->wpt[Ls[q]] = default_wpt(lt.W);
+        if (!b->tiles.count(Ls[q]))
+            b->tiles[Ls[q]] = default_tile(lt.W);
         off += 2 * (uint64_t)lt.W;
     }
     hipError_t e = hipMalloc(&b->d_lats, b->lats.size() * sizeof(BatchLattice));
@@ -278,7 +307,7 @@ int ising_batch_create(ising_batch **out, int32_t n, const int64_t *Ls, const do
         ising_batch_destroy(b);
         return host::hip_fail(e, "batch allocation");
     }
-    if (int r = install_plan(b, make_plan(b, 0, 0))) {
+    if (int r = install_plan(b, make_plan(b, 0, Tile{1, 1}))) {
         ising_batch_destroy(b);
         return r;
     }
@@ -409,30 +438,30 @@ int ising_batch_observables(const ising_batch *b, int64_t *d_bond, int64_t *d_ma
     return host::ok();
 }
 
-int ising_batch_get_tiles(const ising_batch *b, int64_t L, uint32_t *wpt)
+int ising_batch_get_tiles(const ising_batch *b, int64_t L, uint32_t *wpt, uint32_t *lpw)
 {
     if (int e = check_batch(b))
         return e;
-    auto it = b->wpt.find(L);
-    if (!wpt || it == b->wpt.end())
+    auto it = b->tiles.find(L);
+    if (!wpt || !lpw || it == b->tiles.end())
         return host::fail(ISING_E_BADARG, "no lattice of that size in the batch");
-    *wpt = it->second;
+    *wpt = it->second.wpt;
+    *lpw = it->second.lpw;
     return host::ok();
 }
 
-int ising_batch_set_tiles(ising_batch *b, int64_t L, uint32_t wpt)
+int ising_batch_set_tiles(ising_batch *b, int64_t L, uint32_t wpt, uint32_t lpw)
 {
     if (int e = check_batch(b))
         return e;
-    auto it = b->wpt.find(L);
-    if (it == b->wpt.end())
+    auto it = b->tiles.find(L);
+    if (it == b->tiles.end())
         return host::fail(ISING_E_BADARG, "no lattice of that size in the batch");
-    const uint32_t W = words_of(L);
-    if (wpt < 1 || (W + wpt - 1) / wpt > (uint32_t)kBatchThreads)
-        return host::fail(ISING_E_BADARG, "words per thread must be >= 1 and leave at most %d "
-                          "threads per lattice", kBatchThreads);
-    it->second = wpt;
-    return install_plan(b, make_plan(b, 0, 0));
+    if (!tile_ok(words_of(L), Tile{wpt, lpw}))
+        return host::fail(ISING_E_BADARG, "tile (%u words, %u lanes per word) does not fit a "
+                          "workgroup of %d threads", wpt, lpw, kBatchThreads);
+    it->second = Tile{wpt, lpw};
+    return install_plan(b, make_plan(b, 0, Tile{1, 1}));
 }
 
 int ising_batch_autotune(ising_batch *b, int64_t tune_sweeps, const char *cache_path,
@@ -443,15 +472,16 @@ int ising_batch_autotune(ising_batch *b, int64_t tune_sweeps, const char *cache_
     if (tune_sweeps <= 0)
         return host::fail(ISING_E_BADARG, "tune_sweeps must be > 0");
     hipStream_t s = (hipStream_t)hip_stream;
-    std::map<int64_t, uint32_t> cached;
+    std::map<int64_t, Tile> cached;
     if (cache_path && read_cache(cache_path, cached)) {
         bool complete = true;
-        for (auto &kv : b->wpt)
-            complete = complete && cached.count(kv.first);
+        for (auto &kv : b->tiles)
+            complete = complete && cached.count(kv.first) &&
+                       tile_ok(words_of(kv.first), cached[kv.first]);
         if (complete) {
-            for (auto &kv : b->wpt)
+            for (auto &kv : b->tiles)
                 kv.second = cached[kv.first];
-            return install_plan(b, make_plan(b, 0, 0));
+            return install_plan(b, make_plan(b, 0, Tile{1, 1}));
         }
     }
     // Scratch copy of the lattices and counter: tuning never changes the batch.
@@ -471,26 +501,28 @@ int ising_batch_autotune(ising_batch *b, int64_t tune_sweeps, const char *cache_
         e = hipEventCreate(&e1);
     std::vector<uint64_t> out_ref, out_try;
     int rc = ISING_OK;
-    for (auto &kv : b->wpt) {
+    for (auto &kv : b->tiles) {
         if (e != hipSuccess)
             break;
         const int64_t L = kv.first;
         const uint32_t W = words_of(L);
-        std::vector<uint32_t> cands;
-        for (uint32_t w : {1u, 2u, 3u, 4u, 6u, 8u, 12u, 16u}) {
-            if (w > W || (W + w - 1) / w > (uint32_t)kBatchThreads)
-                continue;
-            const uint32_t tpl = (W + w - 1) / w;
-            bool dup = false;
-            for (uint32_t c : cands)
-                dup = dup || (W + c - 1) / c == tpl;
-            if (!dup)
-                cands.push_back(w);
-        }
+        std::vector<Tile> cands;
+        for (uint32_t lpw : {1u, 2u})
+            for (uint32_t w : {1u, 2u, 3u, 4u, 6u, 8u, 12u, 16u}) {
+                const Tile t{w, lpw};
+                if (!tile_ok(W, t))
+                    continue;
+                bool dup = false;
+                for (const Tile &c : cands)
+                    dup = dup || (c.lpw == lpw && threads_per_lattice(W, c) ==
+                                                      threads_per_lattice(W, t));
+                if (!dup)
+                    cands.push_back(t);
+            }
         float best_ms = 1e30f;
-        uint32_t best = kv.second;
+        Tile best = kv.second;
         bool have_ref = false;
-        for (uint32_t w : cands) {
+        for (const Tile &w : cands) {
             const Plan p = make_plan(b, L, w);
             uint32_t grid = 0;
             if ((rc = persistent_grid(p.lds_bytes, (uint32_t)p.bundles.size(), &grid)))
@@ -539,8 +571,8 @@ int ising_batch_autotune(ising_batch *b, int64_t tune_sweeps, const char *cache_
             if (e != hipSuccess)
                 break;
             if (have_ref && out_try != out_ref) {
-                rc = host::fail(ISING_E_HIP, "autotune: tile %u of L=%lld changed the lattice",
-                                w, (long long)L);
+                rc = host::fail(ISING_E_HIP, "autotune: tile (%u, %u) of L=%lld changed the "
+                                "lattice", w.wpt, w.lpw, (long long)L);
                 break;
             }
             have_ref = true;
@@ -571,9 +603,9 @@ int ising_batch_autotune(ising_batch *b, int64_t tune_sweeps, const char *cache_
         return rc;
     if (e != hipSuccess)
         return host::hip_fail(e, "autotune");
-    if (cache_path && !write_cache(cache_path, b->wpt))
+    if (cache_path && !write_cache(cache_path, b->tiles))
         return host::fail(ISING_E_BADARG, "cannot write the autotune cache %s", cache_path);
-    return install_plan(b, make_plan(b, 0, 0));
+    return install_plan(b, make_plan(b, 0, Tile{1, 1}));
 }
 
 } // extern "C"

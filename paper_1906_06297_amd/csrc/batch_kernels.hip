@@ -23,10 +23,35 @@ __global__ __launch_bounds__(256) void k_batch_init(const BatchLattice *__restri
 __device__ __forceinline__ void ext_refresh(uint64_t *E, uint32_t M, uint32_t W)
 {
     uint64_t tail[3];
-    ext_tail(E, M, W, tail);
+    ext_tail_fast(E, M, W, tail);
     E[W - 1] = tail[0];
     E[W] = tail[1];
     E[W + 1] = tail[2];
+}
+
+__device__ __forceinline__ Block shuffle_xor1(const Block &x)
+{
+    return Block{(uint32_t)__shfl_xor((int)x.x0, 1, 64), (uint32_t)__shfl_xor((int)x.x1, 1, 64),
+                 (uint32_t)__shfl_xor((int)x.x2, 1, 64), (uint32_t)__shfl_xor((int)x.x3, 1, 64)};
+}
+
+// Decision of one word by a pair of adjacent lanes: each lane computes every
+// other Philox block (lane parity p takes q = 2j + p), the pair swaps them and
+// both apply the planes in block order, so the pair reaches the sequential
+// result in half the dependent steps.  Both lanes hold the same state.
+__device__ __forceinline__ uint64_t decide_word_pair(const Classes &k, uint64_t valid,
+                                                     uint32_t chunk, const SweepArgs2 &a,
+                                                     uint32_t parity)
+{
+    WordState s = start_word(k, valid, a.m);
+    for (uint32_t q0 = 0; q0 < 16 && s.pending != 0; q0 += 2) {
+        const Block mine = philox4x32_10(ctr_word0(a.stream_id, kDomainSweep, q0 + parity),
+                                         a.t_lo, a.t_hi, chunk, a.key0, a.key1);
+        const Block other = shuffle_xor1(mine);
+        apply_block(s, parity ? other : mine, q0, a.m);
+        apply_block(s, parity ? mine : other, q0 + 1, a.m);
+    }
+    return s.flips;
 }
 
 // Persistent sweep kernel.  Workgroups take bundles from an atomic counter
@@ -52,6 +77,7 @@ __global__ __launch_bounds__(kBatchThreads) void k_batch_sweep(
             return;
         const BatchBundle bd = bundles[b];
         const uint32_t slot = threadIdx.x / bd.tpl, li = threadIdx.x % bd.tpl;
+        const uint32_t group = li / bd.lpw, parity = li % bd.lpw, groups = bd.tpl / bd.lpw;
         const bool on = slot < bd.count;
         BatchLattice lt{};
         if (on)
@@ -64,10 +90,10 @@ __global__ __launch_bounds__(kBatchThreads) void k_batch_sweep(
                 (c ? E1 : E0)[k - c * lt.W] = words[lt.word_off + k];
             }
         __syncthreads();
-        if (on && li < 2 && (li < bd.tpl))
-            ext_refresh(li ? E1 : E0, lt.M, lt.W);
-        if (on && bd.tpl == 1)
+        if (on && li == 0) {
+            ext_refresh(E0, lt.M, lt.W);
             ext_refresh(E1, lt.M, lt.W);
+        }
         __syncthreads();
         for (int64_t sw = 0; sw < nsweeps; ++sw) {
             for (int c = 0; c < 2; ++c) {
@@ -78,13 +104,21 @@ __global__ __launch_bounds__(kBatchThreads) void k_batch_sweep(
                     const SweepArgs2 a{lt.m,      (uint32_t)t, (uint32_t)(t >> 32), lt.stream_id,
                                        lt.key0, lt.key1};
                     for (uint32_t j = 0; j < bd.wpt; ++j) {
-                        const uint32_t k = li + j * bd.tpl;
+                        const uint32_t k = group + j * groups;
                         if (k >= lt.W)
                             break;
-                        const Neighbours nb = neighbours_ext(src, lt.H, lt.M, k, c);
+                        RowMasks rm = row_masks32(k, lt.H, lt.M, 0);
+                        if (c)
+                            rm.left_rows = ~rm.left_rows; // rows of the other parity
+                        const Neighbours nb = neighbours_ext_rm(src, lt.H, lt.M, k, rm);
                         const uint64_t tw = tgt[k];
                         const Classes cl = classify(tw, nb.up, nb.dn, nb.ce, nb.sd);
-                        tgt[k] = tw ^ decide_word(cl, valid_mask(k, lt.M), k, a);
+                        const uint64_t valid = valid_mask(k, lt.M);
+                        const uint64_t flips = (bd.lpw == 2)
+                                                   ? decide_word_pair(cl, valid, k, a, parity)
+                                                   : decide_word(cl, valid, k, a);
+                        if (parity == 0)
+                            tgt[k] = tw ^ flips;
                     }
                 }
                 __syncthreads();

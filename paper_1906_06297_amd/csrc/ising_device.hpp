@@ -174,15 +174,11 @@ __host__ __device__ __forceinline__ void compare_plane(WordState &s, uint64_t pl
     s.pending ^= differ;
 }
 
-// Philox block q of word `chunk`: bit-planes 2q and 2q+1.  After the last
+// Applies the two bit-planes of Philox block q of a word.  After the last
 // block a spin still undecided has r == T, which is not < T: rejected.
-__host__ __device__ __forceinline__ void advance_block(WordState &s, uint32_t q, uint32_t chunk,
-                                                       const Metro2 &m, uint32_t t_lo,
-                                                       uint32_t t_hi, uint32_t stream_id,
-                                                       uint32_t key0, uint32_t key1)
+__host__ __device__ __forceinline__ void apply_block(WordState &s, const Block &x, uint32_t q,
+                                                     const Metro2 &m)
 {
-    const Block x =
-        philox4x32_10(ctr_word0(stream_id, kDomainSweep, q), t_lo, t_hi, chunk, key0, key1);
     const int bit = 31 - 2 * (int)q;
     compare_plane(s, (uint64_t)x.x0 | ((uint64_t)x.x1 << 32), bit_mask(m.thrA, bit),
                   bit_mask(m.thrB, bit));
@@ -190,6 +186,17 @@ __host__ __device__ __forceinline__ void advance_block(WordState &s, uint32_t q,
                   bit_mask(m.thrB, bit - 1));
     if (q == 15)
         s.pending = 0;
+}
+
+// Philox block q of word `chunk`: bit-planes 2q and 2q+1.
+__host__ __device__ __forceinline__ void advance_block(WordState &s, uint32_t q, uint32_t chunk,
+                                                       const Metro2 &m, uint32_t t_lo,
+                                                       uint32_t t_hi, uint32_t stream_id,
+                                                       uint32_t key0, uint32_t key1)
+{
+    apply_block(s,
+                philox4x32_10(ctr_word0(stream_id, kDomainSweep, q), t_lo, t_hi, chunk, key0, key1),
+                q, m);
 }
 
 // As compare_plane, for threshold bits known to be the same for every lane:
@@ -377,6 +384,60 @@ __host__ __device__ __forceinline__ Neighbours neighbours_ext(Ptr E, uint32_t H,
                            (ext_bits(E, wrap_spin(n0 - H + 1, M)) & rm.row_end);
     nb.sd = (left & rm.left_rows) | (right & ~rm.left_rows);
     return nb;
+}
+
+// Row masks of word k for lattices whose spin counts fit 32 bits.
+__host__ __device__ __forceinline__ RowMasks row_masks32(uint32_t k, uint32_t H, uint32_t M, int c)
+{
+    const uint32_t n0 = k << 6;
+    const uint32_t end = (n0 + 64 < M) ? n0 + 64 : M;
+    uint32_t i = n0 / H;
+    RowMasks r{0, 0, 0};
+    for (uint32_t rs = i * H; rs < end; ++i, rs += H) {
+        const uint32_t a = (rs > n0 ? rs : n0) - n0;
+        const uint32_t b = ((rs + H < end) ? rs + H : end) - n0;
+        const uint64_t seg = (b - a >= 64) ? ~0ull : (((1ull << (b - a)) - 1) << a);
+        if (((i + c) & 1) == 0)
+            r.left_rows |= seg;
+        if (rs >= n0)
+            r.row_start |= 1ull << (rs - n0);
+        if (rs + H - 1 < end)
+            r.row_end |= 1ull << (rs + H - 1 - n0);
+    }
+    return r;
+}
+
+// As neighbours_ext with precomputed row masks.
+template <typename Ptr>
+__host__ __device__ __forceinline__ Neighbours neighbours_ext_rm(Ptr E, uint32_t H, uint32_t M,
+                                                                 uint32_t k, const RowMasks &rm)
+{
+    const int64_t n0 = (int64_t)k << 6;
+    Neighbours nb;
+    nb.ce = ext_bits(E, (uint32_t)n0);
+    nb.up = ext_bits(E, wrap_spin(n0 - H, M));
+    nb.dn = ext_bits(E, wrap_spin(n0 + H, M));
+    const uint64_t left = (ext_bits(E, wrap_spin(n0 - 1, M)) & ~rm.row_start) |
+                          (ext_bits(E, wrap_spin(n0 + H - 1, M)) & rm.row_start);
+    const uint64_t right = (ext_bits(E, wrap_spin(n0 + 1, M)) & ~rm.row_end) |
+                           (ext_bits(E, wrap_spin(n0 - H + 1, M)) & rm.row_end);
+    nb.sd = (left & rm.left_rows) | (right & ~rm.left_rows);
+    return nb;
+}
+
+// Tail of an extended colour array, cheap when M is a multiple of 64 and the
+// colour has at least two words (then the tail repeats words 0 and 1).
+template <typename Ptr>
+__host__ __device__ __forceinline__ void ext_tail_fast(Ptr E, uint32_t M, uint32_t W,
+                                                       uint64_t out[3])
+{
+    if ((M & 63) == 0 && W >= 2) {
+        out[0] = E[W - 1];
+        out[1] = E[0];
+        out[2] = E[1];
+    } else {
+        ext_tail(E, M, W, out);
+    }
 }
 
 // New value of target word `chunk` of colour c, any geometry.

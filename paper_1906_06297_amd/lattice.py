@@ -212,13 +212,15 @@ class Batch:
         _lib.check(_lib.load().ising_batch_lattice(self._h, int(q), ctypes.byref(desc)))
         return Lattice.view(desc, self.words)
 
-    def tiles(self, L: int) -> int:
-        v = ctypes.c_uint32()
-        _lib.check(_lib.load().ising_batch_get_tiles(self._h, int(L), ctypes.byref(v)))
-        return int(v.value)
+    def tiles(self, L: int) -> tuple:
+        """(words per lane group, lanes per word) for lattices of size L."""
+        w, l = ctypes.c_uint32(), ctypes.c_uint32()
+        _lib.check(_lib.load().ising_batch_get_tiles(self._h, int(L), ctypes.byref(w),
+                                                     ctypes.byref(l)))
+        return int(w.value), int(l.value)
 
-    def set_tiles(self, L: int, wpt: int) -> None:
-        _lib.check(_lib.load().ising_batch_set_tiles(self._h, int(L), int(wpt)))
+    def set_tiles(self, L: int, wpt: int, lpw: int = 1) -> None:
+        _lib.check(_lib.load().ising_batch_set_tiles(self._h, int(L), int(wpt), int(lpw)))
 
     def autotune(self, tune_sweeps: int = 20, cache_path=None, stream=None) -> dict:
         path = cache_path.encode() if cache_path else None

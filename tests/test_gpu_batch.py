@@ -104,17 +104,18 @@ def test_every_tile_gives_the_same_lattice(gpu, orc, L):
     streams = list(range(100, 100 + n))
     ref = oracle_batch(orc, Ls, betas, 1.0, seeds, streams, 6)
     W = (L * L // 2 + 63) // 64
-    for wpt in sorted({1, 2, 3, 4, 6, 8, 16} & set(range(1, W + 1))):
-        if -(-W // wpt) > 256:
+    for lpw in (1, 2):
+      for wpt in sorted({1, 2, 3, 4, 6, 8, 16} & set(range(1, W + 1))):
+        if -(-W // wpt) * lpw > 1024:
             continue
-        say(f"tiles L={L} wpt={wpt}")
+        say(f"tiles L={L} wpt={wpt} lpw={lpw}")
         b = gpu.Batch(Ls, betas, 1.0, seeds, streams)
-        b.set_tiles(L, wpt)
-        assert b.tiles(L) == wpt
+        b.set_tiles(L, wpt, lpw)
+        assert b.tiles(L) == (wpt, lpw)
         b.init()
         b.sweep(6)
         for q in range(n):
-            assert np.array_equal(batch_words_of(b, q), pack(ref[q])), (wpt, q)
+            assert np.array_equal(batch_words_of(b, q), pack(ref[q])), (wpt, lpw, q)
         b.close()
 
 
