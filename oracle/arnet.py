@@ -1,0 +1,212 @@
+"""Oracle of the learned global proposal: a masked-convolution autoregressive
+network over Ising configurations and the independence Metropolis-Hastings
+step that uses it.
+
+TEST INFRASTRUCTURE ONLY (see ``oracle/__init__.py``).
+
+The paper motivates global moves by critical slowing down of local Metropolis
+updates and by the Wolff cluster algorithm (Sec. 2); it does not specify a
+learned proposal.  The network here is the standard PixelCNN construction
+(van den Oord et al., "Pixel Recurrent Neural Networks", ICML 2016), with the
+readings fixed for this project:
+
+  * sites in raster order p = i*L + j; the model is
+        q(x) = prod_p  q(x_p | x_<p),   q(x_p = +1 | x_<p) = sigmoid(logit_p);
+  * layer 1: 3x3 convolution with mask "A" (only strictly earlier sites:
+    offsets (-1,-1), (-1,0), (-1,+1), (0,-1)), 1 -> C channels, ReLU;
+  * layers 2..5: 3x3 mask "B" (those four offsets and the centre), C -> C, ReLU;
+  * layer 6: mask "B", C -> 1, giving the logit of every site;
+  * zero padding outside the lattice (no periodic wrap), so the conditionals
+    depend only on earlier sites.
+
+Parameters, in this order (the flat vector used everywhere):
+    W1[4][C], b1[C], (W_l[5][C][C], b_l[C]) for l = 2..5, W6[5][C], b6.
+W_l[t][ci][co] multiplies input channel ci at tap offset t into output co.
+
+Sampling draws x_p = +1 iff u_p < P_p with u_p a 24-bit uniform, so the
+realised probability of +1 is P~_p = ceil(P_p * 2^24) / 2^24, and the exact
+proposal probability of a configuration is prod_p (P~_p or 1 - P~_p).
+``log_q_exact`` computes that; ``log_q`` the smooth model value used by training.
+"""
+from __future__ import annotations
+
+import numpy as np
+
+TAPS = ((-1, -1), (-1, 0), (-1, 1), (0, -1), (0, 0))  # mask A = first four
+N_LAYERS = 6
+
+
+def num_params(C: int) -> int:
+    return 4 * C + C + 4 * (5 * C * C + C) + 5 * C + 1
+
+
+def unflatten(theta: np.ndarray, C: int) -> dict:
+    theta = np.asarray(theta, dtype=np.float64)
+    assert theta.size == num_params(C)
+    out, o = {}, 0
+
+    def take(shape):
+        nonlocal o
+        n = int(np.prod(shape))
+        v = theta[o:o + n].reshape(shape)
+        o += n
+        return v
+
+    out["W1"], out["b1"] = take((4, C)), take((C,))
+    for l in range(2, 6):
+        out[f"W{l}"], out[f"b{l}"] = take((5, C, C)), take((C,))
+    out["W6"], out["b6"] = take((5, C)), take(())
+    return out
+
+
+def flatten(p: dict, C: int) -> np.ndarray:
+    parts = [p["W1"], p["b1"]]
+    for l in range(2, 6):
+        parts += [p[f"W{l}"], p[f"b{l}"]]
+    parts += [p["W6"], np.atleast_1d(p["b6"])]
+    return np.concatenate([np.asarray(a, dtype=np.float64).reshape(-1) for a in parts])
+
+
+def init_params(C: int, seed: int, scale: float = 1.0) -> np.ndarray:
+    """He-style random parameters (fan-in = taps x input channels)."""
+    rng = np.random.default_rng(seed)
+    p = {"W1": rng.normal(0, scale * np.sqrt(2 / 4), (4, C)), "b1": np.zeros(C)}
+    for l in range(2, 6):
+        p[f"W{l}"] = rng.normal(0, scale * np.sqrt(2 / (5 * C)), (5, C, C))
+        p[f"b{l}"] = np.zeros(C)
+    p["W6"] = rng.normal(0, scale * np.sqrt(1 / (5 * C)), (5, C))
+    p["b6"] = np.float64(0.0)
+    return flatten(p, C)
+
+
+def bf16(a: np.ndarray) -> np.ndarray:
+    """Round to bfloat16 (nearest, ties to even) and back, via float32."""
+    f = np.asarray(a, dtype=np.float32)
+    u = f.view(np.uint32).astype(np.uint64)
+    u = (u + 0x7FFF + ((u >> 16) & 1)) & 0xFFFF0000
+    return u.astype(np.uint32).view(np.float32).astype(np.float64)
+
+
+def shift(h: np.ndarray, dy: int, dx: int) -> np.ndarray:
+    """out[b, i, j, ...] = h[b, i+dy, j+dx, ...], zero outside the lattice."""
+    out = np.zeros_like(h)
+    L = h.shape[1]
+    i0, i1 = max(0, -dy), min(L, L - dy)
+    j0, j1 = max(0, -dx), min(L, L - dx)
+    out[:, i0:i1, j0:j1] = h[:, i0 + dy:i1 + dy, j0 + dx:j1 + dx]
+    return out
+
+
+def forward(x: np.ndarray, theta: np.ndarray, C: int, emulate_bf16: bool = False):
+    """logits [B, L, L] and the list of activations (post-ReLU) of layers 1..5.
+
+    emulate_bf16: round weights, and activations between layers, to bfloat16
+    where the GPU stores them (sums stay in double)."""
+    p = unflatten(theta, C)
+    r = bf16 if emulate_bf16 else (lambda a: np.asarray(a, dtype=np.float64))
+    x = np.asarray(x, dtype=np.float64)
+    acts = []
+    pre = np.zeros(x.shape + (C,))
+    for t in range(4):
+        pre += shift(x, *TAPS[t])[..., None] * r(p["W1"][t])[None, None, None, :]
+    h = r(np.maximum(pre + p["b1"], 0.0))
+    acts.append(h)
+    for l in range(2, 6):
+        W = r(p[f"W{l}"])
+        pre = np.zeros_like(h)
+        for t in range(5):
+            pre += np.einsum("bijc,cd->bijd", shift(h, *TAPS[t]), W[t])
+        h = r(np.maximum(pre + p[f"b{l}"], 0.0))
+        acts.append(h)
+    W6 = r(p["W6"])
+    logit = np.full(x.shape, float(p["b6"]))
+    for t in range(5):
+        logit += np.einsum("bijc,c->bij", shift(h, *TAPS[t]), W6[t])
+    return logit, acts
+
+
+def log_sigmoid(z):
+    return -np.logaddexp(0.0, -z)
+
+
+def log_q(x, theta, C, emulate_bf16=False) -> np.ndarray:
+    """Model log-probability sum_p log sigmoid(x_p * logit_p), per configuration."""
+    logit, _ = forward(x, theta, C, emulate_bf16)
+    return log_sigmoid(np.asarray(x, np.float64) * logit).sum(axis=(1, 2))
+
+
+def quantised_p(logit: np.ndarray) -> np.ndarray:
+    """P~ = ceil(P * 2^24) / 2^24 with P = sigmoid(logit) in float32."""
+    P = (1.0 / (1.0 + np.exp(-np.asarray(logit, dtype=np.float32)))).astype(np.float32)
+    return np.ceil(P.astype(np.float64) * 2.0 ** 24) / 2.0 ** 24
+
+
+def log_q_exact(x, theta, C, emulate_bf16=True) -> np.ndarray:
+    """Exact log-probability that the sampler produces x (24-bit uniforms)."""
+    logit, _ = forward(x, theta, C, emulate_bf16)
+    Pq = quantised_p(logit)
+    x = np.asarray(x)
+    with np.errstate(divide="ignore"):
+        terms = np.where(x > 0, np.log(Pq), np.log1p(-Pq))
+    return terms.sum(axis=(1, 2))
+
+
+def nll_and_grad(x: np.ndarray, theta: np.ndarray, C: int, emulate_bf16: bool = False):
+    """Mean negative log-likelihood of a batch and its gradient (hand-written
+    backward through the masked convolutions)."""
+    p = unflatten(theta, C)
+    r = bf16 if emulate_bf16 else (lambda a: np.asarray(a, dtype=np.float64))
+    x = np.asarray(x, dtype=np.float64)
+    B = x.shape[0]
+    logit, acts = forward(x, theta, C, emulate_bf16)
+    s = x
+    nll = -log_sigmoid(s * logit).sum() / B
+    # d(-log sigmoid(s z))/dz = -s * sigmoid(-s z)
+    dlogit = -s / (1.0 + np.exp(s * logit)) / B
+    g = {k: np.zeros_like(np.asarray(v, dtype=np.float64)) for k, v in p.items()}
+    g["b6"] = np.float64(dlogit.sum())
+    W6 = r(p["W6"])
+    h5 = acts[4]
+    dh = np.zeros_like(h5)
+    for t in range(5):
+        dy, dx = TAPS[t]
+        g["W6"][t] = np.einsum("bijc,bij->c", shift(h5, dy, dx), dlogit)
+        dh += shift(dlogit[..., None] * W6[t][None, None, None, :], -dy, -dx)
+    for l in range(5, 1, -1):
+        dpre = r(dh * (acts[l - 1] > 0))
+        g[f"b{l}"] = dpre.sum(axis=(0, 1, 2))
+        hin = acts[l - 2]
+        W = r(p[f"W{l}"])
+        dh = np.zeros_like(hin)
+        for t in range(5):
+            dy, dx = TAPS[t]
+            g[f"W{l}"][t] = np.einsum("bijc,bijd->cd", shift(hin, dy, dx), dpre)
+            dh += shift(np.einsum("bijd,cd->bijc", dpre, W[t]), -dy, -dx)
+    dpre = r(dh * (acts[0] > 0))
+    g["b1"] = dpre.sum(axis=(0, 1, 2))
+    for t in range(4):
+        g["W1"][t] = np.einsum("bij,bijc->c", shift(x, *TAPS[t]), dpre)
+    return nll, flatten(g, C)
+
+
+def mh_accept_prob(beta, J, bond_cur, bond_prop, logq_cur, logq_prop):
+    """Independence Metropolis-Hastings acceptance (Metropolis et al. 1953 with
+    Hastings' correction): min(1, pi(x') q(x) / (pi(x) q(x'))), pi ~ exp(beta J bond)."""
+    log_a = beta * J * (np.asarray(bond_prop) - np.asarray(bond_cur)) + np.asarray(logq_cur) - np.asarray(logq_prop)
+    return np.minimum(1.0, np.exp(np.minimum(log_a, 0.0)))
+
+
+def sample(theta, C: int, L: int, B: int, rng, emulate_bf16: bool = True):
+    """Ancestral sampling site by site in raster order; returns (x, log q_exact)."""
+    x = np.zeros((B, L, L))
+    logq = np.zeros(B)
+    for i in range(L):
+        for j in range(L):
+            logit, _ = forward(x, theta, C, emulate_bf16)
+            Pq = quantised_p(logit[:, i, j])
+            u = rng.integers(0, 1 << 24, B) / 2.0 ** 24
+            up = u < Pq
+            x[:, i, j] = np.where(up, 1.0, -1.0)
+            with np.errstate(divide="ignore"):
+                logq += np.where(up, np.log(Pq), np.log1p(-Pq))
+    return x, logq

@@ -1,0 +1,133 @@
+"""Pins of the autoregressive-proposal oracle: hand-written gradient against
+double-precision finite differences and against PyTorch autograd, the
+autoregressive property, normalisation by enumeration, and exactness of the
+independence Metropolis-Hastings chain on 4x4 against enumeration."""
+import numpy as np
+import pytest
+
+from oracle import arnet, exact, stats
+
+
+def rand_spins(B, L, seed):
+    return np.where(np.random.default_rng(seed).random((B, L, L)) < 0.5, 1.0, -1.0)
+
+
+def test_param_count_and_roundtrip():
+    for C in (1, 3, 32, 64):
+        th = arnet.init_params(C, 1)
+        assert th.size == arnet.num_params(C)
+        assert np.array_equal(arnet.flatten(arnet.unflatten(th, C), C), th)
+
+
+def test_gradient_matches_finite_differences():
+    C, L = 3, 5
+    th = arnet.init_params(C, 7, scale=1.3) + np.random.default_rng(8).normal(0, 0.2, arnet.num_params(C))
+    x = rand_spins(4, L, 9)
+    _, g = arnet.nll_and_grad(x, th, C)
+    rng = np.random.default_rng(10)
+    idx = rng.choice(th.size, 60, replace=False)
+    h = 1e-6
+    for k in idx:
+        e = np.zeros_like(th)
+        e[k] = h
+        num = (arnet.nll_and_grad(x, th + e, C)[0] - arnet.nll_and_grad(x, th - e, C)[0]) / (2 * h)
+        assert abs(num - g[k]) <= 1e-6 + 1e-5 * abs(num), (k, num, g[k])
+
+
+def test_gradient_matches_torch_autograd():
+    torch = pytest.importorskip("torch")
+    C, L = 4, 6
+    th = arnet.init_params(C, 3) + np.random.default_rng(4).normal(0, 0.1, arnet.num_params(C))
+    x = rand_spins(5, L, 5)
+    nll, g = arnet.nll_and_grad(x, th, C)
+    p = {k: torch.tensor(np.asarray(v, dtype=np.float64), requires_grad=True) for k, v in arnet.unflatten(th, C).items()}
+    xt = torch.tensor(x)[:, None]  # (B, 1, L, L)
+
+    def masked_conv(h, taps_w, bias):
+        # taps_w: list of (dy, dx, [cin, cout]) ; out[b, co, i, j] = sum h[b, ci, i+dy, j+dx] w[ci, co]
+        out = 0
+        for (dy, dx), w in taps_w:
+            hp = torch.nn.functional.pad(h, (1, 1, 1, 1))
+            hs = hp[:, :, 1 + dy:1 + dy + L, 1 + dx:1 + dx + L]
+            out = out + torch.einsum("bcij,cd->bdij", hs, w)
+        return out + bias.reshape(1, -1, 1, 1)
+
+    h = torch.relu(masked_conv(xt, [(arnet.TAPS[t], p["W1"][t][None, :]) for t in range(4)], p["b1"]))
+    for l in range(2, 6):
+        h = torch.relu(masked_conv(h, [(arnet.TAPS[t], p[f"W{l}"][t]) for t in range(5)], p[f"b{l}"]))
+    logit = masked_conv(h, [(arnet.TAPS[t], p["W6"][t][:, None]) for t in range(5)], p["b6"].reshape(1))[:, 0]
+    loss = -torch.nn.functional.logsigmoid(torch.tensor(x) * logit).sum() / x.shape[0]
+    loss.backward()
+    gt = arnet.flatten({k: v.grad.numpy() for k, v in p.items()}, C)
+    assert abs(float(loss) - nll) < 1e-10
+    assert np.allclose(gt, g, rtol=1e-9, atol=1e-12)
+
+
+def test_autoregressive_property():
+    """logit_p depends only on sites strictly before p in raster order."""
+    C, L = 4, 6
+    th = arnet.init_params(C, 11, scale=1.5)
+    x = rand_spins(1, L, 12)
+    base, _ = arnet.forward(x, th, C)
+    for site in range(L * L):
+        y = x.copy()
+        y[0, site // L, site % L] *= -1
+        logit, _ = arnet.forward(y, th, C)
+        diff = (logit != base).reshape(-1)
+        assert not diff[: site + 1].any(), site  # sites <= the flipped one unchanged
+
+
+@pytest.mark.parametrize("emulate", [False, True])
+def test_normalisation_by_enumeration(emulate):
+    C, L = 3, 4
+    th = arnet.init_params(C, 21, scale=2.0)
+    states = exact.all_states(L).astype(np.float64)
+    lq = arnet.log_q(states, th, C, emulate)
+    assert abs(np.exp(lq).sum() - 1.0) < 1e-12
+    lqe = arnet.log_q_exact(states, th, C, emulate)
+    assert abs(np.exp(lqe).sum() - 1.0) < 1e-9
+
+
+def test_sampler_frequencies_match_q():
+    C, L = 2, 2  # 16 states: compare empirical frequencies with q_exact
+    th = arnet.init_params(C, 5, scale=2.0)
+    rng = np.random.default_rng(6)
+    x, lq = arnet.sample(th, C, L, 40000, rng)
+    assert np.allclose(lq, arnet.log_q_exact(x, th, C), atol=1e-9)
+    codes = ((x.reshape(len(x), -1) > 0) * (1 << np.arange(L * L))).sum(axis=1)
+    states = exact.all_states(L).astype(np.float64)
+    q = np.exp(arnet.log_q_exact(states, th, C))
+    counts = np.bincount(codes, minlength=16)
+    sd = np.sqrt(len(x) * q * (1 - q))
+    assert np.all(np.abs(counts - len(x) * q) <= 5 * sd + 1)
+
+
+def test_independence_chain_is_exact_on_4x4():
+    """A chain of pure learned proposals with a random-weight q reproduces the
+    Boltzmann averages (q has full support; MH corrects for it).  A random q is
+    nearly uniform over the 65536 states, so the temperature is chosen where
+    30000 proposals mix (at beta_c the few ordered states that carry most of
+    the weight are hardly ever proposed)."""
+    C, L, beta = 2, 4, 0.25
+    th = arnet.init_params(C, 33, scale=0.6)
+    rng = np.random.default_rng(34)
+    nprop = 30000
+    xs, lqs = arnet.sample(th, C, L, nprop, rng)
+    bonds = exact.bond_sum_many(xs.astype(np.int8)).astype(np.float64)
+    cur = 0
+    E, M2 = np.empty(nprop), np.empty(nprop)
+    acc = 0
+    u = rng.random(nprop)
+    for k in range(1, nprop):
+        a = arnet.mh_accept_prob(beta, 1.0, bonds[cur], bonds[k], lqs[cur], lqs[k])
+        if u[k] < a:
+            cur = k
+            acc += 1
+        E[k] = -bonds[cur] / 16
+        M2[k] = (xs[cur].sum() / 16) ** 2
+    E, M2 = E[100:], M2[100:]
+    ex = exact.enumerate_lattice(L, beta)
+    assert acc > 1000
+    for s, target in ((E, ex["E_per_site"]), (M2, ex["m2"])):
+        se = stats.blocking_se(s)
+        assert abs(s.mean() - target) < 4.5 * se, (s.mean(), target, se)
