@@ -171,6 +171,84 @@ int ising_batch_set_tiles(ising_batch *b, int64_t L, uint32_t wpt, uint32_t lpw)
 int ising_batch_autotune(ising_batch *b, int64_t tune_sweeps, const char *cache_path,
                          void *hip_stream);
 
+/* Copies every lattice of the batch to / from device int8 spins (+1/-1), L_q x
+ * L_q row-major per lattice, lattices back to back.  set rejects nothing: any
+ * nonzero positive byte is +1.  Asynchronous. */
+int ising_batch_get_spins_dev(const ising_batch *b, int8_t *d_spins, void *hip_stream);
+int ising_batch_set_spins_dev(ising_batch *b, const int8_t *d_spins, void *hip_stream);
+
+/* ------------------------------------------------------------------------
+ * Learned global proposal.  The paper names critical slowing down of local
+ * Metropolis updates and cluster moves (Sec. 2); here an autoregressive
+ * masked-convolution network q(x) = prod_p q(x_p | x_<p) over sites in raster
+ * order p = i*L + j proposes whole configurations, accepted by the
+ * independence Metropolis-Hastings rule, so the chain keeps the Boltzmann
+ * distribution of Eq. (1) exactly.
+ *   layer 1: 3x3 mask A (offsets (-1,-1), (-1,0), (-1,+1), (0,-1)), 1 -> C, ReLU
+ *   layers 2..5: 3x3 mask B (those and (0,0)), C -> C, ReLU
+ *   layer 6: mask B, C -> 1 logit; zero padding; q(x_p = +1 | .) = sigmoid.
+ * Parameters: one float32 vector (ising_arnet_num_params(C) entries) in the
+ * order W1[4][C], b1[C], (W_l[5][C][C], b_l[C]) for l = 2..5, W6[5][C], b6,
+ * W_l[t][ci][co] taking input channel ci at tap t to output co.  Weights are
+ * used in bfloat16, activations stored in bfloat16, sums in float32 (MFMA
+ * for the C -> C layers).  Spins are device int8 arrays, one L x L raster per
+ * configuration.  A sampled spin is +1 iff a 24-bit uniform (Philox domain 3)
+ * is below sigmoid(logit), so its realised probability is P~ = ceil(P 2^24) /
+ * 2^24; log-probabilities returned are the exact log prod_p (P~ or 1 - P~),
+ * bit-identical between the sampler and the evaluator.
+ * ------------------------------------------------------------------------ */
+typedef struct ising_arnet ising_arnet;
+
+/* Number of parameters for C channels (32 or 64); -1 otherwise. */
+int64_t ising_arnet_num_params(int32_t channels);
+
+/* Network for L x L configurations (2 <= L <= 1024), C = 32 or 64, and a
+ * workspace for batches of up to max_batch configurations; parameters start
+ * at zero.  Synchronous. */
+int ising_arnet_create(ising_arnet **out, int32_t L, int32_t channels, int32_t max_batch);
+int ising_arnet_destroy(ising_arnet *net);
+
+/* Copy parameters from / to a device float32 vector.  Asynchronous. */
+int ising_arnet_set_params(ising_arnet *net, const float *d_params, void *hip_stream);
+int ising_arnet_get_params(const ising_arnet *net, float *d_params, void *hip_stream);
+
+/* log q~ of B configurations into d_logq[B]; d_logits[B][L*L] may be NULL.
+ * Asynchronous. */
+int ising_arnet_log_prob(ising_arnet *net, const int8_t *d_spins, int32_t B, float *d_logq,
+                         float *d_logits, void *hip_stream);
+
+/* Mean negative log-likelihood -1/B sum_b sum_p log sigmoid(x_bp logit_bp)
+ * into d_loss[0] and its gradient into d_grad (may be NULL).  Asynchronous. */
+int ising_arnet_gradient(ising_arnet *net, const int8_t *d_spins, int32_t B, float *d_grad,
+                         float *d_loss, void *hip_stream);
+
+/* One Adam step (beta1 0.9, beta2 0.999, eps 1e-8) on that loss.  Asynchronous. */
+int ising_arnet_train_step(ising_arnet *net, const int8_t *d_spins, int32_t B, float lr,
+                           float *d_loss, void *hip_stream);
+
+/* Draws B configurations site by site; configuration b uses Philox stream
+ * id stream_base + b (< 2^24) and counter word `round`.  Writes the spins and
+ * their log q~.  Asynchronous. */
+int ising_arnet_sample(ising_arnet *net, int32_t B, uint64_t seed, uint32_t stream_base,
+                       uint64_t round, int8_t *d_spins, float *d_logq, void *hip_stream);
+
+/* Bond sum and magnetisation of B int8 configurations (periodic, each bond
+ * once).  Asynchronous. */
+int ising_spins_observables(const int8_t *d_spins, int32_t B, int64_t L, int64_t *d_bond,
+                            int64_t *d_mag, void *hip_stream);
+
+/* Independence Metropolis-Hastings step for n chains of L x L spins, in
+ * float32: log A = betaJ[c] (bond'[c] - bond[c]) + logq[c] - logq'[c];
+ * accepted iff log A >= 0 or u < exp(log A), u a 24-bit uniform of Philox
+ * domain 2 (stream stream_base + c, counter word `round`).  Accepted chains
+ * take the proposal's spins, log q and bond sum in place; d_accepted[c] is
+ * 1 or 0.  Asynchronous. */
+int ising_mh_independence(int32_t n, int64_t L, int8_t *d_state, float *d_logq, int64_t *d_bond,
+                          const int8_t *d_prop, const float *d_logq_prop,
+                          const int64_t *d_bond_prop, const float *d_betaJ, uint64_t seed,
+                          uint32_t stream_base, uint64_t round, int32_t *d_accepted,
+                          void *hip_stream);
+
 /* Selects the half-sweep kernel for later calls in this process, for tests and
  * measurements: 0 = default (row-aligned sizes, L % 128 == 0, use the
  * streaming row kernel with its per-wavefront work queue; other sizes the

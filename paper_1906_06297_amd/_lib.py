@@ -66,6 +66,21 @@ SIGNATURES = {
                                              ctypes.POINTER(_u32)]),
     "ising_batch_set_tiles": (ctypes.c_int, [_vp, _i64, _u32, _u32]),
     "ising_batch_autotune": (ctypes.c_int, [_vp, _i64, ctypes.c_char_p, _vp]),
+    "ising_batch_get_spins_dev": (ctypes.c_int, [_vp, _vp, _vp]),
+    "ising_batch_set_spins_dev": (ctypes.c_int, [_vp, _vp, _vp]),
+    "ising_arnet_num_params": (_i64, [ctypes.c_int32]),
+    "ising_arnet_create": (ctypes.c_int, [ctypes.POINTER(_vp), ctypes.c_int32, ctypes.c_int32,
+                                          ctypes.c_int32]),
+    "ising_arnet_destroy": (ctypes.c_int, [_vp]),
+    "ising_arnet_set_params": (ctypes.c_int, [_vp, _vp, _vp]),
+    "ising_arnet_get_params": (ctypes.c_int, [_vp, _vp, _vp]),
+    "ising_arnet_log_prob": (ctypes.c_int, [_vp, _vp, ctypes.c_int32, _vp, _vp, _vp]),
+    "ising_arnet_gradient": (ctypes.c_int, [_vp, _vp, ctypes.c_int32, _vp, _vp, _vp]),
+    "ising_arnet_train_step": (ctypes.c_int, [_vp, _vp, ctypes.c_int32, ctypes.c_float, _vp, _vp]),
+    "ising_arnet_sample": (ctypes.c_int, [_vp, ctypes.c_int32, _u64, _u32, _u64, _vp, _vp, _vp]),
+    "ising_spins_observables": (ctypes.c_int, [_vp, ctypes.c_int32, _i64, _vp, _vp, _vp]),
+    "ising_mh_independence": (ctypes.c_int, [ctypes.c_int32, _i64, _vp, _vp, _vp, _vp, _vp, _vp,
+                                             _vp, _u64, _u32, _u64, _vp, _vp]),
     "ising_set_sweep_kernel": (ctypes.c_int, [ctypes.c_int]),
     "ising_last_error": (ctypes.c_char_p, []),
 }

@@ -39,6 +39,7 @@ struct ising_batch {
     BatchBundle *d_bundles = nullptr;
     uint32_t *d_next = nullptr;
     uint64_t *d_counter = nullptr;
+    int64_t *d_spin_off = nullptr; // offset of lattice q in an int8 spin array
     uint32_t nbundles = 0, grid = 0;
     size_t lds_bytes = 0;
     // captured sweep
@@ -301,6 +302,16 @@ int ising_batch_create(ising_batch **out, int32_t n, const int64_t *Ls, const do
     const uint64_t zero = 0;
     if (e == hipSuccess)
         e = hipMemcpy(b->d_counter, &zero, 8, hipMemcpyHostToDevice);
+    std::vector<int64_t> spin_off((size_t)n);
+    int64_t so = 0;
+    for (int32_t q = 0; q < n; ++q) {
+        spin_off[(size_t)q] = so;
+        so += Ls[q] * Ls[q];
+    }
+    if (e == hipSuccess)
+        e = hipMalloc(&b->d_spin_off, (size_t)n * 8);
+    if (e == hipSuccess)
+        e = hipMemcpy(b->d_spin_off, spin_off.data(), (size_t)n * 8, hipMemcpyHostToDevice);
     if (e == hipSuccess)
         e = hipStreamCreateWithFlags(&b->capture_stream, hipStreamNonBlocking);
     if (e != hipSuccess) {
@@ -326,6 +337,8 @@ int ising_batch_destroy(ising_batch *b)
         (void)hipFree(b->d_next);
     if (b->d_counter)
         (void)hipFree(b->d_counter);
+    if (b->d_spin_off)
+        (void)hipFree(b->d_spin_off);
     if (b->capture_stream)
         (void)hipStreamDestroy(b->capture_stream);
     delete b;
@@ -435,6 +448,32 @@ int ising_batch_observables(const ising_batch *b, int64_t *d_bond, int64_t *d_ma
                                             (hipStream_t)hip_stream);
     if (e != hipSuccess)
         return host::hip_fail(e, "batch observables launch");
+    return host::ok();
+}
+
+int ising_batch_get_spins_dev(const ising_batch *b, int8_t *d_spins, void *hip_stream)
+{
+    if (int e = check_batch(b))
+        return e;
+    if (!d_spins)
+        return host::fail(ISING_E_BADARG, "null spins");
+    hipError_t e = launch_batch_to_spins(b->d_lats, (uint32_t)b->n, b->words, b->d_spin_off,
+                                         d_spins, (hipStream_t)hip_stream);
+    if (e != hipSuccess)
+        return host::hip_fail(e, "batch to spins");
+    return host::ok();
+}
+
+int ising_batch_set_spins_dev(ising_batch *b, const int8_t *d_spins, void *hip_stream)
+{
+    if (int e = check_batch(b))
+        return e;
+    if (!d_spins)
+        return host::fail(ISING_E_BADARG, "null spins");
+    hipError_t e = launch_batch_from_spins(b->d_lats, (uint32_t)b->n, b->words, b->d_spin_off,
+                                           d_spins, (hipStream_t)hip_stream);
+    if (e != hipSuccess)
+        return host::hip_fail(e, "spins to batch");
     return host::ok();
 }
 

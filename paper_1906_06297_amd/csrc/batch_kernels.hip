@@ -185,6 +185,57 @@ __global__ __launch_bounds__(256) void k_batch_observables(const BatchLattice *_
     }
 }
 
+// Bit-packed lattices <-> int8 rasters (one workgroup per lattice).
+__global__ __launch_bounds__(256) void k_batch_to_spins(const BatchLattice *__restrict__ lats,
+                                                        const uint64_t *__restrict__ words,
+                                                        const int64_t *__restrict__ spin_off,
+                                                        int8_t *__restrict__ spins)
+{
+    const BatchLattice lt = lats[blockIdx.x];
+    int8_t *out = spins + spin_off[blockIdx.x];
+    for (uint32_t p = threadIdx.x; p < lt.L * lt.L; p += blockDim.x) {
+        const uint32_t i = p / lt.L, j = p % lt.L, c = (i + j) & 1, n = i * lt.H + (j >> 1);
+        const uint64_t w = words[lt.word_off + (uint64_t)c * lt.W + (n >> 6)];
+        out[p] = ((w >> (n & 63)) & 1u) ? 1 : -1;
+    }
+}
+
+__global__ __launch_bounds__(256) void k_batch_from_spins(const BatchLattice *__restrict__ lats,
+                                                          uint64_t *__restrict__ words,
+                                                          const int64_t *__restrict__ spin_off,
+                                                          const int8_t *__restrict__ spins)
+{
+    const BatchLattice lt = lats[blockIdx.x];
+    const int8_t *in = spins + spin_off[blockIdx.x];
+    for (uint32_t k = threadIdx.x; k < 2 * lt.W; k += blockDim.x) {
+        const uint32_t c = k >= lt.W, kk = k - c * lt.W;
+        uint64_t w = 0;
+        for (uint32_t b = 0; b < 64; ++b) {
+            const uint32_t n = kk * 64 + b;
+            if (n >= lt.M)
+                break;
+            const uint32_t i = n / lt.H, jc = n % lt.H, j = 2 * jc + ((i + c) & 1);
+            if (in[i * lt.L + j] > 0)
+                w |= 1ull << b;
+        }
+        words[lt.word_off + k] = w;
+    }
+}
+
+hipError_t launch_batch_to_spins(const BatchLattice *lats, uint32_t n, const uint64_t *words,
+                                 const int64_t *spin_off, int8_t *spins, hipStream_t s)
+{
+    hipLaunchKernelGGL(k_batch_to_spins, dim3(n), dim3(256), 0, s, lats, words, spin_off, spins);
+    return hipGetLastError();
+}
+
+hipError_t launch_batch_from_spins(const BatchLattice *lats, uint32_t n, uint64_t *words,
+                                   const int64_t *spin_off, const int8_t *spins, hipStream_t s)
+{
+    hipLaunchKernelGGL(k_batch_from_spins, dim3(n), dim3(256), 0, s, lats, words, spin_off, spins);
+    return hipGetLastError();
+}
+
 hipError_t launch_batch_init(const BatchLattice *lats, uint32_t n, uint64_t *words,
                              hipStream_t s)
 {

@@ -32,6 +32,10 @@ def set_sweep_kernel(variant: int) -> None:
     _lib.check(_lib.load().ising_set_sweep_kernel(int(variant)))
 
 
+def _ptr(t):
+    return ctypes.c_void_p(t.data_ptr())
+
+
 def _stream_handle(stream=None):
     s = stream if stream is not None else torch.cuda.current_stream()
     return ctypes.c_void_p(s.cuda_stream)
@@ -207,6 +211,18 @@ class Batch:
         out = self.observables_async(stream).cpu().numpy()
         return out[0], out[1]
 
+    def spins(self, out=None, stream=None):
+        """Every lattice as int8 +1/-1 rasters, concatenated (device tensor)."""
+        n = sum(L * L for L in self.Ls)
+        if out is None:
+            out = torch.empty(n, dtype=torch.int8, device=self.words.device)
+        _lib.check(_lib.load().ising_batch_get_spins_dev(self._h, _ptr(out), _stream_handle(stream)))
+        return out
+
+    def set_spins(self, spins, stream=None) -> None:
+        _lib.check(_lib.load().ising_batch_set_spins_dev(self._h, _ptr(spins),
+                                                         _stream_handle(stream)))
+
     def lattice(self, q: int) -> "Lattice":
         desc = _lib.LatticeStruct()
         _lib.check(_lib.load().ising_batch_lattice(self._h, int(q), ctypes.byref(desc)))
@@ -227,3 +243,117 @@ class Batch:
         _lib.check(_lib.load().ising_batch_autotune(self._h, int(tune_sweeps), path,
                                                     _stream_handle(stream)))
         return {L: self.tiles(L) for L in sorted(set(self.Ls))}
+
+
+
+def arnet_num_params(channels: int) -> int:
+    n = _lib.load().ising_arnet_num_params(int(channels))
+    if n < 0:
+        raise ValueError("channels must be 32 or 64")
+    return int(n)
+
+
+class ARNet:
+    """The learned global proposal: a masked-convolution autoregressive network
+    over L x L configurations (int8 +1/-1 device tensors of shape (B, L, L))."""
+
+    def __init__(self, L: int, channels: int, max_batch: int, device="cuda"):
+        self.L, self.C, self.max_batch = int(L), int(channels), int(max_batch)
+        self.device = torch.device(device)
+        self.P = arnet_num_params(self.C)
+        self._h = ctypes.c_void_p()
+        _lib.check(_lib.load().ising_arnet_create(ctypes.byref(self._h), self.L, self.C,
+                                                  self.max_batch))
+
+    def close(self) -> None:
+        if self._h:
+            _lib.load().ising_arnet_destroy(self._h)
+            self._h = ctypes.c_void_p()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def set_params(self, params, stream=None) -> None:
+        t = torch.as_tensor(params, dtype=torch.float32).to(self.device).contiguous()
+        assert t.numel() == self.P
+        _lib.check(_lib.load().ising_arnet_set_params(self._h, _ptr(t), _stream_handle(stream)))
+        self._keep = t  # the copy is stream-ordered; keep the source alive
+
+    def params(self, stream=None):
+        out = torch.empty(self.P, dtype=torch.float32, device=self.device)
+        _lib.check(_lib.load().ising_arnet_get_params(self._h, _ptr(out), _stream_handle(stream)))
+        return out
+
+    def _check_spins(self, spins):
+        assert spins.dtype == torch.int8 and spins.is_contiguous()
+        assert spins.numel() % (self.L * self.L) == 0
+        return spins.numel() // (self.L * self.L)
+
+    def log_prob(self, spins, logits=False, stream=None):
+        B = self._check_spins(spins)
+        logq = torch.empty(B, dtype=torch.float32, device=self.device)
+        lg = torch.empty((B, self.L, self.L), dtype=torch.float32, device=self.device) if logits else None
+        _lib.check(_lib.load().ising_arnet_log_prob(self._h, _ptr(spins), B, _ptr(logq),
+                                                    _ptr(lg) if logits else None,
+                                                    _stream_handle(stream)))
+        return (logq, lg) if logits else logq
+
+    def gradient(self, spins, stream=None):
+        B = self._check_spins(spins)
+        grad = torch.empty(self.P, dtype=torch.float32, device=self.device)
+        loss = torch.empty(1, dtype=torch.float32, device=self.device)
+        _lib.check(_lib.load().ising_arnet_gradient(self._h, _ptr(spins), B, _ptr(grad), _ptr(loss),
+                                                    _stream_handle(stream)))
+        return loss, grad
+
+    def train_step(self, spins, lr: float, loss=None, stream=None):
+        B = self._check_spins(spins)
+        if loss is None:
+            loss = torch.empty(1, dtype=torch.float32, device=self.device)
+        _lib.check(_lib.load().ising_arnet_train_step(self._h, _ptr(spins), B, float(lr), _ptr(loss),
+                                                      _stream_handle(stream)))
+        return loss
+
+    def sample(self, B: int, seed: int, stream_base: int = 0, round: int = 0, out=None,
+               logq=None, stream=None):
+        if out is None:
+            out = torch.empty((B, self.L, self.L), dtype=torch.int8, device=self.device)
+        if logq is None:
+            logq = torch.empty(B, dtype=torch.float32, device=self.device)
+        _lib.check(_lib.load().ising_arnet_sample(self._h, int(B), int(seed), int(stream_base),
+                                                  int(round), _ptr(out), _ptr(logq),
+                                                  _stream_handle(stream)))
+        return out, logq
+
+
+def spins_observables(spins, L: int, stream=None):
+    """(bond, M) device int64 tensors of int8 configurations of shape (B, L, L)."""
+    B = spins.numel() // (L * L)
+    bond = torch.empty(B, dtype=torch.int64, device=spins.device)
+    mag = torch.empty(B, dtype=torch.int64, device=spins.device)
+    _lib.check(_lib.load().ising_spins_observables(_ptr(spins), B, int(L), _ptr(bond), _ptr(mag),
+                                                   _stream_handle(stream)))
+    return bond, mag
+
+
+def mh_independence(state, logq, bond, prop, logq_prop, bond_prop, betaJ, seed: int,
+                    stream_base: int, round: int, accepted=None, stream=None):
+    """Independence Metropolis-Hastings step on n chains (in place)."""
+    n = logq.numel()
+    L = int(round_sqrt(state.numel() // n))
+    if accepted is None:
+        accepted = torch.empty(n, dtype=torch.int32, device=state.device)
+    _lib.check(_lib.load().ising_mh_independence(
+        n, L, _ptr(state), _ptr(logq), _ptr(bond), _ptr(prop), _ptr(logq_prop), _ptr(bond_prop),
+        _ptr(betaJ), int(seed), int(stream_base), int(round), _ptr(accepted),
+        _stream_handle(stream)))
+    return accepted
+
+
+def round_sqrt(n: int) -> int:
+    r = int(np.sqrt(n) + 0.5)
+    assert r * r == n
+    return r
