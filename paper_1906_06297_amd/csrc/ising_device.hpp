@@ -157,18 +157,27 @@ __host__ __device__ __forceinline__ WordState start_word(const Classes &k, uint6
     return s;
 }
 
-// All ones where bit `bit` of thr is set, else zero.
-__host__ __device__ __forceinline__ uint64_t bit_mask(uint32_t thr, int bit)
+// All ones where bit `bit` of thr is set, else zero (32 bits).
+__host__ __device__ __forceinline__ uint32_t bit_mask(uint32_t thr, int bit)
 {
-    return (uint64_t)0 - (uint64_t)((thr >> bit) & 1u);
+    // move the bit to the sign position and sign-extend: one shift pair
+    return (uint32_t)((int32_t)(thr << (31 - bit)) >> 31);
+}
+
+// Per 32-bit half: bits of m1 where sel is set, bits of m0 elsewhere.
+__host__ __device__ __forceinline__ uint32_t select_bits(uint32_t sel, uint32_t m1, uint32_t m0)
+{
+    return (sel & m1) | (~sel & m0);
 }
 
 // One bit-plane of the exact compare r < T: spins whose r bit differs from
 // their threshold bit are decided (accepted where the threshold bit is 1).
-__host__ __device__ __forceinline__ void compare_plane(WordState &s, uint64_t plane, uint64_t mA,
-                                                       uint64_t mB)
+// mA, mB: the plane's threshold bit of classes A and B as all-ones/zero.
+__host__ __device__ __forceinline__ void compare_plane(WordState &s, uint64_t plane, uint32_t mA,
+                                                       uint32_t mB)
 {
-    const uint64_t tb = (s.classA & mA) | (~s.classA & mB);
+    const uint64_t tb = (uint64_t)select_bits((uint32_t)s.classA, mA, mB) |
+                        ((uint64_t)select_bits((uint32_t)(s.classA >> 32), mA, mB) << 32);
     const uint64_t differ = s.pending & (plane ^ tb);
     s.flips |= differ & tb;
     s.pending ^= differ;

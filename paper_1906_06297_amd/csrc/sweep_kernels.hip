@@ -278,6 +278,48 @@ __global__ __launch_bounds__(256) void k_observables(const uint64_t *__restrict_
     }
 }
 
+// Row-aligned lattices (L % 128 == 0): the same sums with the neighbour words
+// addressed directly, as in the row sweep.
+__global__ __launch_bounds__(256) void k_observables_rows(const uint64_t *__restrict__ black,
+                                                          const uint64_t *__restrict__ white,
+                                                          int64_t L, int64_t Wr, int64_t *bond_out,
+                                                          int64_t *mag_out)
+{
+    int64_t bond = 0, mag = 0;
+    const int64_t W = L * Wr, stride = (int64_t)gridDim.x * blockDim.x;
+    for (int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; k < W; k += stride) {
+        const int64_t i = k / Wr, w = k - i * Wr;
+        const uint64_t t = black[k], ce = white[k];
+        const uint64_t up = white[((i == 0) ? L - 1 : i - 1) * Wr + w];
+        const uint64_t dn = white[((i + 1 == L) ? 0 : i + 1) * Wr + w];
+        const bool left = (i & 1) == 0; // colour 0: side neighbour on the left on even rows
+        const int64_t wa = left ? (w == 0 ? Wr - 1 : w - 1) : (w + 1 == Wr ? 0 : w + 1);
+        const uint64_t sd = side_vector(ce, white[i * Wr + wa], left);
+        const int64_t aligned = (int64_t)__popcll(~(t ^ up)) + (int64_t)__popcll(~(t ^ dn)) +
+                                (int64_t)__popcll(~(t ^ ce)) + (int64_t)__popcll(~(t ^ sd));
+        bond += 2 * aligned - 4 * 64;
+        mag += 2 * ((int64_t)__popcll(t) + (int64_t)__popcll(ce)) - 2 * 64;
+    }
+    bond = wave_sum(bond);
+    mag = wave_sum(mag);
+    __shared__ int64_t part[2][4];
+    const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+    if (lane == 0) {
+        part[0][wv] = bond;
+        part[1][wv] = mag;
+    }
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        int64_t b = 0, m = 0;
+        for (int q = 0; q < (int)(blockDim.x >> 6); ++q) {
+            b += part[0][q];
+            m += part[1][q];
+        }
+        atomicAdd((unsigned long long *)bond_out, (unsigned long long)b);
+        atomicAdd((unsigned long long *)mag_out, (unsigned long long)m);
+    }
+}
+
 // ------------------------------------------------------------------ launches
 static inline uint32_t blocks_for(int64_t n, int threads)
 {
@@ -331,8 +373,12 @@ hipError_t launch_observables(const uint64_t *words, int64_t L, int64_t *bond, i
     hipLaunchKernelGGL(k_fill_i64, dim3(1), dim3(64), 0, s, bond, (int64_t)1, (int64_t)0);
     hipLaunchKernelGGL(k_fill_i64, dim3(1), dim3(64), 0, s, mag, (int64_t)1, (int64_t)0);
     const uint32_t nb = (uint32_t)((W + 255) / 256 < 4096 ? (W + 255) / 256 : 4096);
-    hipLaunchKernelGGL(k_observables, dim3(nb), dim3(256), 0, s, words, words + W, H, M, W, bond,
-                       mag);
+    if (L % 128 == 0)
+        hipLaunchKernelGGL(k_observables_rows, dim3(nb), dim3(256), 0, s, words, words + W, L,
+                           L / 128, bond, mag);
+    else
+        hipLaunchKernelGGL(k_observables, dim3(nb), dim3(256), 0, s, words, words + W, H, M, W,
+                           bond, mag);
     return hipGetLastError();
 }
 

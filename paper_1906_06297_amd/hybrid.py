@@ -1,0 +1,121 @@
+"""Learned global proposals in practice: training data from the plain
+checkerboard sampler, training, and hybrid chains that interleave local
+bit-packed sweeps with independence Metropolis-Hastings moves proposed by the
+autoregressive network.  Every step runs in the library's kernels; this
+module only sequences the calls and keeps the bookkeeping.
+"""
+from __future__ import annotations
+
+import time
+
+import numpy as np
+import torch
+
+from . import lattice as lt
+
+
+def plain_configurations(L: int, beta: float, chains: int, snapshots: int, thin: int, burn: int,
+                         seed: int, J: float = 1.0, stream_base: int = 0):
+    """(chains * snapshots, L, L) int8 configurations from independent plain
+    chains: `burn` sweeps, then a snapshot every `thin` sweeps."""
+    b = lt.Batch([L] * chains, [beta] * chains, J, [seed] * chains,
+                 list(range(stream_base, stream_base + chains)))
+    b.init()
+    b.sweep(burn)
+    out = torch.empty((snapshots, chains, L, L), dtype=torch.int8, device=b.words.device)
+    for k in range(snapshots):
+        b.sweep(thin)
+        b.spins(out=out[k].view(-1))
+    b.close()
+    return out.view(-1, L, L)
+
+
+def augment(x: torch.Tensor, gen: torch.Generator) -> torch.Tensor:
+    """Symmetries of the periodic Boltzmann weight: global spin flip and
+    translations (a random shift per configuration)."""
+    B, L, _ = x.shape
+    flip = (torch.randint(0, 2, (B, 1, 1), generator=gen, device=x.device) * 2 - 1).to(torch.int8)
+    di = torch.randint(0, L, (B,), generator=gen, device=x.device)
+    dj = torch.randint(0, L, (B,), generator=gen, device=x.device)
+    idx_i = (torch.arange(L, device=x.device)[None, :] + di[:, None]) % L
+    idx_j = (torch.arange(L, device=x.device)[None, :] + dj[:, None]) % L
+    y = x[torch.arange(B, device=x.device)[:, None, None], idx_i[:, :, None], idx_j[:, None, :]]
+    return (y * flip).contiguous()
+
+
+def train(net: "lt.ARNet", data: torch.Tensor, steps: int, batch: int, lr: float, seed: int = 0,
+          log_every: int = 0):
+    """Adam on the mean negative log-likelihood of augmented minibatches."""
+    gen = torch.Generator(device=data.device)
+    gen.manual_seed(seed)
+    hist = []
+    loss = torch.empty(1, dtype=torch.float32, device=data.device)
+    for s in range(steps):
+        idx = torch.randint(0, data.shape[0], (batch,), generator=gen, device=data.device)
+        xb = augment(data[idx], gen)
+        net.train_step(xb, lr, loss=loss)
+        if log_every and (s % log_every == 0 or s == steps - 1):
+            hist.append((s, float(loss.item()) / (net.L * net.L)))
+    return hist
+
+
+class Chains:
+    """n independent chains on L x L lattices (bit-packed, batch kernel)."""
+
+    def __init__(self, L: int, betas, seed: int, J: float = 1.0, stream_base: int = 0):
+        self.L, self.n, self.J = int(L), len(betas), float(J)
+        self.betas = np.asarray(betas, dtype=np.float64)
+        self.batch = lt.Batch([L] * self.n, self.betas, J, [seed] * self.n,
+                              list(range(stream_base, stream_base + self.n)))
+        self.batch.init()
+        dev = self.batch.words.device
+        self.spins = torch.empty((self.n, L, L), dtype=torch.int8, device=dev)
+        self.betaJ = torch.as_tensor(self.betas * J, dtype=torch.float32, device=dev)
+        self.accepted = 0
+        self.proposed = 0
+
+    def observables(self):
+        bond, mag = self.batch.observables_async()
+        return bond, mag
+
+    def local(self, nsweeps: int) -> None:
+        self.batch.sweep(nsweeps)
+
+    def global_move(self, net: "lt.ARNet", seed: int, rnd: int, stream_base: int = 0):
+        """One independence MH move per chain with a fresh proposal from `net`."""
+        self.batch.spins(out=self.spins.view(-1))
+        logq = net.log_prob(self.spins)
+        bond, _ = lt.spins_observables(self.spins, self.L)
+        prop, logq_prop = net.sample(self.n, seed=seed, stream_base=stream_base, round=rnd)
+        bond_prop, _ = lt.spins_observables(prop, self.L)
+        acc = lt.mh_independence(self.spins, logq, bond, prop, logq_prop, bond_prop, self.betaJ,
+                                 seed=seed + 1, stream_base=stream_base, round=rnd)
+        self.batch.set_spins(self.spins)
+        self.accepted += int(acc.sum().item())
+        self.proposed += self.n
+        return acc
+
+    def close(self):
+        self.batch.close()
+
+
+def run_series(chains: Chains, rounds: int, local_per_round: int, net=None, seed: int = 0,
+               round0: int = 1):
+    """Per round: `local_per_round` sweeps, then (if net) one global move.
+    Returns (E per site, |m|) arrays of shape (rounds, n) and the wall time."""
+    N = chains.L * chains.L
+    E = torch.empty((rounds, chains.n), dtype=torch.float64, device=chains.spins.device)
+    A = torch.empty_like(E)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for r in range(rounds):
+        if local_per_round:
+            chains.local(local_per_round)
+        if net is not None:
+            chains.global_move(net, seed, round0 + r)
+        bond, mag = chains.observables()
+        E[r] = -chains.J * bond.to(torch.float64) / N
+        A[r] = mag.abs().to(torch.float64) / N
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    return E.cpu().numpy(), A.cpu().numpy(), wall

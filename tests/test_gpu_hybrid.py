@@ -1,0 +1,57 @@
+"""The learned proposal in use: a network trained on plain-sampler
+configurations, hybrid chains (one local sweep + one global move per round)
+against the exact energy, and what the trained network gains over the plain
+sweep in integrated autocorrelation time."""
+import numpy as np
+import pytest
+
+from oracle import exact
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def trained():
+    import torch
+
+    import paper_1906_06297_amd as m
+    from paper_1906_06297_amd import hybrid
+
+    assert torch.cuda.is_available()
+    L, beta = 8, 0.44
+    data = hybrid.plain_configurations(L, beta, chains=512, snapshots=32, thin=10, burn=300, seed=5)
+    net = m.ARNet(L, 32, 512)
+    from oracle import arnet as ref
+    net.set_params(ref.init_params(32, 3, scale=0.5).astype(np.float32))
+    hist = hybrid.train(net, data, steps=600, batch=256, lr=2e-3, seed=1, log_every=100)
+    print("training NLL per site:", hist, flush=True)
+    yield m, hybrid, net, L, beta, hist
+    net.close()
+
+
+def test_training_learned_something(trained):
+    _, _, _, _, _, hist = trained
+    assert hist[-1][1] < 0.8 * hist[0][1]
+
+
+def test_hybrid_chain_matches_exact_energy_and_beats_plain_tau(trained):
+    from paper_1906_06297_amd import stats
+
+    m, hybrid, net, L, beta, _ = trained
+    n, rounds = 256, 400
+    target = exact.transfer_matrix(L, beta)["E_per_site"]
+    res = {}
+    for name, use_net in (("plain", None), ("hybrid", net)):
+        ch = hybrid.Chains(L, [beta] * n, seed=17 if use_net else 19)
+        hybrid.run_series(ch, 200, 1, use_net, seed=23, round0=1)  # burn-in
+        E, A, wall = hybrid.run_series(ch, rounds, 1, use_net, seed=23, round0=1000)
+        acc = ch.accepted / max(ch.proposed, 1)
+        ch.close()
+        per_chain = E.mean(axis=0)
+        se = per_chain.std(ddof=1) / np.sqrt(n)
+        tau = stats.tau_int_chains(A)
+        res[name] = (per_chain.mean(), se, tau, acc, wall)
+        print(name, res[name], "exact", target, flush=True)
+        assert abs(per_chain.mean() - target) < 4.5 * se, (name, per_chain.mean(), target, se)
+    assert res["hybrid"][3] > 0.05  # the trained proposal is accepted
+    assert res["hybrid"][2] < res["plain"][2]  # and decorrelates |m| faster per round

@@ -55,7 +55,7 @@ def test_sweep_parity(gpu, orc, L, beta, J):
     assert np.array_equal(got, pack(ref)), f"first mismatch {np.argwhere(got != pack(ref))[:4]}"
 
 
-@pytest.mark.parametrize("L", [4, 10, 24, 64, 256, 1000])
+@pytest.mark.parametrize("L", [4, 10, 24, 64, 128, 256, 384, 1000])
 def test_set_get_roundtrip_and_observables(gpu, orc, L):
     say(f"set/get/observables L={L}")
     lat = gpu.Lattice(L, seed=1)
