@@ -25,9 +25,45 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 if ROOT not in sys.path:
     sys.path.insert(0, ROOT)
 
+import numpy as np  # noqa: E402
+
 import workloads  # noqa: E402
 
 HBM_PEAK_GBS = 8000.0  # MI355X HBM3E, GB/s
+KERNEL_SOURCES = ("paper_1906_06297_amd/csrc/sweep_kernels.hip",
+                  "paper_1906_06297_amd/csrc/ising_device.hpp")
+COUNTERS_SUMMARY = "profiles/half_sweep_L65536_counters.md"
+
+
+def kernel_source_hash() -> str:
+    import hashlib
+
+    h = hashlib.sha256()
+    for rel in KERNEL_SOURCES:
+        with open(os.path.join(ROOT, rel), "rb") as f:
+            h.update(f.read())
+    return h.hexdigest()
+
+
+def measured_traffic():
+    """HBM bytes per half-sweep launch from the committed counter summary, if it
+    was taken on the kernel sources as they are now (else None)."""
+    path = os.path.join(ROOT, COUNTERS_SUMMARY)
+    if not os.path.exists(path):
+        return None
+    vals = {}
+    with open(path) as f:
+        for line in f:
+            if ":" in line and line.strip().startswith(("source-sha256", "fetch_bytes_per_launch",
+                                                        "write_bytes_per_launch")):
+                k, v = line.split(":", 1)
+                vals[k.strip()] = v.strip()
+    if vals.get("source-sha256") != kernel_source_hash():
+        return None
+    try:
+        return float(vals["fetch_bytes_per_launch"]) + float(vals["write_bytes_per_launch"])
+    except (KeyError, ValueError):
+        return None
 
 
 def onsager_energy(beta: float) -> float:
@@ -118,6 +154,55 @@ def bench_batched(ising, torch, nsweeps: int) -> dict:
     }
 
 
+def bench_learned(ising, torch, L: int = 32, beta: float = 0.44, C: int = 32, chains: int = 256,
+                  rounds: int = 400, train_steps: int = 1500) -> dict:
+    """Learned global proposal against the plain sweep on the same GPU: per round
+    one local sweep, plus one proposal in the hybrid chains; tau_int of |m| and E
+    per round, effective samples per second, and the observables of both."""
+    from paper_1906_06297_amd import hybrid, stats
+
+    t0 = time.perf_counter()
+    data = hybrid.plain_configurations(L, beta, chains=1024, snapshots=64, thin=20, burn=1000,
+                                       seed=41)
+    t_data = time.perf_counter() - t0
+    net = ising.ARNet(L, C, max(256, chains))
+    net.set_params(hybrid.init_params(L, C, seed=1))
+    t0 = time.perf_counter()
+    hist = hybrid.train(net, data, steps=train_steps, batch=256, lr=2e-3, seed=2,
+                        log_every=max(1, train_steps // 5))
+    torch.cuda.synchronize()
+    t_train = time.perf_counter() - t0
+    res = {}
+    for name, use in (("plain", None), ("hybrid", net)):
+        ch = hybrid.Chains(L, [beta] * chains, seed=43, stream_base=0)
+        hybrid.run_series(ch, 200, 1, use, seed=47, round0=1)  # burn-in
+        E, A, wall = hybrid.run_series(ch, rounds, 1, use, seed=47, round0=10_000)
+        acc = ch.accepted / ch.proposed if ch.proposed else None
+        ch.close()
+        tau_m, tau_e = stats.tau_int_chains(A), stats.tau_int_chains(E)
+        pe, pm = E.mean(axis=0), A.mean(axis=0)
+        res[name] = {
+            "acceptance": acc,
+            "tau_int_abs_m_rounds": tau_m,
+            "tau_int_E_rounds": tau_e,
+            "ms_per_round": wall / rounds * 1e3,
+            "ess_per_s_abs_m": chains * rounds / (2 * tau_m) / wall,
+            "ess_per_s_E": chains * rounds / (2 * tau_e) / wall,
+            "E_per_site": float(pe.mean()), "E_se": float(pe.std(ddof=1) / np.sqrt(chains)),
+            "abs_m": float(pm.mean()), "abs_m_se": float(pm.std(ddof=1) / np.sqrt(chains)),
+        }
+    net.close()
+    return {
+        "workload": f"L={L}, beta={beta}, {C}-channel masked-conv autoregressive proposal trained on "
+                    f"{data.shape[0]} plain-sampler configurations ({train_steps} Adam steps, batch 256); "
+                    f"{chains} chains x {rounds} rounds, a round = 1 sweep (+ 1 proposal in hybrid)",
+        "train_nll_per_site": hist,
+        "data_s": t_data,
+        "train_s": t_train,
+        **res,
+    }
+
+
 def main() -> int:
     ap = argparse.ArgumentParser(description=__doc__)
     ap.add_argument("--gpus", type=int, default=1)
@@ -127,10 +212,18 @@ def main() -> int:
                     help="skip the CPU oracle timing (for profiler runs)")
     ap.add_argument("--batched-sweeps", type=int, default=workloads.BATCHED["nsweeps"],
                     help="sweeps of the batched workload reported beside the headline (0 = skip)")
+    ap.add_argument("--learned-rounds", type=int, default=400,
+                    help="rounds of the learned-proposal comparison reported beside the headline "
+                         "(0 = skip)")
+    ap.add_argument("--print-source-hash", action="store_true",
+                    help="print the hash of the half-sweep kernel sources and exit")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="also run three plain 1 GiB device-to-device copies, whose HBM counter "
                          "readings scale the profiler's byte counts")
     args = ap.parse_args()
+    if args.print_source_hash:
+        print(kernel_source_hash())
+        return 0
     if args.gpus != 1:
         print(f"bench.py measures one GPU; --gpus {args.gpus} is not supported (the sweep is "
               "built and measured on a single MI355X)", file=sys.stderr)
@@ -211,13 +304,15 @@ def main() -> int:
             "peak": HBM_PEAK_GBS,
             "unit": "GB/s",
             "frac": achieved / HBM_PEAK_GBS,
-            "traffic": None,
+            "traffic": measured_traffic(),
             "avg_launch_us": half_sweep_ms * 1e3,
             "alg_bytes_per_launch": alg_bytes,
         },
     }
     if args.batched_sweeps > 0:
         out["batched"] = bench_batched(ising, torch, args.batched_sweeps)
+    if args.learned_rounds > 0:
+        out["learned"] = bench_learned(ising, torch, rounds=args.learned_rounds)
     if args.copy_calibration:
         del bufs, lats
         a = torch.empty(1 << 27, dtype=torch.int64, device="cuda").fill_(1)

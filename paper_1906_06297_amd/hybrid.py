@@ -14,6 +14,18 @@ import torch
 from . import lattice as lt
 
 
+def init_params(L_unused: int, C: int, seed: int, scale: float = 0.5) -> np.ndarray:
+    """Random starting parameters in the ABI order (W1, b1, W_l, b_l for
+    l = 2..5, W6, b6): normal weights with variance scale^2 * 2 / fan-in,
+    zero biases."""
+    rng = np.random.default_rng(seed)
+    parts = [rng.normal(0, scale * np.sqrt(2 / 4), 4 * C), np.zeros(C)]
+    for _ in range(4):
+        parts += [rng.normal(0, scale * np.sqrt(2 / (5 * C)), 5 * C * C), np.zeros(C)]
+    parts += [rng.normal(0, scale * np.sqrt(1 / (5 * C)), 5 * C), np.zeros(1)]
+    return np.concatenate(parts).astype(np.float32)
+
+
 def plain_configurations(L: int, beta: float, chains: int, snapshots: int, thin: int, burn: int,
                          seed: int, J: float = 1.0, stream_base: int = 0):
     """(chains * snapshots, L, L) int8 configurations from independent plain
