@@ -1,0 +1,286 @@
+// Streaming half-sweep of row-aligned lattices (L % 128 == 0) on gfx950: the
+// per-word steps written on 32-bit halves with the three-input logic
+// instruction of gfx950, so that the Philox rounds, the neighbour count and
+// the bit-plane compare take as few vector instructions as the hardware
+// allows.  Every helper here computes exactly what the 64-bit helpers of
+// ising_device.hpp compute (same Philox counters, same planes, same
+// thresholds); only the instruction count differs.
+#pragma once
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include "ising_device.hpp"
+
+namespace ising {
+namespace rows {
+
+// ------------------------------------------------------ three-input logic
+// v_bitop3_b32 d, a, b, c, TT: bit (4a + 2b + c) of the 8-bit immediate TT is
+// the result for input bits a, b, c.  kA, kB, kC are the tables of the three
+// inputs themselves, so the table of a logic expression is that expression
+// evaluated on them.
+constexpr uint32_t kA = 0xF0, kB = 0xCC, kC = 0xAA;
+constexpr uint32_t tt(uint32_t v) { return v & 0xFFu; }
+
+template <uint32_t TT>
+__host__ __device__ __forceinline__ uint32_t lop3(uint32_t a, uint32_t b, uint32_t c)
+{
+#if defined(__HIP_DEVICE_COMPILE__)
+    return __builtin_amdgcn_bitop3_b32(a, b, c, TT);
+#else
+    // the instruction's definition, for the host build of these helpers
+    uint32_t r = 0;
+    for (uint32_t i = 0; i < 8; ++i)
+        if ((TT >> i) & 1u)
+            r |= ((i & 4u) ? a : ~a) & ((i & 2u) ? b : ~b) & ((i & 1u) ? c : ~c);
+    return r;
+#endif
+}
+
+constexpr uint32_t kXor3 = tt(kA ^ kB ^ kC);
+
+__host__ __device__ __forceinline__ uint32_t xor3(uint32_t a, uint32_t b, uint32_t c)
+{
+    return lop3<kXor3>(a, b, c);
+}
+
+// ------------------------------------------------------------------ Philox
+// Philox4x32-10 as in ising_device.hpp, with each round's "high product ^
+// counter word ^ key" terms as single three-input XORs.  Which terms vary per
+// lane is fixed by the counter: words 1 and 2 (the half-sweep index) are the
+// same in every lane, word 3 (the word index) is not, and word 0 (stream,
+// domain, block) is too when the block index differs per lane
+// (`Uniform012` false).  The early rounds still have wave-uniform terms,
+// which the scalar unit computes.
+template <bool Uniform012>
+__host__ __device__ __forceinline__ Block philox_fast(uint32_t c0, uint32_t c1, uint32_t c2,
+                                                      uint32_t c3, uint32_t k0, uint32_t k1)
+{
+#pragma unroll
+    for (int round = 0; round < 10; ++round) {
+        if (round > 0) {
+            k0 += 0x9E3779B9u;
+            k1 += 0xBB67AE85u;
+        }
+        const uint64_t pa = (uint64_t)0xD2511F53u * c0;
+        const uint64_t pb = (uint64_t)0xCD9E8D57u * c2;
+        // A XOR with at most one lane-varying input is one vector XOR after
+        // the scalar unit has combined the other two; the fused XOR is used
+        // once both of the first two inputs vary per lane.
+        const bool plain0 = Uniform012 ? round <= 3 : round <= 1;
+        const bool plain2 = Uniform012 ? round <= 2 : (round == 1 || round == 2);
+        const uint32_t n0 = plain0 ? ((uint32_t)(pb >> 32) ^ c1 ^ k0)
+                                   : xor3((uint32_t)(pb >> 32), c1, k0);
+        const uint32_t n2 = plain2 ? ((uint32_t)(pa >> 32) ^ c3 ^ k1)
+                                   : xor3((uint32_t)(pa >> 32), c3, k1);
+        c1 = (uint32_t)pb;
+        c3 = (uint32_t)pa;
+        c0 = n0;
+        c2 = n2;
+    }
+    return Block{c0, c1, c2, c3};
+}
+
+// --------------------------------------------------------- neighbour count
+// Per 32-bit half, with D_k = 1 where neighbour k is "unfavourable" (differs
+// from the spin for J > 0, equals it for J < 0; Sec. 2):
+//   zero = no D_k set      -> class B (|dE| = 8|J|),
+//   one  = exactly one set -> class A (|dE| = 4|J|),
+//   ge2  = two or more set -> dE <= 0, always flipped.
+struct Split {
+    uint32_t ge2, one, zero;
+};
+
+template <bool Anti>
+__host__ __device__ __forceinline__ Split split_classes(uint32_t s, uint32_t n0, uint32_t n1,
+                                                        uint32_t n2, uint32_t n3)
+{
+    // D_k = s ^ n_k (J > 0) or ~(s ^ n_k) (J < 0), folded into the tables
+    constexpr uint32_t dB = Anti ? (~(kA ^ kB)) : (kA ^ kB);
+    constexpr uint32_t dC = Anti ? (~(kA ^ kC)) : (kA ^ kC);
+    const uint32_t o01 = lop3<tt(dB | dC)>(s, n0, n1);
+    const uint32_t a01 = lop3<tt(dB & dC)>(s, n0, n1);
+    const uint32_t o23 = lop3<tt(dB | dC)>(s, n2, n3);
+    const uint32_t a23 = lop3<tt(dB & dC)>(s, n2, n3);
+    Split r;
+    r.ge2 = lop3<tt(kA | kB | kC)>(lop3<tt(kA | (kB & kC))>(a01, o01, o23), a23, 0u);
+    r.one = lop3<tt((kA | kB) & ~kC)>(o01, o23, r.ge2);
+    r.zero = ~(o01 | o23);
+    return r;
+}
+
+// ---------------------------------------------------------- decision state
+// Per 32-bit half h: tf = target word with the flips decided so far applied,
+// p = spins still undecided, a = class-A spins (class B elsewhere).
+struct State {
+    uint32_t tf[2], p[2], a[2];
+};
+
+// Uniform per-launch masks (all ones or zero) of the Metropolis classes.
+struct ClassMasks {
+    uint32_t alwaysA, alwaysB, randA, randB;
+};
+
+__host__ __device__ __forceinline__ ClassMasks class_masks(const Metro2 &m)
+{
+    return ClassMasks{m.alwaysA ? ~0u : 0u, m.alwaysB ? ~0u : 0u, m.randA ? ~0u : 0u,
+                      m.randB ? ~0u : 0u};
+}
+
+// Start state of half h.  `Plain`: both classes need a random number and
+// neither always flips (every J != 0, 0 < beta < infinity with non-degenerate
+// thresholds), the common case.
+template <bool Plain>
+__host__ __device__ __forceinline__ void start_half(State &s, int h, uint32_t t, const Split &k,
+                                                    const ClassMasks &cm)
+{
+    if (Plain) {
+        s.tf[h] = t ^ k.ge2;
+        s.a[h] = k.one;
+        s.p[h] = ~k.ge2;
+    } else {
+        const uint32_t f = lop3<tt(kA | (kB & kC))>(k.ge2, k.one, cm.alwaysA) | (k.zero & cm.alwaysB);
+        s.tf[h] = t ^ f;
+        s.a[h] = k.one & cm.randA;
+        s.p[h] = lop3<tt(kA | (kB & kC))>(s.a[h], k.zero, cm.randB);
+    }
+}
+
+// One bit-plane (both 32-bit halves, Plo and Phi) against threshold bits bA,
+// bB that every lane shares: where the r bit differs from the spin's
+// threshold bit the spin is decided, accepted (flipped) if the threshold bit
+// is 1.
+__host__ __device__ __forceinline__ void plane_uniform(State &s, uint32_t Plo, uint32_t Phi,
+                                                       bool bA, bool bB)
+{
+    const uint32_t P[2] = {Plo, Phi};
+    if (!bA && !bB) { // r bit 1 rejects
+#pragma unroll
+        for (int h = 0; h < 2; ++h)
+            s.p[h] = lop3<tt(kA & ~kB)>(s.p[h], P[h], 0u);
+    } else if (bA && bB) { // r bit 0 accepts
+#pragma unroll
+        for (int h = 0; h < 2; ++h) {
+            s.tf[h] = lop3<tt(kA ^ (kB & ~kC))>(s.tf[h], s.p[h], P[h]);
+            s.p[h] &= P[h];
+        }
+    } else if (bA) { // class A: r bit 0 accepts; class B: r bit 1 rejects
+#pragma unroll
+        for (int h = 0; h < 2; ++h) {
+            s.tf[h] = lop3<tt(kA ^ (kB & kC))>(s.tf[h], lop3<tt(kA & ~kB)>(s.p[h], P[h], 0u), s.a[h]);
+            s.p[h] = lop3<tt(kA & ~(kB ^ kC))>(s.p[h], P[h], s.a[h]);
+        }
+    } else { // class B: r bit 0 accepts; class A: r bit 1 rejects
+#pragma unroll
+        for (int h = 0; h < 2; ++h) {
+            s.tf[h] = lop3<tt(kA ^ (kB & ~kC))>(s.tf[h], lop3<tt(kA & ~kB)>(s.p[h], P[h], 0u), s.a[h]);
+            s.p[h] = lop3<tt(kA & (kB ^ kC))>(s.p[h], P[h], s.a[h]);
+        }
+    }
+}
+
+// The same with per-lane threshold masks mA, mB (all ones where the plane's
+// bit of T_A, T_B is 1): threshold bit tb = a ? mA : mB.
+__host__ __device__ __forceinline__ void plane_lane(State &s, int h, uint32_t P, uint32_t mA,
+                                                    uint32_t mB)
+{
+    uint32_t &tf = s.tf[h], &p = s.p[h];
+    const uint32_t tb = lop3<tt((kA & kB) | (~kA & kC))>(s.a[h], mA, mB);
+    const uint32_t differ = lop3<tt(kA & (kB ^ kC))>(p, P, tb);
+    tf = lop3<tt(kA ^ (kB & kC))>(tf, differ, tb);
+    p ^= differ;
+}
+
+// All ones where bit `bit` of thr is set (per lane).
+__host__ __device__ __forceinline__ uint32_t thr_mask(uint32_t thr, uint32_t bit)
+{
+#if defined(__HIP_DEVICE_COMPILE__)
+    return (uint32_t)__builtin_amdgcn_sbfe((int32_t)thr, bit, 1);
+#else
+    return ((thr >> bit) & 1u) ? ~0u : 0u;
+#endif
+}
+
+// Block q (planes 2q, 2q+1) with lane-shared threshold bits.
+__host__ __device__ __forceinline__ void block_uniform(State &s, uint32_t q, uint32_t chunk,
+                                                       const SweepArgs2 &a)
+{
+    const Block x = philox_fast<true>(ctr_word0(a.stream_id, kDomainSweep, q), a.t_lo, a.t_hi,
+                                      chunk, a.key0, a.key1);
+    const uint32_t b0 = 31 - 2 * q, b1 = 30 - 2 * q;
+    const bool a0 = (a.m.thrA >> b0) & 1u, B0 = (a.m.thrB >> b0) & 1u;
+    const bool a1 = (a.m.thrA >> b1) & 1u, B1 = (a.m.thrB >> b1) & 1u;
+    plane_uniform(s, x.x0, x.x1, a0, B0);
+    plane_uniform(s, x.x2, x.x3, a1, B1);
+}
+
+// Block q with per-lane q.  After block 15 (all 32 planes) a spin still
+// undecided has r == T, not < T: rejected, which the caller does by dropping
+// the word.
+__host__ __device__ __forceinline__ void block_lane(State &s, uint32_t q, uint32_t chunk,
+                                                    const SweepArgs2 &a)
+{
+    const Block x = philox_fast<false>(ctr_word0(a.stream_id, kDomainSweep, q), a.t_lo, a.t_hi,
+                                       chunk, a.key0, a.key1);
+    const uint32_t b0 = 31 - 2 * q, b1 = 30 - 2 * q;
+    const uint32_t mA0 = thr_mask(a.m.thrA, b0), mB0 = thr_mask(a.m.thrB, b0);
+    const uint32_t mA1 = thr_mask(a.m.thrA, b1), mB1 = thr_mask(a.m.thrB, b1);
+    plane_lane(s, 0, x.x0, mA0, mB0);
+    plane_lane(s, 1, x.x1, mA0, mB0);
+    plane_lane(s, 0, x.x2, mA1, mB1);
+    plane_lane(s, 1, x.x3, mA1, mB1);
+}
+
+// ----------------------------------------------------------- word helpers
+__host__ __device__ __forceinline__ uint32_t lo32(uint64_t v) { return (uint32_t)v; }
+__host__ __device__ __forceinline__ uint32_t hi32(uint64_t v) { return (uint32_t)(v >> 32); }
+__host__ __device__ __forceinline__ uint64_t join(uint32_t lo, uint32_t hi)
+{
+    return (uint64_t)lo | ((uint64_t)hi << 32);
+}
+
+// Funnel shift: low 32 bits of (hi:lo) >> sh, 0 < sh < 32.
+__host__ __device__ __forceinline__ uint32_t funnel(uint32_t hi, uint32_t lo, uint32_t sh)
+{
+#if defined(__HIP_DEVICE_COMPILE__)
+    return __builtin_amdgcn_alignbit(hi, lo, sh);
+#else
+    return (uint32_t)((((uint64_t)hi << 32) | lo) >> sh);
+#endif
+}
+
+// Start state of a word from its target word and four source words: up, down
+// and centre words of the same column, `adj_half` = the half of the adjacent
+// source word that feeds the side vector (high half of the left word when
+// `left`, low half of the right word otherwise).
+template <bool Anti, bool Plain>
+__host__ __device__ __forceinline__ State start_word_rows(uint64_t t, uint64_t up, uint64_t dn,
+                                                          uint64_t ce, uint32_t adj_half,
+                                                          bool left, const ClassMasks &cm)
+{
+    const uint32_t cl = lo32(ce), ch = hi32(ce);
+    // side vector: centre shifted by one spin, the adjacent word's edge spin
+    // shifted in (Sec. 3.3, Fig. 3)
+    const uint32_t sl = left ? funnel(cl, adj_half, 31) : funnel(ch, cl, 1);
+    const uint32_t sh = left ? funnel(ch, cl, 31) : funnel(adj_half, ch, 1);
+    State s;
+    start_half<Plain>(s, 0, lo32(t),
+                      split_classes<Anti>(lo32(t), lo32(up), lo32(dn), cl, sl), cm);
+    start_half<Plain>(s, 1, hi32(t),
+                      split_classes<Anti>(hi32(t), hi32(up), hi32(dn), ch, sh), cm);
+    return s;
+}
+
+// --------------------------------------------------- XCD-aware block order
+// Workgroups are handed to the 8 XCDs of the chip in turn (block b to XCD
+// b % 8).  The logical block of hardware block b gives each XCD a contiguous
+// range, so neighbouring bands, whose halo rows overlap, share an L2.
+__host__ __device__ __forceinline__ uint32_t xcd_block(uint32_t b, uint32_t nblocks)
+{
+    const uint32_t x = b & 7u, j = b >> 3;
+    const uint32_t base = nblocks >> 3, extra = nblocks & 7u; // XCDs < extra get base + 1
+    return x * base + (x < extra ? x : extra) + j;
+}
+
+} // namespace rows
+} // namespace ising

@@ -4,6 +4,7 @@
 #include <stdint.h>
 
 #include "ising_device.hpp"
+#include "ising_rows.hpp"
 #include "launch.hpp"
 
 namespace ising {
@@ -80,20 +81,31 @@ __global__ __launch_bounds__(256) void k_sweep_rows(uint64_t *__restrict__ tgt,
 // LDS, which is drained 64 entries at a time so that every lane works on some
 // undecided word.  Each word still receives its blocks q = 0, 1, 2, ... in
 // order, so the result is the same as deciding each word on its own.  The
-// FIFO order finishes words soon after their row, so partly written cache
-// lines are completed before they leave L2.
+// per-word steps run on 32-bit halves with gfx950's three-input logic
+// instruction (ising_rows.hpp).
+//
+// New words are collected in a ring of kRing rows in LDS, and row r goes to
+// memory as one coalesced 512-byte store when row r + kRing needs its slot,
+// so that HBM sees whole lines instead of the scattered 8-byte stores of
+// words finished in the queue.  A word still undecided then (a few per
+// thousand) is stored on its own when it is final.
 constexpr int kBandRows = 32;
 constexpr uint32_t kStreamBlocks = 3;
 constexpr uint32_t kQueueCap = 128; // < 64 entries left after a drain + 64 pushed per row
 constexpr int kWaves = 4;
+constexpr uint32_t kRing = 4; // power of two
 
 struct WaveQueue {
-    uint64_t t[kQueueCap];       // target word before the half-sweep
-    uint64_t flips[kQueueCap];   // flips decided so far
-    uint64_t pending[kQueueCap]; // spins still undecided
-    uint64_t classA[kQueueCap];  // undecided spins of class A
-    uint32_t chunk[kQueueCap];   // word index in its colour
-    uint32_t q[kQueueCap];       // next Philox block
+    uint64_t tf[kQueueCap];    // target word with the flips decided so far
+    uint64_t p[kQueueCap];     // spins still undecided
+    uint64_t a[kQueueCap];     // class-A spins
+    uint32_t chunk[kQueueCap]; // word index in its colour
+    uint32_t meta[kQueueCap];  // next Philox block | lane << 4 | band row << 10
+};
+
+struct WaveRing {
+    uint64_t word[kRing][64]; // new words of the last kRing rows
+    uint8_t done[kRing][64];  // 1 where the word is final
 };
 
 __device__ __forceinline__ uint32_t lanes_below(uint64_t ballot)
@@ -102,55 +114,104 @@ __device__ __forceinline__ uint32_t lanes_below(uint64_t ballot)
                                      __builtin_amdgcn_mbcnt_lo((uint32_t)ballot, 0u));
 }
 
-__device__ __forceinline__ void queue_put(WaveQueue &wq, uint32_t e, uint64_t t,
-                                          const WordState &s, uint32_t chunk, uint32_t q)
+__device__ __forceinline__ void queue_put(WaveQueue &wq, uint32_t e, const rows::State &s,
+                                          uint32_t chunk, uint32_t meta)
 {
-    wq.t[e] = t;
-    wq.flips[e] = s.flips;
-    wq.pending[e] = s.pending;
-    wq.classA[e] = s.classA;
+    wq.tf[e] = rows::join(s.tf[0], s.tf[1]);
+    wq.p[e] = rows::join(s.p[0], s.p[1]);
+    wq.a[e] = rows::join(s.a[0], s.a[1]);
     wq.chunk[e] = chunk;
-    wq.q[e] = q;
+    wq.meta[e] = meta;
+}
+
+__device__ __forceinline__ bool undecided(const rows::State &s) { return (s.p[0] | s.p[1]) != 0; }
+
+// Writes ring slot `sl` to row pointer `rowp`: every word, or (`only_done`)
+// the final ones.
+__device__ __forceinline__ void ring_store(const WaveRing &rg, uint32_t sl,
+                                           uint64_t *__restrict__ rowp, uint32_t wc, bool active,
+                                           int lane, bool only_done)
+{
+    __builtin_amdgcn_wave_barrier();
+    const bool st = active && (!only_done || rg.done[sl][lane] != 0);
+    if (st)
+        __builtin_nontemporal_store(rg.word[sl][lane], &rowp[wc]);
 }
 
 // One pass over the oldest n (<= 64) queue entries: one Philox block each;
-// finished words are stored, the rest appended again at the tail.
-__device__ __forceinline__ void drain_once(WaveQueue &wq, uint32_t &head, uint32_t &len,
-                                           uint32_t n, uint64_t *__restrict__ tgt,
+// finished words go to their ring slot (or, for a row already written, to
+// memory), the rest are appended again at the tail.  A word still undecided
+// after block 15 (all 32 planes) has r == T: rejected, and final as it is.
+// Rows up to r_cur - kRing have left the ring.
+__device__ __forceinline__ void drain_once(WaveQueue &wq, WaveRing &rg, uint32_t &head, uint32_t &len, uint32_t n,
+                                           uint32_t r_cur, uint64_t *__restrict__ tgt,
                                            const SweepArgs2 &a, int lane)
 {
     const bool mine = (uint32_t)lane < n;
-    WordState s{0, 0, 0};
-    uint64_t t = 0;
-    uint32_t chunk = 0, q = 0;
+    rows::State s{};
+    uint32_t chunk = 0, meta = 0, q = 0;
     if (mine) {
         const uint32_t e = (head + (uint32_t)lane) & (kQueueCap - 1);
-        t = wq.t[e];
-        s.flips = wq.flips[e];
-        s.pending = wq.pending[e];
-        s.classA = wq.classA[e];
+        const uint64_t tf = wq.tf[e], p = wq.p[e], ca = wq.a[e];
+        s.tf[0] = rows::lo32(tf);
+        s.tf[1] = rows::hi32(tf);
+        s.p[0] = rows::lo32(p);
+        s.p[1] = rows::hi32(p);
+        s.a[0] = rows::lo32(ca);
+        s.a[1] = rows::hi32(ca);
         chunk = wq.chunk[e];
-        q = wq.q[e];
-        advance_block(s, q, chunk, a.m, a.t_lo, a.t_hi, a.stream_id, a.key0, a.key1);
-        ++q;
+        meta = wq.meta[e];
+        q = meta & 15u;
+        rows::block_lane(s, q, chunk, a);
     }
     __builtin_amdgcn_wave_barrier();
     head = (head + n) & (kQueueCap - 1);
     len -= n;
-    const bool keep = mine && s.pending != 0;
-    if (mine && !keep)
-        tgt[chunk] = t ^ s.flips;
+    const bool keep = mine && q < 15u && undecided(s);
+    const bool fin = mine && !keep;
+    const uint32_t er = meta >> 10, el = (meta >> 4) & 63u, es = er & (kRing - 1);
+    const bool owned = er + kRing > r_cur;
+    if (fin) {
+        const uint64_t v = rows::join(s.tf[0], s.tf[1]);
+        if (owned) {
+            rg.word[es][el] = v;
+            rg.done[es][el] = 1;
+        } else {
+            tgt[chunk] = v;
+        }
+    }
     const uint64_t bal = __ballot(keep);
     if (keep)
-        queue_put(wq, (head + len + lanes_below(bal)) & (kQueueCap - 1), t, s, chunk, q);
+        queue_put(wq, (head + len + lanes_below(bal)) & (kQueueCap - 1), s, chunk, meta + 1);
     __builtin_amdgcn_wave_barrier();
     len += (uint32_t)__popcll(bal);
 }
 
+// Edge word of the side vector of a wavefront that owns whole 64-word row
+// segments: lane 0 (left neighbours) and lane 63 (right neighbours) read the
+// word past the segment; every other lane takes its neighbour lane's centre
+// word by a wavefront shift (DPP wave_shr:1 / wave_shl:1), which leaves the
+// edge lane's own value in place.
+__device__ __forceinline__ uint32_t side_half_dpp(uint32_t cur_lo, uint32_t cur_hi, uint32_t edge,
+                                                  bool left)
+{
+    return left ? (uint32_t)__builtin_amdgcn_update_dpp((int)edge, (int)cur_hi, 0x138, 0xF, 0xF,
+                                                        false)
+                : (uint32_t)__builtin_amdgcn_update_dpp((int)edge, (int)cur_lo, 0x130, 0xF, 0xF,
+                                                        false);
+}
+
 // L % 128 == 0.  A wavefront owns 64 consecutive word columns of a band of
-// kBandRows colour rows and marches down it, holding the three source rows it
-// needs in registers; the side neighbour comes from the adjacent word of the
-// same source row (Sec. 3.3, Fig. 3).  Word indices fit in 32 bits.
+// kBandRows rows and marches down it, keeping the three source rows it needs
+// in registers and loading the next row's words one step ahead; the side
+// neighbour comes from the adjacent word of the same source row (Sec. 3.3,
+// Fig. 3).  `Dpp` (Wr % 64 == 0): the adjacent words are the neighbour lanes'
+// centre words, except at the segment edge.  Otherwise lanes past the row's
+// last word (Wr < 64) read the last word and store nothing, and every lane
+// loads its adjacent word.  The source row that streams in is read
+// non-temporally, so that L2 keeps the target lines, whose words are stored
+// at different times, until they are complete.  Word indices fit in 32 bits.
+template <bool Anti, bool Plain, bool Dpp>
 __global__ __launch_bounds__(256) void k_sweep_rows_q(uint64_t *__restrict__ tgt,
                                                       const uint64_t *__restrict__ src,
                                                       uint32_t L, uint32_t Wr,
@@ -158,64 +219,115 @@ __global__ __launch_bounds__(256) void k_sweep_rows_q(uint64_t *__restrict__ tgt
                                                       int c, SweepArgs2 a)
 {
     __shared__ WaveQueue queues[kWaves];
-    const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+    __shared__ WaveRing rings[kWaves];
+    const int lane = threadIdx.x & 63;
+    // wave-uniform: the row arithmetic stays on the scalar unit
+    const uint32_t wv = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
     WaveQueue &wq = queues[wv];
-    const uint32_t gwave = blockIdx.x * kWaves + wv;
+    WaveRing &rg = rings[wv];
+    const uint32_t gwave = rows::xcd_block(blockIdx.x, gridDim.x) * kWaves + wv;
     const uint32_t band = gwave / waves_per_band;
     if (band >= nbands)
         return; // whole wavefront
-    const uint32_t w = (gwave - band * waves_per_band) * 64 + lane;
+    const uint32_t w0 = (gwave - band * waves_per_band) * 64;
+    const uint32_t w = w0 + lane;
     const bool active = w < Wr;
-    const uint32_t wl = (w == 0) ? Wr - 1 : w - 1;
-    const uint32_t wr = (w + 1 >= Wr) ? 0 : w + 1;
+    const uint32_t wc = active ? w : Wr - 1;
+    const uint32_t wl = (wc == 0) ? Wr - 1 : wc - 1;
+    const uint32_t wr = (wc + 1 >= Wr) ? 0 : wc + 1;
+    // Dpp: the one word each edge lane reads
+    const bool edge_l = lane == 0, edge_r = lane == 63;
     const uint32_t i0 = band * kBandRows;
-    uint64_t prev = 0, cur = 0;
-    if (active) {
-        prev = src[((i0 == 0) ? L - 1 : i0 - 1) * Wr + w];
-        cur = src[i0 * Wr + w];
-    }
-    uint32_t head = 0, len = 0;
-    for (int r = 0; r < kBandRows; ++r) {
+    const rows::ClassMasks cm = rows::class_masks(a.m);
+    auto row = [&](uint32_t i) { return src + (size_t)i * Wr; }; // wave-uniform pointer
+    auto side_word = [&](uint32_t i, bool left) -> uint64_t { return row(i)[left ? wl : wr]; };
+    auto edge_half = [&](uint32_t i, bool left) -> uint32_t {
+        uint32_t e = 0;
+        if (left ? edge_l : edge_r) {
+            const uint64_t v = row(i)[left ? wl : wr];
+            e = left ? rows::hi32(v) : rows::lo32(v);
+        }
+        return e;
+    };
+    uint64_t prev = row((i0 == 0) ? L - 1 : i0 - 1)[wc];
+    uint64_t cur = row(i0)[wc];
+    // row i0 operands
+    bool left = ((i0 + c) & 1) == 0;
+    uint64_t next = __builtin_nontemporal_load(&row((i0 + 1 == L) ? 0 : i0 + 1)[wc]);
+    uint64_t t = tgt[(size_t)i0 * Wr + wc];
+    uint64_t adj = 0;
+    uint32_t edge = 0;
+    if (Dpp)
+        edge = edge_half(i0, left);
+    else
+        adj = side_word(i0, left);
+    auto trow = [&](uint32_t i) { return tgt + (size_t)i * Wr; }; // wave-uniform pointer
+    uint32_t head = 0, len = 0, r_last = 0;
+    for (uint32_t r = 0; r < (uint32_t)kBandRows; ++r) {
         const uint32_t i = i0 + r;
         if (i >= L)
             break;
-        const uint32_t inext = (i + 1 == L) ? 0 : i + 1;
-        const uint32_t idx = i * Wr + w;
-        const bool left = ((i + c) & 1) == 0;
-        uint64_t next = 0, t = 0;
-        WordState s{0, 0, 0};
-        if (active) {
-            next = src[inext * Wr + w];
-            t = tgt[idx];
-            const uint64_t adj = src[i * Wr + (left ? wl : wr)];
-            const Classes k = classify(t, prev, next, cur, side_vector(cur, adj, left));
-            s = start_word(k, ~0ull, a.m);
+        r_last = r;
+        const uint32_t idx = i * Wr + wc;
+        const uint32_t sl = r & (kRing - 1);
+        if (r >= kRing) // row r - kRing leaves the ring
+            ring_store(rg, sl, trow(i - kRing), wc, active, lane, true);
+        // loads of row i + 1, in flight while row i is decided
+        const bool more = r + 1 < kBandRows && i + 1 < L;
+        const uint32_t i1 = (i + 1 == L) ? 0 : i + 1;
+        const uint32_t i2 = (i1 + 1 == L) ? 0 : i1 + 1;
+        const bool left1 = !left;
+        uint64_t next1 = 0, t1 = 0, adj1 = 0;
+        uint32_t edge1 = 0;
+        if (more) {
+            next1 = __builtin_nontemporal_load(&row(i2)[wc]);
+            t1 = tgt[(size_t)i1 * Wr + wc];
+            if (Dpp)
+                edge1 = edge_half(i1, left1);
+            else
+                adj1 = side_word(i1, left1);
         }
+        const uint32_t adj_half =
+            Dpp ? side_half_dpp(rows::lo32(cur), rows::hi32(cur), edge, left)
+                : (left ? rows::hi32(adj) : rows::lo32(adj));
+        rows::State s =
+            rows::start_word_rows<Anti, Plain>(t, prev, next, cur, adj_half, left, cm);
+        // (a block applied to a decided word changes nothing; with both
+        // classes random a whole wavefront is practically never decided
+        // early, so only the other cases test for it)
 #pragma unroll
         for (uint32_t q = 0; q < kStreamBlocks; ++q) {
-            if (__ballot(s.pending != 0) == 0)
+            if (!Plain && __ballot(active && undecided(s)) == 0)
                 break;
-            if (s.pending != 0)
-                advance_block_uniform(s, q, idx, a.m, a.t_lo, a.t_hi, a.stream_id, a.key0,
-                                      a.key1);
+            rows::block_uniform(s, q, idx, a);
         }
-        const bool push = active && s.pending != 0;
-        if (active && !push)
-            tgt[idx] = t ^ s.flips;
+        const bool push = active && undecided(s);
+        rg.word[sl][lane] = rows::join(s.tf[0], s.tf[1]);
+        rg.done[sl][lane] = push ? 0 : 1;
         const uint64_t bal = __ballot(push);
         if (push)
-            queue_put(wq, (head + len + lanes_below(bal)) & (kQueueCap - 1), t, s, idx,
-                      kStreamBlocks);
+            queue_put(wq, (head + len + lanes_below(bal)) & (kQueueCap - 1), s, idx,
+                      kStreamBlocks | ((uint32_t)lane << 4) | (r << 10));
         __builtin_amdgcn_wave_barrier();
         len += (uint32_t)__popcll(bal);
         while (len >= 64)
-            drain_once(wq, head, len, 64, tgt, a, lane);
+            drain_once(wq, rg, head, len, 64, r, tgt, a, lane);
         prev = cur;
         cur = next;
+        next = next1;
+        t = t1;
+        adj = adj1;
+        edge = edge1;
+        left = left1;
     }
     while (len > 0)
-        drain_once(wq, head, len, len < 64 ? len : 64, tgt, a, lane);
+        drain_once(wq, rg, head, len, len < 64 ? len : 64, r_last, tgt, a, lane);
+    // the last rows, all words final
+    const uint32_t nrows = r_last + 1;
+    for (uint32_t r = nrows > kRing ? nrows - kRing : 0; r < nrows; ++r)
+        ring_store(rg, r & (kRing - 1), trow(i0 + r), wc, active, lane, false);
 }
+
 
 // --------------------------------------------------------------- observables
 __global__ __launch_bounds__(256) void k_fill_i64(int64_t *__restrict__ p, int64_t n, int64_t v)
@@ -355,8 +467,18 @@ hipError_t launch_half_sweep(uint64_t *words, int64_t L, int c, const Metro2 &m,
             const int64_t wpb = (Wr + 63) / 64;
             const int64_t nbands = (L + kBandRows - 1) / kBandRows;
             const int64_t waves = wpb * nbands;
-            hipLaunchKernelGGL(k_sweep_rows_q, dim3((uint32_t)((waves + kWaves - 1) / kWaves)),
-                               dim3(64 * kWaves), 0, s, tgt, src, (uint32_t)L, (uint32_t)Wr,
+            const dim3 grid((uint32_t)((waves + kWaves - 1) / kWaves)), block(64 * kWaves);
+            const bool plain = m.randA && m.randB && !m.alwaysA && !m.alwaysB;
+            const bool dpp = Wr % 64 == 0;
+            using Kernel = void (*)(uint64_t *, const uint64_t *, uint32_t, uint32_t, uint32_t,
+                                    uint32_t, int, SweepArgs2);
+            static const Kernel kernels[8] = {
+                k_sweep_rows_q<false, false, false>, k_sweep_rows_q<false, false, true>,
+                k_sweep_rows_q<false, true, false>,  k_sweep_rows_q<false, true, true>,
+                k_sweep_rows_q<true, false, false>,  k_sweep_rows_q<true, false, true>,
+                k_sweep_rows_q<true, true, false>,   k_sweep_rows_q<true, true, true>};
+            const Kernel k = kernels[(m.anti ? 4 : 0) + (plain ? 2 : 0) + (dpp ? 1 : 0)];
+            hipLaunchKernelGGL(k, grid, block, 0, s, tgt, src, (uint32_t)L, (uint32_t)Wr,
                                (uint32_t)wpb, (uint32_t)nbands, c, a);
         }
     } else {

@@ -5,6 +5,7 @@
 #include <vector>
 
 #include "../paper_1906_06297_amd/csrc/ising_device.hpp"
+#include "../paper_1906_06297_amd/csrc/ising_rows.hpp"
 
 using namespace ising;
 
@@ -23,7 +24,55 @@ static Metro2 metro2_from_table(const uint64_t *T, int anti)
     return m;
 }
 
+namespace {
+
+// The queued row kernel's sequence for one word: the start state from the
+// 32-bit-half class split, three blocks with the lane-shared compare, then
+// blocks with the per-lane compare until the word is decided.
+template <bool Anti, bool Plain>
+static uint64_t queued_word(uint64_t t, uint64_t up, uint64_t dn, uint64_t ce, uint64_t adj,
+                            bool left, uint32_t chunk, const SweepArgs2 &a)
+{
+    const rows::ClassMasks cm = rows::class_masks(a.m);
+    rows::State s = rows::start_word_rows<Anti, Plain>(
+        t, up, dn, ce, left ? rows::hi32(adj) : rows::lo32(adj), left, cm);
+    uint32_t q = 0;
+    for (; q < 3; ++q)
+        rows::block_uniform(s, q, chunk, a);
+    for (; q < 16 && (s.p[0] | s.p[1]) != 0; ++q)
+        rows::block_lane(s, q, chunk, a);
+    return rows::join(s.tf[0], s.tf[1]);
+}
+
+static uint64_t queued_word_any(uint64_t t, uint64_t up, uint64_t dn, uint64_t ce, uint64_t adj,
+                                bool left, uint32_t chunk, const SweepArgs2 &a)
+{
+    const bool plain = a.m.randA && a.m.randB && !a.m.alwaysA && !a.m.alwaysB;
+    if (a.m.anti)
+        return plain ? queued_word<true, true>(t, up, dn, ce, adj, left, chunk, a)
+                     : queued_word<true, false>(t, up, dn, ce, adj, left, chunk, a);
+    return plain ? queued_word<false, true>(t, up, dn, ce, adj, left, chunk, a)
+                 : queued_word<false, false>(t, up, dn, ce, adj, left, chunk, a);
+}
+
+} // namespace
+
 extern "C" {
+
+// Logical block of hardware block b of a grid of n blocks.
+uint32_t emu_xcd_block(uint32_t b, uint32_t n) { return rows::xcd_block(b, n); }
+
+// Philox block with the fused-XOR rounds (lane-shared or per-lane counter form).
+void emu_philox_fast(uint32_t c0, uint32_t c1, uint32_t c2, uint32_t c3, uint32_t k0, uint32_t k1,
+                     int uniform012, uint32_t *out)
+{
+    const Block x = uniform012 ? rows::philox_fast<true>(c0, c1, c2, c3, k0, k1)
+                               : rows::philox_fast<false>(c0, c1, c2, c3, k0, k1);
+    out[0] = x.x0;
+    out[1] = x.x1;
+    out[2] = x.x2;
+    out[3] = x.x3;
+}
 
 void emu_init(uint64_t *words, int64_t L, uint64_t seed, uint32_t stream)
 {
@@ -31,19 +80,6 @@ void emu_init(uint64_t *words, int64_t L, uint64_t seed, uint32_t stream)
     for (int64_t idx = 0; idx < 2 * W; ++idx)
         words[idx] = init_word(idx % W, (uint32_t)(idx / W), M, stream, (uint32_t)seed,
                                (uint32_t)(seed >> 32));
-}
-
-// The queued row kernel's sequence for one word: the first three blocks with
-// the uniform-threshold compare, the rest with the per-lane compare.
-static uint64_t decide_queued(const Classes &k, uint32_t chunk, const SweepArgs2 &a)
-{
-    WordState s = start_word(k, ~0ull, a.m);
-    uint32_t q = 0;
-    for (; q < 3 && s.pending != 0; ++q)
-        advance_block_uniform(s, q, chunk, a.m, a.t_lo, a.t_hi, a.stream_id, a.key0, a.key1);
-    for (; q < 16 && s.pending != 0; ++q)
-        advance_block(s, q, chunk, a.m, a.t_lo, a.t_hi, a.stream_id, a.key0, a.key1);
-    return s.flips;
 }
 
 // rows = 1: the row-aligned kernel's formulas (needs L % 128 == 0);
@@ -68,10 +104,9 @@ void emu_half_sweep(uint64_t *words, int64_t L, int c, const uint64_t *T, int an
             const int64_t adjw = left ? (w == 0 ? Wr - 1 : w - 1) : (w == Wr - 1 ? 0 : w + 1);
             const int64_t idx = i * Wr + w;
             if (rows == 2) {
-                const Classes k = classify(tgt[idx], src[((i + L - 1) % L) * Wr + w],
+                tgt[idx] = queued_word_any(tgt[idx], src[((i + L - 1) % L) * Wr + w],
                                            src[((i + 1) % L) * Wr + w], src[idx],
-                                           side_vector(src[idx], src[i * Wr + adjw], left));
-                tgt[idx] ^= decide_queued(k, (uint32_t)idx, a);
+                                           src[i * Wr + adjw], left, (uint32_t)idx, a);
             } else {
                 tgt[idx] = update_word_rows(tgt[idx], src[((i + L - 1) % L) * Wr + w],
                                             src[((i + 1) % L) * Wr + w], src[idx],

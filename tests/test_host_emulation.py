@@ -29,6 +29,10 @@ def emu(tmp_path_factory):
     lib.emu_init.argtypes = [u64p, ctypes.c_int64, ctypes.c_uint64, ctypes.c_uint32]
     lib.emu_half_sweep.argtypes = [u64p, ctypes.c_int64, ctypes.c_int, u64p, ctypes.c_int,
                                    ctypes.c_uint64, ctypes.c_uint64, ctypes.c_uint32, ctypes.c_int]
+    lib.emu_xcd_block.argtypes = [ctypes.c_uint32, ctypes.c_uint32]
+    lib.emu_xcd_block.restype = ctypes.c_uint32
+    lib.emu_philox_fast.argtypes = [ctypes.c_uint32] * 6 + [ctypes.c_int,
+                                                           ctypes.POINTER(ctypes.c_uint32)]
     lib.emu_batch_lattice.argtypes = [u64p, ctypes.c_int64, ctypes.c_double, ctypes.c_double,
                                       ctypes.c_uint64, ctypes.c_uint32, ctypes.c_int64,
                                       ctypes.c_uint64, u64p]
@@ -65,7 +69,8 @@ def test_general_kernel_logic(emu, orc, L, beta, J):
 @pytest.mark.parametrize("rows", [1, 2])
 @pytest.mark.parametrize("L", [128, 256, 512])
 @pytest.mark.parametrize("beta,J", [(0.0, 1.0), (0.40, 1.0), (workloads.BETA_CRIT_CONFIG, 1.0),
-                                    (0.5, 1.0), (0.3, -1.0), (7.0, 1.0)])
+                                    (0.5, 1.0), (0.3, -1.0), (7.0, 1.0), (7.0, -1.0),
+                                    (0.0, -1.0)])
 def test_row_kernel_logic(emu, orc, rows, L, beta, J):
     seed, stream, n, ctr = 7, 0, 3, 0
     ref = orc.init(L, seed, stream)
@@ -85,3 +90,39 @@ def test_batch_kernel_logic(emu, orc, L, beta, J):
     emu.emu_batch_lattice(_p(words), L, beta, J, seed, stream, n, ctr, _p(T))
     orc.sweeps(ref, beta, J, seed, stream, n, ctr)
     assert np.array_equal(words.reshape(2, -1), pack(ref))
+
+
+def _kat_rows():
+    path = os.path.join(HERE, "golden", "philox4x32_10_kat.txt")
+    rows = []
+    for line in open(path):
+        if line.strip() and not line.startswith("#"):
+            v = [int(x, 16) for x in line.split()]
+            rows.append((v[:4], v[4:6], v[6:10]))
+    return rows
+
+
+@pytest.mark.parametrize("uniform012", [0, 1])
+def test_fused_xor_philox(emu, orc, uniform012):
+    """The Philox rounds written with three-input XORs give the published
+    known answers and the oracle's blocks on random counters and keys."""
+    out = (ctypes.c_uint32 * 4)()
+    for ctr, key, want in _kat_rows():
+        emu.emu_philox_fast(*ctr, *key, uniform012, out)
+        assert list(out) == want
+    rng = np.random.default_rng(11)
+    for _ in range(2000):
+        ctr = [int(x) for x in rng.integers(0, 2 ** 32, 4, dtype=np.uint64)]
+        key = [int(x) for x in rng.integers(0, 2 ** 32, 2, dtype=np.uint64)]
+        emu.emu_philox_fast(*ctr, *key, uniform012, out)
+        assert tuple(out) == tuple(orc.philox4x32_10(ctr, key))
+
+
+@pytest.mark.parametrize("n", [1, 7, 8, 9, 15, 16, 17, 255, 256, 4095, 4096, 65536, 65541])
+def test_xcd_block_order_is_a_permutation(emu, n):
+    got = np.array([emu.emu_xcd_block(b, n) for b in range(n)])
+    assert np.array_equal(np.sort(got), np.arange(n))
+    # each XCD (b % 8) receives one contiguous range of logical blocks
+    for x in range(min(n, 8)):
+        mine = np.sort(got[x::8])
+        assert np.all(np.diff(mine) == 1)
