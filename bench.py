@@ -31,7 +31,8 @@ import workloads  # noqa: E402
 
 HBM_PEAK_GBS = 8000.0  # MI355X HBM3E, GB/s
 KERNEL_SOURCES = ("paper_1906_06297_amd/csrc/sweep_kernels.hip",
-                  "paper_1906_06297_amd/csrc/ising_device.hpp")
+                  "paper_1906_06297_amd/csrc/ising_device.hpp",
+                  "paper_1906_06297_amd/csrc/ising_rows.hpp")
 COUNTERS_SUMMARY = "profiles/half_sweep_L65536_counters.md"
 
 
