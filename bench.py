@@ -89,7 +89,7 @@ def cpu_baseline(target_s: float = 15.0) -> dict:
     t0 = time.perf_counter()
     oracle.sweeps(s, beta, 1.0, seed, 0, 1, 0)
     one = time.perf_counter() - t0
-    extra = max(0, min(40, int(target_s / max(one, 1e-3)) - 1))
+    extra = max(0, min(1000, int(target_s / max(one, 1e-3)) - 1))
     t0 = time.perf_counter()
     if extra:
         oracle.sweeps(s, beta, 1.0, seed, 0, extra, 1)
