@@ -182,7 +182,7 @@ int check_batch(const ising_batch *b)
 }
 
 // ---------------------------------------------------------------- cache file
-std::string cache_key() { return "gfx950/batch-sweep-v2"; }
+std::string cache_key() { return "gfx950/batch-sweep-v3"; }
 
 bool read_cache(const char *path, std::map<int64_t, Tile> &out)
 {

@@ -4,6 +4,7 @@
 #include <stdint.h>
 
 #include "batch.hpp"
+#include "ising_rows.hpp"
 
 namespace ising {
 
@@ -39,19 +40,20 @@ __device__ __forceinline__ Block shuffle_xor1(const Block &x)
 // other Philox block (lane parity p takes q = 2j + p), the pair swaps them and
 // both apply the planes in block order, so the pair reaches the sequential
 // result in half the dependent steps.  Both lanes hold the same state.
-__device__ __forceinline__ uint64_t decide_word_pair(const Classes &k, uint64_t valid,
-                                                     uint32_t chunk, const SweepArgs2 &a,
-                                                     uint32_t parity)
+__device__ __forceinline__ uint64_t decide_word_pair(uint64_t t, const Neighbours &nb,
+                                                     uint64_t valid, uint32_t chunk,
+                                                     const SweepArgs2 &a, uint32_t parity)
 {
-    WordState s = start_word(k, valid, a.m);
-    for (uint32_t q0 = 0; q0 < 16 && s.pending != 0; q0 += 2) {
-        const Block mine = philox4x32_10(ctr_word0(a.stream_id, kDomainSweep, q0 + parity),
-                                         a.t_lo, a.t_hi, chunk, a.key0, a.key1);
+    rows::State s = rows::start_word_any(t, nb, valid, a.m);
+    for (uint32_t q0 = 0; q0 < 16 && (s.p[0] | s.p[1]) != 0; q0 += 2) {
+        const Block mine =
+            rows::philox_fast<rows::kCtrKeyLane>(ctr_word0(a.stream_id, kDomainSweep, q0 + parity),
+                                                 a.t_lo, a.t_hi, chunk, a.key0, a.key1);
         const Block other = shuffle_xor1(mine);
-        apply_block(s, parity ? other : mine, q0, a.m);
-        apply_block(s, parity ? mine : other, q0 + 1, a.m);
+        rows::apply_block_lane(s, parity ? other : mine, q0, a.m);
+        rows::apply_block_lane(s, parity ? mine : other, q0 + 1, a.m);
     }
-    return s.flips;
+    return t ^ rows::join(s.tf[0], s.tf[1]);
 }
 
 // Persistent sweep kernel.  Workgroups take bundles from an atomic counter
@@ -112,11 +114,10 @@ __global__ __launch_bounds__(kBatchThreads) void k_batch_sweep(
                             rm.left_rows = ~rm.left_rows; // rows of the other parity
                         const Neighbours nb = neighbours_ext_rm(src, lt.H, lt.M, k, rm);
                         const uint64_t tw = tgt[k];
-                        const Classes cl = classify(tw, nb.up, nb.dn, nb.ce, nb.sd);
                         const uint64_t valid = valid_mask(k, lt.M);
                         const uint64_t flips = (bd.lpw == 2)
-                                                   ? decide_word_pair(cl, valid, k, a, parity)
-                                                   : decide_word(cl, valid, k, a);
+                                                   ? decide_word_pair(tw, nb, valid, k, a, parity)
+                                                   : rows::decide_word_any(tw, nb, valid, k, a);
                         if (parity == 0)
                             tgt[k] = tw ^ flips;
                     }

@@ -47,12 +47,19 @@ __host__ __device__ __forceinline__ uint32_t xor3(uint32_t a, uint32_t b, uint32
 // ------------------------------------------------------------------ Philox
 // Philox4x32-10 as in ising_device.hpp, with each round's "high product ^
 // counter word ^ key" terms as single three-input XORs.  Which terms vary per
-// lane is fixed by the counter: words 1 and 2 (the half-sweep index) are the
-// same in every lane, word 3 (the word index) is not, and word 0 (stream,
-// domain, block) is too when the block index differs per lane
-// (`Uniform012` false).  The early rounds still have wave-uniform terms,
-// which the scalar unit computes.
-template <bool Uniform012>
+// lane is fixed by the counter and the key: counter words 1 and 2 (the
+// half-sweep index) are the same in every lane, word 3 (the word index) is
+// not; word 0 (stream, domain, block) and the key vary per lane or not
+// according to the mode.  The early rounds still have wave-uniform terms,
+// which the scalar unit computes; a XOR with at most one lane-varying input
+// is one vector XOR once the scalar unit has combined the other two.
+enum PhiloxMode {
+    kCtrUniform = 0, // word 0 and key wave-uniform (lock-step blocks of a row)
+    kCtrLane = 1,    // word 0 per lane (block index per lane), key uniform
+    kCtrKeyLane = 2, // word 0 and key per lane (lattices of a batch)
+};
+
+template <int Mode>
 __host__ __device__ __forceinline__ Block philox_fast(uint32_t c0, uint32_t c1, uint32_t c2,
                                                       uint32_t c3, uint32_t k0, uint32_t k1)
 {
@@ -64,11 +71,8 @@ __host__ __device__ __forceinline__ Block philox_fast(uint32_t c0, uint32_t c1, 
         }
         const uint64_t pa = (uint64_t)0xD2511F53u * c0;
         const uint64_t pb = (uint64_t)0xCD9E8D57u * c2;
-        // A XOR with at most one lane-varying input is one vector XOR after
-        // the scalar unit has combined the other two; the fused XOR is used
-        // once both of the first two inputs vary per lane.
-        const bool plain0 = Uniform012 ? round <= 3 : round <= 1;
-        const bool plain2 = Uniform012 ? round <= 2 : (round == 1 || round == 2);
+        const bool plain0 = Mode == kCtrUniform ? round <= 3 : (Mode == kCtrLane ? round <= 1 : round == 0);
+        const bool plain2 = Mode == kCtrUniform ? round <= 2 : (Mode == kCtrLane ? (round == 1 || round == 2) : false);
         const uint32_t n0 = plain0 ? ((uint32_t)(pb >> 32) ^ c1 ^ k0)
                                    : xor3((uint32_t)(pb >> 32), c1, k0);
         const uint32_t n2 = plain2 ? ((uint32_t)(pa >> 32) ^ c3 ^ k1)
@@ -205,13 +209,27 @@ __host__ __device__ __forceinline__ uint32_t thr_mask(uint32_t thr, uint32_t bit
 __host__ __device__ __forceinline__ void block_uniform(State &s, uint32_t q, uint32_t chunk,
                                                        const SweepArgs2 &a)
 {
-    const Block x = philox_fast<true>(ctr_word0(a.stream_id, kDomainSweep, q), a.t_lo, a.t_hi,
-                                      chunk, a.key0, a.key1);
+    const Block x = philox_fast<kCtrUniform>(ctr_word0(a.stream_id, kDomainSweep, q), a.t_lo,
+                                             a.t_hi, chunk, a.key0, a.key1);
     const uint32_t b0 = 31 - 2 * q, b1 = 30 - 2 * q;
     const bool a0 = (a.m.thrA >> b0) & 1u, B0 = (a.m.thrB >> b0) & 1u;
     const bool a1 = (a.m.thrA >> b1) & 1u, B1 = (a.m.thrB >> b1) & 1u;
     plane_uniform(s, x.x0, x.x1, a0, B0);
     plane_uniform(s, x.x2, x.x3, a1, B1);
+}
+
+// Philox block x applied as block q (planes 2q, 2q+1) with per-lane
+// threshold masks.
+__host__ __device__ __forceinline__ void apply_block_lane(State &s, const Block &x, uint32_t q,
+                                                          const Metro2 &m)
+{
+    const uint32_t b0 = 31 - 2 * q, b1 = 30 - 2 * q;
+    const uint32_t mA0 = thr_mask(m.thrA, b0), mB0 = thr_mask(m.thrB, b0);
+    const uint32_t mA1 = thr_mask(m.thrA, b1), mB1 = thr_mask(m.thrB, b1);
+    plane_lane(s, 0, x.x0, mA0, mB0);
+    plane_lane(s, 1, x.x1, mA0, mB0);
+    plane_lane(s, 0, x.x2, mA1, mB1);
+    plane_lane(s, 1, x.x3, mA1, mB1);
 }
 
 // Block q with per-lane q.  After block 15 (all 32 planes) a spin still
@@ -220,15 +238,10 @@ __host__ __device__ __forceinline__ void block_uniform(State &s, uint32_t q, uin
 __host__ __device__ __forceinline__ void block_lane(State &s, uint32_t q, uint32_t chunk,
                                                     const SweepArgs2 &a)
 {
-    const Block x = philox_fast<false>(ctr_word0(a.stream_id, kDomainSweep, q), a.t_lo, a.t_hi,
-                                       chunk, a.key0, a.key1);
-    const uint32_t b0 = 31 - 2 * q, b1 = 30 - 2 * q;
-    const uint32_t mA0 = thr_mask(a.m.thrA, b0), mB0 = thr_mask(a.m.thrB, b0);
-    const uint32_t mA1 = thr_mask(a.m.thrA, b1), mB1 = thr_mask(a.m.thrB, b1);
-    plane_lane(s, 0, x.x0, mA0, mB0);
-    plane_lane(s, 1, x.x1, mA0, mB0);
-    plane_lane(s, 0, x.x2, mA1, mB1);
-    plane_lane(s, 1, x.x3, mA1, mB1);
+    apply_block_lane(s,
+                     philox_fast<kCtrLane>(ctr_word0(a.stream_id, kDomainSweep, q), a.t_lo, a.t_hi,
+                                           chunk, a.key0, a.key1),
+                     q, a.m);
 }
 
 // ----------------------------------------------------------- word helpers
@@ -269,6 +282,46 @@ __host__ __device__ __forceinline__ State start_word_rows(uint64_t t, uint64_t u
     start_half<Plain>(s, 1, hi32(t),
                       split_classes<Anti>(hi32(t), hi32(up), hi32(dn), ch, sh), cm);
     return s;
+}
+
+// Start state of a word of any geometry from its four neighbour vectors, with
+// the lattice's coupling sign and classes taken per lane; spins past the end
+// of the colour (`valid` clear) neither flip nor draw.
+__host__ __device__ __forceinline__ State start_word_any(uint64_t t, const Neighbours &nb,
+                                                         uint64_t valid, const Metro2 &m)
+{
+    // J < 0: the unfavourable neighbours are the aligned ones, i.e. those
+    // differing from the complemented spin
+    const uint32_t f = m.anti ? ~0u : 0u;
+    const ClassMasks cm = class_masks(m);
+    State s;
+#pragma unroll
+    for (int h = 0; h < 2; ++h) {
+        const uint32_t th = h ? hi32(t) : lo32(t), vh = h ? hi32(valid) : lo32(valid);
+        const Split k = split_classes<false>(th ^ f, h ? hi32(nb.up) : lo32(nb.up),
+                                             h ? hi32(nb.dn) : lo32(nb.dn),
+                                             h ? hi32(nb.ce) : lo32(nb.ce),
+                                             h ? hi32(nb.sd) : lo32(nb.sd));
+        start_half<false>(s, h, th, k, cm);
+        s.tf[h] = lop3<tt(kA ^ ((kA ^ kB) & kC))>(th, s.tf[h], vh); // flips on valid spins only
+        s.p[h] &= vh;
+    }
+    return s;
+}
+
+// Flip mask of a word of any geometry, each block computed here (per-lane
+// lattice parameters).
+__host__ __device__ __forceinline__ uint64_t decide_word_any(uint64_t t, const Neighbours &nb,
+                                                             uint64_t valid, uint32_t chunk,
+                                                             const SweepArgs2 &a)
+{
+    State s = start_word_any(t, nb, valid, a.m);
+    for (uint32_t q = 0; q < 16 && (s.p[0] | s.p[1]) != 0; ++q)
+        apply_block_lane(s,
+                         philox_fast<kCtrKeyLane>(ctr_word0(a.stream_id, kDomainSweep, q), a.t_lo,
+                                                  a.t_hi, chunk, a.key0, a.key1),
+                         q, a.m);
+    return t ^ join(s.tf[0], s.tf[1]);
 }
 
 // --------------------------------------------------- XCD-aware block order

@@ -62,12 +62,13 @@ extern "C" {
 // Logical block of hardware block b of a grid of n blocks.
 uint32_t emu_xcd_block(uint32_t b, uint32_t n) { return rows::xcd_block(b, n); }
 
-// Philox block with the fused-XOR rounds (lane-shared or per-lane counter form).
+// Philox block with the fused-XOR rounds, in each counter/key mode.
 void emu_philox_fast(uint32_t c0, uint32_t c1, uint32_t c2, uint32_t c3, uint32_t k0, uint32_t k1,
-                     int uniform012, uint32_t *out)
+                     int mode, uint32_t *out)
 {
-    const Block x = uniform012 ? rows::philox_fast<true>(c0, c1, c2, c3, k0, k1)
-                               : rows::philox_fast<false>(c0, c1, c2, c3, k0, k1);
+    const Block x = mode == 0   ? rows::philox_fast<rows::kCtrUniform>(c0, c1, c2, c3, k0, k1)
+                    : mode == 1 ? rows::philox_fast<rows::kCtrLane>(c0, c1, c2, c3, k0, k1)
+                                : rows::philox_fast<rows::kCtrKeyLane>(c0, c1, c2, c3, k0, k1);
     out[0] = x.x0;
     out[1] = x.x1;
     out[2] = x.x2;
@@ -146,8 +147,7 @@ void emu_batch_lattice(uint64_t *words, int64_t L, double beta, double J, uint64
                                (uint32_t)(seed >> 32)};
             for (uint32_t k = 0; k < W; ++k) {
                 const Neighbours nb = neighbours_ext(src.data(), H, M, k, c);
-                const Classes cl = classify(tgt[k], nb.up, nb.dn, nb.ce, nb.sd);
-                tgt[k] ^= decide_word(cl, valid_mask(k, M), k, a);
+                tgt[k] ^= rows::decide_word_any(tgt[k], nb, valid_mask(k, M), k, a);
             }
             refresh(tgt);
         }
