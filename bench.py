@@ -155,52 +155,60 @@ def bench_batched(ising, torch, nsweeps: int) -> dict:
     }
 
 
-def bench_learned(ising, torch, L: int = 32, beta: float = 0.44, C: int = 32, chains: int = 256,
-                  rounds: int = 400, train_steps: int = 1500) -> dict:
-    """Learned global proposal against the plain sweep on the same GPU: per round
-    one local sweep, plus one proposal in the hybrid chains; tau_int of |m| and E
+def bench_learned(ising, torch, L: int = 32, betas=(0.42, 0.44, 0.46), C: int = 32,
+                  chains: int = 4096, rounds: int = 400, train_steps: int = 1500,
+                  data_log2: int = 20) -> dict:
+    """Learned global proposal against the plain sweep on the same GPU, per beta:
+    a network trained on 2^data_log2 plain-sampler configurations at that beta,
+    then `chains` chains per kind; per round one local sweep, plus one proposal
+    in the hybrid chains (a batch of `chains` proposals).  tau_int of |m| and E
     per round, effective samples per second, and the observables of both."""
     from paper_1906_06297_amd import hybrid, stats
 
-    t0 = time.perf_counter()
-    data = hybrid.plain_configurations(L, beta, chains=1024, snapshots=64, thin=20, burn=1000,
-                                       seed=41)
-    t_data = time.perf_counter() - t0
-    net = ising.ARNet(L, C, max(256, chains))
-    net.set_params(hybrid.init_params(L, C, seed=1))
-    t0 = time.perf_counter()
-    hist = hybrid.train(net, data, steps=train_steps, batch=256, lr=2e-3, seed=2,
-                        log_every=max(1, train_steps // 5))
-    torch.cuda.synchronize()
-    t_train = time.perf_counter() - t0
-    res = {}
-    for name, use in (("plain", None), ("hybrid", net)):
-        ch = hybrid.Chains(L, [beta] * chains, seed=43, stream_base=0)
-        hybrid.run_series(ch, 200, 1, use, seed=47, round0=1)  # burn-in
-        E, A, wall = hybrid.run_series(ch, rounds, 1, use, seed=47, round0=10_000)
-        acc = ch.accepted / ch.proposed if ch.proposed else None
-        ch.close()
-        tau_m, tau_e = stats.tau_int_chains(A), stats.tau_int_chains(E)
-        pe, pm = E.mean(axis=0), A.mean(axis=0)
-        res[name] = {
-            "acceptance": acc,
-            "tau_int_abs_m_rounds": tau_m,
-            "tau_int_E_rounds": tau_e,
-            "ms_per_round": wall / rounds * 1e3,
-            "ess_per_s_abs_m": chains * rounds / (2 * tau_m) / wall,
-            "ess_per_s_E": chains * rounds / (2 * tau_e) / wall,
-            "E_per_site": float(pe.mean()), "E_se": float(pe.std(ddof=1) / np.sqrt(chains)),
-            "abs_m": float(pm.mean()), "abs_m_se": float(pm.std(ddof=1) / np.sqrt(chains)),
-        }
-    net.close()
+    snapshots = (1 << data_log2) // chains
+    out = {}
+    for bi, beta in enumerate(betas):
+        t0 = time.perf_counter()
+        data = hybrid.plain_configurations(L, beta, chains=chains, snapshots=snapshots, thin=10,
+                                           burn=1000, seed=41 + bi, stream_base=1 << 20)
+        torch.cuda.synchronize()
+        t_data = time.perf_counter() - t0
+        net = ising.ARNet(L, C, chains)
+        net.set_params(hybrid.init_params(L, C, seed=1))
+        t0 = time.perf_counter()
+        hist = hybrid.train(net, data, steps=train_steps, batch=256, lr=2e-3, seed=2 + bi,
+                            log_every=max(1, train_steps // 5))
+        torch.cuda.synchronize()
+        t_train = time.perf_counter() - t0
+        del data
+        res = {}
+        for name, use in (("plain", None), ("hybrid", net)):
+            ch = hybrid.Chains(L, [beta] * chains, seed=43 + bi, stream_base=0)
+            ch.local(1000)  # burn-in by plain sweeps, the same for both kinds
+            E, A, wall = hybrid.run_series(ch, rounds, 1, use, seed=47 + bi, round0=10_000)
+            acc = ch.accepted / ch.proposed if ch.proposed else None
+            ch.close()
+            tau_m, tau_e = stats.tau_int_chains(A), stats.tau_int_chains(E)
+            pe, pm = E.mean(axis=0), A.mean(axis=0)
+            res[name] = {
+                "acceptance": acc,
+                "tau_int_abs_m_rounds": tau_m,
+                "tau_int_E_rounds": tau_e,
+                "ms_per_round": wall / rounds * 1e3,
+                "ess_per_s_abs_m": chains * rounds / (2 * tau_m) / wall,
+                "ess_per_s_E": chains * rounds / (2 * tau_e) / wall,
+                "E_per_site": float(pe.mean()), "E_se": float(pe.std(ddof=1) / np.sqrt(chains)),
+                "abs_m": float(pm.mean()), "abs_m_se": float(pm.std(ddof=1) / np.sqrt(chains)),
+            }
+        net.close()
+        out[str(beta)] = {"train_nll_per_site": hist, "data_s": t_data, "train_s": t_train, **res}
     return {
-        "workload": f"L={L}, beta={beta}, {C}-channel masked-conv autoregressive proposal trained on "
-                    f"{data.shape[0]} plain-sampler configurations ({train_steps} Adam steps, batch 256); "
-                    f"{chains} chains x {rounds} rounds, a round = 1 sweep (+ 1 proposal in hybrid)",
-        "train_nll_per_site": hist,
-        "data_s": t_data,
-        "train_s": t_train,
-        **res,
+        "workload": f"L={L}, beta in {list(betas)}: per beta a {C}-channel masked-conv "
+                    f"autoregressive proposal (6 layers, bf16 weights, fp32 sums) trained on 2^{data_log2} "
+                    f"plain-sampler configurations ({train_steps} Adam steps, batch 256, flip/translation "
+                    f"augmentation); {chains} chains x {rounds} rounds after 1000 plain burn-in sweeps, "
+                    f"a round = 1 sweep (+ 1 proposal per chain in hybrid, MH accept in fp32)",
+        "per_beta": out,
     }
 
 
