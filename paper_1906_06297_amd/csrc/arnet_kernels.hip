@@ -54,34 +54,56 @@ __global__ __launch_bounds__(256) void k_pack(NetDev net)
 }
 
 // ------------------------------------------------- per-row shared functions
-// Layer 1 (mask A, one input channel): output channel c at site (i, j).
-__device__ __forceinline__ float l1_value(const int8_t *x, int L, int i, int j, const float *w1,
-                                          const float *b1, int C, int c)
+// Layer 1 (mask A, one input channel): output channel c from the spins at the
+// four mask-A taps (0 outside the lattice).
+__device__ __forceinline__ float l1_from(const float (&xv)[4], const float *w1, const float *b1,
+                                         int C, int c)
 {
     float acc = 0.f;
 #pragma unroll
-    for (int t = 0; t < 4; ++t) {
-        const int ii = i + tap_dy(t), jj = j + tap_dx(t);
-        const float xv = (ii >= 0 && jj >= 0 && jj < L) ? (float)x[ii * L + jj] : 0.f;
-        acc = fmaf(xv, w1[t * C + c], acc);
-    }
+    for (int t = 0; t < 4; ++t)
+        acc = fmaf(xv[t], w1[t * C + c], acc);
     return round_bf16(fmaxf(acc + b1[c], 0.f));
 }
 
-// Layer 6 (mask B, C -> 1): the logit of site (i, j) of configuration b.
-__device__ __forceinline__ float l6_logit(const bf16 *h5, int N, int L, int C, int64_t b, int i,
-                                          int j, const float *w6, float b6)
+// Layer 1 at site (i, j) of a configuration x.
+__device__ __forceinline__ float l1_value(const int8_t *x, int L, int i, int j, const float *w1,
+                                          const float *b1, int C, int c)
+{
+    float xv[4];
+#pragma unroll
+    for (int t = 0; t < 4; ++t) {
+        const int ii = i + tap_dy(t), jj = j + tap_dx(t);
+        xv[t] = (ii >= 0 && jj >= 0 && jj < L) ? (float)x[ii * L + jj] : 0.f;
+    }
+    return l1_from(xv, w1, b1, C, c);
+}
+
+// Layer 6 (mask B, C -> 1) from the five tap rows of h5 (nullptr: outside the
+// lattice), summed tap by tap, channel by channel.
+__device__ __forceinline__ float l6_from_rows(const bf16 *const (&row)[5], int C, const float *w6,
+                                              float b6)
 {
     float acc = 0.f;
     for (int t = 0; t < 5; ++t) {
-        const int ii = i + tap_dy(t), jj = j + tap_dx(t);
-        if (ii < 0 || jj < 0 || jj >= L)
+        if (row[t] == nullptr)
             continue;
-        const bf16 *row = h5 + ((int64_t)b * N + ii * L + jj) * C;
         for (int ci = 0; ci < C; ++ci)
-            acc = fmaf((float)row[ci], w6[t * C + ci], acc);
+            acc = fmaf((float)row[t][ci], w6[t * C + ci], acc);
     }
     return acc + b6;
+}
+
+// Layer 6: the logit of site (i, j) of configuration b.
+__device__ __forceinline__ float l6_logit(const bf16 *h5, int N, int L, int C, int64_t b, int i,
+                                          int j, const float *w6, float b6)
+{
+    const bf16 *row[5];
+    for (int t = 0; t < 5; ++t) {
+        const int ii = i + tap_dy(t), jj = j + tap_dx(t);
+        row[t] = (ii < 0 || jj < 0 || jj >= L) ? nullptr : h5 + ((int64_t)b * N + ii * L + jj) * C;
+    }
+    return l6_from_rows(row, C, w6, b6);
 }
 
 __device__ __forceinline__ float prob_plus(float z) { return 1.f / (1.f + expf(-z)); }
@@ -122,64 +144,116 @@ struct RowsOfConfigs { // 16 configurations at one site
     }
 };
 
-// out[rows, 0..C) of a masked 3x3 convolution with all five mask-B taps:
-//   acc(row, n) = sum_t sum_k in[row shifted by sign * tap t][k] * wk[n][t*C + k]
-// accumulated as MFMA over t = 0..4 and 32-wide k chunks, in that order.
-template <int C, class Rows, class Epi>
-__device__ __forceinline__ void conv_tile(const bf16 *__restrict__ in, const bf16 *__restrict__ wk,
-                                          int L, int N, int sign, const Rows &rows, const Epi &epi)
+// The MFMA part of a masked 3x3 convolution tile: with the A operands of the
+// five taps in registers (a[t][kc]: row lane & 15, k = kc*32 + (lane >> 4)*8
+// + e), acc(row, n) = sum_t sum_k a[t][k] * wk[n][t*C + k], accumulated over
+// t = 0..4 and 32-wide k chunks in that order, then handed to the epilogue.
+// `bop(n0, t, kc)` yields the B operand (weights) of that step.
+template <int C, class BOp, class Rows, class Epi>
+__device__ __forceinline__ void conv_mfma_b(const bf16x8 (&a)[5][C / 32], const BOp &bop,
+                                            const Rows &rows, const Epi &epi)
 {
     constexpr int KC = C / 32;
     const int lane = threadIdx.x & 63, r = lane & 15, kq = lane >> 4;
-    int64_t b;
-    int p;
-    rows(r, b, p);
-    const int i = p / L, j = p - (p / L) * L;
-    bf16x8 a[5][KC];
-#pragma unroll
-    for (int t = 0; t < 5; ++t) {
-        const int ii = i + sign * tap_dy(t), jj = j + sign * tap_dx(t);
-        const bool ok = b >= 0 && ii >= 0 && ii < L && jj >= 0 && jj < L;
-#pragma unroll
-        for (int kc = 0; kc < KC; ++kc) {
-            if (ok) {
-                a[t][kc] = *(const bf16x8 *)(in + ((int64_t)b * N + ii * L + jj) * C + kc * 32 + kq * 8);
-            } else {
-#pragma unroll
-                for (int e = 0; e < 8; ++e)
-                    a[t][kc][e] = (bf16)0.f;
-            }
-        }
-    }
 #pragma unroll
     for (int n0 = 0; n0 < C; n0 += 16) {
         floatx4 acc = {0.f, 0.f, 0.f, 0.f};
-        const bf16 *wrow = wk + (int64_t)(n0 + r) * 5 * C + kq * 8;
 #pragma unroll
         for (int t = 0; t < 5; ++t)
 #pragma unroll
-            for (int kc = 0; kc < KC; ++kc) {
-                const bf16x8 bv = *(const bf16x8 *)(wrow + t * C + kc * 32);
-                acc = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a[t][kc], bv, acc, 0, 0, 0);
-            }
+            for (int kc = 0; kc < KC; ++kc)
+                acc = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a[t][kc], bop(n0, t, kc), acc, 0, 0, 0);
 #pragma unroll
         for (int q = 0; q < 4; ++q) {
             int64_t bb;
             int pp;
             rows(kq * 4 + q, bb, pp);
             if (bb >= 0)
-                epi(bb, pp, n0 + r, acc[q]);
+                epi(kq * 4 + q, bb, pp, n0 + r, acc[q]);
         }
     }
+}
+
+// B operands read from the packed weights of a layer.
+template <int C>
+struct WeightsGlobal {
+    const bf16 *wk;
+    __device__ bf16x8 operator()(int n0, int t, int kc) const
+    {
+        const int lane = threadIdx.x & 63;
+        return *(const bf16x8 *)(wk + (int64_t)(n0 + (lane & 15)) * 5 * C + (lane >> 4) * 8 + t * C +
+                                 kc * 32);
+    }
+};
+
+template <int C, class Rows, class Epi>
+__device__ __forceinline__ void conv_mfma(const bf16x8 (&a)[5][C / 32],
+                                          const bf16 *__restrict__ wk, const Rows &rows,
+                                          const Epi &epi)
+{
+    conv_mfma_b<C>(a, WeightsGlobal<C>{wk}, rows, epi);
+}
+
+// A operand of tap t of a tile row (configuration b, site (i, j)) from an
+// activation array: zero outside the lattice (zero padding).
+template <int C>
+__device__ __forceinline__ void load_tap(bf16x8 (&at)[C / 32], const bf16 *__restrict__ in,
+                                         int64_t b, int N, int L, int ii, int jj, int kq)
+{
+    const bool ok = b >= 0 && ii >= 0 && ii < L && jj >= 0 && jj < L;
+#pragma unroll
+    for (int kc = 0; kc < C / 32; ++kc) {
+        if (ok) {
+            at[kc] = *(const bf16x8 *)(in + ((int64_t)b * N + ii * L + jj) * C + kc * 32 + kq * 8);
+        } else {
+#pragma unroll
+            for (int e = 0; e < 8; ++e)
+                at[kc][e] = (bf16)0.f;
+        }
+    }
+}
+
+// out[rows, 0..C) of a masked 3x3 convolution with all five mask-B taps, the
+// taps read at offset sign * (dy, dx) (sign -1: the transposed convolution of
+// the backward pass).
+template <int C, class Rows, class Epi>
+__device__ __forceinline__ void conv_tile(const bf16 *__restrict__ in, const bf16 *__restrict__ wk,
+                                          int L, int N, int sign, const Rows &rows, const Epi &epi)
+{
+    const int lane = threadIdx.x & 63, r = lane & 15, kq = lane >> 4;
+    int64_t b;
+    int p;
+    rows(r, b, p);
+    const int i = p / L, j = p - (p / L) * L;
+    bf16x8 a[5][C / 32];
+#pragma unroll
+    for (int t = 0; t < 5; ++t)
+        load_tap<C>(a[t], in, b, N, L, i + sign * tap_dy(t), j + sign * tap_dx(t), kq);
+    conv_mfma<C>(a, wk, rows, epi);
 }
 
 struct EpiForward { // post-ReLU bf16 activation
     bf16 *out;
     const float *bias;
     int N, C;
-    __device__ void operator()(int64_t b, int p, int col, float v) const
+    __device__ void operator()(int, int64_t b, int p, int col, float v) const
     {
         out[((int64_t)b * N + p) * C + col] = (bf16)fmaxf(v + bias[col], 0.f);
+    }
+};
+
+// The sampler's epilogue: the activation also goes to an LDS tile (row =
+// configuration within the 16, C channels), the next layer's centre tap.
+struct EpiSample {
+    bf16 *out;
+    bf16 *tile;
+    const float *bias;
+    int N, C;
+    __device__ void operator()(int row, int64_t b, int p, int col, float v) const
+    {
+        const bf16 h = (bf16)fmaxf(v + bias[col], 0.f);
+        out[((int64_t)b * N + p) * C + col] = h;
+        tile[row * C + col] = h;
     }
 };
 
@@ -187,7 +261,7 @@ struct EpiBackward { // data gradient masked by the ReLU of the layer below
     bf16 *out;
     const bf16 *act;
     int N, C;
-    __device__ void operator()(int64_t b, int p, int col, float v) const
+    __device__ void operator()(int, int64_t b, int p, int col, float v) const
     {
         const int64_t o = ((int64_t)b * N + p) * C + col;
         out[o] = (bf16)((float)act[o] > 0.f ? v : 0.f);
@@ -256,6 +330,57 @@ __global__ __launch_bounds__(256) void k_logq(const int8_t *__restrict__ x,
 // final: every activation at a site depends on strictly earlier spins), then
 // draws the spin with a 24-bit uniform of Philox domain 3,
 //   counter (stream<<8 | 3<<4, round lo, round hi, p>>2), word p&3.
+// The operands from the previous row (three taps of every layer) are loaded
+// from the activation arrays at the start of the site, all at once; the
+// outputs and spins of the current and previous site, the other two taps,
+// are kept in LDS, so within a row no site waits on a store to memory (one
+// memory fence per row).  The arithmetic is conv_mfma()'s and l1_from()'s,
+// as in the evaluator.
+// B operands of one layer held in registers for the whole kernel (C == 32:
+// 10 operands per lane and layer).
+template <int C>
+struct WeightsRegs {
+    bf16x8 w[C / 16][5][C / 32];
+    __device__ void load(const bf16 *wk)
+    {
+        const WeightsGlobal<C> g{wk};
+#pragma unroll
+        for (int n = 0; n < C / 16; ++n)
+#pragma unroll
+            for (int t = 0; t < 5; ++t)
+#pragma unroll
+                for (int kc = 0; kc < C / 32; ++kc)
+                    w[n][t][kc] = g(16 * n, t, kc);
+    }
+    __device__ bf16x8 operator()(int n0, int t, int kc) const { return w[n0 / 16][t][kc]; }
+};
+
+// A operand of a tap from an LDS tile of 16 rows x C (zero when !ok).
+template <int C>
+__device__ __forceinline__ void lds_tap(bf16x8 (&at)[C / 32], const bf16 *tile, bool ok, int r,
+                                        int kq)
+{
+#pragma unroll
+    for (int kc = 0; kc < C / 32; ++kc) {
+        if (ok) {
+            at[kc] = *(const bf16x8 *)(tile + r * C + kc * 32 + kq * 8);
+        } else {
+#pragma unroll
+            for (int e = 0; e < 8; ++e)
+                at[kc][e] = (bf16)0.f;
+        }
+    }
+}
+
+// Orders the wavefront's LDS accesses (one wavefront per workgroup) without
+// waiting for its global stores.
+__device__ __forceinline__ void lds_sync()
+{
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup", "local");
+    __builtin_amdgcn_s_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup", "local");
+}
+
 template <int C>
 __global__ __launch_bounds__(64) void k_sample(NetDev net, bf16 *h1, bf16 *h2, bf16 *h3, bf16 *h4,
                                                bf16 *h5, int8_t *__restrict__ x,
@@ -263,41 +388,122 @@ __global__ __launch_bounds__(64) void k_sample(NetDev net, bf16 *h1, bf16 *h2, b
                                                uint32_t key1, uint32_t stream_base,
                                                uint32_t round_lo, uint32_t round_hi)
 {
+    constexpr int KC = C / 32;
+    constexpr bool kRegW = C == 32; // the four layers' weights fit in registers
+    // layer outputs (1..5) and spins at the last two sites, by site parity
+    __shared__ __align__(16) bf16 hist[6][2][16 * C];
+    __shared__ int8_t xs[2][16];
     const int N = net.N, L = net.L;
     const ParamLayout pl = param_layout(C);
-    const int lane = threadIdx.x;
+    const int lane = threadIdx.x, r = lane & 15, kq = lane >> 4;
     const int64_t b0 = (int64_t)blockIdx.x * 16;
     bf16 *hs[6] = {nullptr, h1, h2, h3, h4, h5};
+    WeightsRegs<(kRegW ? C : 32)> wreg[kRegW ? 4 : 1];
+    if (kRegW)
+#pragma unroll
+        for (int l = 2; l <= 5; ++l)
+            wreg[kRegW ? l - 2 : 0].load(net.wf[l]);
     double lq = 0.0;
-    const int s = lane & 15;
-    const bool mine = b0 + s < B;
+    const int64_t b = (b0 + r < B) ? b0 + r : -1; // this lane's tile row
+    const RowsOfConfigs rows_p{b0, B, 0};
     for (int p = 0; p < N; ++p) {
         const int i = p / L, j = p - (p / L) * L;
-        if (mine)
-            for (int c = lane >> 4; c < C; c += 4)
-                h1[((b0 + s) * N + p) * C + c] =
-                    (bf16)l1_value(x + (b0 + s) * N, L, i, j, net.w1, net.params + pl.b1, C, c);
-        __syncthreads();
-        for (int l = 2; l <= 5; ++l) {
-            conv_tile<C>(hs[l - 1], net.wf[l], L, N, +1, RowsOfConfigs{b0, B, p},
-                         EpiForward{hs[l], net.params + pl.b[l], N, C});
-            __syncthreads();
+        const int cur = p & 1, prv = cur ^ 1;
+        const bool left = j > 0; // tap (0, -1) inside the lattice
+        // previous-row taps (dy = -1: t = 0, 1, 2) of layers 2..5 and 6, and spins
+        bf16x8 pre[4][3][KC];
+#pragma unroll
+        for (int l = 2; l <= 5; ++l)
+#pragma unroll
+            for (int t = 0; t < 3; ++t)
+                load_tap<C>(pre[l - 2][t], hs[l - 1], b, N, L, i + tap_dy(t), j + tap_dx(t), kq);
+        bf16x8 r6[3][C / 8];
+        bool in6[3];
+#pragma unroll
+        for (int t = 0; t < 3; ++t) {
+            const int ii = i + tap_dy(t), jj = j + tap_dx(t);
+            in6[t] = !(ii < 0 || jj < 0 || jj >= L);
+            if (lane < 16 && b >= 0 && in6[t]) {
+                const bf16 *src = h5 + (b * N + ii * L + jj) * C;
+#pragma unroll
+                for (int v = 0; v < C / 8; ++v)
+                    r6[t][v] = *(const bf16x8 *)(src + v * 8);
+            }
         }
-        if (lane < 16 && mine) {
-            const float z = l6_logit(h5, N, L, C, b0 + lane, i, j, net.w6, net.params[pl.b6]);
+        // layer 1 at p (mask A: earlier spins only)
+        if (b >= 0) {
+            float xv[4];
+#pragma unroll
+            for (int t = 0; t < 3; ++t) {
+                const int ii = i + tap_dy(t), jj = j + tap_dx(t);
+                xv[t] = (ii >= 0 && jj >= 0 && jj < L) ? (float)x[b * N + ii * L + jj] : 0.f;
+            }
+            xv[3] = left ? (float)xs[prv][r] : 0.f;
+            for (int c = kq; c < C; c += 4) {
+                const bf16 h = (bf16)l1_from(xv, net.w1, net.params + pl.b1, C, c);
+                h1[(b * N + p) * C + c] = h;
+                hist[1][cur][r * C + c] = h;
+            }
+        }
+        lds_sync();
+        RowsOfConfigs rows = rows_p;
+        rows.p = p;
+#pragma unroll
+        for (int l = 2; l <= 5; ++l) {
+            bf16x8 a[5][KC];
+#pragma unroll
+            for (int t = 0; t < 3; ++t)
+#pragma unroll
+                for (int kc = 0; kc < KC; ++kc)
+                    a[t][kc] = pre[l - 2][t][kc];
+            lds_tap<C>(a[3], hist[l - 1][prv], b >= 0 && left, r, kq);
+            lds_tap<C>(a[4], hist[l - 1][cur], b >= 0, r, kq);
+            const EpiSample epi{hs[l], hist[l][cur], net.params + pl.b[l], N, C};
+            if constexpr (kRegW)
+                conv_mfma_b<C>(a, wreg[l - 2], rows, epi);
+            else
+                conv_mfma<C>(a, net.wf[l], rows, epi);
+            lds_sync();
+        }
+        if (lane < 16 && b >= 0) {
+            // layer 6, in l6_from_rows()'s order: taps 0..4, channels 0..C-1
+            const float *w6 = net.w6;
+            float acc = 0.f;
+#pragma unroll
+            for (int t = 0; t < 3; ++t)
+                if (in6[t])
+#pragma unroll
+                    for (int v = 0; v < C / 8; ++v)
+#pragma unroll
+                        for (int e = 0; e < 8; ++e)
+                            acc = fmaf((float)r6[t][v][e], w6[t * C + v * 8 + e], acc);
+            if (left) {
+                const bf16 *w = hist[5][prv] + r * C;
+                for (int ci = 0; ci < C; ++ci)
+                    acc = fmaf((float)w[ci], w6[3 * C + ci], acc);
+            }
+            const bf16 *centre = hist[5][cur] + r * C;
+            for (int ci = 0; ci < C; ++ci)
+                acc = fmaf((float)centre[ci], w6[4 * C + ci], acc);
+            const float z = acc + net.params[pl.b6];
             const float Pq = quantise(prob_plus(z));
-            const Block u = philox4x32_10(ctr_word0(stream_base + (uint32_t)(b0 + lane), 3u, 0u),
-                                          round_lo, round_hi, (uint32_t)(p >> 2), key0, key1);
+            const Block u = philox4x32_10(ctr_word0(stream_base + (uint32_t)b, 3u, 0u), round_lo,
+                                          round_hi, (uint32_t)(p >> 2), key0, key1);
             const uint32_t w = (p & 3) == 0 ? u.x0 : (p & 3) == 1 ? u.x1 : (p & 3) == 2 ? u.x2 : u.x3;
             const float uf = (float)(w >> 8) * (1.f / 16777216.f);
             const int xv = uf < Pq ? 1 : -1;
-            x[(b0 + lane) * N + p] = (int8_t)xv;
+            x[b * N + p] = (int8_t)xv;
+            xs[cur][r] = (int8_t)xv;
             lq += site_logq(Pq, xv);
         }
-        __syncthreads();
+        // the next row reads this row's activations and spins from memory
+        if (j == L - 1)
+            __syncthreads();
+        else
+            lds_sync();
     }
-    if (lane < 16 && mine)
-        logq[b0 + lane] = (float)lq;
+    if (lane < 16 && b >= 0)
+        logq[b] = (float)lq;
 }
 
 // --------------------------------------------------------------- backward
