@@ -26,11 +26,13 @@ def init_params(L_unused: int, C: int, seed: int, scale: float = 0.5) -> np.ndar
     return np.concatenate(parts).astype(np.float32)
 
 
-def plain_configurations(L: int, beta: float, chains: int, snapshots: int, thin: int, burn: int,
+def plain_configurations(L: int, beta, chains: int, snapshots: int, thin: int, burn: int,
                          seed: int, J: float = 1.0, stream_base: int = 0):
     """(chains * snapshots, L, L) int8 configurations from independent plain
-    chains: `burn` sweeps, then a snapshot every `thin` sweeps."""
-    b = lt.Batch([L] * chains, [beta] * chains, J, [seed] * chains,
+    chains: `burn` sweeps, then a snapshot every `thin` sweeps.  `beta` is one
+    inverse temperature, or a sequence that the chains cycle through."""
+    betas = np.resize(np.atleast_1d(np.asarray(beta, dtype=np.float64)), chains)
+    b = lt.Batch([L] * chains, betas, J, [seed] * chains,
                  list(range(stream_base, stream_base + chains)))
     b.init()
     b.sweep(burn)
@@ -85,6 +87,7 @@ class Chains:
         self.betaJ = torch.as_tensor(self.betas * J, dtype=torch.float32, device=dev)
         self.accepted = 0
         self.proposed = 0
+        self.accepted_per_chain = torch.zeros(self.n, dtype=torch.int64, device=dev)
 
     def observables(self):
         bond, mag = self.batch.observables_async()
@@ -103,6 +106,7 @@ class Chains:
         acc = lt.mh_independence(self.spins, logq, bond, prop, logq_prop, bond_prop, self.betaJ,
                                  seed=seed + 1, stream_base=stream_base, round=rnd)
         self.batch.set_spins(self.spins)
+        self.accepted_per_chain += acc.to(torch.int64)
         self.accepted += int(acc.sum().item())
         self.proposed += self.n
         return acc
@@ -131,3 +135,35 @@ def run_series(chains: Chains, rounds: int, local_per_round: int, net=None, seed
     torch.cuda.synchronize()
     wall = time.perf_counter() - t0
     return E.cpu().numpy(), A.cpu().numpy(), wall
+
+
+def compare_over_betas(net, L: int, betas, per_beta: int, sweeps: int, sweeps_per_proposal: int,
+                       burn: int, seed_plain: int, seed_hybrid: int, J: float = 1.0) -> dict:
+    """Plain chains against hybrid chains (one global move every
+    `sweeps_per_proposal` local sweeps) over a set of temperatures, `per_beta`
+    independent chains each, the two kinds seeded independently: per beta the
+    energy per site and the Binder cumulant with jackknife errors over chains,
+    tau_int(|m|) per measurement, acceptance, and the wall time of both."""
+    from . import stats
+
+    betas = np.asarray(betas, dtype=np.float64)
+    all_betas = np.repeat(betas, per_beta)
+    out = {}
+    for kind, use, seed in (("plain", None, seed_plain), ("hybrid", net, seed_hybrid)):
+        ch = Chains(L, all_betas, seed=seed, J=J)
+        ch.local(burn)
+        rounds = sweeps // sweeps_per_proposal
+        E, A, wall = run_series(ch, rounds, sweeps_per_proposal, use, seed=seed, round0=1)
+        acc = ch.accepted_per_chain.cpu().numpy()
+        ch.close()
+        rows = []
+        for k, beta in enumerate(betas):
+            cols = slice(k * per_beta, (k + 1) * per_beta)
+            e, e_se = stats.jackknife_chains(E[:, cols], np.mean)
+            u, u_se = stats.jackknife_chains(A[:, cols], stats.binder)
+            rows.append({"beta": float(beta), "E_per_site": e, "E_se": e_se, "binder": u,
+                         "binder_se": u_se, "tau_int_abs_m": stats.tau_int_chains(A[:, cols]),
+                         "acceptance": (float(acc[cols].sum()) / (per_beta * rounds)
+                                        if use is not None else None)})
+        out[kind] = {"per_beta": rows, "wall_s": wall, "measurements": rounds}
+    return out

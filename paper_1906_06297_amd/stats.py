@@ -53,3 +53,22 @@ def blocking_se(x) -> float:
         x = 0.5 * (x[: x.size // 2 * 2: 2] + x[1: x.size // 2 * 2: 2])
         best = max(best, x.std(ddof=1) / np.sqrt(x.size))
     return float(best)
+
+
+def binder(abs_m) -> float:
+    """Binder cumulant U = 1 - <m^4> / (3 <m^2>^2) of a sample of |m|."""
+    a = np.asarray(abs_m, dtype=np.float64)
+    m2, m4 = np.mean(a ** 2), np.mean(a ** 4)
+    return float(1.0 - m4 / (3.0 * m2 * m2))
+
+
+def jackknife_chains(series: np.ndarray, estimator) -> tuple:
+    """Estimate and jackknife standard error over independent chains (columns of
+    `series`, rows: time): the estimator on all chains, and on the chains with
+    one left out in turn."""
+    s = np.asarray(series, dtype=np.float64)
+    k = s.shape[1]
+    full = estimator(s.reshape(-1))
+    loo = np.array([estimator(np.delete(s, q, axis=1).reshape(-1)) for q in range(k)])
+    se = np.sqrt((k - 1) / k * np.sum((loo - loo.mean()) ** 2))
+    return float(full), float(se)

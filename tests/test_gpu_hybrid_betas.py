@@ -1,0 +1,48 @@
+"""The hybrid chain on its second workload, shortened: L = 64, 16 inverse
+temperatures in [0.40, 0.48] with 16 chains each, a 64-channel network
+trained on plain-sampler configurations pooled over those temperatures, one
+global move per 10 local sweeps.  Energy per site and Binder cumulant of the
+hybrid chains agree with independent plain chains within their errors."""
+import numpy as np
+import pytest
+
+pytestmark = pytest.mark.gpu
+
+
+def test_hybrid_scan_agrees_with_plain_chains():
+    import torch
+
+    import paper_1906_06297_amd as m
+    from paper_1906_06297_amd import hybrid
+
+    assert torch.cuda.is_available()
+    L, C = 64, 64
+    betas = np.linspace(0.40, 0.48, 16)
+    data = hybrid.plain_configurations(L, betas, chains=256, snapshots=8, thin=100, burn=20000,
+                                       seed=61, stream_base=4096)
+    net = m.ARNet(L, C, 256)
+    try:
+        net.set_params(hybrid.init_params(L, C, seed=3))
+        hist = hybrid.train(net, data, steps=300, batch=64, lr=2e-3, seed=4, log_every=100)
+        print("training NLL per site:", hist, flush=True)
+        assert hist[-1][1] < 0.7 * hist[0][1]
+        res = hybrid.compare_over_betas(net, L, betas, per_beta=16, sweeps=1500,
+                                        sweeps_per_proposal=10, burn=20000, seed_plain=71,
+                                        seed_hybrid=72)
+    finally:
+        net.close()
+    z = []
+    for p, h in zip(res["plain"]["per_beta"], res["hybrid"]["per_beta"]):
+        print(f"beta {p['beta']:.4f}: E {p['E_per_site']:.5f}+-{p['E_se']:.5f} vs "
+              f"{h['E_per_site']:.5f}+-{h['E_se']:.5f}; U {p['binder']:.4f}+-{p['binder_se']:.4f} vs "
+              f"{h['binder']:.4f}+-{h['binder_se']:.4f}; acceptance {h['acceptance']:.4f}", flush=True)
+        for key, err in (("E_per_site", "E_se"), ("binder", "binder_se")):
+            z.append((h[key] - p[key]) / np.hypot(p[err], h[err]))
+    z = np.asarray(z)
+    print("z:", np.round(z, 2), flush=True)
+    print("wall s (plain, hybrid):", res["plain"]["wall_s"], res["hybrid"]["wall_s"],
+          "tau_int(|m|) per measurement:",
+          [(round(p["tau_int_abs_m"], 1), round(h["tau_int_abs_m"], 1))
+           for p, h in zip(res["plain"]["per_beta"], res["hybrid"]["per_beta"])], flush=True)
+    assert np.all(np.abs(z) < 4.5)
+    assert np.mean(z ** 2) < 3.0  # 32 comparisons: chi^2 per degree of freedom
