@@ -34,6 +34,7 @@ KERNEL_SOURCES = ("paper_1906_06297_amd/csrc/sweep_kernels.hip",
                   "paper_1906_06297_amd/csrc/ising_device.hpp",
                   "paper_1906_06297_amd/csrc/ising_rows.hpp")
 COUNTERS_SUMMARY = "profiles/half_sweep_L65536_counters.md"
+N_SIMD = 1024  # 256 CUs x 4 SIMDs, one wave64 VALU instruction per 4 cycles each
 
 
 def kernel_source_hash() -> str:
@@ -46,25 +47,47 @@ def kernel_source_hash() -> str:
     return h.hexdigest()
 
 
-def measured_traffic():
-    """HBM bytes per half-sweep launch from the committed counter summary, if it
-    was taken on the kernel sources as they are now (else None)."""
+def counter_summary() -> dict:
+    """Values of the committed counter summary of the half-sweep, if it was taken
+    on the kernel sources as they are now (else empty)."""
     path = os.path.join(ROOT, COUNTERS_SUMMARY)
     if not os.path.exists(path):
-        return None
+        return {}
     vals = {}
     with open(path) as f:
         for line in f:
             if ":" in line and line.strip().startswith(("source-sha256", "fetch_bytes_per_launch",
-                                                        "write_bytes_per_launch")):
+                                                        "write_bytes_per_launch",
+                                                        "valu_insts_per_launch",
+                                                        "shader_clock_ghz")):
                 k, v = line.split(":", 1)
                 vals[k.strip()] = v.strip()
     if vals.get("source-sha256") != kernel_source_hash():
-        return None
+        return {}
+    return vals
+
+
+def measured_traffic():
+    """HBM bytes per half-sweep launch from the counter summary, or None."""
+    vals = counter_summary()
     try:
         return float(vals["fetch_bytes_per_launch"]) + float(vals["write_bytes_per_launch"])
     except (KeyError, ValueError):
         return None
+
+
+def valu_issue(avg_launch_us: float):
+    """The vector-ALU side of the half-sweep: its wave-level VALU instructions
+    per launch (counter summary) at one instruction per 4 cycles on each of the
+    1024 SIMDs, against the measured launch time."""
+    vals = counter_summary()
+    try:
+        insts, ghz = float(vals["valu_insts_per_launch"]), float(vals["shader_clock_ghz"])
+    except (KeyError, ValueError):
+        return None
+    issue_us = insts * 4 / N_SIMD / (ghz * 1e3)
+    return {"valu_insts_per_launch": insts, "shader_clock_ghz": ghz,
+            "issue_us": issue_us, "frac_of_launch": issue_us / avg_launch_us}
 
 
 def onsager_energy(beta: float) -> float:
@@ -95,14 +118,39 @@ def cpu_baseline(target_s: float = 15.0) -> dict:
         oracle.sweeps(s, beta, 1.0, seed, 0, extra, 1)
     dt = time.perf_counter() - t0
     nsw, secs = (extra, dt) if extra else (1, one)
+    # one thread, a shorter sample of the same sweep
+    oracle.set_threads(1)
+    L1 = 2048
+    s1 = oracle.init(L1, seed, 0)
+    t0 = time.perf_counter()
+    n1 = 0
+    while time.perf_counter() - t0 < 3.0:
+        oracle.sweeps(s1, beta, 1.0, seed, 0, 1, n1)
+        n1 += 1
+    single = n1 * L1 * L1 / ((time.perf_counter() - t0) * 1e9)
+    oracle.set_threads(cores)
     return {
         "value": nsw * L * L / (secs * 1e9),
         "unit": "flips/ns",
         "cores": cores,
         "kind": "oracle",
         "sample": (f"C/OpenMP int8 oracle (all 32 bit-planes per spin), {nsw} sweeps of an "
-                   f"L={L} lattice at beta={beta} from the seed-{seed} start, {secs:.1f} s"),
+                   f"L={L} lattice at beta={beta} from the seed-{seed} start, {secs:.1f} s; "
+                   f"one thread: {n1} sweeps of L={L1}"),
+        "single_thread_value": single,
+        "host_cpu": host_cpu(),
     }
+
+
+def host_cpu() -> str:
+    try:
+        with open("/proc/cpuinfo") as f:
+            for line in f:
+                if line.startswith("model name"):
+                    return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return "unknown"
 
 
 def bench_batched(ising, torch, nsweeps: int) -> dict:
@@ -201,6 +249,11 @@ def bench_learned(ising, torch, L: int = 32, betas=(0.42, 0.44, 0.46), C: int = 
                 "abs_m": float(pm.mean()), "abs_m_se": float(pm.std(ddof=1) / np.sqrt(chains)),
             }
         net.close()
+        # wall time the hybrid chains need for the standard error the plain chains reach
+        # in the same wall time, relative to the plain chains (ESS/s ratio)
+        res["hybrid_wall_for_matched_error"] = {
+            obs: res["plain"][f"ess_per_s_{obs}"] / res["hybrid"][f"ess_per_s_{obs}"]
+            for obs in ("abs_m", "E")}
         out[str(beta)] = {"train_nll_per_site": hist, "data_s": t_data, "train_s": t_train, **res}
     return {
         "workload": f"L={L}, beta in {list(betas)}: per beta a {C}-channel masked-conv "
@@ -224,6 +277,9 @@ def main() -> int:
     ap.add_argument("--learned-rounds", type=int, default=400,
                     help="rounds of the learned-proposal comparison reported beside the headline "
                          "(0 = skip)")
+    ap.add_argument("--hold-seconds", type=float, default=0.0,
+                    help="only run L = 65536 sweeps at beta_c for this many seconds (for reading "
+                         "clocks and power beside a steady load) and exit")
     ap.add_argument("--print-source-hash", action="store_true",
                     help="print the hash of the half-sweep kernel sources and exit")
     ap.add_argument("--copy-calibration", action="store_true",
@@ -244,6 +300,16 @@ def main() -> int:
 
     assert torch.cuda.is_available(), "bench.py needs a HIP device"
     torch.cuda.set_device(0)
+    if args.hold_seconds > 0:
+        lat = ising.Lattice(workloads.HEADLINE["L"], workloads.HEADLINE["seed"])
+        t0, n = time.perf_counter(), 0
+        while time.perf_counter() - t0 < args.hold_seconds:
+            lat.sweep(workloads.BETA_CRIT_CONFIG, 1.0, 50, n)
+            torch.cuda.synchronize()
+            n += 50
+        print(f"held: {n} sweeps, {(time.perf_counter() - t0) / (2 * n) * 1e6:.1f} us per "
+              "half-sweep", flush=True)
+        return 0
     cfg = workloads.HEADLINE
     L, betas, seed, J = cfg["L"], cfg["betas"], cfg["seed"], cfg["J"]
     K, Wm = args.steps, args.warmup
@@ -316,6 +382,7 @@ def main() -> int:
             "traffic": measured_traffic(),
             "avg_launch_us": half_sweep_ms * 1e3,
             "alg_bytes_per_launch": alg_bytes,
+            "valu": valu_issue(half_sweep_ms * 1e3),
         },
     }
     if args.batched_sweeps > 0:
