@@ -5,9 +5,10 @@ CPU-baseline leg of ``bench.py`` may import this package.  It shares no code
 with the GPU library (``paper_1906_06297_amd``) and never imports it.
 
 Contents
-  - ``ising_oracle.c``   plain C/OpenMP: Philox4x32-10, the threshold table,
-                         int8 lattice init, half-sweep, sweeps, observables
-                         (paper Sec. 2, Sec. 3.1, Fig. 2; Eq. (1)).
+  - ``ising_oracle.c``   plain C/OpenMP: Philox4x32-10, the threshold tables
+                         (Metropolis and heat bath, Sec. 2), int8 lattice
+                         init, half-sweep, sweeps, observables (paper Sec. 2,
+                         Sec. 3.1, Fig. 2; Eq. (1)).
   - ``exact.py``         exact results: enumeration, transfer matrix,
                          Kaufman's finite-lattice solution, Onsager, Eq. (7).
   - ``stats.py``         blocking standard errors and integrated
@@ -65,6 +66,8 @@ def lib():
         "orc_philox4x32_10": (None, [u32p, u32p, u32p]),
         "orc_site_uniform": (c_u32, [c_u64, c_u32, c_u64, c_i64]),
         "orc_thresholds": (None, [c_dbl, c_dbl, u64p]),
+        "orc_thresholds_heatbath": (None, [c_dbl, c_dbl, u64p]),
+        "orc_sweeps_table": (None, [i8p, c_i64, u64p, c_u64, c_u32, c_i64, c_u64, i64p, i64p]),
         "orc_init": (None, [i8p, c_i64, c_u64, c_u32]),
         "orc_half_sweep": (None, [i8p, c_i64, c_int, u64p, c_u64, c_u32, c_u64]),
         "orc_observables": (None, [i8p, c_i64, i64p, i64p]),
@@ -112,10 +115,16 @@ def site_uniform(seed: int, stream: int, t: int, n: int) -> int:
 
 
 # --------------------------------------------------------------------- thresholds
-def thresholds(beta: float, J: float) -> np.ndarray:
-    """T[a], a = 0..4 aligned neighbours: flip accepted iff r < T[a] (r uniform 32-bit)."""
+RULES = ("metropolis", "heatbath")
+
+
+def thresholds(beta: float, J: float, rule: str = "metropolis") -> np.ndarray:
+    """T[a], a = 0..4 aligned neighbours: flip accepted iff r < T[a] (r uniform 32-bit).
+    rule "metropolis": min(1, e^{-beta dE}); "heatbath": e^{-beta dE} / (e^{-beta dE} + 1)
+    (Sec. 2)."""
     T = np.zeros(5, dtype=np.uint64)
-    lib().orc_thresholds(float(beta), float(J), _ptr(T, ctypes.c_uint64))
+    fn = {"metropolis": lib().orc_thresholds, "heatbath": lib().orc_thresholds_heatbath}[rule]
+    fn(float(beta), float(J), _ptr(T, ctypes.c_uint64))
     return T
 
 
@@ -138,7 +147,7 @@ def half_sweep(s: np.ndarray, colour: int, T: np.ndarray, seed: int, stream: int
 
 
 def sweeps(s: np.ndarray, beta: float, J: float, seed: int, stream: int, nsweeps: int,
-           rng_counter: int = 0, trace: bool = False):
+           rng_counter: int = 0, trace: bool = False, rule: str = "metropolis"):
     """In-place ``nsweeps`` full sweeps; returns (bond_trace, M_trace) if ``trace``."""
     L = s.shape[0]
     _check_L(L)
@@ -149,8 +158,13 @@ def sweeps(s: np.ndarray, beta: float, J: float, seed: int, stream: int, nsweeps
         bp, mp = _ptr(bt, ctypes.c_int64), _ptr(mt, ctypes.c_int64)
     else:
         bp = mp = None
-    lib().orc_sweeps(_ptr(s, ctypes.c_int8), L, float(beta), float(J), seed, stream, nsweeps,
-                     rng_counter, bp, mp)
+    if rule == "metropolis":
+        lib().orc_sweeps(_ptr(s, ctypes.c_int8), L, float(beta), float(J), seed, stream,
+                         nsweeps, rng_counter, bp, mp)
+    else:
+        T = thresholds(beta, J, rule)
+        lib().orc_sweeps_table(_ptr(s, ctypes.c_int8), L, _ptr(T, ctypes.c_uint64), seed, stream,
+                               nsweeps, rng_counter, bp, mp)
     if trace:
         return bt, mt
     return None

@@ -23,6 +23,10 @@
  *    change from flipping sigma with neighbour sum nn is dE = 2*J*sigma*nn,
  *    as in the update kernels of Fig. 2.
  *  - dE = 0 is accepted (exp(0) = 1 exceeds any uniform in [0,1)).
+ *  - Heat bath (Sec. 2, the other local rule named there): the flip
+ *    probability e^{-beta dE} / (e^{-beta dE} + 1) is evaluated as
+ *    1 / (1 + e^{beta dE}) (no intermediate overflow) and quantised the same
+ *    way, T[a] = floor(p * 2^32); every class then draws a random number.
  *  - The acceptance probability is quantised to 32 bits: the flip is taken
  *    iff r < T[a], r a uniform 32-bit integer, a = number of neighbours
  *    aligned with sigma, T[a] = 2^32 when dE <= 0 and
@@ -144,6 +148,20 @@ void orc_thresholds(double beta, double J, uint64_t *T)
     }
 }
 
+/* Heat-bath thresholds (Sec. 2: a spin flips with probability               */
+/* e^{-beta dE} / (e^{-beta dE} + 1)), written as 1 / (1 + e^{beta dE}) so    */
+/* that no intermediate overflows; T[a] = floor(p * 2^32), 2^32 when p rounds */
+/* to 1.                                                                     */
+void orc_thresholds_heatbath(double beta, double J, uint64_t *T)
+{
+    for (int a = 0; a <= 4; ++a) {
+        int sigma_nn = 2 * a - 4;
+        double dE = 2.0 * J * sigma_nn;
+        double p = 1.0 / (1.0 + exp(beta * dE));
+        T[a] = (uint64_t)floor(p * 4294967296.0);
+    }
+}
+
 /* ------------------------------------------------------------------------ */
 /* Lattice helpers.                                                          */
 /* ------------------------------------------------------------------------ */
@@ -253,12 +271,10 @@ void orc_observables(const int8_t *s, int64_t L, int64_t *bond, int64_t *mag)
 
 /* nsweeps full sweeps (black then white) starting at sweep counter
  * rng_counter; optional per-sweep trace of (bond sum, magnetisation). */
-static void orc_sweeps_impl(int8_t *s, int64_t L, double beta, double J, uint64_t seed,
-                            uint32_t stream, int64_t nsweeps, uint64_t rng_counter,
-                            int64_t *bond_trace, int64_t *mag_trace, int parallel)
+static void orc_sweeps_table_impl(int8_t *s, int64_t L, const uint64_t *T, uint64_t seed,
+                                  uint32_t stream, int64_t nsweeps, uint64_t rng_counter,
+                                  int64_t *bond_trace, int64_t *mag_trace, int parallel)
 {
-    uint64_t T[5];
-    orc_thresholds(beta, J, T);
     for (int64_t sw = 0; sw < nsweeps; ++sw) {
         for (int c = 0; c < 2; ++c) {
             uint64_t t = 2 * (rng_counter + (uint64_t)sw) + (uint64_t)c;
@@ -269,10 +285,28 @@ static void orc_sweeps_impl(int8_t *s, int64_t L, double beta, double J, uint64_
     }
 }
 
+static void orc_sweeps_impl(int8_t *s, int64_t L, double beta, double J, uint64_t seed,
+                            uint32_t stream, int64_t nsweeps, uint64_t rng_counter,
+                            int64_t *bond_trace, int64_t *mag_trace, int parallel)
+{
+    uint64_t T[5];
+    orc_thresholds(beta, J, T);
+    orc_sweeps_table_impl(s, L, T, seed, stream, nsweeps, rng_counter, bond_trace, mag_trace,
+                          parallel);
+}
+
 void orc_sweeps(int8_t *s, int64_t L, double beta, double J, uint64_t seed, uint32_t stream,
                 int64_t nsweeps, uint64_t rng_counter, int64_t *bond_trace, int64_t *mag_trace)
 {
     orc_sweeps_impl(s, L, beta, J, seed, stream, nsweeps, rng_counter, bond_trace, mag_trace, 1);
+}
+
+/* Sweeps under any acceptance table T[a] (flip iff r < T[a]). */
+void orc_sweeps_table(int8_t *s, int64_t L, const uint64_t *T, uint64_t seed, uint32_t stream,
+                      int64_t nsweeps, uint64_t rng_counter, int64_t *bond_trace,
+                      int64_t *mag_trace)
+{
+    orc_sweeps_table_impl(s, L, T, seed, stream, nsweeps, rng_counter, bond_trace, mag_trace, 1);
 }
 
 /* Many independent lattices, one per thread at a time.  Lattice q occupies
