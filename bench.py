@@ -203,6 +203,41 @@ def bench_batched(ising, torch, nsweeps: int) -> dict:
     }
 
 
+def bench_heatbath(ising, torch, bufs, steps: int) -> dict:
+    """The headline workload under the heat-bath rule (Sec. 2): same lattices,
+    betas and start; every class draws random numbers."""
+    cfg = workloads.HEADLINE
+    L, betas, seed, J = cfg["L"], cfg["betas"], cfg["seed"], cfg["J"]
+    lats = [ising.Lattice(L, seed, words=b) for b in bufs]
+    for lat, beta in zip(lats, betas):
+        lat.sweep(beta, J, 1, 0, rule="heatbath")
+    lats = [ising.Lattice(L, seed, words=b) for b in bufs]
+    torch.cuda.synchronize()
+    per_beta = {}
+    t_all = 0.0
+    for lat, beta in zip(lats, betas):
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record()
+        lat.sweep(beta, J, steps, 0, rule="heatbath")
+        e1.record()
+        torch.cuda.synchronize()
+        ms = e0.elapsed_time(e1)
+        t_all += ms
+        bond, mag = lat.observables()
+        per_beta[str(beta)] = {"flips_per_ns": steps * L * L / (ms * 1e6),
+                               "E_per_site": -J * bond / (L * L),
+                               "onsager_E_per_site": onsager_energy(beta * J)}
+    half_us = t_all * 1e3 / (2 * steps * len(betas))
+    return {
+        "workload": f"heat-bath checkerboard sweeps, L={L}, J={J}, beta in {list(betas)}, seed {seed}, "
+                    f"{steps} sweeps per beta from a fresh start",
+        "flips_per_ns": len(betas) * steps * L * L / (t_all * 1e6),
+        "avg_half_sweep_us": half_us,
+        "hbm_frac": 805306368 / (half_us * 1e-6) / 1e9 / HBM_PEAK_GBS,
+        "per_beta": per_beta,
+    }
+
+
 def bench_learned(ising, torch, L: int = 32, betas=(0.42, 0.44, 0.46), C: int = 32,
                   chains: int = 4096, rounds: int = 400, train_steps: int = 1500,
                   data_log2: int = 20) -> dict:
@@ -277,6 +312,9 @@ def main() -> int:
     ap.add_argument("--learned-rounds", type=int, default=400,
                     help="rounds of the learned-proposal comparison reported beside the headline "
                          "(0 = skip)")
+    ap.add_argument("--heatbath-sweeps", type=int, default=20,
+                    help="sweeps per beta of the heat-bath rule on the headline lattices, reported "
+                         "beside the headline (0 = skip)")
     ap.add_argument("--hold-seconds", type=float, default=0.0,
                     help="only run L = 65536 sweeps at beta_c for this many seconds (for reading "
                          "clocks and power beside a steady load) and exit")
@@ -385,6 +423,8 @@ def main() -> int:
             "valu": valu_issue(half_sweep_ms * 1e3),
         },
     }
+    if args.heatbath_sweeps > 0:
+        out["heatbath"] = bench_heatbath(ising, torch, bufs, args.heatbath_sweeps)
     if args.batched_sweeps > 0:
         out["batched"] = bench_batched(ising, torch, args.batched_sweeps)
     if args.learned_rounds > 0:

@@ -55,6 +55,12 @@ enum {
     ISING_E_HIP = -3     /* a HIP runtime call or kernel launch failed */
 };
 
+/* Local update rules (Sec. 2). */
+enum {
+    ISING_RULE_METROPOLIS = 0, /* flip with probability min(1, e^{-beta dE}) */
+    ISING_RULE_HEATBATH = 1    /* flip with probability e^{-beta dE} / (e^{-beta dE} + 1) */
+};
+
 /* A lattice: plain data, owned by the caller, as is the memory it points to. */
 typedef struct ising_lattice {
     uint64_t *words;    /* device: 2 * ising_words_per_colour(L) words */
@@ -82,6 +88,20 @@ int ising_init(ising_lattice *lat, uint64_t *d_words, size_t bytes, int64_t L, u
  * with consecutive rng_counter gives the same lattice.  Asynchronous. */
 int ising_sweep(const ising_lattice *lat, double beta, double J, int64_t nsweeps,
                 uint64_t rng_counter, void *hip_stream);
+
+/* The threshold table T[0..4] of a rule (ISING_RULE_*): flip iff r < T[a],
+ * r a uniform 32-bit integer, a the number of neighbours aligned with the
+ * spin; T[a] = floor(p * 2^32) of the rule's flip probability p (heat bath
+ * evaluated as 1 / (1 + e^{beta dE})), 2^32 when p = 1.  Host only.
+ * ISING_E_BADARG for an unknown rule, beta < 0 or a non-finite J. */
+int ising_thresholds_rule(double beta, double J, int rule, uint64_t *T_out);
+
+/* As ising_sweep under rule `rule` (Sec. 2: the checkerboard decomposition
+ * serves any local rule; heat bath draws for all five classes).  Same
+ * counters and planes as ising_sweep, so ISING_RULE_METROPOLIS is
+ * ising_sweep.  Asynchronous; ISING_E_BADARG for an unknown rule. */
+int ising_sweep_rule(const ising_lattice *lat, double beta, double J, int rule, int64_t nsweeps,
+                     uint64_t rng_counter, void *hip_stream);
 
 /* As ising_sweep, and after sweep s writes the bond sum and magnetisation of
  * the lattice to d_bond_trace[s] and d_mag_trace[s] (device, nsweeps int64

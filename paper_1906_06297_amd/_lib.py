@@ -13,6 +13,7 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(HERE, "libising.so")
 
 ISING_OK = 0
+RULE_METROPOLIS, RULE_HEATBATH = 0, 1
 ISING_E_BADARG = -1
 ISING_E_SIZE = -2
 ISING_E_HIP = -3
@@ -47,6 +48,8 @@ SIGNATURES = {
     "ising_thresholds": (ctypes.c_int, [_dbl, _dbl, ctypes.POINTER(_u64)]),
     "ising_init": (ctypes.c_int, [_lat_p, _vp, ctypes.c_size_t, _i64, _u64, _u32, _vp]),
     "ising_sweep": (ctypes.c_int, [_lat_p, _dbl, _dbl, _i64, _u64, _vp]),
+    "ising_thresholds_rule": (ctypes.c_int, [_dbl, _dbl, ctypes.c_int, ctypes.POINTER(_u64)]),
+    "ising_sweep_rule": (ctypes.c_int, [_lat_p, _dbl, _dbl, ctypes.c_int, _i64, _u64, _vp]),
     "ising_sweep_traced": (ctypes.c_int, [_lat_p, _dbl, _dbl, _i64, _u64, _vp, _vp, _vp]),
     "ising_observables": (ctypes.c_int, [_lat_p, _vp, _vp, _vp]),
     "ising_get_spins": (ctypes.c_int, [_lat_p, _vp, _vp]),

@@ -55,6 +55,30 @@ void threshold_table(double beta, double J, uint64_t T[5])
     }
 }
 
+// Heat bath (Sec. 2): flip probability e^{-beta dE} / (e^{-beta dE} + 1),
+// evaluated as 1 / (1 + e^{beta dE}) (no intermediate overflow).
+void heatbath_table(double beta, double J, uint64_t T[5])
+{
+    for (int a = 0; a < 5; ++a) {
+        const double dE = 4.0 * J * (double)(a - 2);
+        T[a] = (uint64_t)std::floor(1.0 / (1.0 + std::exp(beta * dE)) * 4294967296.0);
+    }
+}
+
+rows::Table5 table5(const uint64_t T[5])
+{
+    rows::Table5 tab{};
+    for (int a = 0; a < 5; ++a) {
+        if (T[a] >= (1ull << 32)) {
+            tab.always |= 1u << a;
+        } else if (T[a] > 0) {
+            tab.random |= 1u << a;
+            tab.thr[a] = (uint32_t)T[a];
+        }
+    }
+    return tab;
+}
+
 Metro2 metro2_params(double beta, double J)
 {
     uint64_t T[5];
@@ -142,6 +166,23 @@ int run_sweeps(const ising_lattice *lat, double beta, double J, int64_t nsweeps,
     return ok();
 }
 
+// Sweeps under a rule other than Metropolis.
+int run_sweeps5(const ising_lattice *lat, const uint64_t T[5], int64_t nsweeps,
+                uint64_t rng_counter, hipStream_t s)
+{
+    const ising::rows::Table5 tab = ising::host::table5(T);
+    for (int64_t sw = 0; sw < nsweeps; ++sw) {
+        for (int c = 0; c < 2; ++c) {
+            const uint64_t t = 2 * (rng_counter + (uint64_t)sw) + (uint64_t)c;
+            hipError_t e = ising::launch_half_sweep5(lat->words, lat->L, c, tab, t, lat->seed,
+                                                     lat->stream_id, s);
+            if (e != hipSuccess)
+                return hip_fail(e, "half-sweep launch");
+        }
+    }
+    return ok();
+}
+
 } // namespace
 
 extern "C" {
@@ -198,6 +239,39 @@ int ising_sweep(const ising_lattice *lat, double beta, double J, int64_t nsweeps
         return fail(ISING_E_BADARG, "nsweeps must be >= 0");
     return run_sweeps(lat, beta, J, nsweeps, rng_counter, nullptr, nullptr,
                       (hipStream_t)hip_stream);
+}
+
+int ising_thresholds_rule(double beta, double J, int rule, uint64_t *T_out)
+{
+    if (!T_out)
+        return fail(ISING_E_BADARG, "null output");
+    if (int e = check_temperature(beta, J))
+        return e;
+    if (rule == ISING_RULE_METROPOLIS)
+        ising::host::threshold_table(beta, J, T_out);
+    else if (rule == ISING_RULE_HEATBATH)
+        ising::host::heatbath_table(beta, J, T_out);
+    else
+        return fail(ISING_E_BADARG, "unknown rule %d", rule);
+    return ok();
+}
+
+int ising_sweep_rule(const ising_lattice *lat, double beta, double J, int rule, int64_t nsweeps,
+                     uint64_t rng_counter, void *hip_stream)
+{
+    if (rule == ISING_RULE_METROPOLIS)
+        return ising_sweep(lat, beta, J, nsweeps, rng_counter, hip_stream);
+    if (rule != ISING_RULE_HEATBATH)
+        return fail(ISING_E_BADARG, "unknown rule %d", rule);
+    if (int e = check_lattice(lat))
+        return e;
+    if (int e = check_temperature(beta, J))
+        return e;
+    if (nsweeps < 0)
+        return fail(ISING_E_BADARG, "nsweeps must be >= 0");
+    uint64_t T[5];
+    ising::host::heatbath_table(beta, J, T);
+    return run_sweeps5(lat, T, nsweeps, rng_counter, (hipStream_t)hip_stream);
 }
 
 int ising_sweep_traced(const ising_lattice *lat, double beta, double J, int64_t nsweeps,

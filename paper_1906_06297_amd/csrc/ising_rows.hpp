@@ -324,6 +324,90 @@ __host__ __device__ __forceinline__ uint64_t decide_word_any(uint64_t t, const N
     return t ^ join(s.tf[0], s.tf[1]);
 }
 
+// ------------------------------------------------------- any 5-entry table
+// Rules other than Metropolis give each class a = 0..4 (neighbours aligned
+// with the spin) its own threshold: heat bath (Sec. 2) draws for every class.
+struct Table5 {
+    uint32_t thr[5]; // T[a] of the classes that draw (0 < T < 2^32)
+    uint32_t always; // bit a: T[a] = 2^32, always flipped
+    uint32_t random; // bit a: 0 < T[a] < 2^32
+};
+
+struct SweepArgs5 {
+    Table5 tab;
+    uint32_t t_lo, t_hi, stream_id, key0, key1;
+};
+
+// One-hot masks e[a] of the number of aligned neighbours (one 32-bit half):
+// a bit-sliced sum of the four "aligned" vectors.
+__host__ __device__ __forceinline__ void count_classes(uint32_t s, uint32_t n0, uint32_t n1,
+                                                       uint32_t n2, uint32_t n3,
+                                                       uint32_t (&e)[5])
+{
+    constexpr uint32_t kAligned = tt(~(kA ^ kB)); // 1 where the two inputs are equal
+    const uint32_t x0 = lop3<kAligned>(s, n0, 0u), x1 = lop3<kAligned>(s, n1, 0u);
+    const uint32_t x2 = lop3<kAligned>(s, n2, 0u), x3 = lop3<kAligned>(s, n3, 0u);
+    const uint32_t s1 = xor3(x0, x1, x2);
+    const uint32_t c1 = lop3<tt((kA & kB) | (kA & kC) | (kB & kC))>(x0, x1, x2); // majority
+    const uint32_t b0 = s1 ^ x3, cy = s1 & x3;
+    const uint32_t b1 = c1 ^ cy, b2 = c1 & cy; // count = 4 b2 + 2 b1 + b0
+    e[4] = b2;
+    e[3] = b1 & b0;
+    e[2] = b1 & ~b0;
+    e[1] = b0 & ~b1;
+    e[0] = lop3<tt(~(kA | kB | kC))>(b0, b1, b2);
+}
+
+// New value of a word of any geometry under table `a.tab`: the same lazy
+// most-significant-plane-first compare r < T[a], with the threshold bit of
+// each spin taken from its class.  The block index is the loop counter, the
+// same in every active lane.
+__host__ __device__ __forceinline__ uint64_t decide_word5(uint64_t t, const Neighbours &nb,
+                                                          uint64_t valid, uint32_t chunk,
+                                                          const SweepArgs5 &a)
+{
+    uint32_t e[2][5], tf[2], p[2];
+#pragma unroll
+    for (int h = 0; h < 2; ++h) {
+        const uint32_t th = h ? hi32(t) : lo32(t);
+        count_classes(th, h ? hi32(nb.up) : lo32(nb.up), h ? hi32(nb.dn) : lo32(nb.dn),
+                      h ? hi32(nb.ce) : lo32(nb.ce), h ? hi32(nb.sd) : lo32(nb.sd), e[h]);
+        uint32_t f = 0, r = 0;
+#pragma unroll
+        for (int c = 0; c < 5; ++c) {
+            f |= ((a.tab.always >> c) & 1u) ? e[h][c] : 0u;
+            r |= ((a.tab.random >> c) & 1u) ? e[h][c] : 0u;
+        }
+        const uint32_t vh = h ? hi32(valid) : lo32(valid);
+        tf[h] = th ^ (f & vh);
+        p[h] = r & vh;
+    }
+    for (uint32_t q = 0; q < 16 && (p[0] | p[1]) != 0; ++q) {
+        const Block x = philox_fast<kCtrUniform>(ctr_word0(a.stream_id, kDomainSweep, q), a.t_lo,
+                                                 a.t_hi, chunk, a.key0, a.key1);
+        const uint32_t planes[2][2] = {{x.x0, x.x1}, {x.x2, x.x3}};
+#pragma unroll
+        for (int k = 0; k < 2; ++k) {
+            const uint32_t bit = 31 - (2 * q + (uint32_t)k);
+            uint32_t m[5];
+#pragma unroll
+            for (int c = 0; c < 5; ++c)
+                m[c] = (((a.tab.random >> c) & (a.tab.thr[c] >> bit)) & 1u) ? ~0u : 0u;
+#pragma unroll
+            for (int h = 0; h < 2; ++h) {
+                uint32_t tb = e[h][0] & m[0];
+#pragma unroll
+                for (int c = 1; c < 5; ++c)
+                    tb = lop3<tt(kA | (kB & kC))>(tb, e[h][c], m[c]);
+                const uint32_t differ = lop3<tt(kA & (kB ^ kC))>(p[h], planes[k][h], tb);
+                tf[h] = lop3<tt(kA ^ (kB & kC))>(tf[h], differ, tb);
+                p[h] ^= differ;
+            }
+        }
+    }
+    return join(tf[0], tf[1]); // undecided after 32 planes: r == T, rejected
+}
+
 // --------------------------------------------------- XCD-aware block order
 // Workgroups are handed to the 8 XCDs of the chip in turn (block b to XCD
 // b % 8).  The logical block of hardware block b gives each XCD a contiguous

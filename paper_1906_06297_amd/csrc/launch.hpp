@@ -4,6 +4,7 @@
 #include <stdint.h>
 
 #include "ising_device.hpp"
+#include "ising_rows.hpp"
 
 namespace ising {
 
@@ -16,6 +17,9 @@ enum { kVariantDefault = 0, kVariantGeneral = 1, kVariantRowsPlain = 2 };
 hipError_t launch_half_sweep(uint64_t *words, int64_t L, int c, const Metro2 &m, uint64_t t,
                              uint64_t seed, uint32_t stream_id, hipStream_t s,
                              int variant = kVariantDefault);
+// Half-sweep under any 5-entry acceptance table (heat bath).
+hipError_t launch_half_sweep5(uint64_t *words, int64_t L, int c, const rows::Table5 &tab,
+                              uint64_t t, uint64_t seed, uint32_t stream_id, hipStream_t s);
 hipError_t launch_observables(const uint64_t *words, int64_t L, int64_t *bond, int64_t *mag,
                               hipStream_t s);
 

@@ -329,6 +329,73 @@ __global__ __launch_bounds__(256) void k_sweep_rows_q(uint64_t *__restrict__ tgt
 }
 
 
+// ------------------------------------------- any 5-entry table (heat bath)
+// The other local rule of Sec. 2: every class may draw, so the decision is
+// decide_word5(); the geometry is handled as in the Metropolis kernels.
+__global__ __launch_bounds__(256) void k_sweep_general5(uint64_t *__restrict__ tgt,
+                                                        const uint64_t *__restrict__ src, int64_t H,
+                                                        int64_t M, int64_t W, int c,
+                                                        rows::SweepArgs5 a)
+{
+    const int64_t chunk = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (chunk >= W)
+        return;
+    const Neighbours nb = neighbours_general(src, H, M, W, chunk, c);
+    tgt[chunk] = rows::decide_word5(tgt[chunk], nb, valid_mask(chunk, M), (uint32_t)chunk, a);
+}
+
+// Row-aligned lattices: one thread per word column of a band of kRows rows,
+// three source rows in registers (as k_sweep_rows).
+__global__ __launch_bounds__(256) void k_sweep_rows5(uint64_t *__restrict__ tgt,
+                                                     const uint64_t *__restrict__ src, int64_t L,
+                                                     int64_t Wr, int64_t blocks_per_band, int c,
+                                                     rows::SweepArgs5 a)
+{
+    const int64_t band = blockIdx.x / blocks_per_band;
+    const int64_t w = (blockIdx.x - band * blocks_per_band) * (int64_t)blockDim.x + threadIdx.x;
+    if (w >= Wr)
+        return;
+    const int64_t i0 = band * kRows;
+    const int64_t wl = (w == 0) ? Wr - 1 : w - 1;
+    const int64_t wr = (w == Wr - 1) ? 0 : w + 1;
+    uint64_t prev = src[((i0 == 0) ? L - 1 : i0 - 1) * Wr + w];
+    uint64_t cur = src[i0 * Wr + w];
+    for (int r = 0; r < kRows; ++r) {
+        const int64_t i = i0 + r;
+        if (i >= L)
+            break;
+        const uint64_t next = src[((i + 1 == L) ? 0 : i + 1) * Wr + w];
+        const int64_t idx = i * Wr + w;
+        const bool left = ((i + c) & 1) == 0;
+        const Neighbours nb{prev, next, cur, side_vector(cur, src[i * Wr + (left ? wl : wr)], left)};
+        tgt[idx] = rows::decide_word5(tgt[idx], nb, ~0ull, (uint32_t)idx, a);
+        prev = cur;
+        cur = next;
+    }
+}
+
+hipError_t launch_half_sweep5(uint64_t *words, int64_t L, int c, const rows::Table5 &tab,
+                              uint64_t t, uint64_t seed, uint32_t stream_id, hipStream_t s)
+{
+    const int64_t H = L / 2, M = L * L / 2, W = (M + 63) / 64;
+    uint64_t *tgt = words + (int64_t)c * W;
+    const uint64_t *src = words + (int64_t)(1 - c) * W;
+    const rows::SweepArgs5 a{tab, (uint32_t)t, (uint32_t)(t >> 32), stream_id, (uint32_t)seed,
+                             (uint32_t)(seed >> 32)};
+    if (L % 128 == 0) {
+        const int64_t Wr = L / 128;
+        const int threads = Wr >= 256 ? 256 : (Wr >= 64 ? 64 * (int)((Wr + 63) / 64) : 64);
+        const int64_t bpb = (Wr + threads - 1) / threads;
+        const int64_t bands = (L + kRows - 1) / kRows;
+        hipLaunchKernelGGL(k_sweep_rows5, dim3((uint32_t)(bands * bpb)), dim3(threads), 0, s, tgt,
+                           src, L, Wr, bpb, c, a);
+    } else {
+        hipLaunchKernelGGL(k_sweep_general5, dim3((uint32_t)((W + 255) / 256)), dim3(256), 0, s,
+                           tgt, src, H, M, W, c, a);
+    }
+    return hipGetLastError();
+}
+
 // --------------------------------------------------------------- observables
 __global__ __launch_bounds__(256) void k_fill_i64(int64_t *__restrict__ p, int64_t n, int64_t v)
 {

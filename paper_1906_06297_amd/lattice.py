@@ -21,9 +21,12 @@ def words_per_colour(L: int) -> int:
     return int(w)
 
 
-def thresholds(beta: float, J: float) -> np.ndarray:
+RULES = {"metropolis": 0, "heatbath": 1}  # ISING_RULE_*
+
+
+def thresholds(beta: float, J: float, rule: str = "metropolis") -> np.ndarray:
     T = (ctypes.c_uint64 * 5)()
-    _lib.check(_lib.load().ising_thresholds(float(beta), float(J), T))
+    _lib.check(_lib.load().ising_thresholds_rule(float(beta), float(J), RULES[rule], T))
     return np.array(list(T), dtype=np.uint64)
 
 
@@ -85,9 +88,11 @@ class Lattice:
         return int(self.desc.stream_id)
 
     def sweep(self, beta: float, J: float = 1.0, nsweeps: int = 1, rng_counter: int = 0,
-              stream=None) -> None:
-        _lib.check(_lib.load().ising_sweep(ctypes.byref(self.desc), float(beta), float(J),
-                                           int(nsweeps), int(rng_counter), _stream_handle(stream)))
+              stream=None, rule: str = "metropolis") -> None:
+        """nsweeps checkerboard sweeps under the Metropolis or heat-bath rule."""
+        _lib.check(_lib.load().ising_sweep_rule(ctypes.byref(self.desc), float(beta), float(J),
+                                                RULES[rule], int(nsweeps), int(rng_counter),
+                                                _stream_handle(stream)))
 
     def sweep_traced(self, beta: float, J: float = 1.0, nsweeps: int = 1, rng_counter: int = 0,
                      bond=None, mag=None, stream=None):

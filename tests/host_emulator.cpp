@@ -116,6 +116,44 @@ void emu_half_sweep(uint64_t *words, int64_t L, int c, const uint64_t *T, int an
         }
 }
 
+// The heat-bath kernels' word decision (decide_word5) under table T, with
+// the general kernel's neighbour extraction (rows = 0) or the row kernel's
+// (rows = 1, L % 128 == 0).
+void emu_half_sweep5(uint64_t *words, int64_t L, int c, const uint64_t *T, uint64_t t,
+                     uint64_t seed, uint32_t stream, int rows5)
+{
+    const int64_t H = L / 2, M = L * L / 2, W = (M + 63) / 64;
+    uint64_t *tgt = words + c * W;
+    const uint64_t *src = words + (1 - c) * W;
+    rows::Table5 tab{};
+    for (int a = 0; a < 5; ++a) {
+        if (T[a] >= (1ull << 32))
+            tab.always |= 1u << a;
+        else if (T[a] > 0) {
+            tab.random |= 1u << a;
+            tab.thr[a] = (uint32_t)T[a];
+        }
+    }
+    const rows::SweepArgs5 a{tab, (uint32_t)t, (uint32_t)(t >> 32), stream, (uint32_t)seed,
+                             (uint32_t)(seed >> 32)};
+    if (!rows5) {
+        for (int64_t k = 0; k < W; ++k)
+            tgt[k] = rows::decide_word5(tgt[k], neighbours_general(src, H, M, W, k, c),
+                                        valid_mask(k, M), (uint32_t)k, a);
+        return;
+    }
+    const int64_t Wr = L / 128;
+    for (int64_t i = 0; i < L; ++i)
+        for (int64_t w = 0; w < Wr; ++w) {
+            const bool left = ((i + c) & 1) == 0;
+            const int64_t adjw = left ? (w == 0 ? Wr - 1 : w - 1) : (w == Wr - 1 ? 0 : w + 1);
+            const int64_t idx = i * Wr + w;
+            const Neighbours nb{src[((i + L - 1) % L) * Wr + w], src[((i + 1) % L) * Wr + w],
+                                src[idx], side_vector(src[idx], src[i * Wr + adjw], left)};
+            tgt[idx] = rows::decide_word5(tgt[idx], nb, ~0ull, (uint32_t)idx, a);
+        }
+}
+
 // The persistent batch kernel's per-lattice sequence: extended colour arrays
 // refreshed after every half-sweep, neighbours by funnel shifts.
 void emu_batch_lattice(uint64_t *words, int64_t L, double beta, double J, uint64_t seed,

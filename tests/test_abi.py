@@ -56,6 +56,28 @@ def test_thresholds_match_oracle(lib, orc):
             assert np.array_equal(thresholds(beta, J), orc.thresholds(beta, J)), (beta, J)
 
 
+def test_heatbath_thresholds_match_oracle(lib, orc):
+    from paper_1906_06297_amd import thresholds
+
+    for J in (1.0, -1.0, 0.5, 0.0):
+        for beta in [0.0, 0.3, workloads.BETA_CRIT_CONFIG, 0.5, 7.0, 300.0] + list(np.linspace(0.3, 0.6, 32)):
+            assert np.array_equal(thresholds(beta, J, "heatbath"), orc.thresholds(beta, J, "heatbath")), (beta, J)
+
+
+def test_rule_argument_errors(lib):
+    from paper_1906_06297_amd import _lib
+
+    T = (ctypes.c_uint64 * 5)()
+    assert lib.ising_thresholds_rule(0.4, 1.0, 2, T) == _lib.ISING_E_BADARG
+    assert b"rule" in lib.ising_last_error()
+    assert lib.ising_thresholds_rule(-0.1, 1.0, 1, T) == _lib.ISING_E_BADARG
+    assert lib.ising_thresholds_rule(0.4, 1.0, 1, None) == _lib.ISING_E_BADARG
+    good = _lib.LatticeStruct(words=0x1000, L=8, seed=1, stream_id=0)
+    assert lib.ising_sweep_rule(ctypes.byref(good), 0.4, 1.0, 7, 1, 0, None) == _lib.ISING_E_BADARG
+    assert lib.ising_sweep_rule(ctypes.byref(good), 0.4, 1.0, 1, -1, 0, None) == _lib.ISING_E_BADARG
+    assert lib.ising_thresholds_rule(0.4, 1.0, 1, T) == _lib.ISING_OK
+
+
 def test_argument_errors_without_device(lib):
     from paper_1906_06297_amd import _lib
 

@@ -29,6 +29,8 @@ def emu(tmp_path_factory):
     lib.emu_init.argtypes = [u64p, ctypes.c_int64, ctypes.c_uint64, ctypes.c_uint32]
     lib.emu_half_sweep.argtypes = [u64p, ctypes.c_int64, ctypes.c_int, u64p, ctypes.c_int,
                                    ctypes.c_uint64, ctypes.c_uint64, ctypes.c_uint32, ctypes.c_int]
+    lib.emu_half_sweep5.argtypes = [u64p, ctypes.c_int64, ctypes.c_int, u64p, ctypes.c_uint64,
+                                    ctypes.c_uint64, ctypes.c_uint32, ctypes.c_int]
     lib.emu_xcd_block.argtypes = [ctypes.c_uint32, ctypes.c_uint32]
     lib.emu_xcd_block.restype = ctypes.c_uint32
     lib.emu_philox_fast.argtypes = [ctypes.c_uint32] * 6 + [ctypes.c_int,
@@ -126,3 +128,21 @@ def test_xcd_block_order_is_a_permutation(emu, n):
     for x in range(min(n, 8)):
         mine = np.sort(got[x::8])
         assert np.all(np.diff(mine) == 1)
+
+
+@pytest.mark.parametrize("L,rows5", [(4, 0), (6, 0), (10, 0), (24, 0), (64, 0), (100, 0),
+                                     (128, 0), (128, 1), (256, 1)])
+@pytest.mark.parametrize("beta,J", [(0.0, 1.0), (workloads.BETA_CRIT_CONFIG, 1.0), (0.3, -1.0),
+                                    (3.0, 1.0), (300.0, 1.0)])
+def test_heatbath_kernel_logic(emu, orc, L, rows5, beta, J):
+    """The heat-bath word decision (five classes) against the oracle's heat-bath sweeps."""
+    seed, stream, n, ctr = 55 + L, 3, 3, 4
+    ref = orc.init(L, seed, stream)
+    W = (L * L // 2 + 63) // 64
+    words = np.ascontiguousarray(pack(ref).reshape(-1))
+    T = np.ascontiguousarray(orc.thresholds(beta, J, "heatbath"), dtype=np.uint64)
+    for s in range(n):
+        for c in (0, 1):
+            emu.emu_half_sweep5(_p(words), L, c, _p(T), 2 * (ctr + s) + c, seed, stream, rows5)
+    orc.sweeps(ref, beta, J, seed, stream, n, ctr, rule="heatbath")
+    assert np.array_equal(words.reshape(2, W), pack(ref))
