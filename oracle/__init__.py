@@ -8,7 +8,8 @@ Contents
   - ``ising_oracle.c``   plain C/OpenMP: Philox4x32-10, the threshold tables
                          (Metropolis and heat bath, Sec. 2), int8 lattice
                          init, half-sweep, sweeps, observables (paper Sec. 2,
-                         Sec. 3.1, Fig. 2; Eq. (1)).
+                         Sec. 3.1, Fig. 2; Eq. (1)); the +-J spin glass named
+                         in the conclusions.
   - ``exact.py``         exact results: enumeration, transfer matrix,
                          Kaufman's finite-lattice solution, Onsager, Eq. (7).
   - ``stats.py``         blocking standard errors and integrated
@@ -67,6 +68,10 @@ def lib():
         "orc_site_uniform": (c_u32, [c_u64, c_u32, c_u64, c_i64]),
         "orc_thresholds": (None, [c_dbl, c_dbl, u64p]),
         "orc_thresholds_heatbath": (None, [c_dbl, c_dbl, u64p]),
+        "orc_glass_sweeps": (None, [i8p, i8p, i8p, c_i64, c_dbl, c_dbl, c_u64, c_u32, c_i64, c_u64,
+                                    i64p, i64p]),
+        "orc_glass_observables": (None, [i8p, i8p, i8p, c_i64, i64p, i64p]),
+        "orc_glass_couplings": (None, [i8p, i8p, c_i64, c_u64, c_u32]),
         "orc_sweeps_table": (None, [i8p, c_i64, u64p, c_u64, c_u32, c_i64, c_u64, i64p, i64p]),
         "orc_init": (None, [i8p, c_i64, c_u64, c_u32]),
         "orc_half_sweep": (None, [i8p, c_i64, c_int, u64p, c_u64, c_u32, c_u64]),
@@ -168,6 +173,48 @@ def sweeps(s: np.ndarray, beta: float, J: float, seed: int, stream: int, nsweeps
     if trace:
         return bt, mt
     return None
+
+
+def glass_sweeps(s: np.ndarray, Jr: np.ndarray, Jd: np.ndarray, beta: float, J: float, seed: int,
+                 stream: int, nsweeps: int, rng_counter: int = 0, trace: bool = False):
+    """+-J spin glass: in-place sweeps with bond signs Jr (to the right) and Jd
+    (downwards), int8 +1/-1 arrays of the lattice's shape."""
+    L = s.shape[0]
+    _check_L(L)
+    Jr = np.ascontiguousarray(Jr, dtype=np.int8)
+    Jd = np.ascontiguousarray(Jd, dtype=np.int8)
+    assert s.dtype == np.int8 and Jr.shape == Jd.shape == s.shape == (L, L)
+    if trace:
+        bt = np.zeros(nsweeps, dtype=np.int64)
+        mt = np.zeros(nsweeps, dtype=np.int64)
+        bp, mp = _ptr(bt, ctypes.c_int64), _ptr(mt, ctypes.c_int64)
+    else:
+        bp = mp = None
+    lib().orc_glass_sweeps(_ptr(s, ctypes.c_int8), _ptr(Jr, ctypes.c_int8), _ptr(Jd, ctypes.c_int8),
+                           L, float(beta), float(J), seed, stream, nsweeps, rng_counter, bp, mp)
+    if trace:
+        return bt, mt
+    return None
+
+
+def glass_couplings(L: int, seed: int, stream: int = 0) -> tuple:
+    """Random bond signs (Jr, Jd) of the +-J glass from Philox domain 4."""
+    _check_L(L)
+    Jr = np.zeros((L, L), dtype=np.int8)
+    Jd = np.zeros((L, L), dtype=np.int8)
+    lib().orc_glass_couplings(_ptr(Jr, ctypes.c_int8), _ptr(Jd, ctypes.c_int8), L, seed, stream)
+    return Jr, Jd
+
+
+def glass_observables(s: np.ndarray, Jr: np.ndarray, Jd: np.ndarray) -> tuple:
+    """(bond sum with the bond signs, M)."""
+    L = s.shape[0]
+    b, m = ctypes.c_int64(), ctypes.c_int64()
+    lib().orc_glass_observables(_ptr(np.ascontiguousarray(s), ctypes.c_int8),
+                                _ptr(np.ascontiguousarray(Jr, dtype=np.int8), ctypes.c_int8),
+                                _ptr(np.ascontiguousarray(Jd, dtype=np.int8), ctypes.c_int8), L,
+                                ctypes.byref(b), ctypes.byref(m))
+    return int(b.value), int(m.value)
 
 
 def observables(s: np.ndarray) -> tuple:

@@ -23,6 +23,9 @@
  *    change from flipping sigma with neighbour sum nn is dE = 2*J*sigma*nn,
  *    as in the update kernels of Fig. 2.
  *  - dE = 0 is accepted (exp(0) = 1 exceeds any uniform in [0,1)).
+ *  - +-J spin glass (the extension the conclusions name): couplings
+ *    J * Jr, J * Jd with bond signs +1/-1 from Philox domain 4, one draw per
+ *    bond; the field h replaces the neighbour sum in a = (4 + sigma h) / 2.
  *  - Heat bath (Sec. 2, the other local rule named there): the flip
  *    probability e^{-beta dE} / (e^{-beta dE} + 1) is evaluated as
  *    1 / (1 + e^{beta dE}) (no intermediate overflow) and quantised the same
@@ -84,7 +87,7 @@ void orc_philox4x32_10(const uint32_t *ctr, const uint32_t *key, uint32_t *out)
     out[0] = x0; out[1] = x1; out[2] = x2; out[3] = x3;
 }
 
-enum { ORC_DOMAIN_SWEEP = 0, ORC_DOMAIN_INIT = 1 };
+enum { ORC_DOMAIN_SWEEP = 0, ORC_DOMAIN_INIT = 1, ORC_DOMAIN_COUPLINGS = 4 };
 
 /* One Philox block at the canonical address. */
 static void orc_block(uint64_t seed, uint32_t stream, uint32_t domain, uint32_t q,
@@ -307,6 +310,108 @@ void orc_sweeps_table(int8_t *s, int64_t L, const uint64_t *T, uint64_t seed, ui
                       int64_t *mag_trace)
 {
     orc_sweeps_table_impl(s, L, T, seed, stream, nsweeps, rng_counter, bond_trace, mag_trace, 1);
+}
+
+/* ------------------------------------------------------------------------ */
+/* +-J spin glass (the extension named in the paper's conclusions): bond     */
+/* couplings J * Jr[i][j] between (i,j) and (i,j+1) and J * Jd[i][j] between */
+/* (i,j) and (i+1,j), Jr, Jd = +1/-1.  The local field is h = sum over the   */
+/* four bonds of the bond sign times the neighbour, dE = 2 J sigma h, and     */
+/* a = (4 + sigma h) / 2 takes the Metropolis table of (beta, J) as before.   */
+/* ------------------------------------------------------------------------ */
+static inline int orc_glass_field(const int8_t *s, const int8_t *Jr, const int8_t *Jd,
+                                  int64_t L, int64_t i, int64_t j)
+{
+    int64_t up = orc_wrap(i - 1, L), down = orc_wrap(i + 1, L);
+    int64_t left = orc_wrap(j - 1, L), right = orc_wrap(j + 1, L);
+    return Jd[up * L + j] * s[up * L + j] + Jd[i * L + j] * s[down * L + j] +
+           Jr[i * L + left] * s[i * L + left] + Jr[i * L + j] * s[i * L + right];
+}
+
+static void orc_glass_half_sweep(int8_t *s, const int8_t *Jr, const int8_t *Jd, int64_t L,
+                                 int c, const uint64_t *T, uint64_t seed, uint32_t stream,
+                                 uint64_t t)
+{
+    int64_t H = L / 2, M = L * L / 2;
+    int64_t nchunks = (M + 63) / 64;
+#pragma omp parallel for schedule(static)
+    for (int64_t k = 0; k < nchunks; ++k) {
+        uint64_t planes[32];
+        orc_planes(seed, stream, t, (uint64_t)k, planes);
+        for (int b = 0; b < 64; ++b) {
+            int64_t n = 64 * k + b;
+            if (n >= M)
+                break;
+            int64_t i = n / H, jc = n % H;
+            int64_t j = 2 * jc + ((i + c) & 1);
+            int8_t sigma = s[i * L + j];
+            int h = orc_glass_field(s, Jr, Jd, L, i, j);
+            s[i * L + j] = orc_site_update(sigma, h, orc_r_from_planes(planes, b), T);
+        }
+    }
+}
+
+/* Random bond signs (probability 1/2 each), one Philox block per 64 bonds:
+ * the bond to the right (array x = c) and the bond below (x = 2 + c) of the
+ * colour-c site at colour-linear index n take bit n & 63 of x0 | x1 << 32 of
+ * block (stream << 8 | 4 << 4 | x, 0, 0, n >> 6); bit 1 means -1. */
+void orc_glass_couplings(int8_t *Jr, int8_t *Jd, int64_t L, uint64_t seed, uint32_t stream)
+{
+    int64_t H = L / 2, M = L * L / 2;
+    int64_t nchunks = (M + 63) / 64;
+    for (uint32_t x = 0; x < 4; ++x) {
+        int c = (int)(x & 1);
+        int8_t *dst = x < 2 ? Jr : Jd;
+#pragma omp parallel for schedule(static)
+        for (int64_t k = 0; k < nchunks; ++k) {
+            uint32_t w[4];
+            orc_block(seed, stream, ORC_DOMAIN_COUPLINGS, x, 0, (uint64_t)k, w);
+            uint64_t bits = (uint64_t)w[0] | ((uint64_t)w[1] << 32);
+            for (int b = 0; b < 64; ++b) {
+                int64_t n = 64 * k + b;
+                if (n >= M)
+                    break;
+                int64_t i = n / H, jc = n % H;
+                int64_t j = 2 * jc + ((i + c) & 1);
+                dst[i * L + j] = ((bits >> b) & 1u) ? -1 : 1;
+            }
+        }
+    }
+}
+
+/* Bond sum sum_<ij> J_ij/J sigma_i sigma_j (energy E = -J * bond) and M. */
+void orc_glass_observables(const int8_t *s, const int8_t *Jr, const int8_t *Jd, int64_t L,
+                           int64_t *bond, int64_t *mag)
+{
+    int64_t b = 0, m = 0;
+#pragma omp parallel for reduction(+ : b, m) schedule(static)
+    for (int64_t i = 0; i < L; ++i) {
+        int64_t down = orc_wrap(i + 1, L);
+        for (int64_t j = 0; j < L; ++j) {
+            int64_t right = orc_wrap(j + 1, L);
+            int sigma = s[i * L + j];
+            b += sigma * (Jd[i * L + j] * s[down * L + j] + Jr[i * L + j] * s[i * L + right]);
+            m += sigma;
+        }
+    }
+    *bond = b;
+    *mag = m;
+}
+
+void orc_glass_sweeps(int8_t *s, const int8_t *Jr, const int8_t *Jd, int64_t L, double beta,
+                      double J, uint64_t seed, uint32_t stream, int64_t nsweeps,
+                      uint64_t rng_counter, int64_t *bond_trace, int64_t *mag_trace)
+{
+    uint64_t T[5];
+    orc_thresholds(beta, J, T);
+    for (int64_t sw = 0; sw < nsweeps; ++sw) {
+        for (int c = 0; c < 2; ++c) {
+            uint64_t t = 2 * (rng_counter + (uint64_t)sw) + (uint64_t)c;
+            orc_glass_half_sweep(s, Jr, Jd, L, c, T, seed, stream, t);
+        }
+        if (bond_trace && mag_trace)
+            orc_glass_observables(s, Jr, Jd, L, &bond_trace[sw], &mag_trace[sw]);
+    }
 }
 
 /* Many independent lattices, one per thread at a time.  Lattice q occupies

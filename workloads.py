@@ -48,3 +48,9 @@ def random_spins(L: int, seed: int, p_up: float = 0.5) -> np.ndarray:
     """An L x L int8 lattice of +1/-1 spins, +1 with probability p_up."""
     rng = np.random.default_rng(seed)
     return np.where(rng.random((L, L)) < p_up, 1, -1).astype(np.int8)
+
+
+# +-J spin glass on the headline lattices: bond signs drawn with probability
+# 1/2 from their own Philox key (coupling_seed), the spins as in the headline.
+GLASS = dict(name="glass", L=65536, J=1.0, betas=(0.40, BETA_CRIT_CONFIG, 0.50), seed=7, stream=0,
+             coupling_seed=11)
