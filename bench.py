@@ -238,6 +238,44 @@ def bench_heatbath(ising, torch, bufs, steps: int) -> dict:
     }
 
 
+def bench_glass(ising, torch, bufs, steps: int) -> dict:
+    """+-J spin glass on the headline lattices: random bond signs (probability
+    1/2, their own Philox key), same spins, betas and start as the headline."""
+    cfg = workloads.GLASS
+    L, betas, seed, J = cfg["L"], cfg["betas"], cfg["seed"], cfg["J"]
+    bonds = ising.GlassBonds(L, seed=cfg["coupling_seed"], stream_id=0)
+    lats = [ising.Lattice(L, seed, words=b) for b in bufs]
+    for lat, beta in zip(lats, betas):
+        lat.glass_sweep(bonds, beta, J, 1, 0)
+    lats = [ising.Lattice(L, seed, words=b) for b in bufs]
+    torch.cuda.synchronize()
+    per_beta, t_all = {}, 0.0
+    for lat, beta in zip(lats, betas):
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record()
+        lat.glass_sweep(bonds, beta, J, steps, 0)
+        e1.record()
+        torch.cuda.synchronize()
+        ms = e0.elapsed_time(e1)
+        t_all += ms
+        bond, _ = lat.glass_observables(bonds)
+        per_beta[str(beta)] = {"flips_per_ns": steps * L * L / (ms * 1e6),
+                               "E_per_site": -J * bond / (L * L)}
+    half_us = t_all * 1e3 / (2 * steps * len(betas))
+    alg = 7 * (L * L // 2) // 8  # target read + write, source read, four bond bits per update
+    del bonds
+    return {
+        "workload": f"+-J spin glass, L={L}, J={J}, bond signs -1 with probability 1/2 (Philox "
+                    f"domain 4, seed {cfg['coupling_seed']}), beta in {list(betas)}, spins seed {seed}, "
+                    f"{steps} sweeps per beta from a fresh start",
+        "flips_per_ns": len(betas) * steps * L * L / (t_all * 1e6),
+        "avg_half_sweep_us": half_us,
+        "alg_bytes_per_launch": alg,
+        "hbm_frac": alg / (half_us * 1e-6) / 1e9 / HBM_PEAK_GBS,
+        "per_beta": per_beta,
+    }
+
+
 def bench_learned(ising, torch, L: int = 32, betas=(0.42, 0.44, 0.46), C: int = 32,
                   chains: int = 4096, rounds: int = 400, train_steps: int = 1500,
                   data_log2: int = 20) -> dict:
@@ -315,6 +353,8 @@ def main() -> int:
     ap.add_argument("--heatbath-sweeps", type=int, default=20,
                     help="sweeps per beta of the heat-bath rule on the headline lattices, reported "
                          "beside the headline (0 = skip)")
+    ap.add_argument("--glass-sweeps", type=int, default=20,
+                    help="sweeps per beta of the +-J spin glass on the headline lattices (0 = skip)")
     ap.add_argument("--hold-seconds", type=float, default=0.0,
                     help="only run L = 65536 sweeps at beta_c for this many seconds (for reading "
                          "clocks and power beside a steady load) and exit")
@@ -425,6 +465,8 @@ def main() -> int:
     }
     if args.heatbath_sweeps > 0:
         out["heatbath"] = bench_heatbath(ising, torch, bufs, args.heatbath_sweeps)
+    if args.glass_sweeps > 0:
+        out["glass"] = bench_glass(ising, torch, bufs, args.glass_sweeps)
     if args.batched_sweeps > 0:
         out["batched"] = bench_batched(ising, torch, args.batched_sweeps)
     if args.learned_rounds > 0:

@@ -116,6 +116,40 @@ int ising_sweep_traced(const ising_lattice *lat, double beta, double J, int64_t 
 int ising_observables(const ising_lattice *lat, int64_t *d_bond, int64_t *d_mag,
                       void *hip_stream);
 
+/* +-J spin glass (the extension named in the paper's conclusions): couplings
+ * J_ij = J * (1 - 2 b_ij) with one sign bit b_ij per bond.  The bond array
+ * (device, caller-owned, 4 * ising_words_per_colour(L) uint64 words) holds
+ * four bit arrays in the colour-compact layout of the spins: the bond to the
+ * right of every colour-0 site, of every colour-1 site, then the bond below
+ * every colour-0 site, every colour-1 site; padding bits 0.  Only row-aligned
+ * sizes (L % 128 == 0; ISING_E_SIZE otherwise).  Every call takes the array's
+ * size in bytes and returns ISING_E_SIZE if it is too small.
+ *
+ * Random signs, each -1 with probability 1/2: bit n of array x is bit n & 63
+ * of x0 | x1 << 32 of Philox4x32-10 block (stream_id << 8 | 4 << 4 | x, 0, 0,
+ * n >> 6) under key seed.  Asynchronous. */
+int ising_glass_bonds_init(uint64_t *d_bonds, size_t bytes, int64_t L, uint64_t seed,
+                           uint32_t stream_id, void *hip_stream);
+
+/* Bond array from host L x L int8 arrays of +1/-1: host_right[i*L + j] on the
+ * bond (i, j)-(i, j+1), host_down[i*L + j] on (i, j)-(i+1, j), periodic.
+ * ISING_E_BADARG for other values.  Synchronises hip_stream. */
+int ising_glass_set_bonds(uint64_t *d_bonds, size_t bytes, int64_t L, const int8_t *host_right,
+                          const int8_t *host_down, void *hip_stream);
+
+/* As ising_sweep with the couplings of d_bonds: the Metropolis rule of Sec. 2
+ * with dE = 2 J sigma h, h the sum over the four bonds of sign times neighbour.
+ * Same counters and planes as ising_sweep (all-ferromagnetic bonds give
+ * ising_sweep's lattice).  Asynchronous. */
+int ising_glass_sweep(const ising_lattice *lat, const uint64_t *d_bonds, size_t bond_bytes,
+                      double beta, double J, int64_t nsweeps, uint64_t rng_counter,
+                      void *hip_stream);
+
+/* Bond sum sum over bonds of (J_ij / J) sigma_i sigma_j (energy E = -J * that)
+ * and magnetisation to the device int64 pointers.  Asynchronous. */
+int ising_glass_observables(const ising_lattice *lat, const uint64_t *d_bonds, size_t bond_bytes,
+                            int64_t *d_bond, int64_t *d_mag, void *hip_stream);
+
 /* Copies the lattice to host_spins as an L x L row-major int8 array of
  * +1/-1.  Synchronises hip_stream. */
 int ising_get_spins(const ising_lattice *lat, int8_t *host_spins, void *hip_stream);

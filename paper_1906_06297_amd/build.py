@@ -9,7 +9,7 @@ import sys
 HERE = os.path.dirname(os.path.abspath(__file__))
 CSRC = os.path.join(HERE, "csrc")
 LIB_PATH = os.path.join(HERE, "libising.so")
-SOURCES = ["sweep_kernels.hip", "capi.hip", "batch_kernels.hip", "batch_capi.hip",
+SOURCES = ["sweep_kernels.hip", "capi.hip", "glass_kernels.hip", "batch_kernels.hip", "batch_capi.hip",
            "arnet_kernels.hip", "arnet_capi.hip"]
 
 HIPCC_FLAGS = [

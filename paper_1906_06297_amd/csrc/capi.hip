@@ -10,6 +10,7 @@
 #include <vector>
 
 #include "../../include/ising.h"
+#include "glass.hpp"
 #include "host_common.hpp"
 #include "launch.hpp"
 
@@ -357,6 +358,120 @@ int ising_set_spins(const ising_lattice *lat, const int8_t *host_spins, void *hi
     if (e != hipSuccess)
         return hip_fail(e, "copy to device");
     return ok();
+}
+
+// ------------------------------------------------------------ +-J spin glass
+namespace {
+
+int check_glass(int64_t L)
+{
+    if (int e = check_L(L))
+        return e;
+    if (L % 128 != 0)
+        return fail(ISING_E_SIZE, "the spin-glass sweep needs L %% 128 == 0 (L = %lld)",
+                    (long long)L);
+    return ISING_OK;
+}
+
+int check_bonds(const void *d_bonds, size_t bytes, int64_t L)
+{
+    if (!d_bonds)
+        return fail(ISING_E_BADARG, "null bond array");
+    if (bytes < (size_t)(4 * words_per_colour(L)) * sizeof(uint64_t))
+        return fail(ISING_E_SIZE, "bond array needs %lld bytes",
+                    (long long)(4 * words_per_colour(L) * 8));
+    return ISING_OK;
+}
+
+} // namespace
+
+int ising_glass_bonds_init(uint64_t *d_bonds, size_t bytes, int64_t L, uint64_t seed,
+                           uint32_t stream_id, void *hip_stream)
+{
+    if (int e = check_glass(L))
+        return e;
+    if (int e = check_bonds(d_bonds, bytes, L))
+        return e;
+    if (stream_id >= (1u << 24))
+        return fail(ISING_E_BADARG, "stream_id must be < 2^24");
+    hipError_t e = ising::launch_glass_bonds_init(d_bonds, L, seed, stream_id,
+                                                  (hipStream_t)hip_stream);
+    return e == hipSuccess ? ok() : hip_fail(e, "bond init launch");
+}
+
+int ising_glass_set_bonds(uint64_t *d_bonds, size_t bytes, int64_t L, const int8_t *host_right,
+                          const int8_t *host_down, void *hip_stream)
+{
+    if (int e = check_glass(L))
+        return e;
+    if (int e = check_bonds(d_bonds, bytes, L))
+        return e;
+    if (!host_right || !host_down)
+        return fail(ISING_E_BADARG, "null host bond array");
+    const int64_t H = L / 2, W = words_per_colour(L);
+    std::vector<uint64_t> w((size_t)(4 * W), 0);
+    for (int64_t i = 0; i < L; ++i)
+        for (int64_t j = 0; j < L; ++j) {
+            const int8_t r = host_right[i * L + j], d = host_down[i * L + j];
+            if ((r != 1 && r != -1) || (d != 1 && d != -1))
+                return fail(ISING_E_BADARG, "bond at (%lld, %lld) is not +1/-1", (long long)i,
+                            (long long)j);
+            const int c = (int)((i + j) & 1);
+            const int64_t n = i * H + (j >> 1);
+            if (r < 0)
+                w[(size_t)(c * W + (n >> 6))] |= 1ull << (n & 63);
+            if (d < 0)
+                w[(size_t)((2 + c) * W + (n >> 6))] |= 1ull << (n & 63);
+        }
+    hipStream_t s = (hipStream_t)hip_stream;
+    hipError_t e = hipMemcpyAsync(d_bonds, w.data(), w.size() * sizeof(uint64_t),
+                                  hipMemcpyHostToDevice, s);
+    if (e == hipSuccess)
+        e = hipStreamSynchronize(s);
+    return e == hipSuccess ? ok() : hip_fail(e, "copy to device");
+}
+
+int ising_glass_sweep(const ising_lattice *lat, const uint64_t *d_bonds, size_t bond_bytes,
+                      double beta, double J, int64_t nsweeps, uint64_t rng_counter,
+                      void *hip_stream)
+{
+    if (int e = check_lattice(lat))
+        return e;
+    if (int e = check_glass(lat->L))
+        return e;
+    if (int e = check_bonds(d_bonds, bond_bytes, lat->L))
+        return e;
+    if (int e = check_temperature(beta, J))
+        return e;
+    if (nsweeps < 0)
+        return fail(ISING_E_BADARG, "nsweeps must be >= 0");
+    const ising::Metro2 m = ising::host::metro2_params(beta, J);
+    hipStream_t s = (hipStream_t)hip_stream;
+    for (int64_t sw = 0; sw < nsweeps; ++sw)
+        for (int c = 0; c < 2; ++c) {
+            const uint64_t t = 2 * (rng_counter + (uint64_t)sw) + (uint64_t)c;
+            hipError_t e = ising::launch_glass_half_sweep(lat->words, d_bonds, lat->L, c, m, t,
+                                                          lat->seed, lat->stream_id, s);
+            if (e != hipSuccess)
+                return hip_fail(e, "half-sweep launch");
+        }
+    return ok();
+}
+
+int ising_glass_observables(const ising_lattice *lat, const uint64_t *d_bonds, size_t bond_bytes,
+                            int64_t *d_bond, int64_t *d_mag, void *hip_stream)
+{
+    if (int e = check_lattice(lat))
+        return e;
+    if (int e = check_glass(lat->L))
+        return e;
+    if (int e = check_bonds(d_bonds, bond_bytes, lat->L))
+        return e;
+    if (!d_bond || !d_mag)
+        return fail(ISING_E_BADARG, "null pointer");
+    hipError_t e = ising::launch_glass_observables(lat->words, d_bonds, lat->L, d_bond, d_mag,
+                                                   (hipStream_t)hip_stream);
+    return e == hipSuccess ? ok() : hip_fail(e, "observables launch");
 }
 
 int ising_set_sweep_kernel(int variant)

@@ -122,6 +122,24 @@ class Lattice:
         b, m = out.cpu().tolist()
         return int(b), int(m)
 
+    # ------------------------------------------------------ +-J spin glass
+    def glass_sweep(self, bonds: "GlassBonds", beta: float, J: float = 1.0, nsweeps: int = 1,
+                    rng_counter: int = 0, stream=None) -> None:
+        """Metropolis sweeps with the bond signs of `bonds` (L % 128 == 0)."""
+        _lib.check(_lib.load().ising_glass_sweep(
+            ctypes.byref(self.desc), ctypes.c_void_p(bonds.words.data_ptr()), bonds.nbytes,
+            float(beta), float(J), int(nsweeps), int(rng_counter), _stream_handle(stream)))
+
+    def glass_observables(self, bonds: "GlassBonds", stream=None) -> tuple:
+        """(bond sum with the bond signs, M)."""
+        out = torch.empty(2, dtype=torch.int64, device=self.words.device)
+        p = out.data_ptr()
+        _lib.check(_lib.load().ising_glass_observables(
+            ctypes.byref(self.desc), ctypes.c_void_p(bonds.words.data_ptr()), bonds.nbytes,
+            ctypes.c_void_p(p), ctypes.c_void_p(p + 8), _stream_handle(stream)))
+        b, m = out.cpu().tolist()
+        return int(b), int(m)
+
     def get_spins(self, stream=None) -> np.ndarray:
         out = np.empty((self.L, self.L), dtype=np.int8)
         _lib.check(_lib.load().ising_get_spins(ctypes.byref(self.desc),
@@ -153,6 +171,29 @@ def batch_words(Ls) -> int:
     if n < 0:
         raise ValueError("unsupported lattice size in batch")
     return int(n)
+
+
+class GlassBonds:
+    """Bond signs of a +-J spin glass on an L x L lattice (device tensor of
+    4 * words_per_colour(L) words: right bonds of colour 0, 1, down bonds of
+    colour 0, 1; bit 1 = coupling -J)."""
+
+    def __init__(self, L: int, seed: int = None, stream_id: int = 0, right=None, down=None,
+                 stream=None):
+        self.L = int(L)
+        W = words_per_colour(self.L)
+        self.words = torch.zeros(4 * W, dtype=torch.int64, device="cuda")
+        self.nbytes = 4 * W * 8
+        ptr = ctypes.c_void_p(self.words.data_ptr())
+        if right is not None:
+            r = np.ascontiguousarray(right, dtype=np.int8)
+            d = np.ascontiguousarray(down, dtype=np.int8)
+            _lib.check(_lib.load().ising_glass_set_bonds(
+                ptr, self.nbytes, self.L, r.ctypes.data_as(ctypes.c_void_p),
+                d.ctypes.data_as(ctypes.c_void_p), _stream_handle(stream)))
+        else:
+            _lib.check(_lib.load().ising_glass_bonds_init(ptr, self.nbytes, self.L, int(seed),
+                                                          int(stream_id), _stream_handle(stream)))
 
 
 class Batch:
