@@ -30,14 +30,15 @@ __global__ __launch_bounds__(256) void k_glass_bonds_init(uint64_t *__restrict__
                                                           int64_t W, uint32_t key0, uint32_t key1,
                                                           uint32_t stream_id)
 {
-    const int64_t g = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (g >= 4 * W)
-        return;
-    const uint32_t x = (uint32_t)(g / W);
-    const int64_t k = g - (int64_t)x * W;
-    const Block b = philox4x32_10(ctr_word0(stream_id, kDomainCouplings, x), 0u, 0u, (uint32_t)k,
-                                  key0, key1);
-    bonds[g] = ((uint64_t)b.x0 | ((uint64_t)b.x1 << 32)) & valid_mask(k, M);
+    // grid-stride: 4 W can exceed the 2^32 work-items of one dispatch
+    const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+    for (int64_t g = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; g < 4 * W; g += stride) {
+        const uint32_t x = (uint32_t)(g / W);
+        const int64_t k = g - (int64_t)x * W;
+        const Block b = philox4x32_10(ctr_word0(stream_id, kDomainCouplings, x), 0u, 0u,
+                                      (uint32_t)k, key0, key1);
+        bonds[g] = ((uint64_t)b.x0 | ((uint64_t)b.x1 << 32)) & valid_mask(k, M);
+    }
 }
 
 // Bond vectors of target word (row i, column word w) of colour c; `left`:
@@ -180,8 +181,10 @@ hipError_t launch_glass_bonds_init(uint64_t *bonds, int64_t L, uint64_t seed, ui
                                    hipStream_t s)
 {
     const int64_t M = L * L / 2, W = (M + 63) / 64;
-    hipLaunchKernelGGL(k_glass_bonds_init, dim3((uint32_t)((4 * W + 255) / 256)), dim3(256), 0, s,
-                       bonds, M, W, (uint32_t)seed, (uint32_t)(seed >> 32), stream_id);
+    const int64_t nb = (4 * W + 255) / 256;
+    hipLaunchKernelGGL(k_glass_bonds_init, dim3((uint32_t)(nb < (1 << 20) ? nb : (1 << 20))),
+                       dim3(256), 0, s, bonds, M, W, (uint32_t)seed, (uint32_t)(seed >> 32),
+                       stream_id);
     return hipGetLastError();
 }
 

@@ -10,20 +10,27 @@
 namespace ising {
 
 // ------------------------------------------------------------ initial state
+// A dispatch counts its grid in 32-bit work-items, so kernels over up to 2^33
+// words loop over a capped grid.
+constexpr uint32_t kMaxStrideBlocks = 1u << 20; // x 256 threads < 2^32
+
 __global__ __launch_bounds__(256) void k_init(uint64_t *__restrict__ words, int64_t M, int64_t W,
                                               uint32_t key0, uint32_t key1, uint32_t stream_id)
 {
-    const int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (idx >= 2 * W)
-        return;
-    const uint32_t c = (uint32_t)(idx / W);
-    const int64_t chunk = idx - (int64_t)c * W;
-    words[idx] = init_word(chunk, c, M, stream_id, key0, key1);
+    const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+    for (int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; idx < 2 * W;
+         idx += stride) {
+        const uint32_t c = (uint32_t)(idx / W);
+        const int64_t chunk = idx - (int64_t)c * W;
+        words[idx] = init_word(chunk, c, M, stream_id, key0, key1);
+    }
 }
 
 // ------------------------------------------------- half-sweep, any geometry
 // One thread per target word; neighbour vectors by cyclic extraction from the
-// other colour (row-straddling words, partial last word, tiny lattices).
+// other colour (row-straddling words, partial last word, tiny lattices).  The
+// size limit (fewer than 2^32 - 2^16 words per colour) keeps the grid below
+// 2^32 work-items.
 __global__ __launch_bounds__(256) void k_sweep_general(uint64_t *__restrict__ tgt,
                                                        const uint64_t *__restrict__ src, int64_t H,
                                                        int64_t M, int64_t W, int c, SweepArgs2 a)
@@ -509,7 +516,9 @@ hipError_t launch_init(uint64_t *words, int64_t L, uint64_t seed, uint32_t strea
                        hipStream_t s)
 {
     const int64_t M = L * L / 2, W = (M + 63) / 64;
-    hipLaunchKernelGGL(k_init, dim3(blocks_for(2 * W, 256)), dim3(256), 0, s, words, M, W,
+    const uint32_t nb = blocks_for(2 * W, 256);
+    hipLaunchKernelGGL(k_init, dim3(nb < kMaxStrideBlocks ? nb : kMaxStrideBlocks), dim3(256), 0, s,
+                       words, M, W,
                        (uint32_t)seed, (uint32_t)(seed >> 32), stream_id);
     return hipGetLastError();
 }
