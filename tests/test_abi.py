@@ -148,3 +148,30 @@ def test_batch_argument_errors_without_device(lib):
     assert lib.ising_batch_create(ctypes.byref(h), 2, bad, b, 1.0, s, i, fake, 1 << 20) == _lib.ISING_E_SIZE
     assert lib.ising_batch_sweep(None, 1, None) == _lib.ISING_E_BADARG
     assert lib.ising_batch_destroy(None) == _lib.ISING_OK
+
+
+def test_batch_argument_errors_without_device(lib):
+    """Empty and malformed batches are rejected before any device work."""
+    from paper_1906_06297_amd import _lib
+
+    out = ctypes.c_void_p()
+    fake = ctypes.c_void_p(0x1000)  # never dereferenced: validation fails first
+
+    def create(Ls, betas, J=1.0, bytes_=1 << 20, n=None):
+        n = len(Ls) if n is None else n
+        L = (ctypes.c_int64 * max(len(Ls), 1))(*Ls)
+        b = (ctypes.c_double * max(len(betas), 1))(*betas)
+        s = (ctypes.c_uint64 * max(len(Ls), 1))(*([1] * len(Ls)))
+        q = (ctypes.c_uint32 * max(len(Ls), 1))(*range(len(Ls)))
+        return lib.ising_batch_create(ctypes.byref(out), n, L, b, J, s, q, fake, bytes_)
+
+    assert create([], [], n=0) == _lib.ISING_E_BADARG
+    assert b"empty" in lib.ising_last_error()
+    assert create([16], [0.4], n=-1) == _lib.ISING_E_BADARG
+    assert create([15], [0.4]) == _lib.ISING_E_SIZE  # odd L
+    assert create([2], [0.4]) == _lib.ISING_E_SIZE  # below the minimum
+    assert create([724], [0.4]) == _lib.ISING_E_SIZE  # above the LDS-resident maximum
+    assert create([16], [-0.1]) == _lib.ISING_E_BADARG
+    assert create([16], [float("nan")]) == _lib.ISING_E_BADARG
+    assert create([16], [0.4], J=float("inf")) == _lib.ISING_E_BADARG
+    assert create([256], [0.4], bytes_=8) == _lib.ISING_E_SIZE  # buffer too small
