@@ -48,14 +48,6 @@ __host__ __device__ __forceinline__ Block philox4x32_10(uint32_t c0, uint32_t c1
 
 enum : uint32_t { kDomainSweep = 0, kDomainInit = 1 };
 
-// Sweep acceptance parameters of one lattice at one temperature: thresholds
-// of the classes that need a random number, and which classes always flip.
-struct Accept {
-    uint32_t thr[5];      // T[a] for the classes in random_mask (0 < T < 2^32)
-    uint32_t always_mask; // bit a set: T[a] = 2^32
-    uint32_t random_mask; // bit a set: 0 < T[a] < 2^32
-};
-
 // Counter word 0 of a Philox block.
 __host__ __device__ __forceinline__ uint32_t ctr_word0(uint32_t stream_id, uint32_t domain, uint32_t q)
 {
@@ -85,45 +77,6 @@ __host__ __device__ __forceinline__ Classes classify(uint64_t t, uint64_t up, ui
     k.e[1] = a0 & ~a1;
     k.e[0] = ~(a0 | a1 | a2);
     return k;
-}
-
-// Flip mask of one word: exact r < T[a] per spin.  `valid` masks the spins
-// that exist.  The planes of block q come from counter
-// (stream<<8 | q, t_lo, t_hi, chunk).
-__host__ __device__ __forceinline__ uint64_t decide(const Classes &k, uint64_t valid, const Accept &acc_par,
-                                           uint32_t chunk, uint32_t t_lo, uint32_t t_hi,
-                                           uint32_t stream_id, uint32_t key0, uint32_t key1)
-{
-    uint64_t always = 0, pending = 0;
-#pragma unroll
-    for (int a = 0; a < 5; ++a) {
-        if ((acc_par.always_mask >> a) & 1u)
-            always |= k.e[a];
-        if ((acc_par.random_mask >> a) & 1u)
-            pending |= k.e[a];
-    }
-    always &= valid;
-    pending &= valid;
-    uint64_t accepted = 0;
-    for (uint32_t q = 0; q < 16 && pending != 0; ++q) {
-        const Block x = philox4x32_10(ctr_word0(stream_id, kDomainSweep, q), t_lo, t_hi, chunk,
-                                      key0, key1);
-        const uint64_t planes[2] = {(uint64_t)x.x0 | ((uint64_t)x.x1 << 32),
-                                    (uint64_t)x.x2 | ((uint64_t)x.x3 << 32)};
-#pragma unroll
-        for (int h = 0; h < 2; ++h) {
-            const int bit = 31 - (int)(2 * q + h);
-            uint64_t tb = 0;
-#pragma unroll
-            for (int a = 0; a < 5; ++a)
-                if (((acc_par.random_mask >> a) & 1u) && ((acc_par.thr[a] >> bit) & 1u))
-                    tb |= k.e[a];
-            const uint64_t differ = pending & (planes[h] ^ tb);
-            accepted |= differ & tb; // r bit 0 where T bit 1: r < T
-            pending ^= differ;       // decided either way
-        }
-    }
-    return always | accepted; // r == T after 32 planes: not < T, rejected
 }
 
 // --------------------------------------------- Metropolis, two random classes
@@ -206,42 +159,6 @@ __host__ __device__ __forceinline__ void advance_block(WordState &s, uint32_t q,
     apply_block(s,
                 philox4x32_10(ctr_word0(stream_id, kDomainSweep, q), t_lo, t_hi, chunk, key0, key1),
                 q, m);
-}
-
-// As compare_plane, for threshold bits known to be the same for every lane:
-// the four (bit of T_A, bit of T_B) cases reduce to fewer operations.
-__host__ __device__ __forceinline__ void compare_plane_uniform(WordState &s, uint64_t plane,
-                                                               bool bitA, bool bitB)
-{
-    if (!bitA && !bitB) { // threshold bit 0: a set r bit rejects, a clear one stays equal
-        s.pending &= ~plane;
-    } else if (bitA && bitB) { // threshold bit 1: a clear r bit accepts
-        s.flips |= s.pending & ~plane;
-        s.pending &= plane;
-    } else {
-        const uint64_t tb = bitA ? s.classA : ~s.classA;
-        const uint64_t differ = s.pending & (plane ^ tb);
-        s.flips |= differ & tb;
-        s.pending ^= differ;
-    }
-}
-
-// advance_block for a block index q that is the same for every lane.
-__host__ __device__ __forceinline__ void advance_block_uniform(WordState &s, uint32_t q,
-                                                               uint32_t chunk, const Metro2 &m,
-                                                               uint32_t t_lo, uint32_t t_hi,
-                                                               uint32_t stream_id, uint32_t key0,
-                                                               uint32_t key1)
-{
-    const Block x =
-        philox4x32_10(ctr_word0(stream_id, kDomainSweep, q), t_lo, t_hi, chunk, key0, key1);
-    const int bit = 31 - 2 * (int)q;
-    compare_plane_uniform(s, (uint64_t)x.x0 | ((uint64_t)x.x1 << 32), (m.thrA >> bit) & 1u,
-                          (m.thrB >> bit) & 1u);
-    compare_plane_uniform(s, (uint64_t)x.x2 | ((uint64_t)x.x3 << 32), (m.thrA >> (bit - 1)) & 1u,
-                          (m.thrB >> (bit - 1)) & 1u);
-    if (q == 15)
-        s.pending = 0;
 }
 
 // Sweep parameters shared by every word of one half-sweep launch.
