@@ -34,3 +34,19 @@ def unpack(words: np.ndarray, L: int) -> np.ndarray:
         i, j = colour_sites(L, c)
         s[i, j] = np.where(bits == 1, 1, -1)
     return s
+
+
+def pack_rows(spins: np.ndarray) -> np.ndarray:
+    """pack() for row-aligned sizes (L % 128 == 0) by strided row slices, without
+    index arrays: colour c of row i is spins[i, (i + c) % 2 :: 2]."""
+    L = spins.shape[0]
+    assert L % 128 == 0
+    up = spins > 0
+    out = np.empty((2, L * L // 128), dtype=np.uint64)
+    for c in (0, 1):
+        col = np.empty((L, L // 2), dtype=bool)
+        col[0::2] = up[0::2, c::2]
+        col[1::2] = up[1::2, (1 - c)::2]
+        out[c] = np.packbits(col, axis=1, bitorder="little").view(np.uint64).reshape(-1)
+        del col
+    return out

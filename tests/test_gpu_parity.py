@@ -111,14 +111,32 @@ def test_padding_bits_stay_zero(gpu):
 
 
 def test_row_aligned_4096_full(gpu, orc):
-    L, seed = 4096, 21
-    say("full-lattice parity L=4096, 8 sweeps")
+    """The headline kernel on fewer tiles for the headline's full 200 sweeps."""
+    L, seed, n = 4096, 21, workloads.HEADLINE["nsweeps"]
+    say(f"full-lattice parity L=4096, {n} sweeps")
     lat = gpu.Lattice(L, seed=seed)
-    lat.sweep(workloads.BETA_CRIT_CONFIG, 1.0, 8, 0)
+    lat.sweep(workloads.BETA_CRIT_CONFIG, 1.0, n, 0)
     ref = orc.init(L, seed, 0)
-    orc.sweeps(ref, workloads.BETA_CRIT_CONFIG, 1.0, seed, 0, 8, 0)
+    orc.sweeps(ref, workloads.BETA_CRIT_CONFIG, 1.0, seed, 0, n, 0)
     assert np.array_equal(lat.packed(), pack(ref))
     assert lat.observables() == orc.observables(ref)
+
+
+def test_headline_full_lattice_first_sweeps(gpu, orc):
+    """L = 65536 in the benchmark's launch configuration: the whole lattice
+    (2^32 spins) bit for bit after the first 4 sweeps at beta_c."""
+    from layout import pack_rows
+
+    cfg = workloads.HEADLINE
+    L, n, beta = cfg["L"], 4, workloads.BETA_CRIT_CONFIG
+    say("headline size, whole lattice, 4 sweeps")
+    lat = gpu.Lattice(L, seed=cfg["seed"], stream_id=cfg["stream"])
+    lat.sweep(beta, cfg["J"], n, 0)
+    got = lat.packed()
+    say("oracle: 4 sweeps at L = 65536")
+    ref = orc.init(L, cfg["seed"], cfg["stream"])
+    orc.sweeps(ref, beta, cfg["J"], cfg["seed"], cfg["stream"], n, 0)
+    assert np.array_equal(got, pack_rows(ref))
 
 
 @pytest.mark.parametrize("beta", workloads.HEADLINE["betas"])
