@@ -307,8 +307,9 @@ int ising_mh_independence(int32_t n, int64_t L, int8_t *d_state, float *d_logq, 
  * measurements: 0 = default (row-aligned sizes, L % 128 == 0, use the
  * streaming row kernel with its per-wavefront work queue; other sizes the
  * general kernel), 1 = the general-geometry kernel for every size, 2 = the
- * row kernel without the work queue.  All choices give identical lattices.
- * Process-wide setting; not synchronised with calls running on other
+ * row kernel without the work queue.  ising_glass_sweep takes the queued
+ * row kernel for 0 and its per-word row kernel for 1 and 2.  All choices give
+ * identical lattices.  Process-wide setting; not synchronised with calls running on other
  * threads. */
 int ising_set_sweep_kernel(int variant);
 

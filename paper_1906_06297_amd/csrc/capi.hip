@@ -451,7 +451,7 @@ int ising_glass_sweep(const ising_lattice *lat, const uint64_t *d_bonds, size_t 
         for (int c = 0; c < 2; ++c) {
             const uint64_t t = 2 * (rng_counter + (uint64_t)sw) + (uint64_t)c;
             hipError_t e = ising::launch_glass_half_sweep(lat->words, d_bonds, lat->L, c, m, t,
-                                                          lat->seed, lat->stream_id, s);
+                                                          lat->seed, lat->stream_id, s, g_variant);
             if (e != hipSuccess)
                 return hip_fail(e, "half-sweep launch");
         }

@@ -10,10 +10,11 @@ namespace ising {
 // Random bond signs into the four bond arrays (4 * ceil(L*L/128) words).
 hipError_t launch_glass_bonds_init(uint64_t *bonds, int64_t L, uint64_t seed, uint32_t stream_id,
                                    hipStream_t s);
-// Half-sweep of colour c of a row-aligned lattice (L % 128 == 0).
+// Half-sweep of colour c of a row-aligned lattice (L % 128 == 0): the queued
+// row kernel by default, the per-word row kernel for the other variants.
 hipError_t launch_glass_half_sweep(uint64_t *words, const uint64_t *bonds, int64_t L, int c,
                                    const Metro2 &m, uint64_t t, uint64_t seed, uint32_t stream_id,
-                                   hipStream_t s);
+                                   hipStream_t s, int variant);
 hipError_t launch_glass_observables(const uint64_t *words, const uint64_t *bonds, int64_t L,
                                     int64_t *bond, int64_t *mag, hipStream_t s);
 

@@ -19,6 +19,7 @@
 #include "glass.hpp"
 #include "ising_device.hpp"
 #include "ising_rows.hpp"
+#include "launch.hpp"
 
 namespace ising {
 
@@ -190,13 +191,15 @@ hipError_t launch_glass_bonds_init(uint64_t *bonds, int64_t L, uint64_t seed, ui
 
 hipError_t launch_glass_half_sweep(uint64_t *words, const uint64_t *bonds, int64_t L, int c,
                                    const Metro2 &m, uint64_t t, uint64_t seed, uint32_t stream_id,
-                                   hipStream_t s)
+                                   hipStream_t s, int variant)
 {
     const int64_t Wr = L / 128, W = L * Wr;
     uint64_t *tgt = words + (int64_t)c * W;
     const uint64_t *src = words + (int64_t)(1 - c) * W;
     const SweepArgs2 a{m, (uint32_t)t, (uint32_t)(t >> 32), stream_id, (uint32_t)seed,
                        (uint32_t)(seed >> 32)};
+    if (variant == kVariantDefault)
+        return launch_rows_queue(tgt, src, bonds, (uint64_t)W, L, c, m, a, s);
     const int threads = Wr >= 256 ? 256 : (Wr >= 64 ? 64 * (int)((Wr + 63) / 64) : 64);
     const int64_t bpb = (Wr + threads - 1) / threads;
     const int64_t bands = (L + kGlassRows - 1) / kGlassRows;

@@ -262,26 +262,44 @@ __host__ __device__ __forceinline__ uint32_t funnel(uint32_t hi, uint32_t lo, ui
 #endif
 }
 
+// Side vector halves: centre shifted by one spin, the adjacent word's edge
+// spin shifted in (Sec. 3.3, Fig. 3); `adj_half` = the half of the adjacent
+// word that feeds it (high half of the left word when `left`, low half of
+// the right word otherwise).
+__host__ __device__ __forceinline__ void side_halves(uint64_t ce, uint32_t adj_half, bool left,
+                                                     uint32_t &sl, uint32_t &sh)
+{
+    const uint32_t cl = lo32(ce), ch = hi32(ce);
+    sl = left ? funnel(cl, adj_half, 31) : funnel(ch, cl, 1);
+    sh = left ? funnel(ch, cl, 31) : funnel(adj_half, ch, 1);
+}
+
+// Start state of a word from its target word and its four neighbour vectors
+// (the side one as halves).
+template <bool Anti, bool Plain>
+__host__ __device__ __forceinline__ State start_from_halves(uint64_t t, uint64_t up, uint64_t dn,
+                                                            uint64_t ce, uint32_t sl, uint32_t sh,
+                                                            const ClassMasks &cm)
+{
+    State s;
+    start_half<Plain>(s, 0, lo32(t),
+                      split_classes<Anti>(lo32(t), lo32(up), lo32(dn), lo32(ce), sl), cm);
+    start_half<Plain>(s, 1, hi32(t),
+                      split_classes<Anti>(hi32(t), hi32(up), hi32(dn), hi32(ce), sh), cm);
+    return s;
+}
+
 // Start state of a word from its target word and four source words: up, down
-// and centre words of the same column, `adj_half` = the half of the adjacent
-// source word that feeds the side vector (high half of the left word when
-// `left`, low half of the right word otherwise).
+// and centre words of the same column and the half of the adjacent source
+// word that feeds the side vector.
 template <bool Anti, bool Plain>
 __host__ __device__ __forceinline__ State start_word_rows(uint64_t t, uint64_t up, uint64_t dn,
                                                           uint64_t ce, uint32_t adj_half,
                                                           bool left, const ClassMasks &cm)
 {
-    const uint32_t cl = lo32(ce), ch = hi32(ce);
-    // side vector: centre shifted by one spin, the adjacent word's edge spin
-    // shifted in (Sec. 3.3, Fig. 3)
-    const uint32_t sl = left ? funnel(cl, adj_half, 31) : funnel(ch, cl, 1);
-    const uint32_t sh = left ? funnel(ch, cl, 31) : funnel(adj_half, ch, 1);
-    State s;
-    start_half<Plain>(s, 0, lo32(t),
-                      split_classes<Anti>(lo32(t), lo32(up), lo32(dn), cl, sl), cm);
-    start_half<Plain>(s, 1, hi32(t),
-                      split_classes<Anti>(hi32(t), hi32(up), hi32(dn), ch, sh), cm);
-    return s;
+    uint32_t sl, sh;
+    side_halves(ce, adj_half, left, sl, sh);
+    return start_from_halves<Anti, Plain>(t, up, dn, ce, sl, sh, cm);
 }
 
 // Start state of a word of any geometry from its four neighbour vectors, with

@@ -218,10 +218,17 @@ __device__ __forceinline__ uint32_t side_half_dpp(uint32_t cur_lo, uint32_t cur_
 // loads its adjacent word.  The source row that streams in is read
 // non-temporally, so that L2 keeps the target lines, whose words are stored
 // at different times, until they are complete.  Word indices fit in 32 bits.
-template <bool Anti, bool Plain, bool Dpp>
+//
+// `Glass`: +-J couplings from four bond bit arrays (Wc words each: right bonds
+// of colour 0, 1, down bonds of colour 0, 1; bit 1 = -J), XORed into the
+// neighbour words before the class split (glass_kernels.hip has the layout).
+// The bond words stream in like the spin words; the left bond of a target
+// spin whose left neighbour is the side one takes the same one-spin shift.
+template <bool Anti, bool Plain, bool Dpp, bool Glass>
 __global__ __launch_bounds__(256) void k_sweep_rows_q(uint64_t *__restrict__ tgt,
                                                       const uint64_t *__restrict__ src,
-                                                      uint32_t L, uint32_t Wr,
+                                                      const uint64_t *__restrict__ bonds,
+                                                      uint64_t Wc, uint32_t L, uint32_t Wr,
                                                       uint32_t waves_per_band, uint32_t nbands,
                                                       int c, SweepArgs2 a)
 {
@@ -258,6 +265,35 @@ __global__ __launch_bounds__(256) void k_sweep_rows_q(uint64_t *__restrict__ tgt
     };
     uint64_t prev = row((i0 == 0) ? L - 1 : i0 - 1)[wc];
     uint64_t cur = row(i0)[wc];
+    // Glass: bond arrays of the target colour (right rc, down dc) and of the
+    // other colour (right ro, down dO)
+    const uint32_t xrc = (uint32_t)c, xro = 1u - (uint32_t)c, xdc = 2u + (uint32_t)c,
+                   xdo = 3u - (uint32_t)c;
+    auto brow = [&](uint32_t x, uint32_t i) { return bonds + x * Wc + (size_t)i * Wr; };
+    struct RowBonds {
+        uint64_t dn, rt, ro, dnext; // down, right, other colour's right (aligned), dO of this row
+        uint64_t radj;              // other colour's right bond at the left word (no Dpp)
+        uint32_t redge;             // its high half at the segment edge (Dpp)
+    };
+    auto row_bonds = [&](uint32_t i, bool lft) {
+        RowBonds rb{};
+        if (Glass) {
+            rb.dn = brow(xdc, i)[wc];
+            rb.rt = brow(xrc, i)[wc];
+            rb.ro = brow(xro, i)[wc];
+            rb.dnext = brow(xdo, i)[wc];
+            if (lft) {
+                if (Dpp) {
+                    if (edge_l)
+                        rb.redge = rows::hi32(brow(xro, i)[wl]);
+                } else {
+                    rb.radj = brow(xro, i)[wl];
+                }
+            }
+        }
+        return rb;
+    };
+    uint64_t bup = Glass ? brow(xdo, (i0 == 0) ? L - 1 : i0 - 1)[wc] : 0;
     // row i0 operands
     bool left = ((i0 + c) & 1) == 0;
     uint64_t next = __builtin_nontemporal_load(&row((i0 + 1 == L) ? 0 : i0 + 1)[wc]);
@@ -268,6 +304,7 @@ __global__ __launch_bounds__(256) void k_sweep_rows_q(uint64_t *__restrict__ tgt
         edge = edge_half(i0, left);
     else
         adj = side_word(i0, left);
+    RowBonds rb = row_bonds(i0, left);
     auto trow = [&](uint32_t i) { return tgt + (size_t)i * Wr; }; // wave-uniform pointer
     uint32_t head = 0, len = 0, r_last = 0;
     for (uint32_t r = 0; r < (uint32_t)kBandRows; ++r) {
@@ -286,6 +323,7 @@ __global__ __launch_bounds__(256) void k_sweep_rows_q(uint64_t *__restrict__ tgt
         const bool left1 = !left;
         uint64_t next1 = 0, t1 = 0, adj1 = 0;
         uint32_t edge1 = 0;
+        RowBonds rb1{};
         if (more) {
             next1 = __builtin_nontemporal_load(&row(i2)[wc]);
             t1 = tgt[(size_t)i1 * Wr + wc];
@@ -293,12 +331,33 @@ __global__ __launch_bounds__(256) void k_sweep_rows_q(uint64_t *__restrict__ tgt
                 edge1 = edge_half(i1, left1);
             else
                 adj1 = side_word(i1, left1);
+            rb1 = row_bonds(i1, left1);
         }
         const uint32_t adj_half =
             Dpp ? side_half_dpp(rows::lo32(cur), rows::hi32(cur), edge, left)
                 : (left ? rows::hi32(adj) : rows::lo32(adj));
-        rows::State s =
-            rows::start_word_rows<Anti, Plain>(t, prev, next, cur, adj_half, left, cm);
+        uint32_t shl, shh;
+        rows::side_halves(cur, adj_half, left, shl, shh);
+        uint64_t nu = prev, nd = next, nc = cur;
+        if (Glass) {
+            nu ^= bup;
+            nd ^= rb.dn;
+            if (left) { // centre = right neighbour; side = left neighbour, shifted bonds
+                nc ^= rb.rt;
+                const uint32_t radj_half = Dpp ? side_half_dpp(rows::lo32(rb.ro), rows::hi32(rb.ro),
+                                                               rb.redge, true)
+                                               : rows::hi32(rb.radj);
+                uint32_t bl, bh;
+                rows::side_halves(rb.ro, radj_half, true, bl, bh);
+                shl ^= bl;
+                shh ^= bh;
+            } else { // centre = left neighbour; side = right neighbour
+                nc ^= rb.ro;
+                shl ^= rows::lo32(rb.rt);
+                shh ^= rows::hi32(rb.rt);
+            }
+        }
+        rows::State s = rows::start_from_halves<Anti, Plain>(t, nu, nd, nc, shl, shh, cm);
         // (a block applied to a decided word changes nothing; with both
         // classes random a whole wavefront is practically never decided
         // early, so only the other cases test for it)
@@ -326,6 +385,10 @@ __global__ __launch_bounds__(256) void k_sweep_rows_q(uint64_t *__restrict__ tgt
         adj = adj1;
         edge = edge1;
         left = left1;
+        if (Glass) {
+            bup = rb.dnext;
+            rb = rb1;
+        }
     }
     while (len > 0)
         drain_once(wq, rg, head, len, len < 64 ? len : 64, r_last, tgt, a, lane);
@@ -523,6 +586,37 @@ hipError_t launch_init(uint64_t *words, int64_t L, uint64_t seed, uint32_t strea
     return hipGetLastError();
 }
 
+// The queued row kernel for a row-aligned lattice (L % 128 == 0), with the
+// bond arrays of a +-J glass or without (bonds == nullptr).
+hipError_t launch_rows_queue(uint64_t *tgt, const uint64_t *src, const uint64_t *bonds,
+                             uint64_t Wc, int64_t L, int c, const Metro2 &m, const SweepArgs2 &a,
+                             hipStream_t s)
+{
+    const int64_t Wr = L / 128;
+    const int64_t wpb = (Wr + 63) / 64;
+    const int64_t nbands = (L + kBandRows - 1) / kBandRows;
+    const int64_t waves = wpb * nbands;
+    const dim3 grid((uint32_t)((waves + kWaves - 1) / kWaves)), block(64 * kWaves);
+    const bool plain = m.randA && m.randB && !m.alwaysA && !m.alwaysB;
+    const bool dpp = Wr % 64 == 0;
+    using Kernel = void (*)(uint64_t *, const uint64_t *, const uint64_t *, uint64_t, uint32_t,
+                            uint32_t, uint32_t, uint32_t, int, SweepArgs2);
+    static const Kernel kernels[16] = {
+        k_sweep_rows_q<false, false, false, false>, k_sweep_rows_q<false, false, true, false>,
+        k_sweep_rows_q<false, true, false, false>,  k_sweep_rows_q<false, true, true, false>,
+        k_sweep_rows_q<true, false, false, false>,  k_sweep_rows_q<true, false, true, false>,
+        k_sweep_rows_q<true, true, false, false>,   k_sweep_rows_q<true, true, true, false>,
+        k_sweep_rows_q<false, false, false, true>,  k_sweep_rows_q<false, false, true, true>,
+        k_sweep_rows_q<false, true, false, true>,   k_sweep_rows_q<false, true, true, true>,
+        k_sweep_rows_q<true, false, false, true>,   k_sweep_rows_q<true, false, true, true>,
+        k_sweep_rows_q<true, true, false, true>,    k_sweep_rows_q<true, true, true, true>};
+    const Kernel k =
+        kernels[(bonds ? 8 : 0) + (m.anti ? 4 : 0) + (plain ? 2 : 0) + (dpp ? 1 : 0)];
+    hipLaunchKernelGGL(k, grid, block, 0, s, tgt, src, bonds, Wc, (uint32_t)L, (uint32_t)Wr,
+                       (uint32_t)wpb, (uint32_t)nbands, c, a);
+    return hipGetLastError();
+}
+
 hipError_t launch_half_sweep(uint64_t *words, int64_t L, int c, const Metro2 &m, uint64_t t,
                              uint64_t seed, uint32_t stream_id, hipStream_t s, int variant)
 {
@@ -540,22 +634,7 @@ hipError_t launch_half_sweep(uint64_t *words, int64_t L, int c, const Metro2 &m,
             hipLaunchKernelGGL(k_sweep_rows, dim3((uint32_t)(bands * bpb)), dim3(threads), 0, s,
                                tgt, src, L, Wr, bpb, c, a);
         } else {
-            const int64_t wpb = (Wr + 63) / 64;
-            const int64_t nbands = (L + kBandRows - 1) / kBandRows;
-            const int64_t waves = wpb * nbands;
-            const dim3 grid((uint32_t)((waves + kWaves - 1) / kWaves)), block(64 * kWaves);
-            const bool plain = m.randA && m.randB && !m.alwaysA && !m.alwaysB;
-            const bool dpp = Wr % 64 == 0;
-            using Kernel = void (*)(uint64_t *, const uint64_t *, uint32_t, uint32_t, uint32_t,
-                                    uint32_t, int, SweepArgs2);
-            static const Kernel kernels[8] = {
-                k_sweep_rows_q<false, false, false>, k_sweep_rows_q<false, false, true>,
-                k_sweep_rows_q<false, true, false>,  k_sweep_rows_q<false, true, true>,
-                k_sweep_rows_q<true, false, false>,  k_sweep_rows_q<true, false, true>,
-                k_sweep_rows_q<true, true, false>,   k_sweep_rows_q<true, true, true>};
-            const Kernel k = kernels[(m.anti ? 4 : 0) + (plain ? 2 : 0) + (dpp ? 1 : 0)];
-            hipLaunchKernelGGL(k, grid, block, 0, s, tgt, src, (uint32_t)L, (uint32_t)Wr,
-                               (uint32_t)wpb, (uint32_t)nbands, c, a);
+            return launch_rows_queue(tgt, src, nullptr, 0, L, c, m, a, s);
         }
     } else {
         hipLaunchKernelGGL(k_sweep_general, dim3(blocks_for(W, 256)), dim3(256), 0, s, tgt, src,

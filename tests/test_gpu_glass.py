@@ -45,19 +45,42 @@ def test_bond_generator_matches_oracle(gpu, orc, L):
     assert np.array_equal(got[0], Jr) and np.array_equal(got[1], Jd)
 
 
+# 128 and 384: fewer than 64 words per row (no cross-lane side shift in the
+# queued kernel); 8192: 64 words per row; 16384 with 3 sweeps: several wave
+# segments per row and bands that end mid-lattice.
+@pytest.mark.parametrize("variant", [0, 2])
 @pytest.mark.parametrize("L", [128, 256, 384, 1024, 8192])
 @pytest.mark.parametrize("beta,J", [(0.44, 1.0), (1.2, 1.0), (0.5, -1.0), (0.0, 1.0), (9.0, 1.0)])
-def test_glass_parity(gpu, orc, L, beta, J):
-    print(f"glass L={L} beta={beta} J={J}", flush=True)
+def test_glass_parity(gpu, orc, variant, L, beta, J):
+    print(f"glass variant={variant} L={L} beta={beta} J={J}", flush=True)
     seed, stream, n, ctr = 70 + L, 1, (3 if L <= 1024 else 1), 2
     bonds = gpu.GlassBonds(L, seed=5 + L, stream_id=0)
     lat = gpu.Lattice(L, seed=seed, stream_id=stream)
-    lat.glass_sweep(bonds, beta, J, n, ctr)
+    gpu.set_sweep_kernel(variant)
+    try:
+        lat.glass_sweep(bonds, beta, J, n, ctr)
+    finally:
+        gpu.set_sweep_kernel(0)
     Jr, Jd = orc.glass_couplings(L, 5 + L, 0)
     ref = orc.init(L, seed, stream)
     orc.glass_sweeps(ref, Jr, Jd, beta, J, seed, stream, n, ctr)
     assert np.array_equal(lat.packed(), pack(ref))
     assert lat.glass_observables(bonds) == orc.glass_observables(ref, Jr, Jd)
+
+
+@pytest.mark.parametrize("L,n", [(16384, 2), (8320, 2)])
+def test_glass_parity_large(gpu, orc, L, n):
+    """Several 64-word wave segments per row (16384), a row length that is not
+    a multiple of 64 words with a partial last segment (8320 = 65 words)."""
+    print(f"glass large L={L}", flush=True)
+    seed, stream, ctr, beta, J = 3, 2, 5, 0.44, 1.0
+    bonds = gpu.GlassBonds(L, seed=9, stream_id=1)
+    lat = gpu.Lattice(L, seed=seed, stream_id=stream)
+    lat.glass_sweep(bonds, beta, J, n, ctr)
+    Jr, Jd = orc.glass_couplings(L, 9, 1)
+    ref = orc.init(L, seed, stream)
+    orc.glass_sweeps(ref, Jr, Jd, beta, J, seed, stream, n, ctr)
+    assert np.array_equal(lat.packed(), pack(ref))
 
 
 def test_ferromagnetic_bonds_give_the_plain_sweep(gpu):
