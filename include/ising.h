@@ -119,9 +119,12 @@ int ising_observables(const ising_lattice *lat, int64_t *d_bond, int64_t *d_mag,
 /* +-J spin glass (the extension named in the paper's conclusions): couplings
  * J_ij = J * (1 - 2 b_ij) with one sign bit b_ij per bond.  The bond array
  * (device, caller-owned, 4 * ising_words_per_colour(L) uint64 words) holds
- * four bit arrays in the colour-compact layout of the spins: the bond to the
- * right of every colour-0 site, of every colour-1 site, then the bond below
- * every colour-0 site, every colour-1 site; padding bits 0.  Only row-aligned
+ * four bit arrays x in the colour-compact layout of the spins: x = 0, 1 the
+ * bond to the right of every colour-0, colour-1 site, x = 2, 3 the bond below
+ * every colour-0, colour-1 site; padding bits 0.  Interleaved word by word:
+ * word k of array x is word 4 k + x of the bond array, so that the four bond
+ * words of spin word k are one 32-byte chunk; the array must be 16-byte
+ * aligned (ISING_E_BADARG otherwise; hipMalloc's alignment suffices).  Only row-aligned
  * sizes (L % 128 == 0; ISING_E_SIZE otherwise).  Every call takes the array's
  * size in bytes and returns ISING_E_SIZE if it is too small.
  *

@@ -377,6 +377,8 @@ int check_bonds(const void *d_bonds, size_t bytes, int64_t L)
 {
     if (!d_bonds)
         return fail(ISING_E_BADARG, "null bond array");
+    if ((uintptr_t)d_bonds % 16 != 0) // the sweep reads two words at a time
+        return fail(ISING_E_BADARG, "bond array must be 16-byte aligned");
     if (bytes < (size_t)(4 * words_per_colour(L)) * sizeof(uint64_t))
         return fail(ISING_E_SIZE, "bond array needs %lld bytes",
                     (long long)(4 * words_per_colour(L) * 8));
@@ -418,10 +420,10 @@ int ising_glass_set_bonds(uint64_t *d_bonds, size_t bytes, int64_t L, const int8
                             (long long)j);
             const int c = (int)((i + j) & 1);
             const int64_t n = i * H + (j >> 1);
-            if (r < 0)
-                w[(size_t)(c * W + (n >> 6))] |= 1ull << (n & 63);
+            if (r < 0) // interleaved: word k of array x at 4 k + x
+                w[(size_t)(4 * (n >> 6) + c)] |= 1ull << (n & 63);
             if (d < 0)
-                w[(size_t)((2 + c) * W + (n >> 6))] |= 1ull << (n & 63);
+                w[(size_t)(4 * (n >> 6) + 2 + c)] |= 1ull << (n & 63);
         }
     hipStream_t s = (hipStream_t)hip_stream;
     hipError_t e = hipMemcpyAsync(d_bonds, w.data(), w.size() * sizeof(uint64_t),

@@ -2,17 +2,18 @@
 // name): bond-sign arrays, the half-sweep and the observables.
 //
 // Couplings J_ij = J * (1 - 2 b_ij), b_ij one bit per bond.  Four bit arrays
-// in the colour-compact layout of the spins (W words each, padding bits 0):
-// x = 0, 1: the bond to the right of each colour-x site; x = 2, 3: the bond
-// below each colour-(x - 2) site.  Every bond is stored once.  For a target
-// word of colour c the four bond vectors, aligned bit for bit with the target
-// spins, are: up = down bonds of colour 1 - c one row above, down = down
-// bonds of colour c, right = right bonds of colour c, left = right bonds of
-// colour 1 - c at the left neighbour (the same word, or the side shift of
-// Sec. 3.3 when the left neighbour is the side neighbour).  XORing a bond bit
-// into the neighbour bit turns s * b * n into s * n', so the aligned-count
-// classes, thresholds and compare of the ferromagnetic kernels apply
-// unchanged.
+// in the colour-compact layout of the spins (W words each, padding bits 0),
+// interleaved word by word (word 4 k + x is word k of array x): x = 0, 1: the
+// bond to the right of each colour-x site; x = 2, 3: the bond below each
+// colour-(x - 2) site.  Every bond is stored once, and the four words that a
+// spin word k needs sit in one 32-byte chunk.  For a target word of colour c
+// the four bond vectors, aligned bit for bit with the target spins, are: up =
+// down bonds of colour 1 - c one row above, down = down bonds of colour c,
+// right = right bonds of colour c, left = right bonds of colour 1 - c at the
+// left neighbour (the same word, or the side shift of Sec. 3.3 when the left
+// neighbour is the side neighbour).  XORing a bond bit into the neighbour bit
+// turns s * b * n into s * n', so the aligned-count classes, thresholds and
+// compare of the ferromagnetic kernels apply unchanged.
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
@@ -25,8 +26,9 @@ namespace ising {
 
 enum : uint32_t { kDomainCouplings = 4 };
 
-// Random bond signs (probability 1/2): array x word k is x0 | x1 << 32 of
-// Philox block (stream << 8 | 4 << 4 | x, 0, 0, k), padding bits cleared.
+// Random bond signs (probability 1/2): array x word k (stored at 4 k + x) is
+// x0 | x1 << 32 of Philox block (stream << 8 | 4 << 4 | x, 0, 0, k), padding
+// bits cleared.
 __global__ __launch_bounds__(256) void k_glass_bonds_init(uint64_t *__restrict__ bonds, int64_t M,
                                                           int64_t W, uint32_t key0, uint32_t key1,
                                                           uint32_t stream_id)
@@ -34,8 +36,8 @@ __global__ __launch_bounds__(256) void k_glass_bonds_init(uint64_t *__restrict__
     // grid-stride: 4 W can exceed the 2^32 work-items of one dispatch
     const int64_t stride = (int64_t)gridDim.x * blockDim.x;
     for (int64_t g = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; g < 4 * W; g += stride) {
-        const uint32_t x = (uint32_t)(g / W);
-        const int64_t k = g - (int64_t)x * W;
+        const uint32_t x = (uint32_t)(g & 3);
+        const int64_t k = g >> 2;
         const Block b = philox4x32_10(ctr_word0(stream_id, kDomainCouplings, x), 0u, 0u,
                                       (uint32_t)k, key0, key1);
         bonds[g] = ((uint64_t)b.x0 | ((uint64_t)b.x1 << 32)) & valid_mask(k, M);
@@ -48,21 +50,21 @@ struct BondVectors {
     uint64_t up, dn, ce, sd;
 };
 
-__device__ __forceinline__ BondVectors bond_vectors(const uint64_t *__restrict__ bonds, int64_t W,
-                                                    int64_t Wr, int64_t L, int c, int64_t i,
-                                                    int64_t w, int64_t wl, bool left)
+__device__ __forceinline__ BondVectors bond_vectors(const uint64_t *__restrict__ bonds, int64_t Wr,
+                                                    int64_t L, int c, int64_t i, int64_t w,
+                                                    int64_t wl, bool left)
 {
-    const uint64_t *rc = bonds + (int64_t)c * W, *ro = bonds + (int64_t)(1 - c) * W;
-    const uint64_t *dc = bonds + (int64_t)(2 + c) * W, *dO = bonds + (int64_t)(3 - c) * W;
+    // word (row, column word) of array x
+    const auto at = [&](int64_t row, int64_t col, int x) { return bonds[4 * (row * Wr + col) + x]; };
     const int64_t iu = (i == 0) ? L - 1 : i - 1;
     BondVectors v;
-    v.up = dO[iu * Wr + w];
-    v.dn = dc[i * Wr + w];
-    const uint64_t right = rc[i * Wr + w];
-    const uint64_t left_aligned = ro[i * Wr + w];
+    v.up = at(iu, w, 3 - c);
+    v.dn = at(i, w, 2 + c);
+    const uint64_t right = at(i, w, c);
+    const uint64_t left_aligned = at(i, w, 1 - c);
     if (left) { // centre = right neighbour, side = left neighbour (jc - 1)
         v.ce = right;
-        v.sd = side_vector(left_aligned, ro[i * Wr + wl], true);
+        v.sd = side_vector(left_aligned, at(i, wl, 1 - c), true);
     } else { // centre = left neighbour, side = right neighbour
         v.ce = left_aligned;
         v.sd = right;
@@ -86,7 +88,6 @@ __global__ __launch_bounds__(256) void k_glass_rows(uint64_t *__restrict__ tgt,
     const int64_t w = (blockIdx.x - band * blocks_per_band) * (int64_t)blockDim.x + threadIdx.x;
     if (w >= Wr)
         return;
-    const int64_t W = L * Wr;
     const int64_t i0 = band * kGlassRows;
     const int64_t wl = (w == 0) ? Wr - 1 : w - 1;
     const int64_t wr = (w == Wr - 1) ? 0 : w + 1;
@@ -102,7 +103,7 @@ __global__ __launch_bounds__(256) void k_glass_rows(uint64_t *__restrict__ tgt,
         const bool left = ((i + c) & 1) == 0;
         const uint64_t t = tgt[idx];
         const uint64_t sd = side_vector(cur, src[i * Wr + (left ? wl : wr)], left);
-        const BondVectors b = bond_vectors(bonds, W, Wr, L, c, i, w, wl, left);
+        const BondVectors b = bond_vectors(bonds, Wr, L, c, i, w, wl, left);
         const uint64_t nu = prev ^ b.up, nd = next ^ b.dn, nc = cur ^ b.ce, ns = sd ^ b.sd;
         rows::State s;
 #pragma unroll
@@ -139,7 +140,7 @@ __global__ __launch_bounds__(256) void k_glass_observables(const uint64_t *__res
         const bool left = (i & 1) == 0; // colour 0: side neighbour on the left on even rows
         const int64_t wl = (w == 0) ? Wr - 1 : w - 1, wr = (w + 1 == Wr) ? 0 : w + 1;
         const uint64_t sd = side_vector(ce, white[i * Wr + (left ? wl : wr)], left);
-        const BondVectors b = bond_vectors(bonds, W, Wr, L, 0, i, w, wl, left);
+        const BondVectors b = bond_vectors(bonds, Wr, L, 0, i, w, wl, left);
         const int64_t aligned =
             (int64_t)__popcll(~(t ^ up ^ b.up)) + (int64_t)__popcll(~(t ^ dn ^ b.dn)) +
             (int64_t)__popcll(~(t ^ ce ^ b.ce)) + (int64_t)__popcll(~(t ^ sd ^ b.sd));
@@ -199,7 +200,7 @@ hipError_t launch_glass_half_sweep(uint64_t *words, const uint64_t *bonds, int64
     const SweepArgs2 a{m, (uint32_t)t, (uint32_t)(t >> 32), stream_id, (uint32_t)seed,
                        (uint32_t)(seed >> 32)};
     if (variant == kVariantDefault)
-        return launch_rows_queue(tgt, src, bonds, (uint64_t)W, L, c, m, a, s);
+        return launch_rows_queue(tgt, src, bonds, L, c, m, a, s);
     const int threads = Wr >= 256 ? 256 : (Wr >= 64 ? 64 * (int)((Wr + 63) / 64) : 64);
     const int64_t bpb = (Wr + threads - 1) / threads;
     const int64_t bands = (L + kGlassRows - 1) / kGlassRows;

@@ -18,11 +18,10 @@ hipError_t launch_half_sweep(uint64_t *words, int64_t L, int c, const Metro2 &m,
                              uint64_t seed, uint32_t stream_id, hipStream_t s,
                              int variant = kVariantDefault);
 // The queued row kernel on the target / source colour arrays of a
-// row-aligned lattice; `bonds` (four arrays of Wc words) for a +-J glass, or
-// nullptr for the ferromagnet.
+// row-aligned lattice; `bonds` (the interleaved bond words) for a +-J glass,
+// or nullptr for the ferromagnet.
 hipError_t launch_rows_queue(uint64_t *tgt, const uint64_t *src, const uint64_t *bonds,
-                             uint64_t Wc, int64_t L, int c, const Metro2 &m, const SweepArgs2 &a,
-                             hipStream_t s);
+                             int64_t L, int c, const Metro2 &m, const SweepArgs2 &a, hipStream_t s);
 // Half-sweep under any 5-entry acceptance table (heat bath).
 hipError_t launch_half_sweep5(uint64_t *words, int64_t L, int c, const rows::Table5 &tab,
                               uint64_t t, uint64_t seed, uint32_t stream_id, hipStream_t s);

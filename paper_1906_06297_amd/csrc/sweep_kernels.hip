@@ -96,6 +96,8 @@ __global__ __launch_bounds__(256) void k_sweep_rows(uint64_t *__restrict__ tgt,
 // so that HBM sees whole lines instead of the scattered 8-byte stores of
 // words finished in the queue.  A word still undecided then (a few per
 // thousand) is stored on its own when it is final.
+// two 64-bit words in one 16-byte load
+typedef uint64_t u64x2 __attribute__((ext_vector_type(2)));
 constexpr int kBandRows = 32;
 constexpr uint32_t kStreamBlocks = 3;
 constexpr uint32_t kQueueCap = 128; // < 64 entries left after a drain + 64 pushed per row
@@ -219,16 +221,17 @@ __device__ __forceinline__ uint32_t side_half_dpp(uint32_t cur_lo, uint32_t cur_
 // non-temporally, so that L2 keeps the target lines, whose words are stored
 // at different times, until they are complete.  Word indices fit in 32 bits.
 //
-// `Glass`: +-J couplings from four bond bit arrays (Wc words each: right bonds
-// of colour 0, 1, down bonds of colour 0, 1; bit 1 = -J), XORed into the
-// neighbour words before the class split (glass_kernels.hip has the layout).
-// The bond words stream in like the spin words; the left bond of a target
-// spin whose left neighbour is the side one takes the same one-spin shift.
+// `Glass`: +-J couplings from the interleaved bond words (4 per spin word:
+// right bonds of colour 0, 1, down bonds of colour 0, 1; bit 1 = -J), XORed
+// into the neighbour words before the class split (glass_kernels.hip has the
+// layout).  A lane's four bond words are one 32-byte load per row, streamed
+// like the spin rows; the left bond of a target spin whose left neighbour is
+// the side one takes the same one-spin shift.
 template <bool Anti, bool Plain, bool Dpp, bool Glass>
 __global__ __launch_bounds__(256) void k_sweep_rows_q(uint64_t *__restrict__ tgt,
                                                       const uint64_t *__restrict__ src,
                                                       const uint64_t *__restrict__ bonds,
-                                                      uint64_t Wc, uint32_t L, uint32_t Wr,
+                                                      uint32_t L, uint32_t Wr,
                                                       uint32_t waves_per_band, uint32_t nbands,
                                                       int c, SweepArgs2 a)
 {
@@ -265,11 +268,10 @@ __global__ __launch_bounds__(256) void k_sweep_rows_q(uint64_t *__restrict__ tgt
     };
     uint64_t prev = row((i0 == 0) ? L - 1 : i0 - 1)[wc];
     uint64_t cur = row(i0)[wc];
-    // Glass: bond arrays of the target colour (right rc, down dc) and of the
-    // other colour (right ro, down dO)
-    const uint32_t xrc = (uint32_t)c, xro = 1u - (uint32_t)c, xdc = 2u + (uint32_t)c,
-                   xdo = 3u - (uint32_t)c;
-    auto brow = [&](uint32_t x, uint32_t i) { return bonds + x * Wc + (size_t)i * Wr; };
+    // Glass: bond words of the target colour (right, down) and of the other
+    // colour (right ro, down dO) at word 4 k + x
+    const uint32_t xro = 1u - (uint32_t)c, xdo = 3u - (uint32_t)c;
+    auto bword = [&](uint32_t i, uint32_t w_) { return bonds + 4 * ((size_t)i * Wr + w_); };
     struct RowBonds {
         uint64_t dn, rt, ro, dnext; // down, right, other colour's right (aligned), dO of this row
         uint64_t radj;              // other colour's right bond at the left word (no Dpp)
@@ -278,22 +280,24 @@ __global__ __launch_bounds__(256) void k_sweep_rows_q(uint64_t *__restrict__ tgt
     auto row_bonds = [&](uint32_t i, bool lft) {
         RowBonds rb{};
         if (Glass) {
-            rb.dn = brow(xdc, i)[wc];
-            rb.rt = brow(xrc, i)[wc];
-            rb.ro = brow(xro, i)[wc];
-            rb.dnext = brow(xdo, i)[wc];
+            const u64x2 *p = reinterpret_cast<const u64x2 *>(bword(i, wc));
+            const u64x2 r01 = __builtin_nontemporal_load(p), d01 = __builtin_nontemporal_load(p + 1);
+            rb.rt = c ? r01.y : r01.x;
+            rb.ro = c ? r01.x : r01.y;
+            rb.dn = c ? d01.y : d01.x;
+            rb.dnext = c ? d01.x : d01.y;
             if (lft) {
                 if (Dpp) {
                     if (edge_l)
-                        rb.redge = rows::hi32(brow(xro, i)[wl]);
+                        rb.redge = rows::hi32(bword(i, wl)[xro]);
                 } else {
-                    rb.radj = brow(xro, i)[wl];
+                    rb.radj = bword(i, wl)[xro];
                 }
             }
         }
         return rb;
     };
-    uint64_t bup = Glass ? brow(xdo, (i0 == 0) ? L - 1 : i0 - 1)[wc] : 0;
+    uint64_t bup = Glass ? bword((i0 == 0) ? L - 1 : i0 - 1, wc)[xdo] : 0;
     // row i0 operands
     bool left = ((i0 + c) & 1) == 0;
     uint64_t next = __builtin_nontemporal_load(&row((i0 + 1 == L) ? 0 : i0 + 1)[wc]);
@@ -589,8 +593,7 @@ hipError_t launch_init(uint64_t *words, int64_t L, uint64_t seed, uint32_t strea
 // The queued row kernel for a row-aligned lattice (L % 128 == 0), with the
 // bond arrays of a +-J glass or without (bonds == nullptr).
 hipError_t launch_rows_queue(uint64_t *tgt, const uint64_t *src, const uint64_t *bonds,
-                             uint64_t Wc, int64_t L, int c, const Metro2 &m, const SweepArgs2 &a,
-                             hipStream_t s)
+                             int64_t L, int c, const Metro2 &m, const SweepArgs2 &a, hipStream_t s)
 {
     const int64_t Wr = L / 128;
     const int64_t wpb = (Wr + 63) / 64;
@@ -599,8 +602,8 @@ hipError_t launch_rows_queue(uint64_t *tgt, const uint64_t *src, const uint64_t 
     const dim3 grid((uint32_t)((waves + kWaves - 1) / kWaves)), block(64 * kWaves);
     const bool plain = m.randA && m.randB && !m.alwaysA && !m.alwaysB;
     const bool dpp = Wr % 64 == 0;
-    using Kernel = void (*)(uint64_t *, const uint64_t *, const uint64_t *, uint64_t, uint32_t,
-                            uint32_t, uint32_t, uint32_t, int, SweepArgs2);
+    using Kernel = void (*)(uint64_t *, const uint64_t *, const uint64_t *, uint32_t, uint32_t,
+                            uint32_t, uint32_t, int, SweepArgs2);
     static const Kernel kernels[16] = {
         k_sweep_rows_q<false, false, false, false>, k_sweep_rows_q<false, false, true, false>,
         k_sweep_rows_q<false, true, false, false>,  k_sweep_rows_q<false, true, true, false>,
@@ -612,7 +615,7 @@ hipError_t launch_rows_queue(uint64_t *tgt, const uint64_t *src, const uint64_t 
         k_sweep_rows_q<true, true, false, true>,    k_sweep_rows_q<true, true, true, true>};
     const Kernel k =
         kernels[(bonds ? 8 : 0) + (m.anti ? 4 : 0) + (plain ? 2 : 0) + (dpp ? 1 : 0)];
-    hipLaunchKernelGGL(k, grid, block, 0, s, tgt, src, bonds, Wc, (uint32_t)L, (uint32_t)Wr,
+    hipLaunchKernelGGL(k, grid, block, 0, s, tgt, src, bonds, (uint32_t)L, (uint32_t)Wr,
                        (uint32_t)wpb, (uint32_t)nbands, c, a);
     return hipGetLastError();
 }
@@ -634,7 +637,7 @@ hipError_t launch_half_sweep(uint64_t *words, int64_t L, int c, const Metro2 &m,
             hipLaunchKernelGGL(k_sweep_rows, dim3((uint32_t)(bands * bpb)), dim3(threads), 0, s,
                                tgt, src, L, Wr, bpb, c, a);
         } else {
-            return launch_rows_queue(tgt, src, nullptr, 0, L, c, m, a, s);
+            return launch_rows_queue(tgt, src, nullptr, L, c, m, a, s);
         }
     } else {
         hipLaunchKernelGGL(k_sweep_general, dim3(blocks_for(W, 256)), dim3(256), 0, s, tgt, src,

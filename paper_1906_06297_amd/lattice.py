@@ -176,7 +176,8 @@ def batch_words(Ls) -> int:
 class GlassBonds:
     """Bond signs of a +-J spin glass on an L x L lattice (device tensor of
     4 * words_per_colour(L) words: right bonds of colour 0, 1, down bonds of
-    colour 0, 1; bit 1 = coupling -J)."""
+    colour 0, 1, interleaved word by word, word k of array x at 4 k + x; bit
+    1 = coupling -J)."""
 
     def __init__(self, L: int, seed: int = None, stream_id: int = 0, right=None, down=None,
                  stream=None):

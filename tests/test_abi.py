@@ -150,7 +150,7 @@ def test_batch_argument_errors_without_device(lib):
     assert lib.ising_batch_destroy(None) == _lib.ISING_OK
 
 
-def test_batch_argument_errors_without_device(lib):
+def test_batch_create_rejects_malformed_batches(lib):
     """Empty and malformed batches are rejected before any device work."""
     from paper_1906_06297_amd import _lib
 
@@ -175,3 +175,25 @@ def test_batch_argument_errors_without_device(lib):
     assert create([16], [float("nan")]) == _lib.ISING_E_BADARG
     assert create([16], [0.4], J=float("inf")) == _lib.ISING_E_BADARG
     assert create([256], [0.4], bytes_=8) == _lib.ISING_E_SIZE  # buffer too small
+
+
+def test_glass_argument_errors_without_device(lib):
+    """Bond arrays: size, alignment and lattice checks come before device work."""
+    from paper_1906_06297_amd import _lib
+
+    W = lib.ising_words_per_colour(256)
+    need = 4 * W * 8
+    fake = ctypes.c_void_p(0x1000)  # 16-byte aligned, never dereferenced
+    assert lib.ising_glass_bonds_init(None, need, 256, 1, 0, None) == _lib.ISING_E_BADARG
+    assert lib.ising_glass_bonds_init(ctypes.c_void_p(0x1008), need, 256, 1, 0, None) == _lib.ISING_E_BADARG
+    assert b"aligned" in lib.ising_last_error()
+    assert lib.ising_glass_bonds_init(fake, need - 8, 256, 1, 0, None) == _lib.ISING_E_SIZE
+    assert lib.ising_glass_bonds_init(fake, need, 200, 1, 0, None) == _lib.ISING_E_SIZE  # L % 128
+    assert lib.ising_glass_bonds_init(fake, need, 256, 1, 1 << 24, None) == _lib.ISING_E_BADARG
+    good = _lib.LatticeStruct(words=0x1000, L=256, seed=1, stream_id=0)
+    assert lib.ising_glass_sweep(ctypes.byref(good), ctypes.c_void_p(0x1008), need, 0.4, 1.0, 1, 0,
+                                 None) == _lib.ISING_E_BADARG
+    assert lib.ising_glass_sweep(ctypes.byref(good), fake, need, 0.4, 1.0, -1, 0,
+                                 None) == _lib.ISING_E_BADARG
+    assert lib.ising_glass_observables(ctypes.byref(good), fake, need, None, None,
+                                       None) == _lib.ISING_E_BADARG

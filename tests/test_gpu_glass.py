@@ -23,7 +23,7 @@ def gpu():
 def unpack_bonds(words, L):
     """Device bond arrays -> (Jr, Jd) int8 +1/-1 (host side, independent of the library)."""
     W = (L * L // 2 + 63) // 64
-    w = words.cpu().numpy().view(np.uint64).reshape(4, W)
+    w = words.cpu().numpy().view(np.uint64).reshape(W, 4).T  # word k of array x at 4 k + x
     H = L // 2
     Jr = np.zeros((L, L), np.int8)
     Jd = np.zeros((L, L), np.int8)
