@@ -153,6 +153,45 @@ int ising_glass_sweep(const ising_lattice *lat, const uint64_t *d_bonds, size_t 
 int ising_glass_observables(const ising_lattice *lat, const uint64_t *d_bonds, size_t bond_bytes,
                             int64_t *d_bond, int64_t *d_mag, void *hip_stream);
 
+/* Matrix-multiply formulation of the sweep (Sec. "Tensor Core
+ * Implementation": the bidiagonal kernel matrix K and the four block
+ * equations for the neighbour sums of the black and white blocks), kept as a
+ * measured negative control beside the bit-packed kernels; L % 256 == 0
+ * (ISING_E_SIZE otherwise).
+ *
+ * Spin buffer (device, caller-owned, 16-byte aligned, ising_mm_lattice_bytes
+ * = 2 L^2 bytes): one IEEE binary16 per spin (+1 = 0x3C00, -1 = 0xBC00); the
+ * lattice as 256 x 256 sub-lattices (row-major over sub-lattices), each as
+ * four 128 x 128 row-major blocks sigma_ab, block index 2a + b, holding the
+ * sites (2r + a, 2q + b) of the sub-lattice.  Sum buffer (device, 16-byte
+ * aligned, ising_mm_sums_bytes = L^2 bytes): the fp16 neighbour sums of one
+ * colour, used by the unfused form only.  Both return -1 for an unsupported
+ * L. */
+int64_t ising_mm_lattice_bytes(int64_t L);
+int64_t ising_mm_sums_bytes(int64_t L);
+
+/* Converts the bit-packed lattice `lat` into the fp16 block layout, or back
+ * (the words of `lat` are overwritten).  Asynchronous. */
+int ising_mm_from_words(const ising_lattice *lat, uint16_t *d_spins, size_t bytes,
+                        void *hip_stream);
+int ising_mm_to_words(const ising_lattice *lat, const uint16_t *d_spins, size_t bytes,
+                      void *hip_stream);
+
+/* nsweeps sweeps of the fp16 lattice (seed and stream_id as in
+ * ising_lattice).  Per half-sweep the neighbour sums of the colour are
+ * nn = P M1 + M2 Q per target block (P, Q: the blocks holding its horizontal
+ * and vertical neighbours; M1, M2: K or its transpose) on fp16 MFMA, plus the
+ * edge neighbours from the adjacent sub-lattices, then each run of 64
+ * same-colour spins of a row is decided with the Philox counters, planes and
+ * exact compare of ising_sweep -- the same lattice, bit for bit, as
+ * ising_sweep from the same start.  fused = 0: the paper's three steps
+ * (products writing the sums to d_sums, a boundary kernel, an update kernel);
+ * fused = 1: one kernel per half-sweep with the sums kept on chip (d_sums may
+ * be NULL).  Asynchronous. */
+int ising_mm_sweep(int64_t L, uint64_t seed, uint32_t stream_id, uint16_t *d_spins,
+                   size_t spin_bytes, uint16_t *d_sums, size_t sum_bytes, double beta, double J,
+                   int64_t nsweeps, uint64_t rng_counter, int fused, void *hip_stream);
+
 /* Copies the lattice to host_spins as an L x L row-major int8 array of
  * +1/-1.  Synchronises hip_stream. */
 int ising_get_spins(const ising_lattice *lat, int8_t *host_spins, void *hip_stream);

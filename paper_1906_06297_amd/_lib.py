@@ -52,6 +52,12 @@ SIGNATURES = {
     "ising_glass_set_bonds": (ctypes.c_int, [_vp, ctypes.c_size_t, _i64, _vp, _vp, _vp]),
     "ising_glass_sweep": (ctypes.c_int, [_lat_p, _vp, ctypes.c_size_t, _dbl, _dbl, _i64, _u64, _vp]),
     "ising_glass_observables": (ctypes.c_int, [_lat_p, _vp, ctypes.c_size_t, _vp, _vp, _vp]),
+    "ising_mm_lattice_bytes": (_i64, [_i64]),
+    "ising_mm_sums_bytes": (_i64, [_i64]),
+    "ising_mm_from_words": (ctypes.c_int, [_lat_p, _vp, ctypes.c_size_t, _vp]),
+    "ising_mm_to_words": (ctypes.c_int, [_lat_p, _vp, ctypes.c_size_t, _vp]),
+    "ising_mm_sweep": (ctypes.c_int, [_i64, _u64, _u32, _vp, ctypes.c_size_t, _vp, ctypes.c_size_t,
+                                      _dbl, _dbl, _i64, _u64, ctypes.c_int, _vp]),
     "ising_thresholds_rule": (ctypes.c_int, [_dbl, _dbl, ctypes.c_int, ctypes.POINTER(_u64)]),
     "ising_sweep_rule": (ctypes.c_int, [_lat_p, _dbl, _dbl, ctypes.c_int, _i64, _u64, _vp]),
     "ising_sweep_traced": (ctypes.c_int, [_lat_p, _dbl, _dbl, _i64, _u64, _vp, _vp, _vp]),

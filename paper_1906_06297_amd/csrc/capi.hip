@@ -96,21 +96,6 @@ Metro2 metro2_params(double beta, double J)
     return m;
 }
 
-} // namespace host
-} // namespace ising
-
-namespace {
-
-using ising::host::fail;
-using ising::host::hip_fail;
-using ising::host::ok;
-
-// Half-sweep kernel selection (for tests and measurements; 0 = default).
-int g_variant = 0;
-
-// Largest supported size: chunk indices must fit the 32-bit counter word.
-constexpr int64_t kMaxL = 741454; // floor(sqrt(128 * (2^32 - 1)))
-
 int check_L(int64_t L)
 {
     if (L < 4 || (L & 1))
@@ -142,6 +127,23 @@ int check_temperature(double beta, double J)
         return fail(ISING_E_BADARG, "J must be finite");
     return ISING_OK;
 }
+
+} // namespace host
+} // namespace ising
+
+namespace {
+
+using ising::host::fail;
+using ising::host::hip_fail;
+using ising::host::ok;
+
+// Half-sweep kernel selection (for tests and measurements; 0 = default).
+int g_variant = 0;
+
+using ising::host::check_L;
+using ising::host::check_lattice;
+using ising::host::check_temperature;
+using ising::host::kMaxL;
 
 int64_t words_per_colour(int64_t L) { return (L * L / 2 + 63) / 64; }
 

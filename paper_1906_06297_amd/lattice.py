@@ -165,6 +165,42 @@ class Lattice:
 _VIEW = object()
 
 
+class MatmulLattice:
+    """The matrix-multiply formulation of the sweep (fp16 spins in 256 x 256
+    sub-lattices of four 128 x 128 blocks; L % 256 == 0), started from the
+    bit-packed lattice `lat` (same L, seed and stream).  `fused` picks the
+    one-kernel form; otherwise the products, boundary and update kernels run
+    with the sums in HBM."""
+
+    def __init__(self, lat: Lattice, fused: bool = True, stream=None):
+        lib = _lib.load()
+        self.L, self.seed, self.stream_id = lat.L, lat.seed, lat.stream_id
+        nb = lib.ising_mm_lattice_bytes(self.L)
+        if nb < 0:
+            raise ValueError(f"unsupported lattice size {self.L} (L % 256 == 0 needed)")
+        dev = lat.words.device
+        self.spins = torch.empty(nb // 2, dtype=torch.int16, device=dev)
+        self.fused = bool(fused)
+        self.sums = (None if self.fused else
+                     torch.empty(lib.ising_mm_sums_bytes(self.L) // 2, dtype=torch.int16, device=dev))
+        _lib.check(lib.ising_mm_from_words(ctypes.byref(lat.desc), _ptr(self.spins), nb,
+                                           _stream_handle(stream)))
+
+    def sweep(self, beta: float, J: float = 1.0, nsweeps: int = 1, rng_counter: int = 0,
+              stream=None) -> None:
+        sums = self.sums
+        _lib.check(_lib.load().ising_mm_sweep(
+            self.L, self.seed, self.stream_id, _ptr(self.spins), self.spins.numel() * 2,
+            _ptr(sums) if sums is not None else None, sums.numel() * 2 if sums is not None else 0,
+            float(beta), float(J), int(nsweeps), int(rng_counter), int(self.fused),
+            _stream_handle(stream)))
+
+    def to_lattice(self, lat: Lattice, stream=None) -> None:
+        """Writes the spins into the bit-packed lattice `lat` (same L)."""
+        _lib.check(_lib.load().ising_mm_to_words(ctypes.byref(lat.desc), _ptr(self.spins),
+                                                 self.spins.numel() * 2, _stream_handle(stream)))
+
+
 def batch_words(Ls) -> int:
     arr = (ctypes.c_int64 * len(Ls))(*[int(x) for x in Ls])
     n = _lib.load().ising_batch_words(len(Ls), arr)

@@ -197,3 +197,31 @@ def test_glass_argument_errors_without_device(lib):
                                  None) == _lib.ISING_E_BADARG
     assert lib.ising_glass_observables(ctypes.byref(good), fake, need, None, None,
                                        None) == _lib.ISING_E_BADARG
+
+
+def test_matmul_argument_errors_without_device(lib):
+    """Matrix-multiply form: size, alignment and buffer checks before device work."""
+    from paper_1906_06297_amd import _lib
+
+    assert lib.ising_mm_lattice_bytes(256) == 2 * 256 * 256
+    assert lib.ising_mm_lattice_bytes(384) == -1
+    assert lib.ising_mm_sums_bytes(768) == 768 * 768
+    fake = ctypes.c_void_p(0x1000)
+    need = 2 * 256 * 256
+
+    def sweep(L=256, spins=fake, sb=need, sums=fake, nb=256 * 256, fused=0, beta=0.4, n=1):
+        return lib.ising_mm_sweep(L, 1, 0, spins, sb, sums, nb, beta, 1.0, n, 0, fused, None)
+
+    assert sweep(L=384) == _lib.ISING_E_SIZE
+    assert sweep(spins=None) == _lib.ISING_E_BADARG
+    assert sweep(spins=ctypes.c_void_p(0x1002)) == _lib.ISING_E_BADARG
+    assert sweep(sb=need - 2) == _lib.ISING_E_SIZE
+    assert sweep(sums=None) == _lib.ISING_E_BADARG  # the three-kernel form needs the sums
+    assert sweep(nb=100) == _lib.ISING_E_SIZE
+    assert sweep(fused=2) == _lib.ISING_E_BADARG
+    assert sweep(beta=-1.0) == _lib.ISING_E_BADARG
+    assert sweep(n=-1) == _lib.ISING_E_BADARG
+    lat = _lib.LatticeStruct(words=0x1000, L=384, seed=1, stream_id=0)
+    assert lib.ising_mm_from_words(ctypes.byref(lat), fake, 1 << 20, None) == _lib.ISING_E_SIZE
+    lat = _lib.LatticeStruct(words=0x1000, L=256, seed=1, stream_id=0)
+    assert lib.ising_mm_to_words(ctypes.byref(lat), fake, need - 1, None) == _lib.ISING_E_SIZE
