@@ -30,6 +30,7 @@ import numpy as np  # noqa: E402
 import workloads  # noqa: E402
 
 HBM_PEAK_GBS = 8000.0  # MI355X HBM3E, GB/s
+MFMA_FP16_PEAK_TFLOPS = 2500.0  # MI355X dense fp16 MFMA, TFLOP/s
 KERNEL_SOURCES = ("paper_1906_06297_amd/csrc/sweep_kernels.hip",
                   "paper_1906_06297_amd/csrc/ising_device.hpp",
                   "paper_1906_06297_amd/csrc/ising_rows.hpp")
@@ -276,6 +277,71 @@ def bench_glass(ising, torch, bufs, steps: int) -> dict:
     }
 
 
+def bench_matmul(ising, torch, steps: int, sizes=None) -> dict:
+    """The matrix-multiply formulation of the sweep (Sec. "Tensor Core
+    Implementation") against the bit-packed kernel on the same lattices: the
+    paper's tensor-core lattice sizes (20..640 x 128)^2 and the headline
+    L = 65536, beta_c, seed 7, from a fresh start each.  Both matmul forms
+    yield the bit-packed kernel's lattice bit for bit."""
+    beta, J, seed = workloads.BETA_CRIT_CONFIG, 1.0, 7
+    if not sizes:
+        sizes = [128 * f for f in (20, 40, 80, 160, 320, 640)] + [65536]
+    rows = []
+    head = None
+    for L in sizes:
+        n = max(steps, min(200, int(5e9 / (L * L))))
+        row = {"L": L, "sweeps": n}
+
+        def timed(fn):
+            fn(1, 0)  # warmup sweep
+            torch.cuda.synchronize()
+            e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+            e0.record()
+            fn(n, 1)
+            e1.record()
+            torch.cuda.synchronize()
+            return e0.elapsed_time(e1) / n  # ms per sweep
+
+        lat = ising.Lattice(L, seed)
+        ms = timed(lambda k, ctr: lat.sweep(beta, J, k, ctr))
+        row["bitpacked_flips_per_ns"] = L * L / (ms * 1e6)
+        for fused, key in ((True, "mm_fused"), (False, "mm_three_kernel")):
+            lat = ising.Lattice(L, seed)
+            mm = ising.MatmulLattice(lat, fused=fused)
+            ms = timed(lambda k, ctr: mm.sweep(beta, J, k, ctr))
+            row[f"{key}_flips_per_ns"] = L * L / (ms * 1e6)
+            row[f"{key}_half_sweep_us"] = ms * 1e3 / 2
+            del mm
+            torch.cuda.empty_cache()
+        del lat
+        torch.cuda.empty_cache()
+        row["bitpacked_over_mm_fused"] = row["bitpacked_flips_per_ns"] / row["mm_fused_flips_per_ns"]
+        rows.append(row)
+        if L == 65536:
+            head = row
+    out = {
+        "workload": f"matrix-multiply neighbour sums (fp16 MFMA 16x16x32, 128 x 128 blocks of "
+                    f"256 x 256 sub-lattices) vs the bit-packed kernel, beta {beta}, J {J}, seed "
+                    f"{seed}, L in {sizes}",
+        "per_L": rows,
+    }
+    if head is not None:
+        # the fused kernel at L = 65536: dense fp16 MFMA work and the bytes an
+        # fp16 half-sweep must move (source colour read, target read and written)
+        tiles = 2 * (65536 // 256) ** 2
+        flops = tiles * 2 * 2 * 128 ** 3
+        byts = 6 * (65536 * 65536 // 2)
+        us = head["mm_fused_half_sweep_us"]
+        out["fused_L65536"] = {
+            "mfma_dense_tflops": flops / (us * 1e-6) / 1e12,
+            "mfma_frac_of_fp16_peak": flops / (us * 1e-6) / 1e12 / MFMA_FP16_PEAK_TFLOPS,
+            "useful_flop_fraction": 1 / 64,
+            "alg_bytes_per_launch": byts,
+            "hbm_frac": byts / (us * 1e-6) / 1e9 / HBM_PEAK_GBS,
+        }
+    return out
+
+
 def bench_learned(ising, torch, L: int = 32, betas=(0.42, 0.44, 0.46), C: int = 32,
                   chains: int = 4096, rounds: int = 400, train_steps: int = 1500,
                   data_log2: int = 20) -> dict:
@@ -355,6 +421,11 @@ def main() -> int:
                          "beside the headline (0 = skip)")
     ap.add_argument("--glass-sweeps", type=int, default=20,
                     help="sweeps per beta of the +-J spin glass on the headline lattices (0 = skip)")
+    ap.add_argument("--matmul-sweeps", type=int, default=5,
+                    help="minimum sweeps per size of the matrix-multiply comparison (0 = skip)")
+    ap.add_argument("--matmul-L", type=int, nargs="*", default=None,
+                    help="lattice sizes of the matrix-multiply comparison (default: the paper's "
+                         "tensor-core sizes and 65536)")
     ap.add_argument("--hold-seconds", type=float, default=0.0,
                     help="only run L = 65536 sweeps at beta_c for this many seconds (for reading "
                          "clocks and power beside a steady load) and exit")
@@ -467,6 +538,8 @@ def main() -> int:
         out["heatbath"] = bench_heatbath(ising, torch, bufs, args.heatbath_sweeps)
     if args.glass_sweeps > 0:
         out["glass"] = bench_glass(ising, torch, bufs, args.glass_sweeps)
+    if args.matmul_sweeps > 0:
+        out["matmul"] = bench_matmul(ising, torch, args.matmul_sweeps, args.matmul_L)
     if args.batched_sweeps > 0:
         out["batched"] = bench_batched(ising, torch, args.batched_sweeps)
     if args.learned_rounds > 0:
