@@ -31,7 +31,8 @@ def thresholds(beta: float, J: float, rule: str = "metropolis") -> np.ndarray:
 
 
 def set_sweep_kernel(variant: int) -> None:
-    """0 = default, 1 = general-geometry kernel, 2 = row kernel without work queue."""
+    """0 = default (by size), 1 = general-geometry kernel, 2 = row kernel without work
+    queue, 3 = queued row kernel at every row-aligned size."""
     _lib.check(_lib.load().ising_set_sweep_kernel(int(variant)))
 
 
