@@ -278,8 +278,8 @@ def bench_glass(ising, torch, bufs, steps: int) -> dict:
 
 
 def bench_matmul(ising, torch, steps: int, sizes=None) -> dict:
-    """The matrix-multiply formulation of the sweep (Sec. "Tensor Core
-    Implementation") against the bit-packed kernel on the same lattices: the
+    """The matrix-multiply formulation of the sweep (Sec. 3.2, the tensor-core
+    implementation) against the bit-packed kernel on the same lattices: the
     paper's tensor-core lattice sizes (20..640 x 128)^2 and the headline
     L = 65536, beta_c, seed 7, from a fresh start each.  Both matmul forms
     yield the bit-packed kernel's lattice bit for bit."""

@@ -153,11 +153,10 @@ int ising_glass_sweep(const ising_lattice *lat, const uint64_t *d_bonds, size_t 
 int ising_glass_observables(const ising_lattice *lat, const uint64_t *d_bonds, size_t bond_bytes,
                             int64_t *d_bond, int64_t *d_mag, void *hip_stream);
 
-/* Matrix-multiply formulation of the sweep (Sec. "Tensor Core
- * Implementation": the bidiagonal kernel matrix K and the four block
- * equations for the neighbour sums of the black and white blocks), kept as a
- * measured negative control beside the bit-packed kernels; L % 256 == 0
- * (ISING_E_SIZE otherwise).
+/* Matrix-multiply formulation of the sweep (Sec. 3.2: the bidiagonal kernel
+ * matrix K and the four block equations for the neighbour sums of the black
+ * and white blocks), kept as a measured negative control beside the
+ * bit-packed kernels; L % 256 == 0 (ISING_E_SIZE otherwise).
  *
  * Spin buffer (device, caller-owned, 16-byte aligned, ising_mm_lattice_bytes
  * = 2 L^2 bytes): one IEEE binary16 per spin (+1 = 0x3C00, -1 = 0xBC00); the

@@ -1,6 +1,6 @@
 // gfx950 kernels of the matrix-multiply formulation of the checkerboard sweep
-// (Sec. "Tensor Core Implementation"), kept as a measured negative control
-// beside the bit-packed kernels.
+// (Sec. 3.2, the tensor-core implementation), kept as a measured negative
+// control beside the bit-packed kernels.
 //
 // Storage: one fp16 per spin (+1 = 0x3C00, -1 = 0xBC00), the lattice cut into
 // 256 x 256 sub-lattices, each stored as four 128 x 128 row-major blocks

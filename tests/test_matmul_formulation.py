@@ -1,7 +1,7 @@
-"""The matrix-multiply formulation of the neighbour sums (Sec. "Tensor Core
-Implementation": the bidiagonal kernel matrix K and the four block equations
-for the sub-lattice local sums of the black and white blocks), checked in
-numpy against the plain four-neighbour stencil sum on a periodic lattice.
+"""The matrix-multiply formulation of the neighbour sums (Sec. 3.2: the
+bidiagonal kernel matrix K and the four block equations for the sub-lattice
+local sums of the black and white blocks), checked in numpy against the
+plain four-neighbour stencil sum on a periodic lattice.
 
 This pins the reading the MFMA kernels implement: blocks sigma_ab hold the
 sites (2r + a, 2q + b) of a 256 x 256 sub-lattice, K has ones on the
