@@ -141,25 +141,42 @@ using ising::host::ok;
 int g_variant = 0;
 
 // The default kernel for a Metropolis half-sweep.  The queued row kernel
-// gives each wavefront a 32-row band of 64 word columns, so a small lattice
-// leaves most of the 1024 SIMDs idle while a few wavefronts walk their rows;
-// below 1024 such wavefronts (L < 16384 or so) the general kernel, one thread
-// per word, is faster (at L = 2048: 7 us against 39 us per half-sweep).
+// gives each wavefront a band of rows of 64 word columns and walks the rows
+// in sequence, so a lattice with few bands leaves most of the 1024 SIMDs
+// idle.  Measured per half-sweep at beta_c: with at least 16384 wavefronts of
+// 32-row bands (L >= 65536) the band height hardly matters; below that 8-row
+// bands win (L = 16384: 27 us against 49 us with 32 rows, 54 us general);
+// with fewer than 1024 wavefronts even then (L < 8192) the general kernel,
+// one thread per word, is fastest (L = 2048: 6.5 us against 39 us).
 int default_variant(int64_t L)
 {
     if (L % 128 != 0)
         return ising::kVariantGeneral;
-    const int64_t waves = (L / 128 + 63) / 64 * ((L + 31) / 32);
-    return waves >= 1024 ? ising::kVariantDefault : ising::kVariantGeneral;
+    const int64_t segs = (L / 128 + 63) / 64; // wavefronts across a row
+    if (segs * ((L + 31) / 32) >= 16384)
+        return ising::kVariantDefault;
+    if (segs * ((L + 7) / 8) >= 1024)
+        return ising::kVariantQueue8;
+    return ising::kVariantGeneral;
 }
 
 // Kernel for ising_sweep: the size-dependent default, or the one the caller
-// forced (3: the queued row kernel whatever the size).
+// forced (3, 4, 5: the queued row kernel with 32-, 16- or 8-row bands
+// whatever the size).
 int sweep_variant(int64_t L)
 {
-    if (g_variant == 0)
+    switch (g_variant) {
+    case 0:
         return default_variant(L);
-    return g_variant == 3 ? ising::kVariantDefault : g_variant;
+    case 3:
+        return ising::kVariantDefault;
+    case 4:
+        return ising::kVariantQueue16;
+    case 5:
+        return ising::kVariantQueue8;
+    default:
+        return g_variant;
+    }
 }
 
 using ising::host::check_L;
@@ -478,7 +495,7 @@ int ising_glass_sweep(const ising_lattice *lat, const uint64_t *d_bonds, size_t 
             const uint64_t t = 2 * (rng_counter + (uint64_t)sw) + (uint64_t)c;
             hipError_t e = ising::launch_glass_half_sweep(lat->words, d_bonds, lat->L, c, m, t,
                                                           lat->seed, lat->stream_id, s,
-                                                          g_variant == 3 ? 0 : g_variant);
+                                                          g_variant >= 3 ? 0 : g_variant);
             if (e != hipSuccess)
                 return hip_fail(e, "half-sweep launch");
         }
@@ -503,8 +520,8 @@ int ising_glass_observables(const ising_lattice *lat, const uint64_t *d_bonds, s
 
 int ising_set_sweep_kernel(int variant)
 {
-    if (variant < 0 || variant > 3)
-        return fail(ISING_E_BADARG, "sweep kernel variant must be 0, 1, 2 or 3");
+    if (variant < 0 || variant > 5)
+        return fail(ISING_E_BADARG, "sweep kernel variant must be 0 to 5");
     g_variant = variant;
     return ok();
 }

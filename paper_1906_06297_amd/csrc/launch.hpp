@@ -10,9 +10,16 @@ namespace ising {
 
 hipError_t launch_init(uint64_t *words, int64_t L, uint64_t seed, uint32_t stream_id,
                        hipStream_t s);
-// Half-sweep kernel choice: the default picks the queued row kernel for
-// row-aligned sizes (L % 128 == 0) and the general kernel otherwise.
-enum { kVariantDefault = 0, kVariantGeneral = 1, kVariantRowsPlain = 2 };
+// Half-sweep kernel choice: the default is the queued row kernel with 32-row
+// bands for row-aligned sizes (L % 128 == 0) and the general kernel
+// otherwise; the queued kernel with 16- or 8-row bands on request.
+enum {
+    kVariantDefault = 0,
+    kVariantGeneral = 1,
+    kVariantRowsPlain = 2,
+    kVariantQueue16 = 4,
+    kVariantQueue8 = 5
+};
 
 hipError_t launch_half_sweep(uint64_t *words, int64_t L, int c, const Metro2 &m, uint64_t t,
                              uint64_t seed, uint32_t stream_id, hipStream_t s,
@@ -21,7 +28,8 @@ hipError_t launch_half_sweep(uint64_t *words, int64_t L, int c, const Metro2 &m,
 // row-aligned lattice; `bonds` (the interleaved bond words) for a +-J glass,
 // or nullptr for the ferromagnet.
 hipError_t launch_rows_queue(uint64_t *tgt, const uint64_t *src, const uint64_t *bonds,
-                             int64_t L, int c, const Metro2 &m, const SweepArgs2 &a, hipStream_t s);
+                             int64_t L, int c, const Metro2 &m, const SweepArgs2 &a, hipStream_t s,
+                             int band);
 // Half-sweep under any 5-entry acceptance table (heat bath).
 hipError_t launch_half_sweep5(uint64_t *words, int64_t L, int c, const rows::Table5 &tab,
                               uint64_t t, uint64_t seed, uint32_t stream_id, hipStream_t s);

@@ -98,7 +98,7 @@ __global__ __launch_bounds__(256) void k_sweep_rows(uint64_t *__restrict__ tgt,
 // thousand) is stored on its own when it is final.
 // two 64-bit words in one 16-byte load
 typedef uint64_t u64x2 __attribute__((ext_vector_type(2)));
-constexpr int kBandRows = 32;
+constexpr int kBandRows = 32; // rows per band at large sizes (16 and 8 for mid sizes)
 constexpr uint32_t kStreamBlocks = 3;
 constexpr uint32_t kQueueCap = 128; // < 64 entries left after a drain + 64 pushed per row
 constexpr int kWaves = 4;
@@ -211,7 +211,8 @@ __device__ __forceinline__ uint32_t side_half_dpp(uint32_t cur_lo, uint32_t cur_
 }
 
 // L % 128 == 0.  A wavefront owns 64 consecutive word columns of a band of
-// kBandRows rows and marches down it, keeping the three source rows it needs
+// Band rows (32; 16 or 8 where a lattice has too few bands to fill the chip)
+// and marches down it, keeping the three source rows it needs
 // in registers and loading the next row's words one step ahead; the side
 // neighbour comes from the adjacent word of the same source row (Sec. 3.3,
 // Fig. 3).  `Dpp` (Wr % 64 == 0): the adjacent words are the neighbour lanes'
@@ -227,7 +228,7 @@ __device__ __forceinline__ uint32_t side_half_dpp(uint32_t cur_lo, uint32_t cur_
 // layout).  A lane's four bond words are one 32-byte load per row, streamed
 // like the spin rows; the left bond of a target spin whose left neighbour is
 // the side one takes the same one-spin shift.
-template <bool Anti, bool Plain, bool Dpp, bool Glass>
+template <int Band, bool Anti, bool Plain, bool Dpp, bool Glass>
 __global__ __launch_bounds__(256) void k_sweep_rows_q(uint64_t *__restrict__ tgt,
                                                       const uint64_t *__restrict__ src,
                                                       const uint64_t *__restrict__ bonds,
@@ -254,7 +255,7 @@ __global__ __launch_bounds__(256) void k_sweep_rows_q(uint64_t *__restrict__ tgt
     const uint32_t wr = (wc + 1 >= Wr) ? 0 : wc + 1;
     // Dpp: the one word each edge lane reads
     const bool edge_l = lane == 0, edge_r = lane == 63;
-    const uint32_t i0 = band * kBandRows;
+    const uint32_t i0 = band * Band;
     const rows::ClassMasks cm = rows::class_masks(a.m);
     auto row = [&](uint32_t i) { return src + (size_t)i * Wr; }; // wave-uniform pointer
     auto side_word = [&](uint32_t i, bool left) -> uint64_t { return row(i)[left ? wl : wr]; };
@@ -311,7 +312,7 @@ __global__ __launch_bounds__(256) void k_sweep_rows_q(uint64_t *__restrict__ tgt
     RowBonds rb = row_bonds(i0, left);
     auto trow = [&](uint32_t i) { return tgt + (size_t)i * Wr; }; // wave-uniform pointer
     uint32_t head = 0, len = 0, r_last = 0;
-    for (uint32_t r = 0; r < (uint32_t)kBandRows; ++r) {
+    for (uint32_t r = 0; r < (uint32_t)Band; ++r) {
         const uint32_t i = i0 + r;
         if (i >= L)
             break;
@@ -321,7 +322,7 @@ __global__ __launch_bounds__(256) void k_sweep_rows_q(uint64_t *__restrict__ tgt
         if (r >= kRing) // row r - kRing leaves the ring
             ring_store(rg, sl, trow(i - kRing), wc, active, lane, true);
         // loads of row i + 1, in flight while row i is decided
-        const bool more = r + 1 < kBandRows && i + 1 < L;
+        const bool more = r + 1 < Band && i + 1 < L;
         const uint32_t i1 = (i + 1 == L) ? 0 : i + 1;
         const uint32_t i2 = (i1 + 1 == L) ? 0 : i1 + 1;
         const bool left1 = !left;
@@ -591,30 +592,35 @@ hipError_t launch_init(uint64_t *words, int64_t L, uint64_t seed, uint32_t strea
 }
 
 // The queued row kernel for a row-aligned lattice (L % 128 == 0), with the
-// bond arrays of a +-J glass or without (bonds == nullptr).
+// bond arrays of a +-J glass (32-row bands) or without (bonds == nullptr;
+// band = 32, 16 or 8 rows).
 hipError_t launch_rows_queue(uint64_t *tgt, const uint64_t *src, const uint64_t *bonds,
-                             int64_t L, int c, const Metro2 &m, const SweepArgs2 &a, hipStream_t s)
+                             int64_t L, int c, const Metro2 &m, const SweepArgs2 &a, hipStream_t s,
+                             int band)
 {
     const int64_t Wr = L / 128;
     const int64_t wpb = (Wr + 63) / 64;
-    const int64_t nbands = (L + kBandRows - 1) / kBandRows;
+    if (bonds)
+        band = kBandRows;
+    const int64_t nbands = (L + band - 1) / band;
     const int64_t waves = wpb * nbands;
     const dim3 grid((uint32_t)((waves + kWaves - 1) / kWaves)), block(64 * kWaves);
     const bool plain = m.randA && m.randB && !m.alwaysA && !m.alwaysB;
     const bool dpp = Wr % 64 == 0;
     using Kernel = void (*)(uint64_t *, const uint64_t *, const uint64_t *, uint32_t, uint32_t,
                             uint32_t, uint32_t, int, SweepArgs2);
-    static const Kernel kernels[16] = {
-        k_sweep_rows_q<false, false, false, false>, k_sweep_rows_q<false, false, true, false>,
-        k_sweep_rows_q<false, true, false, false>,  k_sweep_rows_q<false, true, true, false>,
-        k_sweep_rows_q<true, false, false, false>,  k_sweep_rows_q<true, false, true, false>,
-        k_sweep_rows_q<true, true, false, false>,   k_sweep_rows_q<true, true, true, false>,
-        k_sweep_rows_q<false, false, false, true>,  k_sweep_rows_q<false, false, true, true>,
-        k_sweep_rows_q<false, true, false, true>,   k_sweep_rows_q<false, true, true, true>,
-        k_sweep_rows_q<true, false, false, true>,   k_sweep_rows_q<true, false, true, true>,
-        k_sweep_rows_q<true, true, false, true>,    k_sweep_rows_q<true, true, true, true>};
-    const Kernel k =
-        kernels[(bonds ? 8 : 0) + (m.anti ? 4 : 0) + (plain ? 2 : 0) + (dpp ? 1 : 0)];
+#define ISING_ROWS_Q8(B, G)                                                                       \
+    k_sweep_rows_q<B, false, false, false, G>, k_sweep_rows_q<B, false, false, true, G>,          \
+        k_sweep_rows_q<B, false, true, false, G>, k_sweep_rows_q<B, false, true, true, G>,        \
+        k_sweep_rows_q<B, true, false, false, G>, k_sweep_rows_q<B, true, false, true, G>,        \
+        k_sweep_rows_q<B, true, true, false, G>, k_sweep_rows_q<B, true, true, true, G>
+    static const Kernel kernels[4][8] = {{ISING_ROWS_Q8(32, false)},
+                                         {ISING_ROWS_Q8(16, false)},
+                                         {ISING_ROWS_Q8(8, false)},
+                                         {ISING_ROWS_Q8(32, true)}};
+#undef ISING_ROWS_Q8
+    const int set = bonds ? 3 : (band == 32 ? 0 : (band == 16 ? 1 : 2));
+    const Kernel k = kernels[set][(m.anti ? 4 : 0) + (plain ? 2 : 0) + (dpp ? 1 : 0)];
     hipLaunchKernelGGL(k, grid, block, 0, s, tgt, src, bonds, (uint32_t)L, (uint32_t)Wr,
                        (uint32_t)wpb, (uint32_t)nbands, c, a);
     return hipGetLastError();
@@ -637,7 +643,8 @@ hipError_t launch_half_sweep(uint64_t *words, int64_t L, int c, const Metro2 &m,
             hipLaunchKernelGGL(k_sweep_rows, dim3((uint32_t)(bands * bpb)), dim3(threads), 0, s,
                                tgt, src, L, Wr, bpb, c, a);
         } else {
-            return launch_rows_queue(tgt, src, nullptr, L, c, m, a, s);
+            const int band = variant == kVariantQueue16 ? 16 : (variant == kVariantQueue8 ? 8 : 32);
+            return launch_rows_queue(tgt, src, nullptr, L, c, m, a, s, band);
         }
     } else {
         hipLaunchKernelGGL(k_sweep_general, dim3(blocks_for(W, 256)), dim3(256), 0, s, tgt, src,

@@ -32,7 +32,8 @@ def thresholds(beta: float, J: float, rule: str = "metropolis") -> np.ndarray:
 
 def set_sweep_kernel(variant: int) -> None:
     """0 = default (by size), 1 = general-geometry kernel, 2 = row kernel without work
-    queue, 3 = queued row kernel at every row-aligned size."""
+    queue, 3, 4, 5 = queued row kernel with 32-, 16-, 8-row bands at every row-aligned
+    size."""
     _lib.check(_lib.load().ising_set_sweep_kernel(int(variant)))
 
 

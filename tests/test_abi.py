@@ -97,7 +97,7 @@ def test_argument_errors_without_device(lib):
     assert lib.ising_sweep(ctypes.byref(odd), 0.4, 1.0, 1, 0, None) == _lib.ISING_E_BADARG
     assert lib.ising_sweep_traced(ctypes.byref(good), 0.4, 1.0, 3, 0, None, None, None) == _lib.ISING_E_BADARG
     assert lib.ising_observables(ctypes.byref(good), None, None, None) == _lib.ISING_E_BADARG
-    assert lib.ising_set_sweep_kernel(4) == _lib.ISING_E_BADARG
+    assert lib.ising_set_sweep_kernel(6) == _lib.ISING_E_BADARG
     assert lib.ising_set_sweep_kernel(-1) == _lib.ISING_E_BADARG
     assert lib.ising_set_sweep_kernel(0) == _lib.ISING_OK
     T = (ctypes.c_uint64 * 5)()
