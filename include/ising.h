@@ -345,17 +345,17 @@ int ising_mh_independence(int32_t n, int64_t L, int8_t *d_state, float *d_logq, 
                           void *hip_stream);
 
 /* Selects the half-sweep kernel for later calls in this process, for tests and
- * measurements.  0 = default, by size: for row-aligned sizes (L % 128 == 0)
- * the streaming row kernel with its per-wavefront work queue, with 32-row
- * bands when that makes at least 16384 wavefronts (L >= 65536) and 8-row
- * bands when those make at least 1024 (L >= 8192); otherwise the general
- * kernel, one thread per word.  1 = the general-geometry kernel for every
- * size, 2 = the row kernel without the work queue, 3, 4, 5 = the queued row
- * kernel with 32-, 16- or 8-row bands for every row-aligned size.
- * ising_glass_sweep takes the queued row kernel (32-row bands) for 0 and 3 to
- * 5 and its per-word row kernel for 1 and 2.  All choices give identical
- * lattices.  Process-wide setting; not synchronised with calls running on
- * other threads. */
+ * measurements.  0 = default, by size (Metropolis and heat bath): for
+ * row-aligned sizes (L % 128 == 0) the streaming row kernel with its
+ * per-wavefront work queue, with 16-row bands when that makes at least 16384
+ * wavefronts (L >= 49152) and 8-row bands when those make at least 1024 (L >=
+ * 8192); otherwise the general kernel, one thread per word.  1 = the
+ * general-geometry kernel for every size, 2 = the row kernel without the work
+ * queue, 3, 4, 5 = the queued row kernel with 32-, 16- or 8-row bands for
+ * every row-aligned size.  ising_glass_sweep takes the queued row kernel
+ * (32-row bands) for 0 and 3 to 5 and its per-word row kernel for 1 and 2.
+ * All choices give identical lattices.  Process-wide setting; not
+ * synchronised with calls running on other threads. */
 int ising_set_sweep_kernel(int variant);
 
 /* Description of the last error on the calling thread ("" if none). */

@@ -140,21 +140,22 @@ using ising::host::ok;
 // Half-sweep kernel selection (for tests and measurements; 0 = default).
 int g_variant = 0;
 
-// The default kernel for a Metropolis half-sweep.  The queued row kernel
-// gives each wavefront a band of rows of 64 word columns and walks the rows
-// in sequence, so a lattice with few bands leaves most of the 1024 SIMDs
-// idle.  Measured per half-sweep at beta_c: with at least 16384 wavefronts of
-// 32-row bands (L >= 65536) the band height hardly matters; below that 8-row
-// bands win (L = 16384: 27 us against 49 us with 32 rows, 54 us general);
-// with fewer than 1024 wavefronts even then (L < 8192) the general kernel,
-// one thread per word, is fastest (L = 2048: 6.5 us against 39 us).
+// The default kernel for a half-sweep (Metropolis or heat bath).  The queued
+// row kernel gives each wavefront a band of rows of 64 word columns and walks
+// the rows in sequence, so a lattice with few bands leaves most of the 1024
+// SIMDs idle.  Measured per Metropolis half-sweep at beta_c: with at least
+// 16384 wavefronts of 16-row bands (L >= 49152) those are fastest, by ~3 %
+// over 32 rows (L = 65536: 280 against 290 us); below that 8-row bands win
+// (L = 16384: 27 us against 49 us with 32 rows, 53 us general); with fewer
+// than 1024 wavefronts even then (L < 8192) the general kernel, one thread
+// per word, is fastest (L = 2048: 6.5 us against 39 us).
 int default_variant(int64_t L)
 {
     if (L % 128 != 0)
         return ising::kVariantGeneral;
     const int64_t segs = (L / 128 + 63) / 64; // wavefronts across a row
-    if (segs * ((L + 31) / 32) >= 16384)
-        return ising::kVariantDefault;
+    if (segs * ((L + 15) / 16) >= 16384)
+        return ising::kVariantQueue16;
     if (segs * ((L + 7) / 8) >= 1024)
         return ising::kVariantQueue8;
     return ising::kVariantGeneral;
@@ -217,7 +218,7 @@ int run_sweeps5(const ising_lattice *lat, const uint64_t T[5], int64_t nsweeps,
         for (int c = 0; c < 2; ++c) {
             const uint64_t t = 2 * (rng_counter + (uint64_t)sw) + (uint64_t)c;
             hipError_t e = ising::launch_half_sweep5(lat->words, lat->L, c, tab, t, lat->seed,
-                                                     lat->stream_id, s);
+                                                     lat->stream_id, s, sweep_variant(lat->L));
             if (e != hipSuccess)
                 return hip_fail(e, "half-sweep launch");
         }

@@ -356,19 +356,30 @@ struct SweepArgs5 {
     uint32_t t_lo, t_hi, stream_id, key0, key1;
 };
 
-// One-hot masks e[a] of the number of aligned neighbours (one 32-bit half):
-// a bit-sliced sum of the four "aligned" vectors.
-__host__ __device__ __forceinline__ void count_classes(uint32_t s, uint32_t n0, uint32_t n1,
-                                                       uint32_t n2, uint32_t n3,
-                                                       uint32_t (&e)[5])
+// Number of aligned neighbours (one 32-bit half) as bit slices: count =
+// 4 b2 + 2 b1 + b0, a bit-sliced sum of the four "aligned" vectors.
+__host__ __device__ __forceinline__ void count_bits(uint32_t s, uint32_t n0, uint32_t n1,
+                                                    uint32_t n2, uint32_t n3, uint32_t &b0,
+                                                    uint32_t &b1, uint32_t &b2)
 {
     constexpr uint32_t kAligned = tt(~(kA ^ kB)); // 1 where the two inputs are equal
     const uint32_t x0 = lop3<kAligned>(s, n0, 0u), x1 = lop3<kAligned>(s, n1, 0u);
     const uint32_t x2 = lop3<kAligned>(s, n2, 0u), x3 = lop3<kAligned>(s, n3, 0u);
     const uint32_t s1 = xor3(x0, x1, x2);
     const uint32_t c1 = lop3<tt((kA & kB) | (kA & kC) | (kB & kC))>(x0, x1, x2); // majority
-    const uint32_t b0 = s1 ^ x3, cy = s1 & x3;
-    const uint32_t b1 = c1 ^ cy, b2 = c1 & cy; // count = 4 b2 + 2 b1 + b0
+    const uint32_t cy = s1 & x3;
+    b0 = s1 ^ x3;
+    b1 = c1 ^ cy;
+    b2 = c1 & cy;
+}
+
+// The same as one-hot masks e[a], a = 0..4.
+__host__ __device__ __forceinline__ void count_classes(uint32_t s, uint32_t n0, uint32_t n1,
+                                                       uint32_t n2, uint32_t n3,
+                                                       uint32_t (&e)[5])
+{
+    uint32_t b0, b1, b2;
+    count_bits(s, n0, n1, n2, n3, b0, b1, b2);
     e[4] = b2;
     e[3] = b1 & b0;
     e[2] = b1 & ~b0;
@@ -424,6 +435,88 @@ __host__ __device__ __forceinline__ uint64_t decide_word5(uint64_t t, const Neig
         }
     }
     return join(tf[0], tf[1]); // undecided after 32 planes: r == T, rejected
+}
+
+// ------------------------------------- 5-entry table, streamed row kernel
+// Decision state of a word under a 5-entry table, per 32-bit half: flips
+// decided so far, spins still undecided, and each spin's aligned count as
+// bit slices (the class that picks its threshold bit on every plane).
+struct State5 {
+    uint32_t tf[2], p[2], b0[2], b1[2], b2[2];
+};
+
+// Start state from the target word and its neighbour halves (as
+// start_from_halves): always-flip classes flipped, drawing classes pending.
+__host__ __device__ __forceinline__ State5 start5_from_halves(uint64_t t, uint64_t up, uint64_t dn,
+                                                              uint64_t ce, uint32_t sl,
+                                                              uint32_t sh, const Table5 &tab)
+{
+    State5 s;
+#pragma unroll
+    for (int h = 0; h < 2; ++h) {
+        const uint32_t th = h ? hi32(t) : lo32(t);
+        count_bits(th, h ? hi32(up) : lo32(up), h ? hi32(dn) : lo32(dn), h ? hi32(ce) : lo32(ce),
+                   h ? sh : sl, s.b0[h], s.b1[h], s.b2[h]);
+        const uint32_t e[5] = {lop3<tt(~(kA | kB | kC))>(s.b0[h], s.b1[h], s.b2[h]),
+                               s.b0[h] & ~s.b1[h], s.b1[h] & ~s.b0[h], s.b1[h] & s.b0[h],
+                               s.b2[h]};
+        uint32_t f = 0, r = 0;
+#pragma unroll
+        for (int c = 0; c < 5; ++c) {
+            f |= ((tab.always >> c) & 1u) ? e[c] : 0u;
+            r |= ((tab.random >> c) & 1u) ? e[c] : 0u;
+        }
+        s.tf[h] = th ^ f;
+        s.p[h] = r;
+    }
+    return s;
+}
+
+// Threshold bit of every spin from its count slices and the five classes'
+// bits m[a] (all ones or zero): a multiplexer tree over b0, b1, b2.
+__host__ __device__ __forceinline__ uint32_t thr_bits5(uint32_t b0, uint32_t b1, uint32_t b2,
+                                                       const uint32_t (&m)[5])
+{
+    constexpr uint32_t kMux = tt((kA & kB) | (~kA & kC)); // A ? B : C
+    const uint32_t lo = lop3<kMux>(b0, m[1], m[0]);     // count 0, 1
+    const uint32_t hi = lop3<kMux>(b0, m[3], m[2]);     // count 2, 3
+    return lop3<kMux>(b2, m[4], lop3<kMux>(b1, hi, lo));
+}
+
+// One plane P of half h: where the r bit differs from the spin's threshold
+// bit the spin is decided, flipped if the threshold bit is 1.
+__host__ __device__ __forceinline__ void plane5(State5 &s, int h, uint32_t P,
+                                                const uint32_t (&m)[5])
+{
+    const uint32_t tb = thr_bits5(s.b0[h], s.b1[h], s.b2[h], m);
+    const uint32_t differ = lop3<tt(kA & (kB ^ kC))>(s.p[h], P, tb);
+    s.tf[h] = lop3<tt(kA ^ (kB & kC))>(s.tf[h], differ, tb);
+    s.p[h] ^= differ;
+}
+
+// Block q (planes 2q, 2q+1) of a word: lock step (`Lane` false: q and the
+// class bits shared by the wavefront) or per lane (queued words).
+template <bool Lane>
+__host__ __device__ __forceinline__ void block5(State5 &s, uint32_t q, uint32_t chunk,
+                                                const SweepArgs5 &a)
+{
+    const Block x = Lane ? philox_fast<kCtrLane>(ctr_word0(a.stream_id, kDomainSweep, q), a.t_lo,
+                                                 a.t_hi, chunk, a.key0, a.key1)
+                         : philox_fast<kCtrUniform>(ctr_word0(a.stream_id, kDomainSweep, q),
+                                                    a.t_lo, a.t_hi, chunk, a.key0, a.key1);
+    const uint32_t planes[2][2] = {{x.x0, x.x1}, {x.x2, x.x3}};
+#pragma unroll
+    for (int k = 0; k < 2; ++k) {
+        const uint32_t bit = 31 - (2 * q + (uint32_t)k);
+        uint32_t m[5];
+#pragma unroll
+        for (int c = 0; c < 5; ++c)
+            m[c] = ((a.tab.random >> c) & 1u) ? (Lane ? thr_mask(a.tab.thr[c], bit)
+                                                      : (((a.tab.thr[c] >> bit) & 1u) ? ~0u : 0u))
+                                              : 0u;
+        plane5(s, 0, planes[k][0], m);
+        plane5(s, 1, planes[k][1], m);
+    }
 }
 
 // --------------------------------------------------- XCD-aware block order

@@ -30,9 +30,11 @@ hipError_t launch_half_sweep(uint64_t *words, int64_t L, int c, const Metro2 &m,
 hipError_t launch_rows_queue(uint64_t *tgt, const uint64_t *src, const uint64_t *bonds,
                              int64_t L, int c, const Metro2 &m, const SweepArgs2 &a, hipStream_t s,
                              int band);
-// Half-sweep under any 5-entry acceptance table (heat bath).
+// Half-sweep under any 5-entry acceptance table (heat bath); the variants
+// choose kernels as for launch_half_sweep.
 hipError_t launch_half_sweep5(uint64_t *words, int64_t L, int c, const rows::Table5 &tab,
-                              uint64_t t, uint64_t seed, uint32_t stream_id, hipStream_t s);
+                              uint64_t t, uint64_t seed, uint32_t stream_id, hipStream_t s,
+                              int variant);
 hipError_t launch_observables(const uint64_t *words, int64_t L, int64_t *bond, int64_t *mag,
                               hipStream_t s);
 

@@ -104,10 +104,87 @@ constexpr uint32_t kQueueCap = 128; // < 64 entries left after a drain + 64 push
 constexpr int kWaves = 4;
 constexpr uint32_t kRing = 4; // power of two
 
+// The decision rule of the queued kernel: its per-word state, the words a
+// queue entry holds, and the start and block steps (ising_rows.hpp).
+// Metropolis: two drawing classes; state = flips so far, pending spins,
+// class-A spins.
+struct RuleMetro {
+    using State = rows::State;
+    using Args = SweepArgs2;
+    static constexpr int kWords = 3;
+    struct Setup {
+        rows::ClassMasks cm;
+    };
+    __device__ static Setup setup(const Args &a) { return Setup{rows::class_masks(a.m)}; }
+    template <bool Anti, bool Plain>
+    __device__ static State start(uint64_t t, uint64_t up, uint64_t dn, uint64_t ce, uint32_t sl,
+                                  uint32_t sh, const Setup &su, const Args &)
+    {
+        return rows::start_from_halves<Anti, Plain>(t, up, dn, ce, sl, sh, su.cm);
+    }
+    __device__ static void block(State &s, uint32_t q, uint32_t chunk, const Args &a)
+    {
+        rows::block_uniform(s, q, chunk, a);
+    }
+    __device__ static void block_lane(State &s, uint32_t q, uint32_t chunk, const Args &a)
+    {
+        rows::block_lane(s, q, chunk, a);
+    }
+    __device__ static uint64_t word(const State &s, int k)
+    {
+        return k == 0 ? rows::join(s.tf[0], s.tf[1])
+                      : (k == 1 ? rows::join(s.p[0], s.p[1]) : rows::join(s.a[0], s.a[1]));
+    }
+    __device__ static void set_word(State &s, int k, uint64_t v)
+    {
+        uint32_t *h = k == 0 ? s.tf : (k == 1 ? s.p : s.a);
+        h[0] = rows::lo32(v);
+        h[1] = rows::hi32(v);
+    }
+};
+
+// Any 5-entry table (heat bath): every class may draw; state = flips so far,
+// pending spins, the aligned count as three bit slices.
+struct Rule5 {
+    using State = rows::State5;
+    using Args = rows::SweepArgs5;
+    static constexpr int kWords = 5;
+    struct Setup {};
+    __device__ static Setup setup(const Args &) { return Setup{}; }
+    template <bool Anti, bool Plain>
+    __device__ static State start(uint64_t t, uint64_t up, uint64_t dn, uint64_t ce, uint32_t sl,
+                                  uint32_t sh, const Setup &, const Args &a)
+    {
+        return rows::start5_from_halves(t, up, dn, ce, sl, sh, a.tab);
+    }
+    __device__ static void block(State &s, uint32_t q, uint32_t chunk, const Args &a)
+    {
+        rows::block5<false>(s, q, chunk, a);
+    }
+    __device__ static void block_lane(State &s, uint32_t q, uint32_t chunk, const Args &a)
+    {
+        rows::block5<true>(s, q, chunk, a);
+    }
+    __device__ static uint32_t *half_pair(State &s, int k)
+    {
+        return k == 0 ? s.tf : (k == 1 ? s.p : (k == 2 ? s.b0 : (k == 3 ? s.b1 : s.b2)));
+    }
+    __device__ static uint64_t word(const State &s, int k)
+    {
+        const uint32_t *h = half_pair(const_cast<State &>(s), k);
+        return rows::join(h[0], h[1]);
+    }
+    __device__ static void set_word(State &s, int k, uint64_t v)
+    {
+        uint32_t *h = half_pair(s, k);
+        h[0] = rows::lo32(v);
+        h[1] = rows::hi32(v);
+    }
+};
+
+template <int N>
 struct WaveQueue {
-    uint64_t tf[kQueueCap];    // target word with the flips decided so far
-    uint64_t p[kQueueCap];     // spins still undecided
-    uint64_t a[kQueueCap];     // class-A spins
+    uint64_t w[N][kQueueCap];  // the rule's state words (first: flips so far, second: pending)
     uint32_t chunk[kQueueCap]; // word index in its colour
     uint32_t meta[kQueueCap];  // next Philox block | lane << 4 | band row << 10
 };
@@ -123,17 +200,20 @@ __device__ __forceinline__ uint32_t lanes_below(uint64_t ballot)
                                      __builtin_amdgcn_mbcnt_lo((uint32_t)ballot, 0u));
 }
 
-__device__ __forceinline__ void queue_put(WaveQueue &wq, uint32_t e, const rows::State &s,
-                                          uint32_t chunk, uint32_t meta)
+template <class Rule>
+__device__ __forceinline__ void queue_put(WaveQueue<Rule::kWords> &wq, uint32_t e,
+                                          const typename Rule::State &s, uint32_t chunk,
+                                          uint32_t meta)
 {
-    wq.tf[e] = rows::join(s.tf[0], s.tf[1]);
-    wq.p[e] = rows::join(s.p[0], s.p[1]);
-    wq.a[e] = rows::join(s.a[0], s.a[1]);
+#pragma unroll
+    for (int k = 0; k < Rule::kWords; ++k)
+        wq.w[k][e] = Rule::word(s, k);
     wq.chunk[e] = chunk;
     wq.meta[e] = meta;
 }
 
-__device__ __forceinline__ bool undecided(const rows::State &s) { return (s.p[0] | s.p[1]) != 0; }
+template <class State>
+__device__ __forceinline__ bool undecided(const State &s) { return (s.p[0] | s.p[1]) != 0; }
 
 // Writes ring slot `sl` to row pointer `rowp`: every word, or (`only_done`)
 // the final ones.
@@ -152,26 +232,24 @@ __device__ __forceinline__ void ring_store(const WaveRing &rg, uint32_t sl,
 // memory), the rest are appended again at the tail.  A word still undecided
 // after block 15 (all 32 planes) has r == T: rejected, and final as it is.
 // Rows up to r_cur - kRing have left the ring.
-__device__ __forceinline__ void drain_once(WaveQueue &wq, WaveRing &rg, uint32_t &head, uint32_t &len, uint32_t n,
+template <class Rule>
+__device__ __forceinline__ void drain_once(WaveQueue<Rule::kWords> &wq, WaveRing &rg,
+                                           uint32_t &head, uint32_t &len, uint32_t n,
                                            uint32_t r_cur, uint64_t *__restrict__ tgt,
-                                           const SweepArgs2 &a, int lane)
+                                           const typename Rule::Args &a, int lane)
 {
     const bool mine = (uint32_t)lane < n;
-    rows::State s{};
+    typename Rule::State s{};
     uint32_t chunk = 0, meta = 0, q = 0;
     if (mine) {
         const uint32_t e = (head + (uint32_t)lane) & (kQueueCap - 1);
-        const uint64_t tf = wq.tf[e], p = wq.p[e], ca = wq.a[e];
-        s.tf[0] = rows::lo32(tf);
-        s.tf[1] = rows::hi32(tf);
-        s.p[0] = rows::lo32(p);
-        s.p[1] = rows::hi32(p);
-        s.a[0] = rows::lo32(ca);
-        s.a[1] = rows::hi32(ca);
+#pragma unroll
+        for (int k = 0; k < Rule::kWords; ++k)
+            Rule::set_word(s, k, wq.w[k][e]);
         chunk = wq.chunk[e];
         meta = wq.meta[e];
         q = meta & 15u;
-        rows::block_lane(s, q, chunk, a);
+        Rule::block_lane(s, q, chunk, a);
     }
     __builtin_amdgcn_wave_barrier();
     head = (head + n) & (kQueueCap - 1);
@@ -191,7 +269,7 @@ __device__ __forceinline__ void drain_once(WaveQueue &wq, WaveRing &rg, uint32_t
     }
     const uint64_t bal = __ballot(keep);
     if (keep)
-        queue_put(wq, (head + len + lanes_below(bal)) & (kQueueCap - 1), s, chunk, meta + 1);
+        queue_put<Rule>(wq, (head + len + lanes_below(bal)) & (kQueueCap - 1), s, chunk, meta + 1);
     __builtin_amdgcn_wave_barrier();
     len += (uint32_t)__popcll(bal);
 }
@@ -228,20 +306,23 @@ __device__ __forceinline__ uint32_t side_half_dpp(uint32_t cur_lo, uint32_t cur_
 // layout).  A lane's four bond words are one 32-byte load per row, streamed
 // like the spin rows; the left bond of a target spin whose left neighbour is
 // the side one takes the same one-spin shift.
-template <int Band, bool Anti, bool Plain, bool Dpp, bool Glass>
+//
+// `Rule`: Metropolis (RuleMetro) or any 5-entry table (Rule5, heat bath).
+template <class Rule, int Band, bool Anti, bool Plain, bool Dpp, bool Glass>
 __global__ __launch_bounds__(256) void k_sweep_rows_q(uint64_t *__restrict__ tgt,
                                                       const uint64_t *__restrict__ src,
                                                       const uint64_t *__restrict__ bonds,
                                                       uint32_t L, uint32_t Wr,
                                                       uint32_t waves_per_band, uint32_t nbands,
-                                                      int c, SweepArgs2 a)
+                                                      int c, typename Rule::Args a)
 {
-    __shared__ WaveQueue queues[kWaves];
+    using Queue = WaveQueue<Rule::kWords>;
+    __shared__ Queue queues[kWaves];
     __shared__ WaveRing rings[kWaves];
     const int lane = threadIdx.x & 63;
     // wave-uniform: the row arithmetic stays on the scalar unit
     const uint32_t wv = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
-    WaveQueue &wq = queues[wv];
+    Queue &wq = queues[wv];
     WaveRing &rg = rings[wv];
     const uint32_t gwave = rows::xcd_block(blockIdx.x, gridDim.x) * kWaves + wv;
     const uint32_t band = gwave / waves_per_band;
@@ -256,7 +337,7 @@ __global__ __launch_bounds__(256) void k_sweep_rows_q(uint64_t *__restrict__ tgt
     // Dpp: the one word each edge lane reads
     const bool edge_l = lane == 0, edge_r = lane == 63;
     const uint32_t i0 = band * Band;
-    const rows::ClassMasks cm = rows::class_masks(a.m);
+    const typename Rule::Setup su = Rule::setup(a);
     auto row = [&](uint32_t i) { return src + (size_t)i * Wr; }; // wave-uniform pointer
     auto side_word = [&](uint32_t i, bool left) -> uint64_t { return row(i)[left ? wl : wr]; };
     auto edge_half = [&](uint32_t i, bool left) -> uint32_t {
@@ -362,7 +443,7 @@ __global__ __launch_bounds__(256) void k_sweep_rows_q(uint64_t *__restrict__ tgt
                 shh ^= rows::hi32(rb.rt);
             }
         }
-        rows::State s = rows::start_from_halves<Anti, Plain>(t, nu, nd, nc, shl, shh, cm);
+        typename Rule::State s = Rule::template start<Anti, Plain>(t, nu, nd, nc, shl, shh, su, a);
         // (a block applied to a decided word changes nothing; with both
         // classes random a whole wavefront is practically never decided
         // early, so only the other cases test for it)
@@ -370,19 +451,19 @@ __global__ __launch_bounds__(256) void k_sweep_rows_q(uint64_t *__restrict__ tgt
         for (uint32_t q = 0; q < kStreamBlocks; ++q) {
             if (!Plain && __ballot(active && undecided(s)) == 0)
                 break;
-            rows::block_uniform(s, q, idx, a);
+            Rule::block(s, q, idx, a);
         }
         const bool push = active && undecided(s);
         rg.word[sl][lane] = rows::join(s.tf[0], s.tf[1]);
         rg.done[sl][lane] = push ? 0 : 1;
         const uint64_t bal = __ballot(push);
         if (push)
-            queue_put(wq, (head + len + lanes_below(bal)) & (kQueueCap - 1), s, idx,
-                      kStreamBlocks | ((uint32_t)lane << 4) | (r << 10));
+            queue_put<Rule>(wq, (head + len + lanes_below(bal)) & (kQueueCap - 1), s, idx,
+                            kStreamBlocks | ((uint32_t)lane << 4) | (r << 10));
         __builtin_amdgcn_wave_barrier();
         len += (uint32_t)__popcll(bal);
         while (len >= 64)
-            drain_once(wq, rg, head, len, 64, r, tgt, a, lane);
+            drain_once<Rule>(wq, rg, head, len, 64, r, tgt, a, lane);
         prev = cur;
         cur = next;
         next = next1;
@@ -396,7 +477,7 @@ __global__ __launch_bounds__(256) void k_sweep_rows_q(uint64_t *__restrict__ tgt
         }
     }
     while (len > 0)
-        drain_once(wq, rg, head, len, len < 64 ? len : 64, r_last, tgt, a, lane);
+        drain_once<Rule>(wq, rg, head, len, len < 64 ? len : 64, r_last, tgt, a, lane);
     // the last rows, all words final
     const uint32_t nrows = r_last + 1;
     for (uint32_t r = nrows > kRing ? nrows - kRing : 0; r < nrows; ++r)
@@ -450,14 +531,33 @@ __global__ __launch_bounds__(256) void k_sweep_rows5(uint64_t *__restrict__ tgt,
 }
 
 hipError_t launch_half_sweep5(uint64_t *words, int64_t L, int c, const rows::Table5 &tab,
-                              uint64_t t, uint64_t seed, uint32_t stream_id, hipStream_t s)
+                              uint64_t t, uint64_t seed, uint32_t stream_id, hipStream_t s,
+                              int variant)
 {
     const int64_t H = L / 2, M = L * L / 2, W = (M + 63) / 64;
     uint64_t *tgt = words + (int64_t)c * W;
     const uint64_t *src = words + (int64_t)(1 - c) * W;
     const rows::SweepArgs5 a{tab, (uint32_t)t, (uint32_t)(t >> 32), stream_id, (uint32_t)seed,
                              (uint32_t)(seed >> 32)};
-    if (L % 128 == 0) {
+    if (L % 128 == 0 && variant != kVariantGeneral && variant != kVariantRowsPlain) {
+        // the queued row kernel under the table
+        const int band = variant == kVariantQueue16 ? 16 : (variant == kVariantQueue8 ? 8 : 32);
+        const int64_t Wr = L / 128, wpb = (Wr + 63) / 64, nbands = (L + band - 1) / band;
+        const int64_t waves = wpb * nbands;
+        using Kernel = void (*)(uint64_t *, const uint64_t *, const uint64_t *, uint32_t, uint32_t,
+                                uint32_t, uint32_t, int, rows::SweepArgs5);
+        static const Kernel kernels[3][2] = {
+            {k_sweep_rows_q<Rule5, 32, false, false, false, false>,
+             k_sweep_rows_q<Rule5, 32, false, false, true, false>},
+            {k_sweep_rows_q<Rule5, 16, false, false, false, false>,
+             k_sweep_rows_q<Rule5, 16, false, false, true, false>},
+            {k_sweep_rows_q<Rule5, 8, false, false, false, false>,
+             k_sweep_rows_q<Rule5, 8, false, false, true, false>}};
+        const Kernel k = kernels[band == 32 ? 0 : (band == 16 ? 1 : 2)][Wr % 64 == 0 ? 1 : 0];
+        hipLaunchKernelGGL(k, dim3((uint32_t)((waves + kWaves - 1) / kWaves)), dim3(64 * kWaves),
+                           0, s, tgt, src, nullptr, (uint32_t)L, (uint32_t)Wr, (uint32_t)wpb,
+                           (uint32_t)nbands, c, a);
+    } else if (L % 128 == 0 && variant == kVariantRowsPlain) {
         const int64_t Wr = L / 128;
         const int threads = Wr >= 256 ? 256 : (Wr >= 64 ? 64 * (int)((Wr + 63) / 64) : 64);
         const int64_t bpb = (Wr + threads - 1) / threads;
@@ -610,10 +710,14 @@ hipError_t launch_rows_queue(uint64_t *tgt, const uint64_t *src, const uint64_t 
     using Kernel = void (*)(uint64_t *, const uint64_t *, const uint64_t *, uint32_t, uint32_t,
                             uint32_t, uint32_t, int, SweepArgs2);
 #define ISING_ROWS_Q8(B, G)                                                                       \
-    k_sweep_rows_q<B, false, false, false, G>, k_sweep_rows_q<B, false, false, true, G>,          \
-        k_sweep_rows_q<B, false, true, false, G>, k_sweep_rows_q<B, false, true, true, G>,        \
-        k_sweep_rows_q<B, true, false, false, G>, k_sweep_rows_q<B, true, false, true, G>,        \
-        k_sweep_rows_q<B, true, true, false, G>, k_sweep_rows_q<B, true, true, true, G>
+    k_sweep_rows_q<RuleMetro, B, false, false, false, G>,                                         \
+        k_sweep_rows_q<RuleMetro, B, false, false, true, G>,                                      \
+        k_sweep_rows_q<RuleMetro, B, false, true, false, G>,                                      \
+        k_sweep_rows_q<RuleMetro, B, false, true, true, G>,                                       \
+        k_sweep_rows_q<RuleMetro, B, true, false, false, G>,                                      \
+        k_sweep_rows_q<RuleMetro, B, true, false, true, G>,                                       \
+        k_sweep_rows_q<RuleMetro, B, true, true, false, G>,                                       \
+        k_sweep_rows_q<RuleMetro, B, true, true, true, G>
     static const Kernel kernels[4][8] = {{ISING_ROWS_Q8(32, false)},
                                          {ISING_ROWS_Q8(16, false)},
                                          {ISING_ROWS_Q8(8, false)},

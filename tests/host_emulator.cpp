@@ -55,6 +55,22 @@ static uint64_t queued_word_any(uint64_t t, uint64_t up, uint64_t dn, uint64_t c
                  : queued_word<false, false>(t, up, dn, ce, adj, left, chunk, a);
 }
 
+// The queued row kernel's sequence under a 5-entry table: start state from
+// the count slices, three lock-step blocks, then per-lane blocks.
+static uint64_t queued_word5(uint64_t t, uint64_t up, uint64_t dn, uint64_t ce, uint64_t adj,
+                             bool left, uint32_t chunk, const rows::SweepArgs5 &a)
+{
+    uint32_t sl, sh;
+    rows::side_halves(ce, left ? rows::hi32(adj) : rows::lo32(adj), left, sl, sh);
+    rows::State5 s = rows::start5_from_halves(t, up, dn, ce, sl, sh, a.tab);
+    uint32_t q = 0;
+    for (; q < 3; ++q)
+        rows::block5<false>(s, q, chunk, a);
+    for (; q < 16 && (s.p[0] | s.p[1]) != 0; ++q)
+        rows::block5<true>(s, q, chunk, a);
+    return rows::join(s.tf[0], s.tf[1]);
+}
+
 } // namespace
 
 extern "C" {
@@ -118,7 +134,7 @@ void emu_half_sweep(uint64_t *words, int64_t L, int c, const uint64_t *T, int an
 
 // The heat-bath kernels' word decision (decide_word5) under table T, with
 // the general kernel's neighbour extraction (rows = 0) or the row kernel's
-// (rows = 1, L % 128 == 0).
+// (rows = 1, L % 128 == 0); rows = 2: the queued row kernel's sequence.
 void emu_half_sweep5(uint64_t *words, int64_t L, int c, const uint64_t *T, uint64_t t,
                      uint64_t seed, uint32_t stream, int rows5)
 {
@@ -148,8 +164,13 @@ void emu_half_sweep5(uint64_t *words, int64_t L, int c, const uint64_t *T, uint6
             const bool left = ((i + c) & 1) == 0;
             const int64_t adjw = left ? (w == 0 ? Wr - 1 : w - 1) : (w == Wr - 1 ? 0 : w + 1);
             const int64_t idx = i * Wr + w;
-            const Neighbours nb{src[((i + L - 1) % L) * Wr + w], src[((i + 1) % L) * Wr + w],
-                                src[idx], side_vector(src[idx], src[i * Wr + adjw], left)};
+            const uint64_t up = src[((i + L - 1) % L) * Wr + w], dn = src[((i + 1) % L) * Wr + w];
+            if (rows5 == 2) {
+                tgt[idx] = queued_word5(tgt[idx], up, dn, src[idx], src[i * Wr + adjw], left,
+                                        (uint32_t)idx, a);
+                continue;
+            }
+            const Neighbours nb{up, dn, src[idx], side_vector(src[idx], src[i * Wr + adjw], left)};
             tgt[idx] = rows::decide_word5(tgt[idx], nb, ~0ull, (uint32_t)idx, a);
         }
 }

@@ -1,6 +1,7 @@
 """Heat-bath rule (Sec. 2) on the GPU: bit-exact parity with the oracle's
-heat-bath sweeps through the C ABI, for the general and the row-aligned
-kernels, and run-splitting invariance."""
+heat-bath sweeps through the C ABI, for every kernel choice (default by size,
+general, row kernel without queue, queued with 32-, 16-, 8-row bands), and
+run-splitting invariance."""
 import numpy as np
 import pytest
 
@@ -33,6 +34,32 @@ def test_heatbath_parity(gpu, orc, L, beta, J):
     orc.sweeps(ref, beta, J, seed, stream, n, ctr, rule="heatbath")
     assert np.array_equal(lat.packed(), pack(ref))
     assert lat.observables() == orc.observables(ref)
+
+
+# 128, 384: fewer than 64 words per row; 8192: one 64-word segment per row;
+# 8320: 65 words per row, a partial last segment; 16384: two segments
+@pytest.mark.parametrize("variant", [1, 2, 3, 4, 5])
+@pytest.mark.parametrize("L,n", [(128, 4), (384, 4), (1024, 3), (8192, 2), (8320, 2), (16384, 1)])
+@pytest.mark.parametrize("beta,J", [(workloads.BETA_CRIT_CONFIG, 1.0), (0.3, -1.0), (3.0, 1.0)])
+def test_heatbath_every_kernel(gpu, orc, variant, L, n, beta, J):
+    print(f"heat bath variant={variant} L={L} beta={beta} J={J}", flush=True)
+    seed, stream, ctr = 70 + L, 1, 3
+    lat = gpu.Lattice(L, seed=seed, stream_id=stream)
+    gpu.set_sweep_kernel(variant)
+    try:
+        lat.sweep(beta, J, n, ctr, rule="heatbath")
+    finally:
+        gpu.set_sweep_kernel(0)
+    key = (L, n, beta, J)
+    ref = _ref5.get(key)
+    if ref is None:
+        ref = orc.init(L, seed, stream)
+        orc.sweeps(ref, beta, J, seed, stream, n, ctr, rule="heatbath")
+        _ref5[key] = ref
+    assert np.array_equal(lat.packed(), pack(ref))
+
+
+_ref5 = {}
 
 
 def test_heatbath_16384_full_lattice(gpu, orc):

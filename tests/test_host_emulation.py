@@ -131,11 +131,12 @@ def test_xcd_block_order_is_a_permutation(emu, n):
 
 
 @pytest.mark.parametrize("L,rows5", [(4, 0), (6, 0), (10, 0), (24, 0), (64, 0), (100, 0),
-                                     (128, 0), (128, 1), (256, 1)])
+                                     (128, 0), (128, 1), (256, 1), (128, 2), (256, 2), (384, 2)])
 @pytest.mark.parametrize("beta,J", [(0.0, 1.0), (workloads.BETA_CRIT_CONFIG, 1.0), (0.3, -1.0),
                                     (3.0, 1.0), (300.0, 1.0)])
 def test_heatbath_kernel_logic(emu, orc, L, rows5, beta, J):
-    """The heat-bath word decision (five classes) against the oracle's heat-bath sweeps."""
+    """The heat-bath word decision (five classes) against the oracle's heat-bath sweeps:
+    per-word loop, row kernel, and the queued kernel's lock-step then per-lane blocks."""
     seed, stream, n, ctr = 55 + L, 3, 3, 4
     ref = orc.init(L, seed, stream)
     W = (L * L // 2 + 63) // 64
