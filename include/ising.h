@@ -353,7 +353,8 @@ int ising_mh_independence(int32_t n, int64_t L, int8_t *d_state, float *d_logq, 
  * general-geometry kernel for every size, 2 = the row kernel without the work
  * queue, 3, 4, 5 = the queued row kernel with 32-, 16- or 8-row bands for
  * every row-aligned size.  ising_glass_sweep takes the queued row kernel
- * (32-row bands) for 0 and 3 to 5 and its per-word row kernel for 1 and 2.
+ * (default: 8-row bands at every size; 3, 4, 5 as above) and its per-word row
+ * kernel for 1 and 2.
  * All choices give identical lattices.  Process-wide setting; not
  * synchronised with calls running on other threads. */
 int ising_set_sweep_kernel(int variant);

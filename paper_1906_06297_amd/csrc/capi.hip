@@ -161,6 +161,26 @@ int default_variant(int64_t L)
     return ising::kVariantGeneral;
 }
 
+// Kernel for ising_glass_sweep (L % 128 == 0): the queued row kernel with
+// 8-row bands, fastest at every size measured (L = 65536: 402 us against 423
+// with 16 rows and 439 with 32 -- the bond and spin streams gain from the
+// extra wavefronts in flight; L = 2048: 14 us against 42 with 32 rows); or
+// the one the caller forced (1, 2: the per-word row kernel).
+int glass_variant()
+{
+    switch (g_variant) {
+    case 0:
+    case 5:
+        return ising::kVariantQueue8;
+    case 3:
+        return ising::kVariantDefault;
+    case 4:
+        return ising::kVariantQueue16;
+    default:
+        return g_variant;
+    }
+}
+
 // Kernel for ising_sweep: the size-dependent default, or the one the caller
 // forced (3, 4, 5: the queued row kernel with 32-, 16- or 8-row bands
 // whatever the size).
@@ -496,7 +516,7 @@ int ising_glass_sweep(const ising_lattice *lat, const uint64_t *d_bonds, size_t 
             const uint64_t t = 2 * (rng_counter + (uint64_t)sw) + (uint64_t)c;
             hipError_t e = ising::launch_glass_half_sweep(lat->words, d_bonds, lat->L, c, m, t,
                                                           lat->seed, lat->stream_id, s,
-                                                          g_variant >= 3 ? 0 : g_variant);
+                                                          glass_variant());
             if (e != hipSuccess)
                 return hip_fail(e, "half-sweep launch");
         }

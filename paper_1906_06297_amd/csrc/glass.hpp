@@ -11,7 +11,8 @@ namespace ising {
 hipError_t launch_glass_bonds_init(uint64_t *bonds, int64_t L, uint64_t seed, uint32_t stream_id,
                                    hipStream_t s);
 // Half-sweep of colour c of a row-aligned lattice (L % 128 == 0): the queued
-// row kernel by default, the per-word row kernel for the other variants.
+// row kernel (kVariantDefault: 32-row bands, kVariantQueue16, kVariantQueue8),
+// or the per-word row kernel (kVariantGeneral, kVariantRowsPlain).
 hipError_t launch_glass_half_sweep(uint64_t *words, const uint64_t *bonds, int64_t L, int c,
                                    const Metro2 &m, uint64_t t, uint64_t seed, uint32_t stream_id,
                                    hipStream_t s, int variant);

@@ -199,8 +199,10 @@ hipError_t launch_glass_half_sweep(uint64_t *words, const uint64_t *bonds, int64
     const uint64_t *src = words + (int64_t)(1 - c) * W;
     const SweepArgs2 a{m, (uint32_t)t, (uint32_t)(t >> 32), stream_id, (uint32_t)seed,
                        (uint32_t)(seed >> 32)};
-    if (variant == kVariantDefault)
-        return launch_rows_queue(tgt, src, bonds, L, c, m, a, s, 32);
+    if (variant != kVariantGeneral && variant != kVariantRowsPlain)
+        return launch_rows_queue(tgt, src, bonds, L, c, m, a, s,
+                                 variant == kVariantQueue16 ? 16
+                                                            : (variant == kVariantQueue8 ? 8 : 32));
     const int threads = Wr >= 256 ? 256 : (Wr >= 64 ? 64 * (int)((Wr + 63) / 64) : 64);
     const int64_t bpb = (Wr + threads - 1) / threads;
     const int64_t bands = (L + kGlassRows - 1) / kGlassRows;

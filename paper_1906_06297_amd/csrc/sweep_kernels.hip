@@ -98,7 +98,6 @@ __global__ __launch_bounds__(256) void k_sweep_rows(uint64_t *__restrict__ tgt,
 // thousand) is stored on its own when it is final.
 // two 64-bit words in one 16-byte load
 typedef uint64_t u64x2 __attribute__((ext_vector_type(2)));
-constexpr int kBandRows = 32; // rows per band at large sizes (16 and 8 for mid sizes)
 constexpr uint32_t kStreamBlocks = 3;
 constexpr uint32_t kQueueCap = 128; // < 64 entries left after a drain + 64 pushed per row
 constexpr int kWaves = 4;
@@ -692,16 +691,14 @@ hipError_t launch_init(uint64_t *words, int64_t L, uint64_t seed, uint32_t strea
 }
 
 // The queued row kernel for a row-aligned lattice (L % 128 == 0), with the
-// bond arrays of a +-J glass (32-row bands) or without (bonds == nullptr;
-// band = 32, 16 or 8 rows).
+// bond arrays of a +-J glass or without (bonds == nullptr); band = 32, 16 or
+// 8 rows.
 hipError_t launch_rows_queue(uint64_t *tgt, const uint64_t *src, const uint64_t *bonds,
                              int64_t L, int c, const Metro2 &m, const SweepArgs2 &a, hipStream_t s,
                              int band)
 {
     const int64_t Wr = L / 128;
     const int64_t wpb = (Wr + 63) / 64;
-    if (bonds)
-        band = kBandRows;
     const int64_t nbands = (L + band - 1) / band;
     const int64_t waves = wpb * nbands;
     const dim3 grid((uint32_t)((waves + kWaves - 1) / kWaves)), block(64 * kWaves);
@@ -718,12 +715,11 @@ hipError_t launch_rows_queue(uint64_t *tgt, const uint64_t *src, const uint64_t 
         k_sweep_rows_q<RuleMetro, B, true, false, true, G>,                                       \
         k_sweep_rows_q<RuleMetro, B, true, true, false, G>,                                       \
         k_sweep_rows_q<RuleMetro, B, true, true, true, G>
-    static const Kernel kernels[4][8] = {{ISING_ROWS_Q8(32, false)},
-                                         {ISING_ROWS_Q8(16, false)},
-                                         {ISING_ROWS_Q8(8, false)},
-                                         {ISING_ROWS_Q8(32, true)}};
+    static const Kernel kernels[6][8] = {
+        {ISING_ROWS_Q8(32, false)}, {ISING_ROWS_Q8(16, false)}, {ISING_ROWS_Q8(8, false)},
+        {ISING_ROWS_Q8(32, true)},  {ISING_ROWS_Q8(16, true)},  {ISING_ROWS_Q8(8, true)}};
 #undef ISING_ROWS_Q8
-    const int set = bonds ? 3 : (band == 32 ? 0 : (band == 16 ? 1 : 2));
+    const int set = (bonds ? 3 : 0) + (band == 32 ? 0 : (band == 16 ? 1 : 2));
     const Kernel k = kernels[set][(m.anti ? 4 : 0) + (plain ? 2 : 0) + (dpp ? 1 : 0)];
     hipLaunchKernelGGL(k, grid, block, 0, s, tgt, src, bonds, (uint32_t)L, (uint32_t)Wr,
                        (uint32_t)wpb, (uint32_t)nbands, c, a);

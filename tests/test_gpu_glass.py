@@ -48,7 +48,7 @@ def test_bond_generator_matches_oracle(gpu, orc, L):
 # 128 and 384: fewer than 64 words per row (no cross-lane side shift in the
 # queued kernel); 8192: 64 words per row; 16384 with 3 sweeps: several wave
 # segments per row and bands that end mid-lattice.
-@pytest.mark.parametrize("variant", [0, 2, 3])
+@pytest.mark.parametrize("variant", [0, 2, 3, 4, 5])
 @pytest.mark.parametrize("L", [128, 256, 384, 1024, 8192])
 @pytest.mark.parametrize("beta,J", [(0.44, 1.0), (1.2, 1.0), (0.5, -1.0), (0.0, 1.0), (9.0, 1.0)])
 def test_glass_parity(gpu, orc, variant, L, beta, J):
