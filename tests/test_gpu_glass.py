@@ -120,3 +120,23 @@ def test_glass_argument_checks(gpu):
     small = gpu.GlassBonds(128, seed=1)
     with pytest.raises(IsingError):
         lat.glass_sweep(small, 0.4, 1.0, 1, 0)  # bond array too small for L = 256
+
+
+def test_glass_headline_size_full_lattice(gpu, orc):
+    """The glass workload at L = 65536 with the default kernel (queued, 8-row
+    bands): the whole lattice bit for bit after one sweep."""
+    import workloads
+    from layout import pack_rows
+
+    cfg = workloads.GLASS
+    L, beta = cfg["L"], cfg["betas"][1]
+    print("glass L=65536, 1 sweep", flush=True)
+    bonds = gpu.GlassBonds(L, seed=cfg["coupling_seed"], stream_id=0)
+    lat = gpu.Lattice(L, seed=cfg["seed"], stream_id=cfg["stream"])
+    lat.glass_sweep(bonds, beta, cfg["J"], 1, 0)
+    got = lat.packed()
+    del lat, bonds
+    Jr, Jd = orc.glass_couplings(L, cfg["coupling_seed"], 0)
+    ref = orc.init(L, cfg["seed"], cfg["stream"])
+    orc.glass_sweeps(ref, Jr, Jd, beta, cfg["J"], cfg["seed"], cfg["stream"], 1, 0)
+    assert np.array_equal(got, pack_rows(ref))

@@ -80,3 +80,20 @@ def test_heatbath_split_invariance(gpu, L):
     b.sweep(0.41, 1.0, 3, 0, rule="heatbath")
     b.sweep(0.41, 1.0, 4, 3, rule="heatbath")
     assert np.array_equal(a.packed(), b.packed())
+
+
+def test_heatbath_headline_size_full_lattice(gpu, orc):
+    """L = 65536 with the default kernel there (queued, 16-row bands): the whole
+    lattice bit for bit after one heat-bath sweep at beta_c."""
+    from layout import pack_rows
+
+    cfg = workloads.HEADLINE
+    L, beta = cfg["L"], workloads.BETA_CRIT_CONFIG
+    print("heat bath L=65536, 1 sweep", flush=True)
+    lat = gpu.Lattice(L, seed=cfg["seed"], stream_id=cfg["stream"])
+    lat.sweep(beta, cfg["J"], 1, 0, rule="heatbath")
+    got = lat.packed()
+    del lat
+    ref = orc.init(L, cfg["seed"], cfg["stream"])
+    orc.sweeps(ref, beta, cfg["J"], cfg["seed"], cfg["stream"], 1, 0, rule="heatbath")
+    assert np.array_equal(got, pack_rows(ref))
