@@ -164,13 +164,14 @@ struct Rule5 {
     {
         rows::block5<true>(s, q, chunk, a);
     }
-    __device__ static uint32_t *half_pair(State &s, int k)
+    template <class S>
+    __device__ static auto half_pair(S &s, int k) -> decltype(&s.tf[0])
     {
         return k == 0 ? s.tf : (k == 1 ? s.p : (k == 2 ? s.b0 : (k == 3 ? s.b1 : s.b2)));
     }
     __device__ static uint64_t word(const State &s, int k)
     {
-        const uint32_t *h = half_pair(const_cast<State &>(s), k);
+        const uint32_t *h = half_pair(s, k);
         return rows::join(h[0], h[1]);
     }
     __device__ static void set_word(State &s, int k, uint64_t v)
