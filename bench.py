@@ -31,6 +31,13 @@ import workloads  # noqa: E402
 
 HBM_PEAK_GBS = 8000.0  # MI355X HBM3E, GB/s
 MFMA_FP16_PEAK_TFLOPS = 2500.0  # MI355X dense fp16 MFMA, TFLOP/s
+# Philox4x32-10 blocks per second on the whole chip with this counter layout
+# (a throughput probe of the generator alone on gfx950), and the blocks a
+# 64-spin word takes on average near T_c under the lazy compare: together the
+# rate no sweep that draws its random bits this way can exceed.
+PHILOX_BLOCKS_PER_S = 7.0e11
+BLOCKS_PER_WORD = 3.84
+PHILOX_CEILING_FLIPS_PER_NS = PHILOX_BLOCKS_PER_S * 64 / BLOCKS_PER_WORD / 1e9
 KERNEL_SOURCES = ("paper_1906_06297_amd/csrc/sweep_kernels.hip",
                   "paper_1906_06297_amd/csrc/ising_device.hpp",
                   "paper_1906_06297_amd/csrc/ising_rows.hpp")
@@ -201,6 +208,8 @@ def bench_batched(ising, torch, nsweeps: int) -> dict:
         "largest_size_count": len(big),
         "tiles_words_lanes": {str(k): list(v) for k, v in tiles.items()},
         "autotune_s": tune_s,
+        "philox_ceiling_flips_per_ns": PHILOX_CEILING_FLIPS_PER_NS,
+        "frac_of_philox_ceiling": updates / (ms * 1e6) / PHILOX_CEILING_FLIPS_PER_NS,
     }
 
 
@@ -532,6 +541,8 @@ def main() -> int:
             "avg_launch_us": half_sweep_ms * 1e3,
             "alg_bytes_per_launch": alg_bytes,
             "valu": valu_issue(half_sweep_ms * 1e3),
+            "philox_ceiling_flips_per_ns": PHILOX_CEILING_FLIPS_PER_NS,
+            "frac_of_philox_ceiling": (L * L / 2) / (half_sweep_ms * 1e6) / PHILOX_CEILING_FLIPS_PER_NS,
         },
     }
     if args.heatbath_sweeps > 0:
