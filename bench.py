@@ -351,6 +351,52 @@ def bench_matmul(ising, torch, steps: int, sizes=None) -> dict:
     return out
 
 
+def bench_hybrid64(ising, torch, sweeps: int) -> dict:
+    """The hybrid chain at L = 64: 16 betas in [0.40, 0.48] with 16 chains each,
+    a 64-channel network trained on plain-sampler configurations pooled over
+    those betas, one global move per 10 local sweeps, against independent
+    plain chains: E per site and Binder cumulant with jackknife errors,
+    tau_int(|m|) per measurement, and effective samples per second."""
+    from paper_1906_06297_amd import hybrid
+
+    L, C = 64, 64
+    betas = np.linspace(0.40, 0.48, 16)
+    t0 = time.perf_counter()
+    data = hybrid.plain_configurations(L, betas, chains=256, snapshots=8, thin=100, burn=20000,
+                                       seed=61, stream_base=4096)
+    net = ising.ARNet(L, C, 256)
+    try:
+        net.set_params(hybrid.init_params(L, C, seed=3))
+        hist = hybrid.train(net, data, steps=300, batch=64, lr=2e-3, seed=4, log_every=100)
+        torch.cuda.synchronize()
+        t_train = time.perf_counter() - t0
+        res = hybrid.compare_over_betas(net, L, betas, per_beta=16, sweeps=sweeps,
+                                        sweeps_per_proposal=10, burn=20000, seed_plain=71,
+                                        seed_hybrid=72)
+    finally:
+        net.close()
+    out = {"per_beta": [], "train_s": t_train, "train_nll_per_site": hist}
+    z = []
+    for p, h in zip(res["plain"]["per_beta"], res["hybrid"]["per_beta"]):
+        row = {"beta": p["beta"]}
+        for kind, r in (("plain", p), ("hybrid", h)):
+            row[kind] = {k: r[k] for k in ("E_per_site", "E_se", "binder", "binder_se",
+                                           "tau_int_abs_m", "acceptance")}
+        for key, err in (("E_per_site", "E_se"), ("binder", "binder_se")):
+            z.append((h[key] - p[key]) / float(np.hypot(p[err], h[err])))
+        out["per_beta"].append(row)
+    n_meas = res["plain"]["measurements"] * 16  # measurements x chains, per beta
+    for kind in ("plain", "hybrid"):
+        taus = np.array([r["tau_int_abs_m"] for r in res[kind]["per_beta"]])
+        out[f"{kind}_wall_s"] = res[kind]["wall_s"]
+        out[f"{kind}_ess_per_s_abs_m"] = float(np.sum(n_meas / (2 * taus)) / res[kind]["wall_s"])
+    out["max_abs_z"] = float(np.max(np.abs(z)))
+    out["workload"] = (f"L={L}, 16 betas in [0.40, 0.48] x 16 chains, {C}-channel net trained 300 "
+                       f"steps on 2048 pooled plain-sampler configurations; {sweeps} sweeps after "
+                       "20000 burn-in, a global move every 10 sweeps (hybrid) against plain chains")
+    return out
+
+
 def bench_learned(ising, torch, L: int = 32, betas=(0.42, 0.44, 0.46), C: int = 32,
                   chains: int = 4096, rounds: int = 400, train_steps: int = 1500,
                   data_log2: int = 20) -> dict:
@@ -430,6 +476,8 @@ def main() -> int:
                          "beside the headline (0 = skip)")
     ap.add_argument("--glass-sweeps", type=int, default=20,
                     help="sweeps per beta of the +-J spin glass on the headline lattices (0 = skip)")
+    ap.add_argument("--hybrid64-sweeps", type=int, default=1500,
+                    help="sweeps of the L = 64 hybrid-chain comparison (0 = skip)")
     ap.add_argument("--matmul-sweeps", type=int, default=5,
                     help="minimum sweeps per size of the matrix-multiply comparison (0 = skip)")
     ap.add_argument("--matmul-L", type=int, nargs="*", default=None,
@@ -555,6 +603,8 @@ def main() -> int:
         out["batched"] = bench_batched(ising, torch, args.batched_sweeps)
     if args.learned_rounds > 0:
         out["learned"] = bench_learned(ising, torch, rounds=args.learned_rounds)
+    if args.hybrid64_sweeps > 0:
+        out["hybrid_L64"] = bench_hybrid64(ising, torch, args.hybrid64_sweeps)
     if args.copy_calibration:
         del bufs, lats
         a = torch.empty(1 << 27, dtype=torch.int64, device="cuda").fill_(1)
