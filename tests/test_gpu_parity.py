@@ -176,15 +176,17 @@ def test_headline_size_sampled_windows(gpu, orc, beta):
 
 
 @pytest.mark.parametrize("variant", [0, 1, 2, 3, 4, 5])
-@pytest.mark.parametrize("L,nsw", [(128, 6), (384, 6), (1024, 4), (8192, 2), (8320, 2), (16384, 1)])
+@pytest.mark.parametrize("L,nsw", [(128, 6), (384, 6), (1000, 4), (1024, 4), (8190, 2), (8192, 2),
+                                   (8320, 2), (16384, 1)])
 @pytest.mark.parametrize("beta,J", [(workloads.BETA_CRIT_CONFIG, 1.0), (0.40, 1.0), (0.5, 1.0),
                                     (0.33, -1.0), (0.0, 1.0), (6.0, 1.0)])
 def test_every_kernel_variant_bit_exact(gpu, orc, variant, L, nsw, beta, J):
     """Default (by size), general-geometry kernel, the row kernel without the
     queue and the queued row kernel with 32-, 16- and 8-row bands at every size
-    give the oracle's lattice; sizes include wavefronts with
-    idle lanes (384: 3 words per colour row; 8320: 65) and rows of whole
-    64-word segments (8192: one wavefront per row, 16384: two)."""
+    give the oracle's lattice.  Sizes include rows that straddle words (1000,
+    8190: every choice takes the general kernel), wavefronts with idle lanes (384: 3 words per colour row; 8320: 65)
+    and rows of whole 64-word segments (8192: one wavefront per row, 16384:
+    two)."""
     say(f"variant {variant} L={L} beta={beta} J={J}")
     seed, stream = 300 + L, 1
     gpu.set_sweep_kernel(variant)
