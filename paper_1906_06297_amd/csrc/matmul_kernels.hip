@@ -14,7 +14,8 @@
 // with K the 128 x 128 matrix of ones on the diagonal and the first
 // superdiagonal.  The two products run as dense fp16 MFMA
 // (v_mfma_f32_16x16x32_f16, fp32 sums -- exact for these small integers);
-// K's fragments are formed in registers from the indices.  The products miss
+// K's fragments are formed in registers from the indices, once per tile and
+// only where they are nonzero (the products stay dense).  The products miss
 // one neighbour on one edge row and one edge column of the block, which
 // comes from the adjacent sub-lattice (the boundary step).  The spin update
 // then decides each run of 64 same-colour spins of a row -- one word of the
@@ -146,6 +147,14 @@ __device__ __forceinline__ void block_products(_Float16 (*sP)[kLd], _Float16 (*s
 #pragma unroll
         for (int n = 0; n < 8; ++n)
             acc[mi][n] = f32x4{0.f, 0.f, 0.f, 0.f};
+    // M1's fragment of column tile n at k step ks depends only on n - 2 ks
+    // and is zero unless that is -1 .. 2: the four nonzero ones, formed once
+    // (indices shifted by 32, as only differences of row and column matter)
+    half8 m1f[4];
+#pragma unroll
+    for (int d = 0; d < 4; ++d)
+        m1f[d] = k_col((uint32_t)(16 * d + 16) + r16, 32 + kq * 8, b); // n - 2 ks = d - 1
+    const half8 zero8 = {};
 #pragma unroll
     for (uint32_t k0 = 0; k0 < (uint32_t)kB; k0 += 32) {
         const uint32_t kk = k0 + kq * 8;
@@ -154,12 +163,16 @@ __device__ __forceinline__ void block_products(_Float16 (*sP)[kLd], _Float16 (*s
         for (int mi = 0; mi < 2; ++mi) {
             const uint32_t row = (2 * w + mi) * 16 + r16;
             pa[mi] = *reinterpret_cast<const half8 *>(&sP[row][kk]);
-            ma[mi] = k_row(row, kk, !a); // M2 = K for a = 1, K^T for a = 0
+            // M2 = K for a = 1, K^T for a = 0; zero unless the row tile is within
+            // one of this k step's diagonal block (a wave-uniform test)
+            const int d = (int)(2 * w + mi) - (int)(k0 / 16);
+            ma[mi] = (d >= -1 && d <= 2) ? k_row(row, kk, !a) : zero8;
         }
 #pragma unroll
         for (int n = 0; n < 8; ++n) {
             const uint32_t col = n * 16 + r16;
-            const half8 mb = k_col(col, kk, b); // M1 = K^T for b = 1, K for b = 0
+            const int d = n - (int)(k0 / 16); // n - 2 ks
+            const half8 mb = (d >= -1 && d <= 2) ? m1f[d + 1] : zero8; // M1 = K^T (b) or K
             const half8 qb = *reinterpret_cast<const half8 *>(&sQt[col][kk]);
 #pragma unroll
             for (int mi = 0; mi < 2; ++mi) {
