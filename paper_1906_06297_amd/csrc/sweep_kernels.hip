@@ -91,8 +91,10 @@ __global__ __launch_bounds__(256) void k_sweep_rows(uint64_t *__restrict__ tgt,
 // per-word steps run on 32-bit halves with gfx950's three-input logic
 // instruction (ising_rows.hpp).
 //
-// New words are collected in a ring of kRing rows in LDS, and row r goes to
-// memory as one coalesced 512-byte store when row r + kRing needs its slot,
+// New words are collected in a ring of R rows in LDS (R = 4 under Metropolis,
+// 2 under the heat bath, whose larger queue entries leave less LDS: the
+// smaller ring keeps a fifth wavefront per SIMD, ~4 % faster), and row r goes
+// to memory as one coalesced 512-byte store when row r + R needs its slot,
 // so that HBM sees whole lines instead of the scattered 8-byte stores of
 // words finished in the queue.  A word still undecided then (a few per
 // thousand) is stored on its own when it is final.
@@ -101,7 +103,6 @@ typedef uint64_t u64x2 __attribute__((ext_vector_type(2)));
 constexpr uint32_t kStreamBlocks = 3;
 constexpr uint32_t kQueueCap = 128; // < 64 entries left after a drain + 64 pushed per row
 constexpr int kWaves = 4;
-constexpr uint32_t kRing = 4; // power of two
 
 // The decision rule of the queued kernel: its per-word state, the words a
 // queue entry holds, and the start and block steps (ising_rows.hpp).
@@ -111,6 +112,7 @@ struct RuleMetro {
     using State = rows::State;
     using Args = SweepArgs2;
     static constexpr int kWords = 3;
+    static constexpr uint32_t kRing = 4; // LDS row-ring depth
     struct Setup {
         rows::ClassMasks cm;
     };
@@ -148,6 +150,7 @@ struct Rule5 {
     using State = rows::State5;
     using Args = rows::SweepArgs5;
     static constexpr int kWords = 5;
+    static constexpr uint32_t kRing = 2;
     struct Setup {};
     __device__ static Setup setup(const Args &) { return Setup{}; }
     template <bool Anti, bool Plain>
@@ -189,9 +192,10 @@ struct WaveQueue {
     uint32_t meta[kQueueCap];  // next Philox block | lane << 4 | band row << 10
 };
 
+template <uint32_t R> // rows, a power of two
 struct WaveRing {
-    uint64_t word[kRing][64]; // new words of the last kRing rows
-    uint8_t done[kRing][64];  // 1 where the word is final
+    uint64_t word[R][64]; // new words of the last R rows
+    uint8_t done[R][64];  // 1 where the word is final
 };
 
 __device__ __forceinline__ uint32_t lanes_below(uint64_t ballot)
@@ -217,7 +221,8 @@ __device__ __forceinline__ bool undecided(const State &s) { return (s.p[0] | s.p
 
 // Writes ring slot `sl` to row pointer `rowp`: every word, or (`only_done`)
 // the final ones.
-__device__ __forceinline__ void ring_store(const WaveRing &rg, uint32_t sl,
+template <uint32_t R>
+__device__ __forceinline__ void ring_store(const WaveRing<R> &rg, uint32_t sl,
                                            uint64_t *__restrict__ rowp, uint32_t wc, bool active,
                                            int lane, bool only_done)
 {
@@ -231,9 +236,10 @@ __device__ __forceinline__ void ring_store(const WaveRing &rg, uint32_t sl,
 // finished words go to their ring slot (or, for a row already written, to
 // memory), the rest are appended again at the tail.  A word still undecided
 // after block 15 (all 32 planes) has r == T: rejected, and final as it is.
-// Rows up to r_cur - kRing have left the ring.
+// Rows up to r_cur - Rule::kRing have left the ring.
 template <class Rule>
-__device__ __forceinline__ void drain_once(WaveQueue<Rule::kWords> &wq, WaveRing &rg,
+__device__ __forceinline__ void drain_once(WaveQueue<Rule::kWords> &wq,
+                                           WaveRing<Rule::kRing> &rg,
                                            uint32_t &head, uint32_t &len, uint32_t n,
                                            uint32_t r_cur, uint64_t *__restrict__ tgt,
                                            const typename Rule::Args &a, int lane)
@@ -256,8 +262,8 @@ __device__ __forceinline__ void drain_once(WaveQueue<Rule::kWords> &wq, WaveRing
     len -= n;
     const bool keep = mine && q < 15u && undecided(s);
     const bool fin = mine && !keep;
-    const uint32_t er = meta >> 10, el = (meta >> 4) & 63u, es = er & (kRing - 1);
-    const bool owned = er + kRing > r_cur;
+    const uint32_t er = meta >> 10, el = (meta >> 4) & 63u, es = er & (Rule::kRing - 1);
+    const bool owned = er + Rule::kRing > r_cur;
     if (fin) {
         const uint64_t v = rows::join(s.tf[0], s.tf[1]);
         if (owned) {
@@ -318,12 +324,13 @@ __global__ __launch_bounds__(256) void k_sweep_rows_q(uint64_t *__restrict__ tgt
 {
     using Queue = WaveQueue<Rule::kWords>;
     __shared__ Queue queues[kWaves];
-    __shared__ WaveRing rings[kWaves];
+    constexpr uint32_t kRing = Rule::kRing;
+    __shared__ WaveRing<kRing> rings[kWaves];
     const int lane = threadIdx.x & 63;
     // wave-uniform: the row arithmetic stays on the scalar unit
     const uint32_t wv = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
     Queue &wq = queues[wv];
-    WaveRing &rg = rings[wv];
+    WaveRing<kRing> &rg = rings[wv];
     const uint32_t gwave = rows::xcd_block(blockIdx.x, gridDim.x) * kWaves + wv;
     const uint32_t band = gwave / waves_per_band;
     if (band >= nbands)
