@@ -167,7 +167,7 @@ def bench_batched(ising, torch, nsweeps: int) -> dict:
     Ls, betas, seeds, streams = workloads.batched_lattices()
     b = ising.Batch(Ls, betas, cfg["J"], seeds, streams)
     t0 = time.perf_counter()
-    tiles = b.autotune(20, None)
+    tiles = b.autotune(200, None)
     tune_s = time.perf_counter() - t0
     b.init()
     b.sweep(nsweeps)  # captures the graph (untimed), then a timed replay from a fresh start

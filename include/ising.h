@@ -252,17 +252,25 @@ int ising_batch_observables(const ising_batch *b, int64_t *d_bond, int64_t *d_ma
  * word -- a pair of lanes computes alternate Philox blocks of one word and
  * both apply them in order -- and wpt words per lane group, so a lattice of W
  * words per colour takes ceil(W / wpt) * lpw threads and floor(1024 / that)
- * lattices share a workgroup.  set replans the batch; results never depend
- * on the tile. */
+ * lattices share a workgroup (the autotuner may also cap that number).  set
+ * replans the batch and lifts the cap for L; results never depend on the
+ * tile. */
 int ising_batch_get_tiles(const ising_batch *b, int64_t L, uint32_t *wpt, uint32_t *lpw);
 int ising_batch_set_tiles(ising_batch *b, int64_t L, uint32_t wpt, uint32_t lpw);
 
-/* Times every tile candidate of every lattice size in the batch over
- * tune_sweeps sweeps of a scratch copy (the batch itself is unchanged),
- * requires all candidates to produce identical lattices, and keeps the
- * fastest.  cache_path (may be NULL) is a JSON file keyed by target and
- * kernel version: read if it covers every size, written after tuning.
- * Synchronises hip_stream; allocates scratch device memory while it runs. */
+/* Times every tile candidate of every lattice size in the batch -- each tile
+ * also with a half and a quarter of the lattices per workgroup -- over
+ * tune_sweeps sweeps of a scratch copy, each size alone (the batch itself is
+ * unchanged), and requires all candidates to produce identical lattices.  The
+ * tiles kept are chosen together for the whole launch: the workgroups the
+ * chip holds at once bound how many bundles start together, so the fastest
+ * tile of each size alone can leave bundles for a second round.  From the
+ * timings, a longest-first schedule on those workgroups estimates the
+ * makespan of each choice; the best estimate is then timed on the whole
+ * batch against the fastest tiles of each size and kept if faster.
+ * cache_path (may be NULL) is a JSON file keyed by target and kernel version:
+ * read if it covers every size, written after tuning.  Synchronises
+ * hip_stream; allocates scratch device memory while it runs. */
 int ising_batch_autotune(ising_batch *b, int64_t tune_sweeps, const char *cache_path,
                          void *hip_stream);
 

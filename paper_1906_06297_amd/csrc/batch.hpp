@@ -41,6 +41,9 @@ hipError_t launch_batch_sweep(const BatchLattice *lats, const uint32_t *members,
                               const BatchBundle *bundles, uint32_t nbundles, uint32_t grid,
                               size_t lds_bytes, uint32_t *next_bundle, uint64_t *words,
                               uint64_t *rng_counter, int64_t nsweeps, hipStream_t s);
+// Workgroups of the persistent sweep kernel one compute unit holds at once
+// with lds_bytes of dynamic LDS each (registers, wavefront slots and LDS).
+hipError_t batch_sweep_blocks_per_cu(size_t lds_bytes, int *blocks);
 hipError_t launch_batch_to_spins(const BatchLattice *lats, uint32_t n, const uint64_t *words,
                                  const int64_t *spin_off, int8_t *spins, hipStream_t s);
 hipError_t launch_batch_from_spins(const BatchLattice *lats, uint32_t n, uint64_t *words,

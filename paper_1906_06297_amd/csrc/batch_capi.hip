@@ -15,14 +15,16 @@
 
 #include "../../include/ising.h"
 #include "batch.hpp"
+#include "batch_plan.hpp"
 #include "host_common.hpp"
 
 using namespace ising;
 
 namespace {
 struct Tile {
-    uint32_t wpt; // words per lane group
-    uint32_t lpw; // lanes per word (1 or 2)
+    uint32_t wpt;     // words per lane group
+    uint32_t lpw;     // lanes per word (1 or 2)
+    uint32_t cap = 0; // most lattices per bundle, 0 = as many as the workgroup holds
 };
 } // namespace
 
@@ -33,6 +35,7 @@ struct ising_batch {
     uint64_t *words = nullptr;      // caller's buffer
     size_t bytes = 0;
     std::map<int64_t, Tile> tiles;   // per lattice size
+    std::map<int64_t, double> est_ms; // tuned duration of one bundle per size, if known
     // device state owned by the batch
     BatchLattice *d_lats = nullptr;
     uint32_t *d_members = nullptr;
@@ -88,6 +91,11 @@ Plan make_plan(const ising_batch *b, int64_t only_L, Tile only)
     for (int32_t q = 0; q < b->n; ++q)
         if (!only_L || b->Ls[q] == only_L)
             by_size[b->Ls[q]].push_back((uint32_t)q);
+    // bundles start longest first: by their tuned durations when every size
+    // has one, else by spins
+    bool have_est = !only_L;
+    for (auto &kv : by_size)
+        have_est = have_est && b->est_ms.count(kv.first);
     struct Item {
         double work;
         BatchBundle bd;
@@ -101,14 +109,15 @@ Plan make_plan(const ising_batch *b, int64_t only_L, Tile only)
         const uint32_t tpl = threads_per_lattice(W, tile);
         // lattices per workgroup: limited by its threads and by 64 KiB of LDS
         const uint32_t lds_per = (uint32_t)(kMaxBundleLds / ((size_t)batch_lds_words(W) * 8));
-        const uint32_t per =
-            std::max(1u, std::min((uint32_t)kBatchThreads / tpl, lds_per));
+        uint32_t per = std::max(1u, std::min((uint32_t)kBatchThreads / tpl, lds_per));
+        if (tile.cap)
+            per = std::min(per, tile.cap);
         for (size_t i = 0; i < kv.second.size(); i += per) {
             Item it;
             const uint32_t cnt = (uint32_t)std::min<size_t>(per, kv.second.size() - i);
             it.ids.assign(kv.second.begin() + i, kv.second.begin() + i + cnt);
             it.bd = BatchBundle{0, cnt, tile.wpt, tpl, tile.lpw, 0};
-            it.work = (double)cnt * (double)(L * L);
+            it.work = have_est ? b->est_ms.at(L) : (double)cnt * (double)(L * L);
             items.push_back(std::move(it));
         }
     }
@@ -139,20 +148,32 @@ void free_plan_buffers(ising_batch *b)
     b->exec_nsweeps = -1;
 }
 
-// Workgroups of the persistent kernel: enough for every compute unit to hold
-// as many as its LDS and wavefront slots allow (two of 1024 threads), never
-// more than bundles.
-int persistent_grid(size_t lds_bytes, uint32_t nbundles, uint32_t *grid)
+// Workgroups of the persistent kernel the chip holds at once: compute units
+// times what one holds with lds_bytes of LDS each.
+int resident_slots(size_t lds_bytes, uint32_t *slots)
 {
-    int dev = 0, cus = 0;
+    int dev = 0, cus = 0, occ = 0;
     hipError_t e = hipGetDevice(&dev);
     if (e == hipSuccess)
         e = hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev);
     if (e != hipSuccess || cus <= 0)
         return host::fail(ISING_E_HIP, "cannot query the number of compute units");
-    const int by_lds = lds_bytes ? (int)((160 * 1024) / lds_bytes) : 2;
-    const int occ = std::max(1, std::min(2, by_lds));
-    *grid = std::max(1u, std::min(nbundles, (uint32_t)(cus * occ)));
+    e = batch_sweep_blocks_per_cu(lds_bytes, &occ);
+    if (e != hipSuccess || occ <= 0)
+        return host::fail(ISING_E_HIP, "the batch kernel does not fit a compute unit with %zu B "
+                          "of LDS", lds_bytes);
+    *slots = (uint32_t)cus * (uint32_t)occ;
+    return ISING_OK;
+}
+
+// Workgroups of the persistent kernel: all resident at once, never more than
+// bundles; further bundles go to whichever workgroup finishes first.
+int persistent_grid(size_t lds_bytes, uint32_t nbundles, uint32_t *grid)
+{
+    uint32_t slots = 0;
+    if (int rc = resident_slots(lds_bytes, &slots))
+        return rc;
+    *grid = std::max(1u, std::min(nbundles, slots));
     return ISING_OK;
 }
 
@@ -182,7 +203,7 @@ int check_batch(const ising_batch *b)
 }
 
 // ---------------------------------------------------------------- cache file
-std::string cache_key() { return "gfx950/batch-sweep-v3"; }
+std::string cache_key() { return "gfx950/batch-sweep-v5"; }
 
 bool read_cache(const char *path, std::map<int64_t, Tile> &out)
 {
@@ -208,9 +229,9 @@ bool read_cache(const char *path, std::map<int64_t, Tile> &out)
             ch = ' ';
     std::istringstream in(body);
     long long L;
-    unsigned w, l;
-    while (in >> L >> w >> l)
-        out[(int64_t)L] = Tile{w, l};
+    unsigned w, l, c;
+    while (in >> L >> w >> l >> c)
+        out[(int64_t)L] = Tile{w, l, c};
     return true;
 }
 
@@ -223,7 +244,7 @@ bool write_cache(const char *path, const std::map<int64_t, Tile> &tiles)
     bool first = true;
     for (auto &kv : tiles) {
         f << (first ? "" : ", ") << "\"" << kv.first << "\": [" << kv.second.wpt << ", "
-          << kv.second.lpw << "]";
+          << kv.second.lpw << ", " << kv.second.cap << "]";
         first = false;
     }
     f << "}}\n";
@@ -500,6 +521,7 @@ int ising_batch_set_tiles(ising_batch *b, int64_t L, uint32_t wpt, uint32_t lpw)
         return host::fail(ISING_E_BADARG, "tile (%u words, %u lanes per word) does not fit a "
                           "workgroup of %d threads", wpt, lpw, kBatchThreads);
     it->second = Tile{wpt, lpw};
+    b->est_ms.erase(L); // bundles go back to ordering by spins
     return install_plan(b, make_plan(b, 0, Tile{1, 1}));
 }
 
@@ -511,6 +533,7 @@ int ising_batch_autotune(ising_batch *b, int64_t tune_sweeps, const char *cache_
     if (tune_sweeps <= 0)
         return host::fail(ISING_E_BADARG, "tune_sweeps must be > 0");
     hipStream_t s = (hipStream_t)hip_stream;
+    b->est_ms.clear();
     std::map<int64_t, Tile> cached;
     if (cache_path && read_cache(cache_path, cached)) {
         bool complete = true;
@@ -538,10 +561,62 @@ int ising_batch_autotune(ising_batch *b, int64_t tune_sweeps, const char *cache_
         e = hipEventCreate(&e0);
     if (e == hipSuccess)
         e = hipEventCreate(&e1);
-    std::vector<uint64_t> out_ref, out_try;
     int rc = ISING_OK;
+    // Runs plan p for tune_sweeps sweeps on the scratch copy, from the batch's
+    // lattices and counter 0 every time; best of two launches, lattices to out.
+    auto time_plan = [&](const Plan &p, float *best, std::vector<uint64_t> &out) -> bool {
+        uint32_t grid = 0;
+        if ((rc = persistent_grid(p.lds_bytes, (uint32_t)p.bundles.size(), &grid)))
+            return false;
+        if (members)
+            (void)hipFree(members);
+        if (bundles)
+            (void)hipFree(bundles);
+        members = nullptr;
+        bundles = nullptr;
+        e = hipMalloc(&members, p.members.size() * 4);
+        if (e == hipSuccess)
+            e = hipMalloc(&bundles, p.bundles.size() * sizeof(BatchBundle));
+        if (e == hipSuccess)
+            e = hipMemcpy(members, p.members.data(), p.members.size() * 4, hipMemcpyHostToDevice);
+        if (e == hipSuccess)
+            e = hipMemcpy(bundles, p.bundles.data(), p.bundles.size() * sizeof(BatchBundle),
+                          hipMemcpyHostToDevice);
+        *best = 1e30f;
+        for (int rep = 0; rep < 2 && e == hipSuccess; ++rep) {
+            const uint64_t zero = 0;
+            float ms = 0.f;
+            e = hipMemcpyAsync(scratch, b->words, nbytes, hipMemcpyDeviceToDevice, s);
+            if (e == hipSuccess)
+                e = hipMemcpyAsync(ctr, &zero, 8, hipMemcpyHostToDevice, s);
+            if (e == hipSuccess)
+                e = hipEventRecord(e0, s);
+            if (e == hipSuccess)
+                e = launch_batch_sweep(b->d_lats, members, bundles, (uint32_t)p.bundles.size(),
+                                       grid, p.lds_bytes, next, scratch, ctr, tune_sweeps, s);
+            if (e == hipSuccess)
+                e = hipEventRecord(e1, s);
+            if (e == hipSuccess)
+                e = hipEventSynchronize(e1);
+            if (e == hipSuccess)
+                e = hipEventElapsedTime(&ms, e0, e1);
+            *best = std::min(*best, ms);
+        }
+        if (e == hipSuccess) {
+            out.resize(nbytes / 8);
+            e = hipMemcpy(out.data(), scratch, nbytes, hipMemcpyDeviceToHost);
+        }
+        return e == hipSuccess;
+    };
+    // Every tile candidate of each size, timed with that size alone.
+    std::vector<int64_t> sizes;
+    std::vector<std::vector<plan::Option>> opts;
+    std::vector<std::vector<Tile>> opt_tiles;
+    std::vector<size_t> fastest;
+    uint32_t slots = 0;
+    std::vector<uint64_t> out_ref, out_try;
     for (auto &kv : b->tiles) {
-        if (e != hipSuccess)
+        if (e != hipSuccess || rc != ISING_OK)
             break;
         const int64_t L = kv.first;
         const uint32_t W = words_of(L);
@@ -558,71 +633,72 @@ int ising_batch_autotune(ising_batch *b, int64_t tune_sweeps, const char *cache_
                 if (!dup)
                     cands.push_back(t);
             }
-        float best_ms = 1e30f;
-        Tile best = kv.second;
-        bool have_ref = false;
+        // and each with fewer lattices per bundle: half-empty workgroups run
+        // their lattices' sweeps sooner, on compute units the batch leaves idle
+        const size_t nbase = cands.size();
+        for (size_t i = 0; i < nbase; ++i) {
+            const uint32_t full = make_plan(b, L, cands[i]).bundles.front().count;
+            for (uint32_t cap : {full / 2, full / 4})
+                if (cap >= 1 && cap < full)
+                    cands.push_back(Tile{cands[i].wpt, cands[i].lpw, cap});
+        }
+        std::vector<plan::Option> o;
+        std::vector<Tile> ot;
+        size_t fi = 0;
         for (const Tile &w : cands) {
             const Plan p = make_plan(b, L, w);
-            uint32_t grid = 0;
-            if ((rc = persistent_grid(p.lds_bytes, (uint32_t)p.bundles.size(), &grid)))
+            uint32_t held = 0;
+            if ((rc = resident_slots(p.lds_bytes, &held)))
                 break;
-            if (members)
-                (void)hipFree(members);
-            if (bundles)
-                (void)hipFree(bundles);
-            members = nullptr;
-            bundles = nullptr;
-            e = hipMalloc(&members, p.members.size() * 4);
-            if (e == hipSuccess)
-                e = hipMalloc(&bundles, p.bundles.size() * sizeof(BatchBundle));
-            if (e == hipSuccess)
-                e = hipMemcpy(members, p.members.data(), p.members.size() * 4,
-                              hipMemcpyHostToDevice);
-            if (e == hipSuccess)
-                e = hipMemcpy(bundles, p.bundles.data(), p.bundles.size() * sizeof(BatchBundle),
-                              hipMemcpyHostToDevice);
+            slots = slots ? std::min(slots, held) : held;
             float ms = 0.f;
-            for (int rep = 0; rep < 2 && e == hipSuccess; ++rep) {
-                // same start for every candidate: the batch's lattices, counter 0
-                const uint64_t zero = 0;
-                e = hipMemcpyAsync(scratch, b->words, nbytes, hipMemcpyDeviceToDevice, s);
-                if (e == hipSuccess)
-                    e = hipMemcpyAsync(ctr, &zero, 8, hipMemcpyHostToDevice, s);
-                if (e == hipSuccess)
-                    e = hipEventRecord(e0, s);
-                if (e == hipSuccess)
-                    e = launch_batch_sweep(b->d_lats, members, bundles,
-                                           (uint32_t)p.bundles.size(), grid, p.lds_bytes, next,
-                                           scratch, ctr, tune_sweeps, s);
-                if (e == hipSuccess)
-                    e = hipEventRecord(e1, s);
-                if (e == hipSuccess)
-                    e = hipEventSynchronize(e1);
-                if (e == hipSuccess)
-                    e = hipEventElapsedTime(&ms, e0, e1);
-            }
-            if (e != hipSuccess)
+            if (!time_plan(p, &ms, o.empty() ? out_ref : out_try))
                 break;
             // every candidate must reproduce the same lattices bit for bit
-            std::vector<uint64_t> &dst = have_ref ? out_try : out_ref;
-            dst.resize(nbytes / 8);
-            e = hipMemcpy(dst.data(), scratch, nbytes, hipMemcpyDeviceToHost);
-            if (e != hipSuccess)
-                break;
-            if (have_ref && out_try != out_ref) {
-                rc = host::fail(ISING_E_HIP, "autotune: tile (%u, %u) of L=%lld changed the "
-                                "lattice", w.wpt, w.lpw, (long long)L);
+            if (!o.empty() && out_try != out_ref) {
+                rc = host::fail(ISING_E_HIP, "autotune: tile (%u, %u, %u) of L=%lld changed the "
+                                "lattice", w.wpt, w.lpw, w.cap, (long long)L);
                 break;
             }
-            have_ref = true;
-            if (ms < best_ms) {
-                best_ms = ms;
-                best = w;
+            o.push_back(plan::Option{(uint32_t)p.bundles.size(), (double)ms});
+            ot.push_back(w);
+            if (o.back().ms < o[fi].ms)
+                fi = o.size() - 1;
+        }
+        if (e != hipSuccess || rc != ISING_OK)
+            break;
+        sizes.push_back(L);
+        opts.push_back(std::move(o));
+        opt_tiles.push_back(std::move(ot));
+        fastest.push_back(fi);
+    }
+    // The tiles for the whole launch: the estimated best, kept only if the
+    // whole batch, timed both ways, runs faster with it than with the fastest
+    // tile of every size alone.
+    auto apply = [&](const std::vector<size_t> &pick) {
+        for (size_t i = 0; i < sizes.size(); ++i) {
+            b->tiles[sizes[i]] = opt_tiles[i][pick[i]];
+            b->est_ms[sizes[i]] = plan::bundle_ms(opts[i][pick[i]], slots);
+        }
+    };
+    if (e == hipSuccess && rc == ISING_OK) {
+        std::vector<size_t> pick = plan::choose(opts, fastest, slots);
+        if (pick != fastest) {
+            float ms_fast = 0.f, ms_pick = 0.f;
+            apply(fastest);
+            if (time_plan(make_plan(b, 0, Tile{1, 1}), &ms_fast, out_ref)) {
+                apply(pick);
+                if (time_plan(make_plan(b, 0, Tile{1, 1}), &ms_pick, out_try)) {
+                    if (out_try != out_ref)
+                        rc = host::fail(ISING_E_HIP, "autotune: the joint tiles changed the "
+                                        "lattices");
+                    else if (ms_fast < ms_pick)
+                        pick = fastest;
+                }
             }
         }
-        if (rc != ISING_OK)
-            break;
-        kv.second = best;
+        if (e == hipSuccess && rc == ISING_OK)
+            apply(pick);
     }
     if (members)
         (void)hipFree(members);
@@ -638,6 +714,8 @@ int ising_batch_autotune(ising_batch *b, int64_t tune_sweeps, const char *cache_
         (void)hipEventDestroy(e0);
     if (e1)
         (void)hipEventDestroy(e1);
+    if (rc != ISING_OK || e != hipSuccess)
+        b->est_ms.clear();
     if (rc != ISING_OK)
         return rc;
     if (e != hipSuccess)

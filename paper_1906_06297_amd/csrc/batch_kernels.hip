@@ -149,6 +149,12 @@ __global__ void k_batch_advance(uint64_t *rng_counter, int64_t nsweeps)
         *rng_counter += (uint64_t)nsweeps;
 }
 
+hipError_t batch_sweep_blocks_per_cu(size_t lds_bytes, int *blocks)
+{
+    return hipOccupancyMaxActiveBlocksPerMultiprocessor(blocks, k_batch_sweep, kBatchThreads,
+                                                        lds_bytes);
+}
+
 // Per-lattice bond sum and magnetisation; one workgroup per lattice.
 __global__ __launch_bounds__(256) void k_batch_observables(const BatchLattice *__restrict__ lats,
                                                            const uint64_t *__restrict__ words,
