@@ -258,6 +258,12 @@ int ising_batch_observables(const ising_batch *b, int64_t *d_bond, int64_t *d_ma
 int ising_batch_get_tiles(const ising_batch *b, int64_t L, uint32_t *wpt, uint32_t *lpw);
 int ising_batch_set_tiles(ising_batch *b, int64_t L, uint32_t wpt, uint32_t lpw);
 
+/* The current plan for the lattices of size L: how many share one workgroup
+ * of the persistent kernel and how many workgroups they fill.  BADARG if the
+ * batch has no lattice of size L or an output pointer is NULL. */
+int ising_batch_get_plan(const ising_batch *b, int64_t L, uint32_t *lattices_per_workgroup,
+                         uint32_t *workgroups);
+
 /* Times every tile candidate of every lattice size in the batch -- each tile
  * also with a half and a quarter of the lattices per workgroup -- over
  * tune_sweeps sweeps of a scratch copy, each size alone (the batch itself is

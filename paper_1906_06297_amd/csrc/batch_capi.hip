@@ -60,6 +60,16 @@ uint32_t words_of(int64_t L) { return (uint32_t)((L * L / 2 + 63) / 64); }
 
 uint32_t threads_per_lattice(uint32_t W, Tile t) { return ((W + t.wpt - 1) / t.wpt) * t.lpw; }
 
+// Lattices of W words per colour that one workgroup takes: limited by its
+// threads, by 64 KiB of LDS and by the tile's cap.
+uint32_t lattices_per_bundle(uint32_t W, Tile t)
+{
+    const uint32_t lds_per = (uint32_t)(kMaxBundleLds / ((size_t)batch_lds_words(W) * 8));
+    uint32_t per = std::max(1u, std::min((uint32_t)kBatchThreads / threads_per_lattice(W, t),
+                                         lds_per));
+    return t.cap ? std::min(per, t.cap) : per;
+}
+
 bool tile_ok(uint32_t W, Tile t)
 {
     return t.wpt >= 1 && t.wpt <= W && (t.lpw == 1 || t.lpw == 2) &&
@@ -107,11 +117,7 @@ Plan make_plan(const ising_batch *b, int64_t only_L, Tile only)
         const uint32_t W = words_of(L);
         const Tile tile = only_L ? only : b->tiles.at(L);
         const uint32_t tpl = threads_per_lattice(W, tile);
-        // lattices per workgroup: limited by its threads and by 64 KiB of LDS
-        const uint32_t lds_per = (uint32_t)(kMaxBundleLds / ((size_t)batch_lds_words(W) * 8));
-        uint32_t per = std::max(1u, std::min((uint32_t)kBatchThreads / tpl, lds_per));
-        if (tile.cap)
-            per = std::min(per, tile.cap);
+        const uint32_t per = lattices_per_bundle(W, tile);
         for (size_t i = 0; i < kv.second.size(); i += per) {
             Item it;
             const uint32_t cnt = (uint32_t)std::min<size_t>(per, kv.second.size() - i);
@@ -203,7 +209,7 @@ int check_batch(const ising_batch *b)
 }
 
 // ---------------------------------------------------------------- cache file
-std::string cache_key() { return "gfx950/batch-sweep-v5"; }
+std::string cache_key() { return "gfx950/batch-sweep-v6"; }
 
 bool read_cache(const char *path, std::map<int64_t, Tile> &out)
 {
@@ -507,6 +513,21 @@ int ising_batch_get_tiles(const ising_batch *b, int64_t L, uint32_t *wpt, uint32
         return host::fail(ISING_E_BADARG, "no lattice of that size in the batch");
     *wpt = it->second.wpt;
     *lpw = it->second.lpw;
+    return host::ok();
+}
+
+int ising_batch_get_plan(const ising_batch *b, int64_t L, uint32_t *lattices_per_workgroup,
+                         uint32_t *workgroups)
+{
+    if (int e = check_batch(b))
+        return e;
+    auto it = b->tiles.find(L);
+    if (!lattices_per_workgroup || !workgroups || it == b->tiles.end())
+        return host::fail(ISING_E_BADARG, "no lattice of that size in the batch");
+    const uint32_t n = (uint32_t)std::count(b->Ls.begin(), b->Ls.end(), L);
+    const uint32_t per = lattices_per_bundle(words_of(L), it->second);
+    *lattices_per_workgroup = std::min(per, n);
+    *workgroups = (n + per - 1) / per;
     return host::ok();
 }
 

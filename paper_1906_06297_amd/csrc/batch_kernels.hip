@@ -5,6 +5,7 @@
 
 #include "batch.hpp"
 #include "ising_rows.hpp"
+#include "pair_decision.hpp"
 
 namespace ising {
 
@@ -30,16 +31,19 @@ __device__ __forceinline__ void ext_refresh(uint64_t *E, uint32_t M, uint32_t W)
     E[W + 1] = tail[2];
 }
 
-__device__ __forceinline__ Block shuffle_xor1(const Block &x)
+__device__ __forceinline__ rows::BlockDecision shuffle_xor1(const rows::BlockDecision &x)
 {
-    return Block{(uint32_t)__shfl_xor((int)x.x0, 1, 64), (uint32_t)__shfl_xor((int)x.x1, 1, 64),
-                 (uint32_t)__shfl_xor((int)x.x2, 1, 64), (uint32_t)__shfl_xor((int)x.x3, 1, 64)};
+    return rows::BlockDecision{{(uint32_t)__shfl_xor((int)x.d[0], 1, 64),
+                                (uint32_t)__shfl_xor((int)x.d[1], 1, 64)},
+                               {(uint32_t)__shfl_xor((int)x.f[0], 1, 64),
+                                (uint32_t)__shfl_xor((int)x.f[1], 1, 64)}};
 }
 
 // Decision of one word by a pair of adjacent lanes: each lane computes every
-// other Philox block (lane parity p takes q = 2j + p), the pair swaps them and
-// both apply the planes in block order, so the pair reaches the sequential
-// result in half the dependent steps.  Both lanes hold the same state.
+// other Philox block (lane parity p takes q = 2j + p) and what that block
+// decides on its own, the pair swaps those and both apply them in block
+// order, so the pair reaches the sequential result in half the dependent
+// steps.  Both lanes hold the same state.
 __device__ __forceinline__ uint64_t decide_word_pair(uint64_t t, const Neighbours &nb,
                                                      uint64_t valid, uint32_t chunk,
                                                      const SweepArgs2 &a, uint32_t parity)
@@ -49,9 +53,10 @@ __device__ __forceinline__ uint64_t decide_word_pair(uint64_t t, const Neighbour
         const Block mine =
             rows::philox_fast<rows::kCtrKeyLane>(ctr_word0(a.stream_id, kDomainSweep, q0 + parity),
                                                  a.t_lo, a.t_hi, chunk, a.key0, a.key1);
-        const Block other = shuffle_xor1(mine);
-        rows::apply_block_lane(s, parity ? other : mine, q0, a.m);
-        rows::apply_block_lane(s, parity ? mine : other, q0 + 1, a.m);
+        const rows::BlockDecision dm = rows::block_decision_lane(s, mine, q0 + parity, a.m);
+        const rows::BlockDecision other = shuffle_xor1(dm);
+        rows::apply_decision(s, parity ? other : dm);
+        rows::apply_decision(s, parity ? dm : other);
     }
     return t ^ rows::join(s.tf[0], s.tf[1]);
 }
@@ -78,6 +83,12 @@ __global__ __launch_bounds__(kBatchThreads) void k_batch_sweep(
         if (b >= nbundles)
             return;
         const BatchBundle bd = bundles[b];
+        // A bundle holds lattices of one size.  When a colour is a whole
+        // number of words (M % 64 == 0, W >= 2) its continuation is a copy of
+        // words 0 and 1: the lanes that write those write the copies too, and
+        // the refresh and its barrier drop out of every half-sweep.
+        const BatchLattice first = lats[members[bd.first]];
+        const bool copy_ext = (first.M & 63) == 0 && first.W >= 2;
         const uint32_t slot = threadIdx.x / bd.tpl, li = threadIdx.x % bd.tpl;
         const uint32_t group = li / bd.lpw, parity = li % bd.lpw, groups = bd.tpl / bd.lpw;
         const bool on = slot < bd.count;
@@ -118,14 +129,19 @@ __global__ __launch_bounds__(kBatchThreads) void k_batch_sweep(
                         const uint64_t flips = (bd.lpw == 2)
                                                    ? decide_word_pair(tw, nb, valid, k, a, parity)
                                                    : rows::decide_word_any(tw, nb, valid, k, a);
-                        if (parity == 0)
+                        if (parity == 0) {
                             tgt[k] = tw ^ flips;
+                            if (copy_ext && k < 2)
+                                tgt[lt.W + k] = tw ^ flips;
+                        }
                     }
                 }
                 __syncthreads();
-                if (on && li == 0)
-                    ext_refresh(tgt, lt.M, lt.W);
-                __syncthreads();
+                if (!copy_ext) {
+                    if (on && li == 0)
+                        ext_refresh(tgt, lt.M, lt.W);
+                    __syncthreads();
+                }
             }
         }
         if (on)

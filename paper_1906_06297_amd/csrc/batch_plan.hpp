@@ -84,8 +84,8 @@ inline bool better(const Estimate &a, const Estimate &b)
 
 // From `start`, change one size's option at a time while the estimate gets
 // strictly better (the order is strict, so this ends).
-inline std::vector<size_t> choose(const std::vector<std::vector<Option>> &opts,
-                                  std::vector<size_t> start, uint32_t slots)
+inline std::vector<size_t> improve(const std::vector<std::vector<Option>> &opts,
+                                   std::vector<size_t> start, uint32_t slots)
 {
     std::vector<size_t> pick = std::move(start);
     Estimate best = estimate(opts, pick, slots);
@@ -106,6 +106,24 @@ inline std::vector<size_t> choose(const std::vector<std::vector<Option>> &opts,
             }
     }
     return pick;
+}
+
+// The better of two local searches: one from the fastest option of each size
+// alone (`fastest`), one from the option with the fewest bundles (the most
+// lattices per workgroup, the highest throughput of a compute unit).
+inline std::vector<size_t> choose(const std::vector<std::vector<Option>> &opts,
+                                  const std::vector<size_t> &fastest, uint32_t slots)
+{
+    std::vector<size_t> fewest(opts.size(), 0);
+    for (size_t i = 0; i < opts.size(); ++i)
+        for (size_t j = 1; j < opts[i].size(); ++j) {
+            const Option &a = opts[i][j], &c = opts[i][fewest[i]];
+            if (a.bundles < c.bundles || (a.bundles == c.bundles && a.ms < c.ms))
+                fewest[i] = j;
+        }
+    std::vector<size_t> p1 = improve(opts, fastest, slots);
+    std::vector<size_t> p2 = improve(opts, fewest, slots);
+    return better(estimate(opts, p2, slots), estimate(opts, p1, slots)) ? p2 : p1;
 }
 
 } // namespace plan

@@ -320,6 +320,13 @@ class Batch:
                                                      ctypes.byref(l)))
         return int(w.value), int(l.value)
 
+    def plan(self, L: int) -> tuple:
+        """(lattices per workgroup, workgroups) of the lattices of size L."""
+        per, n = ctypes.c_uint32(), ctypes.c_uint32()
+        _lib.check(_lib.load().ising_batch_get_plan(self._h, int(L), ctypes.byref(per),
+                                                    ctypes.byref(n)))
+        return int(per.value), int(n.value)
+
     def set_tiles(self, L: int, wpt: int, lpw: int = 1) -> None:
         _lib.check(_lib.load().ising_batch_set_tiles(self._h, int(L), int(wpt), int(lpw)))
 

@@ -6,6 +6,7 @@
 
 #include "../paper_1906_06297_amd/csrc/ising_device.hpp"
 #include "../paper_1906_06297_amd/csrc/ising_rows.hpp"
+#include "../paper_1906_06297_amd/csrc/pair_decision.hpp"
 
 using namespace ising;
 
@@ -74,6 +75,44 @@ static uint64_t queued_word5(uint64_t t, uint64_t up, uint64_t dn, uint64_t ce, 
 } // namespace
 
 extern "C" {
+
+// A lane pair's step: blocks q and q + 1 each reduced to what it decides on
+// its own and applied in order, against applying their planes one by one,
+// over n random states, blocks and thresholds; returns the mismatches.
+int emu_block_decision_check(uint64_t seed, int n)
+{
+    uint64_t z = seed * 0x9E3779B97F4A7C15ull + 1;
+    auto next = [&z]() { // splitmix64
+        uint64_t x = (z += 0x9E3779B97F4A7C15ull);
+        x = (x ^ (x >> 30)) * 0xBF58476D1CE4E5B9ull;
+        x = (x ^ (x >> 27)) * 0x94D049BB133111EBull;
+        return x ^ (x >> 31);
+    };
+    auto r32 = [&next]() { return (uint32_t)next(); };
+    int bad = 0;
+    for (int i = 0; i < n; ++i) {
+        rows::State s;
+        for (int h = 0; h < 2; ++h) {
+            s.tf[h] = r32();
+            s.p[h] = r32();
+            s.a[h] = r32();
+        }
+        Metro2 m{};
+        // thresholds with long runs of equal bits as well as random ones
+        m.thrA = (i & 1) ? r32() : (r32() | 0xFFFF0000u);
+        m.thrB = (i & 2) ? r32() : (r32() & 0x0000FFFFu);
+        const uint32_t q = (uint32_t)(next() % 15);
+        const Block x0{r32(), r32(), r32(), r32()}, x1{r32(), r32(), r32(), r32()};
+        rows::State ref = s, got = s;
+        rows::apply_block_lane(ref, x0, q, m);
+        rows::apply_block_lane(ref, x1, q + 1, m);
+        rows::apply_decision(got, rows::block_decision_lane(s, x0, q, m));
+        rows::apply_decision(got, rows::block_decision_lane(s, x1, q + 1, m));
+        for (int h = 0; h < 2; ++h)
+            bad += (ref.tf[h] != got.tf[h]) || (ref.p[h] != got.p[h]) || (ref.a[h] != got.a[h]);
+    }
+    return bad;
+}
 
 // Logical block of hardware block b of a grid of n blocks.
 uint32_t emu_xcd_block(uint32_t b, uint32_t n) { return rows::xcd_block(b, n); }

@@ -147,6 +147,8 @@ def test_batch_argument_errors_without_device(lib):
     assert lib.ising_batch_create(ctypes.byref(h), 3, L, b, 1.0, s, i, fake, 64) == _lib.ISING_E_SIZE
     assert lib.ising_batch_create(ctypes.byref(h), 2, bad, b, 1.0, s, i, fake, 1 << 20) == _lib.ISING_E_SIZE
     assert lib.ising_batch_sweep(None, 1, None) == _lib.ISING_E_BADARG
+    per, n = ctypes.c_uint32(), ctypes.c_uint32()
+    assert lib.ising_batch_get_plan(None, 16, ctypes.byref(per), ctypes.byref(n)) == _lib.ISING_E_BADARG
     assert lib.ising_batch_destroy(None) == _lib.ISING_OK
 
 

@@ -163,6 +163,9 @@ def test_autotune_keeps_results_and_writes_cache(gpu, orc, tmp_path):
     b.init()
     chosen = b.autotune(3, path)
     assert set(chosen) == {16, 96, 256}
+    plans = {L: b.plan(L) for L in chosen}
+    for L, (per, groups) in plans.items():
+        assert per >= 1 and (groups - 1) * per < Ls.count(L) <= groups * per, (L, per, groups)
     assert os.path.exists(path) and "gfx950" in open(path).read()
     b.sweep(5)
     ref = oracle_batch(orc, Ls, betas, 1.0, seeds, streams, 5)
@@ -171,4 +174,5 @@ def test_autotune_keeps_results_and_writes_cache(gpu, orc, tmp_path):
     b.close()
     b2 = gpu.Batch(Ls, betas, 1.0, seeds, streams)
     assert b2.autotune(3, path) == chosen  # served from the cache
+    assert {L: b2.plan(L) for L in chosen} == plans  # with the lattices per workgroup
     b2.close()

@@ -31,6 +31,7 @@ def emu(tmp_path_factory):
                                    ctypes.c_uint64, ctypes.c_uint64, ctypes.c_uint32, ctypes.c_int]
     lib.emu_half_sweep5.argtypes = [u64p, ctypes.c_int64, ctypes.c_int, u64p, ctypes.c_uint64,
                                     ctypes.c_uint64, ctypes.c_uint32, ctypes.c_int]
+    lib.emu_block_decision_check.argtypes = [ctypes.c_uint64, ctypes.c_int]
     lib.emu_xcd_block.argtypes = [ctypes.c_uint32, ctypes.c_uint32]
     lib.emu_xcd_block.restype = ctypes.c_uint32
     lib.emu_philox_fast.argtypes = [ctypes.c_uint32] * 6 + [ctypes.c_int,
@@ -147,3 +148,12 @@ def test_heatbath_kernel_logic(emu, orc, L, rows5, beta, J):
             emu.emu_half_sweep5(_p(words), L, c, _p(T), 2 * (ctr + s) + c, seed, stream, rows5)
     orc.sweeps(ref, beta, J, seed, stream, n, ctr, rule="heatbath")
     assert np.array_equal(words.reshape(2, W), pack(ref))
+
+
+@pytest.mark.parametrize("seed", [1, 2, 3])
+def test_lane_pair_block_decisions_equal_plane_by_plane(emu, seed):
+    """A lane pair evaluates two consecutive blocks at once: each reduced to
+    the spins it decides and flips on its own, then applied in order.  That
+    must leave exactly the state that applying the four planes in order
+    leaves, for any pending set, classes and thresholds."""
+    assert emu.emu_block_decision_check(seed, 20000) == 0
