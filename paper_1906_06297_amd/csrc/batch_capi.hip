@@ -209,7 +209,7 @@ int check_batch(const ising_batch *b)
 }
 
 // ---------------------------------------------------------------- cache file
-std::string cache_key() { return "gfx950/batch-sweep-v6"; }
+std::string cache_key() { return "gfx950/batch-sweep-v7"; }
 
 bool read_cache(const char *path, std::map<int64_t, Tile> &out)
 {

@@ -6,6 +6,7 @@
 #include "batch.hpp"
 #include "ising_rows.hpp"
 #include "pair_decision.hpp"
+#include "batch_aligned.hpp"
 
 namespace ising {
 
@@ -89,6 +90,10 @@ __global__ __launch_bounds__(kBatchThreads) void k_batch_sweep(
         // the refresh and its barrier drop out of every half-sweep.
         const BatchLattice first = lats[members[bd.first]];
         const bool copy_ext = (first.M & 63) == 0 && first.W >= 2;
+        // whole-word colour rows: the row-aligned neighbour vectors (their
+        // row arithmetic holds for W < 4096, which L <= 722 keeps)
+        const bool aligned = (first.H & 63) == 0 && first.W < 4096;
+        const uint32_t Wr = first.H >> 6, inv_wr = aligned ? aligned_inv(Wr) : 0;
         const uint32_t slot = threadIdx.x / bd.tpl, li = threadIdx.x % bd.tpl;
         const uint32_t group = li / bd.lpw, parity = li % bd.lpw, groups = bd.tpl / bd.lpw;
         const bool on = slot < bd.count;
@@ -120,10 +125,15 @@ __global__ __launch_bounds__(kBatchThreads) void k_batch_sweep(
                         const uint32_t k = group + j * groups;
                         if (k >= lt.W)
                             break;
-                        RowMasks rm = row_masks32(k, lt.H, lt.M, 0);
-                        if (c)
-                            rm.left_rows = ~rm.left_rows; // rows of the other parity
-                        const Neighbours nb = neighbours_ext_rm(src, lt.H, lt.M, k, rm);
+                        Neighbours nb;
+                        if (aligned) {
+                            nb = neighbours_aligned(src, lt.W, Wr, inv_wr, k, c);
+                        } else {
+                            RowMasks rm = row_masks32(k, lt.H, lt.M, 0);
+                            if (c)
+                                rm.left_rows = ~rm.left_rows; // rows of the other parity
+                            nb = neighbours_ext_rm(src, lt.H, lt.M, k, rm);
+                        }
                         const uint64_t tw = tgt[k];
                         const uint64_t valid = valid_mask(k, lt.M);
                         const uint64_t flips = (bd.lpw == 2)

@@ -10,12 +10,14 @@
 // choice of options longest first on the resident workgroups (the order in
 // which the persistent kernel takes them) and reports the makespan; the
 // choice is improved one size at a time while the makespan falls, and among
-// equal makespans while the sizes' bundle durations, longest first, fall
-// (every size as fast as the workgroups left over allow).  Plain C++ with no
+// equal makespans (to the nanosecond) while the sum of the squared workgroup
+// loads falls: less work in all and less of it stacked on few workgroups,
+// which is what lets a later move shorten the makespan.  Plain C++ with no
 // HIP calls, so it is tested on the host.
 #pragma once
 
 #include <algorithm>
+#include <cmath>
 #include <cstdint>
 #include <functional>
 #include <queue>
@@ -32,6 +34,7 @@ struct Option {
 struct Estimate {
     double makespan = 0.0;        // longest workgroup
     double busy = 0.0;            // sum over bundles of their durations
+    double sumsq = 0.0;           // sum over workgroups of their load squared
     std::vector<double> per_size; // bundle duration of each size, longest first
 };
 
@@ -68,15 +71,25 @@ inline Estimate estimate(const std::vector<std::vector<Option>> &opts,
         load.push(t);
         e.makespan = std::max(e.makespan, t);
     }
+    for (; !load.empty(); load.pop())
+        e.sumsq += load.top() * load.top();
     return e;
 }
 
-// Strict order: shorter makespan, then shorter bundle durations (longest
-// first, lexicographic), then less busy time.
+// Makespan to the nanosecond (times in ms), so that sums taken in another
+// order compare equal.
+inline long long makespan_ns(const Estimate &e) { return std::llround(e.makespan * 1e6); }
+
+// Strict order: shorter makespan (to the nanosecond), then a smaller sum of
+// squared loads, then shorter bundle durations (longest first,
+// lexicographic), then less busy time.
 inline bool better(const Estimate &a, const Estimate &b)
 {
-    if (a.makespan != b.makespan)
-        return a.makespan < b.makespan;
+    const long long ma = makespan_ns(a), mb = makespan_ns(b);
+    if (ma != mb)
+        return ma < mb;
+    if (a.sumsq != b.sumsq)
+        return a.sumsq < b.sumsq;
     if (a.per_size != b.per_size)
         return a.per_size < b.per_size;
     return a.busy < b.busy;
@@ -108,11 +121,14 @@ inline std::vector<size_t> improve(const std::vector<std::vector<Option>> &opts,
     return pick;
 }
 
-// The better of two local searches: one from the fastest option of each size
-// alone (`fastest`), one from the option with the fewest bundles (the most
-// lattices per workgroup, the highest throughput of a compute unit).
+// The best of several local searches: from the fastest option of each size
+// alone (`fastest`), from the option with the fewest bundles (the most
+// lattices per workgroup, the highest throughput of a compute unit), and from
+// `restarts` random choices drawn from a fixed splitmix64 stream (one search
+// takes milliseconds; single-size moves alone stop short of the best plans).
 inline std::vector<size_t> choose(const std::vector<std::vector<Option>> &opts,
-                                  const std::vector<size_t> &fastest, uint32_t slots)
+                                  const std::vector<size_t> &fastest, uint32_t slots,
+                                  int restarts = 16)
 {
     std::vector<size_t> fewest(opts.size(), 0);
     for (size_t i = 0; i < opts.size(); ++i)
@@ -121,9 +137,31 @@ inline std::vector<size_t> choose(const std::vector<std::vector<Option>> &opts,
             if (a.bundles < c.bundles || (a.bundles == c.bundles && a.ms < c.ms))
                 fewest[i] = j;
         }
-    std::vector<size_t> p1 = improve(opts, fastest, slots);
-    std::vector<size_t> p2 = improve(opts, fewest, slots);
-    return better(estimate(opts, p2, slots), estimate(opts, p1, slots)) ? p2 : p1;
+    std::vector<size_t> best = improve(opts, fastest, slots);
+    Estimate be = estimate(opts, best, slots);
+    auto consider = [&](std::vector<size_t> start) {
+        std::vector<size_t> p = improve(opts, std::move(start), slots);
+        const Estimate e = estimate(opts, p, slots);
+        if (better(e, be)) {
+            best = std::move(p);
+            be = e;
+        }
+    };
+    consider(fewest);
+    uint64_t z = 0x5EED5EED5EED5EEDull;
+    auto next = [&z]() {
+        uint64_t x = (z += 0x9E3779B97F4A7C15ull);
+        x = (x ^ (x >> 30)) * 0xBF58476D1CE4E5B9ull;
+        x = (x ^ (x >> 27)) * 0x94D049BB133111EBull;
+        return x ^ (x >> 31);
+    };
+    for (int r = 0; r < restarts; ++r) {
+        std::vector<size_t> start(opts.size());
+        for (size_t i = 0; i < opts.size(); ++i)
+            start[i] = (size_t)(next() % opts[i].size());
+        consider(std::move(start));
+    }
+    return best;
 }
 
 } // namespace plan

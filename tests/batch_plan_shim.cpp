@@ -21,15 +21,17 @@ std::vector<std::vector<Option>> unpack(int n, const int *counts, const uint32_t
 
 extern "C" {
 
-// Makespan and busy time of the choice pick (one option index per size).
+// Makespan, busy time and sum of squared workgroup loads of the choice pick
+// (one option index per size).
 void plan_estimate(int n, const int *counts, const uint32_t *bundles, const double *ms,
-                   const int *pick, uint32_t slots, double *makespan, double *busy)
+                   const int *pick, uint32_t slots, double *makespan, double *busy, double *sumsq)
 {
     const auto opts = unpack(n, counts, bundles, ms);
     const std::vector<size_t> p(pick, pick + n);
     const Estimate e = estimate(opts, p, slots);
     *makespan = e.makespan;
     *busy = e.busy;
+    *sumsq = e.sumsq;
 }
 
 // The improved choice from start, written to pick.

@@ -7,6 +7,7 @@
 #include "../paper_1906_06297_amd/csrc/ising_device.hpp"
 #include "../paper_1906_06297_amd/csrc/ising_rows.hpp"
 #include "../paper_1906_06297_amd/csrc/pair_decision.hpp"
+#include "../paper_1906_06297_amd/csrc/batch_aligned.hpp"
 
 using namespace ising;
 
@@ -111,6 +112,46 @@ int emu_block_decision_check(uint64_t seed, int n)
         for (int h = 0; h < 2; ++h)
             bad += (ref.tf[h] != got.tf[h]) || (ref.p[h] != got.p[h]) || (ref.a[h] != got.a[h]);
     }
+    return bad;
+}
+
+// The batch kernel's row-aligned neighbour vectors against the general
+// extraction from an extended colour array, for every word of both colours
+// of an L x L lattice (L % 128 == 0) filled from `seed`; returns mismatches.
+int emu_aligned_neighbours_check(int64_t L, uint64_t seed)
+{
+    const uint32_t H = (uint32_t)(L / 2), M = (uint32_t)(L * L / 2), W = M / 64, Wr = H / 64;
+    std::vector<uint64_t> E(W + 2);
+    uint64_t z = seed * 0x9E3779B97F4A7C15ull + 7;
+    for (uint32_t k = 0; k < W; ++k) { // splitmix64
+        uint64_t x = (z += 0x9E3779B97F4A7C15ull);
+        x = (x ^ (x >> 30)) * 0xBF58476D1CE4E5B9ull;
+        x = (x ^ (x >> 27)) * 0x94D049BB133111EBull;
+        E[k] = x ^ (x >> 31);
+    }
+    E[W] = E[0];
+    E[W + 1] = E[1 % W];
+    int bad = 0;
+    const uint32_t inv = aligned_inv(Wr);
+    for (int c = 0; c < 2; ++c)
+        for (uint32_t k = 0; k < W; ++k) {
+            RowMasks rm = row_masks32(k, H, M, 0);
+            if (c)
+                rm.left_rows = ~rm.left_rows;
+            const Neighbours a = neighbours_ext_rm(E.data(), H, M, k, rm);
+            const Neighbours b = neighbours_aligned(E.data(), W, Wr, inv, k, c);
+            bad += (a.ce != b.ce) || (a.up != b.up) || (a.dn != b.dn) || (a.sd != b.sd);
+        }
+    return bad;
+}
+
+// floor(k / Wr) by the batch kernel's multiply, over its whole range.
+int emu_aligned_row_check()
+{
+    int bad = 0;
+    for (uint32_t Wr = 1; Wr <= 5; ++Wr)
+        for (uint32_t k = 0; k < 4096; ++k)
+            bad += aligned_row(k, aligned_inv(Wr)) != k / Wr;
     return bad;
 }
 

@@ -1,7 +1,7 @@
 """The batch autotuner's joint choice of tiles (host logic, no GPU): bundles
 of every size scheduled longest first on the resident workgroups, and the
-choice improved one size at a time for the makespan, then for the sizes'
-bundle durations, longest first, then for busy time."""
+choice improved one size at a time for the makespan, then for the sum of
+the squared workgroup loads, from several starts."""
 import ctypes
 import heapq
 import itertools
@@ -35,13 +35,13 @@ def _arrays(opts):
     return counts, bundles, ms
 
 
-def estimate(lib, opts, pick, slots):
+def estimate(lib, opts, pick, slots, sumsq=False):
     counts, bundles, ms = _arrays(opts)
     p = (ctypes.c_int * len(opts))(*pick)
-    mk, busy = ctypes.c_double(), ctypes.c_double()
+    mk, busy, sq = ctypes.c_double(), ctypes.c_double(), ctypes.c_double()
     lib.plan_estimate(len(opts), counts, bundles, ms, p, ctypes.c_uint32(slots),
-                      ctypes.byref(mk), ctypes.byref(busy))
-    return mk.value, busy.value
+                      ctypes.byref(mk), ctypes.byref(busy), ctypes.byref(sq))
+    return (mk.value, busy.value, sq.value) if sumsq else (mk.value, busy.value)
 
 
 def choose(lib, opts, start, slots):
@@ -52,12 +52,14 @@ def choose(lib, opts, start, slots):
     return list(out)
 
 
-def lpt(durations, slots):
+def lpt(durations, slots, loads=False):
     """Longest first, each to the least loaded workgroup."""
     load = [0.0] * slots
     heapq.heapify(load)
     for d in sorted(durations, reverse=True):
         heapq.heappush(load, heapq.heappop(load) + d)
+    if loads:
+        return load
     return max(load) if durations else 0.0
 
 
@@ -79,12 +81,26 @@ def test_too_many_bundles_run_a_second_round(lib):
 
 def test_joint_choice_fits_one_round(lib):
     # halving either of the first two sizes' bundles fits one round (20.2 ms,
-    # set by the third size); the first leaves the second size faster
+    # set by the third size); halving both leaves the least work in all
     pick = choose(lib, OPTS, [0, 0, 0], 200)
-    assert pick == [1, 0, 0]
+    assert pick == [1, 1, 0]
     mk, busy = estimate(lib, OPTS, pick, 200)
     assert mk == pytest.approx(20.2)
-    assert busy == pytest.approx(48 * 19.1 + 114 * 13.2 + 2 * 20.2)
+    assert busy == pytest.approx(48 * 19.1 + 38 * 20.2 + 2 * 20.2)
+
+
+def test_stacked_short_bundles_beat_many_fast_ones(lib):
+    # 4 workgroups.  Size 0: one 10 ms bundle (fixed).  Size 1: 6 bundles of
+    # 3 ms (6 ms alone: two rounds), or 2 of 5 ms.  Six short bundles stack
+    # on three workgroups (6 ms each), two longer ones fit beside the 10 ms
+    # bundle: the makespan is 10 either way, and the squared loads prefer the
+    # second (less work)
+    opts = [[(1, 10.0)], [(6, 6.0), (2, 5.0)]]
+    pick = choose(lib, opts, [0, 0], 4)
+    assert pick == [0, 1]
+    mk, busy, sq = estimate(lib, opts, pick, 4, sumsq=True)
+    assert (mk, busy) == (pytest.approx(10.0), pytest.approx(20.0))
+    assert sq == pytest.approx(sum(x * x for x in lpt([10.0, 5.0, 5.0], 4, loads=True)))
 
 
 def test_enough_workgroups_keep_the_fastest_tiles(lib):
@@ -108,14 +124,15 @@ def test_estimate_and_choice_on_random_batches(lib, seed):
     for pick in itertools.product(*[range(len(o)) for o in opts]):
         d = [per_bundle(b, t, slots) for (b, t), i in
              ((o[i], i) for o, i in zip(opts, pick)) for _ in range(b)]
-        mk, busy = estimate(lib, opts, list(pick), slots)
+        mk, busy, sq = estimate(lib, opts, list(pick), slots, sumsq=True)
         assert mk == pytest.approx(lpt(d, slots))
         assert busy == pytest.approx(sum(d))
+        assert sq == pytest.approx(sum(x * x for x in lpt(d, slots, loads=True)))
         assert mk >= max(d) - 1e-12 and mk >= sum(d) / slots - 1e-12
     def key(pick):
-        mk, busy = estimate(lib, opts, pick, slots)
+        mk, busy, sq = estimate(lib, opts, pick, slots, sumsq=True)
         sizes = sorted((per_bundle(*o[i], slots) for o, i in zip(opts, pick)), reverse=True)
-        return (mk, sizes, busy)
+        return (round(mk * 1e6), sq, sizes, busy)
 
     start = [0] * len(opts)
     pick = choose(lib, opts, start, slots)

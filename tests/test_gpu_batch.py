@@ -94,7 +94,7 @@ def test_batch_member_equals_single_lattice(gpu, workload):
     b.close()
 
 
-@pytest.mark.parametrize("L", [16, 24, 48, 96, 192, 256])
+@pytest.mark.parametrize("L", [16, 24, 48, 96, 128, 192, 256, 384])
 def test_every_tile_gives_the_same_lattice(gpu, orc, L):
     n = 20
     rng = np.random.default_rng(L)

@@ -32,6 +32,7 @@ def emu(tmp_path_factory):
     lib.emu_half_sweep5.argtypes = [u64p, ctypes.c_int64, ctypes.c_int, u64p, ctypes.c_uint64,
                                     ctypes.c_uint64, ctypes.c_uint32, ctypes.c_int]
     lib.emu_block_decision_check.argtypes = [ctypes.c_uint64, ctypes.c_int]
+    lib.emu_aligned_neighbours_check.argtypes = [ctypes.c_int64, ctypes.c_uint64]
     lib.emu_xcd_block.argtypes = [ctypes.c_uint32, ctypes.c_uint32]
     lib.emu_xcd_block.restype = ctypes.c_uint32
     lib.emu_philox_fast.argtypes = [ctypes.c_uint32] * 6 + [ctypes.c_int,
@@ -157,3 +158,12 @@ def test_lane_pair_block_decisions_equal_plane_by_plane(emu, seed):
     must leave exactly the state that applying the four planes in order
     leaves, for any pending set, classes and thresholds."""
     assert emu.emu_block_decision_check(seed, 20000) == 0
+
+
+@pytest.mark.parametrize("L", [128, 256, 384, 512, 640])
+def test_batch_row_aligned_neighbours_equal_the_general_extraction(emu, L):
+    """For L % 128 == 0 the batch kernel reads whole words for the vertical
+    neighbours and one edge word for the side neighbour; that must equal the
+    general funnel-shift extraction for every word of both colours."""
+    assert emu.emu_aligned_neighbours_check(L, L + 1) == 0
+    assert emu.emu_aligned_row_check() == 0
