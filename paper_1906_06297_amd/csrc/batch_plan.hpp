@@ -148,6 +148,10 @@ inline std::vector<size_t> choose(const std::vector<std::vector<Option>> &opts,
         }
     };
     consider(fewest);
+    // each search costs sizes x options x bundles; batches of many sizes keep
+    // to the two deterministic starts
+    if (opts.size() > 32)
+        restarts = 0;
     uint64_t z = 0x5EED5EED5EED5EEDull;
     auto next = [&z]() {
         uint64_t x = (z += 0x9E3779B97F4A7C15ull);
