@@ -120,7 +120,7 @@ def test_every_tile_gives_the_same_lattice(gpu, orc, L):
 
 
 def test_mixed_sizes_and_couplings(gpu, orc):
-    Ls = [4, 6, 8, 10, 12, 14, 16, 24, 30, 40, 64, 100, 128, 200, 256, 300]
+    Ls = [4, 6, 8, 10, 12, 14, 16, 24, 30, 40, 64, 100, 128, 200, 256, 300, 512, 640]
     n = len(Ls)
     for J in (1.0, -0.7):
         betas = np.linspace(0.0, 0.9, n)
