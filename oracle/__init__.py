@@ -14,6 +14,10 @@ Contents
                          Kaufman's finite-lattice solution, Onsager, Eq. (7).
   - ``stats.py``         blocking standard errors and integrated
                          autocorrelation times.
+  - ``arnet.py``         the learned proposal: masked-convolution network
+                         forward and backward, absolute-value scales for
+                         rounding bounds, Adam, the sampling and
+                         Metropolis-Hastings uniforms and decisions.
 
 The readings of the paper that the oracle fixes are listed at the top of
 ``ising_oracle.c``.

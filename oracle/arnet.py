@@ -115,7 +115,7 @@ def forward(x: np.ndarray, theta: np.ndarray, C: int, emulate_bf16: bool = False
         W = r(p[f"W{l}"])
         pre = np.zeros_like(h)
         for t in range(5):
-            pre += np.einsum("bijc,cd->bijd", shift(h, *TAPS[t]), W[t])
+            pre += _apply_right(shift(h, *TAPS[t]), W[t])
         h = r(np.maximum(pre + p[f"b{l}"], 0.0))
         acts.append(h)
     W6 = r(p["W6"])
@@ -153,7 +153,13 @@ def log_q_exact(x, theta, C, emulate_bf16=True) -> np.ndarray:
 
 def nll_and_grad(x: np.ndarray, theta: np.ndarray, C: int, emulate_bf16: bool = False):
     """Mean negative log-likelihood of a batch and its gradient (hand-written
-    backward through the masked convolutions)."""
+    backward through the masked convolutions).
+
+    emulate_bf16 selects the forward pass whose gradient is taken (weights and
+    stored activations rounded to bfloat16, as ``forward``); the gradient is
+    that of the rounded network with the rounding treated as the identity
+    (straight-through).  The backward signal itself is never rounded: every
+    step of the backward pass is exact in double."""
     p = unflatten(theta, C)
     r = bf16 if emulate_bf16 else (lambda a: np.asarray(a, dtype=np.float64))
     x = np.asarray(x, dtype=np.float64)
@@ -162,7 +168,8 @@ def nll_and_grad(x: np.ndarray, theta: np.ndarray, C: int, emulate_bf16: bool = 
     s = x
     nll = -log_sigmoid(s * logit).sum() / B
     # d(-log sigmoid(s z))/dz = -s * sigmoid(-s z)
-    dlogit = -s / (1.0 + np.exp(s * logit)) / B
+    with np.errstate(over="ignore"):
+        dlogit = -s / (1.0 + np.exp(s * logit)) / B
     g = {k: np.zeros_like(np.asarray(v, dtype=np.float64)) for k, v in p.items()}
     g["b6"] = np.float64(dlogit.sum())
     W6 = r(p["W6"])
@@ -173,20 +180,107 @@ def nll_and_grad(x: np.ndarray, theta: np.ndarray, C: int, emulate_bf16: bool = 
         g["W6"][t] = np.einsum("bijc,bij->c", shift(h5, dy, dx), dlogit)
         dh += shift(dlogit[..., None] * W6[t][None, None, None, :], -dy, -dx)
     for l in range(5, 1, -1):
-        dpre = r(dh * (acts[l - 1] > 0))
+        dpre = dh * (acts[l - 1] > 0)
         g[f"b{l}"] = dpre.sum(axis=(0, 1, 2))
         hin = acts[l - 2]
         W = r(p[f"W{l}"])
         dh = np.zeros_like(hin)
         for t in range(5):
             dy, dx = TAPS[t]
-            g[f"W{l}"][t] = np.einsum("bijc,bijd->cd", shift(hin, dy, dx), dpre)
-            dh += shift(np.einsum("bijd,cd->bijc", dpre, W[t]), -dy, -dx)
-    dpre = r(dh * (acts[0] > 0))
+            g[f"W{l}"][t] = _contract_rows(shift(hin, dy, dx), dpre)
+            dh += shift(_apply_right(dpre, W[t].T), -dy, -dx)
+    dpre = dh * (acts[0] > 0)
     g["b1"] = dpre.sum(axis=(0, 1, 2))
     for t in range(4):
         g["W1"][t] = np.einsum("bij,bijc->c", shift(x, *TAPS[t]), dpre)
     return nll, flatten(g, C)
+
+
+def _apply_right(h: np.ndarray, W: np.ndarray) -> np.ndarray:
+    """h[..., c] @ W[c, d] over the trailing axis (one BLAS product)."""
+    return (h.reshape(-1, h.shape[-1]) @ W).reshape(h.shape[:-1] + (W.shape[1],))
+
+
+def _contract_rows(a: np.ndarray, d: np.ndarray) -> np.ndarray:
+    """sum over every leading axis of a[..., c] * d[..., e] -> [c, e]."""
+    return a.reshape(-1, a.shape[-1]).T @ d.reshape(-1, d.shape[-1])
+
+
+def forward_abs(x: np.ndarray, theta: np.ndarray, C: int) -> np.ndarray:
+    """Scale of every logit for rounding-error bounds: the forward pass with
+    every weight, bias and input replaced by its absolute value and no ReLU,
+    A_l = |b_l| + sum_t |W_l[t]|^T A_{l-1}(shifted), A_0 = |x|.  A_l bounds
+    |h_l| of the exact network and every sum of absolute products formed on
+    the way to the logit."""
+    p = unflatten(theta, C)
+    a = np.abs(np.asarray(x, dtype=np.float64))
+    h = np.zeros(a.shape + (C,))
+    for t in range(4):
+        h += shift(a, *TAPS[t])[..., None] * np.abs(p["W1"][t])[None, None, None, :]
+    h += np.abs(p["b1"])
+    for l in range(2, 6):
+        W = np.abs(p[f"W{l}"])
+        nxt = np.zeros_like(h)
+        for t in range(5):
+            nxt += _apply_right(shift(h, *TAPS[t]), W[t])
+        h = nxt + np.abs(p[f"b{l}"])
+    out = np.full(a.shape, abs(float(p["b6"])))
+    for t in range(5):
+        out += _apply_right(shift(h, *TAPS[t]), np.abs(p["W6"][t])[:, None])[..., 0]
+    return out
+
+
+def grad_abs(x: np.ndarray, theta: np.ndarray, C: int, emulate_bf16: bool = True) -> np.ndarray:
+    """Scale of every gradient element for rounding-error bounds: the backward
+    pass of ``nll_and_grad`` with every weight, activation and backward signal
+    replaced by its absolute value (the same ReLU masks), i.e. the sum of the
+    absolute values of the products that make up each gradient element."""
+    p = unflatten(theta, C)
+    r = bf16 if emulate_bf16 else (lambda a: np.asarray(a, dtype=np.float64))
+    x = np.asarray(x, dtype=np.float64)
+    B = x.shape[0]
+    logit, acts = forward(x, theta, C, emulate_bf16)
+    with np.errstate(over="ignore"):
+        dlogit = np.abs(1.0 / (1.0 + np.exp(x * logit)) / B)
+    g = {k: np.zeros_like(np.asarray(v, dtype=np.float64)) for k, v in p.items()}
+    g["b6"] = np.float64(dlogit.sum())
+    W6 = np.abs(r(p["W6"]))
+    h5 = acts[4]
+    dh = np.zeros_like(h5)
+    for t in range(5):
+        dy, dx = TAPS[t]
+        g["W6"][t] = np.einsum("bijc,bij->c", shift(h5, dy, dx), dlogit)
+        dh += shift(dlogit[..., None] * W6[t][None, None, None, :], -dy, -dx)
+    for l in range(5, 1, -1):
+        dpre = dh * (acts[l - 1] > 0)
+        g[f"b{l}"] = dpre.sum(axis=(0, 1, 2))
+        hin = acts[l - 2]
+        W = np.abs(r(p[f"W{l}"]))
+        dh = np.zeros_like(hin)
+        for t in range(5):
+            dy, dx = TAPS[t]
+            g[f"W{l}"][t] = _contract_rows(shift(hin, dy, dx), dpre)
+            dh += shift(_apply_right(dpre, W[t].T), -dy, -dx)
+    dpre = dh * (acts[0] > 0)
+    g["b1"] = dpre.sum(axis=(0, 1, 2))
+    for t in range(4):
+        g["W1"][t] = np.einsum("bij,bijc->c", np.abs(shift(x, *TAPS[t])), dpre)
+    return flatten(g, C)
+
+
+def adam_step(theta, grad, m, v, step: int, lr: float, beta1: float = 0.9, beta2: float = 0.999,
+              eps: float = 1e-8):
+    """One Adam update (Kingma and Ba, ICLR 2015, Algorithm 1) in double:
+    m <- b1 m + (1-b1) g, v <- b2 v + (1-b2) g^2, bias corrections
+    1 - b1^step and 1 - b2^step, theta <- theta - lr m^ / (sqrt(v^) + eps).
+    Returns the new (theta, m, v)."""
+    g = np.asarray(grad, dtype=np.float64)
+    m = beta1 * np.asarray(m, dtype=np.float64) + (1.0 - beta1) * g
+    v = beta2 * np.asarray(v, dtype=np.float64) + (1.0 - beta2) * g * g
+    m_hat = m / (1.0 - beta1 ** step)
+    v_hat = v / (1.0 - beta2 ** step)
+    theta = np.asarray(theta, dtype=np.float64) - lr * m_hat / (np.sqrt(v_hat) + eps)
+    return theta, m, v
 
 
 def mh_accept_prob(beta, J, bond_cur, bond_prop, logq_cur, logq_prop):
@@ -194,6 +288,63 @@ def mh_accept_prob(beta, J, bond_cur, bond_prop, logq_cur, logq_prop):
     Hastings' correction): min(1, pi(x') q(x) / (pi(x) q(x'))), pi ~ exp(beta J bond)."""
     log_a = beta * J * (np.asarray(bond_prop) - np.asarray(bond_cur)) + np.asarray(logq_cur) - np.asarray(logq_prop)
     return np.minimum(1.0, np.exp(np.minimum(log_a, 0.0)))
+
+
+# Counter-based uniforms of the learned part (the same generator as the sweep,
+# Philox4x32-10 of SC'11, called through this package's own C copy):
+#   domain 2 (Metropolis-Hastings accept): counter (stream<<8 | 2<<4,
+#     round mod 2^32, round >> 32, 0), word 0;
+#   domain 3 (ancestral sampling, site p): counter (stream<<8 | 3<<4,
+#     round mod 2^32, round >> 32, p >> 2), word p & 3;
+# each word's top 24 bits give u = k / 2^24.
+DOMAIN_MH = 2
+DOMAIN_SAMPLE = 3
+
+
+def _uniform24(seed: int, stream: int, domain: int, rnd: int, c3: int, word: int) -> float:
+    from . import philox4x32_10
+
+    ctr = ((stream << 8) | (domain << 4), rnd & 0xFFFFFFFF, (rnd >> 32) & 0xFFFFFFFF, c3)
+    out = philox4x32_10(ctr, (seed & 0xFFFFFFFF, (seed >> 32) & 0xFFFFFFFF))
+    return (out[word] >> 8) / float(1 << 24)
+
+
+def sample_uniforms(seed: int, stream: int, rnd: int, N: int) -> np.ndarray:
+    """u_p, p = 0..N-1, of one configuration's ancestral draw (domain 3)."""
+    from . import philox4x32_10
+
+    key = (seed & 0xFFFFFFFF, (seed >> 32) & 0xFFFFFFFF)
+    w0 = (stream << 8) | (DOMAIN_SAMPLE << 4)
+    u = np.empty(N)
+    for blk in range((N + 3) // 4):
+        out = philox4x32_10((w0, rnd & 0xFFFFFFFF, (rnd >> 32) & 0xFFFFFFFF, blk), key)
+        for w in range(4):
+            if 4 * blk + w < N:
+                u[4 * blk + w] = (out[w] >> 8) / float(1 << 24)
+    return u
+
+
+def mh_decisions(bond_cur, bond_prop, logq_cur, logq_prop, betaJ, seed: int, stream_base: int,
+                 rnd: int):
+    """Independence Metropolis-Hastings decisions (Hastings' ratio for an
+    independence proposal, pi ~ exp(beta J bond)) as the reading fixes them:
+    in float32, log A = ((betaJ * float(bond' - bond)) + log q(x)) - log q(x'),
+    each operation rounded; chain c accepts iff log A >= 0 or u_c < exp(log A),
+    u_c the domain-2 uniform of stream stream_base + c.
+    Returns (accept, ambiguous): `ambiguous` marks chains whose u_c lies within
+    4 float32 ulps of exp(log A), where a faithfully rounded exp may decide
+    either way."""
+    f32 = np.float32
+    dB = (np.asarray(bond_prop, dtype=np.int64) - np.asarray(bond_cur, dtype=np.int64)).astype(f32)
+    log_a = ((np.asarray(betaJ, dtype=f32) * dB) + np.asarray(logq_cur, dtype=f32)) \
+        - np.asarray(logq_prop, dtype=f32)
+    n = log_a.size
+    u = np.array([_uniform24(seed, stream_base + c, DOMAIN_MH, rnd, 0, 0) for c in range(n)])
+    with np.errstate(over="ignore", invalid="ignore"):
+        e = np.exp(np.minimum(log_a.astype(np.float64), 0.0))
+    accept = (log_a >= 0) | (u < np.exp(log_a.astype(f32)).astype(np.float64))
+    ambiguous = (log_a < 0) & (np.abs(u - e) <= 4 * 2.0 ** -23 * e)
+    return accept, ambiguous
 
 
 def sample(theta, C: int, L: int, B: int, rng, emulate_bf16: bool = True):

@@ -1,7 +1,10 @@
 """Pins of the autoregressive-proposal oracle: hand-written gradient against
-double-precision finite differences and against PyTorch autograd, the
-autoregressive property, normalisation by enumeration, and exactness of the
-independence Metropolis-Hastings chain on 4x4 against enumeration."""
+double-precision finite differences and against PyTorch autograd (also of the
+bf16-rounded network, straight-through), the autoregressive property,
+normalisation by enumeration, exactness of the independence
+Metropolis-Hastings chain on 4x4 against enumeration, the absolute-value
+scales used by the GPU tolerances, Adam's closed forms, and the addressing
+and frequencies of the sampling and acceptance uniforms."""
 import numpy as np
 import pytest
 
@@ -34,13 +37,28 @@ def test_gradient_matches_finite_differences():
         assert abs(num - g[k]) <= 1e-6 + 1e-5 * abs(num), (k, num, g[k])
 
 
-def test_gradient_matches_torch_autograd():
+def _torch_bf16(t):
+    """Straight-through bfloat16 rounding: the forward value is rounded (the
+    oracle's own bf16() of the detached tensor), the derivative is 1."""
+    import torch
+
+    r = torch.tensor(arnet.bf16(t.detach().numpy()))
+    return t + (r - t).detach()
+
+
+@pytest.mark.parametrize("emulate", [False, True])
+def test_gradient_matches_torch_autograd(emulate):
+    """The hand-written backward against PyTorch CPU autograd: of the plain
+    network, and (emulate) of the network with weights and stored activations
+    rounded to bfloat16, the rounding taken as the identity in the backward
+    pass, the backward signal unrounded."""
     torch = pytest.importorskip("torch")
     C, L = 4, 6
     th = arnet.init_params(C, 3) + np.random.default_rng(4).normal(0, 0.1, arnet.num_params(C))
     x = rand_spins(5, L, 5)
-    nll, g = arnet.nll_and_grad(x, th, C)
+    nll, g = arnet.nll_and_grad(x, th, C, emulate_bf16=emulate)
     p = {k: torch.tensor(np.asarray(v, dtype=np.float64), requires_grad=True) for k, v in arnet.unflatten(th, C).items()}
+    rw = _torch_bf16 if emulate else (lambda t: t)
     xt = torch.tensor(x)[:, None]  # (B, 1, L, L)
 
     def masked_conv(h, taps_w, bias):
@@ -52,14 +70,14 @@ def test_gradient_matches_torch_autograd():
             out = out + torch.einsum("bcij,cd->bdij", hs, w)
         return out + bias.reshape(1, -1, 1, 1)
 
-    h = torch.relu(masked_conv(xt, [(arnet.TAPS[t], p["W1"][t][None, :]) for t in range(4)], p["b1"]))
+    h = rw(torch.relu(masked_conv(xt, [(arnet.TAPS[t], rw(p["W1"][t])[None, :]) for t in range(4)], p["b1"])))
     for l in range(2, 6):
-        h = torch.relu(masked_conv(h, [(arnet.TAPS[t], p[f"W{l}"][t]) for t in range(5)], p[f"b{l}"]))
-    logit = masked_conv(h, [(arnet.TAPS[t], p["W6"][t][:, None]) for t in range(5)], p["b6"].reshape(1))[:, 0]
+        h = rw(torch.relu(masked_conv(h, [(arnet.TAPS[t], rw(p[f"W{l}"][t])) for t in range(5)], p[f"b{l}"])))
+    logit = masked_conv(h, [(arnet.TAPS[t], rw(p["W6"][t])[:, None]) for t in range(5)], p["b6"].reshape(1))[:, 0]
     loss = -torch.nn.functional.logsigmoid(torch.tensor(x) * logit).sum() / x.shape[0]
     loss.backward()
     gt = arnet.flatten({k: v.grad.numpy() for k, v in p.items()}, C)
-    assert abs(float(loss) - nll) < 1e-10
+    assert abs(float(loss.detach()) - nll) < 1e-10
     assert np.allclose(gt, g, rtol=1e-9, atol=1e-12)
 
 
@@ -131,3 +149,80 @@ def test_independence_chain_is_exact_on_4x4():
     for s, target in ((E, ex["E_per_site"]), (M2, ex["m2"])):
         se = stats.blocking_se(s)
         assert abs(s.mean() - target) < 4.5 * se, (s.mean(), target, se)
+
+
+def test_abs_scales_bound_and_are_attained():
+    """forward_abs bounds |logit| and grad_abs bounds |gradient| element by
+    element; with non-negative weights and biases, all spins +1, every product
+    has one sign and both are attained exactly."""
+    C, L = 3, 5
+    th = arnet.init_params(C, 13, scale=1.4) + np.random.default_rng(14).normal(0, 0.1, arnet.num_params(C))
+    x = rand_spins(3, L, 15)
+    z, _ = arnet.forward(x, th, C, emulate_bf16=True)
+    assert np.all(np.abs(z) <= arnet.forward_abs(x, arnet.bf16(th), C) * (1 + 1e-12))
+    _, g = arnet.nll_and_grad(x, th, C, emulate_bf16=True)
+    assert np.all(np.abs(g) <= arnet.grad_abs(x, th, C) * (1 + 1e-12) + 1e-300)
+    pos = np.abs(th)
+    ones = np.ones((2, L, L))
+    z, _ = arnet.forward(ones, pos, C)
+    assert np.allclose(arnet.forward_abs(ones, pos, C), np.abs(z), rtol=1e-13)
+    _, g = arnet.nll_and_grad(ones, pos, C)
+    assert np.allclose(arnet.grad_abs(ones, pos, C, emulate_bf16=False), np.abs(g), rtol=1e-12,
+                       atol=1e-300)
+
+
+def test_adam_closed_forms():
+    """First step: m^ = g, v^ = g^2, so theta moves by lr g / (|g| + eps); a
+    constant gradient keeps m^ = g and v^ = g^2 at every step (the bias
+    corrections undo the zero start)."""
+    rng = np.random.default_rng(16)
+    th0 = rng.normal(size=50)
+    g = rng.normal(size=50) * 10.0 ** rng.uniform(-3, 1, 50)
+    lr, eps = 1e-3, 1e-8
+    th, m, v = arnet.adam_step(th0, g, np.zeros(50), np.zeros(50), 1, lr, eps=eps)
+    step = lr * g / (np.abs(g) + eps)
+    assert np.allclose(th0 - th, step, rtol=1e-12, atol=0)
+    for k in range(2, 12):
+        prev = th
+        th, m, v = arnet.adam_step(th, g, m, v, k, lr, eps=eps)
+        assert np.allclose(prev - th, step, rtol=1e-9, atol=0)
+    # a zero gradient never moves a parameter
+    th2, _, _ = arnet.adam_step(th0, np.zeros(50), np.zeros(50), np.zeros(50), 1, lr)
+    assert np.array_equal(th2, th0)
+
+
+def test_sampling_uniforms_address_the_generator():
+    """u_p of site p is word p & 3 of the block at counter word 3 = p >> 2,
+    scaled 24 bits; distinct streams and rounds give distinct draws."""
+    import oracle
+
+    seed, stream, rnd, N = 0x123456789, 77, (5 << 32) | 9, 10
+    u = arnet.sample_uniforms(seed, stream, rnd, N)
+    for p in range(N):
+        blk = oracle.philox4x32_10(((stream << 8) | (3 << 4), 9, 5, p >> 2),
+                                   (seed & 0xFFFFFFFF, seed >> 32))
+        assert u[p] == (blk[p & 3] >> 8) / 2.0 ** 24
+    assert not np.array_equal(u, arnet.sample_uniforms(seed, stream + 1, rnd, N))
+    assert not np.array_equal(u, arnet.sample_uniforms(seed, stream, rnd + 1, N))
+    big = arnet.sample_uniforms(3, 0, 0, 40000)
+    assert np.all((big >= 0) & (big < 1))
+    assert abs(big.mean() - 0.5) < 4 * np.sqrt(1 / 12 / big.size)
+
+
+def test_mh_decisions_rule_and_frequency():
+    """log A >= 0 always accepts; at a fixed log A = ln a the accepted fraction
+    over independent streams is a (binomial error); the float32 ratio is
+    ((beta J dB) + log q) - log q'."""
+    n = 20000
+    a = 0.3
+    la = np.float32(np.log(a))
+    acc, amb = arnet.mh_decisions(np.zeros(n), np.zeros(n), np.full(n, la), np.zeros(n),
+                                  np.zeros(n), seed=5, stream_base=0, rnd=3)
+    assert abs(acc.mean() - a) < 4 * np.sqrt(a * (1 - a) / n)
+    assert amb.sum() <= 4
+    acc, amb = arnet.mh_decisions(np.zeros(8), np.full(8, 4), np.full(8, -10.0), np.full(8, -9.0),
+                                  np.full(8, 0.25), seed=5, stream_base=0, rnd=3)
+    assert acc.all() and not amb.any()  # 0.25 * 4 - 10 + 9 = 0 >= 0
+    acc, _ = arnet.mh_decisions(np.zeros(8), np.full(8, -400), np.zeros(8), np.zeros(8),
+                                np.full(8, 0.25), seed=5, stream_base=0, rnd=3)
+    assert not acc.any()  # A = e^-100
