@@ -300,8 +300,10 @@ int ising_batch_set_spins_dev(ising_batch *b, const int8_t *d_spins, void *hip_s
  * order W1[4][C], b1[C], (W_l[5][C][C], b_l[C]) for l = 2..5, W6[5][C], b6,
  * W_l[t][ci][co] taking input channel ci at tap t to output co.  Weights are
  * used in bfloat16, activations stored in bfloat16, sums in float32 (MFMA
- * for the C -> C layers).  Spins are device int8 arrays, one L x L raster per
- * configuration.  A sampled spin is +1 iff a 24-bit uniform (Philox domain 3)
+ * for layers 2..6).  The backward signal is float32 (in the MFMA products as
+ * two bfloat16 halves) and gradients are summed in a fixed order, so they do
+ * not vary from run to run.  Spins are device int8 arrays, one L x L raster
+ * per configuration.  A sampled spin is +1 iff a 24-bit uniform (Philox domain 3)
  * is below sigmoid(logit), so its realised probability is P~ = ceil(P 2^24) /
  * 2^24; log-probabilities returned are the exact log prod_p (P~ or 1 - P~),
  * bit-identical between the sampler and the evaluator.
@@ -312,8 +314,8 @@ typedef struct ising_arnet ising_arnet;
 int64_t ising_arnet_num_params(int32_t channels);
 
 /* Network for L x L configurations (2 <= L <= 1024), C = 32 or 64, and a
- * workspace for batches of up to max_batch configurations; parameters start
- * at zero.  Synchronous. */
+ * workspace for batches of up to max_batch configurations (max_batch * L^2 *
+ * C < 2^31); parameters start at zero.  Synchronous. */
 int ising_arnet_create(ising_arnet **out, int32_t L, int32_t channels, int32_t max_batch);
 int ising_arnet_destroy(ising_arnet *net);
 
@@ -331,13 +333,34 @@ int ising_arnet_log_prob(ising_arnet *net, const int8_t *d_spins, int32_t B, flo
 int ising_arnet_gradient(ising_arnet *net, const int8_t *d_spins, int32_t B, float *d_grad,
                          float *d_loss, void *hip_stream);
 
-/* One Adam step (beta1 0.9, beta2 0.999, eps 1e-8) on that loss.  Asynchronous. */
+/* The same backward pass at given forward values instead of the network's
+ * own forward pass: d_acts holds the post-ReLU activations of layers 1..5 as
+ * bfloat16 bit patterns, [5][B][L*L][C], d_logits the logits [B][L*L]
+ * (float32); ReLU masks are d_acts > 0.  The backward pass alone is then a
+ * function of its inputs (the forward pass's bf16 rounding decisions, which
+ * float32 sums may take differently from other evaluations, are fixed), for
+ * checking it element by element.  Asynchronous. */
+int ising_arnet_gradient_at(ising_arnet *net, const int8_t *d_spins, int32_t B,
+                            const uint16_t *d_acts, const float *d_logits, float *d_grad,
+                            float *d_loss, void *hip_stream);
+
+/* One Adam step (Kingma and Ba) on that loss: beta1, beta2 and eps are the
+ * float32 values nearest 0.9, 0.999 and 1e-8, the bias corrections 1 -
+ * beta^t of the network's step count t are formed in double and rounded, the
+ * update itself is float32.  Asynchronous. */
 int ising_arnet_train_step(ising_arnet *net, const int8_t *d_spins, int32_t B, float lr,
                            float *d_loss, void *hip_stream);
 
-/* Draws B configurations site by site; configuration b uses Philox stream
- * id stream_base + b (< 2^24) and counter word `round`.  Writes the spins and
- * their log q~.  Asynchronous. */
+/* The same Adam step with a caller's gradient d_grad (num_params floats,
+ * device).  Asynchronous. */
+int ising_arnet_adam(ising_arnet *net, const float *d_grad, float lr, void *hip_stream);
+
+/* Draws B configurations: sites along anti-diagonals j + 2i = t (each needs
+ * only sites of diagonal t - 1 and earlier), each configuration held in LDS
+ * by one workgroup; configuration b uses Philox stream id stream_base + b
+ * (< 2^24) and counter word `round`.  Writes the spins and their log q~.
+ * Needs L <= 128 and the configuration's activation ring within the
+ * device's LDS per workgroup (ISING_E_SIZE otherwise).  Asynchronous. */
 int ising_arnet_sample(ising_arnet *net, int32_t B, uint64_t seed, uint32_t stream_base,
                        uint64_t round, int8_t *d_spins, float *d_logq, void *hip_stream);
 
@@ -347,7 +370,8 @@ int ising_spins_observables(const int8_t *d_spins, int32_t B, int64_t L, int64_t
                             int64_t *d_mag, void *hip_stream);
 
 /* Independence Metropolis-Hastings step for n chains of L x L spins, in
- * float32: log A = betaJ[c] (bond'[c] - bond[c]) + logq[c] - logq'[c];
+ * float32, each operation rounded on its own:
+ * log A = ((betaJ[c] (bond'[c] - bond[c])) + logq[c]) - logq'[c];
  * accepted iff log A >= 0 or u < exp(log A), u a 24-bit uniform of Philox
  * domain 2 (stream stream_base + c, counter word `round`).  Accepted chains
  * take the proposal's spins, log q and bond sum in place; d_accepted[c] is

@@ -160,11 +160,21 @@ def nll_and_grad(x: np.ndarray, theta: np.ndarray, C: int, emulate_bf16: bool = 
     that of the rounded network with the rounding treated as the identity
     (straight-through).  The backward signal itself is never rounded: every
     step of the backward pass is exact in double."""
-    p = unflatten(theta, C)
-    r = bf16 if emulate_bf16 else (lambda a: np.asarray(a, dtype=np.float64))
-    x = np.asarray(x, dtype=np.float64)
-    B = x.shape[0]
     logit, acts = forward(x, theta, C, emulate_bf16)
+    return backward_from(x, logit, acts, theta, C, emulate_bf16)
+
+
+def backward_from(x, logit, acts, theta, C: int, bf16_weights: bool = True):
+    """The backward pass of the mean NLL from given logits [B, L, L] and
+    post-ReLU activations of layers 1..5 ([B, L, L, C] each): ReLU masks are
+    acts > 0, weight gradients contract the given activations.  Returns
+    (nll, gradient); with bf16_weights the weights are taken rounded."""
+    p = unflatten(theta, C)
+    r = bf16 if bf16_weights else (lambda a: np.asarray(a, dtype=np.float64))
+    x = np.asarray(x, dtype=np.float64)
+    logit = np.asarray(logit, dtype=np.float64)
+    acts = [np.asarray(a, dtype=np.float64) for a in acts]
+    B = x.shape[0]
     s = x
     nll = -log_sigmoid(s * logit).sum() / B
     # d(-log sigmoid(s z))/dz = -s * sigmoid(-s z)
@@ -235,11 +245,18 @@ def grad_abs(x: np.ndarray, theta: np.ndarray, C: int, emulate_bf16: bool = True
     pass of ``nll_and_grad`` with every weight, activation and backward signal
     replaced by its absolute value (the same ReLU masks), i.e. the sum of the
     absolute values of the products that make up each gradient element."""
-    p = unflatten(theta, C)
-    r = bf16 if emulate_bf16 else (lambda a: np.asarray(a, dtype=np.float64))
-    x = np.asarray(x, dtype=np.float64)
-    B = x.shape[0]
     logit, acts = forward(x, theta, C, emulate_bf16)
+    return grad_abs_from(x, logit, acts, theta, C, emulate_bf16)
+
+
+def grad_abs_from(x, logit, acts, theta, C: int, bf16_weights: bool = True) -> np.ndarray:
+    """``grad_abs`` of ``backward_from``: from given logits and activations."""
+    p = unflatten(theta, C)
+    r = bf16 if bf16_weights else (lambda a: np.asarray(a, dtype=np.float64))
+    x = np.asarray(x, dtype=np.float64)
+    logit = np.asarray(logit, dtype=np.float64)
+    acts = [np.asarray(a, dtype=np.float64) for a in acts]
+    B = x.shape[0]
     with np.errstate(over="ignore"):
         dlogit = np.abs(1.0 / (1.0 + np.exp(x * logit)) / B)
     g = {k: np.zeros_like(np.asarray(v, dtype=np.float64)) for k, v in p.items()}

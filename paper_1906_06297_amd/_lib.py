@@ -92,6 +92,8 @@ SIGNATURES = {
     "ising_arnet_log_prob": (ctypes.c_int, [_vp, _vp, ctypes.c_int32, _vp, _vp, _vp]),
     "ising_arnet_gradient": (ctypes.c_int, [_vp, _vp, ctypes.c_int32, _vp, _vp, _vp]),
     "ising_arnet_train_step": (ctypes.c_int, [_vp, _vp, ctypes.c_int32, ctypes.c_float, _vp, _vp]),
+    "ising_arnet_adam": (ctypes.c_int, [_vp, _vp, ctypes.c_float, _vp]),
+    "ising_arnet_gradient_at": (ctypes.c_int, [_vp, _vp, ctypes.c_int32, _vp, _vp, _vp, _vp, _vp]),
     "ising_arnet_sample": (ctypes.c_int, [_vp, ctypes.c_int32, _u64, _u32, _u64, _vp, _vp, _vp]),
     "ising_spins_observables": (ctypes.c_int, [_vp, ctypes.c_int32, _i64, _vp, _vp, _vp]),
     "ising_mh_independence": (ctypes.c_int, [ctypes.c_int32, _i64, _vp, _vp, _vp, _vp, _vp, _vp,

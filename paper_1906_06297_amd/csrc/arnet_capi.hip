@@ -17,7 +17,8 @@ struct ising_arnet {
     NetDev net{};
     int max_batch = 0;
     bf16 *h[6] = {};
-    bf16 *dpre_a = nullptr, *dpre_b = nullptr;
+    float *dpre_a = nullptr, *dpre_b = nullptr; // float32 backward signal
+    float *partial = nullptr;                   // kGradBlocks x (parameters + 1)
     float *logits = nullptr, *dlogit = nullptr, *grad = nullptr, *m = nullptr, *v = nullptr;
     int64_t step = 0;
 };
@@ -26,8 +27,8 @@ namespace {
 
 void release(ising_arnet *a)
 {
-    void *ptrs[] = {a->net.params, a->net.w1, a->net.w6, a->dpre_a, a->dpre_b, a->logits,
-                    a->dlogit, a->grad, a->m, a->v};
+    void *ptrs[] = {a->net.params, a->net.w1, a->net.w6, a->net.w6p, a->dpre_a, a->dpre_b,
+                    a->partial, a->logits, a->dlogit, a->grad, a->m, a->v};
     for (void *p : ptrs)
         if (p)
             (void)hipFree(p);
@@ -50,6 +51,20 @@ int check_batch_size(const ising_arnet *a, int32_t B)
     return ISING_OK;
 }
 
+// One Adam step on the master parameters with gradient g, then the packed
+// weight copies.
+int adam_and_pack(ising_arnet *a, const float *g, float lr, hipStream_t s)
+{
+    a->step += 1;
+    hipError_t e = launch_adam(a->net.params, g, a->m, a->v, param_layout(a->net.C).total, lr,
+                               0.9f, 0.999f, 1e-8f, a->step, s);
+    if (e == hipSuccess)
+        e = launch_pack(a->net, s);
+    if (e != hipSuccess)
+        return host::hip_fail(e, "Adam step");
+    return host::ok();
+}
+
 } // namespace
 
 extern "C" {
@@ -70,6 +85,8 @@ int ising_arnet_create(ising_arnet **out, int32_t L, int32_t channels, int32_t m
         return host::fail(ISING_E_BADARG, "channels must be 32 or 64");
     if (L < 2 || L > 1024 || max_batch < 1)
         return host::fail(ISING_E_BADARG, "need 2 <= L <= 1024 and max_batch >= 1");
+    if ((int64_t)max_batch * L * L * channels >= (int64_t)1 << 31)
+        return host::fail(ISING_E_SIZE, "max_batch * L^2 * channels must stay below 2^31");
     ising_arnet *a = new ising_arnet();
     a->net.L = L;
     a->net.N = L * L;
@@ -78,6 +95,7 @@ int ising_arnet_create(ising_arnet **out, int32_t L, int32_t channels, int32_t m
     const int C = channels;
     const int64_t P = param_layout(C).total;
     const size_t act = (size_t)max_batch * a->net.N * C * sizeof(bf16);
+    const size_t sig = (size_t)max_batch * a->net.N * C * sizeof(float);
     const size_t rowsf = (size_t)max_batch * a->net.N * sizeof(float);
     hipError_t e = hipMalloc(&a->net.params, P * 4);
     if (e == hipSuccess)
@@ -86,6 +104,8 @@ int ising_arnet_create(ising_arnet **out, int32_t L, int32_t channels, int32_t m
         e = hipMalloc(&a->net.w1, 4 * C * 4);
     if (e == hipSuccess)
         e = hipMalloc(&a->net.w6, 5 * C * 4);
+    if (e == hipSuccess)
+        e = hipMalloc(&a->net.w6p, 16 * 5 * C * sizeof(bf16));
     for (int l = 2; l <= 5 && e == hipSuccess; ++l) {
         e = hipMalloc(&a->net.wf[l], 5 * C * C * sizeof(bf16));
         if (e == hipSuccess)
@@ -94,9 +114,11 @@ int ising_arnet_create(ising_arnet **out, int32_t L, int32_t channels, int32_t m
     for (int l = 1; l <= 5 && e == hipSuccess; ++l)
         e = hipMalloc(&a->h[l], act);
     if (e == hipSuccess)
-        e = hipMalloc(&a->dpre_a, act);
+        e = hipMalloc(&a->dpre_a, sig);
     if (e == hipSuccess)
-        e = hipMalloc(&a->dpre_b, act);
+        e = hipMalloc(&a->dpre_b, sig);
+    if (e == hipSuccess)
+        e = hipMalloc(&a->partial, (size_t)kGradBlocks * (P + 1) * sizeof(float));
     if (e == hipSuccess)
         e = hipMalloc(&a->logits, rowsf);
     if (e == hipSuccess)
@@ -194,12 +216,42 @@ int ising_arnet_gradient(ising_arnet *a, const int8_t *d_spins, int32_t B, float
     hipError_t e = launch_forward(a->net, d_spins, B, a->h, a->logits, nullptr, s);
     if (e == hipSuccess)
         e = launch_backward(a->net, d_spins, B, a->h, a->logits, a->dlogit, a->dpre_a, a->dpre_b,
-                            a->grad, d_loss, s);
+                            a->partial, a->grad, d_loss, s);
     if (e == hipSuccess && d_grad)
         e = hipMemcpyAsync(d_grad, a->grad, param_layout(a->net.C).total * 4,
                            hipMemcpyDeviceToDevice, s);
     if (e != hipSuccess)
         return host::hip_fail(e, "gradient");
+    return host::ok();
+}
+
+int ising_arnet_gradient_at(ising_arnet *a, const int8_t *d_spins, int32_t B,
+                            const uint16_t *d_acts, const float *d_logits, float *d_grad,
+                            float *d_loss, void *hip_stream)
+{
+    if (int e = check_net(a))
+        return e;
+    if (int e = check_batch_size(a, B))
+        return e;
+    if (!d_spins || !d_acts || !d_logits || !d_loss)
+        return host::fail(ISING_E_BADARG, "null pointer");
+    hipStream_t s = (hipStream_t)hip_stream;
+    const size_t per = (size_t)B * a->net.N * a->net.C;
+    hipError_t e = hipSuccess;
+    for (int l = 1; l <= 5 && e == hipSuccess; ++l)
+        e = hipMemcpyAsync(a->h[l], d_acts + (size_t)(l - 1) * per, per * sizeof(bf16),
+                           hipMemcpyDeviceToDevice, s);
+    if (e == hipSuccess)
+        e = hipMemcpyAsync(a->logits, d_logits, (size_t)B * a->net.N * sizeof(float),
+                           hipMemcpyDeviceToDevice, s);
+    if (e == hipSuccess)
+        e = launch_backward(a->net, d_spins, B, a->h, a->logits, a->dlogit, a->dpre_a, a->dpre_b,
+                            a->partial, a->grad, d_loss, s);
+    if (e == hipSuccess && d_grad)
+        e = hipMemcpyAsync(d_grad, a->grad, param_layout(a->net.C).total * 4,
+                           hipMemcpyDeviceToDevice, s);
+    if (e != hipSuccess)
+        return host::hip_fail(e, "gradient at given activations");
     return host::ok();
 }
 
@@ -210,15 +262,18 @@ int ising_arnet_train_step(ising_arnet *a, const int8_t *d_spins, int32_t B, flo
         return host::fail(ISING_E_BADARG, "learning rate must be finite and > 0");
     if (int e = ising_arnet_gradient(a, d_spins, B, nullptr, d_loss, hip_stream))
         return e;
-    hipStream_t s = (hipStream_t)hip_stream;
-    a->step += 1;
-    hipError_t e = launch_adam(a->net.params, a->grad, a->m, a->v, param_layout(a->net.C).total,
-                               lr, 0.9f, 0.999f, 1e-8f, a->step, s);
-    if (e == hipSuccess)
-        e = launch_pack(a->net, s);
-    if (e != hipSuccess)
-        return host::hip_fail(e, "train step");
-    return host::ok();
+    return adam_and_pack(a, a->grad, lr, (hipStream_t)hip_stream);
+}
+
+int ising_arnet_adam(ising_arnet *a, const float *d_grad, float lr, void *hip_stream)
+{
+    if (int e = check_net(a))
+        return e;
+    if (!d_grad)
+        return host::fail(ISING_E_BADARG, "null gradient");
+    if (!(lr > 0.f) || !std::isfinite(lr))
+        return host::fail(ISING_E_BADARG, "learning rate must be finite and > 0");
+    return adam_and_pack(a, d_grad, lr, (hipStream_t)hip_stream);
 }
 
 int ising_arnet_sample(ising_arnet *a, int32_t B, uint64_t seed, uint32_t stream_base,
@@ -232,7 +287,13 @@ int ising_arnet_sample(ising_arnet *a, int32_t B, uint64_t seed, uint32_t stream
         return host::fail(ISING_E_BADARG, "null pointer");
     if ((uint64_t)stream_base + (uint64_t)B > (1ull << 24))
         return host::fail(ISING_E_BADARG, "stream_base + B must not exceed 2^24");
-    hipError_t e = launch_sample(a->net, B, a->h, d_spins, d_logq, seed, stream_base, round,
+    if (!sampler_supported(a->net.L, a->net.C))
+        return host::fail(ISING_E_SIZE,
+                          "the sampler holds a configuration in LDS: L <= %d and %zu bytes (L = %d, "
+                          "C = %d needs %zu)",
+                          kSamplerMaxL, lds_limit(), a->net.L, a->net.C,
+                          sampler_lds_bytes(a->net.L, a->net.C));
+    hipError_t e = launch_sample(a->net, B, d_spins, a->logits, d_logq, seed, stream_base, round,
                                  (hipStream_t)hip_stream);
     if (e != hipSuccess)
         return host::hip_fail(e, "sample");

@@ -1,16 +1,22 @@
 // gfx950 kernels of the masked-convolution autoregressive proposal: forward
-// evaluation (log q of given configurations), incremental ancestral sampling,
-// backward pass and Adam, independence Metropolis-Hastings, and conversions
-// between bit-packed lattices and int8 spin arrays.
+// evaluation (log q of given configurations), ancestral sampling along
+// anti-diagonals, backward pass and Adam, independence Metropolis-Hastings,
+// and the observables of int8 configurations.
 //
-// The C -> C layers run on bf16 MFMA (v_mfma_f32_16x16x32_bf16, float32
-// accumulators) through one routine, conv_tile(), which computes 16 rows x C
-// outputs of a masked 3x3 convolution; a row is a (configuration, site)
-// pair.  The evaluator feeds it 16 sites of one configuration, the sampler 16
-// configurations at one site, so every output element is produced by the same
-// instruction sequence in both and the sampler's conditionals are bit for bit
-// those of the evaluator -- the Metropolis-Hastings ratio then uses the exact
-// probability with which a proposal was drawn.
+// Layers 2..6 run on bf16 MFMA (v_mfma_f32_16x16x32_bf16, float32
+// accumulators) through one routine, conv_mfma(), which computes 16 rows x
+// NOUT outputs of a masked 3x3 convolution from the five taps of each row; a
+// row is a (configuration, site) pair.  The evaluator feeds it 16 consecutive
+// sites, the sampler 16 sites of one anti-diagonal of one configuration, and
+// an MFMA output element depends only on its own row of operands, so every
+// conditional the sampler draws from is bit for bit the evaluator's -- the
+// Metropolis-Hastings ratio then uses the exact probability with which a
+// proposal was drawn.
+//
+// The backward pass keeps its signal in float32 and feeds it to the MFMA
+// products as two bfloat16 halves; weight gradients are summed per workgroup
+// over fixed row ranges and the workgroup sums added in workgroup order, so
+// training is reproducible run to run.
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
@@ -29,6 +35,11 @@ __global__ __launch_bounds__(256) void k_pack(NetDev net)
     const int C = net.C;
     const ParamLayout pl = param_layout(C);
     const int64_t g = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (g < 16 * 5 * C) { // the 15 zero columns of layer 6's MFMA operand
+        const int n = (int)(g / (5 * C));
+        if (n > 0)
+            net.w6p[g] = (bf16)0.f;
+    }
     if (g >= pl.total)
         return;
     const float v = net.params[g];
@@ -38,6 +49,7 @@ __global__ __launch_bounds__(256) void k_pack(NetDev net)
     }
     if (g >= pl.W6 && g < pl.W6 + 5 * C) {
         net.w6[g - pl.W6] = round_bf16(v);
+        net.w6p[g - pl.W6] = (bf16)v; // row 0: [t*C + ci]
         return;
     }
     for (int l = 2; l <= 5; ++l) {
@@ -66,46 +78,6 @@ __device__ __forceinline__ float l1_from(const float (&xv)[4], const float *w1, 
     return round_bf16(fmaxf(acc + b1[c], 0.f));
 }
 
-// Layer 1 at site (i, j) of a configuration x.
-__device__ __forceinline__ float l1_value(const int8_t *x, int L, int i, int j, const float *w1,
-                                          const float *b1, int C, int c)
-{
-    float xv[4];
-#pragma unroll
-    for (int t = 0; t < 4; ++t) {
-        const int ii = i + tap_dy(t), jj = j + tap_dx(t);
-        xv[t] = (ii >= 0 && jj >= 0 && jj < L) ? (float)x[ii * L + jj] : 0.f;
-    }
-    return l1_from(xv, w1, b1, C, c);
-}
-
-// Layer 6 (mask B, C -> 1) from the five tap rows of h5 (nullptr: outside the
-// lattice), summed tap by tap, channel by channel.
-__device__ __forceinline__ float l6_from_rows(const bf16 *const (&row)[5], int C, const float *w6,
-                                              float b6)
-{
-    float acc = 0.f;
-    for (int t = 0; t < 5; ++t) {
-        if (row[t] == nullptr)
-            continue;
-        for (int ci = 0; ci < C; ++ci)
-            acc = fmaf((float)row[t][ci], w6[t * C + ci], acc);
-    }
-    return acc + b6;
-}
-
-// Layer 6: the logit of site (i, j) of configuration b.
-__device__ __forceinline__ float l6_logit(const bf16 *h5, int N, int L, int C, int64_t b, int i,
-                                          int j, const float *w6, float b6)
-{
-    const bf16 *row[5];
-    for (int t = 0; t < 5; ++t) {
-        const int ii = i + tap_dy(t), jj = j + tap_dx(t);
-        row[t] = (ii < 0 || jj < 0 || jj >= L) ? nullptr : h5 + ((int64_t)b * N + ii * L + jj) * C;
-    }
-    return l6_from_rows(row, C, w6, b6);
-}
-
 __device__ __forceinline__ float prob_plus(float z) { return 1.f / (1.f + expf(-z)); }
 
 // Realised probability of +1 when x = +1 iff a 24-bit uniform u < P.
@@ -114,6 +86,22 @@ __device__ __forceinline__ float quantise(float P) { return ceilf(P * 16777216.f
 __device__ __forceinline__ double site_logq(float Pq, int xv)
 {
     return xv > 0 ? log((double)Pq) : log1p(-(double)Pq);
+}
+
+// log q~ of one configuration from its logits, computed by a whole wavefront:
+// lane l adds the sites p = l, l + 64, ... in increasing order, then the 64
+// lane sums are combined by a butterfly (offsets 32, 16, .., 1).  Evaluator
+// and sampler both use it, so their results agree bit for bit.
+__device__ __forceinline__ double config_logq(const float *z, const int8_t *x, int N)
+{
+    const int lane = threadIdx.x & 63;
+    double acc = 0.0;
+    for (int p = lane; p < N; p += 64)
+        acc += site_logq(quantise(prob_plus(z[p])), x[p]);
+#pragma unroll
+    for (int off = 32; off > 0; off >>= 1)
+        acc += __shfl_xor(acc, off, 64);
+    return acc;
 }
 
 // ------------------------------------------------------------- MFMA tile
@@ -134,29 +122,20 @@ struct RowsOfSites { // 16 consecutive flattened (configuration, site) rows
     }
 };
 
-struct RowsOfConfigs { // 16 configurations at one site
-    int64_t b0, B;
-    int p;
-    __device__ void operator()(int r, int64_t &b, int &pp) const
-    {
-        b = (b0 + r < B) ? b0 + r : -1;
-        pp = p;
-    }
-};
-
 // The MFMA part of a masked 3x3 convolution tile: with the A operands of the
 // five taps in registers (a[t][kc]: row lane & 15, k = kc*32 + (lane >> 4)*8
-// + e), acc(row, n) = sum_t sum_k a[t][k] * wk[n][t*C + k], accumulated over
-// t = 0..4 and 32-wide k chunks in that order, then handed to the epilogue.
-// `bop(n0, t, kc)` yields the B operand (weights) of that step.
-template <int C, class BOp, class Rows, class Epi>
-__device__ __forceinline__ void conv_mfma_b(const bf16x8 (&a)[5][C / 32], const BOp &bop,
-                                            const Rows &rows, const Epi &epi)
+// + e), acc(row, n) = sum_t sum_k a[t][k] * w[n][t*C + k], accumulated over
+// t = 0..4 and 32-wide k chunks in that order, then handed to the epilogue,
+// for NOUT output columns in blocks of 16.  `bop(n0, t, kc)` yields the B
+// operand (weights) of that step.
+template <int C, int NOUT, class BOp, class Rows, class Epi>
+__device__ __forceinline__ void conv_mfma(const bf16x8 (&a)[5][C / 32], const BOp &bop,
+                                          const Rows &rows, const Epi &epi)
 {
     constexpr int KC = C / 32;
     const int lane = threadIdx.x & 63, r = lane & 15, kq = lane >> 4;
 #pragma unroll
-    for (int n0 = 0; n0 < C; n0 += 16) {
+    for (int n0 = 0; n0 < NOUT; n0 += 16) {
         floatx4 acc = {0.f, 0.f, 0.f, 0.f};
 #pragma unroll
         for (int t = 0; t < 5; ++t)
@@ -174,7 +153,38 @@ __device__ __forceinline__ void conv_mfma_b(const bf16x8 (&a)[5][C / 32], const 
     }
 }
 
-// B operands read from the packed weights of a layer.
+// The same contraction with each A operand the sum of two bf16 halves
+// (backward signal): per step the high half, then the low half.
+template <int C, int NOUT, class BOp, class Rows, class Epi>
+__device__ __forceinline__ void conv_mfma_split(const bf16x8 (&ah)[5][C / 32],
+                                                const bf16x8 (&al)[5][C / 32], const BOp &bop,
+                                                const Rows &rows, const Epi &epi)
+{
+    constexpr int KC = C / 32;
+    const int lane = threadIdx.x & 63, r = lane & 15, kq = lane >> 4;
+#pragma unroll
+    for (int n0 = 0; n0 < NOUT; n0 += 16) {
+        floatx4 acc = {0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+        for (int t = 0; t < 5; ++t)
+#pragma unroll
+            for (int kc = 0; kc < KC; ++kc) {
+                const bf16x8 w = bop(n0, t, kc);
+                acc = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ah[t][kc], w, acc, 0, 0, 0);
+                acc = __builtin_amdgcn_mfma_f32_16x16x32_bf16(al[t][kc], w, acc, 0, 0, 0);
+            }
+#pragma unroll
+        for (int q = 0; q < 4; ++q) {
+            int64_t bb;
+            int pp;
+            rows(kq * 4 + q, bb, pp);
+            if (bb >= 0)
+                epi(kq * 4 + q, bb, pp, n0 + r, acc[q]);
+        }
+    }
+}
+
+// B operands read from packed weights ([n][t*C + k], 5C per column n).
 template <int C>
 struct WeightsGlobal {
     const bf16 *wk;
@@ -186,16 +196,33 @@ struct WeightsGlobal {
     }
 };
 
-template <int C, class Rows, class Epi>
-__device__ __forceinline__ void conv_mfma(const bf16x8 (&a)[5][C / 32],
-                                          const bf16 *__restrict__ wk, const Rows &rows,
-                                          const Epi &epi)
+// The same operands held in registers (NOUT / 16 x 5 x C / 32 per lane).
+template <int C, int NOUT>
+struct WeightsRegs {
+    bf16x8 w[NOUT / 16][5][C / 32];
+    __device__ void load(const bf16 *wk)
+    {
+        const WeightsGlobal<C> g{wk};
+#pragma unroll
+        for (int n = 0; n < NOUT / 16; ++n)
+#pragma unroll
+            for (int t = 0; t < 5; ++t)
+#pragma unroll
+                for (int kc = 0; kc < C / 32; ++kc)
+                    w[n][t][kc] = g(16 * n, t, kc);
+    }
+    __device__ bf16x8 operator()(int n0, int t, int kc) const { return w[n0 / 16][t][kc]; }
+};
+
+__device__ __forceinline__ void zero8(bf16x8 &v)
 {
-    conv_mfma_b<C>(a, WeightsGlobal<C>{wk}, rows, epi);
+#pragma unroll
+    for (int e = 0; e < 8; ++e)
+        v[e] = (bf16)0.f;
 }
 
-// A operand of tap t of a tile row (configuration b, site (i, j)) from an
-// activation array: zero outside the lattice (zero padding).
+// A operand of tap t of a tile row (configuration b, site (ii, jj) of the
+// tap) from an activation array: zero outside the lattice (zero padding).
 template <int C>
 __device__ __forceinline__ void load_tap(bf16x8 (&at)[C / 32], const bf16 *__restrict__ in,
                                          int64_t b, int N, int L, int ii, int jj, int kq)
@@ -203,33 +230,37 @@ __device__ __forceinline__ void load_tap(bf16x8 (&at)[C / 32], const bf16 *__res
     const bool ok = b >= 0 && ii >= 0 && ii < L && jj >= 0 && jj < L;
 #pragma unroll
     for (int kc = 0; kc < C / 32; ++kc) {
-        if (ok) {
+        if (ok)
             at[kc] = *(const bf16x8 *)(in + ((int64_t)b * N + ii * L + jj) * C + kc * 32 + kq * 8);
-        } else {
-#pragma unroll
-            for (int e = 0; e < 8; ++e)
-                at[kc][e] = (bf16)0.f;
-        }
+        else
+            zero8(at[kc]);
     }
 }
 
-// out[rows, 0..C) of a masked 3x3 convolution with all five mask-B taps, the
-// taps read at offset sign * (dy, dx) (sign -1: the transposed convolution of
-// the backward pass).
-template <int C, class Rows, class Epi>
-__device__ __forceinline__ void conv_tile(const bf16 *__restrict__ in, const bf16 *__restrict__ wk,
-                                          int L, int N, int sign, const Rows &rows, const Epi &epi)
+// The same from a float32 backward signal, split into bf16 halves.
+template <int C>
+__device__ __forceinline__ void load_tap_split(bf16x8 (&hi)[C / 32], bf16x8 (&lo)[C / 32],
+                                               const float *__restrict__ in, int64_t b, int N, int L,
+                                               int ii, int jj, int kq)
 {
-    const int lane = threadIdx.x & 63, r = lane & 15, kq = lane >> 4;
-    int64_t b;
-    int p;
-    rows(r, b, p);
-    const int i = p / L, j = p - (p / L) * L;
-    bf16x8 a[5][C / 32];
+    const bool ok = b >= 0 && ii >= 0 && ii < L && jj >= 0 && jj < L;
 #pragma unroll
-    for (int t = 0; t < 5; ++t)
-        load_tap<C>(a[t], in, b, N, L, i + sign * tap_dy(t), j + sign * tap_dx(t), kq);
-    conv_mfma<C>(a, wk, rows, epi);
+    for (int kc = 0; kc < C / 32; ++kc) {
+        if (ok) {
+            const float *src = in + ((int64_t)b * N + ii * L + jj) * C + kc * 32 + kq * 8;
+            const float4 v0 = *(const float4 *)src, v1 = *(const float4 *)(src + 4);
+            const float v[8] = {v0.x, v0.y, v0.z, v0.w, v1.x, v1.y, v1.z, v1.w};
+#pragma unroll
+            for (int e = 0; e < 8; ++e) {
+                const bf16 h = (bf16)v[e];
+                hi[kc][e] = h;
+                lo[kc][e] = (bf16)(v[e] - (float)h);
+            }
+        } else {
+            zero8(hi[kc]);
+            zero8(lo[kc]);
+        }
+    }
 }
 
 struct EpiForward { // post-ReLU bf16 activation
@@ -242,45 +273,54 @@ struct EpiForward { // post-ReLU bf16 activation
     }
 };
 
-// The sampler's epilogue: the activation also goes to an LDS tile (row =
-// configuration within the 16, C channels), the next layer's centre tap.
-struct EpiSample {
-    bf16 *out;
-    bf16 *tile;
-    const float *bias;
-    int N, C;
-    __device__ void operator()(int row, int64_t b, int p, int col, float v) const
+struct EpiLogit { // layer 6: column 0 of the padded product is the logit
+    float *z;
+    float b6;
+    int N;
+    __device__ void operator()(int, int64_t b, int p, int col, float v) const
     {
-        const bf16 h = (bf16)fmaxf(v + bias[col], 0.f);
-        out[((int64_t)b * N + p) * C + col] = h;
-        tile[row * C + col] = h;
+        if (col == 0)
+            z[(int64_t)b * N + p] = v + b6;
     }
 };
 
-struct EpiBackward { // data gradient masked by the ReLU of the layer below
-    bf16 *out;
+struct EpiBackward { // float32 data gradient masked by the ReLU of the layer below
+    float *out;
     const bf16 *act;
     int N, C;
     __device__ void operator()(int, int64_t b, int p, int col, float v) const
     {
         const int64_t o = ((int64_t)b * N + p) * C + col;
-        out[o] = (bf16)((float)act[o] > 0.f ? v : 0.f);
+        out[o] = (float)act[o] > 0.f ? v : 0.f;
     }
 };
 
 // ---------------------------------------------------------------- forward
+// Layer 1: one thread per (row, 8 output channels), one 16-byte store.
 __global__ __launch_bounds__(256) void k_l1_fwd(NetDev net, const int8_t *__restrict__ x,
                                                 bf16 *__restrict__ h1, int64_t rows_total)
 {
+    const int C = net.C, CG = C / 8;
     const int64_t g = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (g >= rows_total)
+    if (g >= rows_total * CG)
         return;
-    const int N = net.N, L = net.L, C = net.C;
-    const int64_t b = g / N;
-    const int p = (int)(g - b * N), i = p / L, j = p % L;
-    const ParamLayout pl = param_layout(C);
-    for (int c = 0; c < C; ++c)
-        h1[g * C + c] = (bf16)l1_value(x + b * N, L, i, j, net.w1, net.params + pl.b1, C, c);
+    const int N = net.N, L = net.L;
+    const int64_t row = g / CG;
+    const int c0 = (int)(g - row * CG) * 8;
+    const int64_t b = row / N;
+    const int p = (int)(row - b * N), i = p / L, j = p - (p / L) * L;
+    float xv[4];
+#pragma unroll
+    for (int t = 0; t < 4; ++t) {
+        const int ii = i + tap_dy(t), jj = j + tap_dx(t);
+        xv[t] = (ii >= 0 && jj >= 0 && jj < L) ? (float)x[b * N + ii * L + jj] : 0.f;
+    }
+    const float *b1 = net.params + param_layout(C).b1;
+    bf16x8 out;
+#pragma unroll
+    for (int e = 0; e < 8; ++e)
+        out[e] = (bf16)l1_from(xv, net.w1, b1, C, c0 + e);
+    *(bf16x8 *)(h1 + row * C + c0) = out;
 }
 
 template <int C>
@@ -292,310 +332,396 @@ __global__ __launch_bounds__(256) void k_conv_fwd(const bf16 *__restrict__ in, b
     const int64_t tile = (int64_t)blockIdx.x * 4 + (threadIdx.x >> 6);
     if (tile * 16 >= rows_total)
         return;
-    conv_tile<C>(in, wk, L, N, +1, RowsOfSites{tile * 16, rows_total, N},
-                 EpiForward{out, bias, N, C});
+    const int lane = threadIdx.x & 63, r = lane & 15, kq = lane >> 4;
+    const RowsOfSites rows{tile * 16, rows_total, N};
+    int64_t b;
+    int p;
+    rows(r, b, p);
+    const int i = p / L, j = p - (p / L) * L;
+    bf16x8 a[5][C / 32];
+#pragma unroll
+    for (int t = 0; t < 5; ++t)
+        load_tap<C>(a[t], in, b, N, L, i + tap_dy(t), j + tap_dx(t), kq);
+    conv_mfma<C, C>(a, WeightsGlobal<C>{wk}, rows, EpiForward{out, bias, N, C});
 }
 
+// Layer 6 on MFMA: the weights as one 16-column operand whose column 0 is W6.
+template <int C>
 __global__ __launch_bounds__(256) void k_l6_fwd(NetDev net, const bf16 *__restrict__ h5,
                                                 float *__restrict__ logits, int64_t rows_total)
 {
-    const int64_t g = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (g >= rows_total)
+    const int64_t tile = (int64_t)blockIdx.x * 4 + (threadIdx.x >> 6);
+    if (tile * 16 >= rows_total)
         return;
     const int N = net.N, L = net.L;
-    const int64_t b = g / N;
-    const int p = (int)(g - b * N);
-    const ParamLayout pl = param_layout(net.C);
-    logits[g] = l6_logit(h5, N, L, net.C, b, p / L, p % L, net.w6, net.params[pl.b6]);
+    const int lane = threadIdx.x & 63, r = lane & 15, kq = lane >> 4;
+    const RowsOfSites rows{tile * 16, rows_total, N};
+    int64_t b;
+    int p;
+    rows(r, b, p);
+    const int i = p / L, j = p - (p / L) * L;
+    bf16x8 a[5][C / 32];
+#pragma unroll
+    for (int t = 0; t < 5; ++t)
+        load_tap<C>(a[t], h5, b, N, L, i + tap_dy(t), j + tap_dx(t), kq);
+    const float b6 = net.params[param_layout(C).b6];
+    conv_mfma<C, 16>(a, WeightsGlobal<C>{net.w6p}, rows, EpiLogit{logits, b6, N});
 }
 
-// Exact log-probability of each configuration under the sampler: sites in
-// raster order, summed in double.
+// Exact log-probability of each configuration under the sampler, one
+// wavefront per configuration.
 __global__ __launch_bounds__(256) void k_logq(const int8_t *__restrict__ x,
                                               const float *__restrict__ logits, int N, int B,
                                               float *__restrict__ logq)
 {
-    const int b = blockIdx.x * blockDim.x + threadIdx.x;
+    const int b = blockIdx.x * 4 + (threadIdx.x >> 6);
     if (b >= B)
         return;
-    double lq = 0.0;
-    for (int p = 0; p < N; ++p)
-        lq += site_logq(quantise(prob_plus(logits[(int64_t)b * N + p])), x[(int64_t)b * N + p]);
-    logq[b] = (float)lq;
+    const double lq = config_logq(logits + (int64_t)b * N, x + (int64_t)b * N, N);
+    if ((threadIdx.x & 63) == 0)
+        logq[b] = (float)lq;
 }
 
 // --------------------------------------------------------------- sampling
-// One wavefront draws 16 configurations site by site.  At site p it computes
-// layer 1 .. 5 activations and the logit of p only (earlier sites are already
-// final: every activation at a site depends on strictly earlier spins), then
-// draws the spin with a 24-bit uniform of Philox domain 3,
-//   counter (stream<<8 | 3<<4, round lo, round hi, p>>2), word p&3.
-// The operands from the previous row (three taps of every layer) are loaded
-// from the activation arrays at the start of the site, all at once; the
-// outputs and spins of the current and previous site, the other two taps,
-// are kept in LDS, so within a row no site waits on a store to memory (one
-// memory fence per row).  The arithmetic is conv_mfma()'s and l1_from()'s,
-// as in the evaluator.
-// B operands of one layer held in registers for the whole kernel (C == 32:
-// 10 operands per lane and layer).
+// Ancestral sampling along anti-diagonals.  Through the masks, every layer's
+// output at site (i, j) depends only on sites (i-1, j-1..j+1) and (i, j-1) of
+// the layer below (and (i, j) itself for mask B), so the six layers and the
+// draw of (i, j) need exactly the sites (i-1, j+1) and (i, j-1) finished:
+// at step t the kernel draws every site with j + 2i = t, all of whose
+// prerequisites belong to step t-1.  A configuration takes 3L - 2 steps
+// instead of L^2.
+//
+// One workgroup per configuration, W wavefronts, each a 16-row MFMA tile of
+// sites of the current diagonal.  Activations live in LDS in a ring of rows
+// (row i at slot i mod R, R = ceil(L/2) + 2 rows: the active diagonal spans
+// at most ceil(L/2) rows plus the one above) with 4 column slots (j mod 4):
+// at step t row i writes column j while its own step and row i+1's read
+// columns j-3 .. j-1, so column j-4 is free.  Spins are kept whole in LDS.
+// Each site draws with a 24-bit uniform of Philox domain 3,
+//   counter (stream<<8 | 3<<4, round lo, round hi, p>>2), word p&3;
+// its logit goes to `zout` and log q~ is summed from there as by the
+// evaluator.
 template <int C>
-struct WeightsRegs {
-    bf16x8 w[C / 16][5][C / 32];
-    __device__ void load(const bf16 *wk)
+struct SamplerRows { // tile row -> (configuration, index on the diagonal)
+    int64_t b;
+    int s0, nsites;
+    __device__ void operator()(int r, int64_t &bb, int &s) const
     {
-        const WeightsGlobal<C> g{wk};
-#pragma unroll
-        for (int n = 0; n < C / 16; ++n)
-#pragma unroll
-            for (int t = 0; t < 5; ++t)
-#pragma unroll
-                for (int kc = 0; kc < C / 32; ++kc)
-                    w[n][t][kc] = g(16 * n, t, kc);
+        s = s0 + r;
+        bb = s < nsites ? b : -1;
     }
-    __device__ bf16x8 operator()(int n0, int t, int kc) const { return w[n0 / 16][t][kc]; }
 };
 
-// A operand of a tap from an LDS tile of 16 rows x C (zero when !ok).
 template <int C>
-__device__ __forceinline__ void lds_tap(bf16x8 (&at)[C / 32], const bf16 *tile, bool ok, int r,
-                                        int kq)
-{
-#pragma unroll
-    for (int kc = 0; kc < C / 32; ++kc) {
-        if (ok) {
-            at[kc] = *(const bf16x8 *)(tile + r * C + kc * 32 + kq * 8);
-        } else {
-#pragma unroll
-            for (int e = 0; e < 8; ++e)
-                at[kc][e] = (bf16)0.f;
-        }
+struct EpiRing { // post-ReLU bf16 activation into the ring
+    bf16 *ring;
+    const float *bias;
+    int R, i_lo, t, layer;
+    __device__ void operator()(int, int64_t, int s, int col, float v) const
+    {
+        const int i = i_lo + s, j = t - 2 * i;
+        ring[(((i % R) * 4 + (j & 3)) * 5 + layer) * C + col] = (bf16)fmaxf(v + bias[col], 0.f);
     }
-}
+};
 
-// Orders the wavefront's LDS accesses (one wavefront per workgroup) without
-// waiting for its global stores.
-__device__ __forceinline__ void lds_sync()
-{
-    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup", "local");
-    __builtin_amdgcn_s_barrier();
-    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup", "local");
-}
+struct EpiZ { // logit of the diagonal's site s
+    float *zs;
+    float b6;
+    __device__ void operator()(int, int64_t, int s, int col, float v) const
+    {
+        if (col == 0)
+            zs[s] = v + b6;
+    }
+};
 
-template <int C>
-__global__ __launch_bounds__(64) void k_sample(NetDev net, bf16 *h1, bf16 *h2, bf16 *h3, bf16 *h4,
-                                               bf16 *h5, int8_t *__restrict__ x,
-                                               float *__restrict__ logq, int B, uint32_t key0,
-                                               uint32_t key1, uint32_t stream_base,
-                                               uint32_t round_lo, uint32_t round_hi)
+template <int C, int W>
+__global__ __launch_bounds__(64 * W) void k_sample(NetDev net, int8_t *__restrict__ x,
+                                                   float *__restrict__ zout, float *__restrict__ logq,
+                                                   uint32_t key0, uint32_t key1,
+                                                   uint32_t stream_base, uint32_t round_lo,
+                                                   uint32_t round_hi)
 {
     constexpr int KC = C / 32;
-    constexpr bool kRegW = C == 32; // the four layers' weights fit in registers
-    // layer outputs (1..5) and spins at the last two sites, by site parity
-    __shared__ __align__(16) bf16 hist[6][2][16 * C];
-    __shared__ int8_t xs[2][16];
-    const int N = net.N, L = net.L;
+    constexpr bool kRegW = C == 32; // the five layers' weights fit in registers
+    extern __shared__ __align__(16) unsigned char smem[];
+    __shared__ float zs[16 * W];
+    const int L = net.L, N = net.N, R = sampler_ring_rows(L);
+    bf16 *ring = (bf16 *)smem; // [R][4][5][C]
+    int8_t *sp = (int8_t *)(smem + (size_t)R * 4 * 5 * C * sizeof(bf16));
+    const int64_t b = blockIdx.x;
+    const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63, r = lane & 15, kq = lane >> 4;
     const ParamLayout pl = param_layout(C);
-    const int lane = threadIdx.x, r = lane & 15, kq = lane >> 4;
-    const int64_t b0 = (int64_t)blockIdx.x * 16;
-    bf16 *hs[6] = {nullptr, h1, h2, h3, h4, h5};
-    WeightsRegs<(kRegW ? C : 32)> wreg[kRegW ? 4 : 1];
-    if (kRegW)
+    const float *b1 = net.params + pl.b1;
+    const float b6 = net.params[pl.b6];
+    WeightsRegs<32, 32> wreg[kRegW ? 4 : 1];
+    WeightsRegs<32, 16> w6reg;
+    if constexpr (kRegW) {
 #pragma unroll
         for (int l = 2; l <= 5; ++l)
-            wreg[kRegW ? l - 2 : 0].load(net.wf[l]);
-    double lq = 0.0;
-    const int64_t b = (b0 + r < B) ? b0 + r : -1; // this lane's tile row
-    const RowsOfConfigs rows_p{b0, B, 0};
-    for (int p = 0; p < N; ++p) {
-        const int i = p / L, j = p - (p / L) * L;
-        const int cur = p & 1, prv = cur ^ 1;
-        const bool left = j > 0; // tap (0, -1) inside the lattice
-        // previous-row taps (dy = -1: t = 0, 1, 2) of layers 2..5 and 6, and spins
-        bf16x8 pre[4][3][KC];
-#pragma unroll
-        for (int l = 2; l <= 5; ++l)
-#pragma unroll
-            for (int t = 0; t < 3; ++t)
-                load_tap<C>(pre[l - 2][t], hs[l - 1], b, N, L, i + tap_dy(t), j + tap_dx(t), kq);
-        bf16x8 r6[3][C / 8];
-        bool in6[3];
-#pragma unroll
-        for (int t = 0; t < 3; ++t) {
-            const int ii = i + tap_dy(t), jj = j + tap_dx(t);
-            in6[t] = !(ii < 0 || jj < 0 || jj >= L);
-            if (lane < 16 && b >= 0 && in6[t]) {
-                const bf16 *src = h5 + (b * N + ii * L + jj) * C;
-#pragma unroll
-                for (int v = 0; v < C / 8; ++v)
-                    r6[t][v] = *(const bf16x8 *)(src + v * 8);
-            }
-        }
-        // layer 1 at p (mask A: earlier spins only)
-        if (b >= 0) {
+            wreg[l - 2].load(net.wf[l]);
+        w6reg.load(net.w6p);
+    }
+    for (int e = threadIdx.x; e < N; e += 64 * W)
+        sp[e] = 0;
+    __syncthreads();
+    const int steps = 3 * L - 2;
+    for (int t = 0; t < steps; ++t) {
+        const int i_lo = t > L - 1 ? (t - L + 2) >> 1 : 0;
+        const int i_hi = (t >> 1) < L - 1 ? (t >> 1) : L - 1;
+        const int nsites = i_hi - i_lo + 1;
+        // this lane's tile row: site s of the diagonal
+        const int s = 16 * wave + r;
+        const bool valid = s < nsites;
+        const int i = i_lo + s, j = t - 2 * i;
+        // layer 1 (mask A) at the row's site, 8 channels per 16-byte group
+        if (valid) {
             float xv[4];
 #pragma unroll
-            for (int t = 0; t < 3; ++t) {
-                const int ii = i + tap_dy(t), jj = j + tap_dx(t);
-                xv[t] = (ii >= 0 && jj >= 0 && jj < L) ? (float)x[b * N + ii * L + jj] : 0.f;
+            for (int tt = 0; tt < 3; ++tt) {
+                const int jj = j + tap_dx(tt);
+                xv[tt] = (i > 0 && jj >= 0 && jj < L) ? (float)sp[(i - 1) * L + jj] : 0.f;
             }
-            xv[3] = left ? (float)xs[prv][r] : 0.f;
-            for (int c = kq; c < C; c += 4) {
-                const bf16 h = (bf16)l1_from(xv, net.w1, net.params + pl.b1, C, c);
-                h1[(b * N + p) * C + c] = h;
-                hist[1][cur][r * C + c] = h;
+            xv[3] = j > 0 ? (float)sp[i * L + j - 1] : 0.f;
+            bf16 *dst = ring + (((i % R) * 4 + (j & 3)) * 5 + 0) * C;
+#pragma unroll
+            for (int g = 0; g < KC; ++g) {
+                const int c0 = (kq * KC + g) * 8;
+                bf16x8 v;
+#pragma unroll
+                for (int e = 0; e < 8; ++e)
+                    v[e] = (bf16)l1_from(xv, net.w1, b1, C, c0 + e);
+                *(bf16x8 *)(dst + c0) = v;
             }
         }
-        lds_sync();
-        RowsOfConfigs rows = rows_p;
-        rows.p = p;
+        __syncthreads();
+        // ring rows of the five taps of this lane's site
+        const bf16 *tap_base[5];
+        bool tap_ok[5];
 #pragma unroll
-        for (int l = 2; l <= 5; ++l) {
+        for (int tt = 0; tt < 5; ++tt) {
+            const int ii = i + tap_dy(tt), jj = j + tap_dx(tt);
+            tap_ok[tt] = valid && ii >= 0 && jj >= 0 && jj < L;
+            tap_base[tt] = ring + (((tap_ok[tt] ? ii % R : 0) * 4 + (jj & 3)) * 5) * C + kq * 8;
+        }
+        const SamplerRows<C> rows{b, 16 * wave, nsites};
+#pragma unroll
+        for (int l = 2; l <= 6; ++l) {
             bf16x8 a[5][KC];
 #pragma unroll
-            for (int t = 0; t < 3; ++t)
+            for (int tt = 0; tt < 5; ++tt)
 #pragma unroll
-                for (int kc = 0; kc < KC; ++kc)
-                    a[t][kc] = pre[l - 2][t][kc];
-            lds_tap<C>(a[3], hist[l - 1][prv], b >= 0 && left, r, kq);
-            lds_tap<C>(a[4], hist[l - 1][cur], b >= 0, r, kq);
-            const EpiSample epi{hs[l], hist[l][cur], net.params + pl.b[l], N, C};
-            if constexpr (kRegW)
-                conv_mfma_b<C>(a, wreg[l - 2], rows, epi);
-            else
-                conv_mfma<C>(a, net.wf[l], rows, epi);
-            lds_sync();
-        }
-        if (lane < 16 && b >= 0) {
-            // layer 6, in l6_from_rows()'s order: taps 0..4, channels 0..C-1
-            const float *w6 = net.w6;
-            float acc = 0.f;
-#pragma unroll
-            for (int t = 0; t < 3; ++t)
-                if (in6[t])
-#pragma unroll
-                    for (int v = 0; v < C / 8; ++v)
-#pragma unroll
-                        for (int e = 0; e < 8; ++e)
-                            acc = fmaf((float)r6[t][v][e], w6[t * C + v * 8 + e], acc);
-            if (left) {
-                const bf16 *w = hist[5][prv] + r * C;
-                for (int ci = 0; ci < C; ++ci)
-                    acc = fmaf((float)w[ci], w6[3 * C + ci], acc);
+                for (int kc = 0; kc < KC; ++kc) {
+                    if (tap_ok[tt])
+                        a[tt][kc] = *(const bf16x8 *)(tap_base[tt] + (l - 2) * C + kc * 32);
+                    else
+                        zero8(a[tt][kc]);
+                }
+            if (l <= 5) {
+                const EpiRing<C> epi{ring, net.params + pl.b[l], R, i_lo, t, l - 1};
+                if constexpr (kRegW)
+                    conv_mfma<C, C>(a, wreg[kRegW ? l - 2 : 0], rows, epi);
+                else
+                    conv_mfma<C, C>(a, WeightsGlobal<C>{net.wf[l]}, rows, epi);
+            } else {
+                const EpiZ epi{zs, b6};
+                if constexpr (kRegW)
+                    conv_mfma<C, 16>(a, w6reg, rows, epi);
+                else
+                    conv_mfma<C, 16>(a, WeightsGlobal<C>{net.w6p}, rows, epi);
             }
-            const bf16 *centre = hist[5][cur] + r * C;
-            for (int ci = 0; ci < C; ++ci)
-                acc = fmaf((float)centre[ci], w6[4 * C + ci], acc);
-            const float z = acc + net.params[pl.b6];
+            __syncthreads();
+        }
+        // the draws of this wavefront's sites
+        if (lane < 16 && valid) {
+            const int p = i * L + j;
+            const float z = zs[s];
             const float Pq = quantise(prob_plus(z));
             const Block u = philox4x32_10(ctr_word0(stream_base + (uint32_t)b, 3u, 0u), round_lo,
                                           round_hi, (uint32_t)(p >> 2), key0, key1);
             const uint32_t w = (p & 3) == 0 ? u.x0 : (p & 3) == 1 ? u.x1 : (p & 3) == 2 ? u.x2 : u.x3;
             const float uf = (float)(w >> 8) * (1.f / 16777216.f);
-            const int xv = uf < Pq ? 1 : -1;
-            x[b * N + p] = (int8_t)xv;
-            xs[cur][r] = (int8_t)xv;
-            lq += site_logq(Pq, xv);
+            const int8_t xv = uf < Pq ? 1 : -1;
+            sp[p] = xv;
+            x[b * N + p] = xv;
+            zout[b * N + p] = z;
         }
-        // the next row reads this row's activations and spins from memory
-        if (j == L - 1)
-            __syncthreads();
-        else
-            lds_sync();
+        __syncthreads();
     }
-    if (lane < 16 && b >= 0)
-        logq[b] = (float)lq;
+    if (wave == 0) {
+        const double lq = config_logq(zout + b * N, sp, N);
+        if (lane == 0)
+            logq[b] = (float)lq;
+    }
 }
 
 // --------------------------------------------------------------- backward
-__device__ __forceinline__ float block_sum(float v, float *scratch)
-{
-    for (int off = 32; off > 0; off >>= 1)
-        v += __shfl_xor(v, off, 64);
-    const int w = threadIdx.x >> 6;
-    __syncthreads();
-    if ((threadIdx.x & 63) == 0)
-        scratch[w] = v;
-    __syncthreads();
-    float t = 0.f;
-    for (int q = 0; q < (int)(blockDim.x >> 6); ++q)
-        t += scratch[q];
-    return t;
-}
-
-// d(mean NLL)/d logit = -s sigmoid(-s z) / B, and the mean NLL itself.
-__global__ __launch_bounds__(256) void k_dlogit(const int8_t *__restrict__ x,
-                                                const float *__restrict__ logits,
-                                                float *__restrict__ dlogit, int64_t rows_total,
-                                                float invB, float *loss)
-{
-    __shared__ float scratch[4];
-    const int64_t g = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    float l = 0.f;
-    if (g < rows_total) {
-        const float s = (float)x[g], z = logits[g], sz = s * z;
-        dlogit[g] = -s / (1.f + expf(sz)) * invB;
-        l = (fmaxf(-sz, 0.f) + log1pf(expf(-fabsf(sz)))) * invB;
+// Rows [0, rows_total) are cut into 64-row chunks; workgroup g of a weight
+// gradient kernel takes chunks [g*cpb, (g+1)*cpb) and writes its sums to row
+// g of `partial` (pstride floats per row, the parameter vector plus the loss).
+struct ChunkRange {
+    int64_t c0, c1;
+    __device__ ChunkRange(int64_t nchunks, int64_t cpb)
+    {
+        c0 = (int64_t)blockIdx.x * cpb;
+        c1 = c0 + cpb < nchunks ? c0 + cpb : nchunks;
     }
-    const float t = block_sum(l, scratch);
-    if (threadIdx.x == 0)
-        atomicAdd(loss, t);
+};
+
+// Fixed-order sum over the 256 threads of a workgroup (thread 0 adds the 256
+// values in thread order); every thread gets the total.
+__device__ __forceinline__ float block_sum_ordered(float v, float *red)
+{
+    __syncthreads();
+    red[threadIdx.x] = v;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        float s = 0.f;
+        for (int k = 0; k < 256; ++k)
+            s += red[k];
+        red[256] = s;
+    }
+    __syncthreads();
+    return red[256];
 }
 
-// Weight and bias gradients of layer 6 over a chunk of rows per block.
-__global__ __launch_bounds__(256) void k_l6_wgrad(NetDev net, const bf16 *__restrict__ h5,
-                                                  const float *__restrict__ dlogit,
-                                                  int64_t rows_total, int rows_per_block,
-                                                  float *__restrict__ grad)
+// d(mean NLL)/d logit = -s sigmoid(-s z) / B (float32, written out), the mean
+// NLL, and the layer-6 weight and bias gradients:
+//   dW6[t][ci] = sum_rows h5[row shifted by tap t][ci] * dlogit[row]
+// on MFMA: rows as the reduction dimension, 64 at a time transposed in LDS,
+// dlogit as columns 0 (high half) and 1 (low half) of the B operand.
+template <int C>
+__global__ __launch_bounds__(256) void k_l6_back(NetDev net, const int8_t *__restrict__ x,
+                                                 const float *__restrict__ logits,
+                                                 const bf16 *__restrict__ h5,
+                                                 float *__restrict__ dlogit, int64_t rows_total,
+                                                 int64_t nchunks, int64_t cpb, float invB,
+                                                 float *__restrict__ partial, int64_t pstride)
 {
-    __shared__ float scratch[4];
-    const int N = net.N, L = net.L, C = net.C;
+    constexpr int MT = C / 16, TILES = 5 * MT, TPW = (TILES + 3) / 4;
+    __shared__ __align__(16) bf16 sA[5][C][64];
+    __shared__ __align__(16) bf16 sD[16][64];
+    __shared__ float red[257];
+    const int N = net.N, L = net.L;
     const ParamLayout pl = param_layout(C);
-    const int64_t r0 = (int64_t)blockIdx.x * rows_per_block;
-    const int64_t r1 = r0 + rows_per_block < rows_total ? r0 + rows_per_block : rows_total;
-    for (int e = threadIdx.x; e < 5 * C; e += blockDim.x) {
-        const int t = e / C, ci = e % C;
-        float acc = 0.f;
-        for (int64_t g = r0; g < r1; ++g) {
-            const int64_t b = g / N;
-            const int p = (int)(g - b * N), ii = p / L + tap_dy(t), jj = p % L + tap_dx(t);
-            if (ii >= 0 && jj >= 0 && jj < L)
-                acc = fmaf((float)h5[((int64_t)b * N + ii * L + jj) * C + ci], dlogit[g], acc);
+    const int tid = threadIdx.x, wave = tid >> 6, lane = tid & 63, r = lane & 15, kq = lane >> 4;
+    floatx4 acc[TPW];
+#pragma unroll
+    for (int q = 0; q < TPW; ++q)
+        acc[q] = floatx4{0.f, 0.f, 0.f, 0.f};
+    for (int e = tid; e < 14 * 64; e += 256)
+        sD[2 + e / 64][e % 64] = (bf16)0.f;
+    float lsum = 0.f, dsum = 0.f;
+    const ChunkRange cr(nchunks, cpb);
+    for (int64_t ch = cr.c0; ch < cr.c1; ++ch) {
+        const int64_t row0 = ch * 64;
+        __syncthreads();
+        for (int e = tid; e < 64 * C; e += 256) {
+            const int k = e / C, c = e % C;
+            const int64_t g = row0 + k;
+            const bool valid = g < rows_total;
+            const int64_t b = valid ? g / N : 0;
+            const int p = valid ? (int)(g - b * N) : 0, i = p / L, j = p - (p / L) * L;
+#pragma unroll
+            for (int t = 0; t < 5; ++t) {
+                const int ii = i + tap_dy(t), jj = j + tap_dx(t);
+                const bool ok = valid && ii >= 0 && jj >= 0 && jj < L;
+                sA[t][c][k] = ok ? h5[((int64_t)b * N + ii * L + jj) * C + c] : (bf16)0.f;
+            }
         }
-        atomicAdd(&grad[pl.W6 + e], acc);
+        if (tid < 64) {
+            const int64_t g = row0 + tid;
+            float d = 0.f;
+            if (g < rows_total) {
+                const float s = (float)x[g], z = logits[g], sz = s * z;
+                d = -s / (1.f + expf(sz)) * invB;
+                lsum += (fmaxf(-sz, 0.f) + log1pf(expf(-fabsf(sz)))) * invB;
+                dlogit[g] = d;
+            }
+            dsum += d;
+            const bf16 h = (bf16)d;
+            sD[0][tid] = h;
+            sD[1][tid] = (bf16)(d - (float)h);
+        }
+        __syncthreads();
+#pragma unroll
+        for (int q = 0; q < TPW; ++q) {
+            const int tile = wave + 4 * q;
+            if (tile < TILES) {
+                const int t = tile / MT, m = tile % MT;
+#pragma unroll
+                for (int ks = 0; ks < 2; ++ks) {
+                    const bf16x8 av = *(const bf16x8 *)&sA[t][m * 16 + r][ks * 32 + kq * 8];
+                    const bf16x8 bv = *(const bf16x8 *)&sD[r][ks * 32 + kq * 8];
+                    acc[q] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(av, bv, acc[q], 0, 0, 0);
+                }
+            }
+        }
     }
-    float db = 0.f;
-    for (int64_t g = r0 + threadIdx.x; g < r1; g += blockDim.x)
-        db += dlogit[g];
-    db = block_sum(db, scratch);
-    if (threadIdx.x == 0)
-        atomicAdd(&grad[pl.b6], db);
+    float *out = partial + (int64_t)blockIdx.x * pstride;
+#pragma unroll
+    for (int q = 0; q < TPW; ++q) {
+        const int tile = wave + 4 * q;
+        if (tile < TILES) { // wave-uniform
+            const int t = tile / MT, m = tile % MT;
+#pragma unroll
+            for (int e = 0; e < 4; ++e) {
+                const float lo = __shfl_down(acc[q][e], 1, 64); // column 1 of the same row
+                if (r == 0)
+                    out[pl.W6 + t * C + m * 16 + kq * 4 + e] = acc[q][e] + lo;
+            }
+        }
+    }
+    const float db = block_sum_ordered(dsum, red);
+    const float ls = block_sum_ordered(lsum, red);
+    if (tid == 0) {
+        out[pl.b6] = db;
+        out[pl.total] = ls;
+    }
 }
 
-// Data gradient into layer 5, masked by its ReLU: dpre5 = bf16(dh5 * [h5 > 0]).
+// Data gradient into layer 5, masked by its ReLU, float32:
+//   dpre5[row][ci] = [h5 > 0] sum_t W6[t][ci] dlogit[row - tap t],
+// one thread per (row, 8 channels).
 __global__ __launch_bounds__(256) void k_l6_dgrad(NetDev net, const bf16 *__restrict__ h5,
                                                   const float *__restrict__ dlogit,
-                                                  bf16 *__restrict__ dpre, int64_t rows_total)
+                                                  float *__restrict__ dpre, int64_t rows_total)
 {
-    const int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    const int N = net.N, L = net.L, C = net.C;
-    if (e >= rows_total * C)
+    const int C = net.C, CG = C / 8, N = net.N, L = net.L;
+    const int64_t g = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (g >= rows_total * CG)
         return;
-    const int64_t g = e / C;
-    const int ci = (int)(e % C);
-    const int64_t b = g / N;
-    const int p = (int)(g - b * N), i = p / L, j = p % L;
-    float dh = 0.f;
+    const int64_t row = g / CG;
+    const int c0 = (int)(g - row * CG) * 8;
+    const int64_t b = row / N;
+    const int p = (int)(row - b * N), i = p / L, j = p - (p / L) * L;
+    float dh[8];
+#pragma unroll
+    for (int e = 0; e < 8; ++e)
+        dh[e] = 0.f;
+#pragma unroll
     for (int t = 0; t < 5; ++t) {
         const int ii = i - tap_dy(t), jj = j - tap_dx(t);
-        if (ii >= 0 && ii < L && jj >= 0 && jj < L)
-            dh = fmaf(net.w6[t * C + ci], dlogit[(int64_t)b * N + ii * L + jj], dh);
+        if (ii >= 0 && ii < L && jj >= 0 && jj < L) {
+            const float d = dlogit[b * N + ii * L + jj];
+#pragma unroll
+            for (int e = 0; e < 8; ++e)
+                dh[e] = fmaf(net.w6[t * C + c0 + e], d, dh[e]);
+        }
     }
-    dpre[e] = (bf16)((float)h5[e] > 0.f ? dh : 0.f);
+    const bf16x8 h = *(const bf16x8 *)(h5 + row * C + c0);
+    float *o = dpre + row * C + c0;
+    *(float4 *)o = float4{(float)h[0] > 0.f ? dh[0] : 0.f, (float)h[1] > 0.f ? dh[1] : 0.f,
+                          (float)h[2] > 0.f ? dh[2] : 0.f, (float)h[3] > 0.f ? dh[3] : 0.f};
+    *(float4 *)(o + 4) = float4{(float)h[4] > 0.f ? dh[4] : 0.f, (float)h[5] > 0.f ? dh[5] : 0.f,
+                                (float)h[6] > 0.f ? dh[6] : 0.f, (float)h[7] > 0.f ? dh[7] : 0.f};
 }
 
+// Data gradient through a C -> C layer (the transposed convolution: taps at
+// negated offsets), float32 signal split into bf16 halves, ReLU mask of the
+// layer below.
 template <int C>
-__global__ __launch_bounds__(256) void k_conv_dgrad(const bf16 *__restrict__ dpre_above,
-                                                    bf16 *__restrict__ dpre_below,
+__global__ __launch_bounds__(256) void k_conv_dgrad(const float *__restrict__ dpre_above,
+                                                    float *__restrict__ dpre_below,
                                                     const bf16 *__restrict__ act_below,
                                                     const bf16 *__restrict__ wk, int L, int N,
                                                     int64_t rows_total)
@@ -603,40 +729,57 @@ __global__ __launch_bounds__(256) void k_conv_dgrad(const bf16 *__restrict__ dpr
     const int64_t tile = (int64_t)blockIdx.x * 4 + (threadIdx.x >> 6);
     if (tile * 16 >= rows_total)
         return;
-    conv_tile<C>(dpre_above, wk, L, N, -1, RowsOfSites{tile * 16, rows_total, N},
-                 EpiBackward{dpre_below, act_below, N, C});
+    const int lane = threadIdx.x & 63, r = lane & 15, kq = lane >> 4;
+    const RowsOfSites rows{tile * 16, rows_total, N};
+    int64_t b;
+    int p;
+    rows(r, b, p);
+    const int i = p / L, j = p - (p / L) * L;
+    bf16x8 ah[5][C / 32], al[5][C / 32];
+#pragma unroll
+    for (int t = 0; t < 5; ++t)
+        load_tap_split<C>(ah[t], al[t], dpre_above, b, N, L, i - tap_dy(t), j - tap_dx(t), kq);
+    conv_mfma_split<C, C>(ah, al, WeightsGlobal<C>{wk}, rows, EpiBackward{dpre_below, act_below, N, C});
 }
 
 // Weight and bias gradients of a C -> C layer:
 //   dW[t][ci][co] = sum_rows act_below[row shifted by tap t][ci] * dpre[row][co]
-// on MFMA, rows as the reduction dimension, 64 rows at a time transposed in LDS.
+// on MFMA, rows as the reduction dimension, 64 rows at a time transposed in
+// LDS, dpre as two bf16 halves; db[co] = sum_rows dpre[row][co] in float32.
 template <int C>
 __global__ __launch_bounds__(256) void k_conv_wgrad(const bf16 *__restrict__ act_below,
-                                                    const bf16 *__restrict__ dpre, int L, int N,
-                                                    int64_t rows_total, int chunks_per_block,
-                                                    float *__restrict__ gW, float *__restrict__ gb)
+                                                    const float *__restrict__ dpre, int L, int N,
+                                                    int64_t rows_total, int64_t nchunks, int64_t cpb,
+                                                    float *__restrict__ pW, float *__restrict__ pb,
+                                                    int64_t pstride)
 {
     constexpr int MT = C / 16, TILES = 5 * MT * MT, TPW = TILES / 4;
+    constexpr int TPC = 256 / C; // threads sharing one channel in the staging loop
     __shared__ __align__(16) bf16 sA[5][C][64];
-    __shared__ __align__(16) bf16 sD[C][64];
+    __shared__ __align__(16) bf16 sDh[C][64];
+    __shared__ __align__(16) bf16 sDl[C][64];
+    __shared__ float red[256];
     const int tid = threadIdx.x, wave = tid >> 6, lane = tid & 63, r = lane & 15, kq = lane >> 4;
     floatx4 acc[TPW];
 #pragma unroll
     for (int q = 0; q < TPW; ++q)
         acc[q] = floatx4{0.f, 0.f, 0.f, 0.f};
-    float bacc = 0.f;
-    for (int ch = 0; ch < chunks_per_block; ++ch) {
-        const int64_t row0 = ((int64_t)blockIdx.x * chunks_per_block + ch) * 64;
-        if (row0 >= rows_total)
-            break;
+    float bacc = 0.f; // channel tid % C, rows k = tid / C + TPC * it of each chunk
+    const ChunkRange cr(nchunks, cpb);
+    for (int64_t ch = cr.c0; ch < cr.c1; ++ch) {
+        const int64_t row0 = ch * 64;
         __syncthreads();
         for (int e = tid; e < 64 * C; e += 256) {
             const int k = e / C, c = e % C;
             const int64_t g = row0 + k;
             const bool valid = g < rows_total;
             const int64_t b = valid ? g / N : 0;
-            const int p = valid ? (int)(g - b * N) : 0, i = p / L, j = p % L;
-            sD[c][k] = valid ? dpre[g * C + c] : (bf16)0.f;
+            const int p = valid ? (int)(g - b * N) : 0, i = p / L, j = p - (p / L) * L;
+            const float d = valid ? dpre[g * C + c] : 0.f;
+            bacc += d;
+            const bf16 h = (bf16)d;
+            sDh[c][k] = h;
+            sDl[c][k] = (bf16)(d - (float)h);
 #pragma unroll
             for (int t = 0; t < 5; ++t) {
                 const int ii = i + tap_dy(t), jj = j + tap_dx(t);
@@ -645,9 +788,6 @@ __global__ __launch_bounds__(256) void k_conv_wgrad(const bf16 *__restrict__ act
             }
         }
         __syncthreads();
-        if (tid < C)
-            for (int k = 0; k < 64; ++k)
-                bacc += (float)sD[tid][k];
 #pragma unroll
         for (int q = 0; q < TPW; ++q) {
             const int tile = wave * TPW + q;
@@ -655,11 +795,14 @@ __global__ __launch_bounds__(256) void k_conv_wgrad(const bf16 *__restrict__ act
 #pragma unroll
             for (int ks = 0; ks < 2; ++ks) {
                 const bf16x8 av = *(const bf16x8 *)&sA[t][m * 16 + r][ks * 32 + kq * 8];
-                const bf16x8 bv = *(const bf16x8 *)&sD[n * 16 + r][ks * 32 + kq * 8];
-                acc[q] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(av, bv, acc[q], 0, 0, 0);
+                const bf16x8 bh = *(const bf16x8 *)&sDh[n * 16 + r][ks * 32 + kq * 8];
+                const bf16x8 bl = *(const bf16x8 *)&sDl[n * 16 + r][ks * 32 + kq * 8];
+                acc[q] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(av, bh, acc[q], 0, 0, 0);
+                acc[q] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(av, bl, acc[q], 0, 0, 0);
             }
         }
     }
+    float *oW = pW + (int64_t)blockIdx.x * pstride;
 #pragma unroll
     for (int q = 0; q < TPW; ++q) {
         const int tile = wave * TPW + q;
@@ -667,46 +810,116 @@ __global__ __launch_bounds__(256) void k_conv_wgrad(const bf16 *__restrict__ act
 #pragma unroll
         for (int e = 0; e < 4; ++e) {
             const int ci = m * 16 + kq * 4 + e, co = n * 16 + r;
-            atomicAdd(&gW[((int64_t)t * C + ci) * C + co], acc[q][e]);
+            oW[((int64_t)t * C + ci) * C + co] = acc[q][e];
         }
     }
-    if (tid < C)
-        atomicAdd(&gb[tid], bacc);
+    // bias: the TPC threads of a channel, in thread order
+    __syncthreads();
+    red[tid] = bacc;
+    __syncthreads();
+    if (tid < C) {
+        float s = 0.f;
+        for (int k = 0; k < TPC; ++k)
+            s += red[tid + k * C];
+        pb[(int64_t)blockIdx.x * pstride + tid] = s;
+    }
 }
 
-// Weight and bias gradients of layer 1 over a chunk of rows per block.
+// Weight and bias gradients of layer 1 on MFMA: A = the four mask-A spins of
+// each row (rows 0..3) and a row of ones (row 4, the bias), B = dpre1 as two
+// bf16 halves; dW1[t][c] = sum_rows x[row shifted by tap t] dpre1[row][c].
+template <int C>
 __global__ __launch_bounds__(256) void k_l1_wgrad(NetDev net, const int8_t *__restrict__ x,
-                                                  const bf16 *__restrict__ dpre1,
-                                                  int64_t rows_total, int rows_per_block,
-                                                  float *__restrict__ grad)
+                                                  const float *__restrict__ dpre1,
+                                                  int64_t rows_total, int64_t nchunks, int64_t cpb,
+                                                  float *__restrict__ partial, int64_t pstride)
 {
-    const int N = net.N, L = net.L, C = net.C;
+    constexpr int NT = C / 16; // 16-column tiles, one or two per wavefront
+    __shared__ __align__(16) bf16 sX[16][64];
+    __shared__ __align__(16) bf16 sDh[C][64];
+    __shared__ __align__(16) bf16 sDl[C][64];
+    const int N = net.N, L = net.L;
     const ParamLayout pl = param_layout(C);
-    const int64_t r0 = (int64_t)blockIdx.x * rows_per_block;
-    const int64_t r1 = r0 + rows_per_block < rows_total ? r0 + rows_per_block : rows_total;
-    for (int e = threadIdx.x; e < 5 * C; e += blockDim.x) {
-        const int t = e / C, c = e % C; // t == 4: bias
-        float acc = 0.f;
-        for (int64_t g = r0; g < r1; ++g) {
-            const float d = (float)dpre1[g * C + c];
-            if (t == 4) {
-                acc += d;
-                continue;
-            }
-            const int64_t b = g / N;
-            const int p = (int)(g - b * N), ii = p / L + tap_dy(t), jj = p % L + tap_dx(t);
-            if (ii >= 0 && jj >= 0 && jj < L)
-                acc = fmaf((float)x[(int64_t)b * N + ii * L + jj], d, acc);
+    const int tid = threadIdx.x, wave = tid >> 6, lane = tid & 63, r = lane & 15, kq = lane >> 4;
+    floatx4 acc[2] = {floatx4{0.f, 0.f, 0.f, 0.f}, floatx4{0.f, 0.f, 0.f, 0.f}};
+    for (int e = tid; e < 11 * 64; e += 256)
+        sX[5 + e / 64][e % 64] = (bf16)0.f;
+    const ChunkRange cr(nchunks, cpb);
+    for (int64_t ch = cr.c0; ch < cr.c1; ++ch) {
+        const int64_t row0 = ch * 64;
+        __syncthreads();
+        for (int e = tid; e < 64 * C; e += 256) {
+            const int k = e / C, c = e % C;
+            const int64_t g = row0 + k;
+            const float d = g < rows_total ? dpre1[g * C + c] : 0.f;
+            const bf16 h = (bf16)d;
+            sDh[c][k] = h;
+            sDl[c][k] = (bf16)(d - (float)h);
         }
-        atomicAdd(&grad[t == 4 ? pl.b1 + c : pl.W1 + t * C + c], acc);
+        if (tid < 64) {
+            const int64_t g = row0 + tid;
+            const bool valid = g < rows_total;
+            const int64_t b = valid ? g / N : 0;
+            const int p = valid ? (int)(g - b * N) : 0, i = p / L, j = p - (p / L) * L;
+#pragma unroll
+            for (int t = 0; t < 4; ++t) {
+                const int ii = i + tap_dy(t), jj = j + tap_dx(t);
+                const bool ok = valid && ii >= 0 && jj >= 0 && jj < L;
+                sX[t][tid] = ok ? (bf16)(float)x[(int64_t)b * N + ii * L + jj] : (bf16)0.f;
+            }
+            sX[4][tid] = valid ? (bf16)1.f : (bf16)0.f;
+        }
+        __syncthreads();
+#pragma unroll
+        for (int q = 0; q < 2; ++q) {
+            const int nt = wave + 4 * q;
+            if (nt < NT) {
+#pragma unroll
+                for (int ks = 0; ks < 2; ++ks) {
+                    const bf16x8 av = *(const bf16x8 *)&sX[r][ks * 32 + kq * 8];
+                    const bf16x8 bh = *(const bf16x8 *)&sDh[nt * 16 + r][ks * 32 + kq * 8];
+                    const bf16x8 bl = *(const bf16x8 *)&sDl[nt * 16 + r][ks * 32 + kq * 8];
+                    acc[q] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(av, bh, acc[q], 0, 0, 0);
+                    acc[q] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(av, bl, acc[q], 0, 0, 0);
+                }
+            }
+        }
+    }
+    float *out = partial + (int64_t)blockIdx.x * pstride;
+#pragma unroll
+    for (int q = 0; q < 2; ++q) {
+        const int nt = wave + 4 * q;
+        if (nt < NT) {
+            const int c = nt * 16 + r;
+#pragma unroll
+            for (int e = 0; e < 4; ++e) {
+                const int row = kq * 4 + e; // 0..3: taps, 4: bias
+                if (row < 4)
+                    out[pl.W1 + row * C + c] = acc[q][e];
+                else if (row == 4)
+                    out[pl.b1 + c] = acc[q][e];
+            }
+        }
     }
 }
 
-__global__ __launch_bounds__(256) void k_fill_f32(float *p, int64_t n, float v)
+// grad[e] = sum over workgroups g = 0, 1, .. of partial[g][e] (in that
+// order); the last slot is the loss.
+__global__ __launch_bounds__(256) void k_reduce_partials(const float *__restrict__ partial,
+                                                         int64_t pstride, int nblk, int64_t P,
+                                                         float *__restrict__ grad,
+                                                         float *__restrict__ loss)
 {
-    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (i < n)
-        p[i] = v;
+    const int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (e > P)
+        return;
+    float s = 0.f;
+    for (int g = 0; g < nblk; ++g)
+        s += partial[(int64_t)g * pstride + e];
+    if (e < P)
+        grad[e] = s;
+    else
+        *loss = s;
 }
 
 // Adam (Kingma and Ba 2015) on the float32 master parameters.
@@ -758,10 +971,19 @@ __global__ __launch_bounds__(256) void k_spins_observables(const int8_t *__restr
     }
 }
 
-// Independence Metropolis-Hastings step per chain, in float32:
-//   log A = beta J (bond' - bond) + log q(x) - log q(x'),
+// Independence Metropolis-Hastings step per chain, in float32 with every
+// operation rounded on its own:
+//   log A = ((beta J * float(bond' - bond)) + log q(x)) - log q(x'),
 // accepted iff log A >= 0 or u < exp(log A), u a 24-bit uniform of Philox
-// domain 2 (counter (stream<<8 | 2<<4, round lo, round hi, 0)).
+// domain 2 (counter (stream<<8 | 2<<4, round lo, round hi, 0), word 0).
+__device__ __forceinline__ float mh_log_ratio(float betaJ, int64_t dB, float lq_cur, float lq_prop)
+{
+#pragma clang fp contract(off)
+    const float e = betaJ * (float)dB;
+    const float s = e + lq_cur;
+    return s - lq_prop;
+}
+
 __global__ __launch_bounds__(256) void k_mh(int N, int8_t *__restrict__ state,
                                             float *__restrict__ logq_cur,
                                             int64_t *__restrict__ bond_cur,
@@ -775,7 +997,7 @@ __global__ __launch_bounds__(256) void k_mh(int N, int8_t *__restrict__ state,
     __shared__ int acc;
     const int c = blockIdx.x;
     if (threadIdx.x == 0) {
-        const float log_a = betaJ[c] * (float)(bond_prop[c] - bond_cur[c]) + logq_cur[c] - logq_prop[c];
+        const float log_a = mh_log_ratio(betaJ[c], bond_prop[c] - bond_cur[c], logq_cur[c], logq_prop[c]);
         const Block u = philox4x32_10(ctr_word0(stream_base + (uint32_t)c, 2u, 0u), round_lo,
                                       round_hi, 0u, key0, key1);
         const float uf = (float)(u.x0 >> 8) * (1.f / 16777216.f);
@@ -798,7 +1020,8 @@ static inline uint32_t nblocks(int64_t n, int per) { return (uint32_t)((n + per 
 hipError_t launch_pack(const NetDev &net, hipStream_t s)
 {
     const int64_t total = param_layout(net.C).total;
-    hipLaunchKernelGGL(k_pack, dim3(nblocks(total, 256)), dim3(256), 0, s, net);
+    const int64_t n = total > 16 * 5 * net.C ? total : 16 * 5 * net.C;
+    hipLaunchKernelGGL(k_pack, dim3(nblocks(n, 256)), dim3(256), 0, s, net);
     return hipGetLastError();
 }
 
@@ -807,7 +1030,8 @@ hipError_t launch_forward(const NetDev &net, const int8_t *x, int B, bf16 *const
 {
     const int64_t rows = (int64_t)B * net.N;
     const ParamLayout pl = param_layout(net.C);
-    hipLaunchKernelGGL(k_l1_fwd, dim3(nblocks(rows, 256)), dim3(256), 0, s, net, x, h[1], rows);
+    hipLaunchKernelGGL(k_l1_fwd, dim3(nblocks(rows * (net.C / 8), 256)), dim3(256), 0, s, net, x, h[1],
+                       rows);
     const uint32_t tiles = nblocks(rows, 16);
     for (int l = 2; l <= 5; ++l) {
         if (net.C == 32)
@@ -817,73 +1041,141 @@ hipError_t launch_forward(const NetDev &net, const int8_t *x, int B, bf16 *const
             hipLaunchKernelGGL(k_conv_fwd<64>, dim3(nblocks(tiles, 4)), dim3(256), 0, s, h[l - 1],
                                h[l], net.wf[l], net.params + pl.b[l], net.L, net.N, rows);
     }
-    hipLaunchKernelGGL(k_l6_fwd, dim3(nblocks(rows, 256)), dim3(256), 0, s, net, h[5], logits, rows);
+    if (net.C == 32)
+        hipLaunchKernelGGL(k_l6_fwd<32>, dim3(nblocks(tiles, 4)), dim3(256), 0, s, net, h[5], logits, rows);
+    else
+        hipLaunchKernelGGL(k_l6_fwd<64>, dim3(nblocks(tiles, 4)), dim3(256), 0, s, net, h[5], logits, rows);
     if (logq)
-        hipLaunchKernelGGL(k_logq, dim3(nblocks(B, 256)), dim3(256), 0, s, x, logits, net.N, B, logq);
+        hipLaunchKernelGGL(k_logq, dim3(nblocks(B, 4)), dim3(256), 0, s, x, logits, net.N, B, logq);
     return hipGetLastError();
 }
 
-hipError_t launch_sample(const NetDev &net, int B, bf16 *const h[6], int8_t *x, float *logq,
+size_t lds_limit()
+{
+    static size_t limit = 0;
+    if (!limit) {
+        int dev = 0, v = 0;
+        if (hipGetDevice(&dev) == hipSuccess &&
+            hipDeviceGetAttribute(&v, hipDeviceAttributeMaxSharedMemoryPerBlock, dev) == hipSuccess && v > 0)
+            limit = (size_t)v;
+        else
+            limit = 64 * 1024;
+    }
+    return limit;
+}
+
+int sampler_waves(int L)
+{
+    const int sites = (L + 1) / 2; // longest anti-diagonal
+    return sites <= 16 ? 1 : sites <= 32 ? 2 : 4;
+}
+
+template <int C, int W>
+static hipError_t launch_sample_cw(const NetDev &net, int B, int8_t *x, float *zout, float *logq,
+                                   uint64_t seed, uint32_t stream_base, uint64_t round, size_t lds,
+                                   hipStream_t s)
+{
+    static size_t allowed = 0; // dynamic LDS granted to this instance so far
+    if (lds > allowed) {
+        const hipError_t e = hipFuncSetAttribute((const void *)k_sample<C, W>,
+                                                 hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+        if (e != hipSuccess) {
+            (void)hipGetLastError(); // leave no sticky error behind for later calls
+            return e;
+        }
+        allowed = lds;
+    }
+    hipLaunchKernelGGL((k_sample<C, W>), dim3(B), dim3(64 * W), lds, s, net, x, zout, logq,
+                       (uint32_t)seed, (uint32_t)(seed >> 32), stream_base, (uint32_t)round,
+                       (uint32_t)(round >> 32));
+    return hipGetLastError();
+}
+
+bool sampler_supported(int L, int C)
+{
+    // dynamic ring and spins, plus the kernel's static logits of one diagonal
+    return L <= kSamplerMaxL &&
+           sampler_lds_bytes(L, C) + 16 * sampler_waves(L) * sizeof(float) <= lds_limit();
+}
+
+hipError_t launch_sample(const NetDev &net, int B, int8_t *x, float *zout, float *logq,
                          uint64_t seed, uint32_t stream_base, uint64_t round, hipStream_t s)
 {
-    const uint32_t grid = nblocks(B, 16);
-    if (net.C == 32)
-        hipLaunchKernelGGL(k_sample<32>, dim3(grid), dim3(64), 0, s, net, h[1], h[2], h[3], h[4],
-                           h[5], x, logq, B, (uint32_t)seed, (uint32_t)(seed >> 32), stream_base,
-                           (uint32_t)round, (uint32_t)(round >> 32));
-    else
-        hipLaunchKernelGGL(k_sample<64>, dim3(grid), dim3(64), 0, s, net, h[1], h[2], h[3], h[4],
-                           h[5], x, logq, B, (uint32_t)seed, (uint32_t)(seed >> 32), stream_base,
-                           (uint32_t)round, (uint32_t)(round >> 32));
-    return hipGetLastError();
+    if (!sampler_supported(net.L, net.C))
+        return hipErrorInvalidValue;
+    const size_t lds = sampler_lds_bytes(net.L, net.C);
+    const int W = sampler_waves(net.L);
+    if (net.C == 32) {
+        if (W == 1)
+            return launch_sample_cw<32, 1>(net, B, x, zout, logq, seed, stream_base, round, lds, s);
+        if (W == 2)
+            return launch_sample_cw<32, 2>(net, B, x, zout, logq, seed, stream_base, round, lds, s);
+        return launch_sample_cw<32, 4>(net, B, x, zout, logq, seed, stream_base, round, lds, s);
+    }
+    if (W == 1)
+        return launch_sample_cw<64, 1>(net, B, x, zout, logq, seed, stream_base, round, lds, s);
+    if (W == 2)
+        return launch_sample_cw<64, 2>(net, B, x, zout, logq, seed, stream_base, round, lds, s);
+    return launch_sample_cw<64, 4>(net, B, x, zout, logq, seed, stream_base, round, lds, s);
 }
 
 hipError_t launch_backward(const NetDev &net, const int8_t *x, int B, bf16 *const h[6],
-                           const float *logits, float *dlogit, bf16 *dpre_a, bf16 *dpre_b,
-                           float *grad, float *loss, hipStream_t s)
+                           const float *logits, float *dlogit, float *dpre_a, float *dpre_b,
+                           float *partial, float *grad, float *loss, hipStream_t s)
 {
     const int64_t rows = (int64_t)B * net.N;
     const int C = net.C;
     const ParamLayout pl = param_layout(C);
-    hipLaunchKernelGGL(k_fill_f32, dim3(nblocks(pl.total, 256)), dim3(256), 0, s, grad, pl.total, 0.f);
-    hipLaunchKernelGGL(k_fill_f32, dim3(1), dim3(64), 0, s, loss, (int64_t)1, 0.f);
-    hipLaunchKernelGGL(k_dlogit, dim3(nblocks(rows, 256)), dim3(256), 0, s, x, logits, dlogit, rows,
-                       1.f / (float)B, loss);
-    const int rpb = 1024;
-    hipLaunchKernelGGL(k_l6_wgrad, dim3(nblocks(rows, rpb)), dim3(256), 0, s, net, h[5], dlogit, rows,
-                       rpb, grad);
-    hipLaunchKernelGGL(k_l6_dgrad, dim3(nblocks(rows * C, 256)), dim3(256), 0, s, net, h[5], dlogit,
-                       dpre_a, rows);
-    bf16 *above = dpre_a, *below = dpre_b;
-    const int cpb = 16; // 64-row chunks per workgroup
+    const int64_t pstride = pl.total + 1;
+    const int64_t nchunks = (rows + 63) / 64;
+    const int nblk = (int)(nchunks < kGradBlocks ? nchunks : kGradBlocks);
+    const int64_t cpb = (nchunks + nblk - 1) / nblk;
     const uint32_t tiles = nblocks(rows, 16);
+    if (C == 32)
+        hipLaunchKernelGGL(k_l6_back<32>, dim3(nblk), dim3(256), 0, s, net, x, logits, h[5], dlogit,
+                           rows, nchunks, cpb, 1.f / (float)B, partial, pstride);
+    else
+        hipLaunchKernelGGL(k_l6_back<64>, dim3(nblk), dim3(256), 0, s, net, x, logits, h[5], dlogit,
+                           rows, nchunks, cpb, 1.f / (float)B, partial, pstride);
+    hipLaunchKernelGGL(k_l6_dgrad, dim3(nblocks(rows * (C / 8), 256)), dim3(256), 0, s, net, h[5],
+                       dlogit, dpre_a, rows);
+    float *above = dpre_a, *below = dpre_b;
     for (int l = 5; l >= 2; --l) {
         if (C == 32) {
-            hipLaunchKernelGGL(k_conv_wgrad<32>, dim3(nblocks(rows, 64 * cpb)), dim3(256), 0, s,
-                               h[l - 1], above, net.L, net.N, rows, cpb, grad + pl.W[l],
-                               grad + pl.b[l]);
+            hipLaunchKernelGGL(k_conv_wgrad<32>, dim3(nblk), dim3(256), 0, s, h[l - 1], above,
+                               net.L, net.N, rows, nchunks, cpb, partial + pl.W[l], partial + pl.b[l],
+                               pstride);
             hipLaunchKernelGGL(k_conv_dgrad<32>, dim3(nblocks(tiles, 4)), dim3(256), 0, s, above,
                                below, h[l - 1], net.wb[l], net.L, net.N, rows);
         } else {
-            hipLaunchKernelGGL(k_conv_wgrad<64>, dim3(nblocks(rows, 64 * cpb)), dim3(256), 0, s,
-                               h[l - 1], above, net.L, net.N, rows, cpb, grad + pl.W[l],
-                               grad + pl.b[l]);
+            hipLaunchKernelGGL(k_conv_wgrad<64>, dim3(nblk), dim3(256), 0, s, h[l - 1], above,
+                               net.L, net.N, rows, nchunks, cpb, partial + pl.W[l], partial + pl.b[l],
+                               pstride);
             hipLaunchKernelGGL(k_conv_dgrad<64>, dim3(nblocks(tiles, 4)), dim3(256), 0, s, above,
                                below, h[l - 1], net.wb[l], net.L, net.N, rows);
         }
-        bf16 *tmp = above;
+        float *tmp = above;
         above = below;
         below = tmp;
     }
-    hipLaunchKernelGGL(k_l1_wgrad, dim3(nblocks(rows, rpb)), dim3(256), 0, s, net, x, above, rows,
-                       rpb, grad);
+    if (C == 32)
+        hipLaunchKernelGGL(k_l1_wgrad<32>, dim3(nblk), dim3(256), 0, s, net, x, above, rows, nchunks,
+                           cpb, partial, pstride);
+    else
+        hipLaunchKernelGGL(k_l1_wgrad<64>, dim3(nblk), dim3(256), 0, s, net, x, above, rows, nchunks,
+                           cpb, partial, pstride);
+    hipLaunchKernelGGL(k_reduce_partials, dim3(nblocks(pl.total + 1, 256)), dim3(256), 0, s, partial,
+                       pstride, nblk, pl.total, grad, loss);
     return hipGetLastError();
 }
 
 hipError_t launch_adam(float *params, const float *grad, float *m, float *v, int64_t n, float lr,
                        float beta1, float beta2, float eps, int64_t step, hipStream_t s)
 {
-    const float bc1 = 1.f - powf(beta1, (float)step), bc2 = 1.f - powf(beta2, (float)step);
+    // bias corrections of the float32 constants, formed in double (1 - beta^t
+    // cancels badly in float32 for beta2 near 1)
+    const float bc1 = (float)(1.0 - pow((double)beta1, (double)step));
+    const float bc2 = (float)(1.0 - pow((double)beta2, (double)step));
     hipLaunchKernelGGL(k_adam, dim3(nblocks(n, 256)), dim3(256), 0, s, params, grad, m, v, n, lr,
                        beta1, beta2, eps, bc1, bc2);
     return hipGetLastError();

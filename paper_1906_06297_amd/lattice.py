@@ -401,6 +401,22 @@ class ARNet:
                                                     _stream_handle(stream)))
         return loss, grad
 
+    def gradient_at(self, spins, acts, logits, stream=None):
+        """(loss, gradient) of the backward pass at given forward values:
+        acts a bfloat16 device tensor [5, B, L, L, C] (layers 1..5, post-ReLU),
+        logits a float32 device tensor [B, L, L]."""
+        B = self._check_spins(spins)
+        assert acts.dtype == torch.bfloat16 and acts.is_contiguous()
+        assert acts.numel() == 5 * B * self.L * self.L * self.C
+        assert logits.dtype == torch.float32 and logits.is_contiguous()
+        assert logits.numel() == B * self.L * self.L
+        grad = torch.empty(self.P, dtype=torch.float32, device=self.device)
+        loss = torch.empty(1, dtype=torch.float32, device=self.device)
+        _lib.check(_lib.load().ising_arnet_gradient_at(self._h, _ptr(spins), B, _ptr(acts),
+                                                       _ptr(logits), _ptr(grad), _ptr(loss),
+                                                       _stream_handle(stream)))
+        return loss, grad
+
     def train_step(self, spins, lr: float, loss=None, stream=None):
         B = self._check_spins(spins)
         if loss is None:
@@ -408,6 +424,12 @@ class ARNet:
         _lib.check(_lib.load().ising_arnet_train_step(self._h, _ptr(spins), B, float(lr), _ptr(loss),
                                                       _stream_handle(stream)))
         return loss
+
+    def adam(self, grad, lr: float, stream=None) -> None:
+        """One Adam step on the master parameters with a caller's gradient
+        (device float32 tensor of num_params entries)."""
+        assert grad.dtype == torch.float32 and grad.is_contiguous() and grad.numel() == self.P
+        _lib.check(_lib.load().ising_arnet_adam(self._h, _ptr(grad), float(lr), _stream_handle(stream)))
 
     def sample(self, B: int, seed: int, stream_base: int = 0, round: int = 0, out=None,
                logq=None, stream=None):

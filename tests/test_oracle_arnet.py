@@ -226,3 +226,34 @@ def test_mh_decisions_rule_and_frequency():
     acc, _ = arnet.mh_decisions(np.zeros(8), np.full(8, -400), np.zeros(8), np.zeros(8),
                                 np.full(8, 0.25), seed=5, stream_base=0, rnd=3)
     assert not acc.any()  # A = e^-100
+
+
+
+def test_backward_from_given_activations_is_the_backward_pass():
+    """backward_from on the forward pass's own logits and activations is
+    nll_and_grad; on other activations its W6 and b6 parts are the plain
+    contractions of the definition (spot-checked by brute force)."""
+    C, L, B = 3, 5, 4
+    th = arnet.init_params(C, 41, scale=1.1) + np.random.default_rng(42).normal(0, 0.1, arnet.num_params(C))
+    x = rand_spins(B, L, 43)
+    z, acts = arnet.forward(x, th, C, emulate_bf16=True)
+    assert np.array_equal(arnet.backward_from(x, z, acts, th, C)[1],
+                          arnet.nll_and_grad(x, th, C, emulate_bf16=True)[1])
+    rng = np.random.default_rng(44)
+    acts2 = [np.maximum(rng.normal(size=a.shape), 0) for a in acts]
+    z2 = rng.normal(size=z.shape)
+    nll, g = arnet.backward_from(x, z2, acts2, th, C)
+    dl = -x / (1 + np.exp(x * z2)) / B
+    gW6 = arnet.unflatten(g, C)["W6"]
+    for t, (dy, dx) in enumerate(arnet.TAPS):
+        want = np.zeros(C)
+        for b in range(B):
+            for i in range(L):
+                for j in range(L):
+                    if 0 <= i + dy < L and 0 <= j + dx < L:
+                        want += acts2[4][b, i + dy, j + dx] * dl[b, i, j]
+        assert np.allclose(gW6[t], want, rtol=1e-12, atol=1e-15)
+    assert abs(float(arnet.unflatten(g, C)["b6"]) - dl.sum()) < 1e-14
+    assert abs(nll - np.logaddexp(0, -x * z2).sum() / B) < 1e-12
+    G = arnet.grad_abs_from(x, z2, acts2, th, C)
+    assert np.all(np.abs(g) <= G * (1 + 1e-12) + 1e-300)
