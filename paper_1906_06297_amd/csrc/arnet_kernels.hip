@@ -412,15 +412,16 @@ struct SamplerRows { // tile row -> (configuration, index on the diagonal)
     }
 };
 
+// Post-ReLU bf16 activation into the ring: `slot[q]` is the ring entry of
+// this lane's output row kq*4 + q, `bias[n]` the bias of its column n*16 + r.
 template <int C>
-struct EpiRing { // post-ReLU bf16 activation into the ring
-    bf16 *ring;
-    const float *bias;
-    int R, i_lo, t, layer;
-    __device__ void operator()(int, int64_t, int s, int col, float v) const
+struct EpiRing {
+    bf16 *const (&slot)[4];
+    const float (&bias)[C / 16];
+    int layer;
+    __device__ void operator()(int row, int64_t, int, int col, float v) const
     {
-        const int i = i_lo + s, j = t - 2 * i;
-        ring[(((i % R) * 4 + (j & 3)) * 5 + layer) * C + col] = (bf16)fmaxf(v + bias[col], 0.f);
+        slot[row & 3][layer * C + col] = (bf16)fmaxf(v + bias[col >> 4], 0.f);
     }
 };
 
@@ -434,6 +435,18 @@ struct EpiZ { // logit of the diagonal's site s
     }
 };
 
+// Orders LDS accesses between the steps of the sampler: a wavefront's own
+// LDS operations complete in order, so one wavefront needs only the fence;
+// several meet at a barrier.  Global stores are not waited for.
+template <int W>
+__device__ __forceinline__ void lds_sync()
+{
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup", "local");
+    if (W > 1)
+        __builtin_amdgcn_s_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup", "local");
+}
+
 template <int C, int W>
 __global__ __launch_bounds__(64 * W) void k_sample(NetDev net, int8_t *__restrict__ x,
                                                    float *__restrict__ zout, float *__restrict__ logq,
@@ -445,13 +458,13 @@ __global__ __launch_bounds__(64 * W) void k_sample(NetDev net, int8_t *__restric
     constexpr bool kRegW = C == 32; // the five layers' weights fit in registers
     extern __shared__ __align__(16) unsigned char smem[];
     __shared__ float zs[16 * W];
+    __shared__ float w1s[4 * C], b1s[C];
     const int L = net.L, N = net.N, R = sampler_ring_rows(L);
     bf16 *ring = (bf16 *)smem; // [R][4][5][C]
     int8_t *sp = (int8_t *)(smem + (size_t)R * 4 * 5 * C * sizeof(bf16));
     const int64_t b = blockIdx.x;
     const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63, r = lane & 15, kq = lane >> 4;
     const ParamLayout pl = param_layout(C);
-    const float *b1 = net.params + pl.b1;
     const float b6 = net.params[pl.b6];
     WeightsRegs<32, 32> wreg[kRegW ? 4 : 1];
     WeightsRegs<32, 16> w6reg;
@@ -461,10 +474,21 @@ __global__ __launch_bounds__(64 * W) void k_sample(NetDev net, int8_t *__restric
             wreg[l - 2].load(net.wf[l]);
         w6reg.load(net.w6p);
     }
+    float bias[4][C / 16]; // layers 2..5, this lane's output columns
+#pragma unroll
+    for (int l = 2; l <= 5; ++l)
+#pragma unroll
+        for (int n = 0; n < C / 16; ++n)
+            bias[l - 2][n] = net.params[pl.b[l] + n * 16 + r];
+    for (int e = threadIdx.x; e < 4 * C; e += 64 * W)
+        w1s[e] = net.w1[e];
+    for (int e = threadIdx.x; e < C; e += 64 * W)
+        b1s[e] = net.params[pl.b1 + e];
     for (int e = threadIdx.x; e < N; e += 64 * W)
         sp[e] = 0;
     __syncthreads();
     const int steps = 3 * L - 2;
+    // ring row of i: i mod R, carried along with i (i_lo never decreases)
     for (int t = 0; t < steps; ++t) {
         const int i_lo = t > L - 1 ? (t - L + 2) >> 1 : 0;
         const int i_hi = (t >> 1) < L - 1 ? (t >> 1) : L - 1;
@@ -473,6 +497,7 @@ __global__ __launch_bounds__(64 * W) void k_sample(NetDev net, int8_t *__restric
         const int s = 16 * wave + r;
         const bool valid = s < nsites;
         const int i = i_lo + s, j = t - 2 * i;
+        const int ri = valid ? i % R : 0, rup = ri == 0 ? R - 1 : ri - 1; // ring rows of i, i-1
         // layer 1 (mask A) at the row's site, 8 channels per 16-byte group
         if (valid) {
             float xv[4];
@@ -482,27 +507,35 @@ __global__ __launch_bounds__(64 * W) void k_sample(NetDev net, int8_t *__restric
                 xv[tt] = (i > 0 && jj >= 0 && jj < L) ? (float)sp[(i - 1) * L + jj] : 0.f;
             }
             xv[3] = j > 0 ? (float)sp[i * L + j - 1] : 0.f;
-            bf16 *dst = ring + (((i % R) * 4 + (j & 3)) * 5 + 0) * C;
+            bf16 *dst = ring + ((ri * 4 + (j & 3)) * 5 + 0) * C;
 #pragma unroll
             for (int g = 0; g < KC; ++g) {
                 const int c0 = (kq * KC + g) * 8;
                 bf16x8 v;
 #pragma unroll
                 for (int e = 0; e < 8; ++e)
-                    v[e] = (bf16)l1_from(xv, net.w1, b1, C, c0 + e);
+                    v[e] = (bf16)l1_from(xv, w1s, b1s, C, c0 + e);
                 *(bf16x8 *)(dst + c0) = v;
             }
         }
-        __syncthreads();
-        // ring rows of the five taps of this lane's site
+        // ring entries of the five taps of this lane's row, and of the four
+        // output rows this lane writes in the epilogues
         const bf16 *tap_base[5];
         bool tap_ok[5];
 #pragma unroll
         for (int tt = 0; tt < 5; ++tt) {
-            const int ii = i + tap_dy(tt), jj = j + tap_dx(tt);
-            tap_ok[tt] = valid && ii >= 0 && jj >= 0 && jj < L;
-            tap_base[tt] = ring + (((tap_ok[tt] ? ii % R : 0) * 4 + (jj & 3)) * 5) * C + kq * 8;
+            const int jj = j + tap_dx(tt);
+            tap_ok[tt] = valid && (tap_dy(tt) == 0 || i > 0) && jj >= 0 && jj < L;
+            tap_base[tt] = ring + (((tap_dy(tt) == 0 ? ri : rup) * 4 + (jj & 3)) * 5) * C + kq * 8;
         }
+        bf16 *slot[4];
+#pragma unroll
+        for (int q = 0; q < 4; ++q) {
+            const int so = 16 * wave + kq * 4 + q;
+            const int io = i_lo + so, jo = t - 2 * io;
+            slot[q] = ring + (((so < nsites ? io % R : 0) * 4 + (jo & 3)) * 5) * C;
+        }
+        lds_sync<W>();
         const SamplerRows<C> rows{b, 16 * wave, nsites};
 #pragma unroll
         for (int l = 2; l <= 6; ++l) {
@@ -517,7 +550,7 @@ __global__ __launch_bounds__(64 * W) void k_sample(NetDev net, int8_t *__restric
                         zero8(a[tt][kc]);
                 }
             if (l <= 5) {
-                const EpiRing<C> epi{ring, net.params + pl.b[l], R, i_lo, t, l - 1};
+                const EpiRing<C> epi{slot, bias[l - 2], l - 1};
                 if constexpr (kRegW)
                     conv_mfma<C, C>(a, wreg[kRegW ? l - 2 : 0], rows, epi);
                 else
@@ -529,7 +562,7 @@ __global__ __launch_bounds__(64 * W) void k_sample(NetDev net, int8_t *__restric
                 else
                     conv_mfma<C, 16>(a, WeightsGlobal<C>{net.w6p}, rows, epi);
             }
-            __syncthreads();
+            lds_sync<W>();
         }
         // the draws of this wavefront's sites
         if (lane < 16 && valid) {
@@ -545,8 +578,9 @@ __global__ __launch_bounds__(64 * W) void k_sample(NetDev net, int8_t *__restric
             x[b * N + p] = xv;
             zout[b * N + p] = z;
         }
-        __syncthreads();
+        lds_sync<W>();
     }
+    __syncthreads(); // the logits in `zout` of every wavefront
     if (wave == 0) {
         const double lq = config_logq(zout + b * N, sp, N);
         if (lane == 0)
