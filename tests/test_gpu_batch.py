@@ -151,6 +151,37 @@ def test_long_run_sample(gpu, orc, workload):
     b.close()
 
 
+@pytest.mark.timeout(1200)
+def test_batched_workload_full_length_every_lattice(gpu, orc, workload):
+    """The batched workload as the benchmark runs it -- tiles autotuned for the
+    whole batch, 10^4 sweeps in one captured-graph replay from a fresh start --
+    every one of the 1024 lattices bit for bit against the oracle (about 1.5e11
+    oracle updates: a few minutes on the host's threads)."""
+    Ls, betas, seeds, streams = workload
+    nsweeps = workloads.BATCHED["nsweeps"]
+    b = gpu.Batch(Ls, betas, 1.0, seeds, streams)
+    say("batch of 1024: autotune, then 10^4 sweeps")
+    b.autotune(200, None)
+    b.init()
+    b.set_counter(0)
+    b.sweep(nsweeps)
+    got = [batch_words_of(b, q) for q in range(len(Ls))]
+    assert b.counter() == nsweeps
+    b.close()
+    say(f"oracle: 1024 lattices x {nsweeps} sweeps on {orc.max_threads()} threads")
+    # in chunks of lattices (each a parallel oracle run), reporting as it goes
+    bad = []
+    order = np.argsort(-np.asarray(Ls), kind="stable")  # large lattices spread over chunks
+    for c in range(16):
+        pick = order[c::16]
+        ref = oracle_batch(orc, *(np.asarray(a)[pick] for a in (Ls, betas)), 1.0,
+                           *(np.asarray(a)[pick] for a in (seeds, streams)), nsweeps)
+        bad += [int(q) for k, q in enumerate(pick) if not np.array_equal(got[q], pack(ref[k]))]
+        say(f"  oracle chunk {c + 1}/16 done, {len(bad)} mismatches so far")
+    say(f"{len(Ls) - len(bad)} of {len(Ls)} lattices bit-exact")
+    assert not bad, bad[:10]
+
+
 def test_autotune_keeps_results_and_writes_cache(gpu, orc, tmp_path):
     Ls = [16] * 40 + [96] * 6 + [256] * 3
     n = len(Ls)
