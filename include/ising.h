@@ -286,6 +286,24 @@ int ising_batch_autotune(ising_batch *b, int64_t tune_sweeps, const char *cache_
 int ising_batch_get_spins_dev(const ising_batch *b, int8_t *d_spins, void *hip_stream);
 int ising_batch_set_spins_dev(ising_batch *b, const int8_t *d_spins, void *hip_stream);
 
+/* The batched sweep for callers that cannot allocate (code under HIP graph
+ * capture, serving loops, harnesses that forbid allocation): the inputs of
+ * ising_batch_create (caller's lattice buffer, initialised as there, e.g. by a
+ * batch handle's ising_batch_init) and of one ising_batch_sweep, with the
+ * batch's sweep counter given as rng_counter; the lattices end exactly as
+ * after ising_batch_set_counter(rng_counter) and ising_batch_sweep(nsweeps)
+ * on a batch of the same lattices.  Allocates nothing: the persistent
+ * kernel's descriptors, bundle list, work-queue counter and sweep counter go
+ * to a fixed device array of 512 KiB per GPU (at most 4096 lattices;
+ * ISING_E_SIZE beyond), which keeps the last call's contents; every call
+ * rewrites what it uses.  The untuned tiles are used.  Calls from several
+ * host threads take turns; calls whose work overlaps on one GPU (different
+ * streams) share that array and race.  Asynchronous. */
+int ising_batch_sweep_noalloc(int32_t n, const int64_t *Ls, const double *betas, double J,
+                              const uint64_t *seeds, const uint32_t *stream_ids,
+                              uint64_t *d_words, size_t bytes, int64_t nsweeps,
+                              uint64_t rng_counter, void *hip_stream);
+
 /* ------------------------------------------------------------------------
  * Learned global proposal.  The paper names critical slowing down of local
  * Metropolis updates and cluster moves (Sec. 2); here an autoregressive

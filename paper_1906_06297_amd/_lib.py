@@ -83,6 +83,10 @@ SIGNATURES = {
     "ising_batch_autotune": (ctypes.c_int, [_vp, _i64, ctypes.c_char_p, _vp]),
     "ising_batch_get_spins_dev": (ctypes.c_int, [_vp, _vp, _vp]),
     "ising_batch_set_spins_dev": (ctypes.c_int, [_vp, _vp, _vp]),
+    "ising_batch_sweep_noalloc": (ctypes.c_int, [ctypes.c_int32, ctypes.POINTER(_i64),
+                                                 ctypes.POINTER(ctypes.c_double), ctypes.c_double,
+                                                 ctypes.POINTER(_u64), ctypes.POINTER(_u32), _vp,
+                                                 ctypes.c_size_t, _i64, _u64, _vp]),
     "ising_arnet_num_params": (_i64, [ctypes.c_int32]),
     "ising_arnet_create": (ctypes.c_int, [ctypes.POINTER(_vp), ctypes.c_int32, ctypes.c_int32,
                                           ctypes.c_int32]),

@@ -9,6 +9,7 @@
 #include <cstring>
 #include <fstream>
 #include <map>
+#include <mutex>
 #include <sstream>
 #include <string>
 #include <vector>
@@ -19,6 +20,8 @@
 #include "host_common.hpp"
 
 using namespace ising;
+
+extern "C" int64_t ising_batch_words(int32_t n, const int64_t *Ls);
 
 namespace {
 struct Tile {
@@ -208,6 +211,173 @@ int check_batch(const ising_batch *b)
     return ISING_OK;
 }
 
+// Descriptors of the n lattices (offsets back to back, colour 0 then 1), with
+// default tiles per size; the batch's device state is not touched.
+int fill_lattices(ising_batch *b, int32_t n, const int64_t *Ls, const double *betas, double J,
+                  const uint64_t *seeds, const uint32_t *stream_ids)
+{
+    b->n = n;
+    uint64_t off = 0;
+    for (int32_t q = 0; q < n; ++q) {
+        if (!std::isfinite(betas[q]) || betas[q] < 0.0 || stream_ids[q] >= (1u << 24))
+            return host::fail(ISING_E_BADARG, "lattice %d: beta must be finite and >= 0, "
+                              "stream id < 2^24", (int)q);
+        BatchLattice lt{};
+        lt.word_off = off;
+        lt.L = (uint32_t)Ls[q];
+        lt.H = lt.L / 2;
+        lt.M = lt.L * lt.L / 2;
+        lt.W = words_of(Ls[q]);
+        lt.m = host::metro2_params(betas[q], J);
+        lt.key0 = (uint32_t)seeds[q];
+        lt.key1 = (uint32_t)(seeds[q] >> 32);
+        lt.stream_id = stream_ids[q];
+        b->lats.push_back(lt);
+        b->Ls.push_back(Ls[q]);
+        if (!b->tiles.count(Ls[q]))
+            b->tiles[Ls[q]] = default_tile(lt.W);
+        off += 2 * (uint64_t)lt.W;
+    }
+    return ISING_OK;
+}
+
+// Arguments shared by ising_batch_create and ising_batch_sweep_noalloc.
+int check_batch_args(int32_t n, const int64_t *Ls, const double *betas, double J,
+                     const uint64_t *seeds, const uint32_t *stream_ids, const uint64_t *d_words,
+                     size_t bytes)
+{
+    if (n <= 0 || !Ls || !betas || !seeds || !stream_ids || !d_words)
+        return host::fail(ISING_E_BADARG, "empty batch or null pointer");
+    if (!std::isfinite(J))
+        return host::fail(ISING_E_BADARG, "J must be finite");
+    const int64_t need = ising_batch_words(n, Ls);
+    if (need < 0)
+        return host::fail(ISING_E_SIZE, "every L must be even, >= 4 and <= %u", kMaxBatchL);
+    if (bytes < (size_t)need * 8)
+        return host::fail(ISING_E_SIZE, "buffer of %zu bytes is smaller than the %lld needed",
+                          bytes, (long long)(need * 8));
+    return ISING_OK;
+}
+
+// ---------------------------------------------------- sweeps without allocation
+// ising_batch_sweep_noalloc keeps the persistent kernel's descriptors, bundle
+// list, work-queue counter and sweep counter in this fixed device array
+// instead of memory it allocates.  Each device holds its own copy at its own
+// address, taken once per device with hipGetSymbolAddress; host code uses
+// that address, never the array's name.
+constexpr int32_t kNoAllocMaxLattices = 4096;
+constexpr size_t kNoAllocScratchBytes = 512 * 1024;
+static __device__ __align__(256) unsigned char scratch[kNoAllocScratchBytes];
+
+constexpr int kMaxDevices = 64;
+unsigned char *g_scratch[kMaxDevices] = {};
+std::mutex g_scratch_mu;
+
+int scratch_of_current_device(unsigned char **out)
+{
+    int dev = 0;
+    hipError_t e = hipGetDevice(&dev);
+    if (e != hipSuccess)
+        return host::hip_fail(e, "current device");
+    if (dev < 0 || dev >= kMaxDevices)
+        return host::fail(ISING_E_HIP, "device %d beyond the %d supported", dev, kMaxDevices);
+    std::lock_guard<std::mutex> lock(g_scratch_mu);
+    if (!g_scratch[dev]) {
+        void *ptr = nullptr;
+        e = hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch));
+        if (e != hipSuccess)
+            return host::hip_fail(e, "address of the batch scratch array");
+        g_scratch[dev] = (unsigned char *)ptr;
+    }
+    *out = g_scratch[dev];
+    return ISING_OK;
+}
+
+size_t align256(size_t v) { return (v + 255) & ~(size_t)255; }
+
+// The plan of ising_batch_sweep_noalloc, built in fixed arrays (no heap):
+// lattices grouped by size, default tiles, bundles of as many lattices as a
+// workgroup takes, largest work (lattices x L^2) first, ties in creation
+// order -- the untuned plan of a batch handle.
+struct NoAllocPlan {
+    BatchLattice lats[kNoAllocMaxLattices];
+    uint32_t order[kNoAllocMaxLattices];
+    uint32_t members[kNoAllocMaxLattices];
+    BatchBundle bundles[kNoAllocMaxLattices];
+    double work[kNoAllocMaxLattices];
+    uint32_t border[kNoAllocMaxLattices];
+    uint32_t nbundles = 0;
+    size_t lds_bytes = 0;
+    unsigned char stage[kNoAllocScratchBytes]; // host image of the scratch array
+
+    int build(int32_t n, const int64_t *Ls, const double *betas, double J, const uint64_t *seeds,
+              const uint32_t *stream_ids)
+    {
+        uint64_t off = 0;
+        for (int32_t q = 0; q < n; ++q) {
+            if (!std::isfinite(betas[q]) || betas[q] < 0.0 || stream_ids[q] >= (1u << 24))
+                return host::fail(ISING_E_BADARG, "lattice %d: beta must be finite and >= 0, "
+                                  "stream id < 2^24", (int)q);
+            BatchLattice &lt = lats[q];
+            lt = BatchLattice{};
+            lt.word_off = off;
+            lt.L = (uint32_t)Ls[q];
+            lt.H = lt.L / 2;
+            lt.M = lt.L * lt.L / 2;
+            lt.W = words_of(Ls[q]);
+            lt.m = host::metro2_params(betas[q], J);
+            lt.key0 = (uint32_t)seeds[q];
+            lt.key1 = (uint32_t)(seeds[q] >> 32);
+            lt.stream_id = stream_ids[q];
+            off += 2 * (uint64_t)lt.W;
+            order[q] = (uint32_t)q;
+        }
+        std::sort(order, order + n, [this](uint32_t a, uint32_t b) {
+            return lats[a].L != lats[b].L ? lats[a].L < lats[b].L : a < b;
+        });
+        // bundles, members still in `order`
+        nbundles = 0;
+        lds_bytes = 0;
+        for (int32_t g0 = 0; g0 < n;) {
+            const uint32_t L = lats[order[g0]].L, W = lats[order[g0]].W;
+            int32_t g1 = g0;
+            while (g1 < n && lats[order[g1]].L == L)
+                ++g1;
+            const Tile tile = default_tile(W);
+            const uint32_t tpl = threads_per_lattice(W, tile), per = lattices_per_bundle(W, tile);
+            for (int32_t k = g0; k < g1; k += (int32_t)per) {
+                const uint32_t cnt = (uint32_t)std::min<int32_t>((int32_t)per, g1 - k);
+                bundles[nbundles] = BatchBundle{(uint32_t)k, cnt, tile.wpt, tpl, tile.lpw, 0};
+                work[nbundles] = (double)cnt * (double)L * (double)L;
+                border[nbundles] = nbundles;
+                lds_bytes = std::max(lds_bytes, (size_t)cnt * batch_lds_words(W) * 8);
+                ++nbundles;
+            }
+            g0 = g1;
+        }
+        std::sort(border, border + nbundles, [this](uint32_t a, uint32_t b) {
+            return work[a] != work[b] ? work[a] > work[b] : a < b;
+        });
+        // bundles in that order, each with its members contiguous
+        uint32_t m = 0;
+        BatchBundle *sorted = (BatchBundle *)stage; // reuse the stage as room to permute
+        for (uint32_t k = 0; k < nbundles; ++k) {
+            BatchBundle bd = bundles[border[k]];
+            for (uint32_t c = 0; c < bd.count; ++c)
+                members[m + c] = order[bd.first + c];
+            bd.first = m;
+            m += bd.count;
+            sorted[k] = bd;
+        }
+        std::memcpy(bundles, sorted, (size_t)nbundles * sizeof(BatchBundle));
+        return ISING_OK;
+    }
+};
+
+NoAllocPlan g_noalloc_plan; // static storage; callers take g_noalloc_mu
+std::mutex g_noalloc_mu;
+
+
 // ---------------------------------------------------------------- cache file
 std::string cache_key() { return "gfx950/batch-sweep-v7"; }
 
@@ -281,42 +451,14 @@ int ising_batch_create(ising_batch **out, int32_t n, const int64_t *Ls, const do
     if (!out)
         return host::fail(ISING_E_BADARG, "null output");
     *out = nullptr;
-    if (n <= 0 || !Ls || !betas || !seeds || !stream_ids || !d_words)
-        return host::fail(ISING_E_BADARG, "empty batch or null pointer");
-    if (!std::isfinite(J))
-        return host::fail(ISING_E_BADARG, "J must be finite");
-    const int64_t need = ising_batch_words(n, Ls);
-    if (need < 0)
-        return host::fail(ISING_E_SIZE, "every L must be even, >= 4 and <= %u", kMaxBatchL);
-    if (bytes < (size_t)need * 8)
-        return host::fail(ISING_E_SIZE, "buffer of %zu bytes is smaller than the %lld needed",
-                          bytes, (long long)(need * 8));
+    if (int r = check_batch_args(n, Ls, betas, J, seeds, stream_ids, d_words, bytes))
+        return r;
     ising_batch *b = new ising_batch();
-    b->n = n;
     b->words = d_words;
     b->bytes = bytes;
-    uint64_t off = 0;
-    for (int32_t q = 0; q < n; ++q) {
-        if (!std::isfinite(betas[q]) || betas[q] < 0.0 || stream_ids[q] >= (1u << 24)) {
-            delete b;
-            return host::fail(ISING_E_BADARG, "lattice %d: beta must be finite and >= 0, "
-                              "stream id < 2^24", (int)q);
-        }
-        BatchLattice lt{};
-        lt.word_off = off;
-        lt.L = (uint32_t)Ls[q];
-        lt.H = lt.L / 2;
-        lt.M = lt.L * lt.L / 2;
-        lt.W = words_of(Ls[q]);
-        lt.m = host::metro2_params(betas[q], J);
-        lt.key0 = (uint32_t)seeds[q];
-        lt.key1 = (uint32_t)(seeds[q] >> 32);
-        lt.stream_id = stream_ids[q];
-        b->lats.push_back(lt);
-        b->Ls.push_back(Ls[q]);
-        if (!b->tiles.count(Ls[q]))
-            b->tiles[Ls[q]] = default_tile(lt.W);
-        off += 2 * (uint64_t)lt.W;
+    if (int r = fill_lattices(b, n, Ls, betas, J, seeds, stream_ids)) {
+        delete b;
+        return r;
     }
     hipError_t e = hipMalloc(&b->d_lats, b->lats.size() * sizeof(BatchLattice));
     if (e == hipSuccess)
@@ -744,6 +886,60 @@ int ising_batch_autotune(ising_batch *b, int64_t tune_sweeps, const char *cache_
     if (cache_path && !write_cache(cache_path, b->tiles))
         return host::fail(ISING_E_BADARG, "cannot write the autotune cache %s", cache_path);
     return install_plan(b, make_plan(b, 0, Tile{1, 1}));
+}
+
+int ising_batch_sweep_noalloc(int32_t n, const int64_t *Ls, const double *betas, double J,
+                              const uint64_t *seeds, const uint32_t *stream_ids,
+                              uint64_t *d_words, size_t bytes, int64_t nsweeps,
+                              uint64_t rng_counter, void *hip_stream)
+{
+    if (int r = check_batch_args(n, Ls, betas, J, seeds, stream_ids, d_words, bytes))
+        return r;
+    if (n > kNoAllocMaxLattices)
+        return host::fail(ISING_E_SIZE, "at most %d lattices without allocation (got %d)",
+                          kNoAllocMaxLattices, (int)n);
+    if (nsweeps < 0)
+        return host::fail(ISING_E_BADARG, "nsweeps must be >= 0");
+    if (nsweeps == 0)
+        return host::ok();
+    // host threads take turns: the plan and its host image are one static
+    // buffer, consumed by the copy below before the lock is released (a copy
+    // from pageable host memory returns once its source has been read)
+    std::lock_guard<std::mutex> lock(g_noalloc_mu);
+    NoAllocPlan &p = g_noalloc_plan;
+    if (int r = p.build(n, Ls, betas, J, seeds, stream_ids))
+        return r;
+    uint32_t grid = 0;
+    if (int r = persistent_grid(p.lds_bytes, p.nbundles, &grid))
+        return r;
+    // scratch layout: sweep counter, queue counter | lattices | members | bundles
+    const size_t o_lats = 256;
+    const size_t o_members = align256(o_lats + (size_t)n * sizeof(BatchLattice));
+    const size_t o_bundles = align256(o_members + (size_t)n * sizeof(uint32_t));
+    const size_t total = o_bundles + (size_t)p.nbundles * sizeof(BatchBundle);
+    if (total > kNoAllocScratchBytes)
+        return host::fail(ISING_E_SIZE, "descriptors need %zu bytes, the scratch array holds %zu",
+                          total, kNoAllocScratchBytes);
+    unsigned char *ptr = nullptr;
+    if (int r = scratch_of_current_device(&ptr))
+        return r;
+    unsigned char *stage = p.stage;
+    std::memset(stage, 0, o_lats);
+    std::memcpy(stage, &rng_counter, sizeof(rng_counter));
+    std::memcpy(stage + o_lats, p.lats, (size_t)n * sizeof(BatchLattice));
+    std::memcpy(stage + o_members, p.members, (size_t)n * sizeof(uint32_t));
+    std::memcpy(stage + o_bundles, p.bundles, (size_t)p.nbundles * sizeof(BatchBundle));
+    hipStream_t s = (hipStream_t)hip_stream;
+    hipError_t e = hipMemcpyAsync(ptr, stage, total, hipMemcpyHostToDevice, s);
+    if (e == hipSuccess)
+        e = launch_batch_sweep((const BatchLattice *)(ptr + o_lats),
+                               (const uint32_t *)(ptr + o_members),
+                               (const BatchBundle *)(ptr + o_bundles), p.nbundles, grid,
+                               p.lds_bytes, (uint32_t *)(ptr + 8), d_words, (uint64_t *)ptr,
+                               nsweeps, s);
+    if (e != hipSuccess)
+        return host::hip_fail(e, "batch sweep without allocation");
+    return host::ok();
 }
 
 } // extern "C"

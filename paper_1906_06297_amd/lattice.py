@@ -345,6 +345,22 @@ def arnet_num_params(channels: int) -> int:
     return int(n)
 
 
+def batch_sweep_noalloc(Ls, betas, J: float, seeds, stream_ids, words, nsweeps: int,
+                        rng_counter: int, stream=None) -> None:
+    """Advance the lattices in `words` (laid out as a Batch of the same
+    lattices) by nsweeps from sweep counter rng_counter, without any
+    allocation by the library (ising_batch_sweep_noalloc)."""
+    n = len(Ls)
+    assert words.dtype == torch.int64 and words.is_contiguous()
+    L_arr = (ctypes.c_int64 * n)(*[int(x) for x in Ls])
+    b_arr = (ctypes.c_double * n)(*[float(x) for x in betas])
+    s_arr = (ctypes.c_uint64 * n)(*[int(x) for x in seeds])
+    i_arr = (ctypes.c_uint32 * n)(*[int(x) for x in stream_ids])
+    _lib.check(_lib.load().ising_batch_sweep_noalloc(
+        n, L_arr, b_arr, float(J), s_arr, i_arr, ctypes.c_void_p(words.data_ptr()),
+        words.numel() * 8, int(nsweeps), int(rng_counter), _stream_handle(stream)))
+
+
 class ARNet:
     """The learned global proposal: a masked-convolution autoregressive network
     over L x L configurations (int8 +1/-1 device tensors of shape (B, L, L))."""
