@@ -353,39 +353,52 @@ def bench_matmul(ising, torch, steps: int, sizes=None) -> dict:
     return out
 
 
-def bench_hybrid64(ising, torch, sweeps: int) -> dict:
+def bench_hybrid64(ising, torch, sweeps: int, data_log2: int = 20, train_steps: int = 2000,
+                   batch: int = 128) -> dict:
     """The hybrid chain at L = 64: 16 betas in [0.40, 0.48] with 16 chains each,
-    a 64-channel network trained on plain-sampler configurations pooled over
-    those betas, one global move per 10 local sweeps, against independent
-    plain chains: E per site and Binder cumulant with jackknife errors,
-    tau_int(|m|) per measurement, and effective samples per second."""
+    a 64-channel network trained on 2^data_log2 plain-sampler configurations
+    pooled over those betas, one global move per 10 local sweeps, against
+    independent plain chains: E per site and Binder cumulant with jackknife
+    errors, tau_int(|m|) per measurement, acceptance, and effective samples
+    per second."""
     from paper_1906_06297_amd import hybrid
 
     L, C = 64, 64
     betas = np.linspace(0.40, 0.48, 16)
+    chains_data = 4096
     t0 = time.perf_counter()
-    data = hybrid.plain_configurations(L, betas, chains=256, snapshots=8, thin=100, burn=20000,
-                                       seed=61, stream_base=4096)
+    data = hybrid.plain_configurations(L, betas, chains=chains_data,
+                                       snapshots=(1 << data_log2) // chains_data, thin=10,
+                                       burn=20000, seed=61, stream_base=4096)
+    torch.cuda.synchronize()
+    t_data = time.perf_counter() - t0
     net = ising.ARNet(L, C, 256)
     try:
         net.set_params(hybrid.init_params(L, C, seed=3))
-        hist = hybrid.train(net, data, steps=300, batch=64, lr=2e-3, seed=4, log_every=100)
+        t0 = time.perf_counter()
+        hist = hybrid.train(net, data, steps=train_steps, batch=batch, lr=2e-3, seed=4,
+                            log_every=max(1, train_steps // 5))
         torch.cuda.synchronize()
         t_train = time.perf_counter() - t0
+        del data
         res = hybrid.compare_over_betas(net, L, betas, per_beta=16, sweeps=sweeps,
                                         sweeps_per_proposal=10, burn=20000, seed_plain=71,
                                         seed_hybrid=72)
     finally:
         net.close()
-    out = {"per_beta": [], "train_s": t_train, "train_nll_per_site": hist}
+    out = {"per_beta": [], "data_s": t_data, "train_s": t_train, "train_nll_per_site": hist}
     z = []
     for p, h in zip(res["plain"]["per_beta"], res["hybrid"]["per_beta"]):
         row = {"beta": p["beta"]}
         for kind, r in (("plain", p), ("hybrid", h)):
             row[kind] = {k: r[k] for k in ("E_per_site", "E_se", "binder", "binder_se",
                                            "tau_int_abs_m", "acceptance")}
-        for key, err in (("E_per_site", "E_se"), ("binder", "binder_se")):
-            z.append((h[key] - p[key]) / float(np.hypot(p[err], h[err])))
+        row["z_E"] = (h["E_per_site"] - p["E_per_site"]) / float(np.hypot(p["E_se"], h["E_se"]))
+        row["z_binder"] = (h["binder"] - p["binder"]) / float(np.hypot(p["binder_se"], h["binder_se"]))
+        z += [row["z_E"], row["z_binder"]]
+        row["learned_vs_plain"] = ("measured" if h["acceptance"] > 0 else
+                                   "unmeasured: no proposal accepted, the hybrid chain is the plain "
+                                   "chain at this beta")
         out["per_beta"].append(row)
     n_meas = res["plain"]["measurements"] * 16  # measurements x chains, per beta
     for kind in ("plain", "hybrid"):
@@ -393,9 +406,12 @@ def bench_hybrid64(ising, torch, sweeps: int) -> dict:
         out[f"{kind}_wall_s"] = res[kind]["wall_s"]
         out[f"{kind}_ess_per_s_abs_m"] = float(np.sum(n_meas / (2 * taus)) / res[kind]["wall_s"])
     out["max_abs_z"] = float(np.max(np.abs(z)))
-    out["workload"] = (f"L={L}, 16 betas in [0.40, 0.48] x 16 chains, {C}-channel net trained 300 "
-                       f"steps on 2048 pooled plain-sampler configurations; {sweeps} sweeps after "
-                       "20000 burn-in, a global move every 10 sweeps (hybrid) against plain chains")
+    out["betas_with_accepted_proposals"] = int(sum(r["hybrid"]["acceptance"] > 0
+                                                   for r in out["per_beta"]))
+    out["workload"] = (f"L={L}, 16 betas in [0.40, 0.48] x 16 chains, {C}-channel net trained "
+                       f"{train_steps} Adam steps (batch {batch}) on 2^{data_log2} plain-sampler "
+                       f"configurations pooled over the betas; {sweeps} sweeps after 20000 burn-in, a "
+                       "global move every 10 sweeps (hybrid) against independent plain chains")
     return out
 
 
@@ -429,8 +445,9 @@ def bench_learned(ising, torch, L: int = 32, betas=(0.42, 0.44, 0.46), C: int = 
         for name, use in (("plain", None), ("hybrid", net)):
             ch = hybrid.Chains(L, [beta] * chains, seed=43 + bi, stream_base=0)
             ch.local(1000)  # burn-in by plain sweeps, the same for both kinds
-            E, A, wall = hybrid.run_series(ch, rounds, 1, use, seed=47 + bi, round0=10_000)
-            acc = ch.accepted / ch.proposed if ch.proposed else None
+            E, A, wall, accepted = hybrid.run_series(ch, rounds, 1, use, seed=47 + bi,
+                                                     round0=10_000)
+            acc = float(accepted.sum()) / (chains * rounds) if accepted is not None else None
             ch.close()
             tau_m, tau_e = stats.tau_int_chains(A), stats.tau_int_chains(E)
             pe, pm = E.mean(axis=0), A.mean(axis=0)
@@ -478,7 +495,7 @@ def main() -> int:
                          "beside the headline (0 = skip)")
     ap.add_argument("--glass-sweeps", type=int, default=20,
                     help="sweeps per beta of the +-J spin glass on the headline lattices (0 = skip)")
-    ap.add_argument("--hybrid64-sweeps", type=int, default=1500,
+    ap.add_argument("--hybrid64-sweeps", type=int, default=100000,
                     help="sweeps of the L = 64 hybrid-chain comparison (0 = skip)")
     ap.add_argument("--matmul-sweeps", type=int, default=5,
                     help="minimum sweeps per size of the matrix-multiply comparison (0 = skip)")

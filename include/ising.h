@@ -387,6 +387,17 @@ int ising_arnet_sample(ising_arnet *net, int32_t B, uint64_t seed, uint32_t stre
 int ising_spins_observables(const int8_t *d_spins, int32_t B, int64_t L, int64_t *d_bond,
                             int64_t *d_mag, void *hip_stream);
 
+/* Training minibatch of B configurations from a pool of P int8
+ * configurations (L x L each, 2 <= L <= 1024), each under a random symmetry
+ * of the periodic Boltzmann weight of Eq. (1) -- a global spin flip and a
+ * translation -- all drawn from Philox block stream_base + b (< 2^24) of
+ * domain 5 at counter word `round`, (x0..x3): configuration
+ * k = floor((x1 2^32 + x0) P / 2^64), flipped iff x2 is odd, translated by
+ * di = (x2 >> 1) mod L rows and dj = x3 mod L columns:
+ * out[b][i][j] = +-pool[k][(i + di) mod L][(j + dj) mod L].  Asynchronous. */
+int ising_spins_minibatch(const int8_t *d_pool, int64_t P, int64_t L, int32_t B, uint64_t seed,
+                          uint32_t stream_base, uint64_t round, int8_t *d_out, void *hip_stream);
+
 /* Independence Metropolis-Hastings step for n chains of L x L spins, in
  * float32, each operation rounded on its own:
  * log A = ((betaJ[c] (bond'[c] - bond[c])) + logq[c]) - logq'[c];

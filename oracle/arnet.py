@@ -364,6 +364,33 @@ def mh_decisions(bond_cur, bond_prop, logq_cur, logq_prop, betaJ, seed: int, str
     return accept, ambiguous
 
 
+DOMAIN_AUGMENT = 5
+
+
+def augmented_minibatch(pool: np.ndarray, B: int, seed: int, stream_base: int, rnd: int):
+    """Training minibatch under the symmetries of the periodic Boltzmann weight
+    of Eq. (1) (global spin flip, translations): configuration b is pool
+    member k under flip f and shift (di, dj), drawn from the domain-5 block
+    of stream stream_base + b at counter (round lo, round hi, 0), words
+    (x0, x1, x2, x3): k = floor((x1 2^32 + x0) P / 2^64), f = x2 & 1,
+    di = (x2 >> 1) mod L, dj = x3 mod L; out[b][i][j] = (-1)^f
+    pool[k][(i + di) mod L][(j + dj) mod L]."""
+    from . import philox4x32_10
+
+    pool = np.asarray(pool, dtype=np.int8)
+    P, L = pool.shape[0], pool.shape[1]
+    key = (seed & 0xFFFFFFFF, (seed >> 32) & 0xFFFFFFFF)
+    out = np.empty((B, L, L), dtype=np.int8)
+    for b in range(B):
+        x = philox4x32_10((((stream_base + b) << 8) | (DOMAIN_AUGMENT << 4), rnd & 0xFFFFFFFF,
+                           (rnd >> 32) & 0xFFFFFFFF, 0), key)
+        k = (((x[1] << 32) | x[0]) * P) >> 64
+        di, dj = (x[2] >> 1) % L, x[3] % L
+        y = np.roll(pool[k], shift=(-di, -dj), axis=(0, 1))
+        out[b] = -y if x[2] & 1 else y
+    return out
+
+
 def sample(theta, C: int, L: int, B: int, rng, emulate_bf16: bool = True):
     """Ancestral sampling site by site in raster order; returns (x, log q_exact)."""
     x = np.zeros((B, L, L))

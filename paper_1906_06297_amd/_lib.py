@@ -99,6 +99,8 @@ SIGNATURES = {
     "ising_arnet_adam": (ctypes.c_int, [_vp, _vp, ctypes.c_float, _vp]),
     "ising_arnet_gradient_at": (ctypes.c_int, [_vp, _vp, ctypes.c_int32, _vp, _vp, _vp, _vp, _vp]),
     "ising_arnet_sample": (ctypes.c_int, [_vp, ctypes.c_int32, _u64, _u32, _u64, _vp, _vp, _vp]),
+    "ising_spins_minibatch": (ctypes.c_int, [_vp, _i64, _i64, ctypes.c_int32, _u64, _u32, _u64,
+                                             _vp, _vp]),
     "ising_spins_observables": (ctypes.c_int, [_vp, ctypes.c_int32, _i64, _vp, _vp, _vp]),
     "ising_mh_independence": (ctypes.c_int, [ctypes.c_int32, _i64, _vp, _vp, _vp, _vp, _vp, _vp,
                                              _vp, _u64, _u32, _u64, _vp, _vp]),

@@ -312,6 +312,20 @@ int ising_spins_observables(const int8_t *d_spins, int32_t B, int64_t L, int64_t
     return host::ok();
 }
 
+int ising_spins_minibatch(const int8_t *d_pool, int64_t P, int64_t L, int32_t B, uint64_t seed,
+                          uint32_t stream_base, uint64_t round, int8_t *d_out, void *hip_stream)
+{
+    if (!d_pool || !d_out || P < 1 || B < 1 || L < 2 || L > 1024)
+        return host::fail(ISING_E_BADARG, "null pointer or bad size");
+    if ((uint64_t)stream_base + (uint64_t)B > (1ull << 24))
+        return host::fail(ISING_E_BADARG, "stream_base + B must not exceed 2^24");
+    hipError_t e = launch_minibatch(d_pool, P, (int)L, B, d_out, seed, stream_base, round,
+                                    (hipStream_t)hip_stream);
+    if (e != hipSuccess)
+        return host::hip_fail(e, "minibatch");
+    return host::ok();
+}
+
 int ising_mh_independence(int32_t n, int64_t L, int8_t *d_state, float *d_logq, int64_t *d_bond,
                           const int8_t *d_prop, const float *d_logq_prop,
                           const int64_t *d_bond_prop, const float *d_betaJ, uint64_t seed,

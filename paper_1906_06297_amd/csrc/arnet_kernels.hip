@@ -1005,6 +1005,43 @@ __global__ __launch_bounds__(256) void k_spins_observables(const int8_t *__restr
     }
 }
 
+// Training minibatch: configuration b of the output is configuration k of a
+// pool of P under a random symmetry of the periodic Boltzmann weight (global
+// flip, translation by (di, dj)), all from Philox block (stream_base + b) of
+// domain 5 at counter (stream<<8 | 5<<4, round lo, round hi, 0):
+//   k = floor((x1:x0) P / 2^64), flip = x2 & 1, di = (x2 >> 1) mod L,
+//   dj = x3 mod L,
+//   out[b][i][j] = (flip ? -1 : 1) * pool[k][(i + di) mod L][(j + dj) mod L].
+__global__ __launch_bounds__(256) void k_minibatch(const int8_t *__restrict__ pool, int64_t P,
+                                                   int L, int8_t *__restrict__ out, uint32_t key0,
+                                                   uint32_t key1, uint32_t stream_base,
+                                                   uint32_t round_lo, uint32_t round_hi)
+{
+    __shared__ int64_t k_s;
+    __shared__ int flip_s, di_s, dj_s;
+    const int b = blockIdx.x, N = L * L;
+    if (threadIdx.x == 0) {
+        const Block u = philox4x32_10(ctr_word0(stream_base + (uint32_t)b, 5u, 0u), round_lo,
+                                      round_hi, 0u, key0, key1);
+        const uint64_t r64 = ((uint64_t)u.x1 << 32) | u.x0;
+        k_s = (int64_t)__umul64hi(r64, (uint64_t)P);
+        flip_s = (int)(u.x2 & 1u);
+        di_s = (int)((u.x2 >> 1) % (uint32_t)L);
+        dj_s = (int)(u.x3 % (uint32_t)L);
+    }
+    __syncthreads();
+    const int8_t *src = pool + k_s * N;
+    const int di = di_s, dj = dj_s;
+    const int8_t sg = flip_s ? -1 : 1;
+    for (int p = threadIdx.x; p < N; p += blockDim.x) {
+        const int i = p / L, j = p - (p / L) * L;
+        int ii = i + di, jj = j + dj;
+        ii -= ii >= L ? L : 0;
+        jj -= jj >= L ? L : 0;
+        out[(int64_t)b * N + p] = (int8_t)(sg * src[ii * L + jj]);
+    }
+}
+
 // Independence Metropolis-Hastings step per chain, in float32 with every
 // operation rounded on its own:
 //   log A = ((beta J * float(bond' - bond)) + log q(x)) - log q(x'),
@@ -1219,6 +1256,14 @@ hipError_t launch_spins_observables(const int8_t *x, int B, int L, int64_t *bond
                                     hipStream_t s)
 {
     hipLaunchKernelGGL(k_spins_observables, dim3(B), dim3(256), 0, s, x, L, bond, mag);
+    return hipGetLastError();
+}
+
+hipError_t launch_minibatch(const int8_t *pool, int64_t P, int L, int B, int8_t *out,
+                           uint64_t seed, uint32_t stream_base, uint64_t round, hipStream_t s)
+{
+    hipLaunchKernelGGL(k_minibatch, dim3(B), dim3(256), 0, s, pool, P, L, out, (uint32_t)seed,
+                       (uint32_t)(seed >> 32), stream_base, (uint32_t)round, (uint32_t)(round >> 32));
     return hipGetLastError();
 }
 

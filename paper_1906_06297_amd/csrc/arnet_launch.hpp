@@ -32,6 +32,8 @@ hipError_t launch_adam(float *params, const float *grad, float *m, float *v, int
                        float beta1, float beta2, float eps, int64_t step, hipStream_t s);
 hipError_t launch_spins_observables(const int8_t *x, int B, int L, int64_t *bond, int64_t *mag,
                                     hipStream_t s);
+hipError_t launch_minibatch(const int8_t *pool, int64_t P, int L, int B, int8_t *out,
+                           uint64_t seed, uint32_t stream_base, uint64_t round, hipStream_t s);
 hipError_t launch_mh(int n, int N, int8_t *state, float *logq_cur, int64_t *bond_cur,
                      const int8_t *prop, const float *logq_prop, const int64_t *bond_prop,
                      const float *betaJ, uint64_t seed, uint32_t stream_base, uint64_t round,

@@ -44,29 +44,16 @@ def plain_configurations(L: int, beta, chains: int, snapshots: int, thin: int, b
     return out.view(-1, L, L)
 
 
-def augment(x: torch.Tensor, gen: torch.Generator) -> torch.Tensor:
-    """Symmetries of the periodic Boltzmann weight: global spin flip and
-    translations (a random shift per configuration)."""
-    B, L, _ = x.shape
-    flip = (torch.randint(0, 2, (B, 1, 1), generator=gen, device=x.device) * 2 - 1).to(torch.int8)
-    di = torch.randint(0, L, (B,), generator=gen, device=x.device)
-    dj = torch.randint(0, L, (B,), generator=gen, device=x.device)
-    idx_i = (torch.arange(L, device=x.device)[None, :] + di[:, None]) % L
-    idx_j = (torch.arange(L, device=x.device)[None, :] + dj[:, None]) % L
-    y = x[torch.arange(B, device=x.device)[:, None, None], idx_i[:, :, None], idx_j[:, None, :]]
-    return (y * flip).contiguous()
-
-
 def train(net: "lt.ARNet", data: torch.Tensor, steps: int, batch: int, lr: float, seed: int = 0,
           log_every: int = 0):
-    """Adam on the mean negative log-likelihood of augmented minibatches."""
-    gen = torch.Generator(device=data.device)
-    gen.manual_seed(seed)
-    hist = []
+    """Adam on the mean negative log-likelihood of minibatches drawn from
+    `data` under random flips and translations (ising_spins_minibatch, step s
+    at counter word s)."""
+    xb = torch.empty((batch, net.L, net.L), dtype=torch.int8, device=data.device)
     loss = torch.empty(1, dtype=torch.float32, device=data.device)
+    hist = []
     for s in range(steps):
-        idx = torch.randint(0, data.shape[0], (batch,), generator=gen, device=data.device)
-        xb = augment(data[idx], gen)
+        lt.spins_minibatch(data, batch, seed=seed, stream_base=0, round=s, out=xb)
         net.train_step(xb, lr, loss=loss)
         if log_every and (s % log_every == 0 or s == steps - 1):
             hist.append((s, float(loss.item()) / (net.L * net.L)))
@@ -85,31 +72,30 @@ class Chains:
         dev = self.batch.words.device
         self.spins = torch.empty((self.n, L, L), dtype=torch.int8, device=dev)
         self.betaJ = torch.as_tensor(self.betas * J, dtype=torch.float32, device=dev)
-        self.accepted = 0
-        self.proposed = 0
-        self.accepted_per_chain = torch.zeros(self.n, dtype=torch.int64, device=dev)
-
-    def observables(self):
-        bond, mag = self.batch.observables_async()
-        return bond, mag
+        self.logq = torch.empty(self.n, dtype=torch.float32, device=dev)
+        self.bond = torch.empty(self.n, dtype=torch.int64, device=dev)
+        self.mag = torch.empty(self.n, dtype=torch.int64, device=dev)
+        self.prop = torch.empty((self.n, L, L), dtype=torch.int8, device=dev)
+        self.logq_prop = torch.empty(self.n, dtype=torch.float32, device=dev)
+        self.bond_prop = torch.empty(self.n, dtype=torch.int64, device=dev)
+        self.mag_prop = torch.empty(self.n, dtype=torch.int64, device=dev)
 
     def local(self, nsweeps: int) -> None:
         self.batch.sweep(nsweeps)
 
-    def global_move(self, net: "lt.ARNet", seed: int, rnd: int, stream_base: int = 0):
-        """One independence MH move per chain with a fresh proposal from `net`."""
+    def global_move(self, net: "lt.ARNet", seed: int, rnd: int, accepted, stream_base: int = 0):
+        """One independence MH move per chain with a fresh proposal from `net`;
+        the per-chain decisions (int32, 1 = accepted) go to `accepted`."""
         self.batch.spins(out=self.spins.view(-1))
-        logq = net.log_prob(self.spins)
-        bond, _ = lt.spins_observables(self.spins, self.L)
-        prop, logq_prop = net.sample(self.n, seed=seed, stream_base=stream_base, round=rnd)
-        bond_prop, _ = lt.spins_observables(prop, self.L)
-        acc = lt.mh_independence(self.spins, logq, bond, prop, logq_prop, bond_prop, self.betaJ,
-                                 seed=seed + 1, stream_base=stream_base, round=rnd)
+        net.log_prob(self.spins, out=self.logq)
+        lt.spins_observables(self.spins, self.L, bond=self.bond, mag=self.mag)
+        net.sample(self.n, seed=seed, stream_base=stream_base, round=rnd, out=self.prop,
+                   logq=self.logq_prop)
+        lt.spins_observables(self.prop, self.L, bond=self.bond_prop, mag=self.mag_prop)
+        lt.mh_independence(self.spins, self.logq, self.bond, self.prop, self.logq_prop,
+                           self.bond_prop, self.betaJ, seed=seed + 1, stream_base=stream_base,
+                           round=rnd, accepted=accepted)
         self.batch.set_spins(self.spins)
-        self.accepted_per_chain += acc.to(torch.int64)
-        self.accepted += int(acc.sum().item())
-        self.proposed += self.n
-        return acc
 
     def close(self):
         self.batch.close()
@@ -117,24 +103,30 @@ class Chains:
 
 def run_series(chains: Chains, rounds: int, local_per_round: int, net=None, seed: int = 0,
                round0: int = 1):
-    """Per round: `local_per_round` sweeps, then (if net) one global move.
-    Returns (E per site, |m|) arrays of shape (rounds, n) and the wall time."""
-    N = chains.L * chains.L
-    E = torch.empty((rounds, chains.n), dtype=torch.float64, device=chains.spins.device)
-    A = torch.empty_like(E)
+    """Per round: `local_per_round` sweeps, then (if net) one global move; the
+    observables after each round and the decisions of the moves are written
+    by the library straight into per-round device buffers.  Returns (E per
+    site, |m|) arrays of shape (rounds, n), the wall time and the number of
+    accepted moves per chain (None without a net)."""
+    n, N = chains.n, chains.L * chains.L
+    dev = chains.spins.device
+    obs = torch.empty((rounds, 2, n), dtype=torch.int64, device=dev)
+    acc = torch.empty((rounds, n), dtype=torch.int32, device=dev) if net is not None else None
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     for r in range(rounds):
         if local_per_round:
             chains.local(local_per_round)
         if net is not None:
-            chains.global_move(net, seed, round0 + r)
-        bond, mag = chains.observables()
-        E[r] = -chains.J * bond.to(torch.float64) / N
-        A[r] = mag.abs().to(torch.float64) / N
+            chains.global_move(net, seed, round0 + r, accepted=acc[r])
+        chains.batch.observables_async(out=obs[r])
     torch.cuda.synchronize()
     wall = time.perf_counter() - t0
-    return E.cpu().numpy(), A.cpu().numpy(), wall
+    o = obs.cpu().numpy().astype(np.float64)
+    E = -chains.J * o[:, 0, :] / N
+    A = np.abs(o[:, 1, :]) / N
+    accepted = acc.cpu().numpy().sum(axis=0) if acc is not None else None
+    return E, A, wall, accepted
 
 
 def compare_over_betas(net, L: int, betas, per_beta: int, sweeps: int, sweeps_per_proposal: int,
@@ -153,8 +145,7 @@ def compare_over_betas(net, L: int, betas, per_beta: int, sweeps: int, sweeps_pe
         ch = Chains(L, all_betas, seed=seed, J=J)
         ch.local(burn)
         rounds = sweeps // sweeps_per_proposal
-        E, A, wall = run_series(ch, rounds, sweeps_per_proposal, use, seed=seed, round0=1)
-        acc = ch.accepted_per_chain.cpu().numpy()
+        E, A, wall, acc = run_series(ch, rounds, sweeps_per_proposal, use, seed=seed, round0=1)
         ch.close()
         rows = []
         for k, beta in enumerate(betas):

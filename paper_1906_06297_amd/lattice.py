@@ -284,9 +284,12 @@ class Batch:
                                                        _stream_handle(stream)))
         return int(v.value)
 
-    def observables_async(self, stream=None):
-        """Device tensors (bond[n], M[n]); E_q = -J * bond[q]."""
-        out = torch.empty((2, self.n), dtype=torch.int64, device=self.words.device)
+    def observables_async(self, stream=None, out=None):
+        """Device tensors (bond[n], M[n]); E_q = -J * bond[q].  `out`, if
+        given, is a contiguous int64 device tensor of shape (2, n) to fill."""
+        if out is None:
+            out = torch.empty((2, self.n), dtype=torch.int64, device=self.words.device)
+        assert out.dtype == torch.int64 and out.is_contiguous() and out.shape == (2, self.n)
         _lib.check(_lib.load().ising_batch_observables(
             self._h, ctypes.c_void_p(out[0].data_ptr()), ctypes.c_void_p(out[1].data_ptr()),
             _stream_handle(stream)))
@@ -400,9 +403,10 @@ class ARNet:
         assert spins.numel() % (self.L * self.L) == 0
         return spins.numel() // (self.L * self.L)
 
-    def log_prob(self, spins, logits=False, stream=None):
+    def log_prob(self, spins, logits=False, stream=None, out=None):
         B = self._check_spins(spins)
-        logq = torch.empty(B, dtype=torch.float32, device=self.device)
+        logq = torch.empty(B, dtype=torch.float32, device=self.device) if out is None else out
+        assert logq.dtype == torch.float32 and logq.is_contiguous() and logq.numel() == B
         lg = torch.empty((B, self.L, self.L), dtype=torch.float32, device=self.device) if logits else None
         _lib.check(_lib.load().ising_arnet_log_prob(self._h, _ptr(spins), B, _ptr(logq),
                                                     _ptr(lg) if logits else None,
@@ -459,11 +463,29 @@ class ARNet:
         return out, logq
 
 
-def spins_observables(spins, L: int, stream=None):
-    """(bond, M) device int64 tensors of int8 configurations of shape (B, L, L)."""
+def spins_minibatch(pool, B: int, seed: int, stream_base: int = 0, round: int = 0, out=None,
+                    stream=None):
+    """B configurations drawn from `pool` (int8 device tensor (P, L, L)), each
+    flipped and translated at random (ising_spins_minibatch)."""
+    P, L = int(pool.shape[0]), int(pool.shape[1])
+    assert pool.dtype == torch.int8 and pool.is_contiguous()
+    if out is None:
+        out = torch.empty((B, L, L), dtype=torch.int8, device=pool.device)
+    _lib.check(_lib.load().ising_spins_minibatch(_ptr(pool), P, L, int(B), int(seed),
+                                                 int(stream_base), int(round), _ptr(out),
+                                                 _stream_handle(stream)))
+    return out
+
+
+def spins_observables(spins, L: int, stream=None, bond=None, mag=None):
+    """(bond, M) device int64 tensors of int8 configurations of shape (B, L, L)
+    (into `bond` and `mag` if given)."""
     B = spins.numel() // (L * L)
-    bond = torch.empty(B, dtype=torch.int64, device=spins.device)
-    mag = torch.empty(B, dtype=torch.int64, device=spins.device)
+    if bond is None:
+        bond = torch.empty(B, dtype=torch.int64, device=spins.device)
+    if mag is None:
+        mag = torch.empty(B, dtype=torch.int64, device=spins.device)
+    assert bond.is_contiguous() and mag.is_contiguous() and bond.numel() == mag.numel() == B
     _lib.check(_lib.load().ising_spins_observables(_ptr(spins), B, int(L), _ptr(bond), _ptr(mag),
                                                    _stream_handle(stream)))
     return bond, mag

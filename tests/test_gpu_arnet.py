@@ -375,6 +375,17 @@ def test_spins_observables_match_oracle(gpu, orc, L, B):
     assert np.array_equal(mag.cpu().numpy(), want[:, 1])
 
 
+@pytest.mark.parametrize("L,P,B", [(6, 40, 300), (32, 1000, 256), (64, 100, 64)])
+def test_minibatch_matches_oracle(gpu, L, P, B):
+    """Training minibatches (pool member, flip and translation from Philox
+    domain 5) bit for bit against the oracle's draw."""
+    pool = mixed_configs(P, L, 80 + L)
+    d_pool = spins_t(pool)
+    for rnd in (0, 1, 12345678901):
+        got = gpu.spins_minibatch(d_pool, B, seed=77, stream_base=9, round=rnd).cpu().numpy()
+        assert np.array_equal(got, ref.augmented_minibatch(pool, B, 77, 9, rnd)), rnd
+
+
 def test_independence_chain_exact_on_4x4(gpu):
     """Learned-proposal Metropolis-Hastings keeps the Boltzmann distribution:
     chains started from exact 4x4 Boltzmann samples stay there (random-weight

@@ -1,7 +1,10 @@
 """The learned proposal in use: a network trained on plain-sampler
 configurations, hybrid chains (one local sweep + one global move per round)
 against the exact energy, and what the trained network gains over the plain
-sweep in integrated autocorrelation time."""
+sweep: a lower integrated autocorrelation time of |m| per round.  Per second
+of wall time the gain does not hold (a round with a proposal costs far more
+than a sweep); the effective samples per second of both kinds are printed
+here and reported by the benchmark at L = 32 and L = 64."""
 import numpy as np
 import pytest
 
@@ -44,14 +47,15 @@ def test_hybrid_chain_matches_exact_energy_and_beats_plain_tau(trained):
     for name, use_net in (("plain", None), ("hybrid", net)):
         ch = hybrid.Chains(L, [beta] * n, seed=17 if use_net else 19)
         hybrid.run_series(ch, 200, 1, use_net, seed=23, round0=1)  # burn-in
-        E, A, wall = hybrid.run_series(ch, rounds, 1, use_net, seed=23, round0=1000)
-        acc = ch.accepted / max(ch.proposed, 1)
+        E, A, wall, accepted = hybrid.run_series(ch, rounds, 1, use_net, seed=23, round0=1000)
+        acc = float(accepted.sum()) / (n * rounds) if accepted is not None else 0.0
         ch.close()
         per_chain = E.mean(axis=0)
         se = per_chain.std(ddof=1) / np.sqrt(n)
         tau = stats.tau_int_chains(A)
         res[name] = (per_chain.mean(), se, tau, acc, wall)
-        print(name, res[name], "exact", target, flush=True)
-        assert abs(per_chain.mean() - target) < 4.5 * se, (name, per_chain.mean(), target, se)
+        print(name, "E", per_chain.mean(), "+-", se, "exact", target, "tau_int(|m|)", tau,
+              "acceptance", acc, "effective samples/s", n * rounds / (2 * tau) / wall, flush=True)
+        assert abs(per_chain.mean() - target) < 3 * se, (name, per_chain.mean(), target, se)
     assert res["hybrid"][3] > 0.05  # the trained proposal is accepted
     assert res["hybrid"][2] < res["plain"][2]  # and decorrelates |m| faster per round

@@ -1,8 +1,13 @@
-"""The hybrid chain on its second workload, shortened: L = 64, 16 inverse
-temperatures in [0.40, 0.48] with 16 chains each, a 64-channel network
-trained on plain-sampler configurations pooled over those temperatures, one
-global move per 10 local sweeps.  Energy per site and Binder cumulant of the
-hybrid chains agree with independent plain chains within their errors."""
+"""The hybrid chain on its second workload, shortened (the benchmark runs it
+at its full length): L = 64, 16 inverse temperatures in [0.40, 0.48] with 16
+chains each, a 64-channel network trained on plain-sampler configurations
+pooled over those temperatures, one global move per 10 local sweeps.  Energy
+per site and Binder cumulant of the hybrid chains agree with independent
+plain chains within 3 standard errors at every temperature.  At L = 64 the
+proposal is almost never accepted (4 of 2.56e6 proposals in the full-length
+run), so this checks that the hybrid machinery leaves the equilibrium
+distribution intact, not the proposal's gain; where no proposal is accepted
+the benchmark reports the learned-vs-plain comparison as unmeasured."""
 import numpy as np
 import pytest
 
@@ -44,5 +49,8 @@ def test_hybrid_scan_agrees_with_plain_chains():
           "tau_int(|m|) per measurement:",
           [(round(p["tau_int_abs_m"], 1), round(h["tau_int_abs_m"], 1))
            for p, h in zip(res["plain"]["per_beta"], res["hybrid"]["per_beta"])], flush=True)
-    assert np.all(np.abs(z) < 4.5)
-    assert np.mean(z ** 2) < 3.0  # 32 comparisons: chi^2 per degree of freedom
+    acc = np.array([h["acceptance"] for h in res["hybrid"]["per_beta"]])
+    print("betas without an accepted proposal:",
+          [round(p["beta"], 4) for p, a in zip(res["plain"]["per_beta"], acc) if a == 0], flush=True)
+    assert np.all(np.abs(z) < 3.0)
+    assert np.mean(z ** 2) < 2.0  # 32 comparisons: chi^2 per degree of freedom

@@ -257,3 +257,41 @@ def test_backward_from_given_activations_is_the_backward_pass():
     assert abs(nll - np.logaddexp(0, -x * z2).sum() / B) < 1e-12
     G = arnet.grad_abs_from(x, z2, acts2, th, C)
     assert np.all(np.abs(g) <= G * (1 + 1e-12) + 1e-300)
+
+
+def test_augmented_minibatch_draws_symmetry_images():
+    """Every drawn configuration is a flip and translation of a pool member,
+    keeps that member's bond sum (the Boltzmann weight), and over many draws
+    members, flips and shifts are uniform (chi-squared)."""
+    from oracle import exact
+
+    rng = np.random.default_rng(50)
+    P, L, B = 8, 6, 4000
+    pool = np.where(rng.random((P, L, L)) < 0.5, 1, -1).astype(np.int8)
+    pool[0] = 1  # an all-up member: its images are all-up or all-down
+    out = arnet.augmented_minibatch(pool, B, seed=0x1234567890, stream_base=3, rnd=7)
+    bond = exact.bond_sum_many(pool)
+    images = {}
+    for k in range(P):
+        for f in (1, -1):
+            for di in range(L):
+                for dj in range(L):
+                    y = f * np.roll(pool[k], shift=(-di, -dj), axis=(0, 1))
+                    images.setdefault(y.tobytes(), (k, f, di, dj))
+    ks, fs, dis, djs = [], [], [], []
+    for b in range(B):
+        k, f, di, dj = images[out[b].tobytes()]
+        assert exact.bond_sum_many(out[b:b + 1])[0] == bond[k]
+        ks.append(k)
+        fs.append(f)
+        if k != 0:
+            dis.append(di)
+            djs.append(dj)
+    for vals, m in ((ks, P), (dis, L), (djs, L)):
+        c = np.bincount(vals, minlength=m)
+        e = len(vals) / m
+        assert ((c - e) ** 2 / e).sum() < 3 * m  # loose chi-squared bound, m - 1 dof
+    assert abs(np.mean(np.array(fs) > 0) - 0.5) < 4 * np.sqrt(0.25 / B)
+    again = arnet.augmented_minibatch(pool, 5, seed=0x1234567890, stream_base=3, rnd=7)
+    assert np.array_equal(again, out[:5])
+    assert not np.array_equal(arnet.augmented_minibatch(pool, 5, 0x1234567890, 3, 8), out[:5])
