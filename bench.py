@@ -31,13 +31,14 @@ import workloads  # noqa: E402
 
 HBM_PEAK_GBS = 8000.0  # MI355X HBM3E, GB/s
 MFMA_FP16_PEAK_TFLOPS = 2500.0  # MI355X dense fp16 MFMA, TFLOP/s
-# Philox4x32-10 blocks per second on the whole chip with this counter layout
-# (a throughput probe of the generator alone on gfx950), and the blocks a
-# 64-spin word takes on average near T_c under the lazy compare: together the
-# rate no sweep that draws its random bits this way can exceed.
-PHILOX_BLOCKS_PER_S = 7.0e11
+# vector ALU: 256 compute units x 64 lanes x 2.4 GHz, one 32-bit lane operation
+# per lane per cycle (a wave64 instruction takes 4 cycles on a 16-lane SIMD)
+VALU_PEAK_TOPS = 256 * 64 * 2.4e9 / 1e12
+# Philox4x32-10 blocks a 64-spin word takes on average near T_c under the lazy
+# compare (host emulation of the kernels' decision on equilibrated lattices);
+# with the generator's measured rate (philox_rate()) the rate no sweep that
+# draws its random bits this way can exceed.
 BLOCKS_PER_WORD = 3.84
-PHILOX_CEILING_FLIPS_PER_NS = PHILOX_BLOCKS_PER_S * 64 / BLOCKS_PER_WORD / 1e9
 KERNEL_SOURCES = ("paper_1906_06297_amd/csrc/sweep_kernels.hip",
                   "paper_1906_06297_amd/csrc/ising_device.hpp",
                   "paper_1906_06297_amd/csrc/ising_rows.hpp")
@@ -96,6 +97,38 @@ def valu_issue(avg_launch_us: float):
     issue_us = insts * 4 / N_SIMD / (ghz * 1e3)
     return {"valu_insts_per_launch": insts, "shader_clock_ghz": ghz,
             "issue_us": issue_us, "frac_of_launch": issue_us / avg_launch_us}
+
+
+def philox_rate(ising, torch) -> dict:
+    """Philox4x32-10 blocks per second on the whole chip with the half-sweep's
+    counter layout (ising_philox_rate: the generator alone), and the sweep
+    rate it allows at BLOCKS_PER_WORD blocks per 64-spin word."""
+    import ctypes
+
+    from paper_1906_06297_amd import _lib
+
+    nwords, nq = 1 << 25, 4  # the words of one half-sweep at L = 65536, 4 blocks each
+    sink = torch.empty(256 * 2048, dtype=torch.int32, device="cuda")
+    stream = torch.cuda.current_stream().cuda_stream
+
+    def run():
+        _lib.check(_lib.load().ising_philox_rate(nwords, nq, 7, 0, 1, ctypes.c_void_p(sink.data_ptr()),
+                                                 sink.numel(), ctypes.c_void_p(stream)))
+
+    run()
+    torch.cuda.synchronize()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    reps = 10
+    e0.record()
+    for _ in range(reps):
+        run()
+    e1.record()
+    torch.cuda.synchronize()
+    sec = e0.elapsed_time(e1) / 1e3 / reps
+    rate = nwords * nq / sec
+    return {"blocks_per_s": rate, "blocks_per_word": BLOCKS_PER_WORD,
+            "ceiling_flips_per_ns": rate * 64 / BLOCKS_PER_WORD / 1e9,
+            "probe": f"{nwords} words x {nq} blocks, {sec * 1e3:.3f} ms per launch"}
 
 
 def onsager_energy(beta: float) -> float:
@@ -161,7 +194,7 @@ def host_cpu() -> str:
     return "unknown"
 
 
-def bench_batched(ising, torch, nsweeps: int) -> dict:
+def bench_batched(ising, torch, nsweeps: int, philox_ceiling: float) -> dict:
     """The batched workload: 1024 lattices of uneven L and beta in one persistent launch."""
     cfg = workloads.BATCHED
     Ls, betas, seeds, streams = workloads.batched_lattices()
@@ -210,8 +243,8 @@ def bench_batched(ising, torch, nsweeps: int) -> dict:
         "tiles_words_lanes": {str(k): list(v) for k, v in tiles.items()},
         "lattices_per_workgroup_and_workgroups": {str(k): list(plans[k]) for k in plans},
         "autotune_s": tune_s,
-        "philox_ceiling_flips_per_ns": PHILOX_CEILING_FLIPS_PER_NS,
-        "frac_of_philox_ceiling": updates / (ms * 1e6) / PHILOX_CEILING_FLIPS_PER_NS,
+        "philox_ceiling_flips_per_ns": philox_ceiling,
+        "frac_of_philox_ceiling": updates / (ms * 1e6) / philox_ceiling,
     }
 
 
@@ -415,8 +448,56 @@ def bench_hybrid64(ising, torch, sweeps: int, data_log2: int = 20, train_steps: 
     return out
 
 
+MFMA_BF16_PEAK_TFLOPS = 2500.0  # MI355X dense bf16 MFMA, TFLOP/s
+
+
+def bench_learned_kernels(ising, torch) -> dict:
+    """The learned proposal's kernels at the workload shapes (L = 32, 32
+    channels, 4096 proposals, training batch 256; L = 64, 64 channels, 256
+    proposals, training batch 64), random bf16 weights: ms per call of the
+    sampler (anti-diagonal, one configuration per workgroup), the evaluator
+    (log q~ of a batch) and one training step (forward, backward, Adam), with
+    the MFMA work of layers 2..6 (2 flops per multiply-add of 5C x C per site and
+    layer, 5C for layer 6) against the bf16 MFMA peak."""
+    from paper_1906_06297_amd import hybrid
+
+    def timeit(fn, n=5):
+        fn()
+        torch.cuda.synchronize()
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record()
+        for _ in range(n):
+            fn()
+        e1.record()
+        torch.cuda.synchronize()
+        return e0.elapsed_time(e1) / n
+
+    out = {}
+    for L, C, B, Bt in ((32, 32, 4096, 256), (64, 64, 256, 64)):
+        net = ising.ARNet(L, C, B)
+        try:
+            net.set_params(hybrid.init_params(L, C, seed=5))
+            x, _ = net.sample(B, seed=1)
+            xb = x[:Bt].contiguous()
+            ms = {"sample": timeit(lambda: net.sample(B, seed=1, round=2)),
+                  "log_prob": timeit(lambda: net.log_prob(x)),
+                  "train_step": timeit(lambda: net.train_step(xb, 1e-5))}
+        finally:
+            net.close()
+        flops_site = 2 * (4 * 5 * C * C + 5 * C)
+        work = {"sample": flops_site * L * L * B, "log_prob": flops_site * L * L * B,
+                "train_step": 3 * flops_site * L * L * Bt}  # forward, data and weight gradients
+        out[f"L{L}_C{C}"] = {
+            "batch": B, "train_batch": Bt, "ms": ms,
+            "mfma_tflops": {k: work[k] / (ms[k] * 1e-3) / 1e12 for k in ms},
+            "frac_of_bf16_mfma_peak": {k: work[k] / (ms[k] * 1e-3) / 1e12 / MFMA_BF16_PEAK_TFLOPS
+                                       for k in ms},
+        }
+    return out
+
+
 def bench_learned(ising, torch, L: int = 32, betas=(0.42, 0.44, 0.46), C: int = 32,
-                  chains: int = 4096, rounds: int = 400, train_steps: int = 1500,
+                  chains: int = 4096, rounds: int = 400, train_steps: int = 4000,
                   data_log2: int = 20) -> dict:
     """Learned global proposal against the plain sweep on the same GPU, per beta:
     a network trained on 2^data_log2 plain-sampler configurations at that beta,
@@ -495,6 +576,8 @@ def main() -> int:
                          "beside the headline (0 = skip)")
     ap.add_argument("--glass-sweeps", type=int, default=20,
                     help="sweeps per beta of the +-J spin glass on the headline lattices (0 = skip)")
+    ap.add_argument("--learned-kernels", type=int, default=1,
+                    help="time the learned proposal's kernels at the workload shapes (0 = skip)")
     ap.add_argument("--hybrid64-sweeps", type=int, default=100000,
                     help="sweeps of the L = 64 hybrid-chain comparison (0 = skip)")
     ap.add_argument("--matmul-sweeps", type=int, default=5,
@@ -511,6 +594,7 @@ def main() -> int:
                     help="also run three plain 1 GiB device-to-device copies, whose HBM counter "
                          "readings scale the profiler's byte counts")
     args = ap.parse_args()
+    t_start = time.perf_counter()
     if args.print_source_hash:
         print(kernel_source_hash())
         return 0
@@ -565,6 +649,29 @@ def main() -> int:
     alg_bytes = 3 * (L * L // 2) // 8  # target read + write, source read: 3 bits per update
     achieved = alg_bytes / (half_sweep_ms * 1e-3) / 1e9
 
+    philox = philox_rate(ising, torch)
+    valu = valu_issue(half_sweep_ms * 1e3)
+    hbm = {"achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+           "frac": achieved / HBM_PEAK_GBS, "alg_bytes_per_launch": alg_bytes}
+    if valu is not None:
+        # the binding limit: vector-ALU issue (instructions per launch from the
+        # counter summary, at 64 lane operations each, over the live launch time)
+        lane_tops = valu["valu_insts_per_launch"] * 64 / (half_sweep_ms * 1e-3) / 1e12
+        roofline = {"bound": "alu", "achieved": lane_tops, "peak": VALU_PEAK_TOPS,
+                    "unit": "Tops/s (32-bit VALU lane operations)", "frac": lane_tops / VALU_PEAK_TOPS}
+    else:  # counters not taken on these sources: the HBM roof only
+        roofline = {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                    "frac": achieved / HBM_PEAK_GBS}
+    roofline.update({
+        "kernel": "half-sweep",
+        "traffic": measured_traffic(),
+        "avg_launch_us": half_sweep_ms * 1e3,
+        "hbm": hbm,
+        "valu": valu,
+        "philox": philox,
+        "frac_of_philox_ceiling": (L * L / 2) / (half_sweep_ms * 1e6) / philox["ceiling_flips_per_ns"],
+    })
+
     physics = {}
     for lat, beta, ms in zip(lats, betas, per_beta_ms):
         bond, mag = lat.observables()
@@ -597,33 +704,34 @@ def main() -> int:
             "sweeps_per_beta": K,
             "per_beta": physics,
         },
-        "roofline": {
-            "bound": "hbm",
-            "kernel": "half-sweep",
-            "achieved": achieved,
-            "peak": HBM_PEAK_GBS,
-            "unit": "GB/s",
-            "frac": achieved / HBM_PEAK_GBS,
-            "traffic": measured_traffic(),
-            "avg_launch_us": half_sweep_ms * 1e3,
-            "alg_bytes_per_launch": alg_bytes,
-            "valu": valu_issue(half_sweep_ms * 1e3),
-            "philox_ceiling_flips_per_ns": PHILOX_CEILING_FLIPS_PER_NS,
-            "frac_of_philox_ceiling": (L * L / 2) / (half_sweep_ms * 1e6) / PHILOX_CEILING_FLIPS_PER_NS,
-        },
+        "roofline": roofline,
     }
+    def progress(msg):  # stderr: the JSON line stays the only thing on stdout
+        print(f"[bench] {msg} ({time.perf_counter() - t_start:.0f} s)", file=sys.stderr, flush=True)
+
+    progress(f"headline: {value:.0f} flips/ns")
     if args.heatbath_sweeps > 0:
         out["heatbath"] = bench_heatbath(ising, torch, bufs, args.heatbath_sweeps)
+        progress("heat bath done")
     if args.glass_sweeps > 0:
         out["glass"] = bench_glass(ising, torch, bufs, args.glass_sweeps)
+        progress("spin glass done")
     if args.matmul_sweeps > 0:
         out["matmul"] = bench_matmul(ising, torch, args.matmul_sweeps, args.matmul_L)
+        progress("matrix-multiply comparison done")
     if args.batched_sweeps > 0:
-        out["batched"] = bench_batched(ising, torch, args.batched_sweeps)
+        out["batched"] = bench_batched(ising, torch, args.batched_sweeps,
+                                       philox["ceiling_flips_per_ns"])
+        progress("batched done")
+    if args.learned_kernels > 0:
+        out["learned_kernels"] = bench_learned_kernels(ising, torch)
+        progress("learned kernels done")
     if args.learned_rounds > 0:
         out["learned"] = bench_learned(ising, torch, rounds=args.learned_rounds)
+        progress("learned proposal at L = 32 done")
     if args.hybrid64_sweeps > 0:
         out["hybrid_L64"] = bench_hybrid64(ising, torch, args.hybrid64_sweeps)
+        progress("hybrid chains at L = 64 done")
     if args.copy_calibration:
         del bufs, lats
         a = torch.empty(1 << 27, dtype=torch.int64, device="cuda").fill_(1)
@@ -634,6 +742,7 @@ def main() -> int:
         out["copy_calibration_bytes"] = a.numel() * 8
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline()
+        progress("CPU baseline done")
     print(json.dumps(out), flush=True)
     return 0
 

@@ -411,6 +411,16 @@ int ising_mh_independence(int32_t n, int64_t L, int8_t *d_state, float *d_logq, 
                           uint32_t stream_base, uint64_t round, int32_t *d_accepted,
                           void *hip_stream);
 
+/* The random-number generator alone, for measurement: blocks q = 0 ..
+ * blocks_per_word-1 of Philox4x32-10 (Salmon et al., SC'11, the generator of
+ * Sec. 3.3) for word indices 0 .. nwords-1 with the half-sweep's counter layout
+ * (stream_id, half-sweep index t, key seed), spread over sink_words threads (a
+ * multiple of 256), each folding its outputs into d_sink[thread].  Its rate
+ * bounds any sweep that decides with the exact lazy compare.  Asynchronous. */
+int ising_philox_rate(uint64_t nwords, uint32_t blocks_per_word, uint64_t seed,
+                      uint32_t stream_id, uint64_t t, uint32_t *d_sink, uint32_t sink_words,
+                      void *hip_stream);
+
 /* Selects the half-sweep kernel for later calls in this process, for tests and
  * measurements.  0 = default, by size (Metropolis and heat bath): for
  * row-aligned sizes (L % 128 == 0) the streaming row kernel with its

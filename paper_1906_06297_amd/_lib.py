@@ -83,6 +83,7 @@ SIGNATURES = {
     "ising_batch_autotune": (ctypes.c_int, [_vp, _i64, ctypes.c_char_p, _vp]),
     "ising_batch_get_spins_dev": (ctypes.c_int, [_vp, _vp, _vp]),
     "ising_batch_set_spins_dev": (ctypes.c_int, [_vp, _vp, _vp]),
+    "ising_philox_rate": (ctypes.c_int, [_u64, _u32, _u64, _u32, _u64, _vp, _u32, _vp]),
     "ising_batch_sweep_noalloc": (ctypes.c_int, [ctypes.c_int32, ctypes.POINTER(_i64),
                                                  ctypes.POINTER(ctypes.c_double), ctypes.c_double,
                                                  ctypes.POINTER(_u64), ctypes.POINTER(_u32), _vp,

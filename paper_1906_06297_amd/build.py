@@ -10,7 +10,8 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 CSRC = os.path.join(HERE, "csrc")
 LIB_PATH = os.path.join(HERE, "libising.so")
 SOURCES = ["sweep_kernels.hip", "capi.hip", "glass_kernels.hip", "batch_kernels.hip", "batch_capi.hip",
-           "arnet_kernels.hip", "arnet_capi.hip", "matmul_kernels.hip", "matmul_capi.hip"]
+           "arnet_kernels.hip", "arnet_capi.hip", "matmul_kernels.hip", "matmul_capi.hip",
+           "philox_rate.hip"]
 
 HIPCC_FLAGS = [
     "--offload-arch=gfx950",

@@ -618,6 +618,63 @@ __device__ __forceinline__ float block_sum_ordered(float v, float *red)
     return red[256];
 }
 
+// Rows of a 64-row chunk as the staging loops need them: flattened site index
+// of the row (configuration * N + site) and its lattice coordinates, or -1.
+struct ChunkRows {
+    int64_t base[64];
+    int16_t i[64], j[64];
+};
+
+__device__ __forceinline__ void chunk_rows(ChunkRows &cr, int64_t row0, int64_t rows_total, int N,
+                                           int L)
+{
+    const int k = threadIdx.x;
+    if (k < 64) {
+        const int64_t g = row0 + k;
+        if (g < rows_total) {
+            const int64_t b = g / N;
+            const int p = (int)(g - b * N);
+            cr.base[k] = b * N;
+            cr.i[k] = (int16_t)(p / L);
+            cr.j[k] = (int16_t)(p - (p / L) * L);
+        } else {
+            cr.base[k] = -1;
+            cr.i[k] = 0;
+            cr.j[k] = 0;
+        }
+    }
+}
+
+// The five mask-B taps of a chunk's 64 rows, transposed into LDS
+// (sA[t][c][k] = act[row k shifted by tap t][c], 0 outside the lattice):
+// items of 4 rows x 8 channels of one tap, four 16-byte loads and eight
+// 8-byte LDS writes each.
+template <int C>
+__device__ __forceinline__ void stage_taps(bf16 (&sA)[5][C][64], const bf16 *__restrict__ act,
+                                           const ChunkRows &cr, int L)
+{
+    constexpr int CG = C / 8;
+    typedef __bf16 bf16x4 __attribute__((ext_vector_type(4)));
+    for (int e = threadIdx.x; e < 5 * 16 * CG; e += blockDim.x) {
+        const int cg = e % CG, k4 = (e / CG) % 16, t = e / (CG * 16);
+        bf16x8 v[4];
+#pragma unroll
+        for (int u = 0; u < 4; ++u) {
+            const int k = 4 * k4 + u;
+            const int ii = cr.i[k] + tap_dy(t), jj = cr.j[k] + tap_dx(t);
+            if (cr.base[k] >= 0 && ii >= 0 && jj >= 0 && jj < L)
+                v[u] = *(const bf16x8 *)(act + (cr.base[k] + ii * L + jj) * C + cg * 8);
+            else
+                zero8(v[u]);
+        }
+#pragma unroll
+        for (int c = 0; c < 8; ++c) {
+            const bf16x4 w = {v[0][c], v[1][c], v[2][c], v[3][c]};
+            *(bf16x4 *)&sA[t][cg * 8 + c][4 * k4] = w;
+        }
+    }
+}
+
 // d(mean NLL)/d logit = -s sigmoid(-s z) / B (float32, written out), the mean
 // NLL, and the layer-6 weight and bias gradients:
 //   dW6[t][ci] = sum_rows h5[row shifted by tap t][ci] * dlogit[row]
@@ -645,23 +702,14 @@ __global__ __launch_bounds__(256) void k_l6_back(NetDev net, const int8_t *__res
     for (int e = tid; e < 14 * 64; e += 256)
         sD[2 + e / 64][e % 64] = (bf16)0.f;
     float lsum = 0.f, dsum = 0.f;
-    const ChunkRange cr(nchunks, cpb);
-    for (int64_t ch = cr.c0; ch < cr.c1; ++ch) {
+    __shared__ ChunkRows crow;
+    const ChunkRange rng(nchunks, cpb);
+    for (int64_t ch = rng.c0; ch < rng.c1; ++ch) {
         const int64_t row0 = ch * 64;
         __syncthreads();
-        for (int e = tid; e < 64 * C; e += 256) {
-            const int k = e / C, c = e % C;
-            const int64_t g = row0 + k;
-            const bool valid = g < rows_total;
-            const int64_t b = valid ? g / N : 0;
-            const int p = valid ? (int)(g - b * N) : 0, i = p / L, j = p - (p / L) * L;
-#pragma unroll
-            for (int t = 0; t < 5; ++t) {
-                const int ii = i + tap_dy(t), jj = j + tap_dx(t);
-                const bool ok = valid && ii >= 0 && jj >= 0 && jj < L;
-                sA[t][c][k] = ok ? h5[((int64_t)b * N + ii * L + jj) * C + c] : (bf16)0.f;
-            }
-        }
+        chunk_rows(crow, row0, rows_total, N, L);
+        __syncthreads();
+        stage_taps<C>(sA, h5, crow, L);
         if (tid < 64) {
             const int64_t g = row0 + tid;
             float d = 0.f;
@@ -780,6 +828,13 @@ __global__ __launch_bounds__(256) void k_conv_dgrad(const float *__restrict__ dp
 //   dW[t][ci][co] = sum_rows act_below[row shifted by tap t][ci] * dpre[row][co]
 // on MFMA, rows as the reduction dimension, 64 rows at a time transposed in
 // LDS, dpre as two bf16 halves; db[co] = sum_rows dpre[row][co] in float32.
+// Weight and bias gradients of a C -> C layer:
+//   dW[t][ci][co] = sum_rows act_below[row shifted by tap t][ci] * dpre[row][co]
+// on MFMA, rows as the reduction dimension, 64 rows at a time transposed in
+// LDS (a thread takes 4 rows x 8 channels: four 16-byte loads, eight 8-byte
+// LDS writes), dpre as two bf16 halves; db[co] = sum_rows dpre[row][co] in
+// float32, each thread adding its rows in order, the threads of a channel in
+// thread order.
 template <int C>
 __global__ __launch_bounds__(256) void k_conv_wgrad(const bf16 *__restrict__ act_below,
                                                     const float *__restrict__ dpre, int L, int N,
@@ -787,38 +842,58 @@ __global__ __launch_bounds__(256) void k_conv_wgrad(const bf16 *__restrict__ act
                                                     float *__restrict__ pW, float *__restrict__ pb,
                                                     int64_t pstride)
 {
-    constexpr int MT = C / 16, TILES = 5 * MT * MT, TPW = TILES / 4;
-    constexpr int TPC = 256 / C; // threads sharing one channel in the staging loop
+    constexpr int MT = C / 16, TILES = 5 * MT * MT, TPW = TILES / 4, CG = C / 8;
     __shared__ __align__(16) bf16 sA[5][C][64];
     __shared__ __align__(16) bf16 sDh[C][64];
     __shared__ __align__(16) bf16 sDl[C][64];
+    __shared__ ChunkRows cr;
     __shared__ float red[256];
     const int tid = threadIdx.x, wave = tid >> 6, lane = tid & 63, r = lane & 15, kq = lane >> 4;
     floatx4 acc[TPW];
 #pragma unroll
     for (int q = 0; q < TPW; ++q)
         acc[q] = floatx4{0.f, 0.f, 0.f, 0.f};
-    float bacc = 0.f; // channel tid % C, rows k = tid / C + TPC * it of each chunk
-    const ChunkRange cr(nchunks, cpb);
-    for (int64_t ch = cr.c0; ch < cr.c1; ++ch) {
+    float bacc[8] = {}; // channels cg*8 .. +7 of the dpre items this thread stages
+    const ChunkRange rng(nchunks, cpb);
+    for (int64_t ch = rng.c0; ch < rng.c1; ++ch) {
         const int64_t row0 = ch * 64;
         __syncthreads();
-        for (int e = tid; e < 64 * C; e += 256) {
-            const int k = e / C, c = e % C;
-            const int64_t g = row0 + k;
-            const bool valid = g < rows_total;
-            const int64_t b = valid ? g / N : 0;
-            const int p = valid ? (int)(g - b * N) : 0, i = p / L, j = p - (p / L) * L;
-            const float d = valid ? dpre[g * C + c] : 0.f;
-            bacc += d;
-            const bf16 h = (bf16)d;
-            sDh[c][k] = h;
-            sDl[c][k] = (bf16)(d - (float)h);
+        chunk_rows(cr, row0, rows_total, N, L);
+        __syncthreads();
+        stage_taps<C>(sA, act_below, cr, L);
+        // backward signal: items (4-row group, 8-channel group), fixed per thread
+        if (tid < 16 * CG) {
+            const int cg = tid % CG, k4 = tid / CG;
+            float d[4][8];
 #pragma unroll
-            for (int t = 0; t < 5; ++t) {
-                const int ii = i + tap_dy(t), jj = j + tap_dx(t);
-                const bool ok = valid && ii >= 0 && jj >= 0 && jj < L;
-                sA[t][c][k] = ok ? act_below[((int64_t)b * N + ii * L + jj) * C + c] : (bf16)0.f;
+            for (int u = 0; u < 4; ++u) {
+                const int64_t g = row0 + 4 * k4 + u;
+                if (g < rows_total) {
+                    const float4 a0 = *(const float4 *)(dpre + g * C + cg * 8);
+                    const float4 a1 = *(const float4 *)(dpre + g * C + cg * 8 + 4);
+                    const float t8[8] = {a0.x, a0.y, a0.z, a0.w, a1.x, a1.y, a1.z, a1.w};
+#pragma unroll
+                    for (int c = 0; c < 8; ++c)
+                        d[u][c] = t8[c];
+                } else {
+#pragma unroll
+                    for (int c = 0; c < 8; ++c)
+                        d[u][c] = 0.f;
+                }
+            }
+#pragma unroll
+            for (int c = 0; c < 8; ++c) {
+                typedef __bf16 bf16x4 __attribute__((ext_vector_type(4)));
+                bf16x4 hi, lo;
+#pragma unroll
+                for (int u = 0; u < 4; ++u) {
+                    bacc[c] += d[u][c];
+                    const bf16 h = (bf16)d[u][c];
+                    hi[u] = h;
+                    lo[u] = (bf16)(d[u][c] - (float)h);
+                }
+                *(bf16x4 *)&sDh[cg * 8 + c][4 * k4] = hi;
+                *(bf16x4 *)&sDl[cg * 8 + c][4 * k4] = lo;
             }
         }
         __syncthreads();
@@ -847,15 +922,18 @@ __global__ __launch_bounds__(256) void k_conv_wgrad(const bf16 *__restrict__ act
             oW[((int64_t)t * C + ci) * C + co] = acc[q][e];
         }
     }
-    // bias: the TPC threads of a channel, in thread order
-    __syncthreads();
-    red[tid] = bacc;
-    __syncthreads();
-    if (tid < C) {
-        float s = 0.f;
-        for (int k = 0; k < TPC; ++k)
-            s += red[tid + k * C];
-        pb[(int64_t)blockIdx.x * pstride + tid] = s;
+    // bias: thread tid < 16 CG holds channels (tid % CG)*8 .. +7 over its row
+    // groups; the 16 threads of a channel group are added in thread order
+    for (int c = 0; c < 8; ++c) {
+        __syncthreads();
+        red[tid] = bacc[c];
+        __syncthreads();
+        if (tid < CG) {
+            float s = 0.f;
+            for (int k4 = 0; k4 < 16; ++k4)
+                s += red[k4 * CG + tid];
+            pb[(int64_t)blockIdx.x * pstride + tid * 8 + c] = s;
+        }
     }
 }
 
@@ -937,23 +1015,31 @@ __global__ __launch_bounds__(256) void k_l1_wgrad(NetDev net, const int8_t *__re
     }
 }
 
-// grad[e] = sum over workgroups g = 0, 1, .. of partial[g][e] (in that
-// order); the last slot is the loss.
+// grad[e] = sum over workgroups of partial[g][e], the last slot the loss: a
+// workgroup takes 64 slots, its four wavefronts the workgroups g = w, w + 4,
+// w + 8, .. (each in increasing g), and the four sums are added as
+// (s0 + s1) + (s2 + s3).  The order is fixed, so the result is too.
 __global__ __launch_bounds__(256) void k_reduce_partials(const float *__restrict__ partial,
                                                          int64_t pstride, int nblk, int64_t P,
                                                          float *__restrict__ grad,
                                                          float *__restrict__ loss)
 {
-    const int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (e > P)
-        return;
+    __shared__ float part[4][64];
+    const int w = threadIdx.x >> 6, lane = threadIdx.x & 63;
+    const int64_t e = (int64_t)blockIdx.x * 64 + lane;
     float s = 0.f;
-    for (int g = 0; g < nblk; ++g)
-        s += partial[(int64_t)g * pstride + e];
-    if (e < P)
-        grad[e] = s;
-    else
-        *loss = s;
+    if (e <= P)
+        for (int g = w; g < nblk; g += 4)
+            s += partial[(int64_t)g * pstride + e];
+    part[w][lane] = s;
+    __syncthreads();
+    if (w == 0 && e <= P) {
+        const float t = (part[0][lane] + part[1][lane]) + (part[2][lane] + part[3][lane]);
+        if (e < P)
+            grad[e] = t;
+        else
+            *loss = t;
+    }
 }
 
 // Adam (Kingma and Ba 2015) on the float32 master parameters.
@@ -1235,7 +1321,7 @@ hipError_t launch_backward(const NetDev &net, const int8_t *x, int B, bf16 *cons
     else
         hipLaunchKernelGGL(k_l1_wgrad<64>, dim3(nblk), dim3(256), 0, s, net, x, above, rows, nchunks,
                            cpb, partial, pstride);
-    hipLaunchKernelGGL(k_reduce_partials, dim3(nblocks(pl.total + 1, 256)), dim3(256), 0, s, partial,
+    hipLaunchKernelGGL(k_reduce_partials, dim3(nblocks(pl.total + 1, 64)), dim3(256), 0, s, partial,
                        pstride, nblk, pl.total, grad, loss);
     return hipGetLastError();
 }

@@ -539,6 +539,21 @@ int ising_glass_observables(const ising_lattice *lat, const uint64_t *d_bonds, s
     return e == hipSuccess ? ok() : hip_fail(e, "observables launch");
 }
 
+int ising_philox_rate(uint64_t nwords, uint32_t blocks_per_word, uint64_t seed,
+                      uint32_t stream_id, uint64_t t, uint32_t *d_sink, uint32_t sink_words,
+                      void *hip_stream)
+{
+    if (!d_sink || sink_words < 256 || sink_words % 256 != 0 || blocks_per_word < 1 ||
+        blocks_per_word > 16 || nwords > (1ull << 32))
+        return fail(ISING_E_BADARG, "need a sink of a multiple of 256 words, 1..16 blocks per "
+                    "word and at most 2^32 words");
+    hipError_t e = ising::launch_philox_rate(nwords, blocks_per_word, seed, stream_id, t, d_sink,
+                                             sink_words, (hipStream_t)hip_stream);
+    if (e != hipSuccess)
+        return hip_fail(e, "generator throughput launch");
+    return ok();
+}
+
 int ising_set_sweep_kernel(int variant)
 {
     if (variant < 0 || variant > 5)

@@ -35,6 +35,8 @@ hipError_t launch_rows_queue(uint64_t *tgt, const uint64_t *src, const uint64_t 
 hipError_t launch_half_sweep5(uint64_t *words, int64_t L, int c, const rows::Table5 &tab,
                               uint64_t t, uint64_t seed, uint32_t stream_id, hipStream_t s,
                               int variant);
+hipError_t launch_philox_rate(uint64_t nwords, uint32_t nq, uint64_t seed, uint32_t stream_id,
+                              uint64_t t, uint32_t *sink, uint32_t sink_words, hipStream_t s);
 hipError_t launch_observables(const uint64_t *words, int64_t L, int64_t *bond, int64_t *mag,
                               hipStream_t s);
 
