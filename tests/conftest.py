@@ -19,3 +19,15 @@ def orc():
 
     oracle.lib()
     return oracle
+
+
+@pytest.fixture
+def progress(capsys):
+    """Prints a progress line past pytest's output capture, so that a long
+    test still writes to the terminal while it runs under -q."""
+
+    def say(*a):
+        with capsys.disabled():
+            print(*a, flush=True)
+
+    return say

@@ -152,7 +152,7 @@ def test_long_run_sample(gpu, orc, workload):
 
 
 @pytest.mark.timeout(1200)
-def test_batched_workload_full_length_every_lattice(gpu, orc, workload):
+def test_batched_workload_full_length_every_lattice(gpu, orc, workload, progress):
     """The batched workload as the benchmark runs it -- tiles autotuned for the
     whole batch, 10^4 sweeps in one captured-graph replay from a fresh start --
     every one of the 1024 lattices bit for bit against the oracle (about 1.5e11
@@ -160,7 +160,7 @@ def test_batched_workload_full_length_every_lattice(gpu, orc, workload):
     Ls, betas, seeds, streams = workload
     nsweeps = workloads.BATCHED["nsweeps"]
     b = gpu.Batch(Ls, betas, 1.0, seeds, streams)
-    say("batch of 1024: autotune, then 10^4 sweeps")
+    progress("batch of 1024: autotune, then 10^4 sweeps")
     b.autotune(200, None)
     b.init()
     b.set_counter(0)
@@ -168,7 +168,7 @@ def test_batched_workload_full_length_every_lattice(gpu, orc, workload):
     got = [batch_words_of(b, q) for q in range(len(Ls))]
     assert b.counter() == nsweeps
     b.close()
-    say(f"oracle: 1024 lattices x {nsweeps} sweeps on {orc.max_threads()} threads")
+    progress(f"oracle: 1024 lattices x {nsweeps} sweeps on {orc.max_threads()} threads")
     # in chunks of lattices (each a parallel oracle run), reporting as it goes
     bad = []
     order = np.argsort(-np.asarray(Ls), kind="stable")  # large lattices spread over chunks
@@ -177,8 +177,8 @@ def test_batched_workload_full_length_every_lattice(gpu, orc, workload):
         ref = oracle_batch(orc, *(np.asarray(a)[pick] for a in (Ls, betas)), 1.0,
                            *(np.asarray(a)[pick] for a in (seeds, streams)), nsweeps)
         bad += [int(q) for k, q in enumerate(pick) if not np.array_equal(got[q], pack(ref[k]))]
-        say(f"  oracle chunk {c + 1}/16 done, {len(bad)} mismatches so far")
-    say(f"{len(Ls) - len(bad)} of {len(Ls)} lattices bit-exact")
+        progress(f"  oracle chunk {c + 1}/16 done, {len(bad)} mismatches so far")
+    progress(f"{len(Ls) - len(bad)} of {len(Ls)} lattices bit-exact")
     assert not bad, bad[:10]
 
 
