@@ -50,4 +50,56 @@ __host__ __device__ __forceinline__ Neighbours neighbours_aligned(Ptr E, uint32_
     return nb;
 }
 
+// Colour rows of a whole number of 32-bit halves (H = L/2 a multiple of 32,
+// i.e. L % 64 == 0; used where H is not a multiple of 64, as for L = 64 and
+// 192): every half lies in one row, so the vertical neighbours of half h are
+// the halves Hr = H/32 away (periodic over the colour's 2W halves) and its
+// side neighbour is half h shifted by one spin with the edge spin taken from
+// the adjacent half of its row, or from the row's other end.  E is the other
+// colour as 32-bit halves (half h = bits 32(h&1).. of word h>>1).
+
+// Row of half h for h < 8192 and Hr <= 11: floor(h / Hr) as a multiply by
+// ceil(2^18 / Hr); the error h / 2^18 < 1/32 stays below the 1/Hr gap.
+__host__ __device__ __forceinline__ uint32_t half_row(uint32_t h, uint32_t inv_hr)
+{
+    return (h * inv_hr) >> 18;
+}
+
+__host__ __device__ __forceinline__ uint32_t half_inv(uint32_t Hr)
+{
+    return ((1u << 18) + Hr - 1) / Hr;
+}
+
+template <typename Ptr32>
+__host__ __device__ __forceinline__ Neighbours neighbours_half_aligned(Ptr32 E, uint32_t W,
+                                                                       uint32_t Hr,
+                                                                       uint32_t inv_hr, uint32_t k,
+                                                                       int c)
+{
+    const uint32_t NH = 2 * W, h0 = 2 * k;
+    const uint32_t r0 = half_row(h0, inv_hr), o0 = h0 - r0 * Hr;
+    uint32_t up[2], dn[2], ce[2], sd[2];
+#pragma unroll
+    for (uint32_t hh = 0; hh < 2; ++hh) {
+        const uint32_t h = h0 + hh;
+        const bool next_row = hh == 1 && o0 + 1 == Hr;
+        const uint32_t r = r0 + (next_row ? 1u : 0u), o = next_row ? 0u : o0 + hh;
+        ce[hh] = E[h];
+        up[hh] = E[h >= Hr ? h - Hr : h + NH - Hr];
+        dn[hh] = E[h + Hr < NH ? h + Hr : h + Hr - NH];
+        const uint32_t before = E[o == 0 ? h + Hr - 1 : h - 1];
+        const uint32_t after = E[o == Hr - 1 ? h + 1 - Hr : h + 1];
+        const uint32_t left = (ce[hh] << 1) | (before >> 31);
+        const uint32_t right = (ce[hh] >> 1) | (after << 31);
+        // rows whose side neighbour is on the left: (row + c) even
+        sd[hh] = ((r + (uint32_t)c) & 1u) == 0 ? left : right;
+    }
+    Neighbours nb;
+    nb.ce = (uint64_t)ce[0] | ((uint64_t)ce[1] << 32);
+    nb.up = (uint64_t)up[0] | ((uint64_t)up[1] << 32);
+    nb.dn = (uint64_t)dn[0] | ((uint64_t)dn[1] << 32);
+    nb.sd = (uint64_t)sd[0] | ((uint64_t)sd[1] << 32);
+    return nb;
+}
+
 } // namespace ising

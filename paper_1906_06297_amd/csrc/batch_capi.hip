@@ -379,7 +379,7 @@ std::mutex g_noalloc_mu;
 
 
 // ---------------------------------------------------------------- cache file
-std::string cache_key() { return "gfx950/batch-sweep-v7"; }
+std::string cache_key() { return "gfx950/batch-sweep-v8"; }
 
 bool read_cache(const char *path, std::map<int64_t, Tile> &out)
 {

@@ -94,6 +94,9 @@ __global__ __launch_bounds__(kBatchThreads) void k_batch_sweep(
         // row arithmetic holds for W < 4096, which L <= 722 keeps)
         const bool aligned = (first.H & 63) == 0 && first.W < 4096;
         const uint32_t Wr = first.H >> 6, inv_wr = aligned ? aligned_inv(Wr) : 0;
+        // colour rows of whole 32-bit halves (L % 64 == 0, e.g. 64 and 192)
+        const bool half_aligned = !aligned && (first.H & 31) == 0 && first.W < 4096;
+        const uint32_t Hr = first.H >> 5, inv_hr = half_aligned ? half_inv(Hr) : 0;
         const uint32_t slot = threadIdx.x / bd.tpl, li = threadIdx.x % bd.tpl;
         const uint32_t group = li / bd.lpw, parity = li % bd.lpw, groups = bd.tpl / bd.lpw;
         const bool on = slot < bd.count;
@@ -128,6 +131,9 @@ __global__ __launch_bounds__(kBatchThreads) void k_batch_sweep(
                         Neighbours nb;
                         if (aligned) {
                             nb = neighbours_aligned(src, lt.W, Wr, inv_wr, k, c);
+                        } else if (half_aligned) {
+                            nb = neighbours_half_aligned((const uint32_t *)src, lt.W, Hr, inv_hr,
+                                                         k, c);
                         } else {
                             RowMasks rm = row_masks32(k, lt.H, lt.M, 0);
                             if (c)

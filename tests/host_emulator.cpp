@@ -145,6 +145,50 @@ int emu_aligned_neighbours_check(int64_t L, uint64_t seed)
     return bad;
 }
 
+// The batch kernel's half-aligned neighbour vectors (L % 64 == 0) against the
+// general extraction, for every word of both colours; returns mismatches.
+int emu_half_aligned_neighbours_check(int64_t L, uint64_t seed)
+{
+    const uint32_t H = (uint32_t)(L / 2), M = (uint32_t)(L * L / 2), W = M / 64, Hr = H / 32;
+    std::vector<uint64_t> E(W + 2);
+    uint64_t z = seed * 0x9E3779B97F4A7C15ull + 11;
+    for (uint32_t k = 0; k < W; ++k) { // splitmix64
+        uint64_t x = (z += 0x9E3779B97F4A7C15ull);
+        x = (x ^ (x >> 30)) * 0xBF58476D1CE4E5B9ull;
+        x = (x ^ (x >> 27)) * 0x94D049BB133111EBull;
+        E[k] = x ^ (x >> 31);
+    }
+    E[W] = E[0];
+    E[W + 1] = E[1 % W];
+    std::vector<uint32_t> E32(2 * W);
+    for (uint32_t k = 0; k < W; ++k) {
+        E32[2 * k] = (uint32_t)E[k];
+        E32[2 * k + 1] = (uint32_t)(E[k] >> 32);
+    }
+    int bad = 0;
+    const uint32_t inv = half_inv(Hr);
+    for (int c = 0; c < 2; ++c)
+        for (uint32_t k = 0; k < W; ++k) {
+            RowMasks rm = row_masks32(k, H, M, 0);
+            if (c)
+                rm.left_rows = ~rm.left_rows;
+            const Neighbours a = neighbours_ext_rm(E.data(), H, M, k, rm);
+            const Neighbours b = neighbours_half_aligned(E32.data(), W, Hr, inv, k, c);
+            bad += (a.ce != b.ce) || (a.up != b.up) || (a.dn != b.dn) || (a.sd != b.sd);
+        }
+    return bad;
+}
+
+// floor(h / Hr) by the half-aligned multiply, over its whole range.
+int emu_half_row_check()
+{
+    int bad = 0;
+    for (uint32_t Hr = 1; Hr <= 11; ++Hr)
+        for (uint32_t h = 0; h < 8192; ++h)
+            bad += half_row(h, half_inv(Hr)) != h / Hr;
+    return bad;
+}
+
 // floor(k / Wr) by the batch kernel's multiply, over its whole range.
 int emu_aligned_row_check()
 {

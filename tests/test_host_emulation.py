@@ -33,6 +33,7 @@ def emu(tmp_path_factory):
                                     ctypes.c_uint64, ctypes.c_uint32, ctypes.c_int]
     lib.emu_block_decision_check.argtypes = [ctypes.c_uint64, ctypes.c_int]
     lib.emu_aligned_neighbours_check.argtypes = [ctypes.c_int64, ctypes.c_uint64]
+    lib.emu_half_aligned_neighbours_check.argtypes = [ctypes.c_int64, ctypes.c_uint64]
     lib.emu_xcd_block.argtypes = [ctypes.c_uint32, ctypes.c_uint32]
     lib.emu_xcd_block.restype = ctypes.c_uint32
     lib.emu_philox_fast.argtypes = [ctypes.c_uint32] * 6 + [ctypes.c_int,
@@ -167,3 +168,14 @@ def test_batch_row_aligned_neighbours_equal_the_general_extraction(emu, L):
     general funnel-shift extraction for every word of both colours."""
     assert emu.emu_aligned_neighbours_check(L, L + 1) == 0
     assert emu.emu_aligned_row_check() == 0
+
+
+@pytest.mark.parametrize("L", [64, 128, 192, 320, 448, 576, 704])
+def test_batch_half_aligned_neighbours_equal_the_general_extraction(emu, L):
+    """For L % 64 == 0 a colour row is a whole number of 32-bit halves: the
+    vertical neighbours are whole halves H/32 away and the side neighbour one
+    edge half; that must equal the general funnel-shift extraction for every
+    word of both colours (sizes with an odd number of halves per row, whose
+    words straddle rows, and whole-word rows alike)."""
+    assert emu.emu_half_aligned_neighbours_check(L, L + 3) == 0
+    assert emu.emu_half_row_check() == 0
