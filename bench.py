@@ -203,6 +203,7 @@ def bench_batched(ising, torch, nsweeps: int, philox_ceiling: float) -> dict:
     tiles = b.autotune(200, None)
     tune_s = time.perf_counter() - t0
     plans = {L: b.plan(L) for L in tiles}
+    mixed = b.mixed()
     b.init()
     b.sweep(nsweeps)  # captures the graph (untimed), then a timed replay from a fresh start
     b.init()
@@ -242,6 +243,7 @@ def bench_batched(ising, torch, nsweeps: int, philox_ceiling: float) -> dict:
         "largest_size_count": len(big),
         "tiles_words_lanes": {str(k): list(v) for k, v in tiles.items()},
         "lattices_per_workgroup_and_workgroups": {str(k): list(plans[k]) for k in plans},
+        "mixed_size_workgroups": mixed,
         "autotune_s": tune_s,
         "philox_ceiling_flips_per_ns": philox_ceiling,
         "frac_of_philox_ceiling": updates / (ms * 1e6) / philox_ceiling,

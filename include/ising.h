@@ -258,11 +258,25 @@ int ising_batch_observables(const ising_batch *b, int64_t *d_bond, int64_t *d_ma
 int ising_batch_get_tiles(const ising_batch *b, int64_t L, uint32_t *wpt, uint32_t *lpw);
 int ising_batch_set_tiles(ising_batch *b, int64_t L, uint32_t wpt, uint32_t lpw);
 
-/* The current plan for the lattices of size L: how many share one workgroup
- * of the persistent kernel and how many workgroups they fill.  BADARG if the
+/* The current plan for the lattices of size L: the most of them that share
+ * one workgroup of the persistent kernel and how many workgroups hold some
+ * (with mixed-size bundles, beside lattices of other sizes).  BADARG if the
  * batch has no lattice of size L or an output pointer is NULL. */
 int ising_batch_get_plan(const ising_batch *b, int64_t L, uint32_t *lattices_per_workgroup,
                          uint32_t *workgroups);
+
+/* *mixed = 1 if the current plan has bundles that may mix lattice sizes (the
+ * autotuner chose them, or ising_batch_set_bundles set them), else 0. */
+int ising_batch_get_mixed(const ising_batch *b, int32_t *mixed);
+
+/* Sets the plan explicitly: nbundles workgroup loads in launch order, bundle
+ * i holding the counts[i] lattices listed next in `lattices` (indices into
+ * the batch; every lattice exactly once), each with its size's current tile,
+ * threads back to back (lane-pair tiles first).  BADARG if a bundle
+ * needs more than 1024 threads or 64 KiB of LDS, or the list is not a
+ * permutation of the batch.  Results never depend on the plan. */
+int ising_batch_set_bundles(ising_batch *b, int32_t nbundles, const int32_t *counts,
+                            const int32_t *lattices);
 
 /* Times every tile candidate of every lattice size in the batch -- each tile
  * also with a half and a quarter of the lattices per workgroup -- over
@@ -273,10 +287,19 @@ int ising_batch_get_plan(const ising_batch *b, int64_t L, uint32_t *lattices_per
  * tile of each size alone can leave bundles for a second round.  From the
  * timings, a longest-first schedule on those workgroups estimates the
  * makespan of each choice; the best estimate is then timed on the whole
- * batch against the fastest tiles of each size and kept if faster.
- * cache_path (may be NULL) is a JSON file keyed by target and kernel version:
- * read if it covers every size, written after tuning.  Synchronises
- * hip_stream; allocates scratch device memory while it runs. */
+ * batch against the fastest tiles of each size and kept if faster.  Then
+ * bundles that mix sizes: from the same timings, each size's tiles get a
+ * duration model (two are tried: a bundle of n lattices takes a + n b, a
+ * workgroup of several sizes max a + sum b; or a + b per round of wavefronts
+ * on the compute unit's SIMDs), lattices are placed largest first where the
+ * model's workgroup duration grows least (sizes whose rows are not whole
+ * 32-bit halves optionally in workgroups of their own), and the plan of each
+ * model replaces the one-size bundles if it runs the whole batch faster
+ * (again with identical lattices).  cache_path (may be NULL) is a JSON file
+ * keyed by target and kernel version: read if it covers every size, written
+ * after tuning.  With ISING_AUTOTUNE_LOG set in the environment the estimates
+ * and timings go to stderr.  Synchronises hip_stream; allocates scratch
+ * device memory while it runs. */
 int ising_batch_autotune(ising_batch *b, int64_t tune_sweeps, const char *cache_path,
                          void *hip_stream);
 

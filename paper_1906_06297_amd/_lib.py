@@ -80,6 +80,10 @@ SIGNATURES = {
     "ising_batch_set_tiles": (ctypes.c_int, [_vp, _i64, _u32, _u32]),
     "ising_batch_get_plan": (ctypes.c_int, [_vp, _i64, ctypes.POINTER(_u32),
                                             ctypes.POINTER(_u32)]),
+    "ising_batch_get_mixed": (ctypes.c_int, [_vp, ctypes.POINTER(ctypes.c_int32)]),
+    "ising_batch_set_bundles": (ctypes.c_int, [_vp, ctypes.c_int32,
+                                               ctypes.POINTER(ctypes.c_int32),
+                                               ctypes.POINTER(ctypes.c_int32)]),
     "ising_batch_autotune": (ctypes.c_int, [_vp, _i64, ctypes.c_char_p, _vp]),
     "ising_batch_get_spins_dev": (ctypes.c_int, [_vp, _vp, _vp]),
     "ising_batch_set_spins_dev": (ctypes.c_int, [_vp, _vp, _vp]),

@@ -17,16 +17,27 @@ struct BatchLattice {
     uint32_t key0, key1, stream_id, pad;
 };
 
-// A work item of the persistent kernel: `count` lattices of one size, swept
-// together by one workgroup.  Thread t serves lattice slot t / tpl; within
-// the slot, lanes form groups of lpw adjacent lanes, and group g serves
-// words g + j * (tpl / lpw), j < wpt.
+// One lattice of a work item and the threads that serve it: threads
+// thread0 .. thread0 + tpl - 1 of the workgroup, in groups of lpw adjacent
+// lanes; group g serves words g + j * (tpl / lpw), j < wpt.  Its two extended
+// colour arrays start at LDS word lds_off.
+struct BatchSlot {
+    uint32_t lat;     // lattice index
+    uint32_t thread0; // first thread (even where lpw = 2)
+    uint32_t tpl;     // threads: ceil(W / wpt) * lpw
+    uint32_t tile;    // wpt | lpw << 16 (lpw 1, or 2: the pair computes alternate Philox blocks)
+    uint32_t lds_off; // first LDS word of the lattice
+};
+
+__host__ __device__ inline uint32_t slot_tile(uint32_t wpt, uint32_t lpw) { return wpt | (lpw << 16); }
+
+// A work item of the persistent kernel: `count` slots -- lattices of one size
+// or of several, each with its own tile -- swept together by one workgroup.
+// Slots are in increasing thread0 and their thread ranges are disjoint.
 struct BatchBundle {
-    uint32_t first; // index of the first slot in the member list
-    uint32_t count; // lattices in the bundle
-    uint32_t wpt;   // words per lane group (per colour)
-    uint32_t tpl;   // threads per lattice: ceil(W / wpt) * lpw
-    uint32_t lpw;   // lanes per word: 1, or 2 (the pair computes alternate Philox blocks)
+    uint32_t first;   // index of the first slot in the slot list
+    uint32_t count;   // slots
+    uint32_t refresh; // 1 if some lattice's colour is not a whole number of words, or one word
     uint32_t pad;
 };
 
@@ -37,7 +48,7 @@ __host__ __device__ inline uint32_t batch_lds_words(uint32_t W) { return 2 * (W 
 
 hipError_t launch_batch_init(const BatchLattice *lats, uint32_t n, uint64_t *words,
                              hipStream_t s);
-hipError_t launch_batch_sweep(const BatchLattice *lats, const uint32_t *members,
+hipError_t launch_batch_sweep(const BatchLattice *lats, const BatchSlot *slots,
                               const BatchBundle *bundles, uint32_t nbundles, uint32_t grid,
                               size_t lds_bytes, uint32_t *next_bundle, uint64_t *words,
                               uint64_t *rng_counter, int64_t nsweeps, hipStream_t s);

@@ -6,6 +6,7 @@
 #include <algorithm>
 #include <cmath>
 #include <cstdio>
+#include <cstdlib>
 #include <cstring>
 #include <fstream>
 #include <map>
@@ -39,9 +40,16 @@ struct ising_batch {
     size_t bytes = 0;
     std::map<int64_t, Tile> tiles;   // per lattice size
     std::map<int64_t, double> est_ms; // tuned duration of one bundle per size, if known
+    // mixed-size bundles (chosen by the autotuner): the duration model of
+    // every size with its tile; otherwise bundles hold one size each
+    bool mixed = false;
+    plan::Model model = plan::kAdditive;
+    std::map<int64_t, plan::Kind> kinds;
+    // the installed plan per size: most lattices in one workgroup, workgroups
+    std::map<int64_t, std::pair<uint32_t, uint32_t>> plan_stats;
     // device state owned by the batch
     BatchLattice *d_lats = nullptr;
-    uint32_t *d_members = nullptr;
+    BatchSlot *d_slots = nullptr;
     BatchBundle *d_bundles = nullptr;
     uint32_t *d_next = nullptr;
     uint64_t *d_counter = nullptr;
@@ -91,10 +99,42 @@ Tile default_tile(uint32_t W)
 }
 
 struct Plan {
-    std::vector<uint32_t> members;
+    std::vector<BatchSlot> slots;
     std::vector<BatchBundle> bundles;
     size_t lds_bytes = 0;
 };
+
+// Appends a bundle of lattices `ids` with their tiles, threads and LDS back
+// to back.  `mixed`: lane-pair lattices first (so pairs start at even
+// threads), then one-lane ones, each group largest first, so that a
+// wavefront rarely serves lattices of different sizes.
+void add_bundle(Plan &p, const ising_batch *b, std::vector<std::pair<uint32_t, Tile>> items,
+                bool mixed)
+{
+    auto threads = [&](const std::pair<uint32_t, Tile> &it) {
+        return threads_per_lattice(b->lats[it.first].W, it.second);
+    };
+    if (mixed)
+        std::stable_sort(items.begin(), items.end(), [&](const auto &x, const auto &y) {
+            if (x.second.lpw != y.second.lpw)
+                return x.second.lpw > y.second.lpw;
+            return b->lats[x.first].L > b->lats[y.first].L;
+        });
+    BatchBundle bd{(uint32_t)p.slots.size(), (uint32_t)items.size(), 0, 0};
+    uint32_t thread = 0, lds = 0;
+    for (const auto &it : items) {
+        const BatchLattice &lt = b->lats[it.first];
+        const uint32_t tpl = threads(it);
+        p.slots.push_back(BatchSlot{it.first, thread, tpl, slot_tile(it.second.wpt, it.second.lpw),
+                                    lds});
+        thread += tpl;
+        lds += batch_lds_words(lt.W);
+        if (!((lt.M & 63) == 0 && lt.W >= 2))
+            bd.refresh = 1;
+    }
+    p.bundles.push_back(bd);
+    p.lds_bytes = std::max(p.lds_bytes, (size_t)lds * 8);
+}
 
 // Bundles of same-size lattices, largest work first.  `only_L` restricts the
 // plan to one size (autotuning) with tile `only`, 0 = all sizes, own tiles.
@@ -111,7 +151,7 @@ Plan make_plan(const ising_batch *b, int64_t only_L, Tile only)
         have_est = have_est && b->est_ms.count(kv.first);
     struct Item {
         double work;
-        BatchBundle bd;
+        Tile tile;
         std::vector<uint32_t> ids;
     };
     std::vector<Item> items;
@@ -119,13 +159,12 @@ Plan make_plan(const ising_batch *b, int64_t only_L, Tile only)
         const int64_t L = kv.first;
         const uint32_t W = words_of(L);
         const Tile tile = only_L ? only : b->tiles.at(L);
-        const uint32_t tpl = threads_per_lattice(W, tile);
         const uint32_t per = lattices_per_bundle(W, tile);
         for (size_t i = 0; i < kv.second.size(); i += per) {
             Item it;
             const uint32_t cnt = (uint32_t)std::min<size_t>(per, kv.second.size() - i);
             it.ids.assign(kv.second.begin() + i, kv.second.begin() + i + cnt);
-            it.bd = BatchBundle{0, cnt, tile.wpt, tpl, tile.lpw, 0};
+            it.tile = tile;
             it.work = have_est ? b->est_ms.at(L) : (double)cnt * (double)(L * L);
             items.push_back(std::move(it));
         }
@@ -134,22 +173,110 @@ Plan make_plan(const ising_batch *b, int64_t only_L, Tile only)
                      [](const Item &a, const Item &c) { return a.work > c.work; });
     Plan p;
     for (auto &it : items) {
-        it.bd.first = (uint32_t)p.members.size();
-        p.members.insert(p.members.end(), it.ids.begin(), it.ids.end());
-        p.bundles.push_back(it.bd);
-        const uint32_t W = b->lats[it.ids[0]].W;
-        p.lds_bytes = std::max(p.lds_bytes, (size_t)it.bd.count * batch_lds_words(W) * 8);
+        std::vector<std::pair<uint32_t, Tile>> v;
+        for (uint32_t q : it.ids)
+            v.emplace_back(q, it.tile);
+        add_bundle(p, b, std::move(v), false);
     }
     return p;
 }
 
+// What the persistent kernel relies on, checked on the host before a plan
+// is launched: every lattice in at most one slot (`all`: in exactly one); in
+// each bundle, slots in increasing, disjoint thread ranges within the
+// workgroup, lane pairs at even threads, the slot's threads matching its
+// tile, and its LDS range within the launch's LDS and apart from the others.
+int check_plan(const BatchLattice *lats, int32_t n, const BatchSlot *slots, size_t nslots,
+               const BatchBundle *bundles, size_t nbundles, size_t lds_bytes, bool all = true)
+{
+    std::vector<uint8_t> seen((size_t)n, 0);
+    size_t used = 0;
+    for (size_t bi = 0; bi < nbundles; ++bi) {
+        const BatchBundle &bd = bundles[bi];
+        if (bd.count == 0 || (size_t)bd.first + bd.count > nslots)
+            return host::fail(ISING_E_HIP, "batch plan: bundle %zu has no slots in range", bi);
+        uint32_t thread_end = 0, lds_end = 0;
+        bool refresh = false;
+        for (uint32_t i = 0; i < bd.count; ++i) {
+            const BatchSlot &sl = slots[bd.first + i];
+            const uint32_t wpt = sl.tile & 0xFFFFu, lpw = sl.tile >> 16;
+            if (sl.lat >= (uint32_t)n || seen[sl.lat])
+                return host::fail(ISING_E_HIP, "batch plan: lattice %u missing or repeated",
+                                  sl.lat);
+            seen[sl.lat] = 1;
+            ++used;
+            const BatchLattice &lt = lats[sl.lat];
+            if (wpt < 1 || (lpw != 1 && lpw != 2) ||
+                sl.tpl != threads_per_lattice(lt.W, Tile{wpt, lpw}) ||
+                (lpw == 2 && (sl.thread0 & 1)) || sl.thread0 < thread_end ||
+                sl.thread0 + sl.tpl > (uint32_t)kBatchThreads || sl.lds_off < lds_end ||
+                ((size_t)sl.lds_off + batch_lds_words(lt.W)) * 8 > lds_bytes)
+                return host::fail(ISING_E_HIP, "batch plan: slot %u of bundle %zu does not fit", i,
+                                  bi);
+            thread_end = sl.thread0 + sl.tpl;
+            lds_end = sl.lds_off + batch_lds_words(lt.W);
+            refresh = refresh || !((lt.M & 63) == 0 && lt.W >= 2);
+        }
+        if (refresh && !bd.refresh)
+            return host::fail(ISING_E_HIP, "batch plan: bundle %zu needs the refresh barrier", bi);
+    }
+    if (all && used != (size_t)n)
+        return host::fail(ISING_E_HIP, "batch plan: %zu of %d lattices placed", used, (int)n);
+    return ISING_OK;
+}
+
+// Threads a lattice of W words takes in a mixed bundle.
+uint32_t mixed_threads(uint32_t W, Tile t) { return threads_per_lattice(W, t); }
+
+// Mixed-size bundles from the duration model of every size (b->kinds, with
+// the tiles in b->tiles) on `slots` workgroups, longest estimate first.
+bool make_mixed_plan(const ising_batch *b, uint32_t slots, Plan *out, double *makespan)
+{
+    std::vector<plan::Kind> kinds;
+    std::map<int64_t, uint32_t> kind_of;
+    for (auto &kv : b->tiles) {
+        auto it = b->kinds.find(kv.first);
+        if (it == b->kinds.end())
+            return false;
+        plan::Kind k = it->second;
+        const uint32_t W = words_of(kv.first);
+        k.threads = mixed_threads(W, kv.second);
+        k.lds_words = batch_lds_words(W);
+        kind_of[kv.first] = (uint32_t)kinds.size();
+        kinds.push_back(k);
+    }
+    std::vector<uint32_t> item_kind((size_t)b->n);
+    for (int32_t q = 0; q < b->n; ++q)
+        item_kind[(size_t)q] = kind_of.at(b->Ls[(size_t)q]);
+    const plan::Packing pk = plan::pack_mixed(kinds, item_kind, slots, (uint32_t)kBatchThreads,
+                                              (uint32_t)(kMaxBundleLds / 8), b->model);
+    if (!pk.ok)
+        return false;
+    std::vector<size_t> order(pk.groups.size());
+    for (size_t i = 0; i < order.size(); ++i)
+        order[i] = i;
+    std::stable_sort(order.begin(), order.end(),
+                     [&](size_t x, size_t y) { return pk.est[x] > pk.est[y]; });
+    Plan p;
+    for (size_t gi : order) {
+        std::vector<std::pair<uint32_t, Tile>> v;
+        for (uint32_t q : pk.groups[gi])
+            v.emplace_back(q, b->tiles.at(b->Ls[q]));
+        add_bundle(p, b, std::move(v), true);
+    }
+    *out = std::move(p);
+    if (makespan)
+        *makespan = pk.makespan;
+    return true;
+}
+
 void free_plan_buffers(ising_batch *b)
 {
-    if (b->d_members)
-        (void)hipFree(b->d_members);
+    if (b->d_slots)
+        (void)hipFree(b->d_slots);
     if (b->d_bundles)
         (void)hipFree(b->d_bundles);
-    b->d_members = nullptr;
+    b->d_slots = nullptr;
     b->d_bundles = nullptr;
     if (b->exec)
         (void)hipGraphExecDestroy(b->exec);
@@ -188,12 +315,16 @@ int persistent_grid(size_t lds_bytes, uint32_t nbundles, uint32_t *grid)
 
 int install_plan(ising_batch *b, const Plan &p)
 {
+    if (int rc = check_plan(b->lats.data(), b->n, p.slots.data(), p.slots.size(),
+                            p.bundles.data(), p.bundles.size(), p.lds_bytes))
+        return rc;
     free_plan_buffers(b);
-    hipError_t e = hipMalloc(&b->d_members, std::max<size_t>(1, p.members.size()) * 4);
+    hipError_t e = hipMalloc(&b->d_slots, std::max<size_t>(1, p.slots.size()) * sizeof(BatchSlot));
     if (e == hipSuccess)
         e = hipMalloc(&b->d_bundles, std::max<size_t>(1, p.bundles.size()) * sizeof(BatchBundle));
-    if (e == hipSuccess && !p.members.empty())
-        e = hipMemcpy(b->d_members, p.members.data(), p.members.size() * 4, hipMemcpyHostToDevice);
+    if (e == hipSuccess && !p.slots.empty())
+        e = hipMemcpy(b->d_slots, p.slots.data(), p.slots.size() * sizeof(BatchSlot),
+                      hipMemcpyHostToDevice);
     if (e == hipSuccess && !p.bundles.empty())
         e = hipMemcpy(b->d_bundles, p.bundles.data(), p.bundles.size() * sizeof(BatchBundle),
                       hipMemcpyHostToDevice);
@@ -201,7 +332,34 @@ int install_plan(ising_batch *b, const Plan &p)
         return host::hip_fail(e, "batch plan upload");
     b->nbundles = (uint32_t)p.bundles.size();
     b->lds_bytes = p.lds_bytes;
+    b->plan_stats.clear();
+    for (const BatchBundle &bd : p.bundles) {
+        std::map<int64_t, uint32_t> here;
+        for (uint32_t i = 0; i < bd.count; ++i)
+            ++here[b->Ls[p.slots[bd.first + i].lat]];
+        for (auto &kv : here) {
+            auto &st = b->plan_stats[kv.first];
+            st.first = std::max(st.first, kv.second);
+            ++st.second;
+        }
+    }
     return persistent_grid(p.lds_bytes, b->nbundles, &b->grid);
+}
+
+// The plan the batch's settings call for: mixed-size bundles when the
+// autotuner chose them, else one size per bundle.
+int install_current_plan(ising_batch *b)
+{
+    if (b->mixed) {
+        uint32_t slots = 0;
+        if (int rc = resident_slots(kMaxBundleLds, &slots))
+            return rc;
+        Plan p;
+        if (make_mixed_plan(b, slots, &p, nullptr))
+            return install_plan(b, p);
+        b->mixed = false;
+    }
+    return install_plan(b, make_plan(b, 0, Tile{1, 1}));
 }
 
 int check_batch(const ising_batch *b)
@@ -302,8 +460,9 @@ size_t align256(size_t v) { return (v + 255) & ~(size_t)255; }
 struct NoAllocPlan {
     BatchLattice lats[kNoAllocMaxLattices];
     uint32_t order[kNoAllocMaxLattices];
-    uint32_t members[kNoAllocMaxLattices];
+    BatchSlot slots[kNoAllocMaxLattices];
     BatchBundle bundles[kNoAllocMaxLattices];
+    Tile tile_of[kNoAllocMaxLattices]; // tile of each bundle
     double work[kNoAllocMaxLattices];
     uint32_t border[kNoAllocMaxLattices];
     uint32_t nbundles = 0;
@@ -344,10 +503,12 @@ struct NoAllocPlan {
             while (g1 < n && lats[order[g1]].L == L)
                 ++g1;
             const Tile tile = default_tile(W);
-            const uint32_t tpl = threads_per_lattice(W, tile), per = lattices_per_bundle(W, tile);
+            const uint32_t per = lattices_per_bundle(W, tile);
+            const uint32_t refresh = ((lats[order[g0]].M & 63) == 0 && W >= 2) ? 0u : 1u;
             for (int32_t k = g0; k < g1; k += (int32_t)per) {
                 const uint32_t cnt = (uint32_t)std::min<int32_t>((int32_t)per, g1 - k);
-                bundles[nbundles] = BatchBundle{(uint32_t)k, cnt, tile.wpt, tpl, tile.lpw, 0};
+                bundles[nbundles] = BatchBundle{(uint32_t)k, cnt, refresh, 0};
+                tile_of[nbundles] = Tile{tile.wpt, tile.lpw};
                 work[nbundles] = (double)cnt * (double)L * (double)L;
                 border[nbundles] = nbundles;
                 lds_bytes = std::max(lds_bytes, (size_t)cnt * batch_lds_words(W) * 8);
@@ -358,13 +519,19 @@ struct NoAllocPlan {
         std::sort(border, border + nbundles, [this](uint32_t a, uint32_t b) {
             return work[a] != work[b] ? work[a] > work[b] : a < b;
         });
-        // bundles in that order, each with its members contiguous
+        // bundles in that order, each with its lattices' slots contiguous
+        // (threads and LDS back to back, as a batch handle's one-size bundles)
         uint32_t m = 0;
         BatchBundle *sorted = (BatchBundle *)stage; // reuse the stage as room to permute
         for (uint32_t k = 0; k < nbundles; ++k) {
             BatchBundle bd = bundles[border[k]];
-            for (uint32_t c = 0; c < bd.count; ++c)
-                members[m + c] = order[bd.first + c];
+            const Tile t = tile_of[border[k]];
+            for (uint32_t c = 0; c < bd.count; ++c) {
+                const uint32_t q = order[bd.first + c];
+                const uint32_t tpl = threads_per_lattice(lats[q].W, t);
+                slots[m + c] = BatchSlot{q, c * tpl, tpl, slot_tile(t.wpt, t.lpw),
+                                         c * batch_lds_words(lats[q].W)};
+            }
             bd.first = m;
             m += bd.count;
             sorted[k] = bd;
@@ -379,9 +546,19 @@ std::mutex g_noalloc_mu;
 
 
 // ---------------------------------------------------------------- cache file
-std::string cache_key() { return "gfx950/batch-sweep-v8"; }
+std::string cache_key() { return "gfx950/batch-sweep-v11"; }
 
-bool read_cache(const char *path, std::map<int64_t, Tile> &out)
+// Tiles per size ([wpt, lpw, cap, a, b, exclusive]: a and b the duration
+// model of the size with that tile, for mixed-size bundles, and whether its
+// lattices keep workgroups of their own), whether bundles mix sizes and
+// under which duration model they were packed.
+struct CacheEntry {
+    Tile tile{1, 1};
+    plan::Kind kind;
+};
+
+bool read_cache(const char *path, std::map<int64_t, CacheEntry> &out, bool *mixed,
+                plan::Model *model)
 {
     std::ifstream f(path);
     if (!f)
@@ -392,6 +569,8 @@ bool read_cache(const char *path, std::map<int64_t, Tile> &out)
     const std::string tag = "\"key\": \"" + cache_key() + "\"";
     if (s.find(tag) == std::string::npos)
         return false;
+    *mixed = s.find("\"mixed\": 1") != std::string::npos;
+    *model = s.find("\"model\": 1") != std::string::npos ? plan::kRounds : plan::kAdditive;
     size_t pos = s.find("\"tiles\"");
     if (pos == std::string::npos)
         return false;
@@ -406,21 +585,35 @@ bool read_cache(const char *path, std::map<int64_t, Tile> &out)
     std::istringstream in(body);
     long long L;
     unsigned w, l, c;
-    while (in >> L >> w >> l >> c)
-        out[(int64_t)L] = Tile{w, l, c};
+    double a, bb;
+    unsigned excl;
+    while (in >> L >> w >> l >> c >> a >> bb >> excl) {
+        CacheEntry e;
+        e.tile = Tile{w, l, c};
+        e.kind.a = a;
+        e.kind.b = bb;
+        e.kind.exclusive = excl != 0;
+        out[(int64_t)L] = e;
+    }
     return true;
 }
 
-bool write_cache(const char *path, const std::map<int64_t, Tile> &tiles)
+bool write_cache(const char *path, const ising_batch *b)
 {
     std::ofstream f(path);
     if (!f)
         return false;
-    f << "{\"key\": \"" << cache_key() << "\", \"tiles\": {";
+    f.precision(17);
+    f << "{\"key\": \"" << cache_key() << "\", \"mixed\": " << (b->mixed ? 1 : 0)
+      << ", \"model\": " << (int)b->model << ", \"tiles\": {";
     bool first = true;
-    for (auto &kv : tiles) {
+    for (auto &kv : b->tiles) {
+        auto k = b->kinds.find(kv.first);
+        const bool have = k != b->kinds.end();
         f << (first ? "" : ", ") << "\"" << kv.first << "\": [" << kv.second.wpt << ", "
-          << kv.second.lpw << ", " << kv.second.cap << "]";
+          << kv.second.lpw << ", " << kv.second.cap << ", " << (have ? k->second.a : 0.0)
+          << ", " << (have ? k->second.b : 0.0) << ", " << (have && k->second.exclusive ? 1 : 0)
+          << "]";
         first = false;
     }
     f << "}}\n";
@@ -583,7 +776,7 @@ int ising_batch_sweep(ising_batch *b, int64_t nsweeps, void *hip_stream)
         hipGraph_t graph = nullptr;
         hipError_t e = hipStreamBeginCapture(b->capture_stream, hipStreamCaptureModeThreadLocal);
         if (e == hipSuccess) {
-            hipError_t le = launch_batch_sweep(b->d_lats, b->d_members, b->d_bundles, b->nbundles,
+            hipError_t le = launch_batch_sweep(b->d_lats, b->d_slots, b->d_bundles, b->nbundles,
                                                b->grid, b->lds_bytes, b->d_next, b->words,
                                                b->d_counter, nsweeps, b->capture_stream);
             e = hipStreamEndCapture(b->capture_stream, &graph);
@@ -666,10 +859,62 @@ int ising_batch_get_plan(const ising_batch *b, int64_t L, uint32_t *lattices_per
     auto it = b->tiles.find(L);
     if (!lattices_per_workgroup || !workgroups || it == b->tiles.end())
         return host::fail(ISING_E_BADARG, "no lattice of that size in the batch");
-    const uint32_t n = (uint32_t)std::count(b->Ls.begin(), b->Ls.end(), L);
-    const uint32_t per = lattices_per_bundle(words_of(L), it->second);
-    *lattices_per_workgroup = std::min(per, n);
-    *workgroups = (n + per - 1) / per;
+    auto st = b->plan_stats.find(L);
+    *lattices_per_workgroup = st == b->plan_stats.end() ? 0 : st->second.first;
+    *workgroups = st == b->plan_stats.end() ? 0 : st->second.second;
+    return host::ok();
+}
+
+int ising_batch_set_bundles(ising_batch *b, int32_t nbundles, const int32_t *counts,
+                            const int32_t *lattices)
+{
+    if (int e = check_batch(b))
+        return e;
+    if (nbundles <= 0 || !counts || !lattices)
+        return host::fail(ISING_E_BADARG, "no bundles or null pointer");
+    Plan p;
+    int64_t at = 0;
+    std::vector<uint8_t> seen((size_t)b->n, 0);
+    for (int32_t i = 0; i < nbundles; ++i) {
+        if (counts[i] <= 0 || at + counts[i] > b->n)
+            return host::fail(ISING_E_BADARG, "bundle %d: count %d out of range", (int)i,
+                              (int)counts[i]);
+        std::vector<std::pair<uint32_t, Tile>> v;
+        uint32_t threads = 0, lds = 0;
+        for (int32_t c = 0; c < counts[i]; ++c, ++at) {
+            const int32_t q = lattices[at];
+            if (q < 0 || q >= b->n || seen[(size_t)q])
+                return host::fail(ISING_E_BADARG, "lattice %d missing, repeated or out of range",
+                                  (int)q);
+            seen[(size_t)q] = 1;
+            const Tile t = b->tiles.at(b->Ls[(size_t)q]);
+            threads += mixed_threads(b->lats[(size_t)q].W, t);
+            lds += batch_lds_words(b->lats[(size_t)q].W);
+            v.emplace_back((uint32_t)q, t);
+        }
+        if (threads > (uint32_t)kBatchThreads || (size_t)lds * 8 > kMaxBundleLds)
+            return host::fail(ISING_E_BADARG, "bundle %d needs %u threads and %u B of LDS (at most "
+                              "%d and %zu)", (int)i, threads, lds * 8, kBatchThreads,
+                              kMaxBundleLds);
+        add_bundle(p, b, std::move(v), true);
+    }
+    if (at != b->n)
+        return host::fail(ISING_E_BADARG, "the bundles hold %lld of %d lattices", (long long)at,
+                          (int)b->n);
+    if (int rc = install_plan(b, p))
+        return rc;
+    b->mixed = true;
+    b->est_ms.clear();
+    return host::ok();
+}
+
+int ising_batch_get_mixed(const ising_batch *b, int32_t *mixed)
+{
+    if (int e = check_batch(b))
+        return e;
+    if (!mixed)
+        return host::fail(ISING_E_BADARG, "null output");
+    *mixed = b->mixed ? 1 : 0;
     return host::ok();
 }
 
@@ -685,6 +930,7 @@ int ising_batch_set_tiles(ising_batch *b, int64_t L, uint32_t wpt, uint32_t lpw)
                           "workgroup of %d threads", wpt, lpw, kBatchThreads);
     it->second = Tile{wpt, lpw};
     b->est_ms.erase(L); // bundles go back to ordering by spins
+    b->mixed = false;   // and to one size each
     return install_plan(b, make_plan(b, 0, Tile{1, 1}));
 }
 
@@ -696,23 +942,34 @@ int ising_batch_autotune(ising_batch *b, int64_t tune_sweeps, const char *cache_
     if (tune_sweeps <= 0)
         return host::fail(ISING_E_BADARG, "tune_sweeps must be > 0");
     hipStream_t s = (hipStream_t)hip_stream;
+    // ISING_AUTOTUNE_LOG set: the plans' estimates and timings to stderr
+    const bool log = std::getenv("ISING_AUTOTUNE_LOG") != nullptr;
     b->est_ms.clear();
-    std::map<int64_t, Tile> cached;
-    if (cache_path && read_cache(cache_path, cached)) {
+    b->kinds.clear();
+    b->mixed = false;
+    std::map<int64_t, CacheEntry> cached;
+    bool cached_mixed = false;
+    plan::Model cached_model = plan::kAdditive;
+    if (cache_path && read_cache(cache_path, cached, &cached_mixed, &cached_model)) {
         bool complete = true;
         for (auto &kv : b->tiles)
             complete = complete && cached.count(kv.first) &&
-                       tile_ok(words_of(kv.first), cached[kv.first]);
+                       tile_ok(words_of(kv.first), cached[kv.first].tile);
         if (complete) {
-            for (auto &kv : b->tiles)
-                kv.second = cached[kv.first];
-            return install_plan(b, make_plan(b, 0, Tile{1, 1}));
+            for (auto &kv : b->tiles) {
+                kv.second = cached[kv.first].tile;
+                b->kinds[kv.first] = cached[kv.first].kind;
+            }
+            b->mixed = cached_mixed;
+            b->model = cached_model;
+            return install_current_plan(b);
         }
     }
     // Scratch copy of the lattices and counter: tuning never changes the batch.
     const size_t nbytes = (size_t)ising_batch_words(b->n, b->Ls.data()) * 8;
     uint64_t *scratch = nullptr, *ctr = nullptr;
-    uint32_t *members = nullptr, *next = nullptr;
+    uint32_t *next = nullptr;
+    BatchSlot *slot_buf = nullptr;
     BatchBundle *bundles = nullptr;
     hipEvent_t e0 = nullptr, e1 = nullptr;
     hipError_t e = hipMalloc(&scratch, nbytes);
@@ -729,19 +986,23 @@ int ising_batch_autotune(ising_batch *b, int64_t tune_sweeps, const char *cache_
     // lattices and counter 0 every time; best of two launches, lattices to out.
     auto time_plan = [&](const Plan &p, float *best, std::vector<uint64_t> &out) -> bool {
         uint32_t grid = 0;
+        if ((rc = check_plan(b->lats.data(), b->n, p.slots.data(), p.slots.size(),
+                             p.bundles.data(), p.bundles.size(), p.lds_bytes, false)))
+            return false;
         if ((rc = persistent_grid(p.lds_bytes, (uint32_t)p.bundles.size(), &grid)))
             return false;
-        if (members)
-            (void)hipFree(members);
+        if (slot_buf)
+            (void)hipFree(slot_buf);
         if (bundles)
             (void)hipFree(bundles);
-        members = nullptr;
+        slot_buf = nullptr;
         bundles = nullptr;
-        e = hipMalloc(&members, p.members.size() * 4);
+        e = hipMalloc(&slot_buf, p.slots.size() * sizeof(BatchSlot));
         if (e == hipSuccess)
             e = hipMalloc(&bundles, p.bundles.size() * sizeof(BatchBundle));
         if (e == hipSuccess)
-            e = hipMemcpy(members, p.members.data(), p.members.size() * 4, hipMemcpyHostToDevice);
+            e = hipMemcpy(slot_buf, p.slots.data(), p.slots.size() * sizeof(BatchSlot),
+                          hipMemcpyHostToDevice);
         if (e == hipSuccess)
             e = hipMemcpy(bundles, p.bundles.data(), p.bundles.size() * sizeof(BatchBundle),
                           hipMemcpyHostToDevice);
@@ -755,7 +1016,7 @@ int ising_batch_autotune(ising_batch *b, int64_t tune_sweeps, const char *cache_
             if (e == hipSuccess)
                 e = hipEventRecord(e0, s);
             if (e == hipSuccess)
-                e = launch_batch_sweep(b->d_lats, members, bundles, (uint32_t)p.bundles.size(),
+                e = launch_batch_sweep(b->d_lats, slot_buf, bundles, (uint32_t)p.bundles.size(),
                                        grid, p.lds_bytes, next, scratch, ctr, tune_sweeps, s);
             if (e == hipSuccess)
                 e = hipEventRecord(e1, s);
@@ -775,6 +1036,7 @@ int ising_batch_autotune(ising_batch *b, int64_t tune_sweeps, const char *cache_
     std::vector<int64_t> sizes;
     std::vector<std::vector<plan::Option>> opts;
     std::vector<std::vector<Tile>> opt_tiles;
+    std::vector<std::vector<uint32_t>> opt_per; // lattices in the option's fullest bundle
     std::vector<size_t> fastest;
     uint32_t slots = 0;
     std::vector<uint64_t> out_ref, out_try;
@@ -807,6 +1069,7 @@ int ising_batch_autotune(ising_batch *b, int64_t tune_sweeps, const char *cache_
         }
         std::vector<plan::Option> o;
         std::vector<Tile> ot;
+        std::vector<uint32_t> op;
         size_t fi = 0;
         for (const Tile &w : cands) {
             const Plan p = make_plan(b, L, w);
@@ -825,6 +1088,7 @@ int ising_batch_autotune(ising_batch *b, int64_t tune_sweeps, const char *cache_
             }
             o.push_back(plan::Option{(uint32_t)p.bundles.size(), (double)ms});
             ot.push_back(w);
+            op.push_back(p.bundles.front().count);
             if (o.back().ms < o[fi].ms)
                 fi = o.size() - 1;
         }
@@ -833,6 +1097,7 @@ int ising_batch_autotune(ising_batch *b, int64_t tune_sweeps, const char *cache_
         sizes.push_back(L);
         opts.push_back(std::move(o));
         opt_tiles.push_back(std::move(ot));
+        opt_per.push_back(std::move(op));
         fastest.push_back(fi);
     }
     // The tiles for the whole launch: the estimated best, kept only if the
@@ -844,12 +1109,15 @@ int ising_batch_autotune(ising_batch *b, int64_t tune_sweeps, const char *cache_
             b->est_ms[sizes[i]] = plan::bundle_ms(opts[i][pick[i]], slots);
         }
     };
+    float ms_best = 0.f;
+    std::vector<size_t> pick;
     if (e == hipSuccess && rc == ISING_OK) {
-        std::vector<size_t> pick = plan::choose(opts, fastest, slots);
-        if (pick != fastest) {
-            float ms_fast = 0.f, ms_pick = 0.f;
-            apply(fastest);
-            if (time_plan(make_plan(b, 0, Tile{1, 1}), &ms_fast, out_ref)) {
+        pick = plan::choose(opts, fastest, slots);
+        float ms_fast = 0.f, ms_pick = 0.f;
+        apply(fastest);
+        if (time_plan(make_plan(b, 0, Tile{1, 1}), &ms_fast, out_ref)) {
+            ms_best = ms_fast;
+            if (pick != fastest) {
                 apply(pick);
                 if (time_plan(make_plan(b, 0, Tile{1, 1}), &ms_pick, out_try)) {
                     if (out_try != out_ref)
@@ -857,14 +1125,173 @@ int ising_batch_autotune(ising_batch *b, int64_t tune_sweeps, const char *cache_
                                         "lattices");
                     else if (ms_fast < ms_pick)
                         pick = fastest;
+                    else
+                        ms_best = ms_pick;
                 }
             }
         }
         if (e == hipSuccess && rc == ISING_OK)
             apply(pick);
     }
-    if (members)
-        (void)hipFree(members);
+    // Mixed-size bundles.  For each duration model, (a, b) per size and tile
+    // from the timings above; tiles per size by one of two rules -- the
+    // cheapest per lattice among the tiles whose single lattice fits the
+    // one-size plan's makespan, or the one-size plan's own tiles -- each with
+    // every size mixing, or with the sizes whose colour rows are not whole
+    // 32-bit halves (general neighbour extraction, long per-word chains) in
+    // workgroups of their own.  The best estimate of each model is timed on
+    // the whole batch; the fastest replaces the one-size plan if faster.
+    if (e == hipSuccess && rc == ISING_OK && !sizes.empty()) {
+        const double hom_est = plan::estimate(opts, pick, slots).makespan;
+        if (log)
+            std::fprintf(stderr, "[autotune] one-size plan: estimated %.4f ms, timed %.4f ms, "
+                         "%u workgroups\n", hom_est, (double)ms_best, slots);
+        const std::map<int64_t, Tile> hom_tiles = b->tiles;
+        float ms_mixed_best = 0.f;
+        std::map<int64_t, Tile> keep_tiles;
+        std::map<int64_t, plan::Kind> keep_kinds;
+        plan::Model keep_model = plan::kAdditive;
+        for (plan::Model model : {plan::kAdditive, plan::kRounds}) {
+            if (e != hipSuccess || rc != ISING_OK)
+                break;
+            std::vector<std::vector<plan::Kind>> fits(sizes.size());
+            std::vector<std::vector<Tile>> fit_tiles(sizes.size());
+            std::vector<std::vector<bool>> fit_two(sizes.size()); // fitted through two x
+            std::vector<double> intercepts;
+            for (int pass = 0; pass < 2; ++pass) {
+                double a_def = 0.0;
+                if (pass == 1 && !intercepts.empty()) {
+                    std::sort(intercepts.begin(), intercepts.end());
+                    a_def = intercepts[intercepts.size() / 2];
+                }
+                for (size_t i = 0; i < sizes.size(); ++i) {
+                    std::map<std::pair<uint32_t, uint32_t>,
+                             std::vector<std::pair<uint32_t, double>>>
+                        pts;
+                    for (size_t j = 0; j < opts[i].size(); ++j)
+                        pts[{opt_tiles[i][j].wpt, opt_tiles[i][j].lpw}].emplace_back(
+                            opt_per[i][j], plan::bundle_ms(opts[i][j], slots));
+                    fits[i].clear();
+                    fit_tiles[i].clear();
+                    fit_two[i].clear();
+                    for (auto &kv : pts) {
+                        const Tile t{kv.first.first, kv.first.second};
+                        const uint32_t tpl = threads_per_lattice(words_of(sizes[i]), t);
+                        plan::Kind k;
+                        plan::fit_kind(kv.second, tpl, model, a_def, &k.a, &k.b);
+                        auto x = [&](uint32_t n) {
+                            return model == plan::kRounds ? plan::simd_waves(n * tpl) : n;
+                        };
+                        bool two = false;
+                        for (auto &pt : kv.second)
+                            two = two || x(pt.first) != x(kv.second.front().first);
+                        if (pass == 0 && two)
+                            intercepts.push_back(k.a);
+                        fits[i].push_back(k);
+                        fit_tiles[i].push_back(t);
+                        fit_two[i].push_back(two);
+                    }
+                }
+            }
+            double best_est = 0.0;
+            std::map<int64_t, Tile> best_tiles;
+            std::map<int64_t, plan::Kind> best_kinds;
+            for (int rule = 0; rule < 4; ++rule) {
+                std::map<int64_t, Tile> tiles;
+                std::map<int64_t, plan::Kind> kinds;
+                for (size_t i = 0; i < sizes.size(); ++i) {
+                    auto tpl = [&](size_t jj) {
+                        return threads_per_lattice(words_of(sizes[i]), fit_tiles[i][jj]);
+                    };
+                    // per-lattice share of the compute unit, and one lattice alone
+                    auto cost = [&](size_t jj) {
+                        return model == plan::kRounds ? fits[i][jj].b * (double)tpl(jj)
+                                                      : fits[i][jj].b;
+                    };
+                    auto alone = [&](size_t jj) {
+                        return plan::group_time(model, fits[i][jj].a, fits[i][jj].b,
+                                                fits[i][jj].b, tpl(jj));
+                    };
+                    size_t c = SIZE_MAX;
+                    bool any_two = false;
+                    for (size_t j = 0; j < fits[i].size(); ++j)
+                        any_two = any_two || fit_two[i][j];
+                    for (size_t j = 0; j < fits[i].size(); ++j) {
+                        if (rule % 2 == 1) {
+                            const Tile &h = hom_tiles.at(sizes[i]);
+                            if (fit_tiles[i][j].wpt == h.wpt && fit_tiles[i][j].lpw == h.lpw)
+                                c = j;
+                        } else if ((!any_two || fit_two[i][j]) && alone(j) <= hom_est &&
+                                   (c == SIZE_MAX || cost(j) < cost(c) ||
+                                    (cost(j) == cost(c) && fits[i][j].a < fits[i][c].a))) {
+                            c = j; // (a one-x fit only guesses its split into a and b)
+                        }
+                    }
+                    if (c == SIZE_MAX)
+                        c = 0;
+                    tiles[sizes[i]] = fit_tiles[i][c];
+                    kinds[sizes[i]] = fits[i][c];
+                    kinds[sizes[i]].exclusive = rule >= 2 && (sizes[i] % 64) != 0;
+                }
+                b->tiles = tiles;
+                b->kinds = kinds;
+                b->model = model;
+                Plan p;
+                double est = 0.0;
+                const bool packed = make_mixed_plan(b, slots, &p, &est);
+                if (log) {
+                    std::fprintf(stderr, "[autotune] %s model, rule %d: %s, estimated %.4f ms\n",
+                                 model == plan::kRounds ? "rounds" : "additive", rule,
+                                 packed ? "packed" : "does not pack", est);
+                    for (auto &kv : tiles)
+                        std::fprintf(stderr, "[autotune]   L=%lld tile (%u, %u) a=%.4f b=%.5f%s\n",
+                                     (long long)kv.first, kv.second.wpt, kv.second.lpw,
+                                     kinds[kv.first].a, kinds[kv.first].b,
+                                     kinds[kv.first].exclusive ? " own workgroups" : "");
+                }
+                if (packed && (best_tiles.empty() || est < best_est)) {
+                    best_est = est;
+                    best_tiles = tiles;
+                    best_kinds = kinds;
+                }
+            }
+            if (best_tiles.empty())
+                continue;
+            b->tiles = best_tiles;
+            b->kinds = best_kinds;
+            b->model = model;
+            Plan p;
+            float ms_mixed = 0.f;
+            if (make_mixed_plan(b, slots, &p, nullptr) && time_plan(p, &ms_mixed, out_try)) {
+                if (log)
+                    std::fprintf(stderr, "[autotune] %s model: mixed plan timed %.4f ms\n",
+                                 model == plan::kRounds ? "rounds" : "additive",
+                                 (double)ms_mixed);
+                if (out_try != out_ref)
+                    rc = host::fail(ISING_E_HIP, "autotune: mixed-size bundles changed the "
+                                    "lattices");
+                else if (ms_mixed < ms_best && (keep_tiles.empty() || ms_mixed < ms_mixed_best)) {
+                    ms_mixed_best = ms_mixed;
+                    keep_tiles = best_tiles;
+                    keep_kinds = best_kinds;
+                    keep_model = model;
+                }
+            }
+        }
+        if (!keep_tiles.empty() && rc == ISING_OK && e == hipSuccess) {
+            b->tiles = keep_tiles;
+            b->kinds = keep_kinds;
+            b->model = keep_model;
+            b->mixed = true;
+        } else {
+            b->tiles = hom_tiles;
+            b->kinds.clear();
+            b->model = plan::kAdditive;
+            b->mixed = false;
+        }
+    }
+    if (slot_buf)
+        (void)hipFree(slot_buf);
     if (bundles)
         (void)hipFree(bundles);
     if (scratch)
@@ -877,15 +1304,18 @@ int ising_batch_autotune(ising_batch *b, int64_t tune_sweeps, const char *cache_
         (void)hipEventDestroy(e0);
     if (e1)
         (void)hipEventDestroy(e1);
-    if (rc != ISING_OK || e != hipSuccess)
+    if (rc != ISING_OK || e != hipSuccess) {
         b->est_ms.clear();
+        b->kinds.clear();
+        b->mixed = false;
+    }
     if (rc != ISING_OK)
         return rc;
     if (e != hipSuccess)
         return host::hip_fail(e, "autotune");
-    if (cache_path && !write_cache(cache_path, b->tiles))
+    if (cache_path && !write_cache(cache_path, b))
         return host::fail(ISING_E_BADARG, "cannot write the autotune cache %s", cache_path);
-    return install_plan(b, make_plan(b, 0, Tile{1, 1}));
+    return install_current_plan(b);
 }
 
 int ising_batch_sweep_noalloc(int32_t n, const int64_t *Ls, const double *betas, double J,
@@ -909,13 +1339,15 @@ int ising_batch_sweep_noalloc(int32_t n, const int64_t *Ls, const double *betas,
     NoAllocPlan &p = g_noalloc_plan;
     if (int r = p.build(n, Ls, betas, J, seeds, stream_ids))
         return r;
+    if (int r = check_plan(p.lats, n, p.slots, (size_t)n, p.bundles, p.nbundles, p.lds_bytes))
+        return r;
     uint32_t grid = 0;
     if (int r = persistent_grid(p.lds_bytes, p.nbundles, &grid))
         return r;
-    // scratch layout: sweep counter, queue counter | lattices | members | bundles
+    // scratch layout: sweep counter, queue counter | lattices | slots | bundles
     const size_t o_lats = 256;
-    const size_t o_members = align256(o_lats + (size_t)n * sizeof(BatchLattice));
-    const size_t o_bundles = align256(o_members + (size_t)n * sizeof(uint32_t));
+    const size_t o_slots = align256(o_lats + (size_t)n * sizeof(BatchLattice));
+    const size_t o_bundles = align256(o_slots + (size_t)n * sizeof(BatchSlot));
     const size_t total = o_bundles + (size_t)p.nbundles * sizeof(BatchBundle);
     if (total > kNoAllocScratchBytes)
         return host::fail(ISING_E_SIZE, "descriptors need %zu bytes, the scratch array holds %zu",
@@ -927,13 +1359,13 @@ int ising_batch_sweep_noalloc(int32_t n, const int64_t *Ls, const double *betas,
     std::memset(stage, 0, o_lats);
     std::memcpy(stage, &rng_counter, sizeof(rng_counter));
     std::memcpy(stage + o_lats, p.lats, (size_t)n * sizeof(BatchLattice));
-    std::memcpy(stage + o_members, p.members, (size_t)n * sizeof(uint32_t));
+    std::memcpy(stage + o_slots, p.slots, (size_t)n * sizeof(BatchSlot));
     std::memcpy(stage + o_bundles, p.bundles, (size_t)p.nbundles * sizeof(BatchBundle));
     hipStream_t s = (hipStream_t)hip_stream;
     hipError_t e = hipMemcpyAsync(ptr, stage, total, hipMemcpyHostToDevice, s);
     if (e == hipSuccess)
         e = launch_batch_sweep((const BatchLattice *)(ptr + o_lats),
-                               (const uint32_t *)(ptr + o_members),
+                               (const BatchSlot *)(ptr + o_slots),
                                (const BatchBundle *)(ptr + o_bundles), p.nbundles, grid,
                                p.lds_bytes, (uint32_t *)(ptr + 8), d_words, (uint64_t *)ptr,
                                nsweeps, s);

@@ -67,46 +67,60 @@ __device__ __forceinline__ uint64_t decide_word_pair(uint64_t t, const Neighbour
 // LDS, run every sweep there -- all spins of one colour from the other
 // colour, a barrier, then the other colour (Sec. 2) -- and copy them back.
 // Sweep s of the call uses half-sweep index t = 2*(rng_counter + s) + colour.
+// A bundle may mix lattice sizes and tiles: every thread finds its slot and
+// takes that lattice's geometry, neighbour extraction and tile as its own.
 __global__ __launch_bounds__(kBatchThreads) void k_batch_sweep(
-    const BatchLattice *__restrict__ lats, const uint32_t *__restrict__ members,
+    const BatchLattice *__restrict__ lats, const BatchSlot *__restrict__ slots,
     const BatchBundle *__restrict__ bundles, uint32_t nbundles, uint32_t *__restrict__ next_bundle,
     uint64_t *__restrict__ words, const uint64_t *__restrict__ rng_counter, int64_t nsweeps)
 {
     extern __shared__ uint64_t lds[];
     __shared__ uint32_t item;
     const uint64_t ctr = *rng_counter;
+    const uint32_t tid = threadIdx.x;
     for (;;) {
         __syncthreads(); // the previous bundle is written back and `item` consumed
-        if (threadIdx.x == 0)
+        if (tid == 0)
             item = atomicAdd(next_bundle, 1u);
         __syncthreads();
         const uint32_t b = item;
         if (b >= nbundles)
             return;
         const BatchBundle bd = bundles[b];
-        // A bundle holds lattices of one size.  When a colour is a whole
-        // number of words (M % 64 == 0, W >= 2) its continuation is a copy of
-        // words 0 and 1: the lanes that write those write the copies too, and
-        // the refresh and its barrier drop out of every half-sweep.
-        const BatchLattice first = lats[members[bd.first]];
-        const bool copy_ext = (first.M & 63) == 0 && first.W >= 2;
-        // whole-word colour rows: the row-aligned neighbour vectors (their
-        // row arithmetic holds for W < 4096, which L <= 722 keeps)
-        const bool aligned = (first.H & 63) == 0 && first.W < 4096;
-        const uint32_t Wr = first.H >> 6, inv_wr = aligned ? aligned_inv(Wr) : 0;
-        // colour rows of whole 32-bit halves (L % 64 == 0, e.g. 64 and 192)
-        const bool half_aligned = !aligned && (first.H & 31) == 0 && first.W < 4096;
-        const uint32_t Hr = first.H >> 5, inv_hr = half_aligned ? half_inv(Hr) : 0;
-        const uint32_t slot = threadIdx.x / bd.tpl, li = threadIdx.x % bd.tpl;
-        const uint32_t group = li / bd.lpw, parity = li % bd.lpw, groups = bd.tpl / bd.lpw;
-        const bool on = slot < bd.count;
+        // this thread's slot: the last one starting at or before it
+        uint32_t lo = 0, hi = bd.count;
+        while (hi - lo > 1) {
+            const uint32_t mid = (lo + hi) >> 1;
+            if (slots[bd.first + mid].thread0 <= tid)
+                lo = mid;
+            else
+                hi = mid;
+        }
+        const BatchSlot sl = slots[bd.first + lo];
+        const uint32_t li = tid - sl.thread0;
+        const bool on = tid >= sl.thread0 && li < sl.tpl;
+        const uint32_t wpt = sl.tile & 0xFFFFu, lpw = sl.tile >> 16;
+        const uint32_t group = lpw == 2 ? li >> 1 : li, parity = lpw == 2 ? li & 1u : 0u;
+        const uint32_t groups = lpw == 2 ? sl.tpl >> 1 : sl.tpl;
         BatchLattice lt{};
         if (on)
-            lt = lats[members[bd.first + slot]];
-        uint64_t *E0 = lds + (size_t)slot * batch_lds_words(lt.W);
+            lt = lats[sl.lat];
+        // When a colour is a whole number of words (M % 64 == 0, W >= 2) its
+        // continuation is a copy of words 0 and 1: the lanes that write those
+        // write the copies too, and the refresh drops out of every
+        // half-sweep (with its barrier, where no lattice of the bundle needs it).
+        const bool copy_ext = (lt.M & 63) == 0 && lt.W >= 2;
+        // whole-word colour rows: the row-aligned neighbour vectors (their
+        // row arithmetic holds for W < 4096, which L <= 722 keeps)
+        const bool aligned = (lt.H & 63) == 0 && lt.W < 4096;
+        const uint32_t Wr = lt.H >> 6, inv_wr = aligned ? aligned_inv(Wr) : 0;
+        // colour rows of whole 32-bit halves (L % 64 == 0, e.g. 64 and 192)
+        const bool half_aligned = !aligned && (lt.H & 31) == 0 && lt.W < 4096;
+        const uint32_t Hr = lt.H >> 5, inv_hr = half_aligned ? half_inv(Hr) : 0;
+        uint64_t *E0 = lds + sl.lds_off;
         uint64_t *E1 = E0 + lt.W + 2;
         if (on)
-            for (uint32_t k = li; k < 2 * lt.W; k += bd.tpl) {
+            for (uint32_t k = li; k < 2 * lt.W; k += sl.tpl) {
                 const uint32_t c = k >= lt.W;
                 (c ? E1 : E0)[k - c * lt.W] = words[lt.word_off + k];
             }
@@ -124,7 +138,7 @@ __global__ __launch_bounds__(kBatchThreads) void k_batch_sweep(
                 if (on) {
                     const SweepArgs2 a{lt.m,      (uint32_t)t, (uint32_t)(t >> 32), lt.stream_id,
                                        lt.key0, lt.key1};
-                    for (uint32_t j = 0; j < bd.wpt; ++j) {
+                    for (uint32_t j = 0; j < wpt; ++j) {
                         const uint32_t k = group + j * groups;
                         if (k >= lt.W)
                             break;
@@ -142,7 +156,7 @@ __global__ __launch_bounds__(kBatchThreads) void k_batch_sweep(
                         }
                         const uint64_t tw = tgt[k];
                         const uint64_t valid = valid_mask(k, lt.M);
-                        const uint64_t flips = (bd.lpw == 2)
+                        const uint64_t flips = (lpw == 2)
                                                    ? decide_word_pair(tw, nb, valid, k, a, parity)
                                                    : rows::decide_word_any(tw, nb, valid, k, a);
                         if (parity == 0) {
@@ -153,15 +167,15 @@ __global__ __launch_bounds__(kBatchThreads) void k_batch_sweep(
                     }
                 }
                 __syncthreads();
-                if (!copy_ext) {
-                    if (on && li == 0)
+                if (bd.refresh) {
+                    if (on && li == 0 && !copy_ext)
                         ext_refresh(tgt, lt.M, lt.W);
                     __syncthreads();
                 }
             }
         }
         if (on)
-            for (uint32_t k = li; k < 2 * lt.W; k += bd.tpl) {
+            for (uint32_t k = li; k < 2 * lt.W; k += sl.tpl) {
                 const uint32_t c = k >= lt.W;
                 const uint32_t kk = k - c * lt.W;
                 words[lt.word_off + k] = (c ? E1 : E0)[kk] & valid_mask(kk, lt.M);
@@ -282,14 +296,14 @@ hipError_t launch_batch_init(const BatchLattice *lats, uint32_t n, uint64_t *wor
     return hipGetLastError();
 }
 
-hipError_t launch_batch_sweep(const BatchLattice *lats, const uint32_t *members,
+hipError_t launch_batch_sweep(const BatchLattice *lats, const BatchSlot *slots,
                               const BatchBundle *bundles, uint32_t nbundles, uint32_t grid,
                               size_t lds_bytes, uint32_t *next_bundle, uint64_t *words,
                               uint64_t *rng_counter, int64_t nsweeps, hipStream_t s)
 {
     hipLaunchKernelGGL(k_batch_prepare, dim3(1), dim3(64), 0, s, next_bundle);
     hipLaunchKernelGGL(k_batch_sweep, dim3(grid), dim3(kBatchThreads), lds_bytes, s, lats,
-                       members, bundles, nbundles, next_bundle, words,
+                       slots, bundles, nbundles, next_bundle, words,
                        (const uint64_t *)rng_counter, nsweeps);
     hipLaunchKernelGGL(k_batch_advance, dim3(1), dim3(64), 0, s, rng_counter, nsweeps);
     return hipGetLastError();

@@ -18,9 +18,11 @@
 
 #include <algorithm>
 #include <cmath>
+#include <climits>
 #include <cstdint>
 #include <functional>
 #include <queue>
+#include <utility>
 #include <vector>
 
 namespace ising {
@@ -164,6 +166,217 @@ inline std::vector<size_t> choose(const std::vector<std::vector<Option>> &opts,
         for (size_t i = 0; i < opts.size(); ++i)
             start[i] = (size_t)(next() % opts[i].size());
         consider(std::move(start));
+    }
+    return best;
+}
+
+// ------------------------------------------------------ mixed-size bundles
+// Lattices of different sizes may also share a workgroup.  Two models of a
+// workgroup's duration, each fitted to the bundles of one kind (a size with
+// its tile) timed alone, neither right everywhere:
+//  - additive: a bundle of n lattices takes a + n b; a workgroup of several
+//    kinds max a + sum b.  Close where lattices are small and the half-sweep
+//    is the latency of one word's decision chain.
+//  - rounds: a half-sweep is bound by vector-ALU issue on the busiest of the
+//    compute unit's four SIMDs, which run the workgroup's wavefronts round
+//    robin: a bundle filling W wavefronts takes a + b ceil(W / 4); several
+//    kinds, threads back to back, max a + max b ceil(W / 4).  Close where
+//    lattices fill wavefronts.
+// The autotuner packs with both and times the results.
+enum Model { kAdditive = 0, kRounds = 1 };
+
+struct Kind {
+    double a = 0.0, b = 0.0; // ms for the sweeps the model was timed on
+    uint32_t threads = 0;    // threads a lattice takes in the workgroup layout
+    uint32_t lds_words = 0;  // LDS words a lattice takes
+    bool exclusive = false;  // shares a workgroup only with lattices of its own kind
+};
+
+// Wavefronts per SIMD of a workgroup with `threads` threads.
+inline uint32_t simd_waves(uint32_t threads) { return ((threads + 63) / 64 + 3) / 4; }
+
+// Model duration of a workgroup: its largest a, largest and summed b, threads.
+inline double group_time(Model m, double a, double bmax, double bsum, uint32_t threads)
+{
+    return m == kRounds ? a + bmax * (double)simd_waves(threads) : a + bsum;
+}
+
+// (a, b) from bundle durations t of n lattices of `threads` threads each: the
+// line through the points with the smallest and the largest x (x = n, or the
+// SIMD rounds of n lattices), a >= 0, b > 0.  With one x, a defaults to
+// a_default, at most 0.8 t.
+inline void fit_kind(const std::vector<std::pair<uint32_t, double>> &pts, uint32_t threads,
+                     Model m, double a_default, double *a, double *b)
+{
+    uint32_t x0 = UINT32_MAX, x1 = 0;
+    double t0 = 0.0, t1 = 0.0;
+    for (const auto &p : pts) {
+        const uint32_t x = m == kRounds ? simd_waves(p.first * threads) : p.first;
+        if (x < x0 || (x == x0 && p.second < t0)) {
+            x0 = x;
+            t0 = p.second;
+        }
+        if (x > x1 || (x == x1 && p.second < t1)) {
+            x1 = x;
+            t1 = p.second;
+        }
+    }
+    if (x1 > x0) {
+        *b = std::max((t1 - t0) / (double)(x1 - x0), 0.02 * t1 / (double)x1);
+        *a = std::max(0.0, t0 - *b * (double)x0);
+    } else {
+        *a = std::min(a_default, 0.8 * t0);
+        *b = (t0 - *a) / (double)std::max(1u, x0);
+    }
+}
+
+struct Packing {
+    std::vector<std::vector<uint32_t>> groups; // item indices per workgroup (none empty)
+    std::vector<double> est;                   // model duration per workgroup
+    double makespan = 0.0;
+    bool ok = false;
+};
+
+// Places the items in `use` (kinds in item_kind) on at most `slots`
+// workgroups of max_threads threads and max_lds LDS words: the largest
+// (threads x b under kRounds, b otherwise) first, each on the workgroup whose
+// model duration after adding it is smallest, among equals the fullest.  Not
+// ok if some item fits nowhere.
+inline Packing lpt_pack(const std::vector<Kind> &kinds, const std::vector<uint32_t> &item_kind,
+                        const std::vector<uint32_t> &use, uint32_t slots, uint32_t max_threads,
+                        uint32_t max_lds, Model model)
+{
+    std::vector<uint32_t> order = use;
+    auto weight = [&](uint32_t i) {
+        const Kind &k = kinds[item_kind[i]];
+        return model == kRounds ? k.b * k.threads : k.b;
+    };
+    std::stable_sort(order.begin(), order.end(),
+                     [&](uint32_t x, uint32_t y) { return weight(x) > weight(y); });
+    struct Load {
+        double a = 0.0, bmax = 0.0, bsum = 0.0;
+        uint32_t threads = 0, lds = 0;
+    };
+    Packing p;
+    const uint32_t g = slots;
+    std::vector<Load> load(g);
+    std::vector<std::vector<uint32_t>> groups(g);
+    for (uint32_t i : order) {
+        const Kind &k = kinds[item_kind[i]];
+        int best = -1;
+        double best_t = 0.0;
+        for (uint32_t w = 0; w < g; ++w) {
+            const Load &l = load[w];
+            if (l.threads + k.threads > max_threads || l.lds + k.lds_words > max_lds)
+                continue;
+            const double t = group_time(model, std::max(l.a, k.a), std::max(l.bmax, k.b),
+                                        l.bsum + k.b, l.threads + k.threads);
+            if (best < 0 || t < best_t - 1e-12 ||
+                (t <= best_t + 1e-12 && l.threads > load[(size_t)best].threads)) {
+                best = (int)w;
+                best_t = t;
+            }
+        }
+        if (best < 0)
+            return p;
+        Load &l = load[(size_t)best];
+        l.a = std::max(l.a, k.a);
+        l.bmax = std::max(l.bmax, k.b);
+        l.bsum += k.b;
+        l.threads += k.threads;
+        l.lds += k.lds_words;
+        groups[(size_t)best].push_back(i);
+    }
+    for (uint32_t w = 0; w < g; ++w)
+        if (!groups[w].empty()) {
+            p.groups.push_back(std::move(groups[w]));
+            p.est.push_back(group_time(model, load[w].a, load[w].bmax, load[w].bsum,
+                                       load[w].threads));
+            p.makespan = std::max(p.makespan, p.est.back());
+        }
+    p.ok = true;
+    return p;
+}
+
+// All items on at most `slots` workgroups.  Without exclusive kinds, one
+// largest-first pass (lpt_pack).  With them, a makespan bound T is searched
+// by bisection: each exclusive kind fills workgroups of its own with as many
+// lattices as keep its model duration <= T (within threads and LDS), and the
+// other items go largest first onto the workgroups left; T is feasible if
+// those end by T.
+inline Packing pack_mixed(const std::vector<Kind> &kinds, const std::vector<uint32_t> &item_kind,
+                          uint32_t slots, uint32_t max_threads, uint32_t max_lds, Model model)
+{
+    slots = std::max(1u, slots);
+    std::vector<uint32_t> mix;
+    std::vector<std::vector<uint32_t>> excl(kinds.size());
+    for (uint32_t i = 0; i < (uint32_t)item_kind.size(); ++i)
+        (kinds[item_kind[i]].exclusive ? excl[item_kind[i]] : mix).push_back(i);
+    bool any_excl = false;
+    for (const auto &e : excl)
+        any_excl = any_excl || !e.empty();
+    if (!any_excl)
+        return lpt_pack(kinds, item_kind, mix, slots, max_threads, max_lds, model);
+    auto own_time = [&](const Kind &kd, uint32_t m) {
+        return group_time(model, kd.a, kd.b, kd.b * (double)m, m * kd.threads);
+    };
+    // lattices per workgroup of exclusive kind k under bound T (0: none fits)
+    auto per_wg = [&](size_t k, double T) -> uint32_t {
+        const Kind &kd = kinds[k];
+        uint32_t m = 0;
+        while (m < excl[k].size() && (m + 1) * kd.threads <= max_threads &&
+               (m + 1) * kd.lds_words <= max_lds && own_time(kd, m + 1) <= T)
+            ++m;
+        return m;
+    };
+    auto attempt = [&](double T, Packing *out) -> bool {
+        uint32_t used = 0;
+        for (size_t k = 0; k < kinds.size(); ++k)
+            if (!excl[k].empty()) {
+                const uint32_t m = per_wg(k, T);
+                if (m == 0)
+                    return false;
+                used += (uint32_t)((excl[k].size() + m - 1) / m);
+            }
+        if (used > slots || (used == slots && !mix.empty()))
+            return false;
+        Packing p;
+        if (!mix.empty()) {
+            p = lpt_pack(kinds, item_kind, mix, slots - used, max_threads, max_lds, model);
+            if (!p.ok || p.makespan > T)
+                return false;
+        }
+        for (size_t k = 0; k < kinds.size(); ++k) {
+            if (excl[k].empty())
+                continue;
+            const uint32_t m = per_wg(k, T);
+            for (size_t s0 = 0; s0 < excl[k].size(); s0 += m) {
+                const size_t cnt = std::min<size_t>(m, excl[k].size() - s0);
+                p.groups.emplace_back(excl[k].begin() + (long)s0,
+                                      excl[k].begin() + (long)(s0 + cnt));
+                p.est.push_back(own_time(kinds[k], (uint32_t)cnt));
+                p.makespan = std::max(p.makespan, p.est.back());
+            }
+        }
+        p.ok = true;
+        *out = std::move(p);
+        return true;
+    };
+    double lo = 0.0, hi = 0.0;
+    for (uint32_t i = 0; i < (uint32_t)item_kind.size(); ++i)
+        hi += own_time(kinds[item_kind[i]], 1);
+    Packing best;
+    if (!attempt(hi, &best))
+        return Packing{};
+    for (int it = 0; it < 50; ++it) {
+        const double mid = 0.5 * (lo + hi);
+        Packing p;
+        if (attempt(mid, &p)) {
+            hi = mid;
+            best = std::move(p);
+        } else {
+            lo = mid;
+        }
     }
     return best;
 }

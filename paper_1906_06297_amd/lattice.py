@@ -330,6 +330,21 @@ class Batch:
                                                     ctypes.byref(n)))
         return int(per.value), int(n.value)
 
+    def mixed(self) -> bool:
+        """True if the current plan has bundles that mix lattice sizes."""
+        v = ctypes.c_int32()
+        _lib.check(_lib.load().ising_batch_get_mixed(self._h, ctypes.byref(v)))
+        return bool(v.value)
+
+    def set_bundles(self, bundles) -> None:
+        """Explicit plan: a list of lists of lattice indices, one list per
+        workgroup load, in launch order (every lattice exactly once)."""
+        counts = [len(g) for g in bundles]
+        flat = [int(q) for g in bundles for q in g]
+        c_arr = (ctypes.c_int32 * len(counts))(*counts)
+        l_arr = (ctypes.c_int32 * max(1, len(flat)))(*flat)
+        _lib.check(_lib.load().ising_batch_set_bundles(self._h, len(counts), c_arr, l_arr))
+
     def set_tiles(self, L: int, wpt: int, lpw: int = 1) -> None:
         _lib.check(_lib.load().ising_batch_set_tiles(self._h, int(L), int(wpt), int(lpw)))
 

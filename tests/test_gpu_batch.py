@@ -136,6 +136,38 @@ def test_mixed_sizes_and_couplings(gpu, orc):
         b.close()
 
 
+def test_mixed_size_bundles_explicit(gpu, orc):
+    """Workgroups that mix lattice sizes, tiles and neighbour extractions
+    (general, half-word and word rows; one- and two-lane tiles; colours that
+    need the refresh): every lattice bit for bit as the oracle."""
+    Ls = [16, 24, 30, 64, 100, 128, 192, 256, 40, 64, 14, 192]
+    n = len(Ls)
+    betas = np.linspace(0.2, 0.7, n)
+    seeds = [21 + q for q in range(n)]
+    streams = list(range(40, 40 + n))
+    say("mixed-size bundles (explicit plan)")
+    b = gpu.Batch(Ls, betas, 1.0, seeds, streams)
+    b.set_tiles(64, 1, 2)
+    b.set_tiles(192, 1, 1)
+    b.set_tiles(24, 1, 2)
+    b.set_tiles(256, 2, 1)
+    b.set_bundles([[7, 0, 1, 4], [6, 3, 2, 9, 10], [5, 11, 8]])
+    assert b.mixed()
+    b.init()
+    b.sweep(8)
+    ref = oracle_batch(orc, Ls, betas, 1.0, seeds, streams, 8)
+    for q in range(n):
+        assert np.array_equal(batch_words_of(b, q), pack(ref[q])), Ls[q]
+    # a workgroup's threads and LDS bound what a bundle may hold
+    from paper_1906_06297_amd._lib import IsingError
+    b.set_tiles(256, 1, 2)  # 1024 threads for one L = 256 lattice
+    with pytest.raises(IsingError):
+        b.set_bundles([[7, 6], [0, 1, 2, 3, 4, 5, 8, 9, 10, 11]])
+    with pytest.raises(IsingError):  # not a permutation
+        b.set_bundles([[0, 1], [1, 2]])
+    b.close()
+
+
 def test_long_run_sample(gpu, orc, workload):
     """The workload's full 10^4 sweeps on a sample of its lattices."""
     Ls, betas, seeds, streams = workload
