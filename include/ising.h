@@ -293,9 +293,9 @@ int ising_batch_set_bundles(ising_batch *b, int32_t nbundles, const int32_t *cou
  * workgroup of several sizes max a + sum b; or a + b per round of wavefronts
  * on the compute unit's SIMDs), lattices are placed largest first where the
  * model's workgroup duration grows least (sizes whose rows are not whole
- * 32-bit halves optionally in workgroups of their own), and the plan of each
- * model replaces the one-size bundles if it runs the whole batch faster
- * (again with identical lattices).  cache_path (may be NULL) is a JSON file
+ * 32-bit halves optionally in workgroups of their own), and the fastest of
+ * these plans, each timed on the whole batch, replaces the one-size bundles
+ * if it is faster (again with identical lattices).  cache_path (may be NULL) is a JSON file
  * keyed by target and kernel version: read if it covers every size, written
  * after tuning.  With ISING_AUTOTUNE_LOG set in the environment the estimates
  * and timings go to stderr.  Synchronises hip_stream; allocates scratch

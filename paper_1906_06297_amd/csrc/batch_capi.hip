@@ -1139,8 +1139,8 @@ int ising_batch_autotune(ising_batch *b, int64_t tune_sweeps, const char *cache_
     // one-size plan's makespan, or the one-size plan's own tiles -- each with
     // every size mixing, or with the sizes whose colour rows are not whole
     // 32-bit halves (general neighbour extraction, long per-word chains) in
-    // workgroups of their own.  The best estimate of each model is timed on
-    // the whole batch; the fastest replaces the one-size plan if faster.
+    // workgroups of their own.  Each packing is timed on the whole batch; the
+    // fastest replaces the one-size plan if faster.
     if (e == hipSuccess && rc == ISING_OK && !sizes.empty()) {
         const double hom_est = plan::estimate(opts, pick, slots).makespan;
         if (log)
@@ -1193,9 +1193,6 @@ int ising_batch_autotune(ising_batch *b, int64_t tune_sweeps, const char *cache_
                     }
                 }
             }
-            double best_est = 0.0;
-            std::map<int64_t, Tile> best_tiles;
-            std::map<int64_t, plan::Kind> best_kinds;
             for (int rule = 0; rule < 4; ++rule) {
                 std::map<int64_t, Tile> tiles;
                 std::map<int64_t, plan::Kind> kinds;
@@ -1249,33 +1246,25 @@ int ising_batch_autotune(ising_batch *b, int64_t tune_sweeps, const char *cache_
                                      kinds[kv.first].a, kinds[kv.first].b,
                                      kinds[kv.first].exclusive ? " own workgroups" : "");
                 }
-                if (packed && (best_tiles.empty() || est < best_est)) {
-                    best_est = est;
-                    best_tiles = tiles;
-                    best_kinds = kinds;
+                // the models' estimates are rough: every packing is timed
+                float ms_mixed = 0.f;
+                if (packed && time_plan(p, &ms_mixed, out_try)) {
+                    if (log)
+                        std::fprintf(stderr, "[autotune]   timed %.4f ms\n", (double)ms_mixed);
+                    if (out_try != out_ref) {
+                        rc = host::fail(ISING_E_HIP, "autotune: mixed-size bundles changed the "
+                                        "lattices");
+                        break;
+                    }
+                    if (ms_mixed < ms_best && (keep_tiles.empty() || ms_mixed < ms_mixed_best)) {
+                        ms_mixed_best = ms_mixed;
+                        keep_tiles = tiles;
+                        keep_kinds = kinds;
+                        keep_model = model;
+                    }
                 }
-            }
-            if (best_tiles.empty())
-                continue;
-            b->tiles = best_tiles;
-            b->kinds = best_kinds;
-            b->model = model;
-            Plan p;
-            float ms_mixed = 0.f;
-            if (make_mixed_plan(b, slots, &p, nullptr) && time_plan(p, &ms_mixed, out_try)) {
-                if (log)
-                    std::fprintf(stderr, "[autotune] %s model: mixed plan timed %.4f ms\n",
-                                 model == plan::kRounds ? "rounds" : "additive",
-                                 (double)ms_mixed);
-                if (out_try != out_ref)
-                    rc = host::fail(ISING_E_HIP, "autotune: mixed-size bundles changed the "
-                                    "lattices");
-                else if (ms_mixed < ms_best && (keep_tiles.empty() || ms_mixed < ms_mixed_best)) {
-                    ms_mixed_best = ms_mixed;
-                    keep_tiles = best_tiles;
-                    keep_kinds = best_kinds;
-                    keep_model = model;
-                }
+                if (e != hipSuccess || rc != ISING_OK)
+                    break;
             }
         }
         if (!keep_tiles.empty() && rc == ISING_OK && e == hipSuccess) {

@@ -117,6 +117,11 @@ __global__ __launch_bounds__(kBatchThreads) void k_batch_sweep(
         // colour rows of whole 32-bit halves (L % 64 == 0, e.g. 64 and 192)
         const bool half_aligned = !aligned && (lt.H & 31) == 0 && lt.W < 4096;
         const uint32_t Hr = lt.H >> 5, inv_hr = half_aligned ? half_inv(Hr) : 0;
+        // general geometry: the row masks of the lane group's first word,
+        // the same every half-sweep, taken once per bundle
+        RowMasks rm0{};
+        if (on && !aligned && !half_aligned && group < lt.W)
+            rm0 = row_masks32(group, lt.H, lt.M, 0);
         uint64_t *E0 = lds + sl.lds_off;
         uint64_t *E1 = E0 + lt.W + 2;
         if (on)
@@ -149,7 +154,7 @@ __global__ __launch_bounds__(kBatchThreads) void k_batch_sweep(
                             nb = neighbours_half_aligned((const uint32_t *)src, lt.W, Hr, inv_hr,
                                                          k, c);
                         } else {
-                            RowMasks rm = row_masks32(k, lt.H, lt.M, 0);
+                            RowMasks rm = j == 0 ? rm0 : row_masks32(k, lt.H, lt.M, 0);
                             if (c)
                                 rm.left_rows = ~rm.left_rows; // rows of the other parity
                             nb = neighbours_ext_rm(src, lt.H, lt.M, k, rm);
