@@ -183,6 +183,79 @@ def cpu_baseline(target_s: float = 15.0) -> dict:
     }
 
 
+def cpu_plan(ising, torch, progress) -> dict:
+    """The oracle at the planned CPU-baseline sizes, each against the GPU on the
+    same start: L = 64 (the correctness workload, 1000 sweeps at beta_c), L =
+    4096 (200 sweeps per headline beta; the single-thread rate on the first 10
+    sweeps per beta) and the first 4 sweeps of the headline lattice at beta_c;
+    flips/ns on one thread and on all, and whether the lattices are
+    identical."""
+    import oracle
+
+    oracle.lib()
+    cores = oracle.max_threads()
+    res = {"cores": cores, "host_cpu": host_cpu()}
+
+    def timed(fn):
+        t0 = time.perf_counter()
+        fn()
+        return time.perf_counter() - t0
+
+    def gpu_spins(L, seed, stream, beta, n):
+        lat = ising.Lattice(L, seed, stream)
+        lat.sweep(beta, 1.0, n, 0)
+        torch.cuda.synchronize()
+        out = lat.get_spins()
+        del lat
+        return out
+
+    c1 = workloads.CORRECTNESS
+    L, n, beta = c1["L"], c1["nsweeps"], c1["beta"]
+    row = {}
+    for threads in (1, cores):
+        oracle.set_threads(threads)
+        s = oracle.init(L, c1["seed"], c1["stream"])
+        dt = timed(lambda: oracle.sweeps(s, beta, 1.0, c1["seed"], c1["stream"], n, 0))
+        row[f"flips_per_ns_{threads}_threads"] = n * L * L / (dt * 1e9)
+    row["bit_exact"] = bool(np.array_equal(s, gpu_spins(L, c1["seed"], c1["stream"], beta, n)))
+    res[f"L{L}_{n}_sweeps"] = row
+    progress("CPU plan: L = 64 done")
+
+    L, n = 4096, 200
+    row = {"betas": list(workloads.HEADLINE["betas"])}
+    oracle.set_threads(cores)
+    secs, ok = 0.0, True
+    for beta in workloads.HEADLINE["betas"]:
+        s = oracle.init(L, workloads.HEADLINE["seed"], 0)
+        secs += timed(lambda: oracle.sweeps(s, beta, 1.0, workloads.HEADLINE["seed"], 0, n, 0))
+        ok = ok and bool(np.array_equal(s, gpu_spins(L, workloads.HEADLINE["seed"], 0, beta, n)))
+    row[f"flips_per_ns_{cores}_threads"] = 3 * n * L * L / (secs * 1e9)
+    row["wall_s_all_threads"] = secs
+    row["bit_exact"] = ok
+    oracle.set_threads(1)
+    n1, secs1 = 10, 0.0
+    for beta in workloads.HEADLINE["betas"]:
+        s = oracle.init(L, workloads.HEADLINE["seed"], 0)
+        secs1 += timed(lambda: oracle.sweeps(s, beta, 1.0, workloads.HEADLINE["seed"], 0, n1, 0))
+    row["flips_per_ns_1_threads"] = 3 * n1 * L * L / (secs1 * 1e9)
+    row["single_thread_sample"] = f"first {n1} sweeps per beta"
+    res[f"L{L}_{n}_sweeps"] = row
+    oracle.set_threads(cores)
+    progress("CPU plan: L = 4096 done")
+
+    cfg = workloads.HEADLINE
+    L, n, beta = cfg["L"], 4, workloads.BETA_CRIT_CONFIG
+    s = oracle.init(L, cfg["seed"], cfg["stream"])
+    secs = timed(lambda: oracle.sweeps(s, beta, 1.0, cfg["seed"], cfg["stream"], n, 0))
+    ok = bool(np.array_equal(s, gpu_spins(L, cfg["seed"], cfg["stream"], beta, n)))
+    del s
+    res[f"L{L}_first_{n}_sweeps"] = {"beta": beta, "wall_s": secs,
+                                     f"flips_per_ns_{cores}_threads": n * L * L / (secs * 1e9),
+                                     "bit_exact": ok}
+    progress("CPU plan: L = 65536 done")
+    return res
+
+
 def host_cpu() -> str:
     try:
         with open("/proc/cpuinfo") as f:
@@ -592,6 +665,9 @@ def main() -> int:
                          "clocks and power beside a steady load) and exit")
     ap.add_argument("--print-source-hash", action="store_true",
                     help="print the hash of the half-sweep kernel sources and exit")
+    ap.add_argument("--cpu-plan", action="store_true",
+                    help="also time the oracle at the planned CPU-baseline sizes (L = 64, 4096 and "
+                         "the first 4 headline sweeps), each checked against the GPU")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="also run three plain 1 GiB device-to-device copies, whose HBM counter "
                          "readings scale the profiler's byte counts")
@@ -745,6 +821,8 @@ def main() -> int:
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline()
         progress("CPU baseline done")
+    if args.cpu_plan:
+        out["cpu_plan"] = cpu_plan(ising, torch, progress)
     print(json.dumps(out), flush=True)
     return 0
 
