@@ -48,10 +48,13 @@ __host__ __device__ inline uint32_t batch_lds_words(uint32_t W) { return 2 * (W 
 
 hipError_t launch_batch_init(const BatchLattice *lats, uint32_t n, uint64_t *words,
                              hipStream_t s);
+// bundle_clock (optional, 2 x nbundles): each bundle's start and end on the
+// device's constant-rate wall clock.
 hipError_t launch_batch_sweep(const BatchLattice *lats, const BatchSlot *slots,
                               const BatchBundle *bundles, uint32_t nbundles, uint32_t grid,
                               size_t lds_bytes, uint32_t *next_bundle, uint64_t *words,
-                              uint64_t *rng_counter, int64_t nsweeps, hipStream_t s);
+                              uint64_t *rng_counter, int64_t nsweeps, hipStream_t s,
+                              uint64_t *bundle_clock = nullptr);
 // Workgroups of the persistent sweep kernel one compute unit holds at once
 // with lds_bytes of dynamic LDS each (registers, wavefront slots and LDS).
 hipError_t batch_sweep_blocks_per_cu(size_t lds_bytes, int *blocks);

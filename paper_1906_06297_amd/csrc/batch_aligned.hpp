@@ -102,4 +102,47 @@ __host__ __device__ __forceinline__ Neighbours neighbours_half_aligned(Ptr32 E, 
     return nb;
 }
 
+// The general extraction (any geometry, extended colour array) on 32-bit
+// halves: a 64-spin window at spin x is two funnel shifts of three
+// consecutive halves, and the wrapped positions are 32-bit (every spin index
+// of a batch lattice is below 2^18).  Same vectors as neighbours_ext_rm.
+__host__ __device__ __forceinline__ uint32_t funnel32(uint32_t hi, uint32_t lo, uint32_t sh)
+{
+#if defined(__HIP_DEVICE_COMPILE__)
+    return __builtin_amdgcn_alignbit(hi, lo, sh);
+#else
+    return (uint32_t)((((uint64_t)hi << 32) | lo) >> sh);
+#endif
+}
+
+template <typename Ptr32>
+__host__ __device__ __forceinline__ uint64_t ext_bits32(Ptr32 E, uint32_t x)
+{
+    const uint32_t w = x >> 5, sh = x & 31;
+    const uint32_t d0 = E[w], d1 = E[w + 1], d2 = E[w + 2];
+    return (uint64_t)funnel32(d1, d0, sh) | ((uint64_t)funnel32(d2, d1, sh) << 32);
+}
+
+__host__ __device__ __forceinline__ uint32_t wrap32(int32_t x, uint32_t M)
+{
+    return (uint32_t)(x < 0 ? x + (int32_t)M : (x >= (int32_t)M ? x - (int32_t)M : x));
+}
+
+template <typename Ptr32>
+__host__ __device__ __forceinline__ Neighbours neighbours_ext32(Ptr32 E, uint32_t H, uint32_t M,
+                                                                uint32_t k, const RowMasks &rm)
+{
+    const int32_t n0 = (int32_t)(k << 6), h = (int32_t)H;
+    Neighbours nb;
+    nb.ce = ext_bits32(E, (uint32_t)n0);
+    nb.up = ext_bits32(E, wrap32(n0 - h, M));
+    nb.dn = ext_bits32(E, wrap32(n0 + h, M));
+    const uint64_t left = (ext_bits32(E, wrap32(n0 - 1, M)) & ~rm.row_start) |
+                          (ext_bits32(E, wrap32(n0 + h - 1, M)) & rm.row_start);
+    const uint64_t right = (ext_bits32(E, wrap32(n0 + 1, M)) & ~rm.row_end) |
+                           (ext_bits32(E, wrap32(n0 - h + 1, M)) & rm.row_end);
+    nb.sd = (left & rm.left_rows) | (right & ~rm.left_rows);
+    return nb;
+}
+
 } // namespace ising

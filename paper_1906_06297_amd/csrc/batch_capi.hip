@@ -45,6 +45,9 @@ struct ising_batch {
     bool mixed = false;
     plan::Model model = plan::kAdditive;
     std::map<int64_t, plan::Kind> kinds;
+    // the mixed plan's workgroup loads as the autotuner left them (lattice
+    // indices); empty: packed from `kinds`
+    std::vector<std::vector<uint32_t>> groups;
     // the installed plan per size: most lattices in one workgroup, workgroups
     std::map<int64_t, std::pair<uint32_t, uint32_t>> plan_stats;
     // device state owned by the batch
@@ -230,7 +233,21 @@ uint32_t mixed_threads(uint32_t W, Tile t) { return threads_per_lattice(W, t); }
 
 // Mixed-size bundles from the duration model of every size (b->kinds, with
 // the tiles in b->tiles) on `slots` workgroups, longest estimate first.
-bool make_mixed_plan(const ising_batch *b, uint32_t slots, Plan *out, double *makespan)
+// A plan of mixed bundles from workgroup loads (lattice indices), in order.
+Plan plan_from_groups(const ising_batch *b, const std::vector<std::vector<uint32_t>> &groups)
+{
+    Plan p;
+    for (const auto &g : groups) {
+        std::vector<std::pair<uint32_t, Tile>> v;
+        for (uint32_t q : g)
+            v.emplace_back(q, b->tiles.at(b->Ls[q]));
+        add_bundle(p, b, std::move(v), true);
+    }
+    return p;
+}
+
+bool make_mixed_plan(const ising_batch *b, uint32_t slots, Plan *out, double *makespan,
+                     std::vector<std::vector<uint32_t>> *groups_out = nullptr)
 {
     std::vector<plan::Kind> kinds;
     std::map<int64_t, uint32_t> kind_of;
@@ -257,16 +274,14 @@ bool make_mixed_plan(const ising_batch *b, uint32_t slots, Plan *out, double *ma
         order[i] = i;
     std::stable_sort(order.begin(), order.end(),
                      [&](size_t x, size_t y) { return pk.est[x] > pk.est[y]; });
-    Plan p;
-    for (size_t gi : order) {
-        std::vector<std::pair<uint32_t, Tile>> v;
-        for (uint32_t q : pk.groups[gi])
-            v.emplace_back(q, b->tiles.at(b->Ls[q]));
-        add_bundle(p, b, std::move(v), true);
-    }
-    *out = std::move(p);
+    std::vector<std::vector<uint32_t>> groups;
+    for (size_t gi : order)
+        groups.push_back(pk.groups[gi]);
+    *out = plan_from_groups(b, groups);
     if (makespan)
         *makespan = pk.makespan;
+    if (groups_out)
+        *groups_out = std::move(groups);
     return true;
 }
 
@@ -350,6 +365,8 @@ int install_plan(ising_batch *b, const Plan &p)
 // autotuner chose them, else one size per bundle.
 int install_current_plan(ising_batch *b)
 {
+    if (b->mixed && !b->groups.empty())
+        return install_plan(b, plan_from_groups(b, b->groups));
     if (b->mixed) {
         uint32_t slots = 0;
         if (int rc = resident_slots(kMaxBundleLds, &slots))
@@ -904,6 +921,7 @@ int ising_batch_set_bundles(ising_batch *b, int32_t nbundles, const int32_t *cou
     if (int rc = install_plan(b, p))
         return rc;
     b->mixed = true;
+    b->groups.clear(); // the caller's plan stands until the batch is replanned
     b->est_ms.clear();
     return host::ok();
 }
@@ -931,6 +949,7 @@ int ising_batch_set_tiles(ising_batch *b, int64_t L, uint32_t wpt, uint32_t lpw)
     it->second = Tile{wpt, lpw};
     b->est_ms.erase(L); // bundles go back to ordering by spins
     b->mixed = false;   // and to one size each
+    b->groups.clear();
     return install_plan(b, make_plan(b, 0, Tile{1, 1}));
 }
 
@@ -946,6 +965,7 @@ int ising_batch_autotune(ising_batch *b, int64_t tune_sweeps, const char *cache_
     const bool log = std::getenv("ISING_AUTOTUNE_LOG") != nullptr;
     b->est_ms.clear();
     b->kinds.clear();
+    b->groups.clear();
     b->mixed = false;
     std::map<int64_t, CacheEntry> cached;
     bool cached_mixed = false;
@@ -983,8 +1003,13 @@ int ising_batch_autotune(ising_batch *b, int64_t tune_sweeps, const char *cache_
         e = hipEventCreate(&e1);
     int rc = ISING_OK;
     // Runs plan p for tune_sweeps sweeps on the scratch copy, from the batch's
-    // lattices and counter 0 every time; best of two launches, lattices to out.
-    auto time_plan = [&](const Plan &p, float *best, std::vector<uint64_t> &out) -> bool {
+    // lattices and counter 0 every time; best of two launches, lattices to out,
+    // and (per_bundle) each bundle's duration in the second launch, in ms.
+    uint64_t *clk = nullptr;
+    size_t clk_n = 0;
+    double wall_khz = 0.0;
+    auto time_plan = [&](const Plan &p, float *best, std::vector<uint64_t> &out,
+                         std::vector<double> *per_bundle = nullptr) -> bool {
         uint32_t grid = 0;
         if ((rc = check_plan(b->lats.data(), b->n, p.slots.data(), p.slots.size(),
                              p.bundles.data(), p.bundles.size(), p.lds_bytes, false)))
@@ -1006,10 +1031,25 @@ int ising_batch_autotune(ising_batch *b, int64_t tune_sweeps, const char *cache_
         if (e == hipSuccess)
             e = hipMemcpy(bundles, p.bundles.data(), p.bundles.size() * sizeof(BatchBundle),
                           hipMemcpyHostToDevice);
+        if (per_bundle && e == hipSuccess && clk_n < 2 * p.bundles.size()) {
+            if (clk)
+                (void)hipFree(clk);
+            clk = nullptr;
+            clk_n = 2 * p.bundles.size();
+            e = hipMalloc(&clk, clk_n * sizeof(uint64_t));
+        }
+        if (per_bundle && e == hipSuccess && wall_khz <= 0.0) {
+            int dev = 0, khz = 0;
+            e = hipGetDevice(&dev);
+            if (e == hipSuccess)
+                e = hipDeviceGetAttribute(&khz, hipDeviceAttributeWallClockRate, dev);
+            wall_khz = khz > 0 ? (double)khz : 1.0e5;
+        }
         *best = 1e30f;
         for (int rep = 0; rep < 2 && e == hipSuccess; ++rep) {
             const uint64_t zero = 0;
             float ms = 0.f;
+            uint64_t *bc = (per_bundle && rep == 1) ? clk : nullptr;
             e = hipMemcpyAsync(scratch, b->words, nbytes, hipMemcpyDeviceToDevice, s);
             if (e == hipSuccess)
                 e = hipMemcpyAsync(ctr, &zero, 8, hipMemcpyHostToDevice, s);
@@ -1017,7 +1057,7 @@ int ising_batch_autotune(ising_batch *b, int64_t tune_sweeps, const char *cache_
                 e = hipEventRecord(e0, s);
             if (e == hipSuccess)
                 e = launch_batch_sweep(b->d_lats, slot_buf, bundles, (uint32_t)p.bundles.size(),
-                                       grid, p.lds_bytes, next, scratch, ctr, tune_sweeps, s);
+                                       grid, p.lds_bytes, next, scratch, ctr, tune_sweeps, s, bc);
             if (e == hipSuccess)
                 e = hipEventRecord(e1, s);
             if (e == hipSuccess)
@@ -1029,6 +1069,13 @@ int ising_batch_autotune(ising_batch *b, int64_t tune_sweeps, const char *cache_
         if (e == hipSuccess) {
             out.resize(nbytes / 8);
             e = hipMemcpy(out.data(), scratch, nbytes, hipMemcpyDeviceToHost);
+        }
+        if (per_bundle && e == hipSuccess) {
+            std::vector<uint64_t> t(2 * p.bundles.size());
+            e = hipMemcpy(t.data(), clk, t.size() * sizeof(uint64_t), hipMemcpyDeviceToHost);
+            per_bundle->assign(p.bundles.size(), 0.0);
+            for (size_t i = 0; i < p.bundles.size() && e == hipSuccess; ++i)
+                (*per_bundle)[i] = (double)(t[2 * i + 1] - t[2 * i]) / wall_khz;
         }
         return e == hipSuccess;
     };
@@ -1150,6 +1197,7 @@ int ising_batch_autotune(ising_batch *b, int64_t tune_sweeps, const char *cache_
         float ms_mixed_best = 0.f;
         std::map<int64_t, Tile> keep_tiles;
         std::map<int64_t, plan::Kind> keep_kinds;
+        std::vector<std::vector<uint32_t>> keep_groups;
         plan::Model keep_model = plan::kAdditive;
         for (plan::Model model : {plan::kAdditive, plan::kRounds}) {
             if (e != hipSuccess || rc != ISING_OK)
@@ -1235,7 +1283,8 @@ int ising_batch_autotune(ising_batch *b, int64_t tune_sweeps, const char *cache_
                 b->model = model;
                 Plan p;
                 double est = 0.0;
-                const bool packed = make_mixed_plan(b, slots, &p, &est);
+                std::vector<std::vector<uint32_t>> groups;
+                const bool packed = make_mixed_plan(b, slots, &p, &est, &groups);
                 if (log) {
                     std::fprintf(stderr, "[autotune] %s model, rule %d: %s, estimated %.4f ms\n",
                                  model == plan::kRounds ? "rounds" : "additive", rule,
@@ -1261,6 +1310,7 @@ int ising_batch_autotune(ising_batch *b, int64_t tune_sweeps, const char *cache_
                         keep_tiles = tiles;
                         keep_kinds = kinds;
                         keep_model = model;
+                        keep_groups = std::move(groups);
                     }
                 }
                 if (e != hipSuccess || rc != ISING_OK)
@@ -1272,6 +1322,126 @@ int ising_batch_autotune(ising_batch *b, int64_t tune_sweeps, const char *cache_
             b->kinds = keep_kinds;
             b->model = keep_model;
             b->mixed = true;
+            // Measured refinement: time every bundle of the kept packing and
+            // move one lattice at a time out of the slowest workgroup onto the
+            // least loaded one it fits.  Many workgroups end within a few per
+            // cent of each other, so a move is kept unless the whole launch
+            // gets slower (beyond 0.3 %, the timing noise): the slowest ones
+            // come down one by one.  The fastest plan seen is the result.
+            std::vector<std::vector<uint32_t>> groups = keep_groups;
+            std::vector<double> dur;
+            float cur = 0.f;
+            auto fits = [&](const std::vector<uint32_t> &g, uint32_t q) {
+                uint32_t threads = 0, lds = 0;
+                for (uint32_t x : g) {
+                    threads += mixed_threads(b->lats[x].W, b->tiles.at(b->Ls[x]));
+                    lds += batch_lds_words(b->lats[x].W);
+                }
+                threads += mixed_threads(b->lats[q].W, b->tiles.at(b->Ls[q]));
+                lds += batch_lds_words(b->lats[q].W);
+                return threads <= (uint32_t)kBatchThreads && (size_t)lds * 8 <= kMaxBundleLds;
+            };
+            bool ok_run = time_plan(plan_from_groups(b, groups), &cur, out_try, &dur) &&
+                          out_try == out_ref;
+            auto show = [&](const char *what) {
+                if (!log || dur.size() < groups.size())
+                    return;
+                std::vector<size_t> o(groups.size());
+                for (size_t i = 0; i < o.size(); ++i)
+                    o[i] = i;
+                std::stable_sort(o.begin(), o.end(), [&](size_t x, size_t y) { return dur[x] > dur[y]; });
+                for (size_t k = 0; k < o.size(); ++k) {
+                    if (k >= 8 && k + 4 < o.size())
+                        continue;
+                    std::map<int64_t, int> comp;
+                    for (uint32_t q : groups[o[k]])
+                        ++comp[b->Ls[q]];
+                    std::string c;
+                    for (auto &kv : comp)
+                        c += " " + std::to_string(kv.first) + "x" + std::to_string(kv.second);
+                    std::fprintf(stderr, "[autotune]   %s #%zu %.4f ms:%s\n", what, k, dur[o[k]],
+                                 c.c_str());
+                }
+            };
+            show("kept");
+            int moves = 0;
+            float best_ms = cur;
+            std::vector<std::vector<uint32_t>> best_groups = groups;
+            for (int it = 0; ok_run && it < 96; ++it) {
+                if (groups.size() < slots)
+                    groups.emplace_back(); // an idle workgroup is a target too
+                if (dur.size() < groups.size())
+                    dur.resize(groups.size(), 0.0);
+                std::vector<size_t> order(groups.size());
+                for (size_t i = 0; i < order.size(); ++i)
+                    order[i] = i;
+                std::stable_sort(order.begin(), order.end(),
+                                 [&](size_t x, size_t y) { return dur[x] > dur[y]; });
+                const size_t sw = order.front();
+                // one lattice of each size in the slowest workgroup, largest first
+                std::vector<uint32_t> cand;
+                for (uint32_t q : groups[sw]) {
+                    bool seen = false;
+                    for (uint32_t c : cand)
+                        seen = seen || b->Ls[c] == b->Ls[q];
+                    if (!seen)
+                        cand.push_back(q);
+                }
+                std::stable_sort(cand.begin(), cand.end(),
+                                 [&](uint32_t x, uint32_t y) { return b->Ls[x] > b->Ls[y]; });
+                bool moved = false;
+                for (uint32_t q : cand) {
+                    if (moved || !ok_run || groups[sw].size() < 2)
+                        break;
+                    // the four least loaded workgroups it fits, least first
+                    std::vector<size_t> targets;
+                    for (size_t k = order.size(); k-- > 1 && targets.size() < 4;)
+                        if (fits(groups[order[k]], q))
+                            targets.push_back(order[k]);
+                    for (size_t tw : targets) {
+                        std::vector<std::vector<uint32_t>> trial = groups;
+                        trial[sw].erase(std::find(trial[sw].begin(), trial[sw].end(), q));
+                        trial[tw].push_back(q);
+                        std::vector<std::vector<uint32_t>> nonempty;
+                        for (auto &g : trial)
+                            if (!g.empty())
+                                nonempty.push_back(g);
+                        float ms_t = 0.f;
+                        std::vector<double> dur_t;
+                        if (!time_plan(plan_from_groups(b, nonempty), &ms_t, out_try, &dur_t)) {
+                            ok_run = false;
+                            break;
+                        }
+                        if (out_try != out_ref) {
+                            rc = host::fail(ISING_E_HIP, "autotune: a refined plan changed the "
+                                            "lattices");
+                            ok_run = false;
+                            break;
+                        }
+                        if (ms_t < cur * 1.003f) {
+                            groups = std::move(nonempty);
+                            dur = std::move(dur_t);
+                            cur = ms_t;
+                            moved = true;
+                            ++moves;
+                            if (cur < best_ms) {
+                                best_ms = cur;
+                                best_groups = groups;
+                            }
+                            break;
+                        }
+                    }
+                }
+                if (!groups.empty() && groups.back().empty())
+                    groups.pop_back();
+                if (!moved)
+                    break;
+            }
+            if (log)
+                std::fprintf(stderr, "[autotune] refined by %d moves: %.4f ms (best %.4f)\n",
+                             moves, (double)cur, (double)best_ms);
+            show("refined");
+            b->groups = (rc == ISING_OK && best_ms < ms_mixed_best) ? best_groups : keep_groups;
         } else {
             b->tiles = hom_tiles;
             b->kinds.clear();
@@ -1283,6 +1453,8 @@ int ising_batch_autotune(ising_batch *b, int64_t tune_sweeps, const char *cache_
         (void)hipFree(slot_buf);
     if (bundles)
         (void)hipFree(bundles);
+    if (clk)
+        (void)hipFree(clk);
     if (scratch)
         (void)hipFree(scratch);
     if (ctr)

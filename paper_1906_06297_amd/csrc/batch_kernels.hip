@@ -72,7 +72,8 @@ __device__ __forceinline__ uint64_t decide_word_pair(uint64_t t, const Neighbour
 __global__ __launch_bounds__(kBatchThreads) void k_batch_sweep(
     const BatchLattice *__restrict__ lats, const BatchSlot *__restrict__ slots,
     const BatchBundle *__restrict__ bundles, uint32_t nbundles, uint32_t *__restrict__ next_bundle,
-    uint64_t *__restrict__ words, const uint64_t *__restrict__ rng_counter, int64_t nsweeps)
+    uint64_t *__restrict__ words, const uint64_t *__restrict__ rng_counter, int64_t nsweeps,
+    uint64_t *__restrict__ bundle_clock)
 {
     extern __shared__ uint64_t lds[];
     __shared__ uint32_t item;
@@ -87,6 +88,8 @@ __global__ __launch_bounds__(kBatchThreads) void k_batch_sweep(
         if (b >= nbundles)
             return;
         const BatchBundle bd = bundles[b];
+        if (bundle_clock && tid == 0) // (optional) start and end of each bundle
+            bundle_clock[2 * b] = (uint64_t)wall_clock64();
         // this thread's slot: the last one starting at or before it
         uint32_t lo = 0, hi = bd.count;
         while (hi - lo > 1) {
@@ -157,7 +160,7 @@ __global__ __launch_bounds__(kBatchThreads) void k_batch_sweep(
                             RowMasks rm = j == 0 ? rm0 : row_masks32(k, lt.H, lt.M, 0);
                             if (c)
                                 rm.left_rows = ~rm.left_rows; // rows of the other parity
-                            nb = neighbours_ext_rm(src, lt.H, lt.M, k, rm);
+                            nb = neighbours_ext32((const uint32_t *)src, lt.H, lt.M, k, rm);
                         }
                         const uint64_t tw = tgt[k];
                         const uint64_t valid = valid_mask(k, lt.M);
@@ -185,6 +188,11 @@ __global__ __launch_bounds__(kBatchThreads) void k_batch_sweep(
                 const uint32_t kk = k - c * lt.W;
                 words[lt.word_off + k] = (c ? E1 : E0)[kk] & valid_mask(kk, lt.M);
             }
+        if (bundle_clock) {
+            __syncthreads();
+            if (tid == 0)
+                bundle_clock[2 * b + 1] = (uint64_t)wall_clock64();
+        }
     }
 }
 
@@ -304,12 +312,13 @@ hipError_t launch_batch_init(const BatchLattice *lats, uint32_t n, uint64_t *wor
 hipError_t launch_batch_sweep(const BatchLattice *lats, const BatchSlot *slots,
                               const BatchBundle *bundles, uint32_t nbundles, uint32_t grid,
                               size_t lds_bytes, uint32_t *next_bundle, uint64_t *words,
-                              uint64_t *rng_counter, int64_t nsweeps, hipStream_t s)
+                              uint64_t *rng_counter, int64_t nsweeps, hipStream_t s,
+                              uint64_t *bundle_clock)
 {
     hipLaunchKernelGGL(k_batch_prepare, dim3(1), dim3(64), 0, s, next_bundle);
     hipLaunchKernelGGL(k_batch_sweep, dim3(grid), dim3(kBatchThreads), lds_bytes, s, lats,
                        slots, bundles, nbundles, next_bundle, words,
-                       (const uint64_t *)rng_counter, nsweeps);
+                       (const uint64_t *)rng_counter, nsweeps, bundle_clock);
     hipLaunchKernelGGL(k_batch_advance, dim3(1), dim3(64), 0, s, rng_counter, nsweeps);
     return hipGetLastError();
 }

@@ -179,6 +179,37 @@ int emu_half_aligned_neighbours_check(int64_t L, uint64_t seed)
     return bad;
 }
 
+// The batch kernel's 32-bit general extraction against the 64-bit one, for
+// every word of both colours of an L x L lattice (any even L <= 722).
+int emu_ext32_neighbours_check(int64_t L, uint64_t seed)
+{
+    const uint32_t H = (uint32_t)(L / 2), M = (uint32_t)(L * L / 2), W = (M + 63) / 64;
+    std::vector<uint64_t> E(W + 2);
+    uint64_t z = seed * 0x9E3779B97F4A7C15ull + 5;
+    for (uint32_t k = 0; k < W + 2; ++k) { // splitmix64; the continuation is arbitrary here
+        uint64_t x = (z += 0x9E3779B97F4A7C15ull);
+        x = (x ^ (x >> 30)) * 0xBF58476D1CE4E5B9ull;
+        x = (x ^ (x >> 27)) * 0x94D049BB133111EBull;
+        E[k] = x ^ (x >> 31);
+    }
+    std::vector<uint32_t> E32(2 * (W + 2));
+    for (uint32_t k = 0; k < W + 2; ++k) {
+        E32[2 * k] = (uint32_t)E[k];
+        E32[2 * k + 1] = (uint32_t)(E[k] >> 32);
+    }
+    int bad = 0;
+    for (int c = 0; c < 2; ++c)
+        for (uint32_t k = 0; k < W; ++k) {
+            RowMasks rm = row_masks32(k, H, M, 0);
+            if (c)
+                rm.left_rows = ~rm.left_rows;
+            const Neighbours a = neighbours_ext_rm(E.data(), H, M, k, rm);
+            const Neighbours b = neighbours_ext32(E32.data(), H, M, k, rm);
+            bad += (a.ce != b.ce) || (a.up != b.up) || (a.dn != b.dn) || (a.sd != b.sd);
+        }
+    return bad;
+}
+
 // floor(h / Hr) by the half-aligned multiply, over its whole range.
 int emu_half_row_check()
 {

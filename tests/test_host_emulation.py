@@ -34,6 +34,7 @@ def emu(tmp_path_factory):
     lib.emu_block_decision_check.argtypes = [ctypes.c_uint64, ctypes.c_int]
     lib.emu_aligned_neighbours_check.argtypes = [ctypes.c_int64, ctypes.c_uint64]
     lib.emu_half_aligned_neighbours_check.argtypes = [ctypes.c_int64, ctypes.c_uint64]
+    lib.emu_ext32_neighbours_check.argtypes = [ctypes.c_int64, ctypes.c_uint64]
     lib.emu_xcd_block.argtypes = [ctypes.c_uint32, ctypes.c_uint32]
     lib.emu_xcd_block.restype = ctypes.c_uint32
     lib.emu_philox_fast.argtypes = [ctypes.c_uint32] * 6 + [ctypes.c_int,
@@ -179,3 +180,12 @@ def test_batch_half_aligned_neighbours_equal_the_general_extraction(emu, L):
     words straddle rows, and whole-word rows alike)."""
     assert emu.emu_half_aligned_neighbours_check(L, L + 3) == 0
     assert emu.emu_half_row_check() == 0
+
+
+@pytest.mark.parametrize("L", [4, 6, 10, 14, 16, 24, 30, 48, 50, 96, 100, 126, 130, 200, 300, 722])
+def test_batch_general_neighbours_32bit_equal_the_64bit_extraction(emu, L):
+    """The batch kernel's general extraction on 32-bit halves (funnel shifts of
+    three halves, 32-bit wrapped positions) equals the 64-bit extraction for
+    every word of both colours, including the partial last word and the
+    cyclic continuation."""
+    assert emu.emu_ext32_neighbours_check(L, L + 11) == 0
