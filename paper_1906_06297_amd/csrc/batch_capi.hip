@@ -637,6 +637,543 @@ bool write_cache(const char *path, const ising_batch *b)
     return (bool)f;
 }
 
+// ------------------------------------------------------------------ tuner
+// The autotuner's state: a scratch copy of the lattices and counter (tuning
+// never changes the batch), the reference result every timed plan must
+// reproduce bit for bit, and the timings of every size alone.
+class Tuner {
+  public:
+    Tuner(ising_batch *b, int64_t sweeps, hipStream_t s)
+        : b_(b), sweeps_(sweeps), s_(s), log_(std::getenv("ISING_AUTOTUNE_LOG") != nullptr)
+    {
+    }
+    ~Tuner()
+    {
+        for (void *p : {(void *)slot_buf_, (void *)bundles_, (void *)clk_, (void *)scratch_,
+                        (void *)ctr_, (void *)next_})
+            if (p)
+                (void)hipFree(p);
+        if (e0_)
+            (void)hipEventDestroy(e0_);
+        if (e1_)
+            (void)hipEventDestroy(e1_);
+    }
+
+    int start()
+    {
+        nbytes_ = (size_t)ising_batch_words(b_->n, b_->Ls.data()) * 8;
+        hipError_t e = hipMalloc(&scratch_, nbytes_);
+        if (e == hipSuccess)
+            e = hipMalloc(&ctr_, 8);
+        if (e == hipSuccess)
+            e = hipMalloc(&next_, 4);
+        if (e == hipSuccess)
+            e = hipEventCreate(&e0_);
+        if (e == hipSuccess)
+            e = hipEventCreate(&e1_);
+        return e == hipSuccess ? ISING_OK : host::hip_fail(e, "autotune");
+    }
+
+    // Runs plan p for the tuning sweeps on the scratch copy, from the batch's
+    // lattices and counter 0 every time; best of two launches in *best, the
+    // lattices in out and (per_bundle) each bundle's duration in the second
+    // launch, in ms.  `all`: the plan must hold every lattice.
+    int time_plan(const Plan &p, float *best, std::vector<uint64_t> &out,
+                  std::vector<double> *per_bundle = nullptr, bool all = true)
+    {
+        uint32_t grid = 0;
+        if (int rc = check_plan(b_->lats.data(), b_->n, p.slots.data(), p.slots.size(),
+                                p.bundles.data(), p.bundles.size(), p.lds_bytes, all))
+            return rc;
+        if (int rc = persistent_grid(p.lds_bytes, (uint32_t)p.bundles.size(), &grid))
+            return rc;
+        for (void *q : {(void *)slot_buf_, (void *)bundles_})
+            if (q)
+                (void)hipFree(q);
+        slot_buf_ = nullptr;
+        bundles_ = nullptr;
+        hipError_t e = hipMalloc(&slot_buf_, p.slots.size() * sizeof(BatchSlot));
+        if (e == hipSuccess)
+            e = hipMalloc(&bundles_, p.bundles.size() * sizeof(BatchBundle));
+        if (e == hipSuccess)
+            e = hipMemcpy(slot_buf_, p.slots.data(), p.slots.size() * sizeof(BatchSlot),
+                          hipMemcpyHostToDevice);
+        if (e == hipSuccess)
+            e = hipMemcpy(bundles_, p.bundles.data(), p.bundles.size() * sizeof(BatchBundle),
+                          hipMemcpyHostToDevice);
+        if (per_bundle && e == hipSuccess && clk_n_ < 2 * p.bundles.size()) {
+            if (clk_)
+                (void)hipFree(clk_);
+            clk_ = nullptr;
+            clk_n_ = 2 * p.bundles.size();
+            e = hipMalloc(&clk_, clk_n_ * sizeof(uint64_t));
+        }
+        if (per_bundle && e == hipSuccess && wall_khz_ <= 0.0) {
+            int dev = 0, khz = 0;
+            e = hipGetDevice(&dev);
+            if (e == hipSuccess)
+                e = hipDeviceGetAttribute(&khz, hipDeviceAttributeWallClockRate, dev);
+            wall_khz_ = khz > 0 ? (double)khz : 1.0e5;
+        }
+        *best = 1e30f;
+        for (int rep = 0; rep < 2 && e == hipSuccess; ++rep) {
+            const uint64_t zero = 0;
+            float ms = 0.f;
+            e = hipMemcpyAsync(scratch_, b_->words, nbytes_, hipMemcpyDeviceToDevice, s_);
+            if (e == hipSuccess)
+                e = hipMemcpyAsync(ctr_, &zero, 8, hipMemcpyHostToDevice, s_);
+            if (e == hipSuccess)
+                e = hipEventRecord(e0_, s_);
+            if (e == hipSuccess)
+                e = launch_batch_sweep(b_->d_lats, slot_buf_, bundles_, (uint32_t)p.bundles.size(),
+                                       grid, p.lds_bytes, next_, scratch_, ctr_, sweeps_, s_,
+                                       (per_bundle && rep == 1) ? clk_ : nullptr);
+            if (e == hipSuccess)
+                e = hipEventRecord(e1_, s_);
+            if (e == hipSuccess)
+                e = hipEventSynchronize(e1_);
+            if (e == hipSuccess)
+                e = hipEventElapsedTime(&ms, e0_, e1_);
+            *best = std::min(*best, ms);
+        }
+        if (e == hipSuccess) {
+            out.resize(nbytes_ / 8);
+            e = hipMemcpy(out.data(), scratch_, nbytes_, hipMemcpyDeviceToHost);
+        }
+        if (per_bundle && e == hipSuccess) {
+            std::vector<uint64_t> t(2 * p.bundles.size());
+            e = hipMemcpy(t.data(), clk_, t.size() * sizeof(uint64_t), hipMemcpyDeviceToHost);
+            per_bundle->assign(p.bundles.size(), 0.0);
+            for (size_t i = 0; i < p.bundles.size() && e == hipSuccess; ++i)
+                (*per_bundle)[i] = (double)(t[2 * i + 1] - t[2 * i]) / wall_khz_;
+        }
+        return e == hipSuccess ? ISING_OK : host::hip_fail(e, "autotune");
+    }
+
+    // Every tile candidate of each size -- each also with a half and a
+    // quarter of the lattices per bundle -- timed with that size alone; all
+    // must reproduce the same lattices.
+    int time_sizes()
+    {
+        for (auto &kv : b_->tiles) {
+            const int64_t L = kv.first;
+            const uint32_t W = words_of(L);
+            std::vector<Tile> cands;
+            for (uint32_t lpw : {1u, 2u})
+                for (uint32_t w : {1u, 2u, 3u, 4u, 6u, 8u, 12u, 16u}) {
+                    const Tile t{w, lpw};
+                    if (!tile_ok(W, t))
+                        continue;
+                    bool dup = false;
+                    for (const Tile &c : cands)
+                        dup = dup || (c.lpw == lpw && threads_per_lattice(W, c) ==
+                                                          threads_per_lattice(W, t));
+                    if (!dup)
+                        cands.push_back(t);
+                }
+            // half-empty workgroups run their lattices' sweeps sooner, on
+            // compute units the batch leaves idle
+            const size_t nbase = cands.size();
+            for (size_t i = 0; i < nbase; ++i) {
+                const uint32_t full = make_plan(b_, L, cands[i]).bundles.front().count;
+                for (uint32_t cap : {full / 2, full / 4})
+                    if (cap >= 1 && cap < full)
+                        cands.push_back(Tile{cands[i].wpt, cands[i].lpw, cap});
+            }
+            std::vector<plan::Option> o;
+            std::vector<Tile> ot;
+            std::vector<uint32_t> op;
+            size_t fi = 0;
+            std::vector<uint64_t> ref, out;
+            for (const Tile &w : cands) {
+                const Plan p = make_plan(b_, L, w);
+                uint32_t held = 0;
+                if (int rc = resident_slots(p.lds_bytes, &held))
+                    return rc;
+                slots_ = slots_ ? std::min(slots_, held) : held;
+                float ms = 0.f;
+                if (int rc = time_plan(p, &ms, o.empty() ? ref : out, nullptr, false))
+                    return rc;
+                if (!o.empty() && out != ref)
+                    return host::fail(ISING_E_HIP, "autotune: tile (%u, %u, %u) of L=%lld changed "
+                                      "the lattice", w.wpt, w.lpw, w.cap, (long long)L);
+                o.push_back(plan::Option{(uint32_t)p.bundles.size(), (double)ms});
+                ot.push_back(w);
+                op.push_back(p.bundles.front().count);
+                if (o.back().ms < o[fi].ms)
+                    fi = o.size() - 1;
+            }
+            sizes_.push_back(L);
+            opts_.push_back(std::move(o));
+            opt_tiles_.push_back(std::move(ot));
+            opt_per_.push_back(std::move(op));
+            fastest_.push_back(fi);
+        }
+        return ISING_OK;
+    }
+
+    // One size per bundle: the jointly estimated best tiles, kept only if the
+    // whole batch, timed both ways, runs faster with them than with the
+    // fastest tile of every size alone.
+    int choose_one_size()
+    {
+        pick_ = plan::choose(opts_, fastest_, slots_);
+        apply(fastest_);
+        if (int rc = time_plan(make_plan(b_, 0, Tile{1, 1}), &ms_best_, ref_))
+            return rc;
+        if (pick_ != fastest_) {
+            float ms_pick = 0.f;
+            apply(pick_);
+            if (int rc = time_plan(make_plan(b_, 0, Tile{1, 1}), &ms_pick, out_))
+                return rc;
+            if (out_ != ref_)
+                return host::fail(ISING_E_HIP, "autotune: the joint tiles changed the lattices");
+            if (ms_fast_wins(ms_pick))
+                pick_ = fastest_;
+            else
+                ms_best_ = ms_pick;
+        }
+        apply(pick_);
+        return ISING_OK;
+    }
+
+    // Mixed-size bundles.  For each duration model, (a, b) per size and tile
+    // from the single-size timings; tiles per size by one of two rules -- the
+    // cheapest per lattice among the tiles whose single lattice fits the
+    // one-size plan's makespan, or the one-size plan's own tiles -- each with
+    // every size mixing, or with the sizes whose colour rows are not whole
+    // 32-bit halves (general neighbour extraction, long per-word chains) in
+    // workgroups of their own.  Each packing is timed on the whole batch; the
+    // fastest is refined by measurement and replaces the one-size plan if
+    // faster.
+    int choose_mixed()
+    {
+        if (sizes_.empty())
+            return ISING_OK;
+        const double hom_est = plan::estimate(opts_, pick_, slots_).makespan;
+        if (log_)
+            std::fprintf(stderr, "[autotune] one-size plan: estimated %.4f ms, timed %.4f ms, "
+                         "%u workgroups\n", hom_est, (double)ms_best_, slots_);
+        const std::map<int64_t, Tile> hom_tiles = b_->tiles;
+        float ms_keep = 0.f;
+        Choice keep;
+        for (plan::Model model : {plan::kAdditive, plan::kRounds}) {
+            Fits f = fit_models(model);
+            for (int rule = 0; rule < 4; ++rule) {
+                Choice c = tiles_by_rule(f, model, rule, hom_tiles, hom_est);
+                b_->tiles = c.tiles;
+                b_->kinds = c.kinds;
+                b_->model = model;
+                Plan p;
+                double est = 0.0;
+                const bool packed = make_mixed_plan(b_, slots_, &p, &est, &c.groups);
+                if (log_)
+                    log_choice(c, model, rule, packed, est);
+                if (!packed)
+                    continue;
+                float ms = 0.f;
+                if (int rc = time_plan(p, &ms, out_))
+                    return rc;
+                if (log_)
+                    std::fprintf(stderr, "[autotune]   timed %.4f ms\n", (double)ms);
+                if (out_ != ref_)
+                    return host::fail(ISING_E_HIP, "autotune: mixed-size bundles changed the "
+                                      "lattices");
+                if (ms < ms_best_ && (keep.tiles.empty() || ms < ms_keep)) {
+                    ms_keep = ms;
+                    keep = std::move(c);
+                    keep.model = model;
+                }
+            }
+        }
+        if (keep.tiles.empty()) {
+            b_->tiles = hom_tiles;
+            b_->kinds.clear();
+            b_->model = plan::kAdditive;
+            b_->mixed = false;
+            return ISING_OK;
+        }
+        b_->tiles = keep.tiles;
+        b_->kinds = keep.kinds;
+        b_->model = keep.model;
+        b_->mixed = true;
+        std::vector<std::vector<uint32_t>> groups = keep.groups;
+        float ms = ms_keep;
+        if (int rc = refine(groups, &ms))
+            return rc;
+        b_->groups = ms < ms_keep ? groups : keep.groups;
+        return ISING_OK;
+    }
+
+  private:
+    struct Fits { // per size: (a, b) of each tile, the tile, fitted through two x
+        std::vector<std::vector<plan::Kind>> kinds;
+        std::vector<std::vector<Tile>> tiles;
+        std::vector<std::vector<bool>> two;
+    };
+    struct Choice {
+        std::map<int64_t, Tile> tiles;
+        std::map<int64_t, plan::Kind> kinds;
+        std::vector<std::vector<uint32_t>> groups;
+        plan::Model model = plan::kAdditive;
+    };
+
+    void apply(const std::vector<size_t> &pick)
+    {
+        for (size_t i = 0; i < sizes_.size(); ++i) {
+            b_->tiles[sizes_[i]] = opt_tiles_[i][pick[i]];
+            b_->est_ms[sizes_[i]] = plan::bundle_ms(opts_[i][pick[i]], slots_);
+        }
+    }
+    bool ms_fast_wins(float ms_pick) const { return ms_best_ < ms_pick; }
+
+    // (a, b) of every size and tile under `model`; a one-x fit takes the
+    // median intercept of the two-x fits.
+    Fits fit_models(plan::Model model) const
+    {
+        Fits f;
+        f.kinds.resize(sizes_.size());
+        f.tiles.resize(sizes_.size());
+        f.two.resize(sizes_.size());
+        std::vector<double> intercepts;
+        for (int pass = 0; pass < 2; ++pass) {
+            double a_def = 0.0;
+            if (pass == 1 && !intercepts.empty()) {
+                std::sort(intercepts.begin(), intercepts.end());
+                a_def = intercepts[intercepts.size() / 2];
+            }
+            for (size_t i = 0; i < sizes_.size(); ++i) {
+                std::map<std::pair<uint32_t, uint32_t>, std::vector<std::pair<uint32_t, double>>>
+                    pts;
+                for (size_t j = 0; j < opts_[i].size(); ++j)
+                    pts[{opt_tiles_[i][j].wpt, opt_tiles_[i][j].lpw}].emplace_back(
+                        opt_per_[i][j], plan::bundle_ms(opts_[i][j], slots_));
+                f.kinds[i].clear();
+                f.tiles[i].clear();
+                f.two[i].clear();
+                for (auto &kv : pts) {
+                    const Tile t{kv.first.first, kv.first.second};
+                    const uint32_t tpl = threads_per_lattice(words_of(sizes_[i]), t);
+                    plan::Kind k;
+                    plan::fit_kind(kv.second, tpl, model, a_def, &k.a, &k.b);
+                    auto x = [&](uint32_t n) {
+                        return model == plan::kRounds ? plan::simd_waves(n * tpl) : n;
+                    };
+                    bool two = false;
+                    for (auto &pt : kv.second)
+                        two = two || x(pt.first) != x(kv.second.front().first);
+                    if (pass == 0 && two)
+                        intercepts.push_back(k.a);
+                    f.kinds[i].push_back(k);
+                    f.tiles[i].push_back(t);
+                    f.two[i].push_back(two);
+                }
+            }
+        }
+        return f;
+    }
+
+    Choice tiles_by_rule(const Fits &f, plan::Model model, int rule,
+                         const std::map<int64_t, Tile> &hom_tiles, double hom_est) const
+    {
+        Choice c;
+        for (size_t i = 0; i < sizes_.size(); ++i) {
+            auto tpl = [&](size_t j) { return threads_per_lattice(words_of(sizes_[i]), f.tiles[i][j]); };
+            // per-lattice share of the compute unit, and one lattice alone
+            auto cost = [&](size_t j) {
+                return model == plan::kRounds ? f.kinds[i][j].b * (double)tpl(j) : f.kinds[i][j].b;
+            };
+            auto alone = [&](size_t j) {
+                return plan::group_time(model, f.kinds[i][j].a, f.kinds[i][j].b, f.kinds[i][j].b,
+                                        tpl(j));
+            };
+            bool any_two = false;
+            for (size_t j = 0; j < f.kinds[i].size(); ++j)
+                any_two = any_two || f.two[i][j];
+            size_t pick = SIZE_MAX;
+            for (size_t j = 0; j < f.kinds[i].size(); ++j) {
+                if (rule % 2 == 1) {
+                    const Tile &h = hom_tiles.at(sizes_[i]);
+                    if (f.tiles[i][j].wpt == h.wpt && f.tiles[i][j].lpw == h.lpw)
+                        pick = j;
+                } else if ((!any_two || f.two[i][j]) && alone(j) <= hom_est &&
+                           (pick == SIZE_MAX || cost(j) < cost(pick) ||
+                            (cost(j) == cost(pick) && f.kinds[i][j].a < f.kinds[i][pick].a))) {
+                    pick = j; // (a one-x fit only guesses its split into a and b)
+                }
+            }
+            if (pick == SIZE_MAX)
+                pick = 0;
+            c.tiles[sizes_[i]] = f.tiles[i][pick];
+            c.kinds[sizes_[i]] = f.kinds[i][pick];
+            c.kinds[sizes_[i]].exclusive = rule >= 2 && (sizes_[i] % 64) != 0;
+        }
+        return c;
+    }
+
+    void log_choice(const Choice &c, plan::Model model, int rule, bool packed, double est) const
+    {
+        std::fprintf(stderr, "[autotune] %s model, rule %d: %s, estimated %.4f ms\n",
+                     model == plan::kRounds ? "rounds" : "additive", rule,
+                     packed ? "packed" : "does not pack", est);
+        for (auto &kv : c.tiles) {
+            const plan::Kind &k = c.kinds.at(kv.first);
+            std::fprintf(stderr, "[autotune]   L=%lld tile (%u, %u) a=%.4f b=%.5f%s\n",
+                         (long long)kv.first, kv.second.wpt, kv.second.lpw, k.a, k.b,
+                         k.exclusive ? " own workgroups" : "");
+        }
+    }
+
+    void log_bundles(const char *what, const std::vector<std::vector<uint32_t>> &groups,
+                     const std::vector<double> &dur) const
+    {
+        if (!log_ || dur.size() < groups.size())
+            return;
+        std::vector<size_t> o(groups.size());
+        for (size_t i = 0; i < o.size(); ++i)
+            o[i] = i;
+        std::stable_sort(o.begin(), o.end(), [&](size_t x, size_t y) { return dur[x] > dur[y]; });
+        for (size_t k = 0; k < o.size(); ++k) {
+            if (k >= 8 && k + 4 < o.size())
+                continue;
+            std::map<int64_t, int> comp;
+            for (uint32_t q : groups[o[k]])
+                ++comp[b_->Ls[q]];
+            std::string c;
+            for (auto &kv : comp)
+                c += " " + std::to_string(kv.first) + "x" + std::to_string(kv.second);
+            std::fprintf(stderr, "[autotune]   %s #%zu %.4f ms:%s\n", what, k, dur[o[k]], c.c_str());
+        }
+    }
+
+    bool fits(const std::vector<uint32_t> &g, uint32_t q) const
+    {
+        uint32_t threads = 0, lds = 0;
+        for (uint32_t x : g) {
+            threads += mixed_threads(b_->lats[x].W, b_->tiles.at(b_->Ls[x]));
+            lds += batch_lds_words(b_->lats[x].W);
+        }
+        threads += mixed_threads(b_->lats[q].W, b_->tiles.at(b_->Ls[q]));
+        lds += batch_lds_words(b_->lats[q].W);
+        return threads <= (uint32_t)kBatchThreads && (size_t)lds * 8 <= kMaxBundleLds;
+    }
+
+    // Measured refinement of a mixed packing: time every bundle and move one
+    // lattice at a time out of the slowest workgroup onto one of the four
+    // least loaded it fits.  Many workgroups end within a few per cent of
+    // each other, so a move is kept unless the whole launch gets slower
+    // (beyond 0.3 %, the timing noise): the slowest ones come down one by
+    // one.  `groups` and *ms end as the fastest plan seen.
+    int refine(std::vector<std::vector<uint32_t>> &groups, float *ms)
+    {
+        std::vector<double> dur;
+        float cur = 0.f;
+        if (int rc = time_plan(plan_from_groups(b_, groups), &cur, out_, &dur))
+            return rc;
+        if (out_ != ref_)
+            return host::fail(ISING_E_HIP, "autotune: a mixed plan changed the lattices");
+        log_bundles("kept", groups, dur);
+        std::vector<std::vector<uint32_t>> best = groups;
+        float best_ms = cur;
+        int moves = 0;
+        for (int it = 0; it < 96; ++it) {
+            if (groups.size() < slots_)
+                groups.emplace_back(); // an idle workgroup is a target too
+            dur.resize(groups.size(), 0.0);
+            std::vector<size_t> order(groups.size());
+            for (size_t i = 0; i < order.size(); ++i)
+                order[i] = i;
+            std::stable_sort(order.begin(), order.end(),
+                             [&](size_t x, size_t y) { return dur[x] > dur[y]; });
+            const size_t sw = order.front();
+            // one lattice of each size in the slowest workgroup, largest first
+            std::vector<uint32_t> cand;
+            for (uint32_t q : groups[sw]) {
+                bool seen = false;
+                for (uint32_t c : cand)
+                    seen = seen || b_->Ls[c] == b_->Ls[q];
+                if (!seen)
+                    cand.push_back(q);
+            }
+            std::stable_sort(cand.begin(), cand.end(),
+                             [&](uint32_t x, uint32_t y) { return b_->Ls[x] > b_->Ls[y]; });
+            bool moved = false;
+            for (uint32_t q : cand) {
+                if (moved || groups[sw].size() < 2)
+                    break;
+                std::vector<size_t> targets; // least loaded first
+                for (size_t k = order.size(); k-- > 1 && targets.size() < 4;)
+                    if (fits(groups[order[k]], q))
+                        targets.push_back(order[k]);
+                for (size_t tw : targets) {
+                    std::vector<std::vector<uint32_t>> trial = groups;
+                    trial[sw].erase(std::find(trial[sw].begin(), trial[sw].end(), q));
+                    trial[tw].push_back(q);
+                    std::vector<std::vector<uint32_t>> nonempty;
+                    for (auto &g : trial)
+                        if (!g.empty())
+                            nonempty.push_back(g);
+                    float ms_t = 0.f;
+                    std::vector<double> dur_t;
+                    if (int rc = time_plan(plan_from_groups(b_, nonempty), &ms_t, out_, &dur_t))
+                        return rc;
+                    if (out_ != ref_)
+                        return host::fail(ISING_E_HIP, "autotune: a refined plan changed the "
+                                          "lattices");
+                    if (ms_t < cur * 1.003f) {
+                        groups = std::move(nonempty);
+                        dur = std::move(dur_t);
+                        cur = ms_t;
+                        moved = true;
+                        ++moves;
+                        if (cur < best_ms) {
+                            best_ms = cur;
+                            best = groups;
+                        }
+                        break;
+                    }
+                }
+            }
+            if (!groups.empty() && groups.back().empty())
+                groups.pop_back();
+            if (!moved)
+                break;
+        }
+        if (log_) {
+            std::fprintf(stderr, "[autotune] refined by %d moves: %.4f ms (best %.4f)\n", moves,
+                         (double)cur, (double)best_ms);
+            log_bundles("refined", groups, dur);
+        }
+        groups = std::move(best);
+        *ms = best_ms;
+        return ISING_OK;
+    }
+
+    ising_batch *b_;
+    int64_t sweeps_;
+    hipStream_t s_;
+    bool log_;
+    size_t nbytes_ = 0;
+    uint64_t *scratch_ = nullptr, *ctr_ = nullptr, *clk_ = nullptr;
+    uint32_t *next_ = nullptr;
+    BatchSlot *slot_buf_ = nullptr;
+    BatchBundle *bundles_ = nullptr;
+    size_t clk_n_ = 0;
+    double wall_khz_ = 0.0;
+    hipEvent_t e0_ = nullptr, e1_ = nullptr;
+    uint32_t slots_ = 0;
+    // per size: the options timed alone, their tiles, lattices in their
+    // fullest bundle, and the fastest
+    std::vector<int64_t> sizes_;
+    std::vector<std::vector<plan::Option>> opts_;
+    std::vector<std::vector<Tile>> opt_tiles_;
+    std::vector<std::vector<uint32_t>> opt_per_;
+    std::vector<size_t> fastest_;
+    std::vector<size_t> pick_;
+    float ms_best_ = 0.f;              // the one-size plan's timing
+    std::vector<uint64_t> ref_, out_; // the whole batch: reference result, latest result
+};
+
 } // namespace
 
 extern "C" {
@@ -960,9 +1497,6 @@ int ising_batch_autotune(ising_batch *b, int64_t tune_sweeps, const char *cache_
         return e;
     if (tune_sweeps <= 0)
         return host::fail(ISING_E_BADARG, "tune_sweeps must be > 0");
-    hipStream_t s = (hipStream_t)hip_stream;
-    // ISING_AUTOTUNE_LOG set: the plans' estimates and timings to stderr
-    const bool log = std::getenv("ISING_AUTOTUNE_LOG") != nullptr;
     b->est_ms.clear();
     b->kinds.clear();
     b->groups.clear();
@@ -985,495 +1519,20 @@ int ising_batch_autotune(ising_batch *b, int64_t tune_sweeps, const char *cache_
             return install_current_plan(b);
         }
     }
-    // Scratch copy of the lattices and counter: tuning never changes the batch.
-    const size_t nbytes = (size_t)ising_batch_words(b->n, b->Ls.data()) * 8;
-    uint64_t *scratch = nullptr, *ctr = nullptr;
-    uint32_t *next = nullptr;
-    BatchSlot *slot_buf = nullptr;
-    BatchBundle *bundles = nullptr;
-    hipEvent_t e0 = nullptr, e1 = nullptr;
-    hipError_t e = hipMalloc(&scratch, nbytes);
-    if (e == hipSuccess)
-        e = hipMalloc(&ctr, 8);
-    if (e == hipSuccess)
-        e = hipMalloc(&next, 4);
-    if (e == hipSuccess)
-        e = hipEventCreate(&e0);
-    if (e == hipSuccess)
-        e = hipEventCreate(&e1);
     int rc = ISING_OK;
-    // Runs plan p for tune_sweeps sweeps on the scratch copy, from the batch's
-    // lattices and counter 0 every time; best of two launches, lattices to out,
-    // and (per_bundle) each bundle's duration in the second launch, in ms.
-    uint64_t *clk = nullptr;
-    size_t clk_n = 0;
-    double wall_khz = 0.0;
-    auto time_plan = [&](const Plan &p, float *best, std::vector<uint64_t> &out,
-                         std::vector<double> *per_bundle = nullptr) -> bool {
-        uint32_t grid = 0;
-        if ((rc = check_plan(b->lats.data(), b->n, p.slots.data(), p.slots.size(),
-                             p.bundles.data(), p.bundles.size(), p.lds_bytes, false)))
-            return false;
-        if ((rc = persistent_grid(p.lds_bytes, (uint32_t)p.bundles.size(), &grid)))
-            return false;
-        if (slot_buf)
-            (void)hipFree(slot_buf);
-        if (bundles)
-            (void)hipFree(bundles);
-        slot_buf = nullptr;
-        bundles = nullptr;
-        e = hipMalloc(&slot_buf, p.slots.size() * sizeof(BatchSlot));
-        if (e == hipSuccess)
-            e = hipMalloc(&bundles, p.bundles.size() * sizeof(BatchBundle));
-        if (e == hipSuccess)
-            e = hipMemcpy(slot_buf, p.slots.data(), p.slots.size() * sizeof(BatchSlot),
-                          hipMemcpyHostToDevice);
-        if (e == hipSuccess)
-            e = hipMemcpy(bundles, p.bundles.data(), p.bundles.size() * sizeof(BatchBundle),
-                          hipMemcpyHostToDevice);
-        if (per_bundle && e == hipSuccess && clk_n < 2 * p.bundles.size()) {
-            if (clk)
-                (void)hipFree(clk);
-            clk = nullptr;
-            clk_n = 2 * p.bundles.size();
-            e = hipMalloc(&clk, clk_n * sizeof(uint64_t));
-        }
-        if (per_bundle && e == hipSuccess && wall_khz <= 0.0) {
-            int dev = 0, khz = 0;
-            e = hipGetDevice(&dev);
-            if (e == hipSuccess)
-                e = hipDeviceGetAttribute(&khz, hipDeviceAttributeWallClockRate, dev);
-            wall_khz = khz > 0 ? (double)khz : 1.0e5;
-        }
-        *best = 1e30f;
-        for (int rep = 0; rep < 2 && e == hipSuccess; ++rep) {
-            const uint64_t zero = 0;
-            float ms = 0.f;
-            uint64_t *bc = (per_bundle && rep == 1) ? clk : nullptr;
-            e = hipMemcpyAsync(scratch, b->words, nbytes, hipMemcpyDeviceToDevice, s);
-            if (e == hipSuccess)
-                e = hipMemcpyAsync(ctr, &zero, 8, hipMemcpyHostToDevice, s);
-            if (e == hipSuccess)
-                e = hipEventRecord(e0, s);
-            if (e == hipSuccess)
-                e = launch_batch_sweep(b->d_lats, slot_buf, bundles, (uint32_t)p.bundles.size(),
-                                       grid, p.lds_bytes, next, scratch, ctr, tune_sweeps, s, bc);
-            if (e == hipSuccess)
-                e = hipEventRecord(e1, s);
-            if (e == hipSuccess)
-                e = hipEventSynchronize(e1);
-            if (e == hipSuccess)
-                e = hipEventElapsedTime(&ms, e0, e1);
-            *best = std::min(*best, ms);
-        }
-        if (e == hipSuccess) {
-            out.resize(nbytes / 8);
-            e = hipMemcpy(out.data(), scratch, nbytes, hipMemcpyDeviceToHost);
-        }
-        if (per_bundle && e == hipSuccess) {
-            std::vector<uint64_t> t(2 * p.bundles.size());
-            e = hipMemcpy(t.data(), clk, t.size() * sizeof(uint64_t), hipMemcpyDeviceToHost);
-            per_bundle->assign(p.bundles.size(), 0.0);
-            for (size_t i = 0; i < p.bundles.size() && e == hipSuccess; ++i)
-                (*per_bundle)[i] = (double)(t[2 * i + 1] - t[2 * i]) / wall_khz;
-        }
-        return e == hipSuccess;
-    };
-    // Every tile candidate of each size, timed with that size alone.
-    std::vector<int64_t> sizes;
-    std::vector<std::vector<plan::Option>> opts;
-    std::vector<std::vector<Tile>> opt_tiles;
-    std::vector<std::vector<uint32_t>> opt_per; // lattices in the option's fullest bundle
-    std::vector<size_t> fastest;
-    uint32_t slots = 0;
-    std::vector<uint64_t> out_ref, out_try;
-    for (auto &kv : b->tiles) {
-        if (e != hipSuccess || rc != ISING_OK)
-            break;
-        const int64_t L = kv.first;
-        const uint32_t W = words_of(L);
-        std::vector<Tile> cands;
-        for (uint32_t lpw : {1u, 2u})
-            for (uint32_t w : {1u, 2u, 3u, 4u, 6u, 8u, 12u, 16u}) {
-                const Tile t{w, lpw};
-                if (!tile_ok(W, t))
-                    continue;
-                bool dup = false;
-                for (const Tile &c : cands)
-                    dup = dup || (c.lpw == lpw && threads_per_lattice(W, c) ==
-                                                      threads_per_lattice(W, t));
-                if (!dup)
-                    cands.push_back(t);
-            }
-        // and each with fewer lattices per bundle: half-empty workgroups run
-        // their lattices' sweeps sooner, on compute units the batch leaves idle
-        const size_t nbase = cands.size();
-        for (size_t i = 0; i < nbase; ++i) {
-            const uint32_t full = make_plan(b, L, cands[i]).bundles.front().count;
-            for (uint32_t cap : {full / 2, full / 4})
-                if (cap >= 1 && cap < full)
-                    cands.push_back(Tile{cands[i].wpt, cands[i].lpw, cap});
-        }
-        std::vector<plan::Option> o;
-        std::vector<Tile> ot;
-        std::vector<uint32_t> op;
-        size_t fi = 0;
-        for (const Tile &w : cands) {
-            const Plan p = make_plan(b, L, w);
-            uint32_t held = 0;
-            if ((rc = resident_slots(p.lds_bytes, &held)))
-                break;
-            slots = slots ? std::min(slots, held) : held;
-            float ms = 0.f;
-            if (!time_plan(p, &ms, o.empty() ? out_ref : out_try))
-                break;
-            // every candidate must reproduce the same lattices bit for bit
-            if (!o.empty() && out_try != out_ref) {
-                rc = host::fail(ISING_E_HIP, "autotune: tile (%u, %u, %u) of L=%lld changed the "
-                                "lattice", w.wpt, w.lpw, w.cap, (long long)L);
-                break;
-            }
-            o.push_back(plan::Option{(uint32_t)p.bundles.size(), (double)ms});
-            ot.push_back(w);
-            op.push_back(p.bundles.front().count);
-            if (o.back().ms < o[fi].ms)
-                fi = o.size() - 1;
-        }
-        if (e != hipSuccess || rc != ISING_OK)
-            break;
-        sizes.push_back(L);
-        opts.push_back(std::move(o));
-        opt_tiles.push_back(std::move(ot));
-        opt_per.push_back(std::move(op));
-        fastest.push_back(fi);
+    {
+        Tuner t(b, tune_sweeps, (hipStream_t)hip_stream);
+        if ((rc = t.start()) == ISING_OK && (rc = t.time_sizes()) == ISING_OK &&
+            (rc = t.choose_one_size()) == ISING_OK)
+            rc = t.choose_mixed();
     }
-    // The tiles for the whole launch: the estimated best, kept only if the
-    // whole batch, timed both ways, runs faster with it than with the fastest
-    // tile of every size alone.
-    auto apply = [&](const std::vector<size_t> &pick) {
-        for (size_t i = 0; i < sizes.size(); ++i) {
-            b->tiles[sizes[i]] = opt_tiles[i][pick[i]];
-            b->est_ms[sizes[i]] = plan::bundle_ms(opts[i][pick[i]], slots);
-        }
-    };
-    float ms_best = 0.f;
-    std::vector<size_t> pick;
-    if (e == hipSuccess && rc == ISING_OK) {
-        pick = plan::choose(opts, fastest, slots);
-        float ms_fast = 0.f, ms_pick = 0.f;
-        apply(fastest);
-        if (time_plan(make_plan(b, 0, Tile{1, 1}), &ms_fast, out_ref)) {
-            ms_best = ms_fast;
-            if (pick != fastest) {
-                apply(pick);
-                if (time_plan(make_plan(b, 0, Tile{1, 1}), &ms_pick, out_try)) {
-                    if (out_try != out_ref)
-                        rc = host::fail(ISING_E_HIP, "autotune: the joint tiles changed the "
-                                        "lattices");
-                    else if (ms_fast < ms_pick)
-                        pick = fastest;
-                    else
-                        ms_best = ms_pick;
-                }
-            }
-        }
-        if (e == hipSuccess && rc == ISING_OK)
-            apply(pick);
-    }
-    // Mixed-size bundles.  For each duration model, (a, b) per size and tile
-    // from the timings above; tiles per size by one of two rules -- the
-    // cheapest per lattice among the tiles whose single lattice fits the
-    // one-size plan's makespan, or the one-size plan's own tiles -- each with
-    // every size mixing, or with the sizes whose colour rows are not whole
-    // 32-bit halves (general neighbour extraction, long per-word chains) in
-    // workgroups of their own.  Each packing is timed on the whole batch; the
-    // fastest replaces the one-size plan if faster.
-    if (e == hipSuccess && rc == ISING_OK && !sizes.empty()) {
-        const double hom_est = plan::estimate(opts, pick, slots).makespan;
-        if (log)
-            std::fprintf(stderr, "[autotune] one-size plan: estimated %.4f ms, timed %.4f ms, "
-                         "%u workgroups\n", hom_est, (double)ms_best, slots);
-        const std::map<int64_t, Tile> hom_tiles = b->tiles;
-        float ms_mixed_best = 0.f;
-        std::map<int64_t, Tile> keep_tiles;
-        std::map<int64_t, plan::Kind> keep_kinds;
-        std::vector<std::vector<uint32_t>> keep_groups;
-        plan::Model keep_model = plan::kAdditive;
-        for (plan::Model model : {plan::kAdditive, plan::kRounds}) {
-            if (e != hipSuccess || rc != ISING_OK)
-                break;
-            std::vector<std::vector<plan::Kind>> fits(sizes.size());
-            std::vector<std::vector<Tile>> fit_tiles(sizes.size());
-            std::vector<std::vector<bool>> fit_two(sizes.size()); // fitted through two x
-            std::vector<double> intercepts;
-            for (int pass = 0; pass < 2; ++pass) {
-                double a_def = 0.0;
-                if (pass == 1 && !intercepts.empty()) {
-                    std::sort(intercepts.begin(), intercepts.end());
-                    a_def = intercepts[intercepts.size() / 2];
-                }
-                for (size_t i = 0; i < sizes.size(); ++i) {
-                    std::map<std::pair<uint32_t, uint32_t>,
-                             std::vector<std::pair<uint32_t, double>>>
-                        pts;
-                    for (size_t j = 0; j < opts[i].size(); ++j)
-                        pts[{opt_tiles[i][j].wpt, opt_tiles[i][j].lpw}].emplace_back(
-                            opt_per[i][j], plan::bundle_ms(opts[i][j], slots));
-                    fits[i].clear();
-                    fit_tiles[i].clear();
-                    fit_two[i].clear();
-                    for (auto &kv : pts) {
-                        const Tile t{kv.first.first, kv.first.second};
-                        const uint32_t tpl = threads_per_lattice(words_of(sizes[i]), t);
-                        plan::Kind k;
-                        plan::fit_kind(kv.second, tpl, model, a_def, &k.a, &k.b);
-                        auto x = [&](uint32_t n) {
-                            return model == plan::kRounds ? plan::simd_waves(n * tpl) : n;
-                        };
-                        bool two = false;
-                        for (auto &pt : kv.second)
-                            two = two || x(pt.first) != x(kv.second.front().first);
-                        if (pass == 0 && two)
-                            intercepts.push_back(k.a);
-                        fits[i].push_back(k);
-                        fit_tiles[i].push_back(t);
-                        fit_two[i].push_back(two);
-                    }
-                }
-            }
-            for (int rule = 0; rule < 4; ++rule) {
-                std::map<int64_t, Tile> tiles;
-                std::map<int64_t, plan::Kind> kinds;
-                for (size_t i = 0; i < sizes.size(); ++i) {
-                    auto tpl = [&](size_t jj) {
-                        return threads_per_lattice(words_of(sizes[i]), fit_tiles[i][jj]);
-                    };
-                    // per-lattice share of the compute unit, and one lattice alone
-                    auto cost = [&](size_t jj) {
-                        return model == plan::kRounds ? fits[i][jj].b * (double)tpl(jj)
-                                                      : fits[i][jj].b;
-                    };
-                    auto alone = [&](size_t jj) {
-                        return plan::group_time(model, fits[i][jj].a, fits[i][jj].b,
-                                                fits[i][jj].b, tpl(jj));
-                    };
-                    size_t c = SIZE_MAX;
-                    bool any_two = false;
-                    for (size_t j = 0; j < fits[i].size(); ++j)
-                        any_two = any_two || fit_two[i][j];
-                    for (size_t j = 0; j < fits[i].size(); ++j) {
-                        if (rule % 2 == 1) {
-                            const Tile &h = hom_tiles.at(sizes[i]);
-                            if (fit_tiles[i][j].wpt == h.wpt && fit_tiles[i][j].lpw == h.lpw)
-                                c = j;
-                        } else if ((!any_two || fit_two[i][j]) && alone(j) <= hom_est &&
-                                   (c == SIZE_MAX || cost(j) < cost(c) ||
-                                    (cost(j) == cost(c) && fits[i][j].a < fits[i][c].a))) {
-                            c = j; // (a one-x fit only guesses its split into a and b)
-                        }
-                    }
-                    if (c == SIZE_MAX)
-                        c = 0;
-                    tiles[sizes[i]] = fit_tiles[i][c];
-                    kinds[sizes[i]] = fits[i][c];
-                    kinds[sizes[i]].exclusive = rule >= 2 && (sizes[i] % 64) != 0;
-                }
-                b->tiles = tiles;
-                b->kinds = kinds;
-                b->model = model;
-                Plan p;
-                double est = 0.0;
-                std::vector<std::vector<uint32_t>> groups;
-                const bool packed = make_mixed_plan(b, slots, &p, &est, &groups);
-                if (log) {
-                    std::fprintf(stderr, "[autotune] %s model, rule %d: %s, estimated %.4f ms\n",
-                                 model == plan::kRounds ? "rounds" : "additive", rule,
-                                 packed ? "packed" : "does not pack", est);
-                    for (auto &kv : tiles)
-                        std::fprintf(stderr, "[autotune]   L=%lld tile (%u, %u) a=%.4f b=%.5f%s\n",
-                                     (long long)kv.first, kv.second.wpt, kv.second.lpw,
-                                     kinds[kv.first].a, kinds[kv.first].b,
-                                     kinds[kv.first].exclusive ? " own workgroups" : "");
-                }
-                // the models' estimates are rough: every packing is timed
-                float ms_mixed = 0.f;
-                if (packed && time_plan(p, &ms_mixed, out_try)) {
-                    if (log)
-                        std::fprintf(stderr, "[autotune]   timed %.4f ms\n", (double)ms_mixed);
-                    if (out_try != out_ref) {
-                        rc = host::fail(ISING_E_HIP, "autotune: mixed-size bundles changed the "
-                                        "lattices");
-                        break;
-                    }
-                    if (ms_mixed < ms_best && (keep_tiles.empty() || ms_mixed < ms_mixed_best)) {
-                        ms_mixed_best = ms_mixed;
-                        keep_tiles = tiles;
-                        keep_kinds = kinds;
-                        keep_model = model;
-                        keep_groups = std::move(groups);
-                    }
-                }
-                if (e != hipSuccess || rc != ISING_OK)
-                    break;
-            }
-        }
-        if (!keep_tiles.empty() && rc == ISING_OK && e == hipSuccess) {
-            b->tiles = keep_tiles;
-            b->kinds = keep_kinds;
-            b->model = keep_model;
-            b->mixed = true;
-            // Measured refinement: time every bundle of the kept packing and
-            // move one lattice at a time out of the slowest workgroup onto the
-            // least loaded one it fits.  Many workgroups end within a few per
-            // cent of each other, so a move is kept unless the whole launch
-            // gets slower (beyond 0.3 %, the timing noise): the slowest ones
-            // come down one by one.  The fastest plan seen is the result.
-            std::vector<std::vector<uint32_t>> groups = keep_groups;
-            std::vector<double> dur;
-            float cur = 0.f;
-            auto fits = [&](const std::vector<uint32_t> &g, uint32_t q) {
-                uint32_t threads = 0, lds = 0;
-                for (uint32_t x : g) {
-                    threads += mixed_threads(b->lats[x].W, b->tiles.at(b->Ls[x]));
-                    lds += batch_lds_words(b->lats[x].W);
-                }
-                threads += mixed_threads(b->lats[q].W, b->tiles.at(b->Ls[q]));
-                lds += batch_lds_words(b->lats[q].W);
-                return threads <= (uint32_t)kBatchThreads && (size_t)lds * 8 <= kMaxBundleLds;
-            };
-            bool ok_run = time_plan(plan_from_groups(b, groups), &cur, out_try, &dur) &&
-                          out_try == out_ref;
-            auto show = [&](const char *what) {
-                if (!log || dur.size() < groups.size())
-                    return;
-                std::vector<size_t> o(groups.size());
-                for (size_t i = 0; i < o.size(); ++i)
-                    o[i] = i;
-                std::stable_sort(o.begin(), o.end(), [&](size_t x, size_t y) { return dur[x] > dur[y]; });
-                for (size_t k = 0; k < o.size(); ++k) {
-                    if (k >= 8 && k + 4 < o.size())
-                        continue;
-                    std::map<int64_t, int> comp;
-                    for (uint32_t q : groups[o[k]])
-                        ++comp[b->Ls[q]];
-                    std::string c;
-                    for (auto &kv : comp)
-                        c += " " + std::to_string(kv.first) + "x" + std::to_string(kv.second);
-                    std::fprintf(stderr, "[autotune]   %s #%zu %.4f ms:%s\n", what, k, dur[o[k]],
-                                 c.c_str());
-                }
-            };
-            show("kept");
-            int moves = 0;
-            float best_ms = cur;
-            std::vector<std::vector<uint32_t>> best_groups = groups;
-            for (int it = 0; ok_run && it < 96; ++it) {
-                if (groups.size() < slots)
-                    groups.emplace_back(); // an idle workgroup is a target too
-                if (dur.size() < groups.size())
-                    dur.resize(groups.size(), 0.0);
-                std::vector<size_t> order(groups.size());
-                for (size_t i = 0; i < order.size(); ++i)
-                    order[i] = i;
-                std::stable_sort(order.begin(), order.end(),
-                                 [&](size_t x, size_t y) { return dur[x] > dur[y]; });
-                const size_t sw = order.front();
-                // one lattice of each size in the slowest workgroup, largest first
-                std::vector<uint32_t> cand;
-                for (uint32_t q : groups[sw]) {
-                    bool seen = false;
-                    for (uint32_t c : cand)
-                        seen = seen || b->Ls[c] == b->Ls[q];
-                    if (!seen)
-                        cand.push_back(q);
-                }
-                std::stable_sort(cand.begin(), cand.end(),
-                                 [&](uint32_t x, uint32_t y) { return b->Ls[x] > b->Ls[y]; });
-                bool moved = false;
-                for (uint32_t q : cand) {
-                    if (moved || !ok_run || groups[sw].size() < 2)
-                        break;
-                    // the four least loaded workgroups it fits, least first
-                    std::vector<size_t> targets;
-                    for (size_t k = order.size(); k-- > 1 && targets.size() < 4;)
-                        if (fits(groups[order[k]], q))
-                            targets.push_back(order[k]);
-                    for (size_t tw : targets) {
-                        std::vector<std::vector<uint32_t>> trial = groups;
-                        trial[sw].erase(std::find(trial[sw].begin(), trial[sw].end(), q));
-                        trial[tw].push_back(q);
-                        std::vector<std::vector<uint32_t>> nonempty;
-                        for (auto &g : trial)
-                            if (!g.empty())
-                                nonempty.push_back(g);
-                        float ms_t = 0.f;
-                        std::vector<double> dur_t;
-                        if (!time_plan(plan_from_groups(b, nonempty), &ms_t, out_try, &dur_t)) {
-                            ok_run = false;
-                            break;
-                        }
-                        if (out_try != out_ref) {
-                            rc = host::fail(ISING_E_HIP, "autotune: a refined plan changed the "
-                                            "lattices");
-                            ok_run = false;
-                            break;
-                        }
-                        if (ms_t < cur * 1.003f) {
-                            groups = std::move(nonempty);
-                            dur = std::move(dur_t);
-                            cur = ms_t;
-                            moved = true;
-                            ++moves;
-                            if (cur < best_ms) {
-                                best_ms = cur;
-                                best_groups = groups;
-                            }
-                            break;
-                        }
-                    }
-                }
-                if (!groups.empty() && groups.back().empty())
-                    groups.pop_back();
-                if (!moved)
-                    break;
-            }
-            if (log)
-                std::fprintf(stderr, "[autotune] refined by %d moves: %.4f ms (best %.4f)\n",
-                             moves, (double)cur, (double)best_ms);
-            show("refined");
-            b->groups = (rc == ISING_OK && best_ms < ms_mixed_best) ? best_groups : keep_groups;
-        } else {
-            b->tiles = hom_tiles;
-            b->kinds.clear();
-            b->model = plan::kAdditive;
-            b->mixed = false;
-        }
-    }
-    if (slot_buf)
-        (void)hipFree(slot_buf);
-    if (bundles)
-        (void)hipFree(bundles);
-    if (clk)
-        (void)hipFree(clk);
-    if (scratch)
-        (void)hipFree(scratch);
-    if (ctr)
-        (void)hipFree(ctr);
-    if (next)
-        (void)hipFree(next);
-    if (e0)
-        (void)hipEventDestroy(e0);
-    if (e1)
-        (void)hipEventDestroy(e1);
-    if (rc != ISING_OK || e != hipSuccess) {
+    if (rc != ISING_OK) {
         b->est_ms.clear();
         b->kinds.clear();
+        b->groups.clear();
         b->mixed = false;
-    }
-    if (rc != ISING_OK)
         return rc;
-    if (e != hipSuccess)
-        return host::hip_fail(e, "autotune");
+    }
     if (cache_path && !write_cache(cache_path, b))
         return host::fail(ISING_E_BADARG, "cannot write the autotune cache %s", cache_path);
     return install_current_plan(b);
