@@ -295,11 +295,14 @@ int ising_batch_set_bundles(ising_batch *b, int32_t nbundles, const int32_t *cou
  * model's workgroup duration grows least (sizes whose rows are not whole
  * 32-bit halves optionally in workgroups of their own), and the fastest of
  * these plans, each timed on the whole batch, replaces the one-size bundles
- * if it is faster (again with identical lattices).  cache_path (may be NULL) is a JSON file
- * keyed by target and kernel version: read if it covers every size, written
- * after tuning.  With ISING_AUTOTUNE_LOG set in the environment the estimates
- * and timings go to stderr.  Synchronises hip_stream; allocates scratch
- * device memory while it runs. */
+ * if it is faster (again with identical lattices); it is then refined by
+ * moving lattices out of the slowest workgroups, timed per workgroup on the
+ * device clock.  cache_path (may be NULL) is a JSON file keyed by target and
+ * kernel version: read if it covers every size, written after tuning (a
+ * mixed plan read from it is packed again from the cached models, without
+ * the measured refinement).  With ISING_AUTOTUNE_LOG set in the environment
+ * the estimates and timings go to stderr.  Synchronises hip_stream;
+ * allocates scratch device memory while it runs. */
 int ising_batch_autotune(ising_batch *b, int64_t tune_sweeps, const char *cache_path,
                          void *hip_stream);
 
