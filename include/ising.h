@@ -299,8 +299,9 @@ int ising_batch_set_bundles(ising_batch *b, int32_t nbundles, const int32_t *cou
  * moving lattices out of the slowest workgroups, timed per workgroup on the
  * device clock.  cache_path (may be NULL) is a JSON file keyed by target and
  * kernel version: read if it covers every size, written after tuning (a
- * mixed plan read from it is packed again from the cached models, without
- * the measured refinement).  With ISING_AUTOTUNE_LOG set in the environment
+ * mixed plan read from it is the tuned one if the file was written for a
+ * batch of the same sizes in the same order, else packed again from the
+ * cached models).  With ISING_AUTOTUNE_LOG set in the environment
  * the estimates and timings go to stderr.  Synchronises hip_stream;
  * allocates scratch device memory while it runs. */
 int ising_batch_autotune(ising_batch *b, int64_t tune_sweeps, const char *cache_path,

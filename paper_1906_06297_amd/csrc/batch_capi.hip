@@ -233,6 +233,28 @@ uint32_t mixed_threads(uint32_t W, Tile t) { return threads_per_lattice(W, t); }
 
 // Mixed-size bundles from the duration model of every size (b->kinds, with
 // the tiles in b->tiles) on `slots` workgroups, longest estimate first.
+// Workgroup loads that hold every lattice of b exactly once, each within a
+// workgroup's threads and LDS (a cached plan is checked before use).
+bool valid_groups(const ising_batch *b, const std::vector<std::vector<uint32_t>> &groups)
+{
+    std::vector<uint8_t> seen((size_t)b->n, 0);
+    size_t used = 0;
+    for (const auto &g : groups) {
+        uint32_t threads = 0, lds = 0;
+        for (uint32_t q : g) {
+            if (q >= (uint32_t)b->n || seen[q])
+                return false;
+            seen[q] = 1;
+            ++used;
+            threads += threads_per_lattice(b->lats[q].W, b->tiles.at(b->Ls[q]));
+            lds += batch_lds_words(b->lats[q].W);
+        }
+        if (g.empty() || threads > (uint32_t)kBatchThreads || (size_t)lds * 8 > kMaxBundleLds)
+            return false;
+    }
+    return used == (size_t)b->n;
+}
+
 // A plan of mixed bundles from workgroup loads (lattice indices), in order.
 Plan plan_from_groups(const ising_batch *b, const std::vector<std::vector<uint32_t>> &groups)
 {
@@ -574,8 +596,24 @@ struct CacheEntry {
     plan::Kind kind;
 };
 
+// The batch a cached workgroup plan belongs to: its lattice count and an
+// FNV-1a hash of the sizes in order (the plan lists lattice indices).
+std::string batch_fingerprint(const ising_batch *b)
+{
+    uint64_t h = 0xcbf29ce484222325ull;
+    for (int64_t L : b->Ls)
+        for (int k = 0; k < 8; ++k) {
+            h ^= (uint64_t)(L >> (8 * k)) & 0xFF;
+            h *= 0x100000001b3ull;
+        }
+    char buf[48];
+    std::snprintf(buf, sizeof buf, "%d:%016llx", (int)b->n, (unsigned long long)h);
+    return buf;
+}
+
 bool read_cache(const char *path, std::map<int64_t, CacheEntry> &out, bool *mixed,
-                plan::Model *model)
+                plan::Model *model, const ising_batch *b,
+                std::vector<std::vector<uint32_t>> *groups)
 {
     std::ifstream f(path);
     if (!f)
@@ -612,6 +650,34 @@ bool read_cache(const char *path, std::map<int64_t, CacheEntry> &out, bool *mixe
         e.kind.exclusive = excl != 0;
         out[(int64_t)L] = e;
     }
+    // the workgroup plan, if it was tuned for this very batch
+    groups->clear();
+    const std::string fp = "\"groups_for\": \"" + batch_fingerprint(b) + "\"";
+    size_t g = s.find("\"groups\": [");
+    if (s.find(fp) != std::string::npos && g != std::string::npos) {
+        int depth = 0;
+        std::vector<uint32_t> cur;
+        for (size_t i = s.find('[', g); i < s.size(); ++i) {
+            const char ch = s[i];
+            if (ch == '[') {
+                ++depth;
+                cur.clear();
+            } else if (ch == ']') {
+                if (depth == 2)
+                    groups->push_back(cur);
+                if (--depth == 0)
+                    break;
+            } else if (ch >= '0' && ch <= '9') {
+                uint32_t v = 0;
+                while (i < s.size() && s[i] >= '0' && s[i] <= '9')
+                    v = v * 10 + (uint32_t)(s[i++] - '0');
+                --i;
+                cur.push_back(v);
+            }
+        }
+        if (depth != 0)
+            groups->clear();
+    }
     return true;
 }
 
@@ -633,7 +699,18 @@ bool write_cache(const char *path, const ising_batch *b)
           << "]";
         first = false;
     }
-    f << "}}\n";
+    f << "}";
+    if (b->mixed && !b->groups.empty()) {
+        f << ", \"groups_for\": \"" << batch_fingerprint(b) << "\", \"groups\": [";
+        for (size_t g = 0; g < b->groups.size(); ++g) {
+            f << (g ? ", [" : "[");
+            for (size_t i = 0; i < b->groups[g].size(); ++i)
+                f << (i ? ", " : "") << b->groups[g][i];
+            f << "]";
+        }
+        f << "]";
+    }
+    f << "}\n";
     return (bool)f;
 }
 
@@ -1063,7 +1140,8 @@ class Tuner {
     // least loaded it fits.  Many workgroups end within a few per cent of
     // each other, so a move is kept unless the whole launch gets slower
     // (beyond 0.3 %, the timing noise): the slowest ones come down one by
-    // one.  `groups` and *ms end as the fastest plan seen.
+    // one.  At most 96 moves and 256 timed trials; `groups` and *ms end as
+    // the fastest plan seen.
     int refine(std::vector<std::vector<uint32_t>> &groups, float *ms)
     {
         std::vector<double> dur;
@@ -1075,8 +1153,8 @@ class Tuner {
         log_bundles("kept", groups, dur);
         std::vector<std::vector<uint32_t>> best = groups;
         float best_ms = cur;
-        int moves = 0;
-        for (int it = 0; it < 96; ++it) {
+        int moves = 0, trials = 0;
+        for (int it = 0; it < 96 && trials < 256; ++it) {
             if (groups.size() < slots_)
                 groups.emplace_back(); // an idle workgroup is a target too
             dur.resize(groups.size(), 0.0);
@@ -1106,6 +1184,8 @@ class Tuner {
                     if (fits(groups[order[k]], q))
                         targets.push_back(order[k]);
                 for (size_t tw : targets) {
+                    if (++trials > 256)
+                        break;
                     std::vector<std::vector<uint32_t>> trial = groups;
                     trial[sw].erase(std::find(trial[sw].begin(), trial[sw].end(), q));
                     trial[tw].push_back(q);
@@ -1504,7 +1584,9 @@ int ising_batch_autotune(ising_batch *b, int64_t tune_sweeps, const char *cache_
     std::map<int64_t, CacheEntry> cached;
     bool cached_mixed = false;
     plan::Model cached_model = plan::kAdditive;
-    if (cache_path && read_cache(cache_path, cached, &cached_mixed, &cached_model)) {
+    std::vector<std::vector<uint32_t>> cached_groups;
+    if (cache_path &&
+        read_cache(cache_path, cached, &cached_mixed, &cached_model, b, &cached_groups)) {
         bool complete = true;
         for (auto &kv : b->tiles)
             complete = complete && cached.count(kv.first) &&
@@ -1516,6 +1598,8 @@ int ising_batch_autotune(ising_batch *b, int64_t tune_sweeps, const char *cache_
             }
             b->mixed = cached_mixed;
             b->model = cached_model;
+            if (cached_mixed && valid_groups(b, cached_groups))
+                b->groups = std::move(cached_groups);
             return install_current_plan(b);
         }
     }
