@@ -218,18 +218,35 @@ __host__ __device__ __forceinline__ void block_uniform(State &s, uint32_t q, uin
     plane_uniform(s, x.x2, x.x3, a1, B1);
 }
 
+// Threshold masks of block q (planes 2q, 2q+1): all ones where the plane's
+// bit of T_A, T_B is set.
+struct BlockMasks {
+    uint32_t mA0, mB0, mA1, mB1;
+};
+
+__host__ __device__ __forceinline__ BlockMasks block_masks(uint32_t q, const Metro2 &m)
+{
+    const uint32_t b0 = 31 - 2 * q, b1 = 30 - 2 * q;
+    return BlockMasks{thr_mask(m.thrA, b0), thr_mask(m.thrB, b0), thr_mask(m.thrA, b1),
+                      thr_mask(m.thrB, b1)};
+}
+
+// Philox block x applied with the threshold masks of its block.
+__host__ __device__ __forceinline__ void apply_block_masks(State &s, const Block &x,
+                                                           const BlockMasks &bm)
+{
+    plane_lane(s, 0, x.x0, bm.mA0, bm.mB0);
+    plane_lane(s, 1, x.x1, bm.mA0, bm.mB0);
+    plane_lane(s, 0, x.x2, bm.mA1, bm.mB1);
+    plane_lane(s, 1, x.x3, bm.mA1, bm.mB1);
+}
+
 // Philox block x applied as block q (planes 2q, 2q+1) with per-lane
 // threshold masks.
 __host__ __device__ __forceinline__ void apply_block_lane(State &s, const Block &x, uint32_t q,
                                                           const Metro2 &m)
 {
-    const uint32_t b0 = 31 - 2 * q, b1 = 30 - 2 * q;
-    const uint32_t mA0 = thr_mask(m.thrA, b0), mB0 = thr_mask(m.thrB, b0);
-    const uint32_t mA1 = thr_mask(m.thrA, b1), mB1 = thr_mask(m.thrB, b1);
-    plane_lane(s, 0, x.x0, mA0, mB0);
-    plane_lane(s, 1, x.x1, mA0, mB0);
-    plane_lane(s, 0, x.x2, mA1, mB1);
-    plane_lane(s, 1, x.x3, mA1, mB1);
+    apply_block_masks(s, x, block_masks(q, m));
 }
 
 // Block q with per-lane q.  After block 15 (all 32 planes) a spin still
@@ -274,6 +291,27 @@ __host__ __device__ __forceinline__ void side_halves(uint64_t ce, uint32_t adj_h
     sh = left ? funnel(ch, cl, 31) : funnel(adj_half, ch, 1);
 }
 
+// start_half<true>(split_classes<Anti>(...)) with the "two or more" mask
+// never formed: 8 three-input ops per half instead of 9.  With x = the
+// pairs-level part of ge2, ge2 = x | a23, so tf = t ^ (x | a23),
+// p = ~(x | a23), and class A = (o01 | o23) & p.
+template <bool Anti>
+__host__ __device__ __forceinline__ void start_half_plain(State &s, int h, uint32_t t,
+                                                          uint32_t n0, uint32_t n1, uint32_t n2,
+                                                          uint32_t n3)
+{
+    constexpr uint32_t dB = Anti ? (~(kA ^ kB)) : (kA ^ kB);
+    constexpr uint32_t dC = Anti ? (~(kA ^ kC)) : (kA ^ kC);
+    const uint32_t o01 = lop3<tt(dB | dC)>(t, n0, n1);
+    const uint32_t a01 = lop3<tt(dB & dC)>(t, n0, n1);
+    const uint32_t o23 = lop3<tt(dB | dC)>(t, n2, n3);
+    const uint32_t a23 = lop3<tt(dB & dC)>(t, n2, n3);
+    const uint32_t x = lop3<tt(kA | (kB & kC))>(a01, o01, o23);
+    s.tf[h] = lop3<tt(kA ^ (kB | kC))>(t, x, a23);
+    s.p[h] = lop3<tt(~(kA | kB))>(x, a23, 0u);
+    s.a[h] = lop3<tt((kA | kB) & kC)>(o01, o23, s.p[h]);
+}
+
 // Start state of a word from its target word and its four neighbour vectors
 // (the side one as halves).
 template <bool Anti, bool Plain>
@@ -282,6 +320,11 @@ __host__ __device__ __forceinline__ State start_from_halves(uint64_t t, uint64_t
                                                             const ClassMasks &cm)
 {
     State s;
+    if (Plain) {
+        start_half_plain<Anti>(s, 0, lo32(t), lo32(up), lo32(dn), lo32(ce), sl);
+        start_half_plain<Anti>(s, 1, hi32(t), hi32(up), hi32(dn), hi32(ce), sh);
+        return s;
+    }
     start_half<Plain>(s, 0, lo32(t),
                       split_classes<Anti>(lo32(t), lo32(up), lo32(dn), lo32(ce), sl), cm);
     start_half<Plain>(s, 1, hi32(t),

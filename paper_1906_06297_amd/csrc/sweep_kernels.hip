@@ -117,6 +117,17 @@ struct RuleMetro {
         rows::ClassMasks cm;
     };
     __device__ static Setup setup(const Args &a) { return Setup{rows::class_masks(a.m)}; }
+    // The lock-step planes branch on threshold bits that are the same for
+    // the whole launch.  Taken as they are, the compiler hoists every
+    // plane's test out of the row loop and keeps each as a 64-bit lane mask,
+    // a dozen scalar-register pairs that then spill; passing the two words
+    // through an empty asm statement per row leaves them opaque, so each
+    // test is a scalar bit test where it is used.
+    __device__ static Args per_row(Args a)
+    {
+        asm volatile("" : "+s"(a.m.thrA), "+s"(a.m.thrB));
+        return a;
+    }
     template <bool Anti, bool Plain>
     __device__ static State start(uint64_t t, uint64_t up, uint64_t dn, uint64_t ce, uint32_t sl,
                                   uint32_t sh, const Setup &su, const Args &)
@@ -127,9 +138,25 @@ struct RuleMetro {
     {
         rows::block_uniform(s, q, chunk, a);
     }
-    __device__ static void block_lane(State &s, uint32_t q, uint32_t chunk, const Args &a)
+    // Per-lane blocks take their threshold masks from a table of the 16
+    // blocks in LDS, one 16-byte read instead of four bit extracts and the
+    // bit-index arithmetic.
+    struct LaneTable {
+        rows::BlockMasks m[16];
+    };
+    __device__ static void fill_table(LaneTable &tab, const Args &a, uint32_t tid)
     {
-        rows::block_lane(s, q, chunk, a);
+        if (tid < 16)
+            tab.m[tid] = rows::block_masks(tid, a.m);
+    }
+    __device__ static void block_lane(State &s, uint32_t q, uint32_t chunk, const Args &a,
+                                      const LaneTable &tab)
+    {
+        rows::apply_block_masks(s,
+                                rows::philox_fast<rows::kCtrLane>(
+                                    ctr_word0(a.stream_id, kDomainSweep, q), a.t_lo, a.t_hi,
+                                    chunk, a.key0, a.key1),
+                                tab.m[q]);
     }
     __device__ static uint64_t word(const State &s, int k)
     {
@@ -153,6 +180,7 @@ struct Rule5 {
     static constexpr uint32_t kRing = 2;
     struct Setup {};
     __device__ static Setup setup(const Args &) { return Setup{}; }
+    __device__ static Args per_row(const Args &a) { return a; }
     template <bool Anti, bool Plain>
     __device__ static State start(uint64_t t, uint64_t up, uint64_t dn, uint64_t ce, uint32_t sl,
                                   uint32_t sh, const Setup &, const Args &a)
@@ -163,7 +191,10 @@ struct Rule5 {
     {
         rows::block5<false>(s, q, chunk, a);
     }
-    __device__ static void block_lane(State &s, uint32_t q, uint32_t chunk, const Args &a)
+    struct LaneTable {};
+    __device__ static void fill_table(LaneTable &, const Args &, uint32_t) {}
+    __device__ static void block_lane(State &s, uint32_t q, uint32_t chunk, const Args &a,
+                                      const LaneTable &)
     {
         rows::block5<true>(s, q, chunk, a);
     }
@@ -187,10 +218,16 @@ struct Rule5 {
 
 template <int N>
 struct WaveQueue {
-    uint64_t w[N][kQueueCap];  // the rule's state words (first: flips so far, second: pending)
-    uint32_t chunk[kQueueCap]; // word index in its colour
-    uint32_t meta[kQueueCap];  // next Philox block | lane << 4 | band row << 10
+    uint64_t w[N][kQueueCap]; // the rule's state words (first: flips so far, second: pending)
+    uint64_t cm[kQueueCap];   // word index in its colour | queue_meta() << 32
 };
+
+// Queue entry metadata: next Philox block (4 bits) | the word's ring cell
+// (slot * 64 + lane, 8 bits) << 4 | band row << 12.
+__device__ __forceinline__ uint32_t queue_meta(uint32_t q, uint32_t cell, uint32_t r)
+{
+    return q | (cell << 4) | (r << 12);
+}
 
 template <uint32_t R> // rows, a power of two
 struct WaveRing {
@@ -212,8 +249,7 @@ __device__ __forceinline__ void queue_put(WaveQueue<Rule::kWords> &wq, uint32_t 
 #pragma unroll
     for (int k = 0; k < Rule::kWords; ++k)
         wq.w[k][e] = Rule::word(s, k);
-    wq.chunk[e] = chunk;
-    wq.meta[e] = meta;
+    wq.cm[e] = rows::join(chunk, meta);
 }
 
 template <class State>
@@ -236,48 +272,77 @@ __device__ __forceinline__ void ring_store(const WaveRing<R> &rg, uint32_t sl,
 // finished words go to their ring slot (or, for a row already written, to
 // memory), the rest are appended again at the tail.  A word still undecided
 // after block 15 (all 32 planes) has r == T: rejected, and final as it is.
-// Rows up to r_cur - Rule::kRing have left the ring.
-template <class Rule>
+// Rows up to r_cur - Rule::kRing have left the ring.  `Head` >= 0: the
+// queue's head is known to be Head (n = 64 passes from an empty queue leave
+// it at 0 or 64), so the entries' LDS addresses are fixed offsets.
+template <class Rule, int Head = -1>
 __device__ __forceinline__ void drain_once(WaveQueue<Rule::kWords> &wq,
                                            WaveRing<Rule::kRing> &rg,
                                            uint32_t &head, uint32_t &len, uint32_t n,
                                            uint32_t r_cur, uint64_t *__restrict__ tgt,
-                                           const typename Rule::Args &a, int lane)
+                                           const typename Rule::Args &a,
+                                           const typename Rule::LaneTable &tab, int lane)
 {
     const bool mine = (uint32_t)lane < n;
     typename Rule::State s{};
     uint32_t chunk = 0, meta = 0, q = 0;
     if (mine) {
-        const uint32_t e = (head + (uint32_t)lane) & (kQueueCap - 1);
+        const uint32_t e = Head >= 0 ? (uint32_t)Head + (uint32_t)lane
+                                     : (head + (uint32_t)lane) & (kQueueCap - 1);
 #pragma unroll
         for (int k = 0; k < Rule::kWords; ++k)
             Rule::set_word(s, k, wq.w[k][e]);
-        chunk = wq.chunk[e];
-        meta = wq.meta[e];
+        const uint64_t cm = wq.cm[e];
+        chunk = rows::lo32(cm);
+        meta = rows::hi32(cm);
         q = meta & 15u;
-        Rule::block_lane(s, q, chunk, a);
+        Rule::block_lane(s, q, chunk, a, tab);
     }
     __builtin_amdgcn_wave_barrier();
     head = (head + n) & (kQueueCap - 1);
     len -= n;
     const bool keep = mine && q < 15u && undecided(s);
     const bool fin = mine && !keep;
-    const uint32_t er = meta >> 10, el = (meta >> 4) & 63u, es = er & (Rule::kRing - 1);
-    const bool owned = er + Rule::kRing > r_cur;
+    // the word's row is still in the ring iff row >= r_cur + 1 - kRing
+    const uint32_t own_min = r_cur + 1 >= Rule::kRing ? (r_cur + 1 - Rule::kRing) << 12 : 0u;
+    const bool owned = meta >= own_min;
     if (fin) {
         const uint64_t v = rows::join(s.tf[0], s.tf[1]);
         if (owned) {
-            rg.word[es][el] = v;
-            rg.done[es][el] = 1;
+            const uint32_t cell = (meta >> 4) & 255u;
+            (&rg.word[0][0])[cell] = v;
+            (&rg.done[0][0])[cell] = 1;
         } else {
             tgt[chunk] = v;
         }
     }
-    const uint64_t bal = __ballot(keep);
+    const uint64_t bal = __builtin_amdgcn_ballot_w64(keep);
     if (keep)
         queue_put<Rule>(wq, (head + len + lanes_below(bal)) & (kQueueCap - 1), s, chunk, meta + 1);
     __builtin_amdgcn_wave_barrier();
     len += (uint32_t)__popcll(bal);
+}
+
+// A load from a wave-uniform row of nwords 64-bit words through a buffer
+// resource that the scalar unit builds from the row pointer: the per-lane
+// byte offset voff is a loop-invariant register and a wave-uniform byte
+// offset soff goes in the scalar offset, so the load takes no vector address
+// arithmetic (and it stays a vector-memory load, in flight like the others,
+// where a wave-uniform address would otherwise become a scalar load that is
+// waited for at once).  The hardware range-checks voff + soff + 8 against
+// the row's bytes; every offset used here lies inside the row.
+typedef unsigned int u32x2 __attribute__((ext_vector_type(2)));
+constexpr int kRsrcWord3 = 0x00020000; // resource word 3 on gfx9: 32-bit data format
+constexpr int kLoadNT = 2;              // cache-policy operand: non-temporal
+
+template <int Policy>
+__device__ __forceinline__ uint64_t row_load(const uint64_t *rowp, uint32_t nwords, uint32_t voff,
+                                             uint32_t soff)
+{
+    const __amdgpu_buffer_rsrc_t rs =
+        __builtin_amdgcn_make_buffer_rsrc((void *)rowp, (short)0, (int)(nwords * 8u), kRsrcWord3);
+    const u32x2 v = __builtin_amdgcn_raw_buffer_load_b64(rs, (int)voff, (int)soff, Policy);
+    return (uint64_t)v.x | ((uint64_t)v.y << 32);
 }
 
 // Edge word of the side vector of a wavefront that owns whole 64-word row
@@ -325,7 +390,12 @@ __global__ __launch_bounds__(256) void k_sweep_rows_q(uint64_t *__restrict__ tgt
     using Queue = WaveQueue<Rule::kWords>;
     __shared__ Queue queues[kWaves];
     constexpr uint32_t kRing = Rule::kRing;
+    static_assert(kRing * 64 <= 256 && Band <= 1 << 19, "queue_meta fields");
+    static_assert(kQueueCap == 128, "64-entry passes alternate the head between 0 and 64");
     __shared__ WaveRing<kRing> rings[kWaves];
+    __shared__ __align__(16) typename Rule::LaneTable lane_tab;
+    Rule::fill_table(lane_tab, a, threadIdx.x);
+    __syncthreads(); // before any wavefront can leave
     const int lane = threadIdx.x & 63;
     // wave-uniform: the row arithmetic stays on the scalar unit
     const uint32_t wv = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
@@ -347,14 +417,17 @@ __global__ __launch_bounds__(256) void k_sweep_rows_q(uint64_t *__restrict__ tgt
     const typename Rule::Setup su = Rule::setup(a);
     auto row = [&](uint32_t i) { return src + (size_t)i * Wr; }; // wave-uniform pointer
     auto side_word = [&](uint32_t i, bool left) -> uint64_t { return row(i)[left ? wl : wr]; };
-    auto edge_half = [&](uint32_t i, bool left) -> uint32_t {
-        uint32_t e = 0;
-        if (left ? edge_l : edge_r) {
-            const uint64_t v = row(i)[left ? wl : wr];
-            e = left ? rows::hi32(v) : rows::lo32(v);
-        }
-        return e;
+    // Dpp: the segment's edge words are the same for every lane of the
+    // wavefront (left of lane 0, right of lane 63), so each is one
+    // wave-uniform load
+    const uint32_t wl_edge = w0 == 0 ? Wr - 1 : w0 - 1;
+    const uint32_t wr_edge = w0 + 64 >= Wr ? 0 : w0 + 64;
+    // (the whole word is kept until the row is decided, so that the load
+    // stays in flight meanwhile)
+    auto edge_word = [&](uint32_t i, bool left) -> uint64_t {
+        return row_load<0>(row(i), Wr, 0u, (left ? wl_edge : wr_edge) * 8u);
     };
+    const uint32_t lane_off = wc * 8u; // byte offset of the lane's word in a row
     uint64_t prev = row((i0 == 0) ? L - 1 : i0 - 1)[wc];
     uint64_t cur = row(i0)[wc];
     // Glass: bond words of the target colour (right, down) and of the other
@@ -392,42 +465,41 @@ __global__ __launch_bounds__(256) void k_sweep_rows_q(uint64_t *__restrict__ tgt
     uint64_t next = __builtin_nontemporal_load(&row((i0 + 1 == L) ? 0 : i0 + 1)[wc]);
     uint64_t t = tgt[(size_t)i0 * Wr + wc];
     uint64_t adj = 0;
-    uint32_t edge = 0;
+    uint64_t edge = 0;
     if (Dpp)
-        edge = edge_half(i0, left);
+        edge = edge_word(i0, left);
     else
         adj = side_word(i0, left);
     RowBonds rb = row_bonds(i0, left);
     auto trow = [&](uint32_t i) { return tgt + (size_t)i * Wr; }; // wave-uniform pointer
-    uint32_t head = 0, len = 0, r_last = 0;
+    uint32_t head = 0, len = 0;
+    // L % 128 == 0 and Band divides 128, so every band has Band rows
+#pragma unroll 2
     for (uint32_t r = 0; r < (uint32_t)Band; ++r) {
         const uint32_t i = i0 + r;
-        if (i >= L)
-            break;
-        r_last = r;
         const uint32_t idx = i * Wr + wc;
         const uint32_t sl = r & (kRing - 1);
         if (r >= kRing) // row r - kRing leaves the ring
             ring_store(rg, sl, trow(i - kRing), wc, active, lane, true);
-        // loads of row i + 1, in flight while row i is decided
-        const bool more = r + 1 < Band && i + 1 < L;
+        // loads of row i + 1, in flight while row i is decided.  They are
+        // issued on every row, the band's last too (rows i + 1 and i + 2
+        // exist in any case, the results are then unused), so that every path
+        // through the loop has the same loads outstanding and the wait for
+        // this row's operands leaves the new ones in flight.
         const uint32_t i1 = (i + 1 == L) ? 0 : i + 1;
         const uint32_t i2 = (i1 + 1 == L) ? 0 : i1 + 1;
         const bool left1 = !left;
-        uint64_t next1 = 0, t1 = 0, adj1 = 0;
-        uint32_t edge1 = 0;
-        RowBonds rb1{};
-        if (more) {
-            next1 = __builtin_nontemporal_load(&row(i2)[wc]);
-            t1 = tgt[(size_t)i1 * Wr + wc];
-            if (Dpp)
-                edge1 = edge_half(i1, left1);
-            else
-                adj1 = side_word(i1, left1);
-            rb1 = row_bonds(i1, left1);
-        }
+        uint64_t adj1 = 0, edge1 = 0;
+        const uint64_t next1 = row_load<kLoadNT>(row(i2), Wr, lane_off, 0u);
+        const uint64_t t1 = row_load<0>(trow(i1), Wr, lane_off, 0u);
+        if (Dpp)
+            edge1 = edge_word(i1, left1);
+        else
+            adj1 = side_word(i1, left1);
+        const RowBonds rb1 = row_bonds(i1, left1);
         const uint32_t adj_half =
-            Dpp ? side_half_dpp(rows::lo32(cur), rows::hi32(cur), edge, left)
+            Dpp ? side_half_dpp(rows::lo32(cur), rows::hi32(cur),
+                                left ? rows::hi32(edge) : rows::lo32(edge), left)
                 : (left ? rows::hi32(adj) : rows::lo32(adj));
         uint32_t shl, shh;
         rows::side_halves(cur, adj_half, left, shl, shh);
@@ -454,23 +526,29 @@ __global__ __launch_bounds__(256) void k_sweep_rows_q(uint64_t *__restrict__ tgt
         // (a block applied to a decided word changes nothing; with both
         // classes random a whole wavefront is practically never decided
         // early, so only the other cases test for it)
+        // (the threshold words are re-read per row, see Rule::per_row)
+        const typename Rule::Args ar = Rule::per_row(a);
 #pragma unroll
         for (uint32_t q = 0; q < kStreamBlocks; ++q) {
             if (!Plain && __ballot(active && undecided(s)) == 0)
                 break;
-            Rule::block(s, q, idx, a);
+            Rule::block(s, q, idx, ar);
         }
         const bool push = active && undecided(s);
         rg.word[sl][lane] = rows::join(s.tf[0], s.tf[1]);
         rg.done[sl][lane] = push ? 0 : 1;
-        const uint64_t bal = __ballot(push);
+        const uint64_t bal = __builtin_amdgcn_ballot_w64(push);
         if (push)
             queue_put<Rule>(wq, (head + len + lanes_below(bal)) & (kQueueCap - 1), s, idx,
-                            kStreamBlocks | ((uint32_t)lane << 4) | (r << 10));
+                            queue_meta(kStreamBlocks, sl * 64 + (uint32_t)lane, r));
         __builtin_amdgcn_wave_barrier();
         len += (uint32_t)__popcll(bal);
-        while (len >= 64)
-            drain_once<Rule>(wq, rg, head, len, 64, r, tgt, a, lane);
+        while (len >= 64) {
+            if (head == 0)
+                drain_once<Rule, 0>(wq, rg, head, len, 64, r, tgt, a, lane_tab, lane);
+            else
+                drain_once<Rule, 64>(wq, rg, head, len, 64, r, tgt, a, lane_tab, lane);
+        }
         prev = cur;
         cur = next;
         next = next1;
@@ -484,10 +562,12 @@ __global__ __launch_bounds__(256) void k_sweep_rows_q(uint64_t *__restrict__ tgt
         }
     }
     while (len > 0)
-        drain_once<Rule>(wq, rg, head, len, len < 64 ? len : 64, r_last, tgt, a, lane);
+        drain_once<Rule>(wq, rg, head, len, len < 64 ? len : 64, Band - 1, tgt, a, lane_tab,
+                         lane);
     // the last rows, all words final
-    const uint32_t nrows = r_last + 1;
-    for (uint32_t r = nrows > kRing ? nrows - kRing : 0; r < nrows; ++r)
+    static_assert(Band >= (int)kRing && 128 % Band == 0, "whole bands of at least kRing rows");
+#pragma unroll
+    for (uint32_t r = Band - kRing; r < (uint32_t)Band; ++r)
         ring_store(rg, r & (kRing - 1), trow(i0 + r), wc, active, lane, false);
 }
 
@@ -705,9 +785,11 @@ hipError_t launch_rows_queue(uint64_t *tgt, const uint64_t *src, const uint64_t 
                              int64_t L, int c, const Metro2 &m, const SweepArgs2 &a, hipStream_t s,
                              int band)
 {
+    if (L % 128 != 0 || (band != 8 && band != 16 && band != 32))
+        return hipErrorInvalidValue; // the kernel assumes whole bands of whole 64-word rows
     const int64_t Wr = L / 128;
     const int64_t wpb = (Wr + 63) / 64;
-    const int64_t nbands = (L + band - 1) / band;
+    const int64_t nbands = L / band;
     const int64_t waves = wpb * nbands;
     const dim3 grid((uint32_t)((waves + kWaves - 1) / kWaves)), block(64 * kWaves);
     const bool plain = m.randA && m.randB && !m.alwaysA && !m.alwaysB;
