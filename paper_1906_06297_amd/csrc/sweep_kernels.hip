@@ -473,8 +473,10 @@ __global__ __launch_bounds__(256) void k_sweep_rows_q(uint64_t *__restrict__ tgt
     RowBonds rb = row_bonds(i0, left);
     auto trow = [&](uint32_t i) { return tgt + (size_t)i * Wr; }; // wave-uniform pointer
     uint32_t head = 0, len = 0;
-    // L % 128 == 0 and Band divides 128, so every band has Band rows
-#pragma unroll 2
+    // L % 128 == 0 and Band divides 128, so every band has Band rows; the
+    // loop is unrolled by four (a multiple of the ring depth), so ring slots
+    // are constants and the row registers rotate without copies
+#pragma unroll 4
     for (uint32_t r = 0; r < (uint32_t)Band; ++r) {
         const uint32_t i = i0 + r;
         const uint32_t idx = i * Wr + wc;
@@ -565,7 +567,8 @@ __global__ __launch_bounds__(256) void k_sweep_rows_q(uint64_t *__restrict__ tgt
         drain_once<Rule>(wq, rg, head, len, len < 64 ? len : 64, Band - 1, tgt, a, lane_tab,
                          lane);
     // the last rows, all words final
-    static_assert(Band >= (int)kRing && 128 % Band == 0, "whole bands of at least kRing rows");
+    static_assert(Band >= (int)kRing && Band % 4 == 0 && 128 % Band == 0,
+                  "whole bands of at least kRing rows");
 #pragma unroll
     for (uint32_t r = Band - kRing; r < (uint32_t)Band; ++r)
         ring_store(rg, r & (kRing - 1), trow(i0 + r), wc, active, lane, false);
