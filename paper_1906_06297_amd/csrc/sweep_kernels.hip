@@ -484,12 +484,13 @@ __global__ __launch_bounds__(256) void k_sweep_rows_q(uint64_t *__restrict__ tgt
         if (r >= kRing) // row r - kRing leaves the ring
             ring_store(rg, sl, trow(i - kRing), wc, active, lane, true);
         // loads of row i + 1, in flight while row i is decided.  They are
-        // issued on every row, the band's last too (rows i + 1 and i + 2
-        // exist in any case, the results are then unused), so that every path
-        // through the loop has the same loads outstanding and the wait for
-        // this row's operands leaves the new ones in flight.
-        const uint32_t i1 = (i + 1 == L) ? 0 : i + 1;
-        const uint32_t i2 = (i1 + 1 == L) ? 0 : i1 + 1;
+        // issued on every row, so that every path through the loop has the
+        // same loads outstanding and the wait for this row's operands leaves
+        // the new ones in flight; on the band's last row they re-read row i
+        // (lines just read, so no new HBM traffic) and the results are unused.
+        const bool more = r + 1 < (uint32_t)Band;
+        const uint32_t i1 = !more ? i : ((i + 1 == L) ? 0 : i + 1);
+        const uint32_t i2 = !more ? i : ((i1 + 1 == L) ? 0 : i1 + 1);
         const bool left1 = !left;
         uint64_t adj1 = 0, edge1 = 0;
         const uint64_t next1 = row_load<kLoadNT>(row(i2), Wr, lane_off, 0u);
