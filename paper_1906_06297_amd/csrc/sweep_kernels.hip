@@ -411,8 +411,8 @@ __global__ __launch_bounds__(256) void k_sweep_rows_q(uint64_t *__restrict__ tgt
     const uint32_t wc = active ? w : Wr - 1;
     const uint32_t wl = (wc == 0) ? Wr - 1 : wc - 1;
     const uint32_t wr = (wc + 1 >= Wr) ? 0 : wc + 1;
-    // Dpp: the one word each edge lane reads
-    const bool edge_l = lane == 0, edge_r = lane == 63;
+    // Dpp (glass bonds): the one word the left edge lane reads
+    const bool edge_l = lane == 0;
     const uint32_t i0 = band * Band;
     const typename Rule::Setup su = Rule::setup(a);
     auto row = [&](uint32_t i) { return src + (size_t)i * Wr; }; // wave-uniform pointer
@@ -499,7 +499,9 @@ __global__ __launch_bounds__(256) void k_sweep_rows_q(uint64_t *__restrict__ tgt
             edge1 = edge_word(i1, left1);
         else
             adj1 = side_word(i1, left1);
-        const RowBonds rb1 = row_bonds(i1, left1);
+        // (the glass's bond words are read non-temporally and are gone from
+        // L2 by then: the last row skips them rather than fetch them again)
+        const RowBonds rb1 = (Glass && !more) ? RowBonds{} : row_bonds(i1, left1);
         const uint32_t adj_half =
             Dpp ? side_half_dpp(rows::lo32(cur), rows::hi32(cur),
                                 left ? rows::hi32(edge) : rows::lo32(edge), left)
