@@ -369,9 +369,22 @@ int ising_arnet_set_params(ising_arnet *net, const float *d_params, void *hip_st
 int ising_arnet_get_params(const ising_arnet *net, float *d_params, void *hip_stream);
 
 /* log q~ of B configurations into d_logq[B]; d_logits[B][L*L] may be NULL.
- * Asynchronous. */
+ * Asynchronous.  Where two L*L x C bf16 activation buffers, the logits and
+ * the spins fit one workgroup's LDS (L = 32 at C = 32 on gfx950), one kernel
+ * evaluates each configuration with all layers on chip; otherwise one launch
+ * per layer moves the activations through the workspace.  Both give the same
+ * values bit for bit (the per-element MFMA sequence of the sampler, so the
+ * log q~ of a sampled configuration equals what the sampler reported). */
 int ising_arnet_log_prob(ising_arnet *net, const int8_t *d_spins, int32_t B, float *d_logq,
                          float *d_logits, void *hip_stream);
+
+/* Evaluation path of ising_arnet_log_prob: ISING_ARNET_EVAL_AUTO (the
+ * on-chip kernel where it fits, the default) or ISING_ARNET_EVAL_LAYERS (one
+ * launch per layer always; for comparing the two).  ISING_E_BADARG for any
+ * other value. */
+#define ISING_ARNET_EVAL_AUTO 0
+#define ISING_ARNET_EVAL_LAYERS 1
+int ising_arnet_set_eval_mode(ising_arnet *net, int32_t mode);
 
 /* Mean negative log-likelihood -1/B sum_b sum_p log sigmoid(x_bp logit_bp)
  * into d_loss[0] and its gradient into d_grad (may be NULL).  Asynchronous. */

@@ -99,6 +99,7 @@ SIGNATURES = {
     "ising_arnet_set_params": (ctypes.c_int, [_vp, _vp, _vp]),
     "ising_arnet_get_params": (ctypes.c_int, [_vp, _vp, _vp]),
     "ising_arnet_log_prob": (ctypes.c_int, [_vp, _vp, ctypes.c_int32, _vp, _vp, _vp]),
+    "ising_arnet_set_eval_mode": (ctypes.c_int, [_vp, ctypes.c_int32]),
     "ising_arnet_gradient": (ctypes.c_int, [_vp, _vp, ctypes.c_int32, _vp, _vp, _vp]),
     "ising_arnet_train_step": (ctypes.c_int, [_vp, _vp, ctypes.c_int32, ctypes.c_float, _vp, _vp]),
     "ising_arnet_adam": (ctypes.c_int, [_vp, _vp, ctypes.c_float, _vp]),

@@ -21,6 +21,7 @@ struct ising_arnet {
     float *partial = nullptr;                   // kGradBlocks x (parameters + 1)
     float *logits = nullptr, *dlogit = nullptr, *grad = nullptr, *m = nullptr, *v = nullptr;
     int64_t step = 0;
+    int eval_mode = ISING_ARNET_EVAL_AUTO;
 };
 
 namespace {
@@ -195,11 +196,27 @@ int ising_arnet_log_prob(ising_arnet *a, const int8_t *d_spins, int32_t B, float
     if (!d_spins || !d_logq)
         return host::fail(ISING_E_BADARG, "null pointer");
     hipStream_t s = (hipStream_t)hip_stream;
-    hipError_t e = launch_forward(a->net, d_spins, B, a->h, a->logits, d_logq, s);
-    if (e == hipSuccess && d_logits)
-        e = hipMemcpyAsync(d_logits, a->logits, (size_t)B * a->net.N * 4, hipMemcpyDeviceToDevice, s);
+    hipError_t e;
+    if (a->eval_mode == ISING_ARNET_EVAL_AUTO && eval_supported(a->net.L, a->net.C)) {
+        e = launch_eval(a->net, d_spins, B, d_logits, d_logq, s);
+    } else {
+        e = launch_forward(a->net, d_spins, B, a->h, a->logits, d_logq, s);
+        if (e == hipSuccess && d_logits)
+            e = hipMemcpyAsync(d_logits, a->logits, (size_t)B * a->net.N * 4,
+                               hipMemcpyDeviceToDevice, s);
+    }
     if (e != hipSuccess)
         return host::hip_fail(e, "log-probability");
+    return host::ok();
+}
+
+int ising_arnet_set_eval_mode(ising_arnet *a, int32_t mode)
+{
+    if (int e = check_net(a))
+        return e;
+    if (mode != ISING_ARNET_EVAL_AUTO && mode != ISING_ARNET_EVAL_LAYERS)
+        return host::fail(ISING_E_BADARG, "evaluation mode %d", (int)mode);
+    a->eval_mode = mode;
     return host::ok();
 }
 

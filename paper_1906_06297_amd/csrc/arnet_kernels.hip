@@ -382,6 +382,193 @@ __global__ __launch_bounds__(256) void k_logq(const int8_t *__restrict__ x,
         logq[b] = (float)lq;
 }
 
+// ------------------------------------------------------- fused evaluator
+// log q~ of whole configurations, one workgroup per configuration with every
+// layer's activations in LDS (two [N][C] bf16 buffers, the logits and the
+// spins): the seven launches of the evaluator above move each layer's
+// activations through HBM, this one reads the spins and writes log q~ (and
+// the logits if asked).  The per-element arithmetic is the evaluator's:
+// layer 1 by l1_from(), layers 2..6 by conv_mfma() over 16-site tiles with the
+// same operands (the weights loaded once per layer into registers from the
+// same packed arrays), the epilogues' bias, ReLU and bf16 rounding, and
+// config_logq() on the logits -- so its results equal the evaluator's, and
+// the sampler's, bit for bit.
+
+// Tile rows within one configuration: sites p0 .. p0 + 15 (valid below N).
+struct CfgRows {
+    int p0, N;
+    __device__ void operator()(int r, int64_t &b, int &p) const
+    {
+        p = p0 + r;
+        b = p < N ? 0 : -1;
+        if (b < 0)
+            p = 0;
+    }
+};
+
+// A operand of tap t from the configuration's activations in LDS.
+template <int C>
+__device__ __forceinline__ void load_tap_lds(bf16x8 (&at)[C / 32], const bf16 *act, bool valid,
+                                             int L, int ii, int jj, int kq)
+{
+    const bool ok = valid && ii >= 0 && ii < L && jj >= 0 && jj < L;
+#pragma unroll
+    for (int kc = 0; kc < C / 32; ++kc) {
+        if (ok)
+            at[kc] = *(const bf16x8 *)(act + (ii * L + jj) * C + kc * 32 + kq * 8);
+        else
+            zero8(at[kc]);
+    }
+}
+
+struct EpiForwardLds { // as EpiForward, into the LDS buffer of the next layer
+    bf16 *out;
+    const float *bias;
+    int C;
+    __device__ void operator()(int, int64_t, int p, int col, float v) const
+    {
+        out[p * C + col] = (bf16)fmaxf(v + bias[col], 0.f);
+    }
+};
+
+struct EpiLogitLds { // as EpiLogit, into the LDS logits
+    float *z;
+    float b6;
+    __device__ void operator()(int, int64_t, int p, int col, float v) const
+    {
+        if (col == 0)
+            z[p] = v + b6;
+    }
+};
+
+__host__ __device__ inline size_t eval_lds_bytes(int N, int C)
+{
+    return 2 * (size_t)N * C * sizeof(bf16) + (size_t)N * sizeof(float) + (((size_t)N + 15) / 16) * 16;
+}
+
+// One configuration's evaluation by the workgroup: spins xs (staged in LDS),
+// activations act[0], act[1], logits z; layer weights from `wl(l)`.
+template <int C, int W, class WL>
+__device__ __forceinline__ void eval_config(const NetDev &net, const int8_t *xs, bf16 *const (&act)[2],
+                                            float *z, const WL &wl)
+{
+    const int N = net.N, L = net.L;
+    const int tid = threadIdx.x, wv = tid >> 6, lane = tid & 63, r = lane & 15, kq = lane >> 4;
+    const ParamLayout pl = param_layout(C);
+    // layer 1: one thread per (site, 8 output channels)
+    const float *b1 = net.params + pl.b1;
+    for (int g = tid; g < N * (C / 8); g += 64 * W) {
+        const int p = g / (C / 8), c0 = (g - p * (C / 8)) * 8;
+        const int i = p / L, j = p - (p / L) * L;
+        float xv[4];
+#pragma unroll
+        for (int t = 0; t < 4; ++t) {
+            const int ii = i + tap_dy(t), jj = j + tap_dx(t);
+            xv[t] = (ii >= 0 && jj >= 0 && jj < L) ? (float)xs[ii * L + jj] : 0.f;
+        }
+        bf16x8 o;
+#pragma unroll
+        for (int e = 0; e < 8; ++e)
+            o[e] = (bf16)l1_from(xv, net.w1, b1, C, c0 + e);
+        *(bf16x8 *)(act[0] + p * C + c0) = o;
+    }
+    __syncthreads();
+    const int tiles = (N + 15) / 16;
+    // layers 2..5: act[(l - 2) & 1] -> act[(l - 1) & 1]
+#pragma unroll
+    for (int l = 2; l <= 5; ++l) {
+        const bf16 *in = act[(l - 2) & 1];
+        const EpiForwardLds epi{act[(l - 1) & 1], net.params + pl.b[l], C};
+        const auto &w = wl(l);
+        for (int tile = wv; tile < tiles; tile += W) {
+            const CfgRows rows{tile * 16, N};
+            int64_t bb;
+            int p;
+            rows(r, bb, p);
+            const int i = p / L, j = p - (p / L) * L;
+            bf16x8 a[5][C / 32];
+#pragma unroll
+            for (int t = 0; t < 5; ++t)
+                load_tap_lds<C>(a[t], in, bb >= 0, L, i + tap_dy(t), j + tap_dx(t), kq);
+            conv_mfma<C, C>(a, w, rows, epi);
+        }
+        __syncthreads();
+    }
+    // layer 6 from act[0] (layer 5's output)
+    const EpiLogitLds epi6{z, net.params[pl.b6]};
+    WeightsRegs<C, 16> w6;
+    w6.load(net.w6p);
+    for (int tile = wv; tile < tiles; tile += W) {
+        const CfgRows rows{tile * 16, N};
+        int64_t bb;
+        int p;
+        rows(r, bb, p);
+        const int i = p / L, j = p - (p / L) * L;
+        bf16x8 a[5][C / 32];
+#pragma unroll
+        for (int t = 0; t < 5; ++t)
+            load_tap_lds<C>(a[t], act[0], bb >= 0, L, i + tap_dy(t), j + tap_dx(t), kq);
+        conv_mfma<C, 16>(a, w6, rows, epi6);
+    }
+    __syncthreads();
+}
+
+// Weights of layers 2..5 held in registers for the whole launch (C = 32:
+// 160 of them per lane) ...
+template <int C>
+struct HeldWeights {
+    WeightsRegs<C, C> w[4];
+    __device__ void load(const NetDev &net)
+    {
+#pragma unroll
+        for (int l = 2; l <= 5; ++l)
+            w[l - 2].load(net.wf[l]);
+    }
+    __device__ const WeightsRegs<C, C> &operator()(int l) const { return w[l - 2]; }
+};
+
+// ... or read from the packed arrays at each use (C = 64).
+template <int C>
+struct GlobalWeights {
+    const NetDev *net;
+    __device__ WeightsGlobal<C> operator()(int l) const { return WeightsGlobal<C>{net->wf[l]}; }
+};
+
+// Persistent: workgroup g evaluates configurations g, g + grid, ...
+template <int C, int W>
+__global__ __launch_bounds__(64 * W) void k_eval(NetDev net, const int8_t *__restrict__ x, int B,
+                                                 float *__restrict__ logits, float *__restrict__ logq)
+{
+    extern __shared__ __align__(16) unsigned char eval_lds[];
+    const int N = net.N;
+    bf16 *const act[2] = {(bf16 *)eval_lds, (bf16 *)eval_lds + (size_t)N * C};
+    float *z = (float *)(act[1] + (size_t)N * C);
+    int8_t *xs = (int8_t *)(z + N);
+    const int tid = threadIdx.x, wv = tid >> 6, lane = tid & 63;
+    constexpr bool kHold = C == 32;
+    HeldWeights<C> held;
+    if (kHold)
+        held.load(net);
+    for (int64_t b = blockIdx.x; b < B; b += gridDim.x) {
+        for (int p = tid; p < N; p += 64 * W)
+            xs[p] = x[b * N + p];
+        __syncthreads();
+        if (kHold)
+            eval_config<C, W>(net, xs, act, z, held);
+        else
+            eval_config<C, W>(net, xs, act, z, GlobalWeights<C>{&net});
+        if (logits)
+            for (int p = tid; p < N; p += 64 * W)
+                logits[b * N + p] = z[p];
+        if (wv == 0) {
+            const double lq = config_logq(z, xs, N);
+            if (lane == 0)
+                logq[b] = (float)lq;
+        }
+        __syncthreads(); // z and xs are rewritten by the next configuration
+    }
+}
+
 // --------------------------------------------------------------- sampling
 // Ancestral sampling along anti-diagonals.  Through the masks, every layer's
 // output at site (i, j) depends only on sites (i-1, j-1..j+1) and (i, j-1) of
@@ -1205,6 +1392,53 @@ hipError_t launch_forward(const NetDev &net, const int8_t *x, int B, bf16 *const
     if (logq)
         hipLaunchKernelGGL(k_logq, dim3(nblocks(B, 4)), dim3(256), 0, s, x, logits, net.N, B, logq);
     return hipGetLastError();
+}
+
+// Evaluator waves per workgroup (one workgroup per configuration).
+constexpr int kEvalWaves = 8;
+
+bool eval_supported(int L, int C)
+{
+    return (C == 32 || C == 64) && eval_lds_bytes(L * L, C) <= lds_limit();
+}
+
+template <int C>
+static hipError_t launch_eval_c(const NetDev &net, const int8_t *x, int B, float *logits,
+                                float *logq, size_t lds, hipStream_t s)
+{
+    static size_t allowed = 0; // dynamic LDS granted to this instance so far
+    if (lds > allowed) {
+        const hipError_t e = hipFuncSetAttribute((const void *)k_eval<C, kEvalWaves>,
+                                                 hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+        if (e != hipSuccess) {
+            (void)hipGetLastError(); // leave no sticky error behind for later calls
+            return e;
+        }
+        allowed = lds;
+    }
+    static int ncu = 0;
+    if (!ncu) {
+        int dev = 0;
+        if (hipGetDevice(&dev) != hipSuccess ||
+            hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess ||
+            ncu <= 0)
+            ncu = 256;
+    }
+    // one resident workgroup per compute unit (the LDS of one configuration)
+    const int grid = B < ncu ? B : ncu;
+    hipLaunchKernelGGL((k_eval<C, kEvalWaves>), dim3(grid), dim3(64 * kEvalWaves), lds, s, net, x, B,
+                       logits, logq);
+    return hipGetLastError();
+}
+
+hipError_t launch_eval(const NetDev &net, const int8_t *x, int B, float *logits, float *logq,
+                       hipStream_t s)
+{
+    if (!eval_supported(net.L, net.C) || !logq)
+        return hipErrorInvalidValue;
+    const size_t lds = eval_lds_bytes(net.N, net.C);
+    return net.C == 32 ? launch_eval_c<32>(net, x, B, logits, logq, lds, s)
+                       : launch_eval_c<64>(net, x, B, logits, logq, lds, s);
 }
 
 size_t lds_limit()

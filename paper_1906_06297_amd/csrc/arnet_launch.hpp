@@ -8,6 +8,14 @@
 namespace ising {
 namespace arnet {
 
+// log q~ (and the logits if `logits` is not null) of B configurations with
+// every layer's activations in LDS, one workgroup per configuration; only
+// where eval_supported() (two [L*L][C] bf16 buffers, the logits and the spins
+// fit one workgroup's LDS).  Same results as launch_forward(), bit for bit.
+bool eval_supported(int L, int C);
+hipError_t launch_eval(const NetDev &net, const int8_t *x, int B, float *logits, float *logq,
+                       hipStream_t s);
+
 // Largest lattice the sampler takes: its longest anti-diagonal (ceil(L/2)
 // sites) must fit four 16-row tiles.
 constexpr int kSamplerMaxL = 128;

@@ -418,6 +418,13 @@ class ARNet:
         assert spins.numel() % (self.L * self.L) == 0
         return spins.numel() // (self.L * self.L)
 
+    EVAL_MODES = {"auto": 0, "layers": 1}  # ISING_ARNET_EVAL_*
+
+    def set_eval_mode(self, mode: str) -> None:
+        """'auto': the on-chip evaluator where its LDS fits (the default);
+        'layers': one launch per layer always."""
+        _lib.check(_lib.load().ising_arnet_set_eval_mode(self._h, self.EVAL_MODES[mode]))
+
     def log_prob(self, spins, logits=False, stream=None, out=None):
         B = self._check_spins(spins)
         logq = torch.empty(B, dtype=torch.float32, device=self.device) if out is None else out

@@ -276,6 +276,42 @@ def test_sampler_matches_evaluator_and_uniforms(gpu, C, L, B):
     net.close()
 
 
+@pytest.mark.parametrize("C,L,B", [(32, 2, 5), (32, 3, 7), (64, 6, 37), (32, 8, 37),
+                                   (64, 16, 40), (32, 16, 100), (32, 32, 4096), (64, 64, 64)])
+def test_on_chip_evaluator_equals_layer_kernels(gpu, C, L, B):
+    """log q~ and the logits of the on-chip evaluator (one workgroup per
+    configuration, activations in LDS) equal those of the one-launch-per-layer
+    path bit for bit, partial last tiles (L*L not a multiple of 16) included;
+    at L = 64, C = 64 the activations do not fit and both modes take the layer
+    kernels."""
+    say(f"evaluators C={C} L={L} B={B}")
+    th = bf16_params(C, 60 + L, scale=1.0)
+    x = spins_t(mixed_configs(B, L, 900 + L))
+    net = gpu.ARNet(L, C, B)
+    net.set_params(th.astype(np.float32))
+    q_auto, z_auto = net.log_prob(x, logits=True)
+    q_only = net.log_prob(x)
+    net.set_eval_mode("layers")
+    q_lay, z_lay = net.log_prob(x, logits=True)
+    net.set_eval_mode("auto")
+    q_auto2 = net.log_prob(x)
+    a, b = q_auto.cpu().numpy(), q_lay.cpu().numpy()
+    assert not np.any(np.isnan(a)) and np.mean(np.isfinite(a)) > 0.5
+    assert np.array_equal(a, b), np.flatnonzero(a != b)[:5]
+    assert np.array_equal(z_auto.cpu().numpy(), z_lay.cpu().numpy())
+    assert np.array_equal(q_only.cpu().numpy(), a) and np.array_equal(q_auto2.cpu().numpy(), a)
+    net.close()
+
+
+def test_eval_mode_rejects_unknown_values(gpu):
+    lib = gpu._lib.load()
+    net = gpu.ARNet(4, 32, 1)
+    assert lib.ising_arnet_set_eval_mode(net._h, 2) != 0
+    assert lib.ising_arnet_set_eval_mode(net._h, -1) != 0
+    assert lib.ising_arnet_set_eval_mode(net._h, 1) == 0
+    net.close()
+
+
 def test_sampler_rejects_lattices_beyond_its_lds(gpu):
     import torch
 
