@@ -92,16 +92,28 @@ __device__ __forceinline__ double site_logq(float Pq, int xv)
 // lane l adds the sites p = l, l + 64, ... in increasing order, then the 64
 // lane sums are combined by a butterfly (offsets 32, 16, .., 1).  Evaluator
 // and sampler both use it, so their results agree bit for bit.
-__device__ __forceinline__ double config_logq(const float *z, const int8_t *x, int N)
+// The summation of config_logq() over terms given by term(p).
+template <class Term>
+__device__ __forceinline__ double wave_ordered_sum(int N, const Term &term)
 {
     const int lane = threadIdx.x & 63;
     double acc = 0.0;
     for (int p = lane; p < N; p += 64)
-        acc += site_logq(quantise(prob_plus(z[p])), x[p]);
+        acc += term(p);
 #pragma unroll
     for (int off = 32; off > 0; off >>= 1)
         acc += __shfl_xor(acc, off, 64);
     return acc;
+}
+
+__device__ __forceinline__ double site_term(const float *z, const int8_t *x, int p)
+{
+    return site_logq(quantise(prob_plus(z[p])), x[p]);
+}
+
+__device__ __forceinline__ double config_logq(const float *z, const int8_t *x, int N)
+{
+    return wave_ordered_sum(N, [&](int p) { return site_term(z, x, p); });
 }
 
 // ------------------------------------------------------------- MFMA tile
@@ -421,13 +433,15 @@ __device__ __forceinline__ void load_tap_lds(bf16x8 (&at)[C / 32], const bf16 *a
     }
 }
 
-struct EpiForwardLds { // as EpiForward, into the LDS buffer of the next layer
+// As EpiForward, into the LDS buffer of the next layer, with the lane's
+// biases in registers (a lane's output columns are n0 + (lane & 15)).
+template <int C>
+struct EpiForwardLds {
     bf16 *out;
-    const float *bias;
-    int C;
+    float bias[C / 16]; // bias[col >> 4] of this lane's column col
     __device__ void operator()(int, int64_t, int p, int col, float v) const
     {
-        out[p * C + col] = (bf16)fmaxf(v + bias[col], 0.f);
+        out[p * C + col] = (bf16)fmaxf(v + bias[col >> 4], 0.f);
     }
 };
 
@@ -441,9 +455,17 @@ struct EpiLogitLds { // as EpiLogit, into the LDS logits
     }
 };
 
+// LDS of one configuration: two [N][C] bf16 activation buffers, the logits
+// (float), the spins (padded to 16 bytes) and the per-site log q terms
+// (double).
+__host__ __device__ inline size_t eval_terms_offset(int N, int C)
+{
+    return ((2 * (size_t)N * C * sizeof(bf16) + (size_t)N * sizeof(float) + (size_t)N + 15) / 16) * 16;
+}
+
 __host__ __device__ inline size_t eval_lds_bytes(int N, int C)
 {
-    return 2 * (size_t)N * C * sizeof(bf16) + (size_t)N * sizeof(float) + (((size_t)N + 15) / 16) * 16;
+    return eval_terms_offset(N, C) + (size_t)N * sizeof(double);
 }
 
 // One configuration's evaluation by the workgroup: spins xs (staged in LDS),
@@ -478,7 +500,11 @@ __device__ __forceinline__ void eval_config(const NetDev &net, const int8_t *xs,
 #pragma unroll
     for (int l = 2; l <= 5; ++l) {
         const bf16 *in = act[(l - 2) & 1];
-        const EpiForwardLds epi{act[(l - 1) & 1], net.params + pl.b[l], C};
+        EpiForwardLds<C> epi;
+        epi.out = act[(l - 1) & 1];
+#pragma unroll
+        for (int k = 0; k < C / 16; ++k)
+            epi.bias[k] = net.params[pl.b[l] + 16 * k + r];
         const auto &w = wl(l);
         for (int tile = wv; tile < tiles; tile += W) {
             const CfgRows rows{tile * 16, N};
@@ -544,6 +570,7 @@ __global__ __launch_bounds__(64 * W) void k_eval(NetDev net, const int8_t *__res
     bf16 *const act[2] = {(bf16 *)eval_lds, (bf16 *)eval_lds + (size_t)N * C};
     float *z = (float *)(act[1] + (size_t)N * C);
     int8_t *xs = (int8_t *)(z + N);
+    double *terms = (double *)(eval_lds + eval_terms_offset(N, C));
     const int tid = threadIdx.x, wv = tid >> 6, lane = tid & 63;
     constexpr bool kHold = C == 32;
     HeldWeights<C> held;
@@ -557,15 +584,20 @@ __global__ __launch_bounds__(64 * W) void k_eval(NetDev net, const int8_t *__res
             eval_config<C, W>(net, xs, act, z, held);
         else
             eval_config<C, W>(net, xs, act, z, GlobalWeights<C>{&net});
-        if (logits)
-            for (int p = tid; p < N; p += 64 * W)
+        // log q~: the per-site terms of config_logq() by every wavefront, then
+        // its summation, in its order, by one
+        for (int p = tid; p < N; p += 64 * W) {
+            terms[p] = site_term(z, xs, p);
+            if (logits)
                 logits[b * N + p] = z[p];
+        }
+        __syncthreads();
         if (wv == 0) {
-            const double lq = config_logq(z, xs, N);
+            const double lq = wave_ordered_sum(N, [&](int p) { return terms[p]; });
             if (lane == 0)
                 logq[b] = (float)lq;
         }
-        __syncthreads(); // z and xs are rewritten by the next configuration
+        __syncthreads(); // z, xs and the terms are rewritten by the next configuration
     }
 }
 
