@@ -233,6 +233,18 @@ __device__ __forceinline__ void zero8(bf16x8 &v)
         v[e] = (bf16)0.f;
 }
 
+// Eight bf16 values from p, or zeros where !ok, moved as one 128-bit integer
+// vector (as bf16 elements the compiler rebuilds the vector 16 bits at a
+// time around the branch).
+typedef unsigned int u32x4 __attribute__((ext_vector_type(4)));
+__device__ __forceinline__ bf16x8 load8_or_zero(bool ok, const bf16 *p)
+{
+    u32x4 v = {0u, 0u, 0u, 0u};
+    if (ok)
+        v = *(const u32x4 *)p;
+    return __builtin_bit_cast(bf16x8, v);
+}
+
 // A operand of tap t of a tile row (configuration b, site (ii, jj) of the
 // tap) from an activation array: zero outside the lattice (zero padding).
 template <int C>
@@ -241,12 +253,8 @@ __device__ __forceinline__ void load_tap(bf16x8 (&at)[C / 32], const bf16 *__res
 {
     const bool ok = b >= 0 && ii >= 0 && ii < L && jj >= 0 && jj < L;
 #pragma unroll
-    for (int kc = 0; kc < C / 32; ++kc) {
-        if (ok)
-            at[kc] = *(const bf16x8 *)(in + ((int64_t)b * N + ii * L + jj) * C + kc * 32 + kq * 8);
-        else
-            zero8(at[kc]);
-    }
+    for (int kc = 0; kc < C / 32; ++kc)
+        at[kc] = load8_or_zero(ok, in + ((int64_t)b * N + ii * L + jj) * C + kc * 32 + kq * 8);
 }
 
 // The same from a float32 backward signal, split into bf16 halves.
@@ -425,12 +433,8 @@ __device__ __forceinline__ void load_tap_lds(bf16x8 (&at)[C / 32], const bf16 *a
 {
     const bool ok = valid && ii >= 0 && ii < L && jj >= 0 && jj < L;
 #pragma unroll
-    for (int kc = 0; kc < C / 32; ++kc) {
-        if (ok)
-            at[kc] = *(const bf16x8 *)(act + (ii * L + jj) * C + kc * 32 + kq * 8);
-        else
-            zero8(at[kc]);
-    }
+    for (int kc = 0; kc < C / 32; ++kc)
+        at[kc] = load8_or_zero(ok, act + (ii * L + jj) * C + kc * 32 + kq * 8);
 }
 
 // As EpiForward, into the LDS buffer of the next layer, with the lane's
@@ -762,12 +766,8 @@ __global__ __launch_bounds__(64 * W) void k_sample(NetDev net, int8_t *__restric
 #pragma unroll
             for (int tt = 0; tt < 5; ++tt)
 #pragma unroll
-                for (int kc = 0; kc < KC; ++kc) {
-                    if (tap_ok[tt])
-                        a[tt][kc] = *(const bf16x8 *)(tap_base[tt] + (l - 2) * C + kc * 32);
-                    else
-                        zero8(a[tt][kc]);
-                }
+                for (int kc = 0; kc < KC; ++kc)
+                    a[tt][kc] = load8_or_zero(tap_ok[tt], tap_base[tt] + (l - 2) * C + kc * 32);
             if (l <= 5) {
                 const EpiRing<C> epi{slot, bias[l - 2], l - 1};
                 if constexpr (kRegW)
