@@ -635,16 +635,19 @@ struct SamplerRows { // tile row -> (configuration, index on the diagonal)
     }
 };
 
-// Post-ReLU bf16 activation into the ring: `slot[q]` is the ring entry of
-// this lane's output row kq*4 + q, `bias[n]` the bias of its column n*16 + r.
+// Post-ReLU bf16 activation into the ring: `slot[q]` is the element offset
+// in `ring` of the entry of this lane's output row kq*4 + q (32-bit offsets,
+// not pointers: half the registers), `bias[n]` the bias of its column
+// n*16 + r.
 template <int C>
 struct EpiRing {
-    bf16 *const (&slot)[4];
+    bf16 *ring;
+    const int (&slot)[4];
     const float (&bias)[C / 16];
     int layer;
     __device__ void operator()(int row, int64_t, int, int col, float v) const
     {
-        slot[row & 3][layer * C + col] = (bf16)fmaxf(v + bias[col >> 4], 0.f);
+        ring[slot[row & 3] + layer * C + col] = (bf16)fmaxf(v + bias[col >> 4], 0.f);
     }
 };
 
@@ -720,7 +723,8 @@ __global__ __launch_bounds__(64 * W) void k_sample(NetDev net, int8_t *__restric
         const int s = 16 * wave + r;
         const bool valid = s < nsites;
         const int i = i_lo + s, j = t - 2 * i;
-        const int ri = valid ? i % R : 0, rup = ri == 0 ? R - 1 : ri - 1; // ring rows of i, i-1
+        // ring rows of i, i-1 (i < L <= 2R - 4, so i mod R is one conditional subtraction)
+        const int ri = valid ? (i >= R ? i - R : i) : 0, rup = ri == 0 ? R - 1 : ri - 1;
         // layer 1 (mask A) at the row's site, 8 channels per 16-byte group
         if (valid) {
             float xv[4];
@@ -743,20 +747,20 @@ __global__ __launch_bounds__(64 * W) void k_sample(NetDev net, int8_t *__restric
         }
         // ring entries of the five taps of this lane's row, and of the four
         // output rows this lane writes in the epilogues
-        const bf16 *tap_base[5];
+        int tap_base[5]; // element offsets in `ring`
         bool tap_ok[5];
 #pragma unroll
         for (int tt = 0; tt < 5; ++tt) {
             const int jj = j + tap_dx(tt);
             tap_ok[tt] = valid && (tap_dy(tt) == 0 || i > 0) && jj >= 0 && jj < L;
-            tap_base[tt] = ring + (((tap_dy(tt) == 0 ? ri : rup) * 4 + (jj & 3)) * 5) * C + kq * 8;
+            tap_base[tt] = (((tap_dy(tt) == 0 ? ri : rup) * 4 + (jj & 3)) * 5) * C + kq * 8;
         }
-        bf16 *slot[4];
+        int slot[4]; // element offsets in `ring`
 #pragma unroll
         for (int q = 0; q < 4; ++q) {
             const int so = 16 * wave + kq * 4 + q;
             const int io = i_lo + so, jo = t - 2 * io;
-            slot[q] = ring + (((so < nsites ? io % R : 0) * 4 + (jo & 3)) * 5) * C;
+            slot[q] = (((so < nsites ? (io >= R ? io - R : io) : 0) * 4 + (jo & 3)) * 5) * C;
         }
         lds_sync<W>();
         const SamplerRows<C> rows{b, 16 * wave, nsites};
@@ -767,9 +771,9 @@ __global__ __launch_bounds__(64 * W) void k_sample(NetDev net, int8_t *__restric
             for (int tt = 0; tt < 5; ++tt)
 #pragma unroll
                 for (int kc = 0; kc < KC; ++kc)
-                    a[tt][kc] = load8_or_zero(tap_ok[tt], tap_base[tt] + (l - 2) * C + kc * 32);
+                    a[tt][kc] = load8_or_zero(tap_ok[tt], ring + tap_base[tt] + (l - 2) * C + kc * 32);
             if (l <= 5) {
-                const EpiRing<C> epi{slot, bias[l - 2], l - 1};
+                const EpiRing<C> epi{ring, slot, bias[l - 2], l - 1};
                 if constexpr (kRegW)
                     conv_mfma<C, C>(a, wreg[kRegW ? l - 2 : 0], rows, epi);
                 else
