@@ -560,8 +560,8 @@ struct HeldWeights {
 // ... or read from the packed arrays at each use (C = 64).
 template <int C>
 struct GlobalWeights {
-    const NetDev *net;
-    __device__ WeightsGlobal<C> operator()(int l) const { return WeightsGlobal<C>{net->wf[l]}; }
+    const bf16 *wf[6];
+    __device__ WeightsGlobal<C> operator()(int l) const { return WeightsGlobal<C>{wf[l]}; }
 };
 
 // Persistent: workgroup g evaluates configurations g, g + grid, ...
@@ -577,17 +577,19 @@ __global__ __launch_bounds__(64 * W) void k_eval(NetDev net, const int8_t *__res
     double *terms = (double *)(eval_lds + eval_terms_offset(N, C));
     const int tid = threadIdx.x, wv = tid >> 6, lane = tid & 63;
     constexpr bool kHold = C == 32;
-    HeldWeights<C> held;
-    if (kHold)
+    HeldWeights<kHold ? C : 32> held;
+    if constexpr (kHold)
         held.load(net);
     for (int64_t b = blockIdx.x; b < B; b += gridDim.x) {
         for (int p = tid; p < N; p += 64 * W)
             xs[p] = x[b * N + p];
         __syncthreads();
-        if (kHold)
+        if constexpr (kHold)
             eval_config<C, W>(net, xs, act, z, held);
         else
-            eval_config<C, W>(net, xs, act, z, GlobalWeights<C>{&net});
+            eval_config<C, W>(net, xs, act, z,
+                              GlobalWeights<C>{{net.wf[0], net.wf[1], net.wf[2], net.wf[3], net.wf[4],
+                                                net.wf[5]}});
         // log q~: the per-site terms of config_logq() by every wavefront, then
         // its summation, in its order, by one
         for (int p = tid; p < N; p += 64 * W) {
