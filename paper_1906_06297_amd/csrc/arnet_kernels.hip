@@ -117,7 +117,8 @@ __device__ __forceinline__ double config_logq(const float *z, const int8_t *x, i
 }
 
 // ------------------------------------------------------------- MFMA tile
-// Rows of a tile: a row is valid when b >= 0.
+// Rows of a tile: a row is valid when b >= 0.  Row indices are below 2^31
+// (a workspace holds at most 2^31 / C rows), so the division is 32-bit.
 struct RowsOfSites { // 16 consecutive flattened (configuration, site) rows
     int64_t g0, total;
     int N;
@@ -129,8 +130,29 @@ struct RowsOfSites { // 16 consecutive flattened (configuration, site) rows
             p = 0;
             return;
         }
-        b = g / N;
-        p = (int)(g - b * N);
+        const uint32_t bq = (uint32_t)g / (uint32_t)N;
+        b = bq;
+        p = (int)((uint32_t)g - bq * (uint32_t)N);
+    }
+};
+
+// The four rows of a tile that one lane writes in conv_mfma()'s epilogue
+// (kq*4 + q, q = 0..3), found once per tile rather than at every output
+// block.
+struct LaneRows {
+    int64_t b[4];
+    int p[4];
+    template <class Rows>
+    __device__ LaneRows(const Rows &rows, int kq)
+    {
+#pragma unroll
+        for (int q = 0; q < 4; ++q)
+            rows(kq * 4 + q, b[q], p[q]);
+    }
+    __device__ void operator()(int row, int64_t &bb, int &pp) const
+    {
+        bb = b[row & 3];
+        pp = p[row & 3];
     }
 };
 
@@ -362,7 +384,7 @@ __global__ __launch_bounds__(256) void k_conv_fwd(const bf16 *__restrict__ in, b
 #pragma unroll
     for (int t = 0; t < 5; ++t)
         load_tap<C>(a[t], in, b, N, L, i + tap_dy(t), j + tap_dx(t), kq);
-    conv_mfma<C, C>(a, WeightsGlobal<C>{wk}, rows, EpiForward{out, bias, N, C});
+    conv_mfma<C, C>(a, WeightsGlobal<C>{wk}, LaneRows(rows, kq), EpiForward{out, bias, N, C});
 }
 
 // Layer 6 on MFMA: the weights as one 16-column operand whose column 0 is W6.
@@ -385,7 +407,7 @@ __global__ __launch_bounds__(256) void k_l6_fwd(NetDev net, const bf16 *__restri
     for (int t = 0; t < 5; ++t)
         load_tap<C>(a[t], h5, b, N, L, i + tap_dy(t), j + tap_dx(t), kq);
     const float b6 = net.params[param_layout(C).b6];
-    conv_mfma<C, 16>(a, WeightsGlobal<C>{net.w6p}, rows, EpiLogit{logits, b6, N});
+    conv_mfma<C, 16>(a, WeightsGlobal<C>{net.w6p}, LaneRows(rows, kq), EpiLogit{logits, b6, N});
 }
 
 // Exact log-probability of each configuration under the sampler, one
@@ -1046,7 +1068,8 @@ __global__ __launch_bounds__(256) void k_conv_dgrad(const float *__restrict__ dp
 #pragma unroll
     for (int t = 0; t < 5; ++t)
         load_tap_split<C>(ah[t], al[t], dpre_above, b, N, L, i - tap_dy(t), j - tap_dx(t), kq);
-    conv_mfma_split<C, C>(ah, al, WeightsGlobal<C>{wk}, rows, EpiBackward{dpre_below, act_below, N, C});
+    conv_mfma_split<C, C>(ah, al, WeightsGlobal<C>{wk}, LaneRows(rows, kq),
+                          EpiBackward{dpre_below, act_below, N, C});
 }
 
 // Weight and bias gradients of a C -> C layer:
