@@ -345,11 +345,11 @@ __device__ __forceinline__ uint64_t row_load(const uint64_t *rowp, uint32_t nwor
     return (uint64_t)v.x | ((uint64_t)v.y << 32);
 }
 
-// Edge word of the side vector of a wavefront that owns whole 64-word row
-// segments: lane 0 (left neighbours) and lane 63 (right neighbours) read the
-// word past the segment; every other lane takes its neighbour lane's centre
-// word by a wavefront shift (DPP wave_shr:1 / wave_shl:1), which leaves the
-// edge lane's own value in place.
+// Edge half of the side vector of a wavefront that owns whole 64-word row
+// segments: every lane takes its neighbour lane's centre word by a wavefront
+// shift (DPP wave_shr:1 / wave_shl:1); the shift leaves lane 0 (left
+// neighbours) or lane 63 (right neighbours) with `edge`, the half of the word
+// past the segment, which the caller holds in every lane.
 __device__ __forceinline__ uint32_t side_half_dpp(uint32_t cur_lo, uint32_t cur_hi, uint32_t edge,
                                                   bool left)
 {
