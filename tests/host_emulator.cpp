@@ -115,6 +115,44 @@ int emu_block_decision_check(uint64_t seed, int n)
     return bad;
 }
 
+// The plain start state built straight from the pair-level terms
+// (start_from_halves<Anti, true>) against the class split followed by
+// start_half<true>, over n random target and neighbour words, both signs of
+// J; returns the mismatches.
+int emu_start_plain_check(uint64_t seed, int n)
+{
+    uint64_t z = seed * 0x9E3779B97F4A7C15ull + 7;
+    auto next = [&z]() { // splitmix64
+        uint64_t x = (z += 0x9E3779B97F4A7C15ull);
+        x = (x ^ (x >> 30)) * 0xBF58476D1CE4E5B9ull;
+        x = (x ^ (x >> 27)) * 0x94D049BB133111EBull;
+        return x ^ (x >> 31);
+    };
+    const rows::ClassMasks cm{0u, 0u, ~0u, ~0u};
+    int bad = 0;
+    for (int i = 0; i < n; ++i) {
+        const uint64_t t = next(), up = next(), dn = next(), ce = next();
+        const uint32_t sl = (uint32_t)next(), sh = (uint32_t)next();
+        for (int anti = 0; anti < 2; ++anti) {
+            const rows::State got = anti ? rows::start_from_halves<true, true>(t, up, dn, ce, sl, sh, cm)
+                                         : rows::start_from_halves<false, true>(t, up, dn, ce, sl, sh, cm);
+            for (int h = 0; h < 2; ++h) {
+                const uint32_t th = h ? rows::hi32(t) : rows::lo32(t);
+                const uint32_t n0 = h ? rows::hi32(up) : rows::lo32(up);
+                const uint32_t n1 = h ? rows::hi32(dn) : rows::lo32(dn);
+                const uint32_t n2 = h ? rows::hi32(ce) : rows::lo32(ce);
+                const uint32_t n3 = h ? sh : sl;
+                const rows::Split k = anti ? rows::split_classes<true>(th, n0, n1, n2, n3)
+                                           : rows::split_classes<false>(th, n0, n1, n2, n3);
+                rows::State ref{};
+                rows::start_half<true>(ref, h, th, k, cm);
+                bad += (ref.tf[h] != got.tf[h]) || (ref.p[h] != got.p[h]) || (ref.a[h] != got.a[h]);
+            }
+        }
+    }
+    return bad;
+}
+
 // The batch kernel's row-aligned neighbour vectors against the general
 // extraction from an extended colour array, for every word of both colours
 // of an L x L lattice (L % 128 == 0) filled from `seed`; returns mismatches.

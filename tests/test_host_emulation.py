@@ -32,6 +32,7 @@ def emu(tmp_path_factory):
     lib.emu_half_sweep5.argtypes = [u64p, ctypes.c_int64, ctypes.c_int, u64p, ctypes.c_uint64,
                                     ctypes.c_uint64, ctypes.c_uint32, ctypes.c_int]
     lib.emu_block_decision_check.argtypes = [ctypes.c_uint64, ctypes.c_int]
+    lib.emu_start_plain_check.argtypes = [ctypes.c_uint64, ctypes.c_int]
     lib.emu_aligned_neighbours_check.argtypes = [ctypes.c_int64, ctypes.c_uint64]
     lib.emu_half_aligned_neighbours_check.argtypes = [ctypes.c_int64, ctypes.c_uint64]
     lib.emu_ext32_neighbours_check.argtypes = [ctypes.c_int64, ctypes.c_uint64]
@@ -160,6 +161,15 @@ def test_lane_pair_block_decisions_equal_plane_by_plane(emu, seed):
     must leave exactly the state that applying the four planes in order
     leaves, for any pending set, classes and thresholds."""
     assert emu.emu_block_decision_check(seed, 20000) == 0
+
+
+@pytest.mark.parametrize("seed", [1, 2, 3])
+def test_plain_start_state_equals_the_class_split(emu, seed):
+    """The queued row kernel's plain start state (flipped word, pending and
+    class-A masks straight from the pair-level terms, without the "two or
+    more" mask) equals the class split followed by the general start, for
+    random words and both signs of J."""
+    assert emu.emu_start_plain_check(seed, 20000) == 0
 
 
 @pytest.mark.parametrize("L", [128, 256, 384, 512, 640])
